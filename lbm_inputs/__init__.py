@@ -1,0 +1,214 @@
+"""Seeded synthetic inputs for the D2Q9 LBGK runs and the balance diagnostic.
+
+This module is shared by the oracle-side tests and the GPU side: it builds the
+initial density/velocity fields and the static forcing field on the host, in
+FP64 NumPy, so that both implementations consume bit-identical inputs.  It
+holds none of the method's arithmetic (no equilibrium, collision, streaming,
+finite differences or box averages).
+
+The paper's runs are the authors' own 256^2 simulations (Sec. 3); their dumped
+configurations are not available, so the workloads below stand in for them:
+
+* Taylor-Green vortex (closed-form decaying solution of the Navier-Stokes
+  equations) for the small FP64 case.
+* A random-phase isotropic velocity field with energy spectrum
+  E(k) ~ k^4 exp(-2 (k/8)^2), scaled to a given maximum Mach number, for the
+  decaying-turbulence, ensemble and differentiable workloads.
+* A divergence-free stream-function force built like Sec. 3, Eqs. 14-15 (a sum
+  of cosines over a shell of integer wavevectors, force = (d_y Psi, -d_x Psi)),
+  with independent seeded phases, for the forced workload.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+__all__ = [
+    "CS", "taylor_green", "spectrum_velocity", "forcing_field", "shell_vectors",
+    "ensemble_members", "balance_levels", "WORKLOADS", "Workload",
+]
+
+#: lattice speed of sound of D2Q9 (used only to turn a Mach number into a speed)
+CS = 1.0 / math.sqrt(3.0)
+
+
+def taylor_green(n: int, u0: float = 0.01):
+    """Taylor-Green vortex with one wavelength per box side.
+
+    u_x = -u0 cos(kx) sin(ky), u_y = u0 sin(kx) cos(ky), k = 2 pi / n, rho = 1,
+    x, y the integer cell indices.  Returns (rho, ux, uy) as float64 [n, n]
+    arrays indexed [y, x].
+    """
+    k = 2.0 * math.pi / n
+    idx = np.arange(n, dtype=np.float64)
+    y, x = np.meshgrid(idx, idx, indexing="ij")
+    ux = -u0 * np.cos(k * x) * np.sin(k * y)
+    uy = u0 * np.sin(k * x) * np.cos(k * y)
+    rho = np.ones((n, n), dtype=np.float64)
+    return rho, ux, uy
+
+
+def _spectral_velocity(n: int, rng: np.random.Generator, k_peak: float):
+    kint = np.fft.fftfreq(n, d=1.0 / n)               # integer wavenumbers
+    ky, kx = np.meshgrid(kint, kint, indexing="ij")
+    kmag = np.hypot(kx, ky)
+    theta = rng.uniform(0.0, 2.0 * math.pi, size=(n, n))
+    with np.errstate(divide="ignore", invalid="ignore"):
+        energy = kmag ** 4 * np.exp(-2.0 * (kmag / k_peak) ** 2)
+        amp = np.sqrt(energy / (math.pi * kmag)) / kmag
+    amp[0, 0] = 0.0
+    psi_hat = amp * np.exp(1j * theta)
+    two_pi_n = 2.0 * math.pi / n
+    ux = np.real(np.fft.ifft2(1j * two_pi_n * ky * psi_hat))
+    uy = np.real(np.fft.ifft2(-1j * two_pi_n * kx * psi_hat))
+    return ux, uy
+
+
+def spectrum_velocity(n: int, seed=0, max_mach: float = 0.05, k_peak: float = 8.0):
+    """Random-phase isotropic velocity field, divergence-free by construction.
+
+    psi_hat(k) = sqrt(E(|k|) / (pi |k|)) / |k| * exp(i theta_k), theta_k drawn
+    uniformly in [0, 2 pi) from ``np.random.default_rng(seed)`` in
+    ``np.fft.fftfreq`` order, E(k) = k^4 exp(-2 (k / k_peak)^2); psi = Re IFFT;
+    u = (d_y psi, -d_x psi) (spectral derivative, sign convention of Eq. 15);
+    the field is scaled so that max |u| / c_s = max_mach.  rho = 1.
+
+    ``seed`` may be an int or an existing ``np.random.Generator``.
+    """
+    rng = seed if isinstance(seed, np.random.Generator) else np.random.default_rng(seed)
+    ux, uy = _spectral_velocity(n, rng, k_peak)
+    scale = max_mach * CS / np.sqrt(ux * ux + uy * uy).max()
+    ux *= scale
+    uy *= scale
+    rho = np.ones((n, n), dtype=np.float64)
+    return rho, ux, uy
+
+
+def shell_vectors(kmin: float, kmax: float):
+    """All integer wavevectors k with kmin <= |k| <= kmax (both signs)."""
+    r = int(math.ceil(kmax))
+    out = []
+    for ky in range(-r, r + 1):
+        for kx in range(-r, r + 1):
+            k2 = kx * kx + ky * ky
+            if kmin * kmin <= k2 <= kmax * kmax:
+                out.append((kx, ky))
+    return out
+
+
+def forcing_field(n: int, seed: int = 0, kmin: float = 4.0, kmax: float = 6.0,
+                  max_force: float | None = None, alpha: float = 1e-4,
+                  target_mach: float = 0.08):
+    """Static divergence-free forcing field (shape of Sec. 3, Eqs. 14-15).
+
+    Psi(x) = sum_{kmin<=|k|<=kmax} cos(2 pi k.x / n + phi_k), phi_k ~ U[0, 2pi)
+    from ``default_rng(seed)`` in the order of :func:`shell_vectors`;
+    F = (d_y Psi, -d_x Psi) analytically.  The amplitude is scaled so that
+    max |F| = max_force, by default alpha * target_mach * c_s (the uniform
+    drag-limited response F / (alpha rho) then has Mach ``target_mach``).
+    Returns (fx, fy) float64 [n, n] indexed [y, x].
+    """
+    if max_force is None:
+        max_force = alpha * target_mach * CS
+    rng = np.random.default_rng(seed)
+    vecs = shell_vectors(kmin, kmax)
+    phases = rng.uniform(0.0, 2.0 * math.pi, size=len(vecs))
+    idx = np.arange(n, dtype=np.float64)
+    y, x = np.meshgrid(idx, idx, indexing="ij")
+    fx = np.zeros((n, n))
+    fy = np.zeros((n, n))
+    w = 2.0 * math.pi / n
+    for (kx, ky), ph in zip(vecs, phases):
+        s = np.sin(w * (kx * x + ky * y) + ph)
+        fx -= w * ky * s          # d/dy cos(.) = -w ky sin(.)
+        fy += w * kx * s          # -d/dx cos(.) = +w kx sin(.)
+    scale = max_force / np.sqrt(fx * fx + fy * fy).max()
+    return fx * scale, fy * scale
+
+
+ENSEMBLE_SIZES = (256, 384, 512, 768, 1024)
+
+
+def ensemble_members(nruns: int = 64, sizes=ENSEMBLE_SIZES, tau_lo: float = 0.505,
+                     tau_hi: float = 0.6, max_mach: float = 0.05, build_fields: bool = True):
+    """Members of the batched decaying-turbulence ensemble.
+
+    Run r uses ``default_rng(r)`` and draws, in order: its grid side from
+    ``sizes`` (uniform), tau ~ U[tau_lo, tau_hi], then the spectrum phases.
+    Returns a list of dicts {n, tau, seed, rho, ux, uy} (fields omitted when
+    ``build_fields`` is False).
+    """
+    out = []
+    for r in range(nruns):
+        rng = np.random.default_rng(r)
+        n = int(rng.choice(np.asarray(sizes)))
+        tau = float(rng.uniform(tau_lo, tau_hi))
+        m = {"n": n, "tau": tau, "seed": r}
+        if build_fields:
+            rho, ux, uy = spectrum_velocity(n, rng, max_mach=max_mach)
+            m.update(rho=rho, ux=ux, uy=uy)
+        out.append(m)
+    return out
+
+
+def balance_levels(n: int, seed: int = 3, max_mach: float = 0.05, drho: float = 1e-3,
+                   dt_scale: float = 2e-3, with_force: bool = True):
+    """Three smooth time levels (n-2, n-1, n) of (rho, u) plus a force field.
+
+    Synthetic inputs for checking the balance diagnostic on its own: the
+    velocity at level n-k is u * (1 + k dt_scale) + k dt_scale * v with u, v
+    two independent spectrum fields; rho = 1 + drho * s_k with smooth
+    perturbations s_k.  Returns dict with lists rho[3], ux[3], uy[3] ordered
+    (n-2, n-1, n) and fx, fy (zeros when ``with_force`` is False).
+    """
+    rng = np.random.default_rng(seed)
+    _, ux, uy = spectrum_velocity(n, rng, max_mach=max_mach)
+    _, vx, vy = spectrum_velocity(n, rng, max_mach=max_mach)
+    _, sx, sy = spectrum_velocity(n, rng, max_mach=1.0)
+    rhos, uxs, uys = [], [], []
+    for lev in (2, 1, 0):
+        a = 1.0 + lev * dt_scale
+        uxs.append(ux * a + lev * dt_scale * vx)
+        uys.append(uy * a + lev * dt_scale * vy)
+        rhos.append(1.0 + drho * ((1.0 + 0.1 * lev) * sx + 0.5 * lev * sy) / CS)
+    if with_force:
+        fx, fy = forcing_field(n, seed=seed, max_force=1e-5)
+    else:
+        fx = np.zeros((n, n))
+        fy = np.zeros((n, n))
+    return {"rho": rhos, "ux": uxs, "uy": uys, "fx": fx, "fy": fy}
+
+
+@dataclass(frozen=True)
+class Workload:
+    """One of the five workloads the library is measured and checked on."""
+    name: str
+    n: int
+    dtype: str
+    tau: float
+    steps: int
+    init: str
+    seed: int = 0
+    force: bool = False
+    alpha: float = 0.0
+    sizes: tuple = ()
+    balance_every: int = 0
+    taus: tuple = field(default_factory=tuple)
+
+
+WORKLOADS = {
+    "tg64": Workload("taylor-green 64^2 fp64", 64, "f64", 0.6, 1000, "tg",
+                     sizes=(4, 8, 16, 32)),
+    "decay1024": Workload("decaying turbulence 1024^2 fp32", 1024, "f32", 0.51, 10000, "spectrum",
+                          seed=0, sizes=(8, 16, 32, 64, 128, 256), balance_every=100),
+    "ensemble64": Workload("ensemble of 64 decaying runs 256^2..1024^2 fp32", 0, "f32", 0.0, 5000,
+                           "ensemble"),
+    "forced4096": Workload("forced turbulence 4096^2 fp32, Guo force + linear drag", 4096, "f32",
+                           0.51, 50000, "rest", seed=0, force=True, alpha=1e-4,
+                           sizes=(8, 16, 32, 64, 128, 256), balance_every=500,
+                           taus=(0.5005, 0.501, 0.505, 0.51, 0.55)),
+    "adjoint512": Workload("differentiable decaying run 512^2 fp32", 512, "f32", 0.51, 2000,
+                           "spectrum", seed=7, sizes=(32,)),
+}
