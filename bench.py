@@ -1,0 +1,215 @@
+"""Throughput benchmark of the D2Q9 LBGK hot path on one MI355X.
+
+One benchmark step = one pass of the whole path over the forced-turbulence
+workload: 500 fused stream+collide steps of a 4096^2 FP32 grid with Guo
+forcing and linear drag, the moments at the last step, and the sub-volume
+energy/enstrophy balance at box sizes 8..256 (the workload's diagnostic
+cadence is one balance every 500 steps).  Inputs are resident in HBM before
+the timed region; the timed region is bracketed by torch.cuda.synchronize().
+
+Prints ONE JSON line on stdout (everything else goes to stderr):
+value = lattice updates per second of the whole pass (MLUPS), with the
+dominant kernel's roofline (HIP events around the step launches on the
+library's stream) and the FP64 CPU oracle timed on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--tau T]
+                       [--no-cpu-baseline] [--no-extras]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "D2Q9 MLUPS/GPU + % HBM roofline; batched-ensemble & adjoint MLUPS vs plain"
+HBM_PEAK_GBS = 8000.0
+STEPS_PER_PASS = 500
+SIZES = (8, 16, 32, 64, 128, 256)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def traffic_from_profile(kernel_tag):
+    """Per-launch HBM bytes of the step kernel from the committed counter summary,
+    or None when it is missing or was taken on another version of the kernel."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel_tag}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    src = os.path.join(ROOT, "paper_1809_06735_amd", "csrc", "lbm_step.hip")
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    rec = None
+    for line in open(path):
+        if line.startswith("TRAFFIC_JSON:"):
+            rec = json.loads(line.split(":", 1)[1])
+    if not rec or rec.get("source_sha256_16") != digest:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(n, tau, alpha, fx, fy, steps):
+    import torch
+    from oracle import ref
+    import numpy as np
+    f = ref.init_populations(np.ones((n, n)), np.zeros((n, n)), np.zeros((n, n)))
+    fxt, fyt = ref.t64(fx), ref.t64(fy)
+    f = ref.step(f, tau, fxt, fyt, alpha)          # warm-up
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        f = ref.step(f, tau, fxt, fyt, alpha)
+    dt = time.perf_counter() - t0
+    return {"value": n * n * steps / dt / 1e6, "unit": "MLUPS", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": f"{steps} FP64 oracle steps (PyTorch CPU) of the {n}^2 forced grid, "
+                      f"{dt:.1f} s; step only, no balance"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--tau", type=float, default=0.51)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=4)
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {a.gpus}); the multi-GPU layout is "
+              "described in the design notes but not built", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import lbm_inputs as inp
+    from paper_1809_06735_amd import Simulation, copy_bandwidth
+
+    w = inp.WORKLOADS["forced4096"]
+    n = w.n
+    log(f"[bench] building inputs {n}^2 (force field seed {w.seed})")
+    fx, fy = inp.forcing_field(n, seed=w.seed, alpha=w.alpha)
+    z = np.zeros((n, n))
+    sim = Simulation(np.ones((n, n)), z, z, a.tau, dtype="f32", fx=fx, fy=fy, alpha=w.alpha,
+                     with_balance=True)
+    tile = sim.autotune(trial_steps=5)
+    log(f"[bench] step kernel shape {tile}")
+
+    def one_pass():
+        sim.step(STEPS_PER_PASS)
+        res = sim.balance(SIZES)
+        return res
+
+    log(f"[bench] warmup {a.warmup} passes")
+    for _ in range(a.warmup):
+        one_pass()
+    torch.cuda.synchronize()
+    sim.step_time(reset=True)
+    sim.step_timing(True)
+    log(f"[bench] timing {a.steps} passes x {STEPS_PER_PASS} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    last = None
+    for _ in range(a.steps):
+        last = one_pass()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    sim.step_timing(False)
+    kern_ms, launches = sim.step_time(reset=True)
+    lu = n * n * STEPS_PER_PASS * a.steps
+    mlups = lu / elapsed / 1e6
+    avg_launch_s = kern_ms * 1e-3 / max(launches, 1)
+    bytes_per_lu = 9 * 4 * 2 + 2 * 4          # 9 reads + 9 writes + 2 force reads, FP32
+    alg_bytes = bytes_per_lu * n * n
+    achieved = alg_bytes / avg_launch_s / 1e9
+    traffic = traffic_from_profile("k_step_forced4096")
+    st = last["stats"]
+    log(f"[bench] {mlups:.0f} MLUPS whole pass; step kernel {avg_launch_s * 1e6:.1f} us/launch "
+        f"= {achieved:.0f} GB/s ({achieved / HBM_PEAK_GBS:.1%} of 8 TB/s)")
+
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(elapsed * 1e3 / a.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic: fluid at rest, seeded random-phase divergence-free force on shells 4<=|k|<=6",
+        "config": {"workload": f"forced4096: D2Q9 BGK {n}x{n} periodic FP32, Guo force + drag "
+                               f"alpha={w.alpha}, tau={a.tau}; one step = {STEPS_PER_PASS} LBGK "
+                               f"steps + moments + sub-volume balance at L={list(SIZES)}",
+                   "grid": n, "tau": a.tau, "lbgk_steps_per_step": STEPS_PER_PASS,
+                   "balance_sizes": list(SIZES), "step_kernel_shape": list(tile),
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel": "k_step (fused pull stream + BGK collide + Guo force)",
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "avg_launch_us": round(avg_launch_s * 1e6, 2)},
+        "balance_at_end": {str(s["L"]): {"mean_dE": s["dE"]["mean"], "mean_dZ": s["dZ"]["mean"],
+                                         "mean_Ma": s["Ma"]["mean"]} for s in st},
+    }
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+
+    if not a.no_extras:
+        extras = {}
+        try:
+            gbs, _ = copy_bandwidth(1 << 30, iters=10)
+            extras["copy_kernel_GBps"] = round(gbs, 1)
+        except Exception as e:  # noqa: BLE001
+            extras["copy_kernel_GBps"] = f"error: {e}"
+        try:
+            rho0, ux0, uy0 = inp.spectrum_velocity(n, seed=0, max_mach=0.05)
+            plain = Simulation(rho0, ux0, uy0, a.tau, dtype="f32")
+            plain.autotune(trial_steps=5)
+            plain.step(200)
+            torch.cuda.synchronize()
+            plain.step_timing(True)
+            t1 = time.perf_counter()
+            plain.step(1000)
+            torch.cuda.synchronize()
+            dtp = time.perf_counter() - t1
+            kms, nl = plain.step_time(reset=True)
+            per = kms * 1e-3 / nl
+            extras["plain_unforced_4096_fp32"] = {
+                "MLUPS": round(n * n * 1000 / dtp / 1e6, 1),
+                "kernel_GBps": round(72 * n * n / per / 1e9, 1),
+                "frac_of_8TBps": round(72 * n * n / per / 1e9 / HBM_PEAK_GBS, 4)}
+            plain.close()
+            del plain
+        except Exception as e:  # noqa: BLE001
+            extras["plain_unforced_4096_fp32"] = f"error: {e}"
+        try:
+            from paper_1809_06735_amd import ensemble as ens_mod
+            extras["ensemble"] = ens_mod.bench_ensemble(log=log)
+        except Exception as e:  # noqa: BLE001
+            extras["ensemble"] = f"unavailable: {e}"
+        try:
+            from paper_1809_06735_amd import adjoint as adj_mod
+            extras["adjoint"] = adj_mod.bench_adjoint(log=log)
+        except Exception as e:  # noqa: BLE001
+            extras["adjoint"] = f"unavailable: {e}"
+        out["extras"] = extras
+
+    if not a.no_cpu_baseline:
+        log(f"[bench] cpu baseline: {a.cpu_steps} oracle steps at {n}^2")
+        out["cpu_baseline"] = cpu_baseline(n, a.tau, w.alpha, fx, fy, a.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

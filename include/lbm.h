@@ -1,0 +1,314 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) D2Q9 lattice-Boltzmann library.
+ *
+ * The library advances a periodic two-dimensional D2Q9 BGK lattice-Boltzmann
+ * model (Tauzin et al., Computers & Fluids 172 (2018), Sec. 1, Eqs. 1-2 and
+ * Eq. 5) with an optional static body force (Guo's forcing term) and linear
+ * drag, and evaluates the sub-volume averaged kinetic-energy and enstrophy
+ * balances with their balancing errors (Sec. 2, Eqs. 8-13; Sec. 3, Eqs. 17-18
+ * and Table 1; Sec. 4, Eq. 20).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every function returns an int status: LBM_OK (0) or a negative LBM_E_*
+ *   code.  Nothing throws and nothing exits.  A failed call leaves a
+ *   human-readable message in lbm_last_error() (per host thread).
+ * - Fields are row-major [ny][nx] (x fastest) with periodic wrap in x and y.
+ *   Lattice units: dx = dt = 1, c_s^2 = 1/3, nu = (tau - 1/2)/3.
+ * - "device" pointers are HIP device memory on the current device; "host"
+ *   pointers are ordinary host memory.  The caller owns every buffer it
+ *   passes, including workspaces; the library only borrows them for the
+ *   lifetime of the object that was created with them.  The library owns only
+ *   its host-side handle, which the matching *_destroy call frees.
+ * - Work is enqueued on the HIP stream given in the config (NULL: the null
+ *   stream).  Calls documented as synchronous wait for that stream.
+ * - Arguments are validated before anything is enqueued; an invalid argument
+ *   gives LBM_E_INVALID and enqueues nothing.
+ * - A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define LBM_API __attribute__((visibility("default")))
+#else
+#define LBM_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------- */
+enum {
+  LBM_OK = 0,
+  LBM_E_INVALID = -1,     /* bad argument (message says which)                     */
+  LBM_E_NOMEM = -2,       /* workspace smaller than the *_workspace_bytes figure   */
+  LBM_E_HIP = -3,         /* a HIP runtime call failed (message holds its text)    */
+  LBM_E_DIVERGED = -4,    /* non-finite moment or rho <= 0 found (step in message) */
+  LBM_E_STATE = -5,       /* call not possible in the current state                */
+  LBM_E_UNSUPPORTED = -6, /* valid request this build does not handle              */
+  LBM_E_TIMEOUT = -7      /* a persistent kernel's bounded barrier wait ran out    */
+};
+
+/* ---- storage types -------------------------------------------------------- */
+enum { LBM_F32 = 0, LBM_F64 = 1 };
+
+/* ---- indices into the 8 global scalars returned by *_moments -------------- */
+enum {
+  LBM_S_MASS = 0,      /* sum rho                                */
+  LBM_S_MOMX = 1,      /* sum rho u_x                            */
+  LBM_S_MOMY = 2,      /* sum rho u_y                            */
+  LBM_S_ENERGY = 3,    /* sum rho |u|^2 / 2                      */
+  LBM_S_MAXSPEED = 4,  /* max |u|                                */
+  LBM_S_MINRHO = 5,    /* min rho                                */
+  LBM_S_NONFINITE = 6, /* number of sites with a non-finite moment */
+  LBM_S_TIME = 7       /* time step t of the moments              */
+};
+
+/* ---- order of the 13 balance integrand fields ----------------------------- */
+enum {
+  LBM_T_LHS_E = 0, /* d_t E, E = rho|u|^2/2, three-level formula (Eq. 17)        */
+  LBM_T_E1 = 1,    /* -div(E u)                         (Eq. 10, first term)     */
+  LBM_T_E2 = 2,    /* -u.grad p, p = rho/3              (Eq. 10, second term)    */
+  LBM_T_E3 = 3,    /* u.F                               (Eq. 10, third term)     */
+  LBM_T_E4 = 4,    /* -sigma_ij d_j u_i                 (Eq. 10, fourth term)    */
+  LBM_T_E5 = 5,    /* d_j(u_i sigma_ij)                 (Eq. 10, fifth term)     */
+  LBM_T_LHS_Z = 6, /* d_t Omega, Omega = omega^2/2                               */
+  LBM_T_Z1 = 7,    /* -div(Omega u)                     (Eq. 11, first term)     */
+  LBM_T_Z2 = 8,    /* -Omega div u                      (Eq. 11, second term)    */
+  LBM_T_Z3 = 9,    /* omega curl(F/rho)                 (Eq. 11, third term)     */
+  LBM_T_Z4 = 10,   /* H_x d_y omega - H_y d_x omega     (Eq. 11, fourth term)    */
+  LBM_T_Z5 = 11,   /* d_x(omega H_y) - d_y(omega H_x)   (Eq. 11, fifth term)     */
+  LBM_T_USQ = 12,  /* |u|^2 (for the sub-volume Mach number, Eq. 20)             */
+  LBM_NTERMS = 13
+};
+
+/* Simulation parameters of one periodic grid. */
+typedef struct {
+  int32_t nx, ny;      /* grid extents, each >= 16 (the composed 8th-order stencils
+                          of the balance reach 12 cells)                          */
+  int32_t dtype;       /* population storage: LBM_F32 or LBM_F64.  The arithmetic
+                          of the step follows the storage type; every reduction,
+                          the balance and the box sums run in FP64.               */
+  int32_t has_force;   /* 1: a static external force field is given to lbm_init */
+  int32_t with_balance;/* 1: the workspace also holds the balance scratch, so
+                          lbm_subvolume_balance can be called on this handle     */
+  int32_t reserved;    /* must be 0                                              */
+  double tau;          /* BGK relaxation time (Eq. 1), > 0.5 (Eq. 5: nu > 0)     */
+  double drag_alpha;   /* linear drag coefficient alpha >= 0: force -alpha rho u */
+  void* stream;        /* hipStream_t to enqueue on, or NULL                     */
+} lbm_config;
+
+/* Statistics over all windows of one box side L (Sec. 3: mu_l, sigma_l).
+ * Every corner (x0, y0) of the periodic grid defines one L x L window when
+ * L < min(nx, ny); L == nx == ny is a single window.  delta^E and delta^Omega
+ * follow Eqs. 12-13 (denominator: the largest |RHS term|); a zero denominator
+ * gives NaN, counted in nan_* and left out of the other figures.  Ma is
+ * sqrt(<|u|^2>_V)/c_s (Eq. 20).  std is the population standard deviation. */
+typedef struct {
+  int32_t L;
+  int32_t reserved;
+  int64_t count_dE, nan_dE, count_dZ, nan_dZ, count_Ma;
+  double mean_dE, std_dE, min_dE, max_dE;
+  double mean_dZ, std_dZ, min_dZ, max_dZ;
+  double mean_Ma, std_Ma, min_Ma, max_Ma;
+} lbm_balance_stats;
+
+/* Step-kernel launch shape.  bx*by threads per workgroup (a multiple of 64,
+ * at most 1024); each thread updates vx consecutive sites in x (1, 2 or 4;
+ * nx must be a multiple of vx) on ry consecutive rows; nt = 1 writes the new
+ * populations with non-temporal stores. */
+typedef struct {
+  int32_t bx, by, vx, ry, nt;
+} lbm_tile;
+
+/* ---- library information --------------------------------------------------- */
+LBM_API const char* lbm_version(void);
+LBM_API const char* lbm_strerror(int status);
+LBM_API const char* lbm_last_error(void);
+
+/* ---- single grid ------------------------------------------------------------ */
+typedef struct lbm_ctx_s* lbm_ctx;
+
+/* Bytes of device workspace lbm_init needs for cfg (populations A/B, force,
+ * moment history, reduction scratch and, if cfg->with_balance, the balance
+ * scratch).  Host call, enqueues nothing. */
+LBM_API int lbm_workspace_bytes(const lbm_config* cfg, size_t* bytes);
+
+/* Create a handle and set the populations to the equilibrium (Eq. 2) of the
+ * given fields: f_l(x, 0) = f^eq_l(rho0(x), u0(x)).
+ *   ws, ws_bytes : device workspace, 256-byte aligned, >= lbm_workspace_bytes.
+ *   rho0, ux0, uy0 : device FP64 [ny][nx] initial density and velocity.
+ *   fx, fy : device FP64 [ny][nx] static external force when cfg->has_force,
+ *            else must be NULL.  Copied into the workspace (storage type).
+ *   out : receives the handle.  Time starts at t = 0.
+ * Asynchronous on cfg->stream; the inputs may be freed after the stream has
+ * passed this point. */
+LBM_API int lbm_init(const lbm_config* cfg, void* ws, size_t ws_bytes,
+             const double* rho0, const double* ux0, const double* uy0,
+             const double* fx, const double* fy, lbm_ctx* out);
+
+/* Advance n >= 0 time steps of Eq. 1 (pull streaming fused with BGK collision,
+ * Guo forcing with the half-force velocity, implicit linear drag).  The last
+ * two steps also record (rho, u) at times t+n-2 and t+n-1 for the time
+ * derivative of the balance.  Asynchronous. */
+LBM_API int lbm_step(lbm_ctx ctx, int64_t n);
+
+/* Moments at the current time t: rho = sum f, u = (sum f c + F/2)/rho with
+ * F = F_ext - alpha rho u solved in closed form (u = j/rho when unforced).
+ *   rho, ux, uy : device [ny][nx] outputs of type out_dtype (LBM_F32/LBM_F64),
+ *                 any of them may be NULL.
+ *   scalars8 : host double[8] (LBM_S_* order) or NULL.  When given, the call
+ *              synchronises and returns LBM_E_DIVERGED if a moment is
+ *              non-finite or rho <= 0 somewhere (the scalars are still
+ *              filled).  Without it the call is asynchronous. */
+LBM_API int lbm_moments(lbm_ctx ctx, void* rho, void* ux, void* uy, int32_t out_dtype,
+                double* scalars8);
+
+/* Sub-volume energy and enstrophy balance at the current time t (needs the
+ * handle created with with_balance = 1 and the two preceding steps recorded:
+ * t >= 2 and the last lbm_step / lbm_load left them, else LBM_E_STATE).
+ *   sizes[nsizes] : host, box sides 1 <= L <= min(nx, ny).
+ *   out[nsizes]   : host, statistics per L.
+ *   dmaps : device FP64 [nsizes][3][ny][nx] maps of delta^E, delta^Omega, Ma
+ *           per window corner (y0, x0), or NULL.  For L == nx == ny only
+ *           element [0][0] of each map is meaningful.
+ *   windows[nwin][3] : host (x0, y0, L) triples, or NULL with nwin = 0.
+ *   wterms[nwin][13] : host box means of the 13 fields at those windows.
+ *   term_fields : device FP64 [13][ny][nx] pointwise integrand fields, or NULL.
+ * Synchronous.  Returns LBM_E_DIVERGED if the moments at t are not finite. */
+LBM_API int lbm_subvolume_balance(lbm_ctx ctx, const int32_t* sizes, int32_t nsizes,
+                          lbm_balance_stats* out, double* dmaps,
+                          const int32_t* windows, int32_t nwin, double* wterms,
+                          double* term_fields);
+
+/* Current time step. */
+LBM_API int lbm_time(lbm_ctx ctx, int64_t* t);
+
+/* Checkpoint: bytes of the state (populations, time, recorded history), and
+ * asynchronous copies of it to / from caller device memory.  lbm_load
+ * restores exactly what lbm_save stored (same configuration only). */
+LBM_API int lbm_state_bytes(lbm_ctx ctx, size_t* bytes);
+LBM_API int lbm_save(lbm_ctx ctx, void* dst_device);
+LBM_API int lbm_load(lbm_ctx ctx, const void* src_device);
+
+/* Launch shape of the step kernel: set explicitly, or choose by timing every
+ * candidate shape on this grid (trial_steps steps each, state unchanged) and
+ * keep the fastest; `chosen` (host, may be NULL) receives it.  The choice is
+ * remembered in a process-wide table keyed by (dtype, nx, ny, force) and, if
+ * the environment variable LBM_TUNE_CACHE names a file, in that file. */
+LBM_API int lbm_set_tile(lbm_ctx ctx, const lbm_tile* tile);
+LBM_API int lbm_get_tile(lbm_ctx ctx, lbm_tile* tile);
+LBM_API int lbm_autotune(lbm_ctx ctx, int32_t trial_steps, lbm_tile* chosen);
+
+/* hipGraph replay of `chunk` (even, >= 2) step launches for long lbm_step
+ * calls; chunk = 0 launches every step directly. */
+LBM_API int lbm_set_graph(lbm_ctx ctx, int32_t chunk);
+
+/* Device-timed step kernels: while enabled, lbm_step brackets its step
+ * launches with HIP events on the handle's stream.  lbm_step_time
+ * synchronises and returns the summed milliseconds and kernel launches since
+ * the last reset (reset = 1 clears them afterwards). */
+LBM_API int lbm_step_timing(lbm_ctx ctx, int32_t enable);
+LBM_API int lbm_step_time(lbm_ctx ctx, double* ms, int64_t* launches, int32_t reset);
+
+/* Free the handle (not the caller's workspace).  Synchronises its stream. */
+LBM_API int lbm_destroy(lbm_ctx ctx);
+
+/* ---- balance of caller-given fields ------------------------------------------ */
+/* Inputs of the stateless balance: three time levels ordered (n-2, n-1, n). */
+typedef struct {
+  int32_t nx, ny;
+  double nu;                /* kinematic viscosity (Eq. 5)                      */
+  const double* rho[3];     /* device FP64 [ny][nx] per level                   */
+  const double* ux[3];
+  const double* uy[3];
+  const double* fx;         /* device FP64 [ny][nx] total body force at level n, */
+  const double* fy;         /* or NULL for none                                 */
+  void* stream;
+} lbm_balance_input;
+
+/* Device workspace of lbm_balance_fields for an nx x ny grid. */
+LBM_API int lbm_balance_workspace_bytes(int32_t nx, int32_t ny, size_t* bytes);
+
+/* The sub-volume balance of lbm_subvolume_balance on given fields (same
+ * outputs, same window definition).  Synchronous. */
+LBM_API int lbm_balance_fields(const lbm_balance_input* in, void* ws, size_t ws_bytes,
+                       const int32_t* sizes, int32_t nsizes, lbm_balance_stats* out,
+                       double* dmaps, const int32_t* windows, int32_t nwin,
+                       double* wterms, double* term_fields);
+
+/* ---- batched ensemble ---------------------------------------------------------- */
+/* Many independent grids (sizes, tau, drag and force may differ per run; the
+ * storage type must be the same) advanced together.  Mode LBM_BATCH_PERSISTENT
+ * runs `chunk` steps of every run in one launch of a persistent kernel whose
+ * workgroups take equal slices of a (run, row-band) work list and meet at a
+ * grid-wide barrier between steps; the barrier waits are bounded and report
+ * LBM_E_TIMEOUT instead of hanging.  Mode LBM_BATCH_PER_STEP launches one
+ * kernel per step over the same work list.  Both are replayed from hipGraphs. */
+enum { LBM_BATCH_PERSISTENT = 0, LBM_BATCH_PER_STEP = 1 };
+typedef struct lbm_batch_s* lbm_batch;
+
+/* cfgs[nruns]: per-run configuration; with_balance must be 0, stream is taken
+ * from cfgs[0]. */
+LBM_API int lbm_batch_workspace_bytes(const lbm_config* cfgs, int32_t nruns, size_t* bytes);
+/* rho0/ux0/uy0/fx/fy: host arrays of nruns device FP64 pointers (fx/fy NULL,
+ * or entries NULL for runs without force). */
+LBM_API int lbm_batch_init(const lbm_config* cfgs, int32_t nruns, void* ws, size_t ws_bytes,
+                   const double* const* rho0, const double* const* ux0,
+                   const double* const* uy0, const double* const* fx,
+                   const double* const* fy, lbm_batch* out);
+LBM_API int lbm_batch_set_mode(lbm_batch b, int32_t mode, int32_t chunk);
+LBM_API int lbm_batch_set_tile(lbm_batch b, int32_t block_threads, int32_t vx, int32_t band_rows);
+LBM_API int lbm_batch_autotune(lbm_batch b, int32_t trial_steps, int32_t* block_threads,
+                       int32_t* vx, int32_t* band_rows);
+LBM_API int lbm_batch_step(lbm_batch b, int64_t n);
+LBM_API int lbm_batch_moments(lbm_batch b, int32_t run, void* rho, void* ux, void* uy,
+                      int32_t out_dtype, double* scalars8);
+LBM_API int lbm_batch_time(lbm_batch b, int64_t* t);
+LBM_API int64_t lbm_batch_sites(lbm_batch b);
+LBM_API int lbm_batch_destroy(lbm_batch b);
+
+/* ---- adjoint ---------------------------------------------------------------------- */
+/* Differentiable unforced run: f(0) = f^eq(rho = 1, u0), `steps` steps of
+ * Eq. 1, then the loss J = mean over all box x box windows of
+ * (RHS^Omega_V - LHS^Omega_V)^2 (Eq. 11 residual at the last step; a box of
+ * side nx == ny is one window).  The gradient is obtained by a discrete
+ * adjoint sweep: checkpoints of the populations every ckpt_every steps, each
+ * segment recomputed forward and swept backward. */
+typedef struct {
+  int32_t nx, ny;
+  int32_t dtype;        /* LBM_F32 or LBM_F64 populations and adjoint states   */
+  int32_t box;          /* window side L of the loss                           */
+  int32_t ckpt_every;   /* K >= 1                                              */
+  int32_t reserved;
+  int64_t steps;        /* T >= 2                                              */
+  double tau;
+  void* stream;
+} lbm_adjoint_config;
+
+LBM_API int lbm_adjoint_workspace_bytes(const lbm_adjoint_config* cfg, size_t* bytes);
+
+/* ux0, uy0 : device FP64 [ny][nx] initial velocity.
+ * loss : host double, receives J.
+ * grad_ux0, grad_uy0 : device FP64 [ny][nx] dJ/du0, or both NULL for the loss only.
+ * grad_tau : host double dJ/dtau, or NULL.
+ * Synchronous. */
+LBM_API int lbm_adjoint_run(const lbm_adjoint_config* cfg, void* ws, size_t ws_bytes,
+                    const double* ux0, const double* uy0, double* loss,
+                    double* grad_ux0, double* grad_uy0, double* grad_tau);
+
+/* ---- bandwidth reference ----------------------------------------------------------- */
+/* Plain device-to-device copy of `bytes` (a multiple of 16) with 16-byte
+ * vector loads and stores, on `stream`: the achievable-bandwidth reference
+ * for the step kernel.  Asynchronous. */
+LBM_API int lbm_copy(void* dst, const void* src, size_t bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

@@ -115,15 +115,17 @@ def forcing_field(n: int, seed: int = 0, kmin: float = 4.0, kmax: float = 6.0,
     rng = np.random.default_rng(seed)
     vecs = shell_vectors(kmin, kmax)
     phases = rng.uniform(0.0, 2.0 * math.pi, size=len(vecs))
-    idx = np.arange(n, dtype=np.float64)
-    y, x = np.meshgrid(idx, idx, indexing="ij")
-    fx = np.zeros((n, n))
-    fy = np.zeros((n, n))
+    # The trigonometric sum is evaluated by one inverse FFT of its (sparse)
+    # coefficient array: d/dy cos(w k.x + phi) = Re(i w k_y exp(i (w k.x + phi))).
     w = 2.0 * math.pi / n
+    ax = np.zeros((n, n), dtype=np.complex128)
+    ay = np.zeros((n, n), dtype=np.complex128)
     for (kx, ky), ph in zip(vecs, phases):
-        s = np.sin(w * (kx * x + ky * y) + ph)
-        fx -= w * ky * s          # d/dy cos(.) = -w ky sin(.)
-        fy += w * kx * s          # -d/dx cos(.) = +w kx sin(.)
+        e = np.exp(1j * ph) * n * n
+        ax[ky % n, kx % n] += 1j * w * ky * e      # F_x = d_y Psi
+        ay[ky % n, kx % n] += -1j * w * kx * e     # F_y = -d_x Psi
+    fx = np.real(np.fft.ifft2(ax))
+    fy = np.real(np.fft.ifft2(ay))
     scale = max_force / np.sqrt(fx * fx + fy * fy).max()
     return fx * scale, fy * scale
 

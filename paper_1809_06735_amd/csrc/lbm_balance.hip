@@ -1,0 +1,629 @@
+// Sub-volume energy / enstrophy balance on gfx950 (FP64 throughout).
+//
+//   pass A  : pointwise terms and the level-n fields needed by later passes
+//             (8th-order centred differences of Eq. 18, three-level time
+//             derivative of Eq. 17)
+//   pass B  : terms that difference products of pass-A fields
+//   pass C  : the diffusion term of the enstrophy balance (third composed
+//             difference, total stencil radius 12)
+//   means   : domain mean of each of the 13 fields (deterministic two-level sum)
+//   SAT     : mean-centred inclusive 2D prefix sums, one (ny+1) x (nx+1) table
+//             per field (row scan, then column scan)
+//   windows : for each box side L and every window corner, 13 box means from
+//             4 table lookups each (periodic wrap through the table totals),
+//             the balancing errors of Eqs. 12-13 and the Mach number of
+//             Eq. 20, reduced to count / mean / M2 / min / max / NaN per block
+//             and merged in a fixed order.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <vector>
+
+#include "lbm_internal.h"
+
+namespace lbm {
+namespace {
+
+constexpr int NT = LBM_NTERMS;
+enum { A_E = 0, A_OM2 = 1, A_W = 2, A_SXX = 3, A_SYY = 4, A_SXY = 5, A_HX = 6, A_HY = 7, NAUX = 8 };
+
+__device__ __forceinline__ int wrap_add(int i, int m, int n) {
+  int j = i + m;
+  j -= j >= n ? n : 0;
+  j += j < 0 ? n : 0;
+  return j;
+}
+
+// Eq. 18 applied to a value accessor g(x, y) along x or y.
+template <class G>
+__device__ __forceinline__ double fd8_x(const G& g, int x, int y, int nx) {
+  const double d1 = g(wrap_add(x, 1, nx), y) - g(wrap_add(x, -1, nx), y);
+  const double d2 = g(wrap_add(x, 2, nx), y) - g(wrap_add(x, -2, nx), y);
+  const double d3 = g(wrap_add(x, 3, nx), y) - g(wrap_add(x, -3, nx), y);
+  const double d4 = g(wrap_add(x, 4, nx), y) - g(wrap_add(x, -4, nx), y);
+  return (4.0 * d1 - d2 + (4.0 / 21.0) * d3 - (1.0 / 56.0) * d4) / 5.0;
+}
+template <class G>
+__device__ __forceinline__ double fd8_y(const G& g, int x, int y, int ny) {
+  const double d1 = g(x, wrap_add(y, 1, ny)) - g(x, wrap_add(y, -1, ny));
+  const double d2 = g(x, wrap_add(y, 2, ny)) - g(x, wrap_add(y, -2, ny));
+  const double d3 = g(x, wrap_add(y, 3, ny)) - g(x, wrap_add(y, -3, ny));
+  const double d4 = g(x, wrap_add(y, 4, ny)) - g(x, wrap_add(y, -4, ny));
+  return (4.0 * d1 - d2 + (4.0 / 21.0) * d3 - (1.0 / 56.0) * d4) / 5.0;
+}
+
+struct F1 {
+  const double* __restrict__ a;
+  int nx;
+  __device__ double operator()(int x, int y) const { return a[static_cast<size_t>(y) * nx + x]; }
+};
+struct F2 {  // a * b
+  const double* __restrict__ a;
+  const double* __restrict__ b;
+  int nx;
+  __device__ double operator()(int x, int y) const {
+    const size_t i = static_cast<size_t>(y) * nx + x;
+    return a[i] * b[i];
+  }
+};
+struct FSum2 {  // a * b + c * d
+  const double* __restrict__ a;
+  const double* __restrict__ b;
+  const double* __restrict__ c;
+  const double* __restrict__ d;
+  int nx;
+  __device__ double operator()(int x, int y) const {
+    const size_t i = static_cast<size_t>(y) * nx + x;
+    return a[i] * b[i] + c[i] * d[i];
+  }
+};
+struct FDiv {  // a / b
+  const double* __restrict__ a;
+  const double* __restrict__ b;
+  int nx;
+  __device__ double operator()(int x, int y) const {
+    const size_t i = static_cast<size_t>(y) * nx + x;
+    return a[i] / b[i];
+  }
+};
+
+struct PassArgs {
+  const double* rho[3];
+  const double* ux[3];
+  const double* uy[3];
+  const double* fx;
+  const double* fy;
+  double nu;
+  int nx, ny;
+  double* terms;
+  double* aux;
+};
+
+__global__ void __launch_bounds__(256) k_bal_a(PassArgs a) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  if (x >= a.nx || y >= a.ny) return;
+  const int nx = a.nx, ny = a.ny;
+  const size_t plane = static_cast<size_t>(nx) * ny;
+  const size_t i = static_cast<size_t>(y) * nx + x;
+  double om[3], en[3], ens[3];
+  double dxux = 0, dyux = 0, dxuy = 0, dyuy = 0;
+  for (int k = 0; k < 3; ++k) {
+    F1 gx{a.ux[k], nx}, gy{a.uy[k], nx};
+    const double dy_ux = fd8_y(gx, x, y, ny);
+    const double dx_uy = fd8_x(gy, x, y, nx);
+    om[k] = dx_uy - dy_ux;
+    ens[k] = 0.5 * om[k] * om[k];
+    const double vx = a.ux[k][i], vy = a.uy[k][i];
+    en[k] = 0.5 * a.rho[k][i] * (vx * vx + vy * vy);
+    if (k == 2) {
+      dxux = fd8_x(gx, x, y, nx);
+      dyux = dy_ux;
+      dxuy = dx_uy;
+      dyuy = fd8_y(gy, x, y, ny);
+    }
+  }
+  const double r = a.rho[2][i], vx = a.ux[2][i], vy = a.uy[2][i];
+  F1 gr{a.rho[2], nx};
+  const double dxp = fd8_x(gr, x, y, nx) / 3.0;
+  const double dyp = fd8_y(gr, x, y, ny) / 3.0;
+  const double nu = a.nu;
+  const double sxx = 2.0 * nu * r * dxux;
+  const double syy = 2.0 * nu * r * dyuy;
+  const double sxy = nu * r * (dxuy + dyux);
+  double fxv = 0.0, fyv = 0.0;
+  if (a.fx) {
+    fxv = a.fx[i];
+    fyv = a.fy[i];
+  }
+  double* t = a.terms;
+  t[LBM_T_LHS_E * plane + i] = (3.0 * en[2] - 4.0 * en[1] + en[0]) / 2.0;
+  t[LBM_T_E2 * plane + i] = -(vx * dxp + vy * dyp);
+  t[LBM_T_E3 * plane + i] = vx * fxv + vy * fyv;
+  t[LBM_T_E4 * plane + i] = -(sxx * dxux + sxy * dyux + sxy * dxuy + syy * dyuy);
+  t[LBM_T_LHS_Z * plane + i] = (3.0 * ens[2] - 4.0 * ens[1] + ens[0]) / 2.0;
+  t[LBM_T_Z2 * plane + i] = -ens[2] * (dxux + dyuy);
+  t[LBM_T_USQ * plane + i] = vx * vx + vy * vy;
+  double* ax = a.aux;
+  ax[A_E * plane + i] = en[2];
+  ax[A_OM2 * plane + i] = ens[2];
+  ax[A_W * plane + i] = om[2];
+  ax[A_SXX * plane + i] = sxx;
+  ax[A_SYY * plane + i] = syy;
+  ax[A_SXY * plane + i] = sxy;
+}
+
+__global__ void __launch_bounds__(256) k_bal_b(PassArgs a) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  if (x >= a.nx || y >= a.ny) return;
+  const int nx = a.nx, ny = a.ny;
+  const size_t plane = static_cast<size_t>(nx) * ny;
+  const size_t i = static_cast<size_t>(y) * nx + x;
+  const double* ux = a.ux[2];
+  const double* uy = a.uy[2];
+  const double* rho = a.rho[2];
+  const double* ax = a.aux;
+  const double* E = ax + A_E * plane;
+  const double* Om = ax + A_OM2 * plane;
+  const double* W = ax + A_W * plane;
+  const double* sxx = ax + A_SXX * plane;
+  const double* syy = ax + A_SYY * plane;
+  const double* sxy = ax + A_SXY * plane;
+
+  const double e1 = -(fd8_x(F2{E, ux, nx}, x, y, nx) + fd8_y(F2{E, uy, nx}, x, y, ny));
+  const double e5 = fd8_x(FSum2{ux, sxx, uy, sxy, nx}, x, y, nx) +
+                    fd8_y(FSum2{ux, sxy, uy, syy, nx}, x, y, ny);
+  const double z1 = -(fd8_x(F2{Om, ux, nx}, x, y, nx) + fd8_y(F2{Om, uy, nx}, x, y, ny));
+  const double r = rho[i];
+  const double hx = (fd8_x(F1{sxx, nx}, x, y, nx) + fd8_y(F1{sxy, nx}, x, y, ny)) / r;
+  const double hy = (fd8_x(F1{sxy, nx}, x, y, nx) + fd8_y(F1{syy, nx}, x, y, ny)) / r;
+  const double dxw = fd8_x(F1{W, nx}, x, y, nx);
+  const double dyw = fd8_y(F1{W, nx}, x, y, ny);
+  const double w = W[i];
+  double z3 = 0.0;
+  if (a.fx) z3 = w * (fd8_x(FDiv{a.fy, rho, nx}, x, y, nx) - fd8_y(FDiv{a.fx, rho, nx}, x, y, ny));
+  double* t = a.terms;
+  t[LBM_T_E1 * plane + i] = e1;
+  t[LBM_T_E5 * plane + i] = e5;
+  t[LBM_T_Z1 * plane + i] = z1;
+  t[LBM_T_Z3 * plane + i] = z3;
+  t[LBM_T_Z4 * plane + i] = hx * dyw - hy * dxw;
+  a.aux[A_HX * plane + i] = hx;
+  a.aux[A_HY * plane + i] = hy;
+}
+
+__global__ void __launch_bounds__(256) k_bal_c(PassArgs a) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  if (x >= a.nx || y >= a.ny) return;
+  const int nx = a.nx, ny = a.ny;
+  const size_t plane = static_cast<size_t>(nx) * ny;
+  const size_t i = static_cast<size_t>(y) * nx + x;
+  const double* W = a.aux + A_W * plane;
+  const double* hx = a.aux + A_HX * plane;
+  const double* hy = a.aux + A_HY * plane;
+  a.terms[LBM_T_Z5 * plane + i] = fd8_x(F2{W, hy, nx}, x, y, nx) - fd8_y(F2{W, hx, nx}, x, y, ny);
+}
+
+// ---- field means ---------------------------------------------------------------------
+constexpr int kRedThreads = 256;
+constexpr int kMeanBlocks = 512;
+
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// partials[field][block] = sum over the block's slice of field
+__global__ void __launch_bounds__(kRedThreads) k_field_sums(const double* __restrict__ f, size_t n,
+                                                             double* partials) {
+  __shared__ double sh[kRedThreads / 64];
+  const double* g = f + blockIdx.y * n;
+  double acc = 0.0;
+  for (size_t i = blockIdx.x * size_t(kRedThreads) + threadIdx.x; i < n;
+       i += size_t(gridDim.x) * kRedThreads)
+    acc += g[i];
+  acc = wsum(acc);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < kRedThreads / 64; ++w) s += sh[w];
+    partials[blockIdx.y * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+__global__ void __launch_bounds__(kRedThreads) k_field_means(const double* __restrict__ partials,
+                                                              int nblocks, double inv_n,
+                                                              double* means) {
+  __shared__ double sh[kRedThreads / 64];
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += kRedThreads) acc += partials[blockIdx.x * nblocks + b];
+  acc = wsum(acc);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < kRedThreads / 64; ++w) s += sh[w];
+    means[blockIdx.x] = s * inv_n;
+  }
+}
+
+// ---- summed-area tables ------------------------------------------------------------------
+// Row pass: P[f][y+1][x+1] = sum_{x' <= x} (g[f][y][x'] - mean_f); P[f][0][*] = P[f][*][0] = 0.
+__global__ void __launch_bounds__(256) k_sat_rows(const double* __restrict__ g,
+                                                  const double* __restrict__ means, double* sat,
+                                                  int nx, int ny) {
+  __shared__ double sh[256];
+  const int y = blockIdx.x;
+  const int f = blockIdx.y;
+  const size_t plane = static_cast<size_t>(nx) * ny;
+  const size_t splane = static_cast<size_t>(nx + 1) * (ny + 1);
+  const double mean = means[f];
+  const double* row = g + f * plane + static_cast<size_t>(y) * nx;
+  double* out = sat + f * splane + static_cast<size_t>(y + 1) * (nx + 1);
+  double* top = sat + f * splane;
+  const int chunk = (nx + 255) / 256;
+  const int xa = threadIdx.x * chunk;
+  const int xb = min(xa + chunk, nx);
+  double s = 0.0;
+  for (int xx = xa; xx < xb; ++xx) s += row[xx] - mean;
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  // inclusive scan of chunk sums (Hillis-Steele over 256 entries)
+  for (int off = 1; off < 256; off <<= 1) {
+    const double v = threadIdx.x >= off ? sh[threadIdx.x - off] : 0.0;
+    __syncthreads();
+    sh[threadIdx.x] += v;
+    __syncthreads();
+  }
+  double acc = threadIdx.x > 0 ? sh[threadIdx.x - 1] : 0.0;
+  for (int xx = xa; xx < xb; ++xx) {
+    acc += row[xx] - mean;
+    out[xx + 1] = acc;
+  }
+  if (threadIdx.x == 0) out[0] = 0.0;
+  if (y == 0)
+    for (int xx = threadIdx.x; xx <= nx; xx += 256) top[xx] = 0.0;
+}
+
+// Column pass: 64 columns x G row-groups per block; each group sums its
+// segment, the group totals are scanned in LDS, then each group rewrites its
+// segment as running sums.
+constexpr int kColG = 4;
+__global__ void __launch_bounds__(64 * kColG) k_sat_cols(double* sat, int nx, int ny) {
+  __shared__ double sh[kColG][64];
+  const int c = blockIdx.x * 64 + threadIdx.x;
+  const int gidx = threadIdx.y;
+  const int f = blockIdx.y;
+  const size_t splane = static_cast<size_t>(nx + 1) * (ny + 1);
+  double* P = sat + f * splane;
+  const int seg = (ny + kColG - 1) / kColG;
+  const int ya = 1 + gidx * seg;
+  const int yb = min(ya + seg, ny + 1);
+  const bool active = c <= nx;
+  double s = 0.0;
+  if (active)
+    for (int yy = ya; yy < yb; ++yy) s += P[static_cast<size_t>(yy) * (nx + 1) + c];
+  sh[gidx][threadIdx.x] = s;
+  __syncthreads();
+  double off = 0.0;
+  for (int k = 0; k < gidx; ++k) off += sh[k][threadIdx.x];
+  if (active) {
+    double acc = off;
+    for (int yy = ya; yy < yb; ++yy) {
+      double* p = P + static_cast<size_t>(yy) * (nx + 1) + c;
+      acc += *p;
+      *p = acc;
+    }
+  }
+}
+
+// ---- windows -----------------------------------------------------------------------------------
+struct SatView {
+  const double* P;  // [NT][ny+1][nx+1]
+  const double* means;
+  int nx, ny;
+  size_t splane;
+  // Q(y, x) for 0 <= y < 2 ny, 0 <= x < 2 nx: the periodic continuation of the
+  // prefix table through its totals.
+  __device__ __forceinline__ double Q(int f, int y, int x) const {
+    const double* p = P + f * splane;
+    const int qy = y > ny ? 1 : 0;
+    const int qx = x > nx ? 1 : 0;
+    const int ym = y - qy * ny;
+    const int xm = x - qx * nx;
+    const size_t s = nx + 1;
+    double v = p[ym * s + xm];
+    if (qy) v += p[static_cast<size_t>(ny) * s + xm];
+    if (qx) v += p[ym * s + nx];
+    if (qy && qx) v += p[static_cast<size_t>(ny) * s + nx];
+    return v;
+  }
+  __device__ __forceinline__ double box_mean(int f, int x0, int y0, int L) const {
+    const double s = Q(f, y0 + L, x0 + L) - Q(f, y0, x0 + L) - Q(f, y0 + L, x0) + Q(f, y0, x0);
+    return means[f] + s / (double(L) * double(L));
+  }
+};
+
+__device__ void window_errors(const double (&m)[NT], double& dE, double& dZ, double& ma) {
+  const double rE = (((m[LBM_T_E1] + m[LBM_T_E2]) + m[LBM_T_E3]) + m[LBM_T_E4]) + m[LBM_T_E5];
+  const double denE = fmax(fmax(fmax(fabs(m[LBM_T_E1]), fabs(m[LBM_T_E2])),
+                                fmax(fabs(m[LBM_T_E3]), fabs(m[LBM_T_E4]))),
+                           fabs(m[LBM_T_E5]));
+  const double rZ = (((m[LBM_T_Z1] + m[LBM_T_Z2]) + m[LBM_T_Z3]) + m[LBM_T_Z4]) + m[LBM_T_Z5];
+  const double denZ = fmax(fmax(fmax(fabs(m[LBM_T_Z1]), fabs(m[LBM_T_Z2])),
+                                fmax(fabs(m[LBM_T_Z3]), fabs(m[LBM_T_Z4]))),
+                           fabs(m[LBM_T_Z5]));
+  dE = denE > 0.0 ? fabs(rE - m[LBM_T_LHS_E]) / denE : __builtin_nan("");
+  dZ = denZ > 0.0 ? fabs(rZ - m[LBM_T_LHS_Z]) / denZ : __builtin_nan("");
+  ma = sqrt(m[LBM_T_USQ]) * 1.7320508075688772;  // / c_s, c_s = 1/sqrt(3)
+}
+
+// Running statistics: n, mean, M2, min, max, nan count.
+struct RS {
+  double n, mean, m2, mn, mx, nan;
+  __device__ void init() {
+    n = mean = m2 = nan = 0.0;
+    mn = 1e300;
+    mx = -1e300;
+  }
+  __device__ void add(double v) {
+    if (!isfinite(v)) {
+      nan += 1.0;
+      return;
+    }
+    n += 1.0;
+    const double d = v - mean;
+    mean += d / n;
+    m2 += d * (v - mean);
+    mn = fmin(mn, v);
+    mx = fmax(mx, v);
+  }
+  __device__ void merge(const RS& b) {
+    const double nn = n + b.n;
+    if (b.n > 0.0) {
+      const double d = b.mean - mean;
+      mean = nn > 0.0 ? mean + d * (b.n / nn) : 0.0;
+      m2 = m2 + b.m2 + d * d * (n * b.n / nn);
+      n = nn;
+      mn = fmin(mn, b.mn);
+      mx = fmax(mx, b.mx);
+    }
+    nan += b.nan;
+  }
+};
+constexpr int kRS = 6;
+constexpr int kStatVals = 3 * kRS;  // dE, dZ, Ma
+
+__device__ void rs_shfl_merge(RS& r, int off) {
+  RS o;
+  o.n = __shfl_xor(r.n, off, 64);
+  o.mean = __shfl_xor(r.mean, off, 64);
+  o.m2 = __shfl_xor(r.m2, off, 64);
+  o.mn = __shfl_xor(r.mn, off, 64);
+  o.mx = __shfl_xor(r.mx, off, 64);
+  o.nan = __shfl_xor(r.nan, off, 64);
+  // merge in a lane-independent order so every lane of a pair ends equal
+  if ((threadIdx.x & off) == 0) {
+    r.merge(o);
+  } else {
+    o.merge(r);
+    r = o;
+  }
+}
+
+__device__ void block_stats(RS (&r)[3], double* out) {
+  __shared__ double sh[4][3][kRS];
+  for (int q = 0; q < 3; ++q)
+    for (int off = 1; off < 64; off <<= 1) rs_shfl_merge(r[q], off);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0)
+    for (int q = 0; q < 3; ++q) {
+      sh[wv][q][0] = r[q].n;
+      sh[wv][q][1] = r[q].mean;
+      sh[wv][q][2] = r[q].m2;
+      sh[wv][q][3] = r[q].mn;
+      sh[wv][q][4] = r[q].mx;
+      sh[wv][q][5] = r[q].nan;
+    }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = blockDim.x / 64;
+    for (int q = 0; q < 3; ++q) {
+      RS acc;
+      acc.init();
+      for (int w = 0; w < nw; ++w) {
+        RS b{sh[w][q][0], sh[w][q][1], sh[w][q][2], sh[w][q][3], sh[w][q][4], sh[w][q][5]};
+        acc.merge(b);
+      }
+      out[q * kRS + 0] = acc.n;
+      out[q * kRS + 1] = acc.mean;
+      out[q * kRS + 2] = acc.m2;
+      out[q * kRS + 3] = acc.mn;
+      out[q * kRS + 4] = acc.mx;
+      out[q * kRS + 5] = acc.nan;
+    }
+  }
+}
+
+constexpr int kWinThreads = 256;
+constexpr int kWinMaxBlocks = 1024;
+
+__global__ void __launch_bounds__(kWinThreads) k_windows(SatView v, int L, int single,
+                                                         double* maps, double* partials) {
+  RS r[3];
+  for (int q = 0; q < 3; ++q) r[q].init();
+  const size_t plane = static_cast<size_t>(v.nx) * v.ny;
+  const size_t count = single ? 1 : plane;
+  for (size_t i = blockIdx.x * size_t(kWinThreads) + threadIdx.x; i < count;
+       i += size_t(gridDim.x) * kWinThreads) {
+    const int x0 = static_cast<int>(i % v.nx);
+    const int y0 = static_cast<int>(i / v.nx);
+    double m[NT];
+#pragma unroll
+    for (int f = 0; f < NT; ++f) m[f] = v.box_mean(f, x0, y0, L);
+    double dE, dZ, ma;
+    window_errors(m, dE, dZ, ma);
+    r[0].add(dE);
+    r[1].add(dZ);
+    r[2].add(ma);
+    if (maps) {
+      maps[i] = dE;
+      maps[plane + i] = dZ;
+      maps[2 * plane + i] = ma;
+    }
+  }
+  block_stats(r, partials + blockIdx.x * kStatVals);
+}
+
+__global__ void __launch_bounds__(kWinThreads) k_stats_final(const double* __restrict__ partials,
+                                                             int nblocks, double* out) {
+  RS r[3];
+  for (int q = 0; q < 3; ++q) r[q].init();
+  for (int b = threadIdx.x; b < nblocks; b += kWinThreads)
+    for (int q = 0; q < 3; ++q) {
+      const double* p = partials + b * kStatVals + q * kRS;
+      RS o{p[0], p[1], p[2], p[3], p[4], p[5]};
+      r[q].merge(o);
+    }
+  block_stats(r, out);
+}
+
+__global__ void k_window_terms(SatView v, const int32_t* __restrict__ win, int nwin, double* out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nwin) return;
+  const int x0 = win[3 * k], y0 = win[3 * k + 1], L = win[3 * k + 2];
+  for (int f = 0; f < NT; ++f) out[k * NT + f] = v.box_mean(f, x0, y0, L);
+}
+
+int stat_blocks(size_t count) {
+  size_t b = (count + kWinThreads - 1) / kWinThreads;
+  if (b > kWinMaxBlocks) b = kWinMaxBlocks;
+  return static_cast<int>(b < 1 ? 1 : b);
+}
+
+}  // namespace
+
+size_t balance_ws_bytes(int nx, int ny) {
+  Carver c(nullptr, 0);
+  carve_balance(c, nx, ny);
+  return c.used + 256;
+}
+
+BalanceWs carve_balance(Carver& c, int nx, int ny) {
+  const size_t plane = static_cast<size_t>(nx) * ny;
+  const size_t splane = static_cast<size_t>(nx + 1) * (ny + 1);
+  BalanceWs w;
+  w.terms = c.take<double>(NT * plane);
+  w.aux = c.take<double>(NAUX * plane);
+  w.sat = c.take<double>(NT * splane);
+  w.means = c.take<double>(16);
+  w.partials = c.take<double>(static_cast<size_t>(kWinMaxBlocks) * kStatVals +
+                              static_cast<size_t>(NT) * kMeanBlocks);
+  w.stats = c.take<double>(static_cast<size_t>(kMaxSizes) * kStatVals);
+  w.wterms = c.take<double>(static_cast<size_t>(kMaxWindows) * NT);
+  w.windows = c.take<int32_t>(static_cast<size_t>(kMaxWindows) * 3);
+  return w;
+}
+
+int run_balance(const lbm_balance_input& in, const BalanceWs& ws, const int32_t* sizes,
+                int nsizes, lbm_balance_stats* out, double* dmaps, const int32_t* windows,
+                int nwin, double* wterms, double* term_fields) {
+  hipStream_t s = static_cast<hipStream_t>(in.stream);
+  const int nx = in.nx, ny = in.ny;
+  const size_t plane = static_cast<size_t>(nx) * ny;
+  PassArgs a;
+  for (int k = 0; k < 3; ++k) {
+    a.rho[k] = in.rho[k];
+    a.ux[k] = in.ux[k];
+    a.uy[k] = in.uy[k];
+  }
+  a.fx = in.fx;
+  a.fy = in.fy;
+  a.nu = in.nu;
+  a.nx = nx;
+  a.ny = ny;
+  a.terms = ws.terms;
+  a.aux = ws.aux;
+  dim3 blk(64, 4), grd((nx + 63) / 64, (ny + 3) / 4);
+  hipLaunchKernelGGL(k_bal_a, grd, blk, 0, s, a);
+  LBM_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_bal_b, grd, blk, 0, s, a);
+  LBM_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_bal_c, grd, blk, 0, s, a);
+  LBM_HIP(hipGetLastError());
+  if (term_fields)
+    LBM_HIP(hipMemcpyAsync(term_fields, ws.terms, NT * plane * sizeof(double),
+                           hipMemcpyDeviceToDevice, s));
+
+  // means
+  int mb = static_cast<int>((plane + kRedThreads - 1) / kRedThreads);
+  if (mb > kMeanBlocks) mb = kMeanBlocks;
+  double* mpart = ws.partials + static_cast<size_t>(kWinMaxBlocks) * kStatVals;
+  hipLaunchKernelGGL(k_field_sums, dim3(mb, NT), dim3(kRedThreads), 0, s, ws.terms, plane, mpart);
+  LBM_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_field_means, dim3(NT), dim3(kRedThreads), 0, s, mpart, mb,
+                     1.0 / double(plane), ws.means);
+  LBM_HIP(hipGetLastError());
+  // SAT
+  hipLaunchKernelGGL(k_sat_rows, dim3(ny, NT), dim3(256), 0, s, ws.terms, ws.means, ws.sat, nx, ny);
+  LBM_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_sat_cols, dim3((nx + 1 + 63) / 64, NT), dim3(64, kColG), 0, s, ws.sat, nx,
+                     ny);
+  LBM_HIP(hipGetLastError());
+
+  SatView v{ws.sat, ws.means, nx, ny, static_cast<size_t>(nx + 1) * (ny + 1)};
+  for (int k = 0; k < nsizes; ++k) {
+    const int L = sizes[k];
+    const int single = (L == nx && L == ny) ? 1 : 0;
+    const size_t count = single ? 1 : plane;
+    const int nb = stat_blocks(count);
+    double* maps = dmaps ? dmaps + static_cast<size_t>(k) * 3 * plane : nullptr;
+    hipLaunchKernelGGL(k_windows, dim3(nb), dim3(kWinThreads), 0, s, v, L, single, maps,
+                       ws.partials);
+    LBM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(kWinThreads), 0, s, ws.partials, nb,
+                       ws.stats + static_cast<size_t>(k) * kStatVals);
+    LBM_HIP(hipGetLastError());
+  }
+  if (nwin > 0) {
+    LBM_HIP(hipMemcpyAsync(ws.windows, windows, sizeof(int32_t) * 3 * nwin, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_window_terms, dim3((nwin + 63) / 64), dim3(64), 0, s, v, ws.windows, nwin,
+                       ws.wterms);
+    LBM_HIP(hipGetLastError());
+  }
+  std::vector<double> st(static_cast<size_t>(nsizes) * kStatVals);
+  if (nsizes > 0)
+    LBM_HIP(hipMemcpyAsync(st.data(), ws.stats, st.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (nwin > 0)
+    LBM_HIP(hipMemcpyAsync(wterms, ws.wterms, sizeof(double) * NT * nwin, hipMemcpyDeviceToHost, s));
+  LBM_HIP(hipStreamSynchronize(s));
+  for (int k = 0; k < nsizes; ++k) {
+    const double* q = st.data() + static_cast<size_t>(k) * kStatVals;
+    lbm_balance_stats& o = out[k];
+    o = lbm_balance_stats{};
+    o.L = sizes[k];
+    auto fill = [](const double* r, int64_t& cnt, int64_t* nan, double& mean, double& sd, double& mn,
+                   double& mx) {
+      cnt = static_cast<int64_t>(r[0]);
+      if (nan) *nan = static_cast<int64_t>(r[5]);
+      if (cnt > 0) {
+        mean = r[1];
+        sd = std::sqrt(r[2] / r[0]);
+        mn = r[3];
+        mx = r[4];
+      } else {
+        mean = sd = mn = mx = NAN;
+      }
+    };
+    fill(q + 0 * kRS, o.count_dE, &o.nan_dE, o.mean_dE, o.std_dE, o.min_dE, o.max_dE);
+    fill(q + 1 * kRS, o.count_dZ, &o.nan_dZ, o.mean_dZ, o.std_dZ, o.min_dZ, o.max_dZ);
+    fill(q + 2 * kRS, o.count_Ma, nullptr, o.mean_Ma, o.std_Ma, o.min_Ma, o.max_Ma);
+  }
+  return LBM_OK;
+}
+
+}  // namespace lbm

@@ -1,0 +1,122 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/lbm.h"
+
+namespace lbm {
+
+// ---- error reporting ---------------------------------------------------------
+int fail(int code, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+
+#define LBM_HIP(call)                                   \
+  do {                                                  \
+    hipError_t e_ = (call);                             \
+    if (e_ != hipSuccess) return ::lbm::hip_fail(e_, #call); \
+  } while (0)
+
+// ---- D2Q9 lattice -----------------------------------------------------------
+// Velocities in the order rest, +x, +y, -x, -y, (+1,+1), (-1,+1), (-1,-1), (+1,-1);
+// weights 4/9, 1/9 (axis), 1/36 (diagonal).
+constexpr int Q = 9;
+__host__ __device__ constexpr int cxq(int l) {
+  return l == 1 || l == 5 || l == 8 ? 1 : (l == 3 || l == 6 || l == 7 ? -1 : 0);
+}
+__host__ __device__ constexpr int cyq(int l) {
+  return l == 2 || l == 5 || l == 6 ? 1 : (l == 4 || l == 7 || l == 8 ? -1 : 0);
+}
+__host__ __device__ constexpr double wq(int l) {
+  return l == 0 ? 4.0 / 9.0 : (l <= 4 ? 1.0 / 9.0 : 1.0 / 36.0);
+}
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Simple bump allocator over a caller workspace.
+struct Carver {
+  char* base;
+  size_t used = 0;
+  size_t cap;
+  Carver(void* b, size_t c) : base(static_cast<char*>(b)), cap(c) {}
+  template <typename T>
+  T* take(size_t count) {
+    used = align_up(used, 256);
+    T* p = base ? reinterpret_cast<T*>(base + used) : nullptr;
+    used += count * sizeof(T);
+    return p;
+  }
+};
+
+// ---- step kernels ---------------------------------------------------------------
+struct StepParams {
+  const void* src;   // populations (deviation from the weights), [9][ny][nx]
+  void* dst;
+  const void* fx;    // external force, storage type, or null
+  const void* fy;
+  double* h_rho;     // optional FP64 moment record (pre-collision, time t)
+  double* h_ux;
+  double* h_uy;
+  int nx, ny;
+  double omega;      // 1/tau
+  double alpha;      // drag
+};
+
+int launch_init(int dtype, void* pop, const double* rho0, const double* ux0,
+                const double* uy0, int nx, int ny, hipStream_t s);
+int launch_step(int dtype, bool force, const StepParams& p, const lbm_tile& t, hipStream_t s);
+bool tile_ok(const lbm_tile& t, int dtype, int nx, int ny);
+lbm_tile default_tile(int dtype, int nx, int ny);
+int tile_candidates(int dtype, int nx, int ny, lbm_tile* out, int cap);
+
+// Moments of the populations at their time: writes rho, ux, uy (out_dtype, any
+// may be null), optional FP64 copies and total force, and per-block partial
+// reductions (7 doubles per block) into `partials`; nblocks returned.
+struct MomentParams {
+  const void* pop;
+  const void* fx;
+  const void* fy;
+  void* rho;
+  void* ux;
+  void* uy;
+  int out_dtype;
+  double* rho64;     // optional FP64 copies (for the balance)
+  double* ux64;
+  double* uy64;
+  double* ftx64;     // optional FP64 total force F_ext - alpha rho u
+  double* fty64;
+  double* partials;  // [nblocks][8]
+  int nx, ny;
+  double alpha;
+};
+int moment_blocks(int nx, int ny);
+int launch_moments(int dtype, bool force, const MomentParams& p, hipStream_t s);
+int launch_reduce_scalars(const double* partials, int nblocks, double* out8, hipStream_t s);
+int launch_to_storage(int dtype, void* dst, const double* src, size_t n, hipStream_t s);
+
+int launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+
+// ---- balance --------------------------------------------------------------------
+struct BalanceWs {
+  double* terms;     // [13][ny][nx]
+  double* aux;       // [8][ny][nx]: E, Omega, omega, sxx, syy, sxy, Hx, Hy
+  double* sat;       // [13][ny+1][nx+1]
+  double* means;     // [16]
+  double* partials;  // block partials
+  double* stats;     // device stats scratch
+  double* wterms;    // [LBM_MAX_WINDOWS][13]
+  int32_t* windows;  // [LBM_MAX_WINDOWS][3]
+};
+constexpr int kMaxWindows = 4096;
+constexpr int kMaxSizes = 64;
+size_t balance_ws_bytes(int nx, int ny);
+BalanceWs carve_balance(Carver& c, int nx, int ny);
+int run_balance(const lbm_balance_input& in, const BalanceWs& ws, const int32_t* sizes,
+                int nsizes, lbm_balance_stats* out, double* dmaps, const int32_t* windows,
+                int nwin, double* wterms, double* term_fields);
+
+}  // namespace lbm

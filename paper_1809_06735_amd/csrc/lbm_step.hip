@@ -1,0 +1,557 @@
+// D2Q9 BGK step, initialisation, moments and copy kernels for gfx950.
+//
+// Storage: structure of arrays, plane l of [9][ny][nx] holds f_l - w_l (the
+// deviation from the rest state), x fastest.  The state at time t is kept
+// "un-streamed": plane l at site y holds f_l(y + c_l, t), so the pre-collision
+// populations at x are pulled from x - c_l, and one step is a single pass
+// that pulls, collides (Eq. 1 with the equilibrium of Eq. 2) and writes the
+// post-collision values back at x into the other buffer.  Every population is
+// read once and written once per step: 9 + 9 values per lattice update.
+#include <hip/hip_runtime.h>
+
+#include "lbm_internal.h"
+
+namespace lbm {
+namespace {
+
+// ---- vector types ---------------------------------------------------------------
+template <typename T, int VX> struct Vec;
+template <> struct Vec<float, 2> {
+  typedef float A __attribute__((ext_vector_type(2), aligned(8)));
+  typedef float U __attribute__((ext_vector_type(2), aligned(4)));
+};
+template <> struct Vec<float, 4> {
+  typedef float A __attribute__((ext_vector_type(4), aligned(16)));
+  typedef float U __attribute__((ext_vector_type(4), aligned(4)));
+};
+template <> struct Vec<double, 2> {
+  typedef double A __attribute__((ext_vector_type(2), aligned(16)));
+  typedef double U __attribute__((ext_vector_type(2), aligned(8)));
+};
+template <> struct Vec<double, 4> {
+  typedef double A __attribute__((ext_vector_type(4), aligned(32)));
+  typedef double U __attribute__((ext_vector_type(4), aligned(8)));
+};
+
+// o[i] = row[(x0 + i - cx) mod nx], i < VX; x0 is a multiple of VX.
+template <typename T, int VX, int CX>
+__device__ __forceinline__ void pull_row(const T* __restrict__ row, int x0, int nx, T (&o)[VX]) {
+  if constexpr (VX == 1) {
+    int xs = x0 - CX;
+    if (CX == 1 && xs < 0) xs += nx;
+    if (CX == -1 && xs >= nx) xs -= nx;
+    o[0] = row[xs];
+  } else {
+    typedef typename Vec<T, VX>::A VA;
+    typedef typename Vec<T, VX>::U VU;
+    if constexpr (CX == 0) {
+      VA v = *reinterpret_cast<const VA*>(row + x0);
+#pragma unroll
+      for (int i = 0; i < VX; ++i) o[i] = v[i];
+    } else if constexpr (CX == 1) {
+      if (x0 > 0) {
+        VU v = *reinterpret_cast<const VU*>(row + x0 - 1);
+#pragma unroll
+        for (int i = 0; i < VX; ++i) o[i] = v[i];
+      } else {
+        VA v = *reinterpret_cast<const VA*>(row);
+        o[0] = row[nx - 1];
+#pragma unroll
+        for (int i = 1; i < VX; ++i) o[i] = v[i - 1];
+      }
+    } else {
+      if (x0 + VX < nx) {
+        VU v = *reinterpret_cast<const VU*>(row + x0 + 1);
+#pragma unroll
+        for (int i = 0; i < VX; ++i) o[i] = v[i];
+      } else {
+        VA v = *reinterpret_cast<const VA*>(row + x0);
+#pragma unroll
+        for (int i = 0; i < VX - 1; ++i) o[i] = v[i + 1];
+        o[VX - 1] = row[0];
+      }
+    }
+  }
+}
+
+template <typename T, int VX>
+__device__ __forceinline__ void load_aligned(const T* __restrict__ p, T (&o)[VX]) {
+  if constexpr (VX == 1) {
+    o[0] = *p;
+  } else {
+    typedef typename Vec<T, VX>::A VA;
+    VA v = *reinterpret_cast<const VA*>(p);
+#pragma unroll
+    for (int i = 0; i < VX; ++i) o[i] = v[i];
+  }
+}
+
+template <typename T, int VX, bool NT>
+__device__ __forceinline__ void store_aligned(T* __restrict__ p, const T (&o)[VX]) {
+  if constexpr (VX == 1) {
+    if constexpr (NT) __builtin_nontemporal_store(o[0], p);
+    else *p = o[0];
+  } else {
+    typedef typename Vec<T, VX>::A VA;
+    VA v;
+#pragma unroll
+    for (int i = 0; i < VX; ++i) v[i] = o[i];
+    if constexpr (NT) __builtin_nontemporal_store(v, reinterpret_cast<VA*>(p));
+    else *reinterpret_cast<VA*>(p) = v;
+  }
+}
+
+// Pre-collision moments of one site from the deviations d_l = f_l - w_l.
+// rho = 1 + sum d; j = sum c d; half-force velocity with implicit drag:
+// u = (j + F_ext/2) / (rho (1 + alpha/2)), total force F = F_ext - alpha rho u.
+template <typename T, bool FORCE>
+struct SiteMoments {
+  T drho, rho, ux, uy, Fx, Fy;
+  __device__ __forceinline__ SiteMoments(const T (&d)[9], T fx, T fy, T alpha) {
+    drho = ((d[0] + (d[1] + d[3])) + (d[2] + d[4])) + ((d[5] + d[7]) + (d[6] + d[8]));
+    rho = T(1) + drho;
+    const T jx = (d[1] - d[3]) + ((d[5] - d[7]) + (d[8] - d[6]));
+    const T jy = (d[2] - d[4]) + ((d[5] - d[7]) + (d[6] - d[8]));
+    if constexpr (FORCE) {
+      const T inv = T(1) / (rho * (T(1) + T(0.5) * alpha));
+      ux = (jx + T(0.5) * fx) * inv;
+      uy = (jy + T(0.5) * fy) * inv;
+      Fx = fx - alpha * rho * ux;
+      Fy = fy - alpha * rho * uy;
+    } else {
+      const T inv = T(1) / rho;
+      ux = jx * inv;
+      uy = jy * inv;
+      Fx = T(0);
+      Fy = T(0);
+    }
+  }
+};
+
+// BGK collision (Eq. 1) towards the equilibrium of Eq. 2, with Guo's forcing
+// term (1 - 1/(2 tau)) w [3 (c - u) + 9 (c.u) c] . F, all in deviation form.
+template <typename T, bool FORCE>
+__device__ __forceinline__ void collide_site(const T (&d)[9], const SiteMoments<T, FORCE>& m,
+                                             T omega, T guo, T (&o)[9]) {
+  const T usq15 = T(1.5) * (m.ux * m.ux + m.uy * m.uy);
+  const T uF3 = FORCE ? T(3) * (m.ux * m.Fx + m.uy * m.Fy) : T(0);
+#pragma unroll
+  for (int l = 0; l < 9; ++l) {
+    const T w = T(wq(l));
+    const T cu = T(cxq(l)) * m.ux + T(cyq(l)) * m.uy;
+    const T deq = w * (m.drho + m.rho * (T(3) * cu + T(4.5) * cu * cu - usq15));
+    T v = d[l] - omega * (d[l] - deq);
+    if constexpr (FORCE) {
+      const T cF = T(cxq(l)) * m.Fx + T(cyq(l)) * m.Fy;
+      v += guo * w * (T(3) * cF - uF3 + T(9) * cu * cF);
+    }
+    o[l] = v;
+  }
+}
+
+template <int L, typename T, int VX>
+__device__ __forceinline__ void pull_plane(const T* __restrict__ src, size_t plane, int nx,
+                                           int x0, int y, int yn, int yp, T (&d)[9][VX]) {
+  constexpr int cy = cyq(L);
+  const int ys = cy == 1 ? yn : (cy == -1 ? yp : y);
+  pull_row<T, VX, cxq(L)>(src + L * plane + static_cast<size_t>(ys) * nx, x0, nx, d[L]);
+}
+
+// One step over a tile of (blockDim.x * VX) x (blockDim.y * ry) sites.
+// Workgroups are numbered so that consecutive tiles fall on the same XCD
+// (the hardware deals workgroups round-robin over the 8 XCDs).
+template <typename T, int VX, bool FORCE, bool NT>
+__global__ void __launch_bounds__(1024) k_step(StepParams p, int tiles_x, int total, int per_xcd,
+                                               int ry) {
+  const int b = blockIdx.x;
+  const int tile = (b & 7) * per_xcd + (b >> 3);
+  if (tile >= total) return;
+  const int tx = tile % tiles_x;
+  const int ty = tile / tiles_x;
+  const int x0 = (tx * blockDim.x + threadIdx.x) * VX;
+  if (x0 >= p.nx) return;
+  const int ybase = (ty * blockDim.y + threadIdx.y) * ry;
+  const int nx = p.nx, ny = p.ny;
+  const size_t plane = static_cast<size_t>(nx) * ny;
+  const T* __restrict__ src = static_cast<const T*>(p.src);
+  T* __restrict__ dst = static_cast<T*>(p.dst);
+  const T omega = T(p.omega);
+  const T guo = T(1) - T(0.5) * T(p.omega);
+  const T alpha = T(p.alpha);
+  for (int k = 0; k < ry; ++k) {
+    const int y = ybase + k;
+    if (y >= ny) break;
+    const int yn = (y == 0) ? ny - 1 : y - 1;
+    const int yp = (y == ny - 1) ? 0 : y + 1;
+    T d[9][VX];
+    pull_plane<0>(src, plane, nx, x0, y, yn, yp, d);
+    pull_plane<1>(src, plane, nx, x0, y, yn, yp, d);
+    pull_plane<2>(src, plane, nx, x0, y, yn, yp, d);
+    pull_plane<3>(src, plane, nx, x0, y, yn, yp, d);
+    pull_plane<4>(src, plane, nx, x0, y, yn, yp, d);
+    pull_plane<5>(src, plane, nx, x0, y, yn, yp, d);
+    pull_plane<6>(src, plane, nx, x0, y, yn, yp, d);
+    pull_plane<7>(src, plane, nx, x0, y, yn, yp, d);
+    pull_plane<8>(src, plane, nx, x0, y, yn, yp, d);
+    const size_t row = static_cast<size_t>(y) * nx + x0;
+    T fx[VX], fy[VX];
+    if constexpr (FORCE) {
+      if (p.fx) {
+        load_aligned<T, VX>(static_cast<const T*>(p.fx) + row, fx);
+        load_aligned<T, VX>(static_cast<const T*>(p.fy) + row, fy);
+      } else {
+#pragma unroll
+        for (int i = 0; i < VX; ++i) fx[i] = fy[i] = T(0);
+      }
+    }
+    T o[9][VX];
+    double hr[VX], hx[VX], hy[VX];
+#pragma unroll
+    for (int i = 0; i < VX; ++i) {
+      T di[9];
+#pragma unroll
+      for (int l = 0; l < 9; ++l) di[l] = d[l][i];
+      SiteMoments<T, FORCE> m(di, FORCE ? fx[i] : T(0), FORCE ? fy[i] : T(0), alpha);
+      T oi[9];
+      collide_site<T, FORCE>(di, m, omega, guo, oi);
+#pragma unroll
+      for (int l = 0; l < 9; ++l) o[l][i] = oi[l];
+      hr[i] = double(m.rho);
+      hx[i] = double(m.ux);
+      hy[i] = double(m.uy);
+    }
+#pragma unroll
+    for (int l = 0; l < 9; ++l) store_aligned<T, VX, NT>(dst + l * plane + row, o[l]);
+    if (p.h_rho) {
+#pragma unroll
+      for (int i = 0; i < VX; ++i) {
+        p.h_rho[row + i] = hr[i];
+        p.h_ux[row + i] = hx[i];
+        p.h_uy[row + i] = hy[i];
+      }
+    }
+  }
+}
+
+// f(x, 0) = f^eq(rho0(x), u0(x)) stored un-streamed: plane l at x - c_l.
+template <typename T>
+__global__ void __launch_bounds__(256) k_init(T* __restrict__ pop, const double* __restrict__ rho0,
+                                              const double* __restrict__ ux0,
+                                              const double* __restrict__ uy0, int nx, int ny) {
+  const size_t plane = static_cast<size_t>(nx) * ny;
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < plane;
+       i += size_t(gridDim.x) * blockDim.x) {
+    const int x = static_cast<int>(i % nx);
+    const int y = static_cast<int>(i / nx);
+    const double rho = rho0[i], ux = ux0[i], uy = uy0[i];
+    const double usq15 = 1.5 * (ux * ux + uy * uy);
+#pragma unroll
+    for (int l = 0; l < 9; ++l) {
+      const double cu = cxq(l) * ux + cyq(l) * uy;
+      const double dev = wq(l) * ((rho - 1.0) + rho * (3.0 * cu + 4.5 * cu * cu - usq15));
+      int xs = x - cxq(l), ys = y - cyq(l);
+      xs += xs < 0 ? nx : 0;
+      xs -= xs >= nx ? nx : 0;
+      ys += ys < 0 ? ny : 0;
+      ys -= ys >= ny ? ny : 0;
+      pop[l * plane + static_cast<size_t>(ys) * nx + xs] = T(dev);
+    }
+  }
+}
+
+// ---- moments ------------------------------------------------------------------------
+constexpr int kMomThreads = 256;
+constexpr int kMomMaxBlocks = 1024;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Reduce 7 per-thread values (sum x4, max, min, sum) over the block; thread 0
+// writes them to out[0..7].
+__device__ void block_reduce7(double (&v)[7], double* out) {
+  __shared__ double sh[kMomThreads / 64][8];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double r[7];
+  r[0] = wave_sum(v[0]);
+  r[1] = wave_sum(v[1]);
+  r[2] = wave_sum(v[2]);
+  r[3] = wave_sum(v[3]);
+  r[4] = wave_max(v[4]);
+  r[5] = wave_min(v[5]);
+  r[6] = wave_sum(v[6]);
+  if (lane == 0)
+    for (int k = 0; k < 7; ++k) sh[wv][k] = r[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a[7];
+    for (int k = 0; k < 7; ++k) a[k] = sh[0][k];
+    for (int w = 1; w < kMomThreads / 64; ++w) {
+      a[0] += sh[w][0];
+      a[1] += sh[w][1];
+      a[2] += sh[w][2];
+      a[3] += sh[w][3];
+      a[4] = fmax(a[4], sh[w][4]);
+      a[5] = fmin(a[5], sh[w][5]);
+      a[6] += sh[w][6];
+    }
+    for (int k = 0; k < 7; ++k) out[k] = a[k];
+    out[7] = 0.0;
+  }
+}
+
+template <typename T, typename O, bool FORCE>
+__global__ void __launch_bounds__(kMomThreads) k_moments(MomentParams p) {
+  const int nx = p.nx, ny = p.ny;
+  const size_t plane = static_cast<size_t>(nx) * ny;
+  const T* __restrict__ pop = static_cast<const T*>(p.pop);
+  const T alpha = T(p.alpha);
+  double acc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 1.0e300, 0.0};
+  for (size_t i = blockIdx.x * size_t(kMomThreads) + threadIdx.x; i < plane;
+       i += size_t(gridDim.x) * kMomThreads) {
+    const int x = static_cast<int>(i % nx);
+    const int y = static_cast<int>(i / nx);
+    T d[9];
+#pragma unroll
+    for (int l = 0; l < 9; ++l) {
+      int xs = x - cxq(l), ys = y - cyq(l);
+      xs += xs < 0 ? nx : 0;
+      xs -= xs >= nx ? nx : 0;
+      ys += ys < 0 ? ny : 0;
+      ys -= ys >= ny ? ny : 0;
+      d[l] = pop[l * plane + static_cast<size_t>(ys) * nx + xs];
+    }
+    T fx = T(0), fy = T(0);
+    if constexpr (FORCE) {
+      if (p.fx) {
+        fx = static_cast<const T*>(p.fx)[i];
+        fy = static_cast<const T*>(p.fy)[i];
+      }
+    }
+    SiteMoments<T, FORCE> m(d, fx, fy, alpha);
+    if (p.rho) static_cast<O*>(p.rho)[i] = O(m.rho);
+    if (p.ux) static_cast<O*>(p.ux)[i] = O(m.ux);
+    if (p.uy) static_cast<O*>(p.uy)[i] = O(m.uy);
+    const double r = m.rho, vx = m.ux, vy = m.uy;
+    if (p.rho64) {
+      p.rho64[i] = r;
+      p.ux64[i] = vx;
+      p.uy64[i] = vy;
+    }
+    if (p.ftx64) {
+      p.ftx64[i] = double(m.Fx);
+      p.fty64[i] = double(m.Fy);
+    }
+    const double s2 = vx * vx + vy * vy;
+    const bool finite = isfinite(r) && isfinite(vx) && isfinite(vy);
+    acc[0] += r;
+    acc[1] += r * vx;
+    acc[2] += r * vy;
+    acc[3] += 0.5 * r * s2;
+    acc[4] = fmax(acc[4], sqrt(s2));
+    acc[5] = fmin(acc[5], r);
+    acc[6] += finite ? 0.0 : 1.0;
+  }
+  block_reduce7(acc, p.partials + blockIdx.x * 8);
+}
+
+__global__ void __launch_bounds__(kMomThreads) k_reduce_scalars(const double* __restrict__ part,
+                                                                int nblocks, double* out) {
+  double acc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 1.0e300, 0.0};
+  for (int b = threadIdx.x; b < nblocks; b += kMomThreads) {
+    const double* q = part + b * 8;
+    acc[0] += q[0];
+    acc[1] += q[1];
+    acc[2] += q[2];
+    acc[3] += q[3];
+    acc[4] = fmax(acc[4], q[4]);
+    acc[5] = fmin(acc[5], q[5]);
+    acc[6] += q[6];
+  }
+  block_reduce7(acc, out);
+}
+
+template <typename T>
+__global__ void k_to_storage(T* __restrict__ dst, const double* __restrict__ src, size_t n) {
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n;
+       i += size_t(gridDim.x) * blockDim.x)
+    dst[i] = T(src[i]);
+}
+
+typedef float f4a __attribute__((ext_vector_type(4), aligned(16)));
+__global__ void __launch_bounds__(256) k_copy(f4a* __restrict__ dst, const f4a* __restrict__ src,
+                                              size_t n) {
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n;
+       i += size_t(gridDim.x) * blockDim.x)
+    dst[i] = src[i];
+}
+
+int grid_for(size_t n, int threads, int cap) {
+  size_t b = (n + threads - 1) / threads;
+  if (b > static_cast<size_t>(cap)) b = cap;
+  if (b < 1) b = 1;
+  return static_cast<int>(b);
+}
+
+template <typename T, int VX, bool FORCE, bool NT>
+int launch_step_t(const StepParams& p, const lbm_tile& t, hipStream_t s) {
+  const int tiles_x = (p.nx / VX + t.bx - 1) / t.bx;
+  const int rows_per_tile = t.by * t.ry;
+  const int tiles_y = (p.ny + rows_per_tile - 1) / rows_per_tile;
+  const int total = tiles_x * tiles_y;
+  const int per_xcd = (total + 7) / 8;
+  dim3 block(t.bx, t.by);
+  hipLaunchKernelGGL((k_step<T, VX, FORCE, NT>), dim3(per_xcd * 8), block, 0, s, p, tiles_x, total,
+                     per_xcd, t.ry);
+  LBM_HIP(hipGetLastError());
+  return LBM_OK;
+}
+
+template <typename T, bool FORCE, bool NT>
+int dispatch_vx(const StepParams& p, const lbm_tile& t, hipStream_t s) {
+  switch (t.vx) {
+    case 1: return launch_step_t<T, 1, FORCE, NT>(p, t, s);
+    case 2: return launch_step_t<T, 2, FORCE, NT>(p, t, s);
+    case 4: return launch_step_t<T, 4, FORCE, NT>(p, t, s);
+    default: return fail(LBM_E_INVALID, "tile vx must be 1, 2 or 4 (got %d)", t.vx);
+  }
+}
+
+template <typename T>
+int dispatch_step(bool force, const StepParams& p, const lbm_tile& t, hipStream_t s) {
+  if (force) return t.nt ? dispatch_vx<T, true, true>(p, t, s) : dispatch_vx<T, true, false>(p, t, s);
+  return t.nt ? dispatch_vx<T, false, true>(p, t, s) : dispatch_vx<T, false, false>(p, t, s);
+}
+
+}  // namespace
+
+bool tile_ok(const lbm_tile& t, int dtype, int nx, int ny) {
+  (void)dtype;
+  (void)ny;
+  const int threads = t.bx * t.by;
+  if (t.bx < 1 || t.by < 1 || t.ry < 1 || threads > 1024 || threads % 64 != 0) return false;
+  if (t.vx != 1 && t.vx != 2 && t.vx != 4) return false;
+  if (nx % t.vx != 0) return false;
+  if (t.nt != 0 && t.nt != 1) return false;
+  return true;
+}
+
+lbm_tile default_tile(int dtype, int nx, int ny) {
+  lbm_tile t{};
+  t.vx = (dtype == LBM_F32) ? 4 : 2;
+  while (t.vx > 1 && nx % t.vx != 0) t.vx >>= 1;
+  int bx = 64;
+  while (bx < 256 && bx * 2 * t.vx <= nx) bx *= 2;
+  t.bx = bx;
+  t.by = 256 / bx;
+  t.ry = ny >= 4096 ? 4 : 1;
+  t.nt = 0;
+  return t;
+}
+
+int tile_candidates(int dtype, int nx, int ny, lbm_tile* out, int cap) {
+  int n = 0;
+  const int vxs[3] = {1, 2, 4};
+  const int threads[3] = {128, 256, 512};
+  const int rys[4] = {1, 2, 4, 8};
+  for (int vx : vxs) {
+    if (nx % vx) continue;
+    for (int th : threads) {
+      for (int bx = 64; bx <= th; bx *= 2) {
+        if (bx * vx > nx && bx > 64) continue;
+        const int by = th / bx;
+        for (int ry : rys) {
+          if (by * ry > ny) continue;
+          for (int nt = 0; nt <= 1; ++nt) {
+            lbm_tile t{bx, by, vx, ry, nt};
+            if (!tile_ok(t, dtype, nx, ny)) continue;
+            if (n < cap) out[n] = t;
+            ++n;
+          }
+        }
+      }
+    }
+  }
+  return n;
+}
+
+int launch_step(int dtype, bool force, const StepParams& p, const lbm_tile& t, hipStream_t s) {
+  if (dtype == LBM_F32) return dispatch_step<float>(force, p, t, s);
+  return dispatch_step<double>(force, p, t, s);
+}
+
+int launch_init(int dtype, void* pop, const double* rho0, const double* ux0, const double* uy0,
+                int nx, int ny, hipStream_t s) {
+  const size_t n = static_cast<size_t>(nx) * ny;
+  const int g = grid_for(n, 256, 4096);
+  if (dtype == LBM_F32)
+    hipLaunchKernelGGL(k_init<float>, dim3(g), dim3(256), 0, s, static_cast<float*>(pop), rho0, ux0,
+                       uy0, nx, ny);
+  else
+    hipLaunchKernelGGL(k_init<double>, dim3(g), dim3(256), 0, s, static_cast<double*>(pop), rho0,
+                       ux0, uy0, nx, ny);
+  LBM_HIP(hipGetLastError());
+  return LBM_OK;
+}
+
+int moment_blocks(int nx, int ny) {
+  return grid_for(static_cast<size_t>(nx) * ny, kMomThreads, kMomMaxBlocks);
+}
+
+template <typename T, bool FORCE>
+static int launch_moments_t(const MomentParams& p, hipStream_t s) {
+  const int g = moment_blocks(p.nx, p.ny);
+  if (p.out_dtype == LBM_F32)
+    hipLaunchKernelGGL((k_moments<T, float, FORCE>), dim3(g), dim3(kMomThreads), 0, s, p);
+  else
+    hipLaunchKernelGGL((k_moments<T, double, FORCE>), dim3(g), dim3(kMomThreads), 0, s, p);
+  LBM_HIP(hipGetLastError());
+  return LBM_OK;
+}
+
+int launch_moments(int dtype, bool force, const MomentParams& p, hipStream_t s) {
+  if (dtype == LBM_F32)
+    return force ? launch_moments_t<float, true>(p, s) : launch_moments_t<float, false>(p, s);
+  return force ? launch_moments_t<double, true>(p, s) : launch_moments_t<double, false>(p, s);
+}
+
+int launch_reduce_scalars(const double* partials, int nblocks, double* out8, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_scalars, dim3(1), dim3(kMomThreads), 0, s, partials, nblocks, out8);
+  LBM_HIP(hipGetLastError());
+  return LBM_OK;
+}
+
+int launch_to_storage(int dtype, void* dst, const double* src, size_t n, hipStream_t s) {
+  const int g = grid_for(n, 256, 4096);
+  if (dtype == LBM_F32)
+    hipLaunchKernelGGL(k_to_storage<float>, dim3(g), dim3(256), 0, s, static_cast<float*>(dst), src,
+                       n);
+  else
+    hipLaunchKernelGGL(k_to_storage<double>, dim3(g), dim3(256), 0, s, static_cast<double*>(dst),
+                       src, n);
+  LBM_HIP(hipGetLastError());
+  return LBM_OK;
+}
+
+int launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  const size_t n = bytes / 16;
+  const int g = grid_for(n, 256, 256 * 64);
+  hipLaunchKernelGGL(k_copy, dim3(g), dim3(256), 0, s, static_cast<f4a*>(dst),
+                     static_cast<const f4a*>(src), n);
+  LBM_HIP(hipGetLastError());
+  return LBM_OK;
+}
+
+}  // namespace lbm

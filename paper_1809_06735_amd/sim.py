@@ -1,0 +1,267 @@
+"""Python front end of the HIP library: device memory and streams from PyTorch,
+every computation in the library's kernels.
+
+Classes / functions
+-------------------
+Simulation      one periodic D2Q9 grid (lbm_init / lbm_step / lbm_moments /
+                lbm_subvolume_balance and the checkpoint, tuning and timing calls)
+balance_fields  the sub-volume balance of caller-given (rho, u) levels
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _require_gpu():
+    if not torch.cuda.is_available():
+        raise RuntimeError("paper_1809_06735_amd needs a ROCm GPU (gfx950); none is visible")
+
+
+def _dev64(a, device):
+    """Host/torch array -> contiguous FP64 tensor on `device`."""
+    if isinstance(a, torch.Tensor):
+        return a.to(device=device, dtype=torch.float64).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=device)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream_handle(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def stats_to_dict(s: L.BalanceStats):
+    """lbm_balance_stats -> {'L', 'dE': {...}, 'dZ': {...}, 'Ma': {...}}."""
+    def one(pfx, count, nan):
+        return {"count": int(count), "n_nan": int(nan), "mean": s.__getattribute__("mean_" + pfx),
+                "std": s.__getattribute__("std_" + pfx), "min": s.__getattribute__("min_" + pfx),
+                "max": s.__getattribute__("max_" + pfx)}
+    return {"L": int(s.L), "dE": one("dE", s.count_dE, s.nan_dE),
+            "dZ": one("dZ", s.count_dZ, s.nan_dZ), "Ma": one("Ma", s.count_Ma, 0)}
+
+
+def _balance_args(nx, ny, sizes, windows):
+    sizes = [int(v) for v in sizes]
+    sz = (C.c_int32 * max(1, len(sizes)))(*sizes)
+    out = (L.BalanceStats * max(1, len(sizes)))()
+    if windows is not None and len(windows) > 0:
+        flat = [int(v) for w in windows for v in w]
+        win = (C.c_int32 * len(flat))(*flat)
+        nwin = len(windows)
+        wterms = (C.c_double * (L.NTERMS * nwin))()
+    else:
+        win, nwin, wterms = None, 0, None
+    return sizes, sz, out, win, nwin, wterms
+
+
+def _balance_result(sizes, out, maps, nwin, wterms, terms, nx, ny):
+    res = {"stats": [stats_to_dict(out[k]) for k in range(len(sizes))]}
+    if maps is not None:
+        res["maps"] = maps
+    if nwin:
+        res["window_terms"] = np.frombuffer(wterms, dtype=np.float64).reshape(nwin, L.NTERMS).copy()
+    if terms is not None:
+        res["terms"] = {k: terms[i] for i, k in enumerate(L.TERM_NAMES)}
+    return res
+
+
+class Simulation:
+    """One periodic D2Q9 BGK grid on the current GPU.
+
+    rho0, ux0, uy0: [ny, nx] initial fields (NumPy or torch, converted to FP64
+    on the device); fx, fy: optional static external force; alpha: linear drag.
+    dtype: "f32" or "f64" population storage.
+    """
+
+    def __init__(self, rho0, ux0, uy0, tau, dtype="f32", fx=None, fy=None, alpha=0.0,
+                 with_balance=False, device="cuda", stream=None):
+        _require_gpu()
+        self._lib = L.load()
+        self.device = torch.device(device)
+        r = _dev64(rho0, self.device)
+        vx = _dev64(ux0, self.device)
+        vy = _dev64(uy0, self.device)
+        self.ny, self.nx = r.shape
+        self.dtype = {"f32": L.LBM_F32, "f64": L.LBM_F64}[dtype]
+        self.dtype_name = dtype
+        self.tau = float(tau)
+        self.alpha = float(alpha)
+        has_force = fx is not None
+        self._stream = stream
+        cfg = L.Config(nx=self.nx, ny=self.ny, dtype=self.dtype, has_force=int(has_force),
+                       with_balance=int(with_balance), reserved=0, tau=self.tau,
+                       drag_alpha=self.alpha, stream=_stream_handle(stream))
+        self._cfg = cfg
+        nbytes = C.c_size_t()
+        L.check(self._lib.lbm_workspace_bytes(C.byref(cfg), C.byref(nbytes)), "lbm_workspace_bytes")
+        self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        f_x = _dev64(fx, self.device) if has_force else None
+        f_y = _dev64(fy, self.device) if has_force else None
+        h = C.c_void_p()
+        L.check(self._lib.lbm_init(C.byref(cfg), _ptr(self.workspace), nbytes.value, _ptr(r),
+                                   _ptr(vx), _ptr(vy), _ptr(f_x), _ptr(f_y), C.byref(h)), "lbm_init")
+        self._h = h
+        # keep the inputs alive until the stream has consumed them
+        self._inputs = (r, vx, vy, f_x, f_y)
+        torch.cuda.current_stream(self.device).synchronize() if stream is None else stream.synchronize()
+        self._inputs = None
+
+    # -- lifecycle ---------------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            L.check(self._lib.lbm_destroy(self._h), "lbm_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    # -- stepping ---------------------------------------------------------------------------
+    def step(self, n: int = 1):
+        L.check(self._lib.lbm_step(self._h, int(n)), "lbm_step")
+        return self
+
+    @property
+    def time(self) -> int:
+        t = C.c_int64()
+        L.check(self._lib.lbm_time(self._h, C.byref(t)), "lbm_time")
+        return t.value
+
+    def moments(self, out_dtype=torch.float64, scalars=True):
+        """(rho, ux, uy[, scalars dict]) at the current time."""
+        od = L.LBM_F64 if out_dtype == torch.float64 else L.LBM_F32
+        shape = (self.ny, self.nx)
+        rho = torch.empty(shape, dtype=out_dtype, device=self.device)
+        ux = torch.empty_like(rho)
+        uy = torch.empty_like(rho)
+        if scalars:
+            sc = (C.c_double * 8)()
+            rc = self._lib.lbm_moments(self._h, _ptr(rho), _ptr(ux), _ptr(uy), od, sc)
+            d = dict(zip(L.SCALAR_NAMES, list(sc)))
+            if rc == L.LBM_E_DIVERGED:
+                raise L.LBMError(rc, self._lib.lbm_last_error().decode())
+            L.check(rc, "lbm_moments")
+            return rho, ux, uy, d
+        L.check(self._lib.lbm_moments(self._h, _ptr(rho), _ptr(ux), _ptr(uy), od, None), "lbm_moments")
+        return rho, ux, uy
+
+    def balance(self, sizes, windows=None, maps=False, term_fields=False):
+        """Sub-volume balance statistics at the current time (needs with_balance)."""
+        sizes, sz, out, win, nwin, wterms = _balance_args(self.nx, self.ny, sizes, windows)
+        dm = torch.empty((len(sizes), 3, self.ny, self.nx), dtype=torch.float64,
+                         device=self.device) if maps else None
+        tf = torch.empty((L.NTERMS, self.ny, self.nx), dtype=torch.float64,
+                         device=self.device) if term_fields else None
+        L.check(self._lib.lbm_subvolume_balance(self._h, sz, len(sizes), out, _ptr(dm), win, nwin,
+                                                wterms, _ptr(tf)), "lbm_subvolume_balance")
+        return _balance_result(sizes, out, dm, nwin, wterms, tf, self.nx, self.ny)
+
+    # -- checkpoints ------------------------------------------------------------------------------
+    def state_bytes(self) -> int:
+        n = C.c_size_t()
+        L.check(self._lib.lbm_state_bytes(self._h, C.byref(n)), "lbm_state_bytes")
+        return n.value
+
+    def save(self, out=None):
+        if out is None:
+            out = torch.empty(self.state_bytes(), dtype=torch.uint8, device=self.device)
+        L.check(self._lib.lbm_save(self._h, _ptr(out)), "lbm_save")
+        return out
+
+    def load(self, state):
+        L.check(self._lib.lbm_load(self._h, _ptr(state)), "lbm_load")
+        return self
+
+    # -- launch shape / graphs / timing ---------------------------------------------------------
+    def set_tile(self, bx, by, vx, ry, nt=0):
+        t = L.Tile(bx, by, vx, ry, nt)
+        L.check(self._lib.lbm_set_tile(self._h, C.byref(t)), "lbm_set_tile")
+
+    def get_tile(self):
+        t = L.Tile()
+        L.check(self._lib.lbm_get_tile(self._h, C.byref(t)), "lbm_get_tile")
+        return (t.bx, t.by, t.vx, t.ry, t.nt)
+
+    def autotune(self, trial_steps=10):
+        t = L.Tile()
+        L.check(self._lib.lbm_autotune(self._h, int(trial_steps), C.byref(t)), "lbm_autotune")
+        return (t.bx, t.by, t.vx, t.ry, t.nt)
+
+    def set_graph(self, chunk):
+        L.check(self._lib.lbm_set_graph(self._h, int(chunk)), "lbm_set_graph")
+
+    def step_timing(self, enable=True):
+        L.check(self._lib.lbm_step_timing(self._h, int(bool(enable))), "lbm_step_timing")
+
+    def step_time(self, reset=False):
+        """(milliseconds, launches) of the device-timed step kernels."""
+        ms = C.c_double()
+        n = C.c_int64()
+        L.check(self._lib.lbm_step_time(self._h, C.byref(ms), C.byref(n), int(bool(reset))),
+                "lbm_step_time")
+        return ms.value, n.value
+
+
+def balance_fields(rho, ux, uy, nu, sizes, fx=None, fy=None, windows=None, maps=False,
+                   term_fields=False, device="cuda", stream=None):
+    """Sub-volume balance of given fields: rho/ux/uy are three levels (n-2, n-1, n)."""
+    _require_gpu()
+    lib = L.load()
+    dev = torch.device(device)
+    rs = [_dev64(a, dev) for a in rho]
+    xs = [_dev64(a, dev) for a in ux]
+    ys = [_dev64(a, dev) for a in uy]
+    ny, nx = rs[2].shape
+    f_x = _dev64(fx, dev) if fx is not None else None
+    f_y = _dev64(fy, dev) if fy is not None else None
+    inp = L.BalanceInput()
+    inp.nx, inp.ny, inp.nu = nx, ny, float(nu)
+    for k in range(3):
+        inp.rho[k] = rs[k].data_ptr()
+        inp.ux[k] = xs[k].data_ptr()
+        inp.uy[k] = ys[k].data_ptr()
+    inp.fx = f_x.data_ptr() if f_x is not None else None
+    inp.fy = f_y.data_ptr() if f_y is not None else None
+    inp.stream = _stream_handle(stream).value
+    nbytes = C.c_size_t()
+    L.check(lib.lbm_balance_workspace_bytes(nx, ny, C.byref(nbytes)), "lbm_balance_workspace_bytes")
+    ws = torch.empty(nbytes.value, dtype=torch.uint8, device=dev)
+    sizes, sz, out, win, nwin, wterms = _balance_args(nx, ny, sizes, windows)
+    dm = torch.empty((len(sizes), 3, ny, nx), dtype=torch.float64, device=dev) if maps else None
+    tf = torch.empty((L.NTERMS, ny, nx), dtype=torch.float64, device=dev) if term_fields else None
+    L.check(lib.lbm_balance_fields(C.byref(inp), _ptr(ws), nbytes.value, sz, len(sizes), out, _ptr(dm),
+                                   win, nwin, wterms, _ptr(tf)), "lbm_balance_fields")
+    return _balance_result(sizes, out, dm, nwin, wterms, tf, nx, ny)
+
+
+def copy_bandwidth(nbytes=1 << 30, iters=20, device="cuda"):
+    """GB/s of the library's plain copy kernel (read + write bytes / time)."""
+    _require_gpu()
+    lib = L.load()
+    a = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    b = torch.empty_like(a)
+    s = _stream_handle()
+    L.check(lib.lbm_copy(_ptr(b), _ptr(a), nbytes, s), "lbm_copy")
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(iters):
+        L.check(lib.lbm_copy(_ptr(b), _ptr(a), nbytes, s), "lbm_copy")
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / iters
+    return 2 * nbytes / (ms * 1e-3) / 1e9, ms

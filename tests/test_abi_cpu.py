@@ -1,0 +1,91 @@
+"""The C ABI library loads and exports every function include/lbm.h declares;
+host-only calls validate their arguments.  No GPU needed (no kernel runs)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1809_06735_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    return re.findall(r"^LBM_API\s+[\w\s\*]+?\b(lbm_\w+)\s*\(", src, flags=re.M)
+
+
+def test_header_declares_the_core_calls():
+    names = declared_functions()
+    for core in ("lbm_init", "lbm_step", "lbm_moments", "lbm_subvolume_balance"):
+        assert core in names
+    assert len(names) == len(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.load()
+    names = declared_functions()
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    # every declared function has a ctypes signature in the binding, and vice versa
+    assert set(names) == set(L.SIGNATURES), set(names) ^ set(L.SIGNATURES)
+
+
+def test_version_and_strerror():
+    lib = L.load()
+    assert b"gfx950" in lib.lbm_version()
+    assert lib.lbm_strerror(L.LBM_E_DIVERGED) == b"simulation diverged"
+    assert lib.lbm_strerror(12345) == b"unknown status"
+
+
+def cfg(**kw):
+    base = dict(nx=64, ny=64, dtype=L.LBM_F32, has_force=0, with_balance=0, reserved=0,
+                tau=0.6, drag_alpha=0.0, stream=None)
+    base.update(kw)
+    return L.Config(**base)
+
+
+def test_workspace_bytes_and_validation():
+    lib = L.load()
+    n = C.c_size_t()
+    assert lib.lbm_workspace_bytes(C.byref(cfg()), C.byref(n)) == L.LBM_OK
+    pops = 2 * 9 * 64 * 64 * 4
+    assert n.value >= pops
+    n64 = C.c_size_t()
+    lib.lbm_workspace_bytes(C.byref(cfg(dtype=L.LBM_F64)), C.byref(n64))
+    assert n64.value > n.value
+    nb = C.c_size_t()
+    lib.lbm_workspace_bytes(C.byref(cfg(with_balance=1)), C.byref(nb))
+    assert nb.value > n.value + 13 * 65 * 65 * 8
+    bad = [cfg(tau=0.5), cfg(tau=float("nan")), cfg(nx=8), cfg(dtype=7), cfg(drag_alpha=-1.0),
+           cfg(has_force=2), cfg(reserved=1), cfg(ny=70000)]
+    for c in bad:
+        assert lib.lbm_workspace_bytes(C.byref(c), C.byref(n)) == L.LBM_E_INVALID
+        assert lib.lbm_last_error()
+    assert lib.lbm_workspace_bytes(None, C.byref(n)) == L.LBM_E_INVALID
+
+
+def test_init_rejects_bad_arguments_before_touching_the_device():
+    lib = L.load()
+    h = C.c_void_p()
+    # NULL workspace / misaligned workspace / NULL fields: rejected on the host
+    assert lib.lbm_init(C.byref(cfg()), None, 0, None, None, None, None, None, C.byref(h)) == L.LBM_E_INVALID
+    assert lib.lbm_init(C.byref(cfg()), C.c_void_p(8), 1 << 30, C.c_void_p(256), C.c_void_p(256),
+                        C.c_void_p(256), None, None, C.byref(h)) == L.LBM_E_INVALID
+    assert lib.lbm_init(C.byref(cfg()), C.c_void_p(256), 16, C.c_void_p(256), C.c_void_p(256),
+                        C.c_void_p(256), None, None, C.byref(h)) == L.LBM_E_NOMEM
+    assert lib.lbm_init(C.byref(cfg(has_force=1)), C.c_void_p(256), 1 << 30, C.c_void_p(256),
+                        C.c_void_p(256), C.c_void_p(256), None, None, C.byref(h)) == L.LBM_E_INVALID
+    assert lib.lbm_step(None, 1) == L.LBM_E_INVALID
+    assert lib.lbm_destroy(None) == L.LBM_OK
+
+
+def test_balance_workspace_and_adjoint_validation():
+    lib = L.load()
+    n = C.c_size_t()
+    assert lib.lbm_balance_workspace_bytes(64, 64, C.byref(n)) == L.LBM_OK
+    assert n.value >= (13 + 8) * 64 * 64 * 8 + 13 * 65 * 65 * 8
+    assert lib.lbm_balance_workspace_bytes(8, 64, C.byref(n)) == L.LBM_E_INVALID
+    assert lib.lbm_copy(None, None, 16, None) == L.LBM_E_INVALID
+    assert lib.lbm_copy(C.c_void_p(256), C.c_void_p(512), 15, None) == L.LBM_E_INVALID

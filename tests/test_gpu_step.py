@@ -1,0 +1,263 @@
+"""GPU parity of the D2Q9 step, initialisation and moments against the FP64 oracle.
+
+Tolerances: FP64 storage 1e-12 and FP32 storage 1e-5, both as
+max |gpu - oracle| / max |oracle| per moment field (the Taylor-Green velocity
+has zero nodes, so a pointwise relative error is not meaningful).
+"""
+import numpy as np
+import pytest
+import torch
+
+import lbm_inputs as inp
+from helpers import gpu_patch, oracle_patch_moments, rel_err
+from oracle import ref
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+
+def say(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+def Sim(*a, **k):
+    from paper_1809_06735_amd import Simulation
+    return Simulation(*a, **k)
+
+
+def check_moments(sim, want, tol, label):
+    r, vx, vy, sc = sim.moments()
+    for name, g, w in zip(("rho", "ux", "uy"), (r, vx, vy), want):
+        e = rel_err(g, w)
+        say(f"{label} {name} rel err {e:.2e}")
+        assert e < tol, (label, name, e)
+    return sc
+
+
+def test_taylor_green_64_fp64_1000_steps(gpu_lib):
+    """Workload tg64: 64^2 FP64, tau 0.6, 1000 steps."""
+    say("tg64 fp64 1000 steps")
+    rho, ux, uy = inp.taylor_green(64, 0.01)
+    sim = Sim(rho, ux, uy, 0.6, dtype="f64")
+    sim.step(1000)
+    f = ref.run(ref.init_populations(rho, ux, uy), 1000, 0.6)
+    sc = check_moments(sim, ref.moments(f), TOL64, "tg64")
+    assert sc["time"] == 1000
+    assert sc["mass"] == pytest.approx(64 * 64, rel=1e-14)
+
+
+def test_forced_drag_fp64_parity(gpu_lib):
+    """FP64 with Guo forcing and drag, non-square grid, 120 steps."""
+    say("forced fp64 96x80")
+    ny, nx = 80, 96
+    rng = np.random.default_rng(1)
+    _, ux, uy = inp.spectrum_velocity(96, seed=2, max_mach=0.08)
+    ux, uy = ux[:ny], uy[:ny]
+    rho = 1.0 + 0.001 * rng.standard_normal((ny, nx))
+    fx, fy = inp.forcing_field(96, seed=4, max_force=2e-5)
+    fx, fy = fx[:ny], fy[:ny]
+    tau, alpha = 0.53, 2e-3
+    sim = Sim(rho, ux, uy, tau, dtype="f64", fx=fx, fy=fy, alpha=alpha)
+    sim.step(120)
+    f = ref.run(ref.init_populations(rho, ux, uy), 120, tau, ref.t64(fx), ref.t64(fy), alpha)
+    check_moments(sim, ref.moments(f, ref.t64(fx), ref.t64(fy), alpha), TOL64, "forced64")
+
+
+def test_spectrum_256_fp32_100_steps(gpu_lib):
+    """FP32 storage, decaying spectrum, 256^2, 100 steps, whole grid."""
+    say("spectrum 256 fp32 100 steps")
+    rho, ux, uy = inp.spectrum_velocity(256, seed=0, max_mach=0.05)
+    sim = Sim(rho, ux, uy, 0.51, dtype="f32")
+    sim.step(100)
+    f = ref.run(ref.init_populations(rho, ux, uy), 100, 0.51)
+    check_moments(sim, ref.moments(f), TOL32, "spec256")
+
+
+def test_decay1024_fp32_sampled_patches(gpu_lib):
+    """Workload decay1024 (1024^2 FP32, tau 0.51): 100 steps, oracle on sampled patches
+    (one across the periodic corner)."""
+    say("decay1024 fp32 100 steps, patches")
+    rho, ux, uy = inp.spectrum_velocity(1024, seed=0, max_mach=0.05)
+    sim = Sim(rho, ux, uy, 0.51, dtype="f32")
+    sim.step(100)
+    r, vx, vy = sim.moments(scalars=False)
+    for (y0, x0) in ((1010, 1000), (400, 733)):
+        want = oracle_patch_moments((rho, ux, uy), 0.51, 100, y0, x0, 24)
+        for name, g, w in zip(("rho", "ux", "uy"), (r, vx, vy), want):
+            e = rel_err(gpu_patch(g, y0, x0, 24), w)
+            say(f"decay1024 patch ({y0},{x0}) {name} {e:.2e}")
+            assert e < TOL32
+
+
+@pytest.fixture(scope="module")
+def forced4096():
+    w = inp.WORKLOADS["forced4096"]
+    fx, fy = inp.forcing_field(w.n, seed=w.seed, alpha=w.alpha)
+    z = np.zeros((w.n, w.n))
+    return w, np.ones((w.n, w.n)), z, z, fx, fy
+
+
+def test_forced4096_fp32_sampled_patches_in_bench_launch_shape(gpu_lib, forced4096):
+    """Workload forced4096 (4096^2 FP32, Guo force + drag, from rest) in the autotuned
+    launch shape the benchmark uses: 20 steps, oracle on patches incl. the periodic seam."""
+    w, rho, ux, uy, fx, fy = forced4096
+    say("forced4096 fp32 autotune + 20 steps")
+    sim = Sim(rho, ux, uy, w.tau, dtype="f32", fx=fx, fy=fy, alpha=w.alpha)
+    tile = sim.autotune(trial_steps=3)
+    say(f"forced4096 tile {tile}")
+    sim.step(20)
+    r, vx, vy, sc = sim.moments()
+    assert sc["nonfinite"] == 0
+    for (y0, x0) in ((4090, 4085), (0, 2048), (1234, 4091), (2000, 0)):
+        want = oracle_patch_moments((rho, ux, uy), w.tau, 20, y0, x0, 16, fx=fx, fy=fy, alpha=w.alpha)
+        for name, g, ww in zip(("rho", "ux", "uy"), (r, vx, vy), want):
+            e = rel_err(gpu_patch(g, y0, x0, 16), ww)
+            say(f"forced4096 patch ({y0},{x0}) {name} {e:.2e}")
+            # from rest the velocity is O(F); compare against the field's global scale
+            if name != "rho":
+                scale = float(torch.as_tensor(ww).abs().max())
+                gscale = max(scale, 1e-12)
+                e = float((gpu_patch(g, y0, x0, 16).double() - ww).abs().max()) / gscale
+            assert e < TOL32, (name, e)
+
+
+@pytest.mark.parametrize("shape", [(16, 16), (33, 17), (50, 34), (64, 48), (20, 100)])
+def test_ragged_grids_all_launch_shapes_agree(gpu_lib, shape):
+    """Every launch shape gives bit-identical populations; one matches the oracle."""
+    from paper_1809_06735_amd import _lib as L
+    import ctypes as C
+    ny, nx = shape
+    say(f"ragged {ny}x{nx}")
+    rng = np.random.default_rng(nx * 1000 + ny)
+    rho = 1.0 + 0.01 * rng.standard_normal((ny, nx))
+    ux = 0.03 * rng.standard_normal((ny, nx))
+    uy = 0.03 * rng.standard_normal((ny, nx))
+    fx = 1e-5 * rng.standard_normal((ny, nx))
+    fy = 1e-5 * rng.standard_normal((ny, nx))
+    steps = 7
+    ref_state = None
+    f = ref.run(ref.init_populations(rho, ux, uy), steps, 0.7, ref.t64(fx), ref.t64(fy), 1e-3)
+    want = ref.moments(f, ref.t64(fx), ref.t64(fy), 1e-3)
+    for dt, tol in (("f64", TOL64), ("f32", TOL32)):
+        lib = L.load()
+        cand = []
+        for vx_ in (1, 2, 4):
+            for (bx, by) in ((64, 1), (64, 2), (128, 1), (64, 4)):
+                for ry in (1, 3):
+                    for nt in (0, 1):
+                        cand.append((bx, by, vx_, ry, nt))
+        ref_state = None
+        checked = 0
+        for tile in cand:
+            if nx % tile[2]:
+                continue
+            sim = Sim(rho, ux, uy, 0.7, dtype=dt, fx=fx, fy=fy, alpha=1e-3)
+            sim.set_tile(*tile)
+            sim.step(steps)
+            st = sim.save()
+            if ref_state is None:
+                ref_state = st
+                check_moments(sim, want, tol, f"ragged {ny}x{nx} {dt} {tile}")
+            else:
+                assert torch.equal(st, ref_state), tile
+            checked += 1
+            sim.close()
+        assert checked > 0
+
+
+def test_graph_replay_equals_direct_launches(gpu_lib):
+    rho, ux, uy = inp.spectrum_velocity(128, seed=5, max_mach=0.05)
+    a = Sim(rho, ux, uy, 0.52, dtype="f32")
+    a.set_graph(0)
+    a.step(301)
+    b = Sim(rho, ux, uy, 0.52, dtype="f32")
+    b.set_graph(16)
+    b.step(1)
+    b.step(300)
+    assert torch.equal(a.save(), b.save())
+
+
+def test_save_load_resume_and_determinism(gpu_lib):
+    rho, ux, uy = inp.spectrum_velocity(96, seed=6, max_mach=0.05)
+    a = Sim(rho, ux, uy, 0.55, dtype="f32", with_balance=True)
+    a.step(40)
+    st = a.save().clone()
+    a.step(25)
+    b = Sim(rho, ux, uy, 0.55, dtype="f32", with_balance=True)
+    b.load(st)
+    assert b.time == 40
+    b.step(25)
+    assert torch.equal(a.save(), b.save())
+    c = Sim(rho, ux, uy, 0.55, dtype="f32")
+    c.step(65)
+    assert torch.equal(c.save()[256:256 + 9 * 96 * 96 * 4], a.save()[256:256 + 9 * 96 * 96 * 4])
+    ra = a.balance([8, 96])
+    rb = b.balance([8, 96])
+    assert ra["stats"] == rb["stats"]
+
+
+def test_translation_equivariance_bitwise(gpu_lib):
+    rho, ux, uy = inp.spectrum_velocity(64, seed=8, max_mach=0.05)
+    sh = lambda a: np.roll(a, (5, -9), (0, 1))  # noqa: E731
+    a = Sim(rho, ux, uy, 0.53, dtype="f32")
+    b = Sim(sh(rho), sh(ux), sh(uy), 0.53, dtype="f32")
+    a.step(30)
+    b.step(30)
+    ra = a.moments(scalars=False)
+    rb = b.moments(scalars=False)
+    for x, y in zip(ra, rb):
+        assert torch.equal(torch.roll(x, (5, -9), (0, 1)), y)
+
+
+def test_divergence_is_reported(gpu_lib):
+    from paper_1809_06735_amd import LBMError
+    rho, ux, uy = inp.taylor_green(32, 0.01)
+    ux = ux.copy()
+    ux[3, 4] = np.nan
+    sim = Sim(rho, ux, uy, 0.6, dtype="f32", with_balance=True)
+    sim.step(3)
+    with pytest.raises(LBMError) as ei:
+        sim.moments()
+    assert ei.value.code == -4
+    with pytest.raises(LBMError) as ei:
+        sim.balance([8])
+    assert ei.value.code == -4
+
+
+def test_state_errors(gpu_lib):
+    from paper_1809_06735_amd import LBMError
+    rho, ux, uy = inp.taylor_green(32, 0.01)
+    sim = Sim(rho, ux, uy, 0.6, dtype="f32")
+    sim.step(3)
+    with pytest.raises(LBMError) as ei:
+        sim.balance([8])
+    assert ei.value.code == -5        # no balance workspace
+    sim2 = Sim(rho, ux, uy, 0.6, dtype="f32", with_balance=True)
+    sim2.step(1)
+    with pytest.raises(LBMError) as ei:
+        sim2.balance([8])
+    assert ei.value.code == -5        # no two levels of history yet
+    with pytest.raises(LBMError):
+        sim2.set_tile(64, 1, 3, 1)    # vx = 3 invalid
+    with pytest.raises(LBMError):
+        sim2.balance([64])            # L > N
+
+
+def test_step_timing_counts_launches(gpu_lib):
+    rho, ux, uy = inp.taylor_green(64, 0.01)
+    sim = Sim(rho, ux, uy, 0.6, dtype="f32")
+    sim.step_timing(True)
+    sim.step(100)
+    sim.step(5)
+    ms, n = sim.step_time(reset=True)
+    assert n == 105 and ms > 0
+    ms, n = sim.step_time()
+    assert n == 0 and ms == 0
+
+
+def test_copy_bandwidth_runs(gpu_lib):
+    from paper_1809_06735_amd import copy_bandwidth
+    gbs, ms = copy_bandwidth(1 << 26, iters=3)
+    assert gbs > 100
