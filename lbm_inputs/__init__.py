@@ -155,20 +155,28 @@ def ensemble_members(nruns: int = 64, sizes=ENSEMBLE_SIZES, tau_lo: float = 0.50
     return out
 
 
-def balance_levels(n: int, seed: int = 3, max_mach: float = 0.05, drho: float = 1e-3,
-                   dt_scale: float = 2e-3, with_force: bool = True):
+def balance_levels(n: int, seed: int = 3, max_mach: float = 0.05, drho: float = 1e-2,
+                   dt_scale: float = 2e-3, compressive: float = 0.2, with_force: bool = True):
     """Three smooth time levels (n-2, n-1, n) of (rho, u) plus a force field.
 
-    Synthetic inputs for checking the balance diagnostic on its own: the
-    velocity at level n-k is u * (1 + k dt_scale) + k dt_scale * v with u, v
-    two independent spectrum fields; rho = 1 + drho * s_k with smooth
-    perturbations s_k.  Returns dict with lists rho[3], ux[3], uy[3] ordered
-    (n-2, n-1, n) and fx, fy (zeros when ``with_force`` is False).
+    Synthetic inputs for checking the balance diagnostic on its own.  The
+    velocity at level n-k is u * (1 + k dt_scale) + k dt_scale * v, where u and
+    v are spectrum fields plus a compressive part ``compressive`` * grad(phi)
+    (so that div u, and with it the compressibility terms, is not zero);
+    rho = 1 + drho * s_k with smooth perturbations s_k.  Returns a dict with
+    lists rho[3], ux[3], uy[3] ordered (n-2, n-1, n) and fx, fy (zeros when
+    ``with_force`` is False).
     """
     rng = np.random.default_rng(seed)
     _, ux, uy = spectrum_velocity(n, rng, max_mach=max_mach)
     _, vx, vy = spectrum_velocity(n, rng, max_mach=max_mach)
     _, sx, sy = spectrum_velocity(n, rng, max_mach=1.0)
+    _, gx, gy = spectrum_velocity(n, rng, max_mach=max_mach)
+    # a curl-free field: rotate a divergence-free one by 90 degrees (grad phi)
+    ux = ux + compressive * gy
+    uy = uy - compressive * gx
+    vx = vx - compressive * gx
+    vy = vy - compressive * gy
     rhos, uxs, uys = [], [], []
     for lev in (2, 1, 0):
         a = 1.0 + lev * dt_scale

@@ -268,12 +268,16 @@ int moments_into(lbm_ctx_s* c, void* rho, void* ux, void* uy, int out_dtype, dou
   return LBM_OK;
 }
 
+// Header of a saved state: 32 int64 words (256 bytes), unused words zero.
 __global__ void k_write_header(int64_t* h, int64_t t, int64_t h0, int64_t h1) {
-  if (threadIdx.x == 0) {
-    h[0] = 0x4c424d32;  // format tag
-    h[1] = t;
-    h[2] = h0;
-    h[3] = h1;
+  const int i = threadIdx.x;
+  if (i < 32) {
+    int64_t v = 0;
+    if (i == 0) v = 0x4c424d32;  // format tag
+    if (i == 1) v = t;
+    if (i == 2) v = h0;
+    if (i == 3) v = h1;
+    h[i] = v;
   }
 }
 

@@ -391,11 +391,23 @@ __global__ void k_to_storage(T* __restrict__ dst, const double* __restrict__ src
 }
 
 typedef float f4a __attribute__((ext_vector_type(4), aligned(16)));
+constexpr int kCopyUnroll = 4;
+// Each workgroup copies 256 * kCopyUnroll 16-byte vectors; all loads of a
+// thread are issued before its stores.
 __global__ void __launch_bounds__(256) k_copy(f4a* __restrict__ dst, const f4a* __restrict__ src,
                                               size_t n) {
-  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n;
-       i += size_t(gridDim.x) * blockDim.x)
-    dst[i] = src[i];
+  const size_t base = blockIdx.x * size_t(256 * kCopyUnroll) + threadIdx.x;
+  f4a v[kCopyUnroll];
+#pragma unroll
+  for (int k = 0; k < kCopyUnroll; ++k) {
+    const size_t i = base + size_t(k) * 256;
+    if (i < n) v[k] = src[i];
+  }
+#pragma unroll
+  for (int k = 0; k < kCopyUnroll; ++k) {
+    const size_t i = base + size_t(k) * 256;
+    if (i < n) __builtin_nontemporal_store(v[k], dst + i);
+  }
 }
 
 int grid_for(size_t n, int threads, int cap) {
@@ -547,7 +559,9 @@ int launch_to_storage(int dtype, void* dst, const double* src, size_t n, hipStre
 
 int launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
   const size_t n = bytes / 16;
-  const int g = grid_for(n, 256, 256 * 64);
+  const size_t per = size_t(256) * kCopyUnroll;
+  if ((n + per - 1) / per > 0x7fffffffu) return fail(LBM_E_INVALID, "copy too large");
+  const int g = static_cast<int>((n + per - 1) / per);
   hipLaunchKernelGGL(k_copy, dim3(g), dim3(256), 0, s, static_cast<f4a*>(dst),
                      static_cast<const f4a*>(src), n);
   LBM_HIP(hipGetLastError());

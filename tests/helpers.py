@@ -47,3 +47,41 @@ def oracle_patch_moments(fields, tau, steps, y0, x0, core, fx=None, fy=None, alp
 
 def gpu_patch(t, y0, x0, core):
     return torch.as_tensor(wrap_patch(t.detach().cpu().numpy(), y0, x0, core))
+
+
+def _perturb(a, rel, rng):
+    a = np.asarray(a, dtype=np.float64)
+    return a * (1.0 + rel * rng.standard_normal(a.shape))
+
+
+def balance_sensitivity(lv, nu, sizes, fx=None, fy=None, rel=2.2e-16, trials=2, seed=0):
+    """Conditioning of the balance on these inputs, measured with the oracle.
+
+    Every input value is multiplied by (1 + rel * N(0, 1)) and the oracle rerun;
+    returns (fields, stats, kappa_terms, kappa_stats) where kappa_* is the
+    largest observed change relative to the unperturbed value (terms: relative
+    to the field's max |value|).  Rounding inside any correct implementation
+    moves the results by about this much, so parity tolerances scale with it.
+    """
+    flds = ref.balance_fields(lv["rho"], lv["ux"], lv["uy"], fx, fy, nu)
+    stats = ref.subvolume_balance(flds, sizes) if sizes else []
+    rng = np.random.default_rng(seed)
+    kt = {k: 0.0 for k in ref.TERM_NAMES}
+    ks = [{q: {s: 0.0 for s in ("mean", "std", "min", "max")} for q in ("dE", "dZ", "Ma")}
+          for _ in stats]
+    for _ in range(trials):
+        p = {k: [_perturb(a, rel, rng) for a in lv[k]] for k in ("rho", "ux", "uy")}
+        pf = (_perturb(fx, rel, rng), _perturb(fy, rel, rng)) if fx is not None else (None, None)
+        f2 = ref.balance_fields(p["rho"], p["ux"], p["uy"], pf[0], pf[1], nu)
+        for k in ref.TERM_NAMES:
+            den = float(flds[k].abs().max()) or 1.0
+            kt[k] = max(kt[k], float((f2[k] - flds[k]).abs().max()) / den)
+        if stats:
+            s2 = ref.subvolume_balance(f2, sizes)
+            for j, (a, b) in enumerate(zip(stats, s2)):
+                for q in ("dE", "dZ", "Ma"):
+                    for s in ("mean", "std", "min", "max"):
+                        va, vb = a[q][s], b[q][s]
+                        if np.isfinite(va) and va != 0:
+                            ks[j][q][s] = max(ks[j][q][s], abs(vb - va) / abs(va))
+    return flds, stats, kt, ks
