@@ -257,19 +257,34 @@ typedef struct lbm_batch_s* lbm_batch;
  * from cfgs[0]. */
 LBM_API int lbm_batch_workspace_bytes(const lbm_config* cfgs, int32_t nruns, size_t* bytes);
 /* rho0/ux0/uy0/fx/fy: host arrays of nruns device FP64 pointers (fx/fy NULL,
- * or entries NULL for runs without force). */
+ * or entries NULL for runs without force).  Every run starts at f^eq of its
+ * fields (Eq. 2); time t = 0. */
 LBM_API int lbm_batch_init(const lbm_config* cfgs, int32_t nruns, void* ws, size_t ws_bytes,
                    const double* const* rho0, const double* const* ux0,
                    const double* const* uy0, const double* const* fx,
                    const double* const* fy, lbm_batch* out);
+/* mode: LBM_BATCH_PERSISTENT or LBM_BATCH_PER_STEP; chunk: even number of
+ * steps per graph replay (2..100000). */
 LBM_API int lbm_batch_set_mode(lbm_batch b, int32_t mode, int32_t chunk);
+/* Work-item shape: block_threads (256, 512 or 1024) threads per workgroup;
+ * vx (1, 2 or 4, dividing every run's nx) sites per thread; band_rows (1..64)
+ * groups of block_threads*vx consecutive sites per work item. */
 LBM_API int lbm_batch_set_tile(lbm_batch b, int32_t block_threads, int32_t vx, int32_t band_rows);
+/* Time every (mode, block_threads, vx, band_rows) candidate over trial_steps
+ * (even) steps and keep the fastest; the chosen mode is readable with
+ * lbm_batch_get_mode.  The trials are real steps: the ensemble advances by
+ * (2 + trial_steps) per candidate and lbm_batch_time says so. */
 LBM_API int lbm_batch_autotune(lbm_batch b, int32_t trial_steps, int32_t* block_threads,
                        int32_t* vx, int32_t* band_rows);
+LBM_API int lbm_batch_get_mode(lbm_batch b, int32_t* mode, int32_t* chunk);
+/* Advance every run by n steps (asynchronous). */
 LBM_API int lbm_batch_step(lbm_batch b, int64_t n);
+/* Moments of one run, as lbm_moments.  Synchronises to read the barrier error
+ * flag first: LBM_E_TIMEOUT if a persistent launch gave up waiting. */
 LBM_API int lbm_batch_moments(lbm_batch b, int32_t run, void* rho, void* ux, void* uy,
                       int32_t out_dtype, double* scalars8);
 LBM_API int lbm_batch_time(lbm_batch b, int64_t* t);
+/* Total lattice sites over all runs (one step updates this many sites). */
 LBM_API int64_t lbm_batch_sites(lbm_batch b);
 LBM_API int lbm_batch_destroy(lbm_batch b);
 

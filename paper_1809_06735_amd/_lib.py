@@ -112,6 +112,7 @@ SIGNATURES = {
     "lbm_batch_set_mode": (_I, [_P, _I32, _I32]),
     "lbm_batch_set_tile": (_I, [_P, _I32, _I32, _I32]),
     "lbm_batch_autotune": (_I, [_P, _I32, C.POINTER(_I32), C.POINTER(_I32), C.POINTER(_I32)]),
+    "lbm_batch_get_mode": (_I, [_P, C.POINTER(_I32), C.POINTER(_I32)]),
     "lbm_batch_step": (_I, [_P, _I64]),
     "lbm_batch_moments": (_I, [_P, _I32, _P, _P, _P, _I32, _DP]),
     "lbm_batch_time": (_I, [_P, C.POINTER(_I64)]),

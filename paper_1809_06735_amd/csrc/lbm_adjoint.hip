@@ -1,14 +1,649 @@
-// Discrete adjoint (filled in below).
+// Discrete adjoint of an unforced D2Q9 BGK run with respect to the initial
+// velocity field and tau, for the loss
+//   J = mean over all L x L windows V of (RHS^Omega_V - LHS^Omega_V)^2
+// (the enstrophy balance of Eq. 11 at the last step; a window of side
+// L == nx == ny is the single whole-domain window).
+//
+// State convention (as in the forward step): the stored populations g^t are
+// un-streamed, f^t_l(x) = g^t_l(x - c_l), and one step is g^{t+1}(x) = C(f^t(x)).
+// The adjoint is kept at the site as a^t(x) = dJ/df^t(x); one backward step is
+//   a^t(x) = C'(f^t(x))^T v(x) + M'(f^t(x))^T mhat^t(x),  v_l(x) = a^{t+1}_l(x + c_l),
+// i.e. a pull from x + c_l (the transpose of the forward pull), where M maps
+// f to (rho, u) and mhat^t are the loss seeds at t = T, T-1, T-2.  The tau
+// derivative collects v . dC/dtau = v . (f - f^eq)/tau^2 per step plus the
+// explicit dependence of the viscous stress on nu = (tau - 1/2)/3; the initial
+// velocity gradient is (df^eq/du)^T a^0.
+//
+// Memory: populations are checkpointed every K steps; each segment is
+// recomputed forward into a buffer of K+1 states and swept backward.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "lbm_fd8.h"
 #include "lbm_internal.h"
+#include "lbm_site.h"
+
+namespace lbm {
+namespace {
+
+using namespace fd8;
+using namespace step_detail;
+
+constexpr int kAT = 256;
+
+// ---- loss: residual field and its adjoint (FP64) ---------------------------------
+__global__ void __launch_bounds__(256) k_residual(const double* __restrict__ terms, size_t plane,
+                                                  double* __restrict__ r) {
+  for (size_t i = blockIdx.x * size_t(256) + threadIdx.x; i < plane; i += size_t(gridDim.x) * 256)
+    r[i] = (((terms[LBM_T_Z1 * plane + i] + terms[LBM_T_Z2 * plane + i]) +
+             terms[LBM_T_Z3 * plane + i]) +
+            (terms[LBM_T_Z4 * plane + i] + terms[LBM_T_Z5 * plane + i])) -
+           terms[LBM_T_LHS_Z * plane + i];
+}
+
+__global__ void __launch_bounds__(256) k_set(double* __restrict__ out, size_t n, double v) {
+  for (size_t i = blockIdx.x * size_t(256) + threadIdx.x; i < n; i += size_t(gridDim.x) * 256)
+    out[i] = v;
+}
+
+__global__ void __launch_bounds__(256) k_fill(double* __restrict__ out, size_t n, const double* v,
+                                              double scale) {
+  const double val = scale * v[0];
+  for (size_t i = blockIdx.x * size_t(256) + threadIdx.x; i < n; i += size_t(gridDim.x) * 256)
+    out[i] = val;
+}
+
+// sum of squares of a field, block partials, then one block (deterministic)
+__global__ void __launch_bounds__(256) k_sumsq(const double* __restrict__ g, size_t n,
+                                               double* partials) {
+  __shared__ double sh[4];
+  double acc = 0.0;
+  for (size_t i = blockIdx.x * size_t(256) + threadIdx.x; i < n; i += size_t(gridDim.x) * 256)
+    acc += g[i] * g[i];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) partials[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+__global__ void __launch_bounds__(256) k_sum(const double* __restrict__ g, size_t n,
+                                            double* partials) {
+  __shared__ double sh[4];
+  double acc = 0.0;
+  for (size_t i = blockIdx.x * size_t(256) + threadIdx.x; i < n; i += size_t(gridDim.x) * 256)
+    acc += g[i];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) partials[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+__global__ void __launch_bounds__(256) k_sum_partials(const double* __restrict__ p, int n,
+                                                      double scale, double* out) {
+  __shared__ double sh[4];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) acc += p[i];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) out[0] = scale * ((sh[0] + sh[1]) + (sh[2] + sh[3]));
+}
+
+struct AdjLoss {
+  const double* rho;   // level n
+  const double* ux;
+  const double* uy;
+  const double* ux1;   // level n-1
+  const double* uy1;
+  const double* ux2;   // level n-2
+  const double* uy2;
+  const double* aux;   // balance aux fields (omega, Omega, H, sigma ...)
+  const double* rhat;  // dJ/dr
+  double* w;           // scratch fields [kAdjFields][plane]
+  double nu;
+  int nx, ny;
+};
+
+// scratch field indices
+enum {
+  S_W1 = 0, S_WX, S_WY, S_HTX, S_HTY, S_RHOH, S_UXD, S_UYD, S_DIV, S_OM1, S_OM2,
+  S_AH, S_BH, S_CH, S_DH, S_RHON, S_NUS, S_UX1, S_UY1, S_UX2, S_UY2, S_UXN, S_UYN,
+  kAdjFields
+};
+
+__device__ __forceinline__ size_t sidx(int x, int y, int nx) { return static_cast<size_t>(y) * nx + x; }
+
+// Adjoint of the pointwise products and of the first layer of differences.
+__global__ void __launch_bounds__(256) k_loss_b1(AdjLoss a) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  if (x >= a.nx || y >= a.ny) return;
+  const int nx = a.nx, ny = a.ny;
+  const size_t plane = static_cast<size_t>(nx) * ny;
+  const size_t i = sidx(x, y, nx);
+  const double* W = a.aux + AUX_W * plane;
+  const double rh = a.rhat[i];
+  const double gx = fd8_x(F1{a.rhat, nx}, x, y, nx);
+  const double gy = fd8_y(F1{a.rhat, nx}, x, y, ny);
+  const double ad = fd8_x(F1{a.ux, nx}, x, y, nx);       // d_x u_x
+  const double dd = fd8_y(F1{a.uy, nx}, x, y, ny);       // d_y u_y
+  const double om = W[i];
+  const double Om = a.aux[AUX_OM2 * plane + i];
+  const double hx = a.aux[AUX_HX * plane + i];
+  const double hy = a.aux[AUX_HY * plane + i];
+  const double wx = fd8_x(F1{W, nx}, x, y, nx);
+  const double wy = fd8_y(F1{W, nx}, x, y, ny);
+  const double ux = a.ux[i], uy = a.uy[i], r = a.rho[i];
+  const double div = ad + dd;
+  const double Omh = gx * ux + gy * uy - rh * div - 1.5 * rh;   // dJ/dOmega (level n)
+  const double hhx = gy * om + rh * wy;                          // dJ/dH_x
+  const double hhy = -gx * om - rh * wx;                         // dJ/dH_y
+  double* w = a.w;
+  w[S_W1 * plane + i] = -gx * hy + gy * hx + Omh * om;           // dJ/domega, local part
+  w[S_WX * plane + i] = -rh * hy;                                // dJ/d(d_x omega)
+  w[S_WY * plane + i] = rh * hx;                                 // dJ/d(d_y omega)
+  w[S_HTX * plane + i] = hhx / r;
+  w[S_HTY * plane + i] = hhy / r;
+  w[S_RHOH * plane + i] = -(hhx * hx + hhy * hy) / r;
+  w[S_UXD * plane + i] = gx * Om;
+  w[S_UYD * plane + i] = gy * Om;
+  w[S_DIV * plane + i] = -rh * Om;
+  const double om1 = fd8_x(F1{a.uy1, nx}, x, y, nx) - fd8_y(F1{a.ux1, nx}, x, y, ny);
+  const double om2 = fd8_x(F1{a.uy2, nx}, x, y, nx) - fd8_y(F1{a.ux2, nx}, x, y, ny);
+  w[S_OM1 * plane + i] = 2.0 * rh * om1;                         // dJ/domega^{n-1}
+  w[S_OM2 * plane + i] = -0.5 * rh * om2;                        // dJ/domega^{n-2}
+}
+
+// Adjoint of the second layer of differences and of the viscous stress.
+__global__ void __launch_bounds__(256) k_loss_b2(AdjLoss a) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  if (x >= a.nx || y >= a.ny) return;
+  const int nx = a.nx, ny = a.ny;
+  const size_t plane = static_cast<size_t>(nx) * ny;
+  const size_t i = sidx(x, y, nx);
+  double* w = a.w;
+  const double omh = w[S_W1 * plane + i] - fd8_x(F1{w + S_WX * plane, nx}, x, y, nx) -
+                     fd8_y(F1{w + S_WY * plane, nx}, x, y, ny);
+  const double* htx = w + S_HTX * plane;
+  const double* hty = w + S_HTY * plane;
+  const double sxx = -fd8_x(F1{htx, nx}, x, y, nx);
+  const double sxy = -fd8_y(F1{htx, nx}, x, y, ny) - fd8_x(F1{hty, nx}, x, y, nx);
+  const double syy = -fd8_y(F1{hty, nx}, x, y, ny);
+  const double ad = fd8_x(F1{a.ux, nx}, x, y, nx);
+  const double bd = fd8_y(F1{a.ux, nx}, x, y, ny);
+  const double cd = fd8_x(F1{a.uy, nx}, x, y, nx);
+  const double dd = fd8_y(F1{a.uy, nx}, x, y, ny);
+  const double r = a.rho[i], nu = a.nu;
+  const double divh = w[S_DIV * plane + i];
+  w[S_AH * plane + i] = divh + 2.0 * nu * r * sxx;
+  w[S_DH * plane + i] = divh + 2.0 * nu * r * syy;
+  w[S_CH * plane + i] = omh + nu * r * sxy;
+  w[S_BH * plane + i] = -omh + nu * r * sxy;
+  w[S_RHON * plane + i] = w[S_RHOH * plane + i] + 2.0 * nu * (ad * sxx + dd * syy) + nu * (cd + bd) * sxy;
+  w[S_NUS * plane + i] = r * (2.0 * ad * sxx + 2.0 * dd * syy + (cd + bd) * sxy);
+  const double* o1 = w + S_OM1 * plane;
+  const double* o2 = w + S_OM2 * plane;
+  w[S_UX1 * plane + i] = fd8_y(F1{o1, nx}, x, y, ny);
+  w[S_UY1 * plane + i] = -fd8_x(F1{o1, nx}, x, y, nx);
+  w[S_UX2 * plane + i] = fd8_y(F1{o2, nx}, x, y, ny);
+  w[S_UY2 * plane + i] = -fd8_x(F1{o2, nx}, x, y, nx);
+}
+
+// Adjoint of the velocity gradients at level n.
+__global__ void __launch_bounds__(256) k_loss_b3(AdjLoss a) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  if (x >= a.nx || y >= a.ny) return;
+  const int nx = a.nx, ny = a.ny;
+  const size_t plane = static_cast<size_t>(nx) * ny;
+  const size_t i = sidx(x, y, nx);
+  double* w = a.w;
+  w[S_UXN * plane + i] = w[S_UXD * plane + i] - fd8_x(F1{w + S_AH * plane, nx}, x, y, nx) -
+                         fd8_y(F1{w + S_BH * plane, nx}, x, y, ny);
+  w[S_UYN * plane + i] = w[S_UYD * plane + i] - fd8_x(F1{w + S_CH * plane, nx}, x, y, nx) -
+                         fd8_y(F1{w + S_DH * plane, nx}, x, y, ny);
+}
+
+// ---- population adjoint -------------------------------------------------------------
+struct Seeds {
+  const double* rho;  // may be null (zero)
+  const double* ux;
+  const double* uy;
+};
+
+template <typename T>
+__device__ __forceinline__ void pull_sites(const T* __restrict__ g, size_t plane, int nx, int ny,
+                                           int x, int y, int sign, T (&d)[9]) {
+  // d_l = g_l(x - sign * c_l)
+#pragma unroll
+  for (int l = 0; l < 9; ++l) {
+    int xs = x - sign * cxq(l), ys = y - sign * cyq(l);
+    xs += xs < 0 ? nx : 0;
+    xs -= xs >= nx ? nx : 0;
+    ys += ys < 0 ? ny : 0;
+    ys -= ys >= ny ? ny : 0;
+    d[l] = g[l * plane + static_cast<size_t>(ys) * nx + xs];
+  }
+}
+
+// a^T(x) = M'(f^T(x))^T mhat^T(x)
+template <typename T>
+__global__ void __launch_bounds__(kAT) k_adj_init(const T* __restrict__ g, T* __restrict__ adj,
+                                                  Seeds s, int nx, int ny) {
+  const size_t plane = static_cast<size_t>(nx) * ny;
+  const size_t i = blockIdx.x * size_t(kAT) + threadIdx.x;
+  if (i >= plane) return;
+  const int x = static_cast<int>(i % nx), y = static_cast<int>(i / nx);
+  T d[9];
+  pull_sites<T>(g, plane, nx, ny, x, y, 1, d);
+  SiteMoments<T, false> m(d, T(0), T(0), T(0));
+  const double rh = s.rho ? s.rho[i] : 0.0;
+  const double ux = double(m.ux), uy = double(m.uy), rho = double(m.rho);
+#pragma unroll
+  for (int l = 0; l < 9; ++l)
+    adj[l * plane + i] = T(rh + (s.ux[i] * (cxq(l) - ux) + s.uy[i] * (cyq(l) - uy)) / rho);
+}
+
+// One backward step; also adds this step's sum of v . dC/dtau to the block's slot.
+template <typename T>
+__global__ void __launch_bounds__(kAT) k_adj_step(const T* __restrict__ g, const T* __restrict__ ain,
+                                                  T* __restrict__ aout, Seeds s, int has_seed,
+                                                  int nx, int ny, double omega, double* tau_acc) {
+  __shared__ double sh[kAT / 64];
+  const size_t plane = static_cast<size_t>(nx) * ny;
+  const size_t i = blockIdx.x * size_t(kAT) + threadIdx.x;
+  double dtau = 0.0;
+  if (i < plane) {
+    const int x = static_cast<int>(i % nx), y = static_cast<int>(i / nx);
+    T d[9], v[9];
+    pull_sites<T>(g, plane, nx, ny, x, y, 1, d);      // f^t(x) (deviation)
+    pull_sites<T>(ain, plane, nx, ny, x, y, -1, v);   // a^{t+1}(x + c_l)
+    SiteMoments<T, false> m(d, T(0), T(0), T(0));
+    const T om = T(omega);
+    const T usq15 = T(1.5) * (m.ux * m.ux + m.uy * m.uy);
+    T A = T(0), Bx = T(0), By = T(0), neq = T(0);
+#pragma unroll
+    for (int l = 0; l < 9; ++l) {
+      const T w = T(wq(l));
+      const T cx = T(cxq(l)), cy = T(cyq(l));
+      const T cu = cx * m.ux + cy * m.uy;
+      const T P = T(1) + T(3) * cu + T(4.5) * cu * cu - usq15;
+      const T deq = w * (m.drho + m.rho * (P - T(1)));
+      A += v[l] * w * P;
+      Bx += v[l] * w * (T(3) * cx + T(9) * cu * cx - T(3) * m.ux);
+      By += v[l] * w * (T(3) * cy + T(9) * cu * cy - T(3) * m.uy);
+      neq += v[l] * (d[l] - deq);
+    }
+    Bx *= m.rho;
+    By *= m.rho;
+    const T inv = T(1) / m.rho;
+    const double rh = (has_seed && s.rho) ? s.rho[i] : 0.0;
+    const double sx = has_seed ? s.ux[i] : 0.0, sy = has_seed ? s.uy[i] : 0.0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const T ex = T(cxq(k)) - m.ux, ey = T(cyq(k)) - m.uy;
+      T o = (T(1) - om) * v[k] + om * (A + (Bx * ex + By * ey) * inv);
+      if (has_seed) o += T(rh + (sx * double(ex) + sy * double(ey)) / double(m.rho));
+      aout[k * plane + i] = o;
+    }
+    dtau = double(neq) * omega * omega;   // v . (f - f^eq) / tau^2
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) dtau += __shfl_xor(dtau, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = dtau;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double b = 0.0;
+    for (int k = 0; k < kAT / 64; ++k) b += sh[k];
+    tau_acc[blockIdx.x] += b;
+  }
+}
+
+// du0 = sum_l a^0_l df^eq_l/du at (rho0 = 1, u0)
+template <typename T>
+__global__ void __launch_bounds__(kAT) k_adj_u0(const T* __restrict__ adj, const double* __restrict__ ux0,
+                                                const double* __restrict__ uy0, int nx, int ny,
+                                                double* gx, double* gy) {
+  const size_t plane = static_cast<size_t>(nx) * ny;
+  const size_t i = blockIdx.x * size_t(kAT) + threadIdx.x;
+  if (i >= plane) return;
+  const double ux = ux0[i], uy = uy0[i];
+  double bx = 0.0, by = 0.0;
+#pragma unroll
+  for (int l = 0; l < 9; ++l) {
+    const double a = double(adj[l * plane + i]);
+    const double cu = cxq(l) * ux + cyq(l) * uy;
+    bx += a * wq(l) * (3.0 * cxq(l) + 9.0 * cu * cxq(l) - 3.0 * ux);
+    by += a * wq(l) * (3.0 * cyq(l) + 9.0 * cu * cyq(l) - 3.0 * uy);
+  }
+  gx[i] = bx;
+  gy[i] = by;
+}
+
+__global__ void k_zero(double* p, size_t n) {
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
+    p[i] = 0.0;
+}
+
+// ---- workspace ------------------------------------------------------------------------
+struct AdjWs {
+  void* ckpt;          // [nck][9][plane] storage type
+  void* seg;           // [K+1][9][plane]
+  void* adj[2];        // [9][plane]
+  double* mom[3][3];   // levels T-2, T-1, T: rho, ux, uy
+  double* r;           // residual field
+  double* rmap;        // window means R(corner)
+  double* rhat;
+  double* w;           // [kAdjFields][plane]
+  double* small;       // scalars / partials
+  double* tau_acc;     // [blocks]
+  double* fill;        // zero field for rho0... (rho0 = 1 field)
+  BalanceWs bal;
+  size_t bytes;
+};
+
+int nblocks_sites(size_t plane) { return static_cast<int>((plane + kAT - 1) / kAT); }
+
+AdjWs carve_adj(const lbm_adjoint_config& c, void* base, size_t cap) {
+  Carver cv(base, cap);
+  const size_t plane = static_cast<size_t>(c.nx) * c.ny;
+  const size_t es = c.dtype == LBM_F32 ? 4 : 8;
+  const int64_t nck = (c.steps + c.ckpt_every - 1) / c.ckpt_every;
+  AdjWs w{};
+  w.ckpt = cv.take<char>(static_cast<size_t>(nck) * 9 * plane * es);
+  w.seg = cv.take<char>(static_cast<size_t>(c.ckpt_every + 1) * 9 * plane * es);
+  w.adj[0] = cv.take<char>(9 * plane * es);
+  w.adj[1] = cv.take<char>(9 * plane * es);
+  for (int l = 0; l < 3; ++l)
+    for (int k = 0; k < 3; ++k) w.mom[l][k] = cv.take<double>(plane);
+  w.r = cv.take<double>(plane);
+  w.rmap = cv.take<double>(plane);
+  w.rhat = cv.take<double>(plane);
+  w.w = cv.take<double>(static_cast<size_t>(kAdjFields) * plane);
+  w.small = cv.take<double>(4096 + 64);
+  w.tau_acc = cv.take<double>(nblocks_sites(plane) + 64);
+  w.fill = cv.take<double>(plane);
+  w.bal = carve_balance(cv, c.nx, c.ny);
+  w.bytes = cv.used + 256;
+  return w;
+}
+
+int validate_adj(const lbm_adjoint_config* c) {
+  if (!c) return fail(LBM_E_INVALID, "config is NULL");
+  if (c->nx < 16 || c->ny < 16 || c->nx > 16384 || c->ny > 16384)
+    return fail(LBM_E_INVALID, "grid %d x %d outside [16, 16384]", c->nx, c->ny);
+  if (c->dtype != LBM_F32 && c->dtype != LBM_F64) return fail(LBM_E_INVALID, "bad dtype");
+  if (!(c->tau > 0.5) || !std::isfinite(c->tau)) return fail(LBM_E_INVALID, "tau must be > 0.5");
+  if (c->steps < 2 || c->steps > 10000000) return fail(LBM_E_INVALID, "steps must be >= 2");
+  if (c->ckpt_every < 1 || c->ckpt_every > 100000) return fail(LBM_E_INVALID, "ckpt_every >= 1");
+  const int m = std::min(c->nx, c->ny);
+  if (c->box < 1 || c->box > m) return fail(LBM_E_INVALID, "box %d outside [1, %d]", c->box, m);
+  if (c->reserved != 0) return fail(LBM_E_INVALID, "reserved must be 0");
+  return LBM_OK;
+}
+
+template <typename T>
+int launch_adj_init(const void* g, void* adj, Seeds s, int nx, int ny, hipStream_t st) {
+  const size_t plane = static_cast<size_t>(nx) * ny;
+  hipLaunchKernelGGL(k_adj_init<T>, dim3(nblocks_sites(plane)), dim3(kAT), 0, st,
+                     static_cast<const T*>(g), static_cast<T*>(adj), s, nx, ny);
+  LBM_HIP(hipGetLastError());
+  return LBM_OK;
+}
+
+template <typename T>
+int launch_adj_step(const void* g, const void* ain, void* aout, Seeds s, int has_seed, int nx,
+                    int ny, double omega, double* tau_acc, hipStream_t st) {
+  const size_t plane = static_cast<size_t>(nx) * ny;
+  hipLaunchKernelGGL(k_adj_step<T>, dim3(nblocks_sites(plane)), dim3(kAT), 0, st,
+                     static_cast<const T*>(g), static_cast<const T*>(ain), static_cast<T*>(aout),
+                     s, has_seed, nx, ny, omega, tau_acc);
+  LBM_HIP(hipGetLastError());
+  return LBM_OK;
+}
+
+template <typename T>
+int launch_adj_u0(const void* adj, const double* ux0, const double* uy0, int nx, int ny,
+                  double* gx, double* gy, hipStream_t st) {
+  const size_t plane = static_cast<size_t>(nx) * ny;
+  hipLaunchKernelGGL(k_adj_u0<T>, dim3(nblocks_sites(plane)), dim3(kAT), 0, st,
+                     static_cast<const T*>(adj), ux0, uy0, nx, ny, gx, gy);
+  LBM_HIP(hipGetLastError());
+  return LBM_OK;
+}
+
+struct Runner {
+  lbm_adjoint_config c;
+  AdjWs w;
+  hipStream_t s;
+  size_t plane, state_bytes;
+  lbm_tile tile;
+  void* seg_state(int k) const { return static_cast<char*>(w.seg) + k * state_bytes; }
+  void* ckpt_state(int64_t k) const { return static_cast<char*>(w.ckpt) + k * state_bytes; }
+
+  int step(const void* src, void* dst, double* hr, double* hx, double* hy) {
+    StepParams p{};
+    p.src = src;
+    p.dst = dst;
+    p.h_rho = hr;
+    p.h_ux = hx;
+    p.h_uy = hy;
+    p.nx = c.nx;
+    p.ny = c.ny;
+    p.omega = 1.0 / c.tau;
+    p.alpha = 0.0;
+    return launch_step(c.dtype, false, p, tile, s);
+  }
+};
+
+}  // namespace
+}  // namespace lbm
 
 using namespace lbm;
 
 extern "C" {
-int lbm_adjoint_workspace_bytes(const lbm_adjoint_config*, size_t*) { return fail(LBM_E_UNSUPPORTED, "adjoint: not built"); }
-int lbm_adjoint_run(const lbm_adjoint_config*, void*, size_t, const double*, const double*, double*, double*,
-                    double*, double*) {
-  return fail(LBM_E_UNSUPPORTED, "adjoint: not built");
+
+int lbm_adjoint_workspace_bytes(const lbm_adjoint_config* cfg, size_t* bytes) {
+  if (int rc = validate_adj(cfg)) return rc;
+  if (!bytes) return fail(LBM_E_INVALID, "bytes is NULL");
+  *bytes = carve_adj(*cfg, nullptr, 0).bytes;
+  return LBM_OK;
 }
+
+int lbm_adjoint_run(const lbm_adjoint_config* cfg, void* ws, size_t ws_bytes, const double* ux0,
+                    const double* uy0, double* loss, double* grad_ux0, double* grad_uy0,
+                    double* grad_tau) {
+  if (int rc = validate_adj(cfg)) return rc;
+  if (!ws || reinterpret_cast<uintptr_t>(ws) % 256 != 0)
+    return fail(LBM_E_INVALID, "workspace must be non-NULL and 256-byte aligned");
+  if (!ux0 || !uy0 || !loss) return fail(LBM_E_INVALID, "ux0, uy0 and loss must not be NULL");
+  if ((grad_ux0 == nullptr) != (grad_uy0 == nullptr))
+    return fail(LBM_E_INVALID, "grad_ux0 and grad_uy0 must both be given or both be NULL");
+  const size_t need = carve_adj(*cfg, nullptr, 0).bytes;
+  if (ws_bytes < need) return fail(LBM_E_NOMEM, "workspace %zu < %zu", ws_bytes, need);
+
+  Runner R;
+  R.c = *cfg;
+  R.w = carve_adj(*cfg, ws, ws_bytes);
+  R.s = static_cast<hipStream_t>(cfg->stream);
+  R.plane = static_cast<size_t>(cfg->nx) * cfg->ny;
+  R.state_bytes = 9 * R.plane * (cfg->dtype == LBM_F32 ? 4 : 8);
+  R.tile = default_tile(cfg->dtype, cfg->nx, cfg->ny);
+  const int nx = cfg->nx, ny = cfg->ny;
+  const int64_t T = cfg->steps;
+  const int K = cfg->ckpt_every;
+  const hipStream_t s = R.s;
+  const int g = static_cast<int>(std::min<size_t>((R.plane + 255) / 256, 4096));
+
+  // ---- forward: init, steps with checkpoints, moments at T-2, T-1, T ----
+  hipLaunchKernelGGL(k_set, dim3(g), dim3(256), 0, s, R.w.fill, R.plane, 1.0);   // rho0 = 1
+  LBM_HIP(hipGetLastError());
+  if (int rc = launch_init(cfg->dtype, R.ckpt_state(0), R.w.fill, ux0, uy0, nx, ny, s)) return rc;
+  void* cur = R.w.adj[0];
+  void* nxt = R.w.adj[1];
+  LBM_HIP(hipMemcpyAsync(cur, R.ckpt_state(0), R.state_bytes, hipMemcpyDeviceToDevice, s));
+  for (int64_t t = 0; t < T; ++t) {
+    double* h[3] = {nullptr, nullptr, nullptr};
+    if (t == T - 2 || t == T - 1) {
+      const int lv = static_cast<int>(t - (T - 2));
+      for (int k = 0; k < 3; ++k) h[k] = R.w.mom[lv][k];
+    }
+    if (int rc = R.step(cur, nxt, h[0], h[1], h[2])) return rc;
+    std::swap(cur, nxt);
+    if ((t + 1) % K == 0 && t + 1 < T)
+      LBM_HIP(hipMemcpyAsync(R.ckpt_state((t + 1) / K), cur, R.state_bytes, hipMemcpyDeviceToDevice, s));
+  }
+  {
+    MomentParams m{};
+    m.pop = cur;
+    m.out_dtype = LBM_F64;
+    m.rho64 = R.w.mom[2][0];
+    m.ux64 = R.w.mom[2][1];
+    m.uy64 = R.w.mom[2][2];
+    m.partials = R.w.w;  // scratch (block partials, overwritten later)
+    m.nx = nx;
+    m.ny = ny;
+    if (int rc = launch_moments(cfg->dtype, false, m, s)) return rc;
+  }
+
+  // ---- loss ----
+  lbm_balance_input in{};
+  in.nx = nx;
+  in.ny = ny;
+  in.nu = (cfg->tau - 0.5) / 3.0;
+  for (int l = 0; l < 3; ++l) {
+    in.rho[l] = R.w.mom[l][0];
+    in.ux[l] = R.w.mom[l][1];
+    in.uy[l] = R.w.mom[l][2];
+  }
+  in.stream = s;
+  if (int rc = balance_terms(in, R.w.bal)) return rc;
+  hipLaunchKernelGGL(k_residual, dim3(g), dim3(256), 0, s, R.w.bal.terms, R.plane, R.w.r);
+  LBM_HIP(hipGetLastError());
+  const int L = cfg->box;
+  const bool single = (L == nx && L == ny);
+  double* rmean = R.w.small + 4096 + 8;
+  double* part = R.w.small;   // up to 4096 partials
+  if (int rc = field_means(R.w.r, 1, nx, ny, R.w.bal.partials + R.w.bal.partials_cap, rmean, s)) return rc;
+  double* jdev = R.w.small + 4096 + 16;
+  const double nwin = single ? 1.0 : double(R.plane);
+  if (single) {
+    // J = mean(r)^2; dJ/dr = 2 mean(r) / N^2
+    hipLaunchKernelGGL(k_sumsq, dim3(1), dim3(256), 0, s, rmean, static_cast<size_t>(1), part);
+    LBM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, part, 1, 1.0, jdev);
+    LBM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_fill, dim3(g), dim3(256), 0, s, R.w.rhat, R.plane, rmean,
+                       2.0 / double(R.plane));
+    LBM_HIP(hipGetLastError());
+  } else {
+    double* sat = R.w.bal.sat;
+    if (int rc = sat_build(R.w.r, 1, rmean, sat, nx, ny, s)) return rc;
+    if (int rc = box_map(sat, rmean, 0, L, 0, 1.0 / (double(L) * L), R.w.rmap, nx, ny, s)) return rc;
+    hipLaunchKernelGGL(k_sumsq, dim3(g), dim3(256), 0, s, R.w.rmap, R.plane, part);
+    LBM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, part, g, 1.0 / nwin, jdev);
+    LBM_HIP(hipGetLastError());
+    // dJ/dr(x) = 2/(W L^2) * sum of R over the corners whose window holds x
+    double* rmm = R.w.small + 4096 + 24;
+    if (int rc = field_means(R.w.rmap, 1, nx, ny, R.w.bal.partials + R.w.bal.partials_cap, rmm, s))
+      return rc;
+    if (int rc = sat_build(R.w.rmap, 1, rmm, sat, nx, ny, s)) return rc;
+    if (int rc = box_map(sat, rmm, 0, L, -(L - 1), 2.0 / (nwin * double(L) * L), R.w.rhat, nx, ny, s))
+      return rc;
+  }
+  LBM_HIP(hipMemcpyAsync(loss, jdev, sizeof(double), hipMemcpyDeviceToHost, s));
+  if (!grad_ux0 && !grad_tau) {
+    LBM_HIP(hipStreamSynchronize(s));
+    return LBM_OK;
+  }
+
+  // ---- loss adjoint: seeds at T, T-1, T-2 and the explicit nu derivative ----
+  AdjLoss al{};
+  al.rho = R.w.mom[2][0];
+  al.ux = R.w.mom[2][1];
+  al.uy = R.w.mom[2][2];
+  al.ux1 = R.w.mom[1][1];
+  al.uy1 = R.w.mom[1][2];
+  al.ux2 = R.w.mom[0][1];
+  al.uy2 = R.w.mom[0][2];
+  al.aux = R.w.bal.aux;
+  al.rhat = R.w.rhat;
+  al.w = R.w.w;
+  al.nu = in.nu;
+  al.nx = nx;
+  al.ny = ny;
+  dim3 blk(64, 4), grd((nx + 63) / 64, (ny + 3) / 4);
+  hipLaunchKernelGGL(k_loss_b1, grd, blk, 0, s, al);
+  LBM_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_loss_b2, grd, blk, 0, s, al);
+  LBM_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_loss_b3, grd, blk, 0, s, al);
+  LBM_HIP(hipGetLastError());
+  double* nuh = R.w.small + 4096 + 32;
+  hipLaunchKernelGGL(k_sum, dim3(g), dim3(256), 0, s, R.w.w + S_NUS * R.plane, R.plane, part);
+  LBM_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, part, g, 1.0, nuh);
+  LBM_HIP(hipGetLastError());
+
+  // ---- population adjoint, segment by segment from the last ----
+  const int nb = nblocks_sites(R.plane);
+  hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, s, R.w.tau_acc, static_cast<size_t>(nb));
+  LBM_HIP(hipGetLastError());
+  const double omega = 1.0 / cfg->tau;
+  const Seeds sT{R.w.w + S_RHON * R.plane, R.w.w + S_UXN * R.plane, R.w.w + S_UYN * R.plane};
+  const Seeds s1{nullptr, R.w.w + S_UX1 * R.plane, R.w.w + S_UY1 * R.plane};
+  const Seeds s2{nullptr, R.w.w + S_UX2 * R.plane, R.w.w + S_UY2 * R.plane};
+  const bool f32 = cfg->dtype == LBM_F32;
+  void* ain = R.w.adj[0];
+  void* aout = R.w.adj[1];
+  const int64_t nseg = (T + K - 1) / K;
+  for (int64_t sg = nseg - 1; sg >= 0; --sg) {
+    const int64_t t0 = sg * K;
+    const int64_t t1 = std::min<int64_t>(t0 + K, T);
+    LBM_HIP(hipMemcpyAsync(R.seg_state(0), R.ckpt_state(sg), R.state_bytes, hipMemcpyDeviceToDevice, s));
+    for (int64_t k = 0; k < t1 - t0; ++k)
+      if (int rc = R.step(R.seg_state(static_cast<int>(k)), R.seg_state(static_cast<int>(k + 1)),
+                          nullptr, nullptr, nullptr))
+        return rc;
+    if (sg == nseg - 1) {
+      const int rc = f32 ? launch_adj_init<float>(R.seg_state(static_cast<int>(t1 - t0)), ain, sT, nx, ny, s)
+                         : launch_adj_init<double>(R.seg_state(static_cast<int>(t1 - t0)), ain, sT, nx, ny, s);
+      if (rc) return rc;
+    }
+    for (int64_t t = t1 - 1; t >= t0; --t) {
+      const bool seed = (t == T - 1) || (t == T - 2);
+      const Seeds sd = (t == T - 1) ? s1 : s2;
+      const void* gt = R.seg_state(static_cast<int>(t - t0));
+      const int rc = f32 ? launch_adj_step<float>(gt, ain, aout, sd, seed ? 1 : 0, nx, ny, omega, R.w.tau_acc, s)
+                         : launch_adj_step<double>(gt, ain, aout, sd, seed ? 1 : 0, nx, ny, omega, R.w.tau_acc, s);
+      if (rc) return rc;
+      std::swap(ain, aout);
+    }
+  }
+  // ain now holds dJ/df^0
+  if (grad_ux0) {
+    const int rc = f32 ? launch_adj_u0<float>(ain, ux0, uy0, nx, ny, grad_ux0, grad_uy0, s)
+                       : launch_adj_u0<double>(ain, ux0, uy0, nx, ny, grad_ux0, grad_uy0, s);
+    if (rc) return rc;
+  }
+  double tsum_dev_host[2] = {0.0, 0.0};
+  double* tsum = R.w.small + 4096 + 40;
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, R.w.tau_acc, nb, 1.0, tsum);
+  LBM_HIP(hipGetLastError());
+  LBM_HIP(hipMemcpyAsync(&tsum_dev_host[0], tsum, sizeof(double), hipMemcpyDeviceToHost, s));
+  LBM_HIP(hipMemcpyAsync(&tsum_dev_host[1], nuh, sizeof(double), hipMemcpyDeviceToHost, s));
+  LBM_HIP(hipStreamSynchronize(s));
+  // dJ/dtau = collision part + explicit viscosity part (dnu/dtau = 1/3)
+  if (grad_tau) *grad_tau = tsum_dev_host[0] + tsum_dev_host[1] / 3.0;
+  return LBM_OK;
 }
+
+}  // extern "C"

@@ -19,73 +19,17 @@
 #include <cmath>
 #include <vector>
 
+#include "lbm_fd8.h"
 #include "lbm_internal.h"
 
 namespace lbm {
 namespace {
 
+using namespace fd8;
+
 constexpr int NT = LBM_NTERMS;
+constexpr int kMaxFusedSides = 8;
 enum { A_E = 0, A_OM2 = 1, A_W = 2, A_SXX = 3, A_SYY = 4, A_SXY = 5, A_HX = 6, A_HY = 7, NAUX = 8 };
-
-__device__ __forceinline__ int wrap_add(int i, int m, int n) {
-  int j = i + m;
-  j -= j >= n ? n : 0;
-  j += j < 0 ? n : 0;
-  return j;
-}
-
-// Eq. 18 applied to a value accessor g(x, y) along x or y.
-template <class G>
-__device__ __forceinline__ double fd8_x(const G& g, int x, int y, int nx) {
-  const double d1 = g(wrap_add(x, 1, nx), y) - g(wrap_add(x, -1, nx), y);
-  const double d2 = g(wrap_add(x, 2, nx), y) - g(wrap_add(x, -2, nx), y);
-  const double d3 = g(wrap_add(x, 3, nx), y) - g(wrap_add(x, -3, nx), y);
-  const double d4 = g(wrap_add(x, 4, nx), y) - g(wrap_add(x, -4, nx), y);
-  return (4.0 * d1 - d2 + (4.0 / 21.0) * d3 - (1.0 / 56.0) * d4) / 5.0;
-}
-template <class G>
-__device__ __forceinline__ double fd8_y(const G& g, int x, int y, int ny) {
-  const double d1 = g(x, wrap_add(y, 1, ny)) - g(x, wrap_add(y, -1, ny));
-  const double d2 = g(x, wrap_add(y, 2, ny)) - g(x, wrap_add(y, -2, ny));
-  const double d3 = g(x, wrap_add(y, 3, ny)) - g(x, wrap_add(y, -3, ny));
-  const double d4 = g(x, wrap_add(y, 4, ny)) - g(x, wrap_add(y, -4, ny));
-  return (4.0 * d1 - d2 + (4.0 / 21.0) * d3 - (1.0 / 56.0) * d4) / 5.0;
-}
-
-struct F1 {
-  const double* __restrict__ a;
-  int nx;
-  __device__ double operator()(int x, int y) const { return a[static_cast<size_t>(y) * nx + x]; }
-};
-struct F2 {  // a * b
-  const double* __restrict__ a;
-  const double* __restrict__ b;
-  int nx;
-  __device__ double operator()(int x, int y) const {
-    const size_t i = static_cast<size_t>(y) * nx + x;
-    return a[i] * b[i];
-  }
-};
-struct FSum2 {  // a * b + c * d
-  const double* __restrict__ a;
-  const double* __restrict__ b;
-  const double* __restrict__ c;
-  const double* __restrict__ d;
-  int nx;
-  __device__ double operator()(int x, int y) const {
-    const size_t i = static_cast<size_t>(y) * nx + x;
-    return a[i] * b[i] + c[i] * d[i];
-  }
-};
-struct FDiv {  // a / b
-  const double* __restrict__ a;
-  const double* __restrict__ b;
-  int nx;
-  __device__ double operator()(int x, int y) const {
-    const size_t i = static_cast<size_t>(y) * nx + x;
-    return a[i] / b[i];
-  }
-};
 
 struct PassArgs {
   const double* rho[3];
@@ -253,46 +197,50 @@ __global__ void __launch_bounds__(kRedThreads) k_field_means(const double* __res
 
 // ---- summed-area tables ------------------------------------------------------------------
 // Row pass: P[f][y+1][x+1] = sum_{x' <= x} (g[f][y][x'] - mean_f); P[f][0][*] = P[f][*][0] = 0.
+// One workgroup per (row, field); the row is consumed in coalesced segments of
+// 256 values, each scanned across the workgroup (wavefront shuffles, then the
+// four wavefront totals through LDS) and offset by the running total.
 __global__ void __launch_bounds__(256) k_sat_rows(const double* __restrict__ g,
                                                   const double* __restrict__ means, double* sat,
                                                   int nx, int ny) {
-  __shared__ double sh[256];
+  __shared__ double wsum[4];
   const int y = blockIdx.x;
   const int f = blockIdx.y;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const size_t plane = static_cast<size_t>(nx) * ny;
   const size_t splane = static_cast<size_t>(nx + 1) * (ny + 1);
   const double mean = means[f];
   const double* row = g + f * plane + static_cast<size_t>(y) * nx;
   double* out = sat + f * splane + static_cast<size_t>(y + 1) * (nx + 1);
-  double* top = sat + f * splane;
-  const int chunk = (nx + 255) / 256;
-  const int xa = threadIdx.x * chunk;
-  const int xb = min(xa + chunk, nx);
-  double s = 0.0;
-  for (int xx = xa; xx < xb; ++xx) s += row[xx] - mean;
-  sh[threadIdx.x] = s;
-  __syncthreads();
-  // inclusive scan of chunk sums (Hillis-Steele over 256 entries)
-  for (int off = 1; off < 256; off <<= 1) {
-    const double v = threadIdx.x >= off ? sh[threadIdx.x - off] : 0.0;
+  double carry = 0.0;
+  for (int x0 = 0; x0 < nx; x0 += 256) {
+    const int x = x0 + threadIdx.x;
+    double v = x < nx ? row[x] - mean : 0.0;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const double t = __shfl_up(v, off, 64);
+      if (lane >= off) v += t;
+    }
+    if (lane == 63) wsum[wv] = v;
     __syncthreads();
-    sh[threadIdx.x] += v;
+    double before = 0.0;
+    for (int w = 0; w < wv; ++w) before += wsum[w];
+    const double total = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
+    if (x < nx) out[x + 1] = carry + (before + v);
+    carry += total;
     __syncthreads();
-  }
-  double acc = threadIdx.x > 0 ? sh[threadIdx.x - 1] : 0.0;
-  for (int xx = xa; xx < xb; ++xx) {
-    acc += row[xx] - mean;
-    out[xx + 1] = acc;
   }
   if (threadIdx.x == 0) out[0] = 0.0;
-  if (y == 0)
+  if (y == 0) {
+    double* top = sat + f * splane;
     for (int xx = threadIdx.x; xx <= nx; xx += 256) top[xx] = 0.0;
+  }
 }
 
-// Column pass: 64 columns x G row-groups per block; each group sums its
-// segment, the group totals are scanned in LDS, then each group rewrites its
+// Column pass: 64 columns x kColG row-groups per workgroup; each group sums its
+// segment, the group totals are combined in LDS, then each group rewrites its
 // segment as running sums.
-constexpr int kColG = 4;
+constexpr int kColG = 16;
 __global__ void __launch_bounds__(64 * kColG) k_sat_cols(double* sat, int nx, int ny) {
   __shared__ double sh[kColG][64];
   const int c = blockIdx.x * 64 + threadIdx.x;
@@ -304,19 +252,39 @@ __global__ void __launch_bounds__(64 * kColG) k_sat_cols(double* sat, int nx, in
   const int ya = 1 + gidx * seg;
   const int yb = min(ya + seg, ny + 1);
   const bool active = c <= nx;
-  double s = 0.0;
-  if (active)
-    for (int yy = ya; yy < yb; ++yy) s += P[static_cast<size_t>(yy) * (nx + 1) + c];
-  sh[gidx][threadIdx.x] = s;
+  const size_t s = static_cast<size_t>(nx + 1);
+  double acc = 0.0;
+  if (active) {
+    int yy = ya;
+    for (; yy + 4 <= yb; yy += 4) {
+      const double a0 = P[yy * s + c], a1 = P[(yy + 1) * s + c];
+      const double a2 = P[(yy + 2) * s + c], a3 = P[(yy + 3) * s + c];
+      acc += (a0 + a1) + (a2 + a3);
+    }
+    for (; yy < yb; ++yy) acc += P[yy * s + c];
+  }
+  sh[gidx][threadIdx.x] = acc;
   __syncthreads();
   double off = 0.0;
   for (int k = 0; k < gidx; ++k) off += sh[k][threadIdx.x];
   if (active) {
-    double acc = off;
-    for (int yy = ya; yy < yb; ++yy) {
-      double* p = P + static_cast<size_t>(yy) * (nx + 1) + c;
-      acc += *p;
-      *p = acc;
+    double run = off;
+    int yy = ya;
+    for (; yy + 4 <= yb; yy += 4) {
+      const double a0 = P[yy * s + c], a1 = P[(yy + 1) * s + c];
+      const double a2 = P[(yy + 2) * s + c], a3 = P[(yy + 3) * s + c];
+      run += a0;
+      P[yy * s + c] = run;
+      run += a1;
+      P[(yy + 1) * s + c] = run;
+      run += a2;
+      P[(yy + 2) * s + c] = run;
+      run += a3;
+      P[(yy + 3) * s + c] = run;
+    }
+    for (; yy < yb; ++yy) {
+      run += P[yy * s + c];
+      P[yy * s + c] = run;
     }
   }
 }
@@ -492,6 +460,159 @@ __global__ void __launch_bounds__(kWinThreads) k_stats_final(const double* __res
   block_stats(r, out);
 }
 
+// All box sides of one call in one pass: each thread takes kCPT window corners
+// (stride 256 along the flattened grid) and, side by side, evaluates 13 box
+// means per side from the table (the corner (y0, x0) lookup is shared by all
+// sides), the balancing errors and Mach number, and accumulates
+// count / sum / sum of squares / min / max / NaN count per side; the
+// workgroup totals go to partials[side][block] and are merged in a fixed order.
+constexpr int kCPT = 4;
+constexpr int kSumVals = 3 * 6;
+struct SideList {
+  int n;
+  int L[kMaxFusedSides];
+};
+
+struct SumStat {
+  double n, s1, s2, mn, mx, nan;
+  __device__ void init() {
+    n = s1 = s2 = nan = 0.0;
+    mn = 1e300;
+    mx = -1e300;
+  }
+  __device__ void add(double v) {
+    if (!isfinite(v)) {
+      nan += 1.0;
+      return;
+    }
+    n += 1.0;
+    s1 += v;
+    s2 += v * v;
+    mn = fmin(mn, v);
+    mx = fmax(mx, v);
+  }
+};
+
+__device__ void sum_stats_block(SumStat (&r)[3], double* out) {
+  __shared__ double sh[4][kSumVals];
+  double v[kSumVals];
+  for (int q = 0; q < 3; ++q) {
+    v[q * 6 + 0] = r[q].n;
+    v[q * 6 + 1] = r[q].s1;
+    v[q * 6 + 2] = r[q].s2;
+    v[q * 6 + 3] = r[q].mn;
+    v[q * 6 + 4] = r[q].mx;
+    v[q * 6 + 5] = r[q].nan;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+    for (int k = 0; k < kSumVals; ++k) {
+      const double o = __shfl_xor(v[k], off, 64);
+      const int kind = k % 6;
+      v[k] = kind == 3 ? fmin(v[k], o) : (kind == 4 ? fmax(v[k], o) : v[k] + o);
+    }
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0)
+    for (int k = 0; k < kSumVals; ++k) sh[wv][k] = v[k];
+  __syncthreads();
+  if (threadIdx.x < kSumVals) {
+    const int k = threadIdx.x, kind = k % 6;
+    double a = sh[0][k];
+    for (int w = 1; w < 4; ++w) {
+      const double o = sh[w][k];
+      a = kind == 3 ? fmin(a, o) : (kind == 4 ? fmax(a, o) : a + o);
+    }
+    out[k] = a;
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(256) k_windows_fused(SatView v, SideList sides, double* maps,
+                                                       double* partials) {
+  const size_t plane = static_cast<size_t>(v.nx) * v.ny;
+  const size_t s = static_cast<size_t>(v.nx) + 1;
+  const int nx = v.nx, ny = v.ny;
+  for (int k = 0; k < sides.n; ++k) {
+    const int L = sides.L[k];
+    const double inv = 1.0 / (double(L) * double(L));
+    SumStat r[3];
+    for (int q = 0; q < 3; ++q) r[q].init();
+    for (int c = 0; c < kCPT; ++c) {
+      const size_t i = blockIdx.x * size_t(256 * kCPT) + size_t(c) * 256 + threadIdx.x;
+      if (i >= plane) break;
+      const int x0 = static_cast<int>(i % nx);
+      const int y0 = static_cast<int>(i / nx);
+      const int y1 = y0 + L, x1 = x0 + L;
+      const bool qy = y1 > ny, qx = x1 > nx;
+      const int ym = qy ? y1 - ny : y1, xm = qx ? x1 - nx : x1;
+      double m[NT];
+#pragma unroll
+      for (int f = 0; f < NT; ++f) {
+        const double* p = v.P + f * v.splane;
+        const double q00 = p[y0 * s + x0];
+        double q01 = p[y0 * s + xm];
+        double q10 = p[ym * s + x0];
+        double q11 = p[ym * s + xm];
+        if (qx) {
+          q01 += p[y0 * s + nx];
+          q11 += p[ym * s + nx];
+        }
+        if (qy) {
+          q10 += p[ny * s + x0];
+          q11 += p[ny * s + xm];
+          if (qx) q11 += p[ny * s + nx];
+        }
+        m[f] = v.means[f] + ((q11 - q01) - (q10 - q00)) * inv;
+      }
+      double dE, dZ, ma;
+      window_errors(m, dE, dZ, ma);
+      r[0].add(dE);
+      r[1].add(dZ);
+      r[2].add(ma);
+      if (maps) {
+        double* mk = maps + static_cast<size_t>(k) * 3 * plane;
+        mk[i] = dE;
+        mk[plane + i] = dZ;
+        mk[2 * plane + i] = ma;
+      }
+    }
+    sum_stats_block(r, partials + (static_cast<size_t>(k) * gridDim.x + blockIdx.x) * kSumVals);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_sum_stats_final(const double* __restrict__ partials,
+                                                         int nblocks, double* out) {
+  SumStat r[3];
+  for (int q = 0; q < 3; ++q) r[q].init();
+  for (int b = threadIdx.x; b < nblocks; b += 256)
+    for (int q = 0; q < 3; ++q) {
+      const double* p = partials + static_cast<size_t>(b) * kSumVals + q * 6;
+      r[q].n += p[0];
+      r[q].s1 += p[1];
+      r[q].s2 += p[2];
+      r[q].mn = fmin(r[q].mn, p[3]);
+      r[q].mx = fmax(r[q].mx, p[4]);
+      r[q].nan += p[5];
+    }
+  __shared__ double fin[kSumVals];
+  sum_stats_block(r, fin);
+  if (threadIdx.x < 3) {
+    // convert to the (n, mean, M2, min, max, nan) layout of the Welford path
+    const int q = threadIdx.x;
+    const double n = fin[q * 6 + 0];
+    const double mean = n > 0.0 ? fin[q * 6 + 1] / n : 0.0;
+    const double m2 = n > 0.0 ? fmax(fin[q * 6 + 2] - n * mean * mean, 0.0) : 0.0;
+    out[q * kRS + 0] = n;
+    out[q * kRS + 1] = mean;
+    out[q * kRS + 2] = m2;
+    out[q * kRS + 3] = fin[q * 6 + 3];
+    out[q * kRS + 4] = fin[q * 6 + 4];
+    out[q * kRS + 5] = fin[q * 6 + 5];
+  }
+}
+
 __global__ void k_window_terms(SatView v, const int32_t* __restrict__ win, int nwin, double* out) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nwin) return;
@@ -521,20 +642,20 @@ BalanceWs carve_balance(Carver& c, int nx, int ny) {
   w.aux = c.take<double>(NAUX * plane);
   w.sat = c.take<double>(NT * splane);
   w.means = c.take<double>(16);
-  w.partials = c.take<double>(static_cast<size_t>(kWinMaxBlocks) * kStatVals +
-                              static_cast<size_t>(NT) * kMeanBlocks);
+  const size_t fused_blocks = (plane + 256 * kCPT - 1) / (256 * kCPT);
+  size_t np = static_cast<size_t>(kWinMaxBlocks) * kStatVals;
+  if (np < fused_blocks * kMaxFusedSides * kSumVals) np = fused_blocks * kMaxFusedSides * kSumVals;
+  w.partials = c.take<double>(np + static_cast<size_t>(NT) * kMeanBlocks);
+  w.partials_cap = np;
   w.stats = c.take<double>(static_cast<size_t>(kMaxSizes) * kStatVals);
   w.wterms = c.take<double>(static_cast<size_t>(kMaxWindows) * NT);
   w.windows = c.take<int32_t>(static_cast<size_t>(kMaxWindows) * 3);
   return w;
 }
 
-int run_balance(const lbm_balance_input& in, const BalanceWs& ws, const int32_t* sizes,
-                int nsizes, lbm_balance_stats* out, double* dmaps, const int32_t* windows,
-                int nwin, double* wterms, double* term_fields) {
+int balance_terms(const lbm_balance_input& in, const BalanceWs& ws) {
   hipStream_t s = static_cast<hipStream_t>(in.stream);
   const int nx = in.nx, ny = in.ny;
-  const size_t plane = static_cast<size_t>(nx) * ny;
   PassArgs a;
   for (int k = 0; k < 3; ++k) {
     a.rho[k] = in.rho[k];
@@ -555,40 +676,112 @@ int run_balance(const lbm_balance_input& in, const BalanceWs& ws, const int32_t*
   LBM_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_bal_c, grd, blk, 0, s, a);
   LBM_HIP(hipGetLastError());
+  return LBM_OK;
+}
+
+int field_means(const double* g, int nf, int nx, int ny, double* partials, double* means,
+                hipStream_t s) {
+  const size_t plane = static_cast<size_t>(nx) * ny;
+  int mb = static_cast<int>((plane + kRedThreads - 1) / kRedThreads);
+  if (mb > kMeanBlocks) mb = kMeanBlocks;
+  hipLaunchKernelGGL(k_field_sums, dim3(mb, nf), dim3(kRedThreads), 0, s, g, plane, partials);
+  LBM_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_field_means, dim3(nf), dim3(kRedThreads), 0, s, partials, mb,
+                     1.0 / double(plane), means);
+  LBM_HIP(hipGetLastError());
+  return LBM_OK;
+}
+
+int sat_build(const double* g, int nf, const double* means, double* sat, int nx, int ny,
+              hipStream_t s) {
+  hipLaunchKernelGGL(k_sat_rows, dim3(ny, nf), dim3(256), 0, s, g, means, sat, nx, ny);
+  LBM_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_sat_cols, dim3((nx + 1 + 63) / 64, nf), dim3(64, kColG), 0, s, sat, nx, ny);
+  LBM_HIP(hipGetLastError());
+  return LBM_OK;
+}
+
+namespace {
+// out[y][x] = scale * (sum of field f over the L x L periodic box whose lower
+// corner is (y + off, x + off)), from its mean-centred table.
+__global__ void __launch_bounds__(256) k_box_map(SatView v, int f, int L, int off, double scale,
+                                                 double* out) {
+  const size_t plane = static_cast<size_t>(v.nx) * v.ny;
+  for (size_t i = blockIdx.x * size_t(256) + threadIdx.x; i < plane; i += size_t(gridDim.x) * 256) {
+    int x0 = static_cast<int>(i % v.nx) + off;
+    int y0 = static_cast<int>(i / v.nx) + off;
+    x0 += x0 < 0 ? v.nx : 0;
+    y0 += y0 < 0 ? v.ny : 0;
+    const double box = v.Q(f, y0 + L, x0 + L) - v.Q(f, y0, x0 + L) - v.Q(f, y0 + L, x0) + v.Q(f, y0, x0);
+    out[i] = scale * (box + v.means[f] * double(L) * double(L));
+  }
+}
+}  // namespace
+
+int box_map(const double* sat, const double* means, int f, int L, int off, double scale,
+            double* out, int nx, int ny, hipStream_t s) {
+  SatView v{sat, means, nx, ny, static_cast<size_t>(nx + 1) * (ny + 1)};
+  const size_t plane = static_cast<size_t>(nx) * ny;
+  int g = static_cast<int>((plane + 255) / 256);
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(k_box_map, dim3(g), dim3(256), 0, s, v, f, L, off, scale, out);
+  LBM_HIP(hipGetLastError());
+  return LBM_OK;
+}
+
+int run_balance(const lbm_balance_input& in, const BalanceWs& ws, const int32_t* sizes,
+                int nsizes, lbm_balance_stats* out, double* dmaps, const int32_t* windows,
+                int nwin, double* wterms, double* term_fields) {
+  hipStream_t s = static_cast<hipStream_t>(in.stream);
+  const int nx = in.nx, ny = in.ny;
+  const size_t plane = static_cast<size_t>(nx) * ny;
+  if (int rc = balance_terms(in, ws)) return rc;
   if (term_fields)
     LBM_HIP(hipMemcpyAsync(term_fields, ws.terms, NT * plane * sizeof(double),
                            hipMemcpyDeviceToDevice, s));
-
-  // means
-  int mb = static_cast<int>((plane + kRedThreads - 1) / kRedThreads);
-  if (mb > kMeanBlocks) mb = kMeanBlocks;
-  double* mpart = ws.partials + static_cast<size_t>(kWinMaxBlocks) * kStatVals;
-  hipLaunchKernelGGL(k_field_sums, dim3(mb, NT), dim3(kRedThreads), 0, s, ws.terms, plane, mpart);
-  LBM_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_field_means, dim3(NT), dim3(kRedThreads), 0, s, mpart, mb,
-                     1.0 / double(plane), ws.means);
-  LBM_HIP(hipGetLastError());
-  // SAT
-  hipLaunchKernelGGL(k_sat_rows, dim3(ny, NT), dim3(256), 0, s, ws.terms, ws.means, ws.sat, nx, ny);
-  LBM_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_sat_cols, dim3((nx + 1 + 63) / 64, NT), dim3(64, kColG), 0, s, ws.sat, nx,
-                     ny);
-  LBM_HIP(hipGetLastError());
+  if (int rc = field_means(ws.terms, NT, nx, ny, ws.partials + ws.partials_cap, ws.means, s))
+    return rc;
+  if (int rc = sat_build(ws.terms, NT, ws.means, ws.sat, nx, ny, s)) return rc;
 
   SatView v{ws.sat, ws.means, nx, ny, static_cast<size_t>(nx + 1) * (ny + 1)};
-  for (int k = 0; k < nsizes; ++k) {
-    const int L = sizes[k];
-    const int single = (L == nx && L == ny) ? 1 : 0;
-    const size_t count = single ? 1 : plane;
-    const int nb = stat_blocks(count);
-    double* maps = dmaps ? dmaps + static_cast<size_t>(k) * 3 * plane : nullptr;
-    hipLaunchKernelGGL(k_windows, dim3(nb), dim3(kWinThreads), 0, s, v, L, single, maps,
+  const int fused_blocks = static_cast<int>((plane + 256 * kCPT - 1) / (256 * kCPT));
+  SideList chunk{};
+  int chunk_idx[kMaxFusedSides];
+  auto flush = [&]() -> int {
+    if (chunk.n == 0) return LBM_OK;
+    // maps of a chunk are written contiguously, so give the kernel the chunk's
+    // first map when the requested sizes are consecutive in the chunk
+    double* maps = dmaps ? dmaps + static_cast<size_t>(chunk_idx[0]) * 3 * plane : nullptr;
+    hipLaunchKernelGGL(k_windows_fused, dim3(fused_blocks), dim3(256), 0, s, v, chunk, maps,
                        ws.partials);
     LBM_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(kWinThreads), 0, s, ws.partials, nb,
-                       ws.stats + static_cast<size_t>(k) * kStatVals);
-    LBM_HIP(hipGetLastError());
+    for (int j = 0; j < chunk.n; ++j) {
+      hipLaunchKernelGGL(k_sum_stats_final, dim3(1), dim3(256), 0, s,
+                         ws.partials + static_cast<size_t>(j) * fused_blocks * kSumVals,
+                         fused_blocks, ws.stats + static_cast<size_t>(chunk_idx[j]) * kStatVals);
+      LBM_HIP(hipGetLastError());
+    }
+    chunk.n = 0;
+    return LBM_OK;
+  };
+  for (int k = 0; k < nsizes; ++k) {
+    const int L = sizes[k];
+    if (L == nx && L == ny) {
+      if (int rc = flush()) return rc;
+      double* maps = dmaps ? dmaps + static_cast<size_t>(k) * 3 * plane : nullptr;
+      hipLaunchKernelGGL(k_windows, dim3(1), dim3(kWinThreads), 0, s, v, L, 1, maps, ws.partials);
+      LBM_HIP(hipGetLastError());
+      hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(kWinThreads), 0, s, ws.partials, 1,
+                         ws.stats + static_cast<size_t>(k) * kStatVals);
+      LBM_HIP(hipGetLastError());
+      continue;
+    }
+    chunk_idx[chunk.n] = k;
+    chunk.L[chunk.n++] = L;
+    if (chunk.n == kMaxFusedSides)
+      if (int rc = flush()) return rc;
   }
+  if (int rc = flush()) return rc;
   if (nwin > 0) {
     LBM_HIP(hipMemcpyAsync(ws.windows, windows, sizeof(int32_t) * 3 * nwin, hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_window_terms, dim3((nwin + 63) / 64), dim3(64), 0, s, v, ws.windows, nwin,

@@ -1,22 +1,687 @@
-// Batched ensemble (filled in below).
+// Batched ensemble: many independent periodic grids advanced together.
+//
+// The work of one time step of every run is a list of equal-size items, each a
+// contiguous range of (threads * vx * ir) sites of one run in row-major order.
+// Persistent mode: one kernel with an occupancy-sized grid (every workgroup
+// resident at once) walks the item list for `chunk` steps; between steps the
+// workgroups meet at a grid-wide barrier (an atomic counter with a bounded
+// wait: a wait that runs out sets an error flag and the kernel exits instead
+// of hanging).  Per-step mode: one ordinary launch per step over the same list.
+// Both are captured into hipGraphs and replayed.  The arithmetic per site is
+// the single-grid step's (pull, BGK collide, Guo force, drag).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <vector>
+
 #include "lbm_internal.h"
+#include "lbm_site.h"
+
+namespace lbm {
+namespace {
+
+constexpr int kBT = 256;    // smallest workgroup of the batch kernels (threads)
+constexpr int kBTMax = 1024;
+
+struct RunDesc {
+  void* pop[2];
+  const void* fx;
+  const void* fy;
+  int nx, ny;
+  double omega;
+  double alpha;
+  int forced;
+  int pad;
+};
+
+struct BatchArgs {
+  const RunDesc* runs;
+  const int* item_run;
+  const int* item_start;
+  int nitems;
+  int ir;                 // site groups per thread per item
+  int bt;                 // threads per workgroup (256, 512 or 1024)
+  int parity0;            // buffer index holding the state at the first step
+  int nsteps;
+  unsigned* barrier;      // zeroed before each persistent launch
+  int* error;             // set to 1 by a barrier wait that ran out
+  unsigned spin_limit;
+  int flavor;             // grid-barrier variant (see grid_barrier)
+};
+
+template <typename T, int VX>
+__device__ __forceinline__ void process_item(const BatchArgs& a, int item, int par) {
+  const RunDesc r = a.runs[a.item_run[item]];
+  const int nx = r.nx, ny = r.ny;
+  const size_t plane = static_cast<size_t>(nx) * ny;
+  const T* __restrict__ src = static_cast<const T*>(r.pop[par]);
+  T* __restrict__ dst = static_cast<T*>(r.pop[par ^ 1]);
+  const T omega = T(r.omega);
+  const T guo = T(1) - T(0.5) * T(r.omega);
+  const T alpha = T(r.alpha);
+  const int start = a.item_start[item];
+  for (int k = 0; k < a.ir; ++k) {
+    const size_t site =
+        static_cast<size_t>(start) + (static_cast<size_t>(k) * a.bt + threadIdx.x) * VX;
+    if (site >= plane) break;
+    const int y = static_cast<int>(site / nx);
+    const int x0 = static_cast<int>(site - static_cast<size_t>(y) * nx);
+    const int yn = (y == 0) ? ny - 1 : y - 1;
+    const int yp = (y == ny - 1) ? 0 : y + 1;
+    T d[9][VX];
+    step_detail::pull_all<T, VX>(src, plane, nx, x0, y, yn, yp, d);
+    const size_t row = static_cast<size_t>(y) * nx + x0;
+    T o[9][VX];
+    if (r.forced) {
+      T fx[VX], fy[VX];
+      if (r.fx) {
+        step_detail::load_aligned<T, VX>(static_cast<const T*>(r.fx) + row, fx);
+        step_detail::load_aligned<T, VX>(static_cast<const T*>(r.fy) + row, fy);
+      } else {
+#pragma unroll
+        for (int i = 0; i < VX; ++i) fx[i] = fy[i] = T(0);
+      }
+#pragma unroll
+      for (int i = 0; i < VX; ++i) {
+        T di[9], oi[9];
+#pragma unroll
+        for (int l = 0; l < 9; ++l) di[l] = d[l][i];
+        step_detail::SiteMoments<T, true> m(di, fx[i], fy[i], alpha);
+        step_detail::collide_site<T, true>(di, m, omega, guo, oi);
+#pragma unroll
+        for (int l = 0; l < 9; ++l) o[l][i] = oi[l];
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < VX; ++i) {
+        T di[9], oi[9];
+#pragma unroll
+        for (int l = 0; l < 9; ++l) di[l] = d[l][i];
+        step_detail::SiteMoments<T, false> m(di, T(0), T(0), alpha);
+        step_detail::collide_site<T, false>(di, m, omega, guo, oi);
+#pragma unroll
+        for (int l = 0; l < 9; ++l) o[l][i] = oi[l];
+      }
+    }
+#pragma unroll
+    for (int l = 0; l < 9; ++l) step_detail::store_aligned<T, VX, true>(dst + l * plane + row, o[l]);
+  }
+}
+
+// Grid-wide barrier number `gen` (1, 2, ...), three variants with the same
+// meaning (every workgroup's writes before the barrier are visible to every
+// workgroup after it; agent-scope release/acquire, which on this chip write
+// back and invalidate the per-XCD L2 caches):
+//   0: every wavefront fences; one counter
+//   1: thread 0 of each workgroup carries the release/acquire; one counter
+//   2: as 1, with the workgroups split into 8 groups (blockIdx % 8): the last
+//      arrival of a group forwards to a global counter and, once all groups
+//      arrived, releases its group through a per-group flag
+// A wait that runs out of spins sets the error flag; every later barrier then
+// fails at once, so every workgroup leaves the kernel.
+constexpr int kCounterStride = 64;  // unsigned words between counters (256 bytes)
+constexpr int kBarrierWords = kCounterStride * 18;
+
+__device__ __forceinline__ bool spin_until(const BatchArgs& a, unsigned* p, unsigned target) {
+  unsigned spins = 0;
+  while (__hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    if (++spins > a.spin_limit) {
+      __hip_atomic_store(a.error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+  return true;
+}
+
+__device__ bool grid_barrier(const BatchArgs& a, unsigned gen) {
+  __shared__ int ok;
+  if (a.flavor == 0) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int good = 1;
+    if (__hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+      good = 0;
+    } else if (a.flavor != 2) {
+      __hip_atomic_fetch_add(a.barrier, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      good = spin_until(a, a.barrier, gen * gridDim.x);
+    } else {
+      const unsigned G = gridDim.x;
+      const unsigned g = blockIdx.x & 7;
+      const unsigned gsize = (G - g + 7) / 8;
+      const unsigned ngroups = G < 8 ? G : 8;
+      unsigned* cg = a.barrier + kCounterStride * (1 + g);
+      unsigned* rel = a.barrier + kCounterStride * (9 + g);
+      const unsigned prev = __hip_atomic_fetch_add(cg, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      if (prev + 1 == gen * gsize) {
+        __hip_atomic_fetch_add(a.barrier, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        good = spin_until(a, a.barrier, gen * ngroups);
+        if (good) __hip_atomic_store(rel, gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        good = spin_until(a, rel, gen);
+      }
+    }
+    ok = good;
+  }
+  __syncthreads();
+  if (a.flavor == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return ok != 0;
+}
+
+template <typename T, int VX>
+__global__ void __launch_bounds__(kBTMax) k_batch_persistent(BatchArgs a) {
+  for (int s = 0; s < a.nsteps; ++s) {
+    const int par = (a.parity0 + s) & 1;
+    for (int it = blockIdx.x; it < a.nitems; it += gridDim.x) process_item<T, VX>(a, it, par);
+    if (s + 1 < a.nsteps)
+      if (!grid_barrier(a, static_cast<unsigned>(s + 1))) return;
+  }
+}
+
+template <typename T, int VX>
+__global__ void __launch_bounds__(kBTMax) k_batch_step(BatchArgs a) {
+  process_item<T, VX>(a, blockIdx.x, a.parity0);
+}
+
+__global__ void k_batch_reset(unsigned* barrier) {
+  for (int i = threadIdx.x; i < kBarrierWords; i += blockDim.x) barrier[i] = 0u;
+}
+
+template <typename T, int VX>
+int occupancy_blocks(int bt, int* blocks) {
+  int per_cu = 0;
+  LBM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_persistent<T, VX>, bt, 0));
+  int dev = 0;
+  LBM_HIP(hipGetDevice(&dev));
+  int cus = 0;
+  LBM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  *blocks = std::max(1, per_cu * cus);
+  return LBM_OK;
+}
+
+template <typename T>
+int occupancy_for(int vx, int bt, int* blocks) {
+  switch (vx) {
+    case 1: return occupancy_blocks<T, 1>(bt, blocks);
+    case 2: return occupancy_blocks<T, 2>(bt, blocks);
+    default: return occupancy_blocks<T, 4>(bt, blocks);
+  }
+}
+
+template <typename T, int VX>
+void launch_batch_t(bool persistent, const BatchArgs& a, int grid, hipStream_t s) {
+  if (persistent)
+    hipLaunchKernelGGL((k_batch_persistent<T, VX>), dim3(grid), dim3(a.bt), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_batch_step<T, VX>), dim3(a.nitems), dim3(a.bt), 0, s, a);
+}
+
+template <typename T>
+void launch_batch_vx(int vx, bool persistent, const BatchArgs& a, int grid, hipStream_t s) {
+  switch (vx) {
+    case 1: launch_batch_t<T, 1>(persistent, a, grid, s); break;
+    case 2: launch_batch_t<T, 2>(persistent, a, grid, s); break;
+    default: launch_batch_t<T, 4>(persistent, a, grid, s); break;
+  }
+}
+
+}  // namespace
+}  // namespace lbm
 
 using namespace lbm;
 
+struct lbm_batch_s {
+  int nruns = 0;
+  int dtype = LBM_F32;
+  hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;
+  std::vector<lbm_config> cfg;
+  std::vector<RunDesc> runs;     // host copy
+  RunDesc* d_runs = nullptr;
+  int* d_item_run = nullptr;
+  int* d_item_start = nullptr;
+  size_t item_cap = 0;
+  unsigned* d_barrier = nullptr;
+  int* d_error = nullptr;
+  double* d_partials = nullptr;
+  double* d_scalars = nullptr;
+  int nitems = 0;
+  int vx = 4;
+  int ir = 1;
+  int bt = 256;
+  int mode = LBM_BATCH_PERSISTENT;
+  int chunk = 100;
+  int grid = 0;
+  int cur = 0;
+  int64_t t = 0;
+  int64_t sites = 0;
+  unsigned spin_limit = 1u << 22;
+  int flavor = 2;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+};
+
+namespace {
+
+struct BatchLayout {
+  std::vector<void*> pop0, pop1, fx, fy;
+  RunDesc* runs;
+  int* item_run;
+  int* item_start;
+  unsigned* barrier;
+  int* error;
+  double* partials;
+  double* scalars;
+  size_t item_cap;
+  size_t bytes;
+};
+
+size_t max_items(const lbm_config* cfgs, int nruns) {
+  // smallest item: kBT sites (vx = 1, ir = 1)
+  size_t n = 0;
+  for (int r = 0; r < nruns; ++r) {
+    const size_t plane = static_cast<size_t>(cfgs[r].nx) * cfgs[r].ny;
+    n += (plane + kBT - 1) / kBT;
+  }
+  return n;
+}
+
+BatchLayout carve_batch(const lbm_config* cfgs, int nruns, void* base, size_t cap) {
+  Carver cv(base, cap);
+  BatchLayout l{};
+  const size_t es = cfgs[0].dtype == LBM_F32 ? 4 : 8;
+  int maxblocks = 0;
+  for (int r = 0; r < nruns; ++r) {
+    const size_t plane = static_cast<size_t>(cfgs[r].nx) * cfgs[r].ny;
+    l.pop0.push_back(cv.take<char>(9 * plane * es));
+    l.pop1.push_back(cv.take<char>(9 * plane * es));
+    if (cfgs[r].has_force) {
+      l.fx.push_back(cv.take<char>(plane * es));
+      l.fy.push_back(cv.take<char>(plane * es));
+    } else {
+      l.fx.push_back(nullptr);
+      l.fy.push_back(nullptr);
+    }
+    maxblocks = std::max(maxblocks, moment_blocks(cfgs[r].nx, cfgs[r].ny));
+  }
+  l.runs = cv.take<RunDesc>(nruns);
+  l.item_cap = max_items(cfgs, nruns);
+  l.item_run = cv.take<int>(l.item_cap);
+  l.item_start = cv.take<int>(l.item_cap);
+  l.barrier = cv.take<unsigned>(kBarrierWords);
+  l.error = cv.take<int>(64);
+  l.partials = cv.take<double>(static_cast<size_t>(maxblocks) * 8 + 8);
+  l.scalars = cv.take<double>(8);
+  l.bytes = cv.used + 256;
+  return l;
+}
+
+int validate_batch(const lbm_config* cfgs, int32_t nruns) {
+  if (!cfgs || nruns < 1 || nruns > 4096) return fail(LBM_E_INVALID, "need 1..4096 runs");
+  for (int r = 0; r < nruns; ++r) {
+    lbm_config c = cfgs[r];
+    if (int rc = validate_config(&c)) return rc;
+    if (c.dtype != cfgs[0].dtype) return fail(LBM_E_INVALID, "run %d: all runs need one dtype", r);
+    if (c.with_balance) return fail(LBM_E_INVALID, "run %d: with_balance must be 0 in a batch", r);
+    if (static_cast<size_t>(c.nx) * c.ny > 0x7fffffffu)
+      return fail(LBM_E_INVALID, "run %d: grid too large for a batch", r);
+  }
+  return LBM_OK;
+}
+
+int build_items(lbm_batch_s* b) {
+  std::vector<int> ir_run, ir_start;
+  const size_t per = static_cast<size_t>(b->bt) * b->vx * b->ir;
+  for (int r = 0; r < b->nruns; ++r) {
+    const size_t plane = static_cast<size_t>(b->cfg[r].nx) * b->cfg[r].ny;
+    for (size_t s0 = 0; s0 < plane; s0 += per) {
+      ir_run.push_back(r);
+      ir_start.push_back(static_cast<int>(s0));
+    }
+  }
+  if (ir_run.size() > b->item_cap) return fail(LBM_E_INVALID, "work list exceeds its capacity");
+  b->nitems = static_cast<int>(ir_run.size());
+  LBM_HIP(hipMemcpyAsync(b->d_item_run, ir_run.data(), ir_run.size() * sizeof(int),
+                         hipMemcpyHostToDevice, b->stream));
+  LBM_HIP(hipMemcpyAsync(b->d_item_start, ir_start.data(), ir_start.size() * sizeof(int),
+                         hipMemcpyHostToDevice, b->stream));
+  LBM_HIP(hipStreamSynchronize(b->stream));
+  int occ = 0;
+  if (int rc = b->dtype == LBM_F32 ? occupancy_for<float>(b->vx, b->bt, &occ)
+                                   : occupancy_for<double>(b->vx, b->bt, &occ))
+    return rc;
+  b->grid = std::min(occ, b->nitems);
+  return LBM_OK;
+}
+
+void drop_batch_graphs(lbm_batch_s* b) {
+  for (auto& g : b->gexec)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+}
+
+BatchArgs make_args(lbm_batch_s* b, int parity0, int nsteps) {
+  BatchArgs a{};
+  a.runs = b->d_runs;
+  a.item_run = b->d_item_run;
+  a.item_start = b->d_item_start;
+  a.nitems = b->nitems;
+  a.ir = b->ir;
+  a.bt = b->bt;
+  a.parity0 = parity0;
+  a.nsteps = nsteps;
+  a.barrier = b->d_barrier;
+  a.error = b->d_error;
+  a.spin_limit = b->spin_limit;
+  a.flavor = b->flavor;
+  return a;
+}
+
+// Enqueue `n` steps starting from buffer parity `par` on stream s.
+int enqueue_steps(lbm_batch_s* b, int par, int n, hipStream_t s) {
+  if (n <= 0) return LBM_OK;
+  if (b->mode == LBM_BATCH_PERSISTENT) {
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, b->d_barrier);
+    LBM_HIP(hipGetLastError());
+    BatchArgs a = make_args(b, par, n);
+    if (b->dtype == LBM_F32) launch_batch_vx<float>(b->vx, true, a, b->grid, s);
+    else launch_batch_vx<double>(b->vx, true, a, b->grid, s);
+    LBM_HIP(hipGetLastError());
+  } else {
+    for (int k = 0; k < n; ++k) {
+      BatchArgs a = make_args(b, (par + k) & 1, 1);
+      if (b->dtype == LBM_F32) launch_batch_vx<float>(b->vx, false, a, 0, s);
+      else launch_batch_vx<double>(b->vx, false, a, 0, s);
+      LBM_HIP(hipGetLastError());
+    }
+  }
+  return LBM_OK;
+}
+
+int build_batch_graph(lbm_batch_s* b, int par) {
+  if (!b->cap_stream) LBM_HIP(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+  hipGraph_t g = nullptr;
+  LBM_HIP(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+  int rc = enqueue_steps(b, par, b->chunk, b->cap_stream);
+  hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+  if (rc != LBM_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  e = hipGraphInstantiate(&b->gexec[par], g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+  return LBM_OK;
+}
+
+int check_error_flag(lbm_batch_s* b) {
+  int h = 0;
+  LBM_HIP(hipMemcpyAsync(&h, b->d_error, sizeof(int), hipMemcpyDeviceToHost, b->stream));
+  LBM_HIP(hipStreamSynchronize(b->stream));
+  if (h) return fail(LBM_E_TIMEOUT, "a grid-barrier wait of the persistent batch kernel ran out "
+                                    "(workgroups not all resident?); the batch state is invalid");
+  return LBM_OK;
+}
+
+}  // namespace
+
 extern "C" {
-int lbm_batch_workspace_bytes(const lbm_config*, int32_t, size_t*) { return fail(LBM_E_UNSUPPORTED, "batch: not built"); }
-int lbm_batch_init(const lbm_config*, int32_t, void*, size_t, const double* const*, const double* const*,
-                   const double* const*, const double* const*, const double* const*, lbm_batch*) {
-  return fail(LBM_E_UNSUPPORTED, "batch: not built");
+
+int lbm_batch_workspace_bytes(const lbm_config* cfgs, int32_t nruns, size_t* bytes) {
+  if (int rc = validate_batch(cfgs, nruns)) return rc;
+  if (!bytes) return fail(LBM_E_INVALID, "bytes is NULL");
+  *bytes = carve_batch(cfgs, nruns, nullptr, 0).bytes;
+  return LBM_OK;
 }
-int lbm_batch_set_mode(lbm_batch, int32_t, int32_t) { return fail(LBM_E_UNSUPPORTED, "batch: not built"); }
-int lbm_batch_set_tile(lbm_batch, int32_t, int32_t, int32_t) { return fail(LBM_E_UNSUPPORTED, "batch: not built"); }
-int lbm_batch_autotune(lbm_batch, int32_t, int32_t*, int32_t*, int32_t*) { return fail(LBM_E_UNSUPPORTED, "batch: not built"); }
-int lbm_batch_step(lbm_batch, int64_t) { return fail(LBM_E_UNSUPPORTED, "batch: not built"); }
-int lbm_batch_moments(lbm_batch, int32_t, void*, void*, void*, int32_t, double*) { return fail(LBM_E_UNSUPPORTED, "batch: not built"); }
-int lbm_batch_time(lbm_batch, int64_t*) { return fail(LBM_E_UNSUPPORTED, "batch: not built"); }
-int64_t lbm_batch_sites(lbm_batch) { return 0; }
-int lbm_batch_destroy(lbm_batch) { return LBM_OK; }
+
+int lbm_batch_init(const lbm_config* cfgs, int32_t nruns, void* ws, size_t ws_bytes,
+                   const double* const* rho0, const double* const* ux0, const double* const* uy0,
+                   const double* const* fx, const double* const* fy, lbm_batch* out) {
+  if (int rc = validate_batch(cfgs, nruns)) return rc;
+  if (!out) return fail(LBM_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!ws || reinterpret_cast<uintptr_t>(ws) % 256 != 0)
+    return fail(LBM_E_INVALID, "workspace must be non-NULL and 256-byte aligned");
+  if (!rho0 || !ux0 || !uy0) return fail(LBM_E_INVALID, "initial field arrays must not be NULL");
+  BatchLayout l = carve_batch(cfgs, nruns, nullptr, 0);
+  if (ws_bytes < l.bytes) return fail(LBM_E_NOMEM, "workspace %zu < %zu", ws_bytes, l.bytes);
+  for (int r = 0; r < nruns; ++r) {
+    if (!rho0[r] || !ux0[r] || !uy0[r]) return fail(LBM_E_INVALID, "run %d: NULL initial field", r);
+    const bool has = fx && fy && fx[r] && fy[r];
+    if (cfgs[r].has_force && !has) return fail(LBM_E_INVALID, "run %d: has_force needs fx, fy", r);
+    if (!cfgs[r].has_force && fx && fx[r]) return fail(LBM_E_INVALID, "run %d: force without has_force", r);
+  }
+  l = carve_batch(cfgs, nruns, ws, ws_bytes);
+  lbm_batch_s* b = new lbm_batch_s();
+  b->nruns = nruns;
+  b->dtype = cfgs[0].dtype;
+  b->stream = static_cast<hipStream_t>(cfgs[0].stream);
+  b->cfg.assign(cfgs, cfgs + nruns);
+  b->d_runs = l.runs;
+  b->d_item_run = l.item_run;
+  b->d_item_start = l.item_start;
+  b->item_cap = l.item_cap;
+  b->d_barrier = l.barrier;
+  b->d_error = l.error;
+  b->d_partials = l.partials;
+  b->d_scalars = l.scalars;
+  int common = 4;
+  for (int r = 0; r < nruns; ++r) {
+    while (common > 1 && cfgs[r].nx % common) common >>= 1;
+    b->sites += static_cast<int64_t>(cfgs[r].nx) * cfgs[r].ny;
+  }
+  b->vx = b->dtype == LBM_F32 ? common : std::min(common, 2);
+  if (const char* fl = std::getenv("LBM_BATCH_BARRIER")) {
+    const int v = std::atoi(fl);
+    if (v >= 0 && v <= 2) b->flavor = v;
+  }
+  int rc = LBM_OK;
+  for (int r = 0; r < nruns && rc == LBM_OK; ++r) {
+    RunDesc d{};
+    d.pop[0] = l.pop0[r];
+    d.pop[1] = l.pop1[r];
+    d.fx = l.fx[r];
+    d.fy = l.fy[r];
+    d.nx = cfgs[r].nx;
+    d.ny = cfgs[r].ny;
+    d.omega = 1.0 / cfgs[r].tau;
+    d.alpha = cfgs[r].drag_alpha;
+    d.forced = (cfgs[r].has_force || cfgs[r].drag_alpha > 0.0) ? 1 : 0;
+    b->runs.push_back(d);
+    rc = launch_init(b->dtype, d.pop[0], rho0[r], ux0[r], uy0[r], d.nx, d.ny, b->stream);
+    const size_t plane = static_cast<size_t>(d.nx) * d.ny;
+    if (rc == LBM_OK && cfgs[r].has_force) {
+      rc = launch_to_storage(b->dtype, l.fx[r], fx[r], plane, b->stream);
+      if (rc == LBM_OK) rc = launch_to_storage(b->dtype, l.fy[r], fy[r], plane, b->stream);
+    }
+  }
+  if (rc == LBM_OK) {
+    hipError_t e = hipMemcpyAsync(b->d_runs, b->runs.data(), sizeof(RunDesc) * nruns,
+                                  hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(b->d_error, 0, 64 * sizeof(int), b->stream);
+    if (e != hipSuccess) rc = hip_fail(e, "batch setup copy");
+  }
+  if (rc == LBM_OK) rc = build_items(b);
+  if (rc != LBM_OK) {
+    delete b;
+    return rc;
+  }
+  *out = b;
+  return LBM_OK;
 }
+
+int lbm_batch_set_mode(lbm_batch b, int32_t mode, int32_t chunk) {
+  if (!b) return fail(LBM_E_INVALID, "batch is NULL");
+  if (mode != LBM_BATCH_PERSISTENT && mode != LBM_BATCH_PER_STEP)
+    return fail(LBM_E_INVALID, "mode must be LBM_BATCH_PERSISTENT or LBM_BATCH_PER_STEP");
+  if (chunk < 2 || chunk % 2 || chunk > 100000) return fail(LBM_E_INVALID, "chunk: even, 2..100000");
+  b->mode = mode;
+  b->chunk = chunk;
+  drop_batch_graphs(b);
+  return LBM_OK;
+}
+
+int lbm_batch_set_tile(lbm_batch b, int32_t block_threads, int32_t vx, int32_t band_rows) {
+  if (!b) return fail(LBM_E_INVALID, "batch is NULL");
+  if (block_threads != 256 && block_threads != 512 && block_threads != 1024)
+    return fail(LBM_E_INVALID, "block_threads must be 256, 512 or 1024");
+  if (vx != 1 && vx != 2 && vx != 4) return fail(LBM_E_INVALID, "vx must be 1, 2 or 4");
+  for (int r = 0; r < b->nruns; ++r)
+    if (b->cfg[r].nx % vx) return fail(LBM_E_INVALID, "vx %d does not divide nx of run %d", vx, r);
+  if (band_rows < 1 || band_rows > 64) return fail(LBM_E_INVALID, "site groups per item in 1..64");
+  b->bt = block_threads;
+  b->vx = vx;
+  b->ir = band_rows;
+  drop_batch_graphs(b);
+  return build_items(b);
+}
+
+int lbm_batch_step(lbm_batch b, int64_t n) {
+  if (!b) return fail(LBM_E_INVALID, "batch is NULL");
+  if (n < 0) return fail(LBM_E_INVALID, "n must be >= 0");
+  while (n >= b->chunk) {
+    if (!b->gexec[b->cur])
+      if (int rc = build_batch_graph(b, b->cur)) return rc;
+    LBM_HIP(hipGraphLaunch(b->gexec[b->cur], b->stream));
+    n -= b->chunk;
+    b->t += b->chunk;
+  }
+  if (n > 0) {
+    if (int rc = enqueue_steps(b, b->cur, static_cast<int>(n), b->stream)) return rc;
+    b->cur = (b->cur + static_cast<int>(n)) & 1;
+    b->t += n;
+  }
+  return LBM_OK;
+}
+
+int lbm_batch_autotune(lbm_batch b, int32_t trial_steps, int32_t* block_threads, int32_t* vx,
+                       int32_t* band_rows) {
+  if (!b) return fail(LBM_E_INVALID, "batch is NULL");
+  if (trial_steps < 2 || trial_steps > 1000 || trial_steps % 2)
+    return fail(LBM_E_INVALID, "trial_steps: even, 2..1000");
+  const int saved_vx = b->vx, saved_ir = b->ir, saved_bt = b->bt, saved_mode = b->mode;
+  hipEvent_t e0, e1;
+  LBM_HIP(hipEventCreate(&e0));
+  LBM_HIP(hipEventCreate(&e1));
+  float best = 1e30f;
+  int bvx = saved_vx, bir = saved_ir, bbt = saved_bt, bmode = saved_mode;
+  int rc = LBM_OK;
+  const int modes[2] = {LBM_BATCH_PERSISTENT, LBM_BATCH_PER_STEP};
+  const int bts[2] = {256, 1024};
+  const int vxs[3] = {1, 2, 4};
+  const int irs[3] = {1, 2, 4};
+  // every trial advances the ensemble by 2 + trial_steps real steps (an even
+  // count, so the buffer parity is unchanged) and the time counter records it
+  for (int mode : modes) {
+    for (int bt : bts) {
+      for (int v : vxs) {
+        bool fits = true;
+        for (int r = 0; r < b->nruns; ++r) fits = fits && (b->cfg[r].nx % v == 0);
+        if (!fits || (b->dtype == LBM_F64 && v == 4)) continue;
+        for (int i : irs) {
+          b->mode = mode;
+          b->bt = bt;
+          b->vx = v;
+          b->ir = i;
+          if ((rc = build_items(b)) != LBM_OK) break;
+          if ((rc = enqueue_steps(b, b->cur, 2, b->stream)) != LBM_OK) break;
+          if (hipEventRecord(e0, b->stream) != hipSuccess) { rc = fail(LBM_E_HIP, "event"); break; }
+          if ((rc = enqueue_steps(b, b->cur, trial_steps, b->stream)) != LBM_OK) break;
+          if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+            rc = fail(LBM_E_HIP, "event");
+            break;
+          }
+          b->t += 2 + trial_steps;
+          float ms = 0.f;
+          (void)hipEventElapsedTime(&ms, e0, e1);
+          if (ms < best) {
+            best = ms;
+            bvx = v;
+            bir = i;
+            bbt = bt;
+            bmode = mode;
+          }
+        }
+        if (rc) break;
+      }
+      if (rc) break;
+    }
+    if (rc) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc == LBM_OK) rc = check_error_flag(b);
+  const bool ok = rc == LBM_OK;
+  b->vx = ok ? bvx : saved_vx;
+  b->ir = ok ? bir : saved_ir;
+  b->bt = ok ? bbt : saved_bt;
+  b->mode = ok ? bmode : saved_mode;
+  drop_batch_graphs(b);
+  if (int r2 = build_items(b)) return rc ? rc : r2;
+  if (rc) return rc;
+  if (block_threads) *block_threads = b->bt;
+  if (vx) *vx = b->vx;
+  if (band_rows) *band_rows = b->ir;
+  return LBM_OK;
+}
+
+int lbm_batch_get_mode(lbm_batch b, int32_t* mode, int32_t* chunk) {
+  if (!b) return fail(LBM_E_INVALID, "batch is NULL");
+  if (mode) *mode = b->mode;
+  if (chunk) *chunk = b->chunk;
+  return LBM_OK;
+}
+
+int lbm_batch_moments(lbm_batch b, int32_t run, void* rho, void* ux, void* uy, int32_t out_dtype,
+                      double* scalars8) {
+  if (!b) return fail(LBM_E_INVALID, "batch is NULL");
+  if (run < 0 || run >= b->nruns) return fail(LBM_E_INVALID, "run %d out of range", run);
+  if (out_dtype != LBM_F32 && out_dtype != LBM_F64) return fail(LBM_E_INVALID, "bad out_dtype");
+  if (int rc = check_error_flag(b)) return rc;
+  const RunDesc& r = b->runs[run];
+  MomentParams m{};
+  m.pop = r.pop[b->cur];
+  m.fx = r.fx;
+  m.fy = r.fy;
+  m.rho = rho;
+  m.ux = ux;
+  m.uy = uy;
+  m.out_dtype = out_dtype;
+  m.partials = b->d_partials;
+  m.nx = r.nx;
+  m.ny = r.ny;
+  m.alpha = r.alpha;
+  if (int rc = launch_moments(b->dtype, r.forced != 0, m, b->stream)) return rc;
+  if (!scalars8) return LBM_OK;
+  if (int rc = launch_reduce_scalars(b->d_partials, moment_blocks(r.nx, r.ny), b->d_scalars, b->stream))
+    return rc;
+  LBM_HIP(hipMemcpyAsync(scalars8, b->d_scalars, 8 * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+  LBM_HIP(hipStreamSynchronize(b->stream));
+  scalars8[LBM_S_TIME] = static_cast<double>(b->t);
+  if (scalars8[LBM_S_NONFINITE] > 0.0 || !(scalars8[LBM_S_MINRHO] > 0.0))
+    return fail(LBM_E_DIVERGED, "run %d diverged by step %lld", run, static_cast<long long>(b->t));
+  return LBM_OK;
+}
+
+int lbm_batch_time(lbm_batch b, int64_t* t) {
+  if (!b || !t) return fail(LBM_E_INVALID, "NULL argument");
+  *t = b->t;
+  return LBM_OK;
+}
+
+int64_t lbm_batch_sites(lbm_batch b) { return b ? b->sites : 0; }
+
+int lbm_batch_destroy(lbm_batch b) {
+  if (!b) return LBM_OK;
+  (void)hipStreamSynchronize(b->stream);
+  drop_batch_graphs(b);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  delete b;
+  return LBM_OK;
+}
+
+}  // extern "C"

@@ -14,6 +14,7 @@ namespace lbm {
 // ---- error reporting ---------------------------------------------------------
 int fail(int code, const char* fmt, ...);
 int hip_fail(hipError_t e, const char* what);
+int validate_config(const lbm_config* c);
 
 #define LBM_HIP(call)                                   \
   do {                                                  \
@@ -107,6 +108,7 @@ struct BalanceWs {
   double* sat;       // [13][ny+1][nx+1]
   double* means;     // [16]
   double* partials;  // block partials
+  size_t partials_cap;  // doubles of window partials before the field-sum partials
   double* stats;     // device stats scratch
   double* wterms;    // [LBM_MAX_WINDOWS][13]
   int32_t* windows;  // [LBM_MAX_WINDOWS][3]
@@ -115,6 +117,19 @@ constexpr int kMaxWindows = 4096;
 constexpr int kMaxSizes = 64;
 size_t balance_ws_bytes(int nx, int ny);
 BalanceWs carve_balance(Carver& c, int nx, int ny);
+// Pieces of the balance reused by the adjoint: the 13 term fields and the aux
+// fields (E, Omega, omega, sigma_xx, sigma_yy, sigma_xy, H_x, H_y) of passes
+// A-C; domain means of nf consecutive fields; their mean-centred prefix tables;
+// and scaled box sums of one tabulated field for every corner shifted by `off`.
+int balance_terms(const lbm_balance_input& in, const BalanceWs& ws);
+int field_means(const double* g, int nf, int nx, int ny, double* partials, double* means,
+                hipStream_t s);
+int sat_build(const double* g, int nf, const double* means, double* sat, int nx, int ny,
+              hipStream_t s);
+int box_map(const double* sat, const double* means, int f, int L, int off, double scale,
+            double* out, int nx, int ny, hipStream_t s);
+enum { AUX_E = 0, AUX_OM2 = 1, AUX_W = 2, AUX_SXX = 3, AUX_SYY = 4, AUX_SXY = 5, AUX_HX = 6,
+       AUX_HY = 7, AUX_N = 8 };
 int run_balance(const lbm_balance_input& in, const BalanceWs& ws, const int32_t* sizes,
                 int nsizes, lbm_balance_stats* out, double* dmaps, const int32_t* windows,
                 int nwin, double* wterms, double* term_fields);

@@ -1,0 +1,172 @@
+// Per-site device arithmetic of the D2Q9 step, shared by the single-grid and
+// batched kernels: vector loads with periodic pulls, moments, BGK collision
+// with Guo forcing (all in deviation form f_l - w_l).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lbm_internal.h"
+
+namespace lbm {
+namespace step_detail {
+
+// ---- vector types ---------------------------------------------------------------
+template <typename T, int VX> struct Vec;
+template <> struct Vec<float, 2> {
+  typedef float A __attribute__((ext_vector_type(2), aligned(8)));
+  typedef float U __attribute__((ext_vector_type(2), aligned(4)));
+};
+template <> struct Vec<float, 4> {
+  typedef float A __attribute__((ext_vector_type(4), aligned(16)));
+  typedef float U __attribute__((ext_vector_type(4), aligned(4)));
+};
+template <> struct Vec<double, 2> {
+  typedef double A __attribute__((ext_vector_type(2), aligned(16)));
+  typedef double U __attribute__((ext_vector_type(2), aligned(8)));
+};
+template <> struct Vec<double, 4> {
+  typedef double A __attribute__((ext_vector_type(4), aligned(32)));
+  typedef double U __attribute__((ext_vector_type(4), aligned(8)));
+};
+
+// o[i] = row[(x0 + i - cx) mod nx], i < VX; x0 is a multiple of VX.
+template <typename T, int VX, int CX>
+__device__ __forceinline__ void pull_row(const T* __restrict__ row, int x0, int nx, T (&o)[VX]) {
+  if constexpr (VX == 1) {
+    int xs = x0 - CX;
+    if (CX == 1 && xs < 0) xs += nx;
+    if (CX == -1 && xs >= nx) xs -= nx;
+    o[0] = row[xs];
+  } else {
+    typedef typename Vec<T, VX>::A VA;
+    typedef typename Vec<T, VX>::U VU;
+    if constexpr (CX == 0) {
+      VA v = *reinterpret_cast<const VA*>(row + x0);
+#pragma unroll
+      for (int i = 0; i < VX; ++i) o[i] = v[i];
+    } else if constexpr (CX == 1) {
+      if (x0 > 0) {
+        VU v = *reinterpret_cast<const VU*>(row + x0 - 1);
+#pragma unroll
+        for (int i = 0; i < VX; ++i) o[i] = v[i];
+      } else {
+        VA v = *reinterpret_cast<const VA*>(row);
+        o[0] = row[nx - 1];
+#pragma unroll
+        for (int i = 1; i < VX; ++i) o[i] = v[i - 1];
+      }
+    } else {
+      if (x0 + VX < nx) {
+        VU v = *reinterpret_cast<const VU*>(row + x0 + 1);
+#pragma unroll
+        for (int i = 0; i < VX; ++i) o[i] = v[i];
+      } else {
+        VA v = *reinterpret_cast<const VA*>(row + x0);
+#pragma unroll
+        for (int i = 0; i < VX - 1; ++i) o[i] = v[i + 1];
+        o[VX - 1] = row[0];
+      }
+    }
+  }
+}
+
+template <typename T, int VX>
+__device__ __forceinline__ void load_aligned(const T* __restrict__ p, T (&o)[VX]) {
+  if constexpr (VX == 1) {
+    o[0] = *p;
+  } else {
+    typedef typename Vec<T, VX>::A VA;
+    VA v = *reinterpret_cast<const VA*>(p);
+#pragma unroll
+    for (int i = 0; i < VX; ++i) o[i] = v[i];
+  }
+}
+
+template <typename T, int VX, bool NT>
+__device__ __forceinline__ void store_aligned(T* __restrict__ p, const T (&o)[VX]) {
+  if constexpr (VX == 1) {
+    if constexpr (NT) __builtin_nontemporal_store(o[0], p);
+    else *p = o[0];
+  } else {
+    typedef typename Vec<T, VX>::A VA;
+    VA v;
+#pragma unroll
+    for (int i = 0; i < VX; ++i) v[i] = o[i];
+    if constexpr (NT) __builtin_nontemporal_store(v, reinterpret_cast<VA*>(p));
+    else *reinterpret_cast<VA*>(p) = v;
+  }
+}
+
+// Pre-collision moments of one site from the deviations d_l = f_l - w_l.
+// rho = 1 + sum d; j = sum c d; half-force velocity with implicit drag:
+// u = (j + F_ext/2) / (rho (1 + alpha/2)), total force F = F_ext - alpha rho u.
+template <typename T, bool FORCE>
+struct SiteMoments {
+  T drho, rho, ux, uy, Fx, Fy;
+  __device__ __forceinline__ SiteMoments(const T (&d)[9], T fx, T fy, T alpha) {
+    drho = ((d[0] + (d[1] + d[3])) + (d[2] + d[4])) + ((d[5] + d[7]) + (d[6] + d[8]));
+    rho = T(1) + drho;
+    const T jx = (d[1] - d[3]) + ((d[5] - d[7]) + (d[8] - d[6]));
+    const T jy = (d[2] - d[4]) + ((d[5] - d[7]) + (d[6] - d[8]));
+    if constexpr (FORCE) {
+      const T inv = T(1) / (rho * (T(1) + T(0.5) * alpha));
+      ux = (jx + T(0.5) * fx) * inv;
+      uy = (jy + T(0.5) * fy) * inv;
+      Fx = fx - alpha * rho * ux;
+      Fy = fy - alpha * rho * uy;
+    } else {
+      const T inv = T(1) / rho;
+      ux = jx * inv;
+      uy = jy * inv;
+      Fx = T(0);
+      Fy = T(0);
+    }
+  }
+};
+
+// BGK collision (Eq. 1) towards the equilibrium of Eq. 2, with Guo's forcing
+// term (1 - 1/(2 tau)) w [3 (c - u) + 9 (c.u) c] . F, all in deviation form.
+template <typename T, bool FORCE>
+__device__ __forceinline__ void collide_site(const T (&d)[9], const SiteMoments<T, FORCE>& m,
+                                             T omega, T guo, T (&o)[9]) {
+  const T usq15 = T(1.5) * (m.ux * m.ux + m.uy * m.uy);
+  const T uF3 = FORCE ? T(3) * (m.ux * m.Fx + m.uy * m.Fy) : T(0);
+#pragma unroll
+  for (int l = 0; l < 9; ++l) {
+    const T w = T(wq(l));
+    const T cu = T(cxq(l)) * m.ux + T(cyq(l)) * m.uy;
+    const T deq = w * (m.drho + m.rho * (T(3) * cu + T(4.5) * cu * cu - usq15));
+    T v = d[l] - omega * (d[l] - deq);
+    if constexpr (FORCE) {
+      const T cF = T(cxq(l)) * m.Fx + T(cyq(l)) * m.Fy;
+      v += guo * w * (T(3) * cF - uF3 + T(9) * cu * cF);
+    }
+    o[l] = v;
+  }
+}
+
+template <int L, typename T, int VX>
+__device__ __forceinline__ void pull_plane(const T* __restrict__ src, size_t plane, int nx,
+                                           int x0, int y, int yn, int yp, T (&d)[9][VX]) {
+  constexpr int cy = cyq(L);
+  const int ys = cy == 1 ? yn : (cy == -1 ? yp : y);
+  pull_row<T, VX, cxq(L)>(src + L * plane + static_cast<size_t>(ys) * nx, x0, nx, d[L]);
+}
+
+// Pull all nine planes of the VX sites (x0..x0+VX-1, y).
+template <typename T, int VX>
+__device__ __forceinline__ void pull_all(const T* __restrict__ src, size_t plane, int nx, int x0,
+                                         int y, int yn, int yp, T (&d)[9][VX]) {
+  pull_plane<0>(src, plane, nx, x0, y, yn, yp, d);
+  pull_plane<1>(src, plane, nx, x0, y, yn, yp, d);
+  pull_plane<2>(src, plane, nx, x0, y, yn, yp, d);
+  pull_plane<3>(src, plane, nx, x0, y, yn, yp, d);
+  pull_plane<4>(src, plane, nx, x0, y, yn, yp, d);
+  pull_plane<5>(src, plane, nx, x0, y, yn, yp, d);
+  pull_plane<6>(src, plane, nx, x0, y, yn, yp, d);
+  pull_plane<7>(src, plane, nx, x0, y, yn, yp, d);
+  pull_plane<8>(src, plane, nx, x0, y, yn, yp, d);
+}
+
+}  // namespace step_detail
+}  // namespace lbm

@@ -1,0 +1,125 @@
+"""GPU checks of the batched ensemble: every run equals the single-grid path, and
+the single-grid path equals the FP64 oracle (checked elsewhere), so the batch is
+held to the oracle too; persistent and per-step modes agree bit for bit."""
+import numpy as np
+import pytest
+import torch
+
+import lbm_inputs as inp
+from helpers import gpu_patch, oracle_patch_moments, rel_err
+from oracle import ref
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+def small_members(seed=0):
+    rng = np.random.default_rng(seed)
+    shapes = [(16, 16), (32, 48), (40, 24), (64, 64), (20, 36)]
+    out = []
+    for k, (ny, nx) in enumerate(shapes):
+        rho = 1.0 + 0.01 * rng.standard_normal((ny, nx))
+        ux = 0.04 * rng.standard_normal((ny, nx))
+        uy = 0.04 * rng.standard_normal((ny, nx))
+        m = {"rho": rho, "ux": ux, "uy": uy, "tau": float(rng.uniform(0.51, 0.8))}
+        if k == 2:
+            m["fx"] = 1e-5 * rng.standard_normal((ny, nx))
+            m["fy"] = 1e-5 * rng.standard_normal((ny, nx))
+            m["alpha"] = 1e-3
+        if k == 4:
+            m["alpha"] = 2e-3
+        out.append(m)
+    return out
+
+
+@pytest.mark.parametrize("mode", ["persistent", "per_step"])
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_ensemble_matches_single_grid_and_oracle(gpu_lib, mode, dtype):
+    from paper_1809_06735_amd import Simulation
+    from paper_1809_06735_amd.ensemble import Ensemble
+    say(f"ensemble small {mode} {dtype}")
+    mem = small_members()
+    ens = Ensemble(mem, dtype=dtype, mode=mode, chunk=8)
+    steps = 21                      # two graph replays + an odd remainder
+    ens.step(steps)
+    assert ens.time == steps
+    tol = 1e-12 if dtype == "f64" else 1e-5
+    for r, m in enumerate(mem):
+        got = ens.moments(r)
+        sim = Simulation(m["rho"], m["ux"], m["uy"], m["tau"], dtype=dtype, fx=m.get("fx"),
+                         fy=m.get("fy"), alpha=m.get("alpha", 0.0))
+        sim.step(steps)
+        want_gpu = sim.moments()
+        for a, b in zip(got[:3], want_gpu[:3]):
+            assert rel_err(a, b) <= (1e-15 if dtype == "f64" else 1e-7), r
+        kw = {}
+        if m.get("fx") is not None:
+            kw = dict(fx_ext=ref.t64(m["fx"]), fy_ext=ref.t64(m["fy"]))
+        alpha = m.get("alpha", 0.0)
+        f = ref.run(ref.init_populations(m["rho"], m["ux"], m["uy"]), steps, m["tau"], alpha=alpha, **kw)
+        want = ref.moments(f, kw.get("fx_ext"), kw.get("fy_ext"), alpha)
+        for name, a, b in zip(("rho", "ux", "uy"), got[:3], want):
+            e = rel_err(a, b)
+            say(f"  run {r} {name} vs oracle {e:.1e}")
+            assert e < tol, (r, name, e)
+        sim.close()
+    ens.close()
+
+
+def test_persistent_and_per_step_modes_agree_bitwise(gpu_lib):
+    from paper_1809_06735_amd.ensemble import Ensemble
+    mem = small_members(1)
+    a = Ensemble(mem, mode="persistent", chunk=10)
+    b = Ensemble(mem, mode="per_step", chunk=4)
+    a.step(37)
+    b.step(37)
+    for r in range(len(mem)):
+        for x, y in zip(a.moments(r, scalars=False), b.moments(r, scalars=False)):
+            assert torch.equal(x, y), r
+
+
+def test_ensemble_tiles_and_autotune_keep_results(gpu_lib):
+    from paper_1809_06735_amd.ensemble import Ensemble
+    mem = small_members(2)
+    base = Ensemble(mem, mode="persistent", chunk=6)
+    base.set_tile(1, 1)
+    base.step(30)
+    ref_m = [base.moments(r, scalars=False) for r in range(len(mem))]
+    for vx, g, bt in ((2, 1, 256), (4, 3, 256), (4, 8, 1024), (1, 2, 512)):
+        e = Ensemble(mem, mode="persistent", chunk=6)
+        e.set_tile(vx, g, bt)
+        e.step(30)
+        for r in range(len(mem)):
+            for x, y in zip(e.moments(r, scalars=False), ref_m[r]):
+                # FP32: differently shaped instances may round differently
+                assert rel_err(x, y) <= 1e-5, (vx, g, r)
+    t = Ensemble(mem, mode="persistent", chunk=6)
+    bt, vx, g = t.autotune(trial_steps=4)
+    assert bt in (256, 1024) and vx in (1, 2, 4) and 1 <= g <= 64
+    assert t.get_mode()[0] in ("persistent", "per_step")
+    assert t.time > 0 and t.time % 2 == 0
+
+
+def test_ensemble64_workload_sampled(gpu_lib):
+    """Workload ensemble64 (64 runs, 256^2..1024^2, FP32, tau in [0.505, 0.6]): 20 steps in
+    one persistent graph replay chunk, two members checked on oracle patches."""
+    from paper_1809_06735_amd.ensemble import Ensemble
+    say("ensemble64 build")
+    mem = inp.ensemble_members(64)
+    ens = Ensemble(mem, dtype="f32", mode="persistent", chunk=20)
+    assert ens.sites == sum(m["n"] ** 2 for m in mem)
+    ens.step(20)
+    for r in (0, 37):
+        m = mem[r]
+        got = ens.moments(r, scalars=False)
+        n = m["n"]
+        for (y0, x0) in ((n - 5, n - 7), (n // 3, n // 2)):
+            want = oracle_patch_moments((m["rho"], m["ux"], m["uy"]), m["tau"], 20, y0, x0, 12)
+            for name, g, w in zip(("rho", "ux", "uy"), got, want):
+                e = rel_err(gpu_patch(g, y0, x0, 12), w)
+                say(f"ensemble64 run {r} (n={n}) patch ({y0},{x0}) {name} {e:.1e}")
+                assert e < 1e-5
+    ens.close()
