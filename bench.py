@@ -36,20 +36,26 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def step_source_digest():
+    """Digest of the step kernel's sources (the counters are valid only for it)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("lbm_step.hip", "lbm_site.h"):
+        h.update(open(os.path.join(ROOT, "paper_1809_06735_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def traffic_from_profile(kernel_tag):
     """Per-launch HBM bytes of the step kernel from the committed counter summary,
     or None when it is missing or was taken on another version of the kernel."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", f"{kernel_tag}_traffic.md")
     if not os.path.exists(path):
         return None
-    src = os.path.join(ROOT, "paper_1809_06735_amd", "csrc", "lbm_step.hip")
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     rec = None
     for line in open(path):
         if line.startswith("TRAFFIC_JSON:"):
             rec = json.loads(line.split(":", 1)[1])
-    if not rec or rec.get("source_sha256_16") != digest:
+    if not rec or rec.get("source_sha256_16") != step_source_digest():
         return None
     return rec.get("bytes_per_launch")
 
@@ -80,6 +86,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="only launch the step kernel of the workload (20 times, autotuned shape) "
+                         "and the 1 GiB copy kernel (5 times), for hardware-counter runs")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); the multi-GPU layout is "
@@ -101,6 +110,20 @@ def main():
                      with_balance=True)
     tile = sim.autotune(trial_steps=5)
     log(f"[bench] step kernel shape {tile}")
+    if a.kernels_only:
+        torch.cuda.synchronize()
+        sim.step(20)
+        torch.cuda.synchronize()
+        sim.close()
+        buf = torch.empty(2 << 30, dtype=torch.uint8, device="cuda")
+        from paper_1809_06735_amd import _lib as L
+        lib = L.load()
+        for _ in range(5):
+            L.check(lib.lbm_copy(buf[1 << 30:].data_ptr(), buf[:1 << 30].data_ptr(), 1 << 30,
+                                 torch.cuda.current_stream().cuda_stream), "lbm_copy")
+        torch.cuda.synchronize()
+        log("[bench] kernels-only run done: 20 step launches, 5 copies of 1 GiB")
+        return
 
     def one_pass():
         sim.step(STEPS_PER_PASS)
