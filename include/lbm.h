@@ -54,8 +54,9 @@ enum {
   LBM_E_TIMEOUT = -7      /* a persistent kernel's bounded barrier wait ran out    */
 };
 
-/* ---- storage types -------------------------------------------------------- */
+/* ---- storage types and population layouts ---------------------------------- */
 enum { LBM_F32 = 0, LBM_F64 = 1 };
+enum { LBM_LAYOUT_PLANES = 0, LBM_LAYOUT_ROWS = 1 };
 
 /* ---- indices into the 8 global scalars returned by *_moments -------------- */
 enum {
@@ -97,7 +98,9 @@ typedef struct {
   int32_t has_force;   /* 1: a static external force field is given to lbm_init */
   int32_t with_balance;/* 1: the workspace also holds the balance scratch, so
                           lbm_subvolume_balance can be called on this handle     */
-  int32_t reserved;    /* must be 0                                              */
+  int32_t layout;      /* population layout in the workspace: LBM_LAYOUT_PLANES
+                          ([9][ny][nx]) or LBM_LAYOUT_ROWS ([ny][9][nx], the nine
+                          populations of a grid row contiguous)                    */
   double tau;          /* BGK relaxation time (Eq. 1), > 0.5 (Eq. 5: nu > 0)     */
   double drag_alpha;   /* linear drag coefficient alpha >= 0: force -alpha rho u */
   void* stream;        /* hipStream_t to enqueue on, or NULL                     */

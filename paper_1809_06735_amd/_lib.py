@@ -22,6 +22,9 @@ LBM_E_UNSUPPORTED = -6
 LBM_E_TIMEOUT = -7
 LBM_F32 = 0
 LBM_F64 = 1
+LBM_LAYOUT_PLANES = 0
+LBM_LAYOUT_ROWS = 1
+LAYOUTS = {"planes": LBM_LAYOUT_PLANES, "rows": LBM_LAYOUT_ROWS}
 LBM_BATCH_PERSISTENT = 0
 LBM_BATCH_PER_STEP = 1
 NTERMS = 13
@@ -40,7 +43,7 @@ class LBMError(RuntimeError):
 
 class Config(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("dtype", C.c_int32),
-                ("has_force", C.c_int32), ("with_balance", C.c_int32), ("reserved", C.c_int32),
+                ("has_force", C.c_int32), ("with_balance", C.c_int32), ("layout", C.c_int32),
                 ("tau", C.c_double), ("drag_alpha", C.c_double), ("stream", C.c_void_p)]
 
 

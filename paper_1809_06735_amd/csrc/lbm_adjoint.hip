@@ -219,7 +219,7 @@ struct Seeds {
 };
 
 template <typename T>
-__device__ __forceinline__ void pull_sites(const T* __restrict__ g, size_t plane, int nx, int ny,
+__device__ __forceinline__ void pull_sites(const T* __restrict__ g, PopLayout lay, int nx, int ny,
                                            int x, int y, int sign, T (&d)[9]) {
   // d_l = g_l(x - sign * c_l)
 #pragma unroll
@@ -229,33 +229,35 @@ __device__ __forceinline__ void pull_sites(const T* __restrict__ g, size_t plane
     xs -= xs >= nx ? nx : 0;
     ys += ys < 0 ? ny : 0;
     ys -= ys >= ny ? ny : 0;
-    d[l] = g[l * plane + static_cast<size_t>(ys) * nx + xs];
+    d[l] = g[l * lay.ps + static_cast<size_t>(ys) * lay.rs + xs];
   }
 }
 
 // a^T(x) = M'(f^T(x))^T mhat^T(x)
 template <typename T>
 __global__ void __launch_bounds__(kAT) k_adj_init(const T* __restrict__ g, T* __restrict__ adj,
-                                                  Seeds s, int nx, int ny) {
+                                                  Seeds s, PopLayout lay, int nx, int ny) {
   const size_t plane = static_cast<size_t>(nx) * ny;
   const size_t i = blockIdx.x * size_t(kAT) + threadIdx.x;
   if (i >= plane) return;
   const int x = static_cast<int>(i % nx), y = static_cast<int>(i / nx);
   T d[9];
-  pull_sites<T>(g, plane, nx, ny, x, y, 1, d);
+  pull_sites<T>(g, lay, nx, ny, x, y, 1, d);
   SiteMoments<T, false> m(d, T(0), T(0), T(0));
   const double rh = s.rho ? s.rho[i] : 0.0;
+  const size_t at = static_cast<size_t>(y) * lay.rs + x;
   const double ux = double(m.ux), uy = double(m.uy), rho = double(m.rho);
 #pragma unroll
   for (int l = 0; l < 9; ++l)
-    adj[l * plane + i] = T(rh + (s.ux[i] * (cxq(l) - ux) + s.uy[i] * (cyq(l) - uy)) / rho);
+    adj[l * lay.ps + at] = T(rh + (s.ux[i] * (cxq(l) - ux) + s.uy[i] * (cyq(l) - uy)) / rho);
 }
 
 // One backward step; also adds this step's sum of v . dC/dtau to the block's slot.
 template <typename T>
 __global__ void __launch_bounds__(kAT) k_adj_step(const T* __restrict__ g, const T* __restrict__ ain,
                                                   T* __restrict__ aout, Seeds s, int has_seed,
-                                                  int nx, int ny, double omega, double* tau_acc) {
+                                                  PopLayout lay, int nx, int ny, double omega,
+                                                  double* tau_acc) {
   __shared__ double sh[kAT / 64];
   const size_t plane = static_cast<size_t>(nx) * ny;
   const size_t i = blockIdx.x * size_t(kAT) + threadIdx.x;
@@ -263,8 +265,9 @@ __global__ void __launch_bounds__(kAT) k_adj_step(const T* __restrict__ g, const
   if (i < plane) {
     const int x = static_cast<int>(i % nx), y = static_cast<int>(i / nx);
     T d[9], v[9];
-    pull_sites<T>(g, plane, nx, ny, x, y, 1, d);      // f^t(x) (deviation)
-    pull_sites<T>(ain, plane, nx, ny, x, y, -1, v);   // a^{t+1}(x + c_l)
+    pull_sites<T>(g, lay, nx, ny, x, y, 1, d);      // f^t(x) (deviation)
+    pull_sites<T>(ain, lay, nx, ny, x, y, -1, v);   // a^{t+1}(x + c_l)
+    const size_t at = static_cast<size_t>(y) * lay.rs + x;
     SiteMoments<T, false> m(d, T(0), T(0), T(0));
     const T om = T(omega);
     const T usq15 = T(1.5) * (m.ux * m.ux + m.uy * m.uy);
@@ -291,7 +294,7 @@ __global__ void __launch_bounds__(kAT) k_adj_step(const T* __restrict__ g, const
       const T ex = T(cxq(k)) - m.ux, ey = T(cyq(k)) - m.uy;
       T o = (T(1) - om) * v[k] + om * (A + (Bx * ex + By * ey) * inv);
       if (has_seed) o += T(rh + (sx * double(ex) + sy * double(ey)) / double(m.rho));
-      aout[k * plane + i] = o;
+      aout[k * lay.ps + at] = o;
     }
     dtau = double(neq) * omega * omega;   // v . (f - f^eq) / tau^2
   }
@@ -309,16 +312,17 @@ __global__ void __launch_bounds__(kAT) k_adj_step(const T* __restrict__ g, const
 // du0 = sum_l a^0_l df^eq_l/du at (rho0 = 1, u0)
 template <typename T>
 __global__ void __launch_bounds__(kAT) k_adj_u0(const T* __restrict__ adj, const double* __restrict__ ux0,
-                                                const double* __restrict__ uy0, int nx, int ny,
-                                                double* gx, double* gy) {
+                                                const double* __restrict__ uy0, PopLayout lay, int nx,
+                                                int ny, double* gx, double* gy) {
   const size_t plane = static_cast<size_t>(nx) * ny;
   const size_t i = blockIdx.x * size_t(kAT) + threadIdx.x;
   if (i >= plane) return;
   const double ux = ux0[i], uy = uy0[i];
+  const size_t at = (i / nx) * lay.rs + (i % nx);
   double bx = 0.0, by = 0.0;
 #pragma unroll
   for (int l = 0; l < 9; ++l) {
-    const double a = double(adj[l * plane + i]);
+    const double a = double(adj[l * lay.ps + at]);
     const double cu = cxq(l) * ux + cyq(l) * uy;
     bx += a * wq(l) * (3.0 * cxq(l) + 9.0 * cu * cxq(l) - 3.0 * ux);
     by += a * wq(l) * (3.0 * cyq(l) + 9.0 * cu * cyq(l) - 3.0 * uy);
@@ -389,11 +393,14 @@ int validate_adj(const lbm_adjoint_config* c) {
   return LBM_OK;
 }
 
+constexpr int kAdjLayout = LBM_LAYOUT_ROWS;
+
 template <typename T>
 int launch_adj_init(const void* g, void* adj, Seeds s, int nx, int ny, hipStream_t st) {
   const size_t plane = static_cast<size_t>(nx) * ny;
   hipLaunchKernelGGL(k_adj_init<T>, dim3(nblocks_sites(plane)), dim3(kAT), 0, st,
-                     static_cast<const T*>(g), static_cast<T*>(adj), s, nx, ny);
+                     static_cast<const T*>(g), static_cast<T*>(adj), s,
+                     pop_layout(kAdjLayout, nx, ny), nx, ny);
   LBM_HIP(hipGetLastError());
   return LBM_OK;
 }
@@ -404,7 +411,7 @@ int launch_adj_step(const void* g, const void* ain, void* aout, Seeds s, int has
   const size_t plane = static_cast<size_t>(nx) * ny;
   hipLaunchKernelGGL(k_adj_step<T>, dim3(nblocks_sites(plane)), dim3(kAT), 0, st,
                      static_cast<const T*>(g), static_cast<const T*>(ain), static_cast<T*>(aout),
-                     s, has_seed, nx, ny, omega, tau_acc);
+                     s, has_seed, pop_layout(kAdjLayout, nx, ny), nx, ny, omega, tau_acc);
   LBM_HIP(hipGetLastError());
   return LBM_OK;
 }
@@ -414,7 +421,8 @@ int launch_adj_u0(const void* adj, const double* ux0, const double* uy0, int nx,
                   double* gx, double* gy, hipStream_t st) {
   const size_t plane = static_cast<size_t>(nx) * ny;
   hipLaunchKernelGGL(k_adj_u0<T>, dim3(nblocks_sites(plane)), dim3(kAT), 0, st,
-                     static_cast<const T*>(adj), ux0, uy0, nx, ny, gx, gy);
+                     static_cast<const T*>(adj), ux0, uy0, pop_layout(kAdjLayout, nx, ny), nx, ny, gx,
+                     gy);
   LBM_HIP(hipGetLastError());
   return LBM_OK;
 }
@@ -437,6 +445,9 @@ struct Runner {
     p.h_uy = hy;
     p.nx = c.nx;
     p.ny = c.ny;
+    const PopLayout lay = pop_layout(kAdjLayout, c.nx, c.ny);
+    p.ps = lay.ps;
+    p.rs = lay.rs;
     p.omega = 1.0 / c.tau;
     p.alpha = 0.0;
     return launch_step(c.dtype, false, p, tile, s);
@@ -485,7 +496,9 @@ int lbm_adjoint_run(const lbm_adjoint_config* cfg, void* ws, size_t ws_bytes, co
   // ---- forward: init, steps with checkpoints, moments at T-2, T-1, T ----
   hipLaunchKernelGGL(k_set, dim3(g), dim3(256), 0, s, R.w.fill, R.plane, 1.0);   // rho0 = 1
   LBM_HIP(hipGetLastError());
-  if (int rc = launch_init(cfg->dtype, R.ckpt_state(0), R.w.fill, ux0, uy0, nx, ny, s)) return rc;
+  if (int rc = launch_init(cfg->dtype, R.ckpt_state(0), pop_layout(kAdjLayout, nx, ny), R.w.fill,
+                           ux0, uy0, nx, ny, s))
+    return rc;
   void* cur = R.w.adj[0];
   void* nxt = R.w.adj[1];
   LBM_HIP(hipMemcpyAsync(cur, R.ckpt_state(0), R.state_bytes, hipMemcpyDeviceToDevice, s));
@@ -510,6 +523,8 @@ int lbm_adjoint_run(const lbm_adjoint_config* cfg, void* ws, size_t ws_bytes, co
     m.partials = R.w.w;  // scratch (block partials, overwritten later)
     m.nx = nx;
     m.ny = ny;
+    m.ps = pop_layout(kAdjLayout, nx, ny).ps;
+    m.rs = pop_layout(kAdjLayout, nx, ny).rs;
     if (int rc = launch_moments(cfg->dtype, false, m, s)) return rc;
   }
 

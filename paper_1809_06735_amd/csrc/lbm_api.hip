@@ -45,7 +45,8 @@ int validate_config(const lbm_config* c) {
   if (c->has_force != 0 && c->has_force != 1) return fail(LBM_E_INVALID, "has_force must be 0 or 1");
   if (c->with_balance != 0 && c->with_balance != 1)
     return fail(LBM_E_INVALID, "with_balance must be 0 or 1");
-  if (c->reserved != 0) return fail(LBM_E_INVALID, "reserved must be 0");
+  if (c->layout != LBM_LAYOUT_PLANES && c->layout != LBM_LAYOUT_ROWS)
+    return fail(LBM_E_INVALID, "layout must be LBM_LAYOUT_PLANES or LBM_LAYOUT_ROWS");
   return LBM_OK;
 }
 
@@ -81,6 +82,7 @@ struct lbm_ctx_s {
   int64_t timed_launches = 0;
   int64_t pending_launches = 0;
   size_t plane = 0;
+  PopLayout lay{};
 };
 
 namespace {
@@ -122,9 +124,10 @@ Layout carve_ctx(const lbm_config& c, void* base, size_t cap) {
 std::mutex g_tune_mu;
 std::map<std::string, lbm_tile> g_tune;
 
-std::string tune_key(int dtype, int nx, int ny, bool force) {
+std::string tune_key(int dtype, int nx, int ny, bool force, int layout) {
   char b[128];
-  snprintf(b, sizeof(b), "step dtype=%d nx=%d ny=%d force=%d", dtype, nx, ny, force ? 1 : 0);
+  snprintf(b, sizeof(b), "step dtype=%d nx=%d ny=%d force=%d layout=%d", dtype, nx, ny, force ? 1 : 0,
+           layout);
   return b;
 }
 
@@ -138,12 +141,12 @@ void tune_cache_load() {
   if (!f) return;
   char line[256];
   while (std::fgets(line, sizeof(line), f)) {
-    int dt, nx, ny, fo;
+    int dt, nx, ny, fo, lay;
     lbm_tile t;
-    if (std::sscanf(line, "step dtype=%d nx=%d ny=%d force=%d : %d %d %d %d %d", &dt, &nx, &ny, &fo,
-                    &t.bx, &t.by, &t.vx, &t.ry, &t.nt) == 9 &&
+    if (std::sscanf(line, "step dtype=%d nx=%d ny=%d force=%d layout=%d : %d %d %d %d %d", &dt, &nx,
+                    &ny, &fo, &lay, &t.bx, &t.by, &t.vx, &t.ry, &t.nt) == 10 &&
         tile_ok(t, dt, nx, ny))
-      g_tune[tune_key(dt, nx, ny, fo != 0)] = t;
+      g_tune[tune_key(dt, nx, ny, fo != 0, lay)] = t;
   }
   std::fclose(f);
 }
@@ -172,6 +175,8 @@ int enqueue_step(lbm_ctx_s* c, int src, hipStream_t s, double* hr, double* hx, d
   p.h_uy = hy;
   p.nx = c->cfg.nx;
   p.ny = c->cfg.ny;
+  p.ps = c->lay.ps;
+  p.rs = c->lay.rs;
   p.omega = 1.0 / c->cfg.tau;
   p.alpha = c->cfg.drag_alpha;
   return launch_step(c->cfg.dtype, is_forced(c), p, c->tile, s);
@@ -251,6 +256,8 @@ int moments_into(lbm_ctx_s* c, void* rho, void* ux, void* uy, int out_dtype, dou
   m.partials = c->partials;
   m.nx = c->cfg.nx;
   m.ny = c->cfg.ny;
+  m.ps = c->lay.ps;
+  m.rs = c->lay.rs;
   m.alpha = c->cfg.drag_alpha;
   int rc = launch_moments(c->cfg.dtype, is_forced(c), m, c->stream);
   if (rc) return rc;
@@ -344,13 +351,14 @@ int lbm_init(const lbm_config* cfg, void* ws, size_t ws_bytes, const double* rho
   c->scalars_dev = l.scalars;
   c->bal = l.bal;
   c->plane = static_cast<size_t>(cfg->nx) * cfg->ny;
+  c->lay = pop_layout(cfg->layout, cfg->nx, cfg->ny);
   {
     std::lock_guard<std::mutex> g(g_tune_mu);
     tune_cache_load();
-    auto it = g_tune.find(tune_key(cfg->dtype, cfg->nx, cfg->ny, is_forced(c)));
+    auto it = g_tune.find(tune_key(cfg->dtype, cfg->nx, cfg->ny, is_forced(c), cfg->layout));
     c->tile = it != g_tune.end() ? it->second : default_tile(cfg->dtype, cfg->nx, cfg->ny);
   }
-  int rc = launch_init(cfg->dtype, c->pop[0], rho0, ux0, uy0, cfg->nx, cfg->ny, c->stream);
+  int rc = launch_init(cfg->dtype, c->pop[0], c->lay, rho0, ux0, uy0, cfg->nx, cfg->ny, c->stream);
   if (rc == LBM_OK && cfg->has_force) {
     rc = launch_to_storage(cfg->dtype, c->fx, fx, c->plane, c->stream);
     if (rc == LBM_OK) rc = launch_to_storage(cfg->dtype, c->fy, fy, c->plane, c->stream);
@@ -614,7 +622,7 @@ int lbm_autotune(lbm_ctx c, int32_t trial_steps, lbm_tile* chosen) {
   if (rc) return rc;
   {
     std::lock_guard<std::mutex> g(g_tune_mu);
-    g_tune[tune_key(c->cfg.dtype, c->cfg.nx, c->cfg.ny, is_forced(c))] = best_t;
+    g_tune[tune_key(c->cfg.dtype, c->cfg.nx, c->cfg.ny, is_forced(c), c->cfg.layout)] = best_t;
     tune_cache_store();
   }
   if (chosen) *chosen = best_t;

@@ -29,6 +29,7 @@ struct RunDesc {
   void* pop[2];
   const void* fx;
   const void* fy;
+  size_t ps, rs;
   int nx, ny;
   double omega;
   double alpha;
@@ -71,7 +72,7 @@ __device__ __forceinline__ void process_item(const BatchArgs& a, int item, int p
     const int yn = (y == 0) ? ny - 1 : y - 1;
     const int yp = (y == ny - 1) ? 0 : y + 1;
     T d[9][VX];
-    step_detail::pull_all<T, VX>(src, plane, nx, x0, y, yn, yp, d);
+    step_detail::pull_all<T, VX>(src, r.ps, r.rs, nx, x0, y, yn, yp, d);
     const size_t row = static_cast<size_t>(y) * nx + x0;
     T o[9][VX];
     if (r.forced) {
@@ -106,7 +107,8 @@ __device__ __forceinline__ void process_item(const BatchArgs& a, int item, int p
       }
     }
 #pragma unroll
-    for (int l = 0; l < 9; ++l) step_detail::store_aligned<T, VX, true>(dst + l * plane + row, o[l]);
+    for (int l = 0; l < 9; ++l)
+      step_detail::store_aligned<T, VX, true>(dst + l * r.ps + static_cast<size_t>(y) * r.rs + x0, o[l]);
   }
 }
 
@@ -488,11 +490,14 @@ int lbm_batch_init(const lbm_config* cfgs, int32_t nruns, void* ws, size_t ws_by
     d.fy = l.fy[r];
     d.nx = cfgs[r].nx;
     d.ny = cfgs[r].ny;
+    const PopLayout lay = pop_layout(cfgs[r].layout, d.nx, d.ny);
+    d.ps = lay.ps;
+    d.rs = lay.rs;
     d.omega = 1.0 / cfgs[r].tau;
     d.alpha = cfgs[r].drag_alpha;
     d.forced = (cfgs[r].has_force || cfgs[r].drag_alpha > 0.0) ? 1 : 0;
     b->runs.push_back(d);
-    rc = launch_init(b->dtype, d.pop[0], rho0[r], ux0[r], uy0[r], d.nx, d.ny, b->stream);
+    rc = launch_init(b->dtype, d.pop[0], lay, rho0[r], ux0[r], uy0[r], d.nx, d.ny, b->stream);
     const size_t plane = static_cast<size_t>(d.nx) * d.ny;
     if (rc == LBM_OK && cfgs[r].has_force) {
       rc = launch_to_storage(b->dtype, l.fx[r], fx[r], plane, b->stream);
@@ -654,6 +659,8 @@ int lbm_batch_moments(lbm_batch b, int32_t run, void* rho, void* ux, void* uy, i
   m.partials = b->d_partials;
   m.nx = r.nx;
   m.ny = r.ny;
+  m.ps = r.ps;
+  m.rs = r.rs;
   m.alpha = r.alpha;
   if (int rc = launch_moments(b->dtype, r.forced != 0, m, b->stream)) return rc;
   if (!scalars8) return LBM_OK;

@@ -38,6 +38,17 @@ __host__ __device__ constexpr double wq(int l) {
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// Element strides of the population array: element (l, y, x) is at
+// l * ps + y * rs + x.  LBM_LAYOUT_PLANES: [9][ny][nx] (ps = nx ny, rs = nx);
+// LBM_LAYOUT_ROWS: [ny][9][nx] (ps = nx, rs = 9 nx).
+struct PopLayout {
+  size_t ps, rs;
+};
+inline PopLayout pop_layout(int layout, int nx, int ny) {
+  if (layout == LBM_LAYOUT_ROWS) return PopLayout{static_cast<size_t>(nx), static_cast<size_t>(9) * nx};
+  return PopLayout{static_cast<size_t>(nx) * ny, static_cast<size_t>(nx)};
+}
+
 // Simple bump allocator over a caller workspace.
 struct Carver {
   char* base;
@@ -63,11 +74,12 @@ struct StepParams {
   double* h_ux;
   double* h_uy;
   int nx, ny;
+  size_t ps, rs;     // population layout strides
   double omega;      // 1/tau
   double alpha;      // drag
 };
 
-int launch_init(int dtype, void* pop, const double* rho0, const double* ux0,
+int launch_init(int dtype, void* pop, PopLayout lay, const double* rho0, const double* ux0,
                 const double* uy0, int nx, int ny, hipStream_t s);
 int launch_step(int dtype, bool force, const StepParams& p, const lbm_tile& t, hipStream_t s);
 bool tile_ok(const lbm_tile& t, int dtype, int nx, int ny);
@@ -92,6 +104,7 @@ struct MomentParams {
   double* fty64;
   double* partials;  // [nblocks][8]
   int nx, ny;
+  size_t ps, rs;     // population layout strides
   double alpha;
 };
 int moment_blocks(int nx, int ny);

@@ -146,26 +146,26 @@ __device__ __forceinline__ void collide_site(const T (&d)[9], const SiteMoments<
 }
 
 template <int L, typename T, int VX>
-__device__ __forceinline__ void pull_plane(const T* __restrict__ src, size_t plane, int nx,
+__device__ __forceinline__ void pull_plane(const T* __restrict__ src, size_t ps, size_t rs, int nx,
                                            int x0, int y, int yn, int yp, T (&d)[9][VX]) {
   constexpr int cy = cyq(L);
   const int ys = cy == 1 ? yn : (cy == -1 ? yp : y);
-  pull_row<T, VX, cxq(L)>(src + L * plane + static_cast<size_t>(ys) * nx, x0, nx, d[L]);
+  pull_row<T, VX, cxq(L)>(src + L * ps + static_cast<size_t>(ys) * rs, x0, nx, d[L]);
 }
 
 // Pull all nine planes of the VX sites (x0..x0+VX-1, y).
 template <typename T, int VX>
-__device__ __forceinline__ void pull_all(const T* __restrict__ src, size_t plane, int nx, int x0,
-                                         int y, int yn, int yp, T (&d)[9][VX]) {
-  pull_plane<0>(src, plane, nx, x0, y, yn, yp, d);
-  pull_plane<1>(src, plane, nx, x0, y, yn, yp, d);
-  pull_plane<2>(src, plane, nx, x0, y, yn, yp, d);
-  pull_plane<3>(src, plane, nx, x0, y, yn, yp, d);
-  pull_plane<4>(src, plane, nx, x0, y, yn, yp, d);
-  pull_plane<5>(src, plane, nx, x0, y, yn, yp, d);
-  pull_plane<6>(src, plane, nx, x0, y, yn, yp, d);
-  pull_plane<7>(src, plane, nx, x0, y, yn, yp, d);
-  pull_plane<8>(src, plane, nx, x0, y, yn, yp, d);
+__device__ __forceinline__ void pull_all(const T* __restrict__ src, size_t ps, size_t rs, int nx,
+                                         int x0, int y, int yn, int yp, T (&d)[9][VX]) {
+  pull_plane<0>(src, ps, rs, nx, x0, y, yn, yp, d);
+  pull_plane<1>(src, ps, rs, nx, x0, y, yn, yp, d);
+  pull_plane<2>(src, ps, rs, nx, x0, y, yn, yp, d);
+  pull_plane<3>(src, ps, rs, nx, x0, y, yn, yp, d);
+  pull_plane<4>(src, ps, rs, nx, x0, y, yn, yp, d);
+  pull_plane<5>(src, ps, rs, nx, x0, y, yn, yp, d);
+  pull_plane<6>(src, ps, rs, nx, x0, y, yn, yp, d);
+  pull_plane<7>(src, ps, rs, nx, x0, y, yn, yp, d);
+  pull_plane<8>(src, ps, rs, nx, x0, y, yn, yp, d);
 }
 
 }  // namespace step_detail

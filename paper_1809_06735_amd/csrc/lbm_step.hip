@@ -1,7 +1,8 @@
 // D2Q9 BGK step, initialisation, moments and copy kernels for gfx950.
 //
-// Storage: structure of arrays, plane l of [9][ny][nx] holds f_l - w_l (the
-// deviation from the rest state), x fastest.  The state at time t is kept
+// Storage: population l at site (y, x) is element l * ps + y * rs + x (either
+// nine planes [9][ny][nx] or nine rows per grid row [ny][9][nx]) and holds
+// f_l - w_l (the deviation from the rest state), x fastest.  The state at time t is kept
 // "un-streamed": plane l at site y holds f_l(y + c_l, t), so the pre-collision
 // populations at x are pulled from x - c_l, and one step is a single pass
 // that pulls, collides (Eq. 1 with the equilibrium of Eq. 2) and writes the
@@ -32,7 +33,6 @@ __global__ void __launch_bounds__(1024) k_step(StepParams p, int tiles_x, int to
   if (x0 >= p.nx) return;
   const int ybase = (ty * blockDim.y + threadIdx.y) * ry;
   const int nx = p.nx, ny = p.ny;
-  const size_t plane = static_cast<size_t>(nx) * ny;
   const T* __restrict__ src = static_cast<const T*>(p.src);
   T* __restrict__ dst = static_cast<T*>(p.dst);
   const T omega = T(p.omega);
@@ -44,7 +44,7 @@ __global__ void __launch_bounds__(1024) k_step(StepParams p, int tiles_x, int to
     const int yn = (y == 0) ? ny - 1 : y - 1;
     const int yp = (y == ny - 1) ? 0 : y + 1;
     T d[9][VX];
-    pull_all<T, VX>(src, plane, nx, x0, y, yn, yp, d);
+    pull_all<T, VX>(src, p.ps, p.rs, nx, x0, y, yn, yp, d);
     const size_t row = static_cast<size_t>(y) * nx + x0;
     T fx[VX], fy[VX];
     if constexpr (FORCE) {
@@ -73,7 +73,8 @@ __global__ void __launch_bounds__(1024) k_step(StepParams p, int tiles_x, int to
       hy[i] = double(m.uy);
     }
 #pragma unroll
-    for (int l = 0; l < 9; ++l) store_aligned<T, VX, NT>(dst + l * plane + row, o[l]);
+    for (int l = 0; l < 9; ++l)
+      store_aligned<T, VX, NT>(dst + l * p.ps + static_cast<size_t>(y) * p.rs + x0, o[l]);
     if (p.h_rho) {
 #pragma unroll
       for (int i = 0; i < VX; ++i) {
@@ -87,7 +88,8 @@ __global__ void __launch_bounds__(1024) k_step(StepParams p, int tiles_x, int to
 
 // f(x, 0) = f^eq(rho0(x), u0(x)) stored un-streamed: plane l at x - c_l.
 template <typename T>
-__global__ void __launch_bounds__(256) k_init(T* __restrict__ pop, const double* __restrict__ rho0,
+__global__ void __launch_bounds__(256) k_init(T* __restrict__ pop, PopLayout lay,
+                                              const double* __restrict__ rho0,
                                               const double* __restrict__ ux0,
                                               const double* __restrict__ uy0, int nx, int ny) {
   const size_t plane = static_cast<size_t>(nx) * ny;
@@ -106,7 +108,7 @@ __global__ void __launch_bounds__(256) k_init(T* __restrict__ pop, const double*
       xs -= xs >= nx ? nx : 0;
       ys += ys < 0 ? ny : 0;
       ys -= ys >= ny ? ny : 0;
-      pop[l * plane + static_cast<size_t>(ys) * nx + xs] = T(dev);
+      pop[l * lay.ps + static_cast<size_t>(ys) * lay.rs + xs] = T(dev);
     }
   }
 }
@@ -183,7 +185,7 @@ __global__ void __launch_bounds__(kMomThreads) k_moments(MomentParams p) {
       xs -= xs >= nx ? nx : 0;
       ys += ys < 0 ? ny : 0;
       ys -= ys >= ny ? ny : 0;
-      d[l] = pop[l * plane + static_cast<size_t>(ys) * nx + xs];
+      d[l] = pop[l * p.ps + static_cast<size_t>(ys) * p.rs + xs];
     }
     T fx = T(0), fy = T(0);
     if constexpr (FORCE) {
@@ -356,16 +358,16 @@ int launch_step(int dtype, bool force, const StepParams& p, const lbm_tile& t, h
   return dispatch_step<double>(force, p, t, s);
 }
 
-int launch_init(int dtype, void* pop, const double* rho0, const double* ux0, const double* uy0,
-                int nx, int ny, hipStream_t s) {
+int launch_init(int dtype, void* pop, PopLayout lay, const double* rho0, const double* ux0,
+                const double* uy0, int nx, int ny, hipStream_t s) {
   const size_t n = static_cast<size_t>(nx) * ny;
   const int g = grid_for(n, 256, 4096);
   if (dtype == LBM_F32)
-    hipLaunchKernelGGL(k_init<float>, dim3(g), dim3(256), 0, s, static_cast<float*>(pop), rho0, ux0,
-                       uy0, nx, ny);
-  else
-    hipLaunchKernelGGL(k_init<double>, dim3(g), dim3(256), 0, s, static_cast<double*>(pop), rho0,
+    hipLaunchKernelGGL(k_init<float>, dim3(g), dim3(256), 0, s, static_cast<float*>(pop), lay, rho0,
                        ux0, uy0, nx, ny);
+  else
+    hipLaunchKernelGGL(k_init<double>, dim3(g), dim3(256), 0, s, static_cast<double*>(pop), lay,
+                       rho0, ux0, uy0, nx, ny);
   LBM_HIP(hipGetLastError());
   return LBM_OK;
 }

@@ -21,7 +21,7 @@ class Ensemble:
     """
 
     def __init__(self, members, dtype="f32", device="cuda", stream=None, mode="persistent",
-                 chunk=100):
+                 chunk=100, layout="rows"):
         _require_gpu()
         self._lib = L.load()
         self.device = torch.device(device)
@@ -41,7 +41,8 @@ class Ensemble:
             ny, nx = rho.shape
             self.shapes.append((ny, nx))
             cfgs[r] = L.Config(nx=nx, ny=ny, dtype=dt, has_force=int(has_f), with_balance=0,
-                               reserved=0, tau=float(m["tau"]), drag_alpha=float(m.get("alpha", 0.0)),
+                               layout=L.LAYOUTS[layout], tau=float(m["tau"]),
+                               drag_alpha=float(m.get("alpha", 0.0)),
                                stream=sh)
             dev_inputs.append((rho, ux, uy, fx, fy))
         nbytes = C.c_size_t()

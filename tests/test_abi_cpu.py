@@ -40,7 +40,7 @@ def test_version_and_strerror():
 
 
 def cfg(**kw):
-    base = dict(nx=64, ny=64, dtype=L.LBM_F32, has_force=0, with_balance=0, reserved=0,
+    base = dict(nx=64, ny=64, dtype=L.LBM_F32, has_force=0, with_balance=0, layout=0,
                 tau=0.6, drag_alpha=0.0, stream=None)
     base.update(kw)
     return L.Config(**base)
@@ -59,7 +59,7 @@ def test_workspace_bytes_and_validation():
     lib.lbm_workspace_bytes(C.byref(cfg(with_balance=1)), C.byref(nb))
     assert nb.value > n.value + 13 * 65 * 65 * 8
     bad = [cfg(tau=0.5), cfg(tau=float("nan")), cfg(nx=8), cfg(dtype=7), cfg(drag_alpha=-1.0),
-           cfg(has_force=2), cfg(reserved=1), cfg(ny=70000)]
+           cfg(has_force=2), cfg(layout=2), cfg(ny=70000)]
     for c in bad:
         assert lib.lbm_workspace_bytes(C.byref(c), C.byref(n)) == L.LBM_E_INVALID
         assert lib.lbm_last_error()

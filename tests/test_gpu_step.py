@@ -261,3 +261,34 @@ def test_copy_bandwidth_runs(gpu_lib):
     from paper_1809_06735_amd import copy_bandwidth
     gbs, ms = copy_bandwidth(1 << 26, iters=3)
     assert gbs > 100
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_rows_layout_equals_planes_layout(gpu_lib, dtype):
+    """The row-interleaved population layout gives bit-identical moments and balance to the
+    plane layout (same arithmetic, other addresses), for several launch shapes."""
+    ny, nx = 48, 80
+    rng = np.random.default_rng(11)
+    rho = 1.0 + 0.01 * rng.standard_normal((ny, nx))
+    ux = 0.03 * rng.standard_normal((ny, nx))
+    uy = 0.03 * rng.standard_normal((ny, nx))
+    fx = 1e-5 * rng.standard_normal((ny, nx))
+    fy = 1e-5 * rng.standard_normal((ny, nx))
+    ref_m = None
+    for layout in ("planes", "rows"):
+        for tile in ((64, 1, 1, 1, 0), (64, 4, 2, 3, 1), (64, 2, 4, 1, 1)):
+            if dtype == "f64" and tile[2] == 4:
+                continue
+            s = Sim(rho, ux, uy, 0.57, dtype=dtype, fx=fx, fy=fy, alpha=1e-3, with_balance=True,
+                    layout=layout)
+            s.set_tile(*tile)
+            s.step(17)
+            m = s.moments(scalars=False)
+            b = s.balance((4, 16, 48))["stats"]
+            if ref_m is None:
+                ref_m, ref_b = m, b
+            else:
+                for x, y in zip(m, ref_m):
+                    assert torch.equal(x, y), (layout, tile)
+                assert b == ref_b
+            s.close()
