@@ -82,6 +82,9 @@ def bench_adjoint(log=print):
     vy = torch.as_tensor(uy, device=dev)
     sites = w.n * w.n
     out = {"grid": w.n, "steps": w.steps, "ckpt_every": 100, "box": 32, "dtype": "f32"}
+    # tune the step-kernel shape for this grid once; the adjoint run reuses it
+    s = Simulation(torch.ones_like(vx), vx, vy, w.tau, dtype="f32")
+    out["tile"] = list(s.autotune(trial_steps=10))
     adjoint_run(vx, vy, w.tau, 20, 32, 10)          # warm-up (allocations, code load)
 
     def timed(fn):
@@ -98,7 +101,6 @@ def bench_adjoint(log=print):
     out["forward_and_loss_MLUPS"] = round(sites * w.steps / t_fwd / 1e6, 1)
     out["gradient_run_MLUPS"] = round(sites * w.steps / t_all / 1e6, 1)
     out["backward_part_MLUPS"] = round(sites * w.steps / max(t_all - t_fwd, 1e-9) / 1e6, 1)
-    s = Simulation(torch.ones_like(vx), vx, vy, w.tau, dtype="f32")
     s.step(100)
     tp, _ = timed(lambda: s.step(w.steps))
     out["plain_forward_MLUPS"] = round(sites * w.steps / tp / 1e6, 1)

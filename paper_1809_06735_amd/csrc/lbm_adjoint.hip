@@ -252,60 +252,95 @@ __global__ void __launch_bounds__(kAT) k_adj_init(const T* __restrict__ g, T* __
     adj[l * lay.ps + at] = T(rh + (s.ux[i] * (cxq(l) - ux) + s.uy[i] * (cyq(l) - uy)) / rho);
 }
 
-// One backward step; also adds this step's sum of v . dC/dtau to the block's slot.
+// C'(f)^T v + M'(f)^T (rho_hat, u_hat) for one site; returns v . (f - f^eq)/tau^2.
 template <typename T>
-__global__ void __launch_bounds__(kAT) k_adj_step(const T* __restrict__ g, const T* __restrict__ ain,
-                                                  T* __restrict__ aout, Seeds s, int has_seed,
-                                                  PopLayout lay, int nx, int ny, double omega,
-                                                  double* tau_acc) {
-  __shared__ double sh[kAT / 64];
-  const size_t plane = static_cast<size_t>(nx) * ny;
-  const size_t i = blockIdx.x * size_t(kAT) + threadIdx.x;
+__device__ __forceinline__ double adjoint_site(const T (&d)[9], const T (&v)[9], T om, bool seed,
+                                               double rh, double sx, double sy, T (&o)[9]) {
+  SiteMoments<T, false> m(d, T(0), T(0), T(0));
+  const T usq15 = T(1.5) * (m.ux * m.ux + m.uy * m.uy);
+  T A = T(0), Bx = T(0), By = T(0), neq = T(0);
+#pragma unroll
+  for (int l = 0; l < 9; ++l) {
+    const T w = T(wq(l));
+    const T cx = T(cxq(l)), cy = T(cyq(l));
+    const T cu = cx * m.ux + cy * m.uy;
+    const T P = T(1) + T(3) * cu + T(4.5) * cu * cu - usq15;
+    const T deq = w * (m.drho + m.rho * (P - T(1)));
+    A += v[l] * w * P;
+    Bx += v[l] * w * (T(3) * cx + T(9) * cu * cx - T(3) * m.ux);
+    By += v[l] * w * (T(3) * cy + T(9) * cu * cy - T(3) * m.uy);
+    neq += v[l] * (d[l] - deq);
+  }
+  Bx *= m.rho;
+  By *= m.rho;
+  const T inv = T(1) / m.rho;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const T ex = T(cxq(k)) - m.ux, ey = T(cyq(k)) - m.uy;
+    T r = (T(1) - om) * v[k] + om * (A + (Bx * ex + By * ey) * inv);
+    if (seed) r += T(rh + (sx * double(ex) + sy * double(ey)) / double(m.rho));
+    o[k] = r;
+  }
+  return double(neq) * double(om) * double(om);
+}
+
+// One backward step over a tile of (blockDim.x * VX) x (blockDim.y * ry) sites (the
+// step kernel's tiling and XCD-aware numbering); adds the tile's sum of
+// v . dC/dtau to its own slot of tau_acc.
+template <typename T, int VX>
+__global__ void __launch_bounds__(512) k_adj_step(const T* __restrict__ g, const T* __restrict__ ain,
+                                                   T* __restrict__ aout, Seeds s, int has_seed,
+                                                   PopLayout lay, int nx, int ny, double omega,
+                                                   double* tau_acc, int tiles_x, int total,
+                                                   int per_xcd, int ry) {
+  __shared__ double sh[16];
+  const int b = blockIdx.x;
+  const int tile = (b & 7) * per_xcd + (b >> 3);
+  if (tile >= total) return;
+  const int tx = tile % tiles_x, ty = tile / tiles_x;
+  const int x0 = (tx * blockDim.x + threadIdx.x) * VX;
+  const int ybase = (ty * blockDim.y + threadIdx.y) * ry;
+  const T om = T(omega);
   double dtau = 0.0;
-  if (i < plane) {
-    const int x = static_cast<int>(i % nx), y = static_cast<int>(i / nx);
-    T d[9], v[9];
-    pull_sites<T>(g, lay, nx, ny, x, y, 1, d);      // f^t(x) (deviation)
-    pull_sites<T>(ain, lay, nx, ny, x, y, -1, v);   // a^{t+1}(x + c_l)
-    const size_t at = static_cast<size_t>(y) * lay.rs + x;
-    SiteMoments<T, false> m(d, T(0), T(0), T(0));
-    const T om = T(omega);
-    const T usq15 = T(1.5) * (m.ux * m.ux + m.uy * m.uy);
-    T A = T(0), Bx = T(0), By = T(0), neq = T(0);
+  if (x0 < nx) {
+    for (int k = 0; k < ry; ++k) {
+      const int y = ybase + k;
+      if (y >= ny) break;
+      const int yn = (y == 0) ? ny - 1 : y - 1;
+      const int yp = (y == ny - 1) ? 0 : y + 1;
+      T d[9][VX], v[9][VX], o[9][VX];
+      pull_all<T, VX>(g, lay.ps, lay.rs, nx, x0, y, yn, yp, d);        // f^t(x) - w
+      pull_all_rev<T, VX>(ain, lay.ps, lay.rs, nx, x0, y, yn, yp, v);  // a^{t+1}(x + c_l)
+      const size_t row = static_cast<size_t>(y) * nx + x0;
 #pragma unroll
-    for (int l = 0; l < 9; ++l) {
-      const T w = T(wq(l));
-      const T cx = T(cxq(l)), cy = T(cyq(l));
-      const T cu = cx * m.ux + cy * m.uy;
-      const T P = T(1) + T(3) * cu + T(4.5) * cu * cu - usq15;
-      const T deq = w * (m.drho + m.rho * (P - T(1)));
-      A += v[l] * w * P;
-      Bx += v[l] * w * (T(3) * cx + T(9) * cu * cx - T(3) * m.ux);
-      By += v[l] * w * (T(3) * cy + T(9) * cu * cy - T(3) * m.uy);
-      neq += v[l] * (d[l] - deq);
-    }
-    Bx *= m.rho;
-    By *= m.rho;
-    const T inv = T(1) / m.rho;
-    const double rh = (has_seed && s.rho) ? s.rho[i] : 0.0;
-    const double sx = has_seed ? s.ux[i] : 0.0, sy = has_seed ? s.uy[i] : 0.0;
+      for (int i = 0; i < VX; ++i) {
+        T di[9], vi[9], oi[9];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      const T ex = T(cxq(k)) - m.ux, ey = T(cyq(k)) - m.uy;
-      T o = (T(1) - om) * v[k] + om * (A + (Bx * ex + By * ey) * inv);
-      if (has_seed) o += T(rh + (sx * double(ex) + sy * double(ey)) / double(m.rho));
-      aout[k * lay.ps + at] = o;
+        for (int l = 0; l < 9; ++l) {
+          di[l] = d[l][i];
+          vi[l] = v[l][i];
+        }
+        const double rh = (has_seed && s.rho) ? s.rho[row + i] : 0.0;
+        const double sx = has_seed ? s.ux[row + i] : 0.0, sy = has_seed ? s.uy[row + i] : 0.0;
+        dtau += adjoint_site<T>(di, vi, om, has_seed != 0, rh, sx, sy, oi);
+#pragma unroll
+        for (int l = 0; l < 9; ++l) o[l][i] = oi[l];
+      }
+#pragma unroll
+      for (int l = 0; l < 9; ++l)
+        store_aligned<T, VX, true>(aout + l * lay.ps + static_cast<size_t>(y) * lay.rs + x0, o[l]);
     }
-    dtau = double(neq) * omega * omega;   // v . (f - f^eq) / tau^2
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) dtau += __shfl_xor(dtau, o, 64);
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = dtau;
+  const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+  if ((tid & 63) == 0) sh[tid >> 6] = dtau;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double b = 0.0;
-    for (int k = 0; k < kAT / 64; ++k) b += sh[k];
-    tau_acc[blockIdx.x] += b;
+  if (tid == 0) {
+    double acc = 0.0;
+    const int nw = (blockDim.x * blockDim.y + 63) / 64;
+    for (int w = 0; w < nw; ++w) acc += sh[w];
+    tau_acc[tile] += acc;
   }
 }
 
@@ -372,7 +407,8 @@ AdjWs carve_adj(const lbm_adjoint_config& c, void* base, size_t cap) {
   w.rhat = cv.take<double>(plane);
   w.w = cv.take<double>(static_cast<size_t>(kAdjFields) * plane);
   w.small = cv.take<double>(4096 + 64);
-  w.tau_acc = cv.take<double>(nblocks_sites(plane) + 64);
+  // one slot per tile of the launch shape; a tile holds >= 64 threads, so this bounds any shape
+  w.tau_acc = cv.take<double>(std::max<size_t>(plane / 16, static_cast<size_t>(c.ny)) + 1024);
   w.fill = cv.take<double>(plane);
   w.bal = carve_balance(cv, c.nx, c.ny);
   w.bytes = cv.used + 256;
@@ -405,15 +441,34 @@ int launch_adj_init(const void* g, void* adj, Seeds s, int nx, int ny, hipStream
   return LBM_OK;
 }
 
-template <typename T>
-int launch_adj_step(const void* g, const void* ain, void* aout, Seeds s, int has_seed, int nx,
-                    int ny, double omega, double* tau_acc, hipStream_t st) {
-  const size_t plane = static_cast<size_t>(nx) * ny;
-  hipLaunchKernelGGL(k_adj_step<T>, dim3(nblocks_sites(plane)), dim3(kAT), 0, st,
-                     static_cast<const T*>(g), static_cast<const T*>(ain), static_cast<T*>(aout),
-                     s, has_seed, pop_layout(kAdjLayout, nx, ny), nx, ny, omega, tau_acc);
+template <typename T, int VX>
+int launch_adj_step_t(const void* g, const void* ain, void* aout, Seeds s, int has_seed, int nx, int ny,
+                      double omega, double* tau_acc, const lbm_tile& t, hipStream_t st) {
+  const int tiles_x = (nx / VX + t.bx - 1) / t.bx;
+  const int tiles_y = (ny + t.by * t.ry - 1) / (t.by * t.ry);
+  const int total = tiles_x * tiles_y;
+  const int per_xcd = (total + 7) / 8;
+  hipLaunchKernelGGL((k_adj_step<T, VX>), dim3(per_xcd * 8), dim3(t.bx, t.by), 0, st,
+                     static_cast<const T*>(g), static_cast<const T*>(ain), static_cast<T*>(aout), s,
+                     has_seed, pop_layout(kAdjLayout, nx, ny), nx, ny, omega, tau_acc, tiles_x, total,
+                     per_xcd, t.ry);
   LBM_HIP(hipGetLastError());
   return LBM_OK;
+}
+
+template <typename T>
+int launch_adj_step(const void* g, const void* ain, void* aout, Seeds s, int has_seed, int nx, int ny,
+                    double omega, double* tau_acc, const lbm_tile& t, hipStream_t st) {
+  switch (t.vx) {
+    case 1: return launch_adj_step_t<T, 1>(g, ain, aout, s, has_seed, nx, ny, omega, tau_acc, t, st);
+    case 2: return launch_adj_step_t<T, 2>(g, ain, aout, s, has_seed, nx, ny, omega, tau_acc, t, st);
+    default: return launch_adj_step_t<T, 4>(g, ain, aout, s, has_seed, nx, ny, omega, tau_acc, t, st);
+  }
+}
+
+// number of tiles of a launch shape (slots of the tau accumulator)
+int tile_count(int nx, int ny, const lbm_tile& t) {
+  return ((nx / t.vx + t.bx - 1) / t.bx) * ((ny + t.by * t.ry - 1) / (t.by * t.ry));
 }
 
 template <typename T>
@@ -437,6 +492,9 @@ struct Runner {
   void* ckpt_state(int64_t k) const { return static_cast<char*>(w.ckpt) + k * state_bytes; }
 
   int step(const void* src, void* dst, double* hr, double* hx, double* hy) {
+    return step_on(s, src, dst, hr, hx, hy);
+  }
+  int step_on(hipStream_t st, const void* src, void* dst, double* hr, double* hx, double* hy) {
     StepParams p{};
     p.src = src;
     p.dst = dst;
@@ -450,7 +508,42 @@ struct Runner {
     p.rs = lay.rs;
     p.omega = 1.0 / c.tau;
     p.alpha = 0.0;
-    return launch_step(c.dtype, false, p, tile, s);
+    return launch_step(c.dtype, false, p, tile, st);
+  }
+};
+
+// Graphs captured on a private stream, destroyed with the cache.
+struct GraphCache {
+  hipStream_t cs = nullptr;
+  hipStream_t main = nullptr;   // replays go here; synchronised before the graphs are freed
+  hipGraphExec_t fwd = nullptr;
+  hipGraphExec_t bwd[2] = {nullptr, nullptr};
+  int init() {
+    LBM_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    return LBM_OK;
+  }
+  template <class F>
+  int capture(hipGraphExec_t* out, F&& body) {
+    hipGraph_t g = nullptr;
+    LBM_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    const int rc = body(cs);
+    hipError_t e = hipStreamEndCapture(cs, &g);
+    if (rc != LBM_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    return LBM_OK;
+  }
+  ~GraphCache() {
+    if (main) (void)hipStreamSynchronize(main);
+    if (fwd) (void)hipGraphExecDestroy(fwd);
+    for (auto& b : bwd)
+      if (b) (void)hipGraphExecDestroy(b);
+    if (cs) (void)hipStreamDestroy(cs);
   }
 };
 
@@ -486,7 +579,9 @@ int lbm_adjoint_run(const lbm_adjoint_config* cfg, void* ws, size_t ws_bytes, co
   R.s = static_cast<hipStream_t>(cfg->stream);
   R.plane = static_cast<size_t>(cfg->nx) * cfg->ny;
   R.state_bytes = 9 * R.plane * (cfg->dtype == LBM_F32 ? 4 : 8);
-  R.tile = default_tile(cfg->dtype, cfg->nx, cfg->ny);
+  // the step-kernel shape tuned for this grid if lbm_autotune has seen it, else the default
+  if (!tuned_tile(cfg->dtype, cfg->nx, cfg->ny, false, kAdjLayout, &R.tile))
+    R.tile = default_tile(cfg->dtype, cfg->nx, cfg->ny, kAdjLayout);
   const int nx = cfg->nx, ny = cfg->ny;
   const int64_t T = cfg->steps;
   const int K = cfg->ckpt_every;
@@ -499,20 +594,50 @@ int lbm_adjoint_run(const lbm_adjoint_config* cfg, void* ws, size_t ws_bytes, co
   if (int rc = launch_init(cfg->dtype, R.ckpt_state(0), pop_layout(kAdjLayout, nx, ny), R.w.fill,
                            ux0, uy0, nx, ny, s))
     return rc;
-  void* cur = R.w.adj[0];
-  void* nxt = R.w.adj[1];
-  LBM_HIP(hipMemcpyAsync(cur, R.ckpt_state(0), R.state_bytes, hipMemcpyDeviceToDevice, s));
-  for (int64_t t = 0; t < T; ++t) {
-    double* h[3] = {nullptr, nullptr, nullptr};
-    if (t == T - 2 || t == T - 1) {
-      const int lv = static_cast<int>(t - (T - 2));
-      for (int k = 0; k < 3; ++k) h[k] = R.w.mom[lv][k];
+  // Full segments without a recorded level replay captured graphs of K steps
+  // through the segment buffer (seg[0] -> seg[K]); the rest is launched directly.
+  const int64_t nseg = (T + K - 1) / K;
+  GraphCache gc;
+  gc.main = s;
+  if (int rc = gc.init()) return rc;
+  auto seg_len = [&](int64_t sg) { return std::min<int64_t>(sg * K + K, T) - sg * K; };
+  auto seg_plain = [&](int64_t sg) { return seg_len(sg) == K && sg * K + K <= T - 2; };
+  auto forward_segment = [&](int64_t sg, bool record) -> int {
+    const int64_t t0 = sg * K, len = seg_len(sg);
+    LBM_HIP(hipMemcpyAsync(R.seg_state(0), R.ckpt_state(sg), R.state_bytes, hipMemcpyDeviceToDevice, s));
+    if (seg_plain(sg)) {
+      if (!gc.fwd) {
+        if (int rc = gc.capture(&gc.fwd, [&](hipStream_t cs) -> int {
+              for (int k = 0; k < K; ++k)
+                if (int r2 = R.step_on(cs, R.seg_state(k), R.seg_state(k + 1), nullptr, nullptr, nullptr))
+                  return r2;
+              return LBM_OK;
+            }))
+          return rc;
+      }
+      LBM_HIP(hipGraphLaunch(gc.fwd, s));
+      return LBM_OK;
     }
-    if (int rc = R.step(cur, nxt, h[0], h[1], h[2])) return rc;
-    std::swap(cur, nxt);
-    if ((t + 1) % K == 0 && t + 1 < T)
-      LBM_HIP(hipMemcpyAsync(R.ckpt_state((t + 1) / K), cur, R.state_bytes, hipMemcpyDeviceToDevice, s));
+    for (int64_t k = 0; k < len; ++k) {
+      const int64_t t = t0 + k;
+      double* h[3] = {nullptr, nullptr, nullptr};
+      if (record && (t == T - 2 || t == T - 1)) {
+        const int lv = static_cast<int>(t - (T - 2));
+        for (int q = 0; q < 3; ++q) h[q] = R.w.mom[lv][q];
+      }
+      if (int rc = R.step(R.seg_state(static_cast<int>(k)), R.seg_state(static_cast<int>(k + 1)), h[0],
+                          h[1], h[2]))
+        return rc;
+    }
+    return LBM_OK;
+  };
+  for (int64_t sg = 0; sg < nseg; ++sg) {
+    if (int rc = forward_segment(sg, true)) return rc;
+    if (sg + 1 < nseg)
+      LBM_HIP(hipMemcpyAsync(R.ckpt_state(sg + 1), R.seg_state(static_cast<int>(seg_len(sg))),
+                             R.state_bytes, hipMemcpyDeviceToDevice, s));
   }
+  void* cur = R.seg_state(static_cast<int>(seg_len(nseg - 1)));   // g^T
   {
     MomentParams m{};
     m.pop = cur;
@@ -609,7 +734,7 @@ int lbm_adjoint_run(const lbm_adjoint_config* cfg, void* ws, size_t ws_bytes, co
   LBM_HIP(hipGetLastError());
 
   // ---- population adjoint, segment by segment from the last ----
-  const int nb = nblocks_sites(R.plane);
+  const int nb = tile_count(nx, ny, R.tile);
   hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, s, R.w.tau_acc, static_cast<size_t>(nb));
   LBM_HIP(hipGetLastError());
   const double omega = 1.0 / cfg->tau;
@@ -617,32 +742,55 @@ int lbm_adjoint_run(const lbm_adjoint_config* cfg, void* ws, size_t ws_bytes, co
   const Seeds s1{nullptr, R.w.w + S_UX1 * R.plane, R.w.w + S_UY1 * R.plane};
   const Seeds s2{nullptr, R.w.w + S_UX2 * R.plane, R.w.w + S_UY2 * R.plane};
   const bool f32 = cfg->dtype == LBM_F32;
-  void* ain = R.w.adj[0];
-  void* aout = R.w.adj[1];
-  const int64_t nseg = (T + K - 1) / K;
+  int par = 0;                       // ain = adj[par], aout = adj[par ^ 1]
   for (int64_t sg = nseg - 1; sg >= 0; --sg) {
     const int64_t t0 = sg * K;
-    const int64_t t1 = std::min<int64_t>(t0 + K, T);
-    LBM_HIP(hipMemcpyAsync(R.seg_state(0), R.ckpt_state(sg), R.state_bytes, hipMemcpyDeviceToDevice, s));
-    for (int64_t k = 0; k < t1 - t0; ++k)
-      if (int rc = R.step(R.seg_state(static_cast<int>(k)), R.seg_state(static_cast<int>(k + 1)),
-                          nullptr, nullptr, nullptr))
-        return rc;
+    const int64_t t1 = t0 + seg_len(sg);
+    // the last segment's states are still in the buffer from the forward pass
+    if (sg != nseg - 1)
+      if (int rc = forward_segment(sg, false)) return rc;
     if (sg == nseg - 1) {
-      const int rc = f32 ? launch_adj_init<float>(R.seg_state(static_cast<int>(t1 - t0)), ain, sT, nx, ny, s)
-                         : launch_adj_init<double>(R.seg_state(static_cast<int>(t1 - t0)), ain, sT, nx, ny, s);
+      const void* gT = R.seg_state(static_cast<int>(t1 - t0));
+      const int rc = f32 ? launch_adj_init<float>(gT, R.w.adj[par], sT, nx, ny, s)
+                         : launch_adj_init<double>(gT, R.w.adj[par], sT, nx, ny, s);
       if (rc) return rc;
+    }
+    const bool seeded = t1 >= T - 1;   // holds t = T-1 or T-2
+    if (seg_len(sg) == K && !seeded) {
+      hipGraphExec_t& gb = gc.bwd[par];
+      if (!gb) {
+        const int p0 = par;
+        if (int rc = gc.capture(&gb, [&](hipStream_t cs) -> int {
+              int pp = p0;
+              for (int k = K - 1; k >= 0; --k) {
+                const int r2 = f32 ? launch_adj_step<float>(R.seg_state(k), R.w.adj[pp], R.w.adj[pp ^ 1], s2, 0,
+                                                            nx, ny, omega, R.w.tau_acc, R.tile, cs)
+                                   : launch_adj_step<double>(R.seg_state(k), R.w.adj[pp], R.w.adj[pp ^ 1], s2,
+                                                             0, nx, ny, omega, R.w.tau_acc, R.tile, cs);
+                if (r2) return r2;
+                pp ^= 1;
+              }
+              return LBM_OK;
+            }))
+          return rc;
+      }
+      LBM_HIP(hipGraphLaunch(gb, s));
+      par ^= (K & 1);
+      continue;
     }
     for (int64_t t = t1 - 1; t >= t0; --t) {
       const bool seed = (t == T - 1) || (t == T - 2);
       const Seeds sd = (t == T - 1) ? s1 : s2;
       const void* gt = R.seg_state(static_cast<int>(t - t0));
-      const int rc = f32 ? launch_adj_step<float>(gt, ain, aout, sd, seed ? 1 : 0, nx, ny, omega, R.w.tau_acc, s)
-                         : launch_adj_step<double>(gt, ain, aout, sd, seed ? 1 : 0, nx, ny, omega, R.w.tau_acc, s);
+      const int rc = f32 ? launch_adj_step<float>(gt, R.w.adj[par], R.w.adj[par ^ 1], sd, seed ? 1 : 0, nx, ny,
+                                                  omega, R.w.tau_acc, R.tile, s)
+                         : launch_adj_step<double>(gt, R.w.adj[par], R.w.adj[par ^ 1], sd, seed ? 1 : 0, nx,
+                                                   ny, omega, R.w.tau_acc, R.tile, s);
       if (rc) return rc;
-      std::swap(ain, aout);
+      par ^= 1;
     }
   }
+  void* ain = R.w.adj[par];
   // ain now holds dJ/df^0
   if (grad_ux0) {
     const int rc = f32 ? launch_adj_u0<float>(ain, ux0, uy0, nx, ny, grad_ux0, grad_uy0, s)

@@ -164,6 +164,21 @@ void tune_cache_store() {
 
 bool is_forced(const lbm_ctx_s* c) { return c->cfg.has_force || c->cfg.drag_alpha > 0.0; }
 
+}  // namespace
+
+namespace lbm {
+bool tuned_tile(int dtype, int nx, int ny, bool force, int layout, lbm_tile* out) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  tune_cache_load();
+  auto it = g_tune.find(tune_key(dtype, nx, ny, force, layout));
+  if (it == g_tune.end()) return false;
+  *out = it->second;
+  return true;
+}
+}  // namespace lbm
+
+namespace {
+
 int enqueue_step(lbm_ctx_s* c, int src, hipStream_t s, double* hr, double* hx, double* hy) {
   StepParams p{};
   p.src = c->pop[src];
@@ -356,7 +371,7 @@ int lbm_init(const lbm_config* cfg, void* ws, size_t ws_bytes, const double* rho
     std::lock_guard<std::mutex> g(g_tune_mu);
     tune_cache_load();
     auto it = g_tune.find(tune_key(cfg->dtype, cfg->nx, cfg->ny, is_forced(c), cfg->layout));
-    c->tile = it != g_tune.end() ? it->second : default_tile(cfg->dtype, cfg->nx, cfg->ny);
+    c->tile = it != g_tune.end() ? it->second : default_tile(cfg->dtype, cfg->nx, cfg->ny, cfg->layout);
   }
   int rc = launch_init(cfg->dtype, c->pop[0], c->lay, rho0, ux0, uy0, cfg->nx, cfg->ny, c->stream);
   if (rc == LBM_OK && cfg->has_force) {

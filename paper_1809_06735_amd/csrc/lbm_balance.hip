@@ -43,6 +43,11 @@ struct PassArgs {
   double* aux;
 };
 
+// Weights of Eq. 18 per offset m = 1..4 (the difference g(i+m) - g(i-m) is
+// multiplied by kFd8[m-1]); each stencil below accumulates over m in a loop
+// that is not unrolled, so that only one offset's loads are live at a time.
+__constant__ double kFd8[4] = {4.0 / 5.0, -1.0 / 5.0, (4.0 / 21.0) / 5.0, -(1.0 / 56.0) / 5.0};
+
 __global__ void __launch_bounds__(256) k_bal_a(PassArgs a) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
@@ -50,31 +55,42 @@ __global__ void __launch_bounds__(256) k_bal_a(PassArgs a) {
   const int nx = a.nx, ny = a.ny;
   const size_t plane = static_cast<size_t>(nx) * ny;
   const size_t i = static_cast<size_t>(y) * nx + x;
+  // d_x u_y and d_y u_x at the three levels; d_x u_x, d_y u_y, grad rho at level n
+  double dxuy[3] = {0.0, 0.0, 0.0}, dyux[3] = {0.0, 0.0, 0.0};
+  double dxux = 0.0, dyuy = 0.0, dxr = 0.0, dyr = 0.0;
+#pragma unroll 1
+  for (int m = 1; m <= 4; ++m) {
+    const double c = kFd8[m - 1];
+    const size_t xp = static_cast<size_t>(y) * nx + wrap_add(x, m, nx);
+    const size_t xm = static_cast<size_t>(y) * nx + wrap_add(x, -m, nx);
+    const size_t yp = static_cast<size_t>(wrap_add(y, m, ny)) * nx + x;
+    const size_t ym = static_cast<size_t>(wrap_add(y, -m, ny)) * nx + x;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      dxuy[k] += c * (a.uy[k][xp] - a.uy[k][xm]);
+      dyux[k] += c * (a.ux[k][yp] - a.ux[k][ym]);
+    }
+    dxux += c * (a.ux[2][xp] - a.ux[2][xm]);
+    dyuy += c * (a.uy[2][yp] - a.uy[2][ym]);
+    dxr += c * (a.rho[2][xp] - a.rho[2][xm]);
+    dyr += c * (a.rho[2][yp] - a.rho[2][ym]);
+  }
   double om[3], en[3], ens[3];
-  double dxux = 0, dyux = 0, dxuy = 0, dyuy = 0;
+#pragma unroll
   for (int k = 0; k < 3; ++k) {
-    F1 gx{a.ux[k], nx}, gy{a.uy[k], nx};
-    const double dy_ux = fd8_y(gx, x, y, ny);
-    const double dx_uy = fd8_x(gy, x, y, nx);
-    om[k] = dx_uy - dy_ux;
+    om[k] = dxuy[k] - dyux[k];
     ens[k] = 0.5 * om[k] * om[k];
     const double vx = a.ux[k][i], vy = a.uy[k][i];
     en[k] = 0.5 * a.rho[k][i] * (vx * vx + vy * vy);
-    if (k == 2) {
-      dxux = fd8_x(gx, x, y, nx);
-      dyux = dy_ux;
-      dxuy = dx_uy;
-      dyuy = fd8_y(gy, x, y, ny);
-    }
   }
+  const double dyux_n = dyux[2], dxuy_n = dxuy[2];
   const double r = a.rho[2][i], vx = a.ux[2][i], vy = a.uy[2][i];
-  F1 gr{a.rho[2], nx};
-  const double dxp = fd8_x(gr, x, y, nx) / 3.0;
-  const double dyp = fd8_y(gr, x, y, ny) / 3.0;
+  const double dxp = dxr / 3.0;
+  const double dyp = dyr / 3.0;
   const double nu = a.nu;
   const double sxx = 2.0 * nu * r * dxux;
   const double syy = 2.0 * nu * r * dyuy;
-  const double sxy = nu * r * (dxuy + dyux);
+  const double sxy = nu * r * (dxuy_n + dyux_n);
   double fxv = 0.0, fyv = 0.0;
   if (a.fx) {
     fxv = a.fx[i];
@@ -84,7 +100,7 @@ __global__ void __launch_bounds__(256) k_bal_a(PassArgs a) {
   t[LBM_T_LHS_E * plane + i] = (3.0 * en[2] - 4.0 * en[1] + en[0]) / 2.0;
   t[LBM_T_E2 * plane + i] = -(vx * dxp + vy * dyp);
   t[LBM_T_E3 * plane + i] = vx * fxv + vy * fyv;
-  t[LBM_T_E4 * plane + i] = -(sxx * dxux + sxy * dyux + sxy * dxuy + syy * dyuy);
+  t[LBM_T_E4 * plane + i] = -(sxx * dxux + sxy * dyux_n + sxy * dxuy_n + syy * dyuy);
   t[LBM_T_LHS_Z * plane + i] = (3.0 * ens[2] - 4.0 * ens[1] + ens[0]) / 2.0;
   t[LBM_T_Z2 * plane + i] = -ens[2] * (dxux + dyuy);
   t[LBM_T_USQ * plane + i] = vx * vx + vy * vy;
@@ -114,24 +130,50 @@ __global__ void __launch_bounds__(256) k_bal_b(PassArgs a) {
   const double* sxx = ax + A_SXX * plane;
   const double* syy = ax + A_SYY * plane;
   const double* sxy = ax + A_SXY * plane;
-
-  const double e1 = -(fd8_x(F2{E, ux, nx}, x, y, nx) + fd8_y(F2{E, uy, nx}, x, y, ny));
-  const double e5 = fd8_x(FSum2{ux, sxx, uy, sxy, nx}, x, y, nx) +
-                    fd8_y(FSum2{ux, sxy, uy, syy, nx}, x, y, ny);
-  const double z1 = -(fd8_x(F2{Om, ux, nx}, x, y, nx) + fd8_y(F2{Om, uy, nx}, x, y, ny));
+  const bool forced = a.fx != nullptr;
+  // x-derivatives: E u_x, u.sigma_x, Omega u_x, sigma_xx, sigma_xy, omega, F_y/rho
+  // y-derivatives: E u_y, u.sigma_y, Omega u_y, sigma_xy, sigma_yy, omega, F_x/rho
+  double dEx = 0, dEy = 0, dSx = 0, dSy = 0, dOx = 0, dOy = 0;
+  double dxsxx = 0, dysxy = 0, dxsxy = 0, dysyy = 0, dxw = 0, dyw = 0, dxf = 0, dyf = 0;
+#pragma unroll 1
+  for (int m = 1; m <= 4; ++m) {
+    const double c = kFd8[m - 1];
+    const size_t xp = static_cast<size_t>(y) * nx + wrap_add(x, m, nx);
+    const size_t xm = static_cast<size_t>(y) * nx + wrap_add(x, -m, nx);
+    const size_t yp = static_cast<size_t>(wrap_add(y, m, ny)) * nx + x;
+    const size_t ym = static_cast<size_t>(wrap_add(y, -m, ny)) * nx + x;
+    {
+      const double uxp = ux[xp], uxm = ux[xm], uyp = uy[xp], uym = uy[xm];
+      const double sxxp = sxx[xp], sxxm = sxx[xm], sxyp = sxy[xp], sxym = sxy[xm];
+      dEx += c * (E[xp] * uxp - E[xm] * uxm);
+      dSx += c * ((uxp * sxxp + uyp * sxyp) - (uxm * sxxm + uym * sxym));
+      dOx += c * (Om[xp] * uxp - Om[xm] * uxm);
+      dxsxx += c * (sxxp - sxxm);
+      dxsxy += c * (sxyp - sxym);
+      dxw += c * (W[xp] - W[xm]);
+      if (forced) dxf += c * (a.fy[xp] / rho[xp] - a.fy[xm] / rho[xm]);
+    }
+    {
+      const double uxp = ux[yp], uxm = ux[ym], uyp = uy[yp], uym = uy[ym];
+      const double sxyp = sxy[yp], sxym = sxy[ym], syyp = syy[yp], syym = syy[ym];
+      dEy += c * (E[yp] * uyp - E[ym] * uym);
+      dSy += c * ((uxp * sxyp + uyp * syyp) - (uxm * sxym + uym * syym));
+      dOy += c * (Om[yp] * uyp - Om[ym] * uym);
+      dysxy += c * (sxyp - sxym);
+      dysyy += c * (syyp - syym);
+      dyw += c * (W[yp] - W[ym]);
+      if (forced) dyf += c * (a.fx[yp] / rho[yp] - a.fx[ym] / rho[ym]);
+    }
+  }
   const double r = rho[i];
-  const double hx = (fd8_x(F1{sxx, nx}, x, y, nx) + fd8_y(F1{sxy, nx}, x, y, ny)) / r;
-  const double hy = (fd8_x(F1{sxy, nx}, x, y, nx) + fd8_y(F1{syy, nx}, x, y, ny)) / r;
-  const double dxw = fd8_x(F1{W, nx}, x, y, nx);
-  const double dyw = fd8_y(F1{W, nx}, x, y, ny);
+  const double hx = (dxsxx + dysxy) / r;
+  const double hy = (dxsxy + dysyy) / r;
   const double w = W[i];
-  double z3 = 0.0;
-  if (a.fx) z3 = w * (fd8_x(FDiv{a.fy, rho, nx}, x, y, nx) - fd8_y(FDiv{a.fx, rho, nx}, x, y, ny));
   double* t = a.terms;
-  t[LBM_T_E1 * plane + i] = e1;
-  t[LBM_T_E5 * plane + i] = e5;
-  t[LBM_T_Z1 * plane + i] = z1;
-  t[LBM_T_Z3 * plane + i] = z3;
+  t[LBM_T_E1 * plane + i] = -(dEx + dEy);
+  t[LBM_T_E5 * plane + i] = dSx + dSy;
+  t[LBM_T_Z1 * plane + i] = -(dOx + dOy);
+  t[LBM_T_Z3 * plane + i] = forced ? w * (dxf - dyf) : 0.0;
   t[LBM_T_Z4 * plane + i] = hx * dyw - hy * dxw;
   a.aux[A_HX * plane + i] = hx;
   a.aux[A_HY * plane + i] = hy;
@@ -548,7 +590,7 @@ __global__ void __launch_bounds__(256) k_windows_fused(SatView v, SideList sides
       const bool qy = y1 > ny, qx = x1 > nx;
       const int ym = qy ? y1 - ny : y1, xm = qx ? x1 - nx : x1;
       double m[NT];
-#pragma unroll
+#pragma unroll 1
       for (int f = 0; f < NT; ++f) {
         const double* p = v.P + f * v.splane;
         const double q00 = p[y0 * s + x0];

@@ -83,8 +83,11 @@ int launch_init(int dtype, void* pop, PopLayout lay, const double* rho0, const d
                 const double* uy0, int nx, int ny, hipStream_t s);
 int launch_step(int dtype, bool force, const StepParams& p, const lbm_tile& t, hipStream_t s);
 bool tile_ok(const lbm_tile& t, int dtype, int nx, int ny);
-lbm_tile default_tile(int dtype, int nx, int ny);
+lbm_tile default_tile(int dtype, int nx, int ny, int layout);
 int tile_candidates(int dtype, int nx, int ny, lbm_tile* out, int cap);
+// Step-kernel shape chosen by lbm_autotune for this grid (process table or the
+// LBM_TUNE_CACHE file), if any.
+bool tuned_tile(int dtype, int nx, int ny, bool force, int layout, lbm_tile* out);
 
 // Moments of the populations at their time: writes rho, ux, uy (out_dtype, any
 // may be null), optional FP64 copies and total force, and per-block partial

@@ -168,5 +168,28 @@ __device__ __forceinline__ void pull_all(const T* __restrict__ src, size_t ps, s
   pull_plane<8>(src, ps, rs, nx, x0, y, yn, yp, d);
 }
 
+// The transpose of the pull: d_l = a_l(x + c_l) for the VX sites (x0.., y).
+template <int L, typename T, int VX>
+__device__ __forceinline__ void pull_plane_rev(const T* __restrict__ src, size_t ps, size_t rs, int nx,
+                                               int x0, int y, int yn, int yp, T (&d)[9][VX]) {
+  constexpr int cy = cyq(L);
+  const int ys = cy == 1 ? yp : (cy == -1 ? yn : y);
+  pull_row<T, VX, -cxq(L)>(src + L * ps + static_cast<size_t>(ys) * rs, x0, nx, d[L]);
+}
+
+template <typename T, int VX>
+__device__ __forceinline__ void pull_all_rev(const T* __restrict__ src, size_t ps, size_t rs, int nx,
+                                             int x0, int y, int yn, int yp, T (&d)[9][VX]) {
+  pull_plane_rev<0>(src, ps, rs, nx, x0, y, yn, yp, d);
+  pull_plane_rev<1>(src, ps, rs, nx, x0, y, yn, yp, d);
+  pull_plane_rev<2>(src, ps, rs, nx, x0, y, yn, yp, d);
+  pull_plane_rev<3>(src, ps, rs, nx, x0, y, yn, yp, d);
+  pull_plane_rev<4>(src, ps, rs, nx, x0, y, yn, yp, d);
+  pull_plane_rev<5>(src, ps, rs, nx, x0, y, yn, yp, d);
+  pull_plane_rev<6>(src, ps, rs, nx, x0, y, yn, yp, d);
+  pull_plane_rev<7>(src, ps, rs, nx, x0, y, yn, yp, d);
+  pull_plane_rev<8>(src, ps, rs, nx, x0, y, yn, yp, d);
+}
+
 }  // namespace step_detail
 }  // namespace lbm

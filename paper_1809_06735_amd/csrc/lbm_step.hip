@@ -314,8 +314,20 @@ bool tile_ok(const lbm_tile& t, int dtype, int nx, int ny) {
   return true;
 }
 
-lbm_tile default_tile(int dtype, int nx, int ny) {
+lbm_tile default_tile(int dtype, int nx, int ny, int layout) {
   lbm_tile t{};
+  if (layout == LBM_LAYOUT_ROWS) {
+    // measured best on MI355X for the row layout: one site per thread, wide
+    // workgroups along x, non-temporal stores
+    t.vx = 1;
+    int bx = 64;
+    while (bx < 512 && bx * 2 <= nx) bx *= 2;
+    t.bx = bx;
+    t.by = bx >= 256 ? 1 : 256 / bx;
+    t.ry = 1;
+    t.nt = 1;
+    return t;
+  }
   t.vx = (dtype == LBM_F32) ? 4 : 2;
   while (t.vx > 1 && nx % t.vx != 0) t.vx >>= 1;
   int bx = 64;
