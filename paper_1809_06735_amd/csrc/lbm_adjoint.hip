@@ -579,8 +579,10 @@ int lbm_adjoint_run(const lbm_adjoint_config* cfg, void* ws, size_t ws_bytes, co
   R.s = static_cast<hipStream_t>(cfg->stream);
   R.plane = static_cast<size_t>(cfg->nx) * cfg->ny;
   R.state_bytes = 9 * R.plane * (cfg->dtype == LBM_F32 ? 4 : 8);
-  // the step-kernel shape tuned for this grid if lbm_autotune has seen it, else the default
-  if (!tuned_tile(cfg->dtype, cfg->nx, cfg->ny, false, kAdjLayout, &R.tile))
+  // the single-step shape tuned for this grid if lbm_autotune has seen it, else the default
+  // (the segments keep every intermediate state, so each launch advances one step)
+  if (!tuned_tile(cfg->dtype, cfg->nx, cfg->ny, false, kAdjLayout, &R.tile) ||
+      steps_per_launch(R.tile) != 1)
     R.tile = default_tile(cfg->dtype, cfg->nx, cfg->ny, kAdjLayout);
   const int nx = cfg->nx, ny = cfg->ny;
   const int64_t T = cfg->steps;

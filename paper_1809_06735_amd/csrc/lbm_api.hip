@@ -72,7 +72,8 @@ struct lbm_ctx_s {
   double* scalars_dev = nullptr;
   BalanceWs bal{};
   int64_t t = 0;
-  lbm_tile tile{};
+  lbm_tile tile{};   // shape of the bulk of the steps (one or two steps per launch)
+  lbm_tile tile1{};  // single-step shape for history-recording and odd steps
   int graph_chunk = 64;
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   bool timing = false;
@@ -143,8 +144,8 @@ void tune_cache_load() {
   while (std::fgets(line, sizeof(line), f)) {
     int dt, nx, ny, fo, lay;
     lbm_tile t;
-    if (std::sscanf(line, "step dtype=%d nx=%d ny=%d force=%d layout=%d : %d %d %d %d %d", &dt, &nx,
-                    &ny, &fo, &lay, &t.bx, &t.by, &t.vx, &t.ry, &t.nt) == 10 &&
+    if (std::sscanf(line, "step dtype=%d nx=%d ny=%d force=%d layout=%d : %d %d %d %d %d %d %d", &dt,
+                    &nx, &ny, &fo, &lay, &t.bx, &t.by, &t.vx, &t.ry, &t.nt, &t.fuse, &t.pf) == 12 &&
         tile_ok(t, dt, nx, ny))
       g_tune[tune_key(dt, nx, ny, fo != 0, lay)] = t;
   }
@@ -157,8 +158,8 @@ void tune_cache_store() {
   FILE* f = std::fopen(path, "w");
   if (!f) return;
   for (auto& kv : g_tune)
-    std::fprintf(f, "%s : %d %d %d %d %d\n", kv.first.c_str(), kv.second.bx, kv.second.by,
-                 kv.second.vx, kv.second.ry, kv.second.nt);
+    std::fprintf(f, "%s : %d %d %d %d %d %d %d\n", kv.first.c_str(), kv.second.bx, kv.second.by,
+                 kv.second.vx, kv.second.ry, kv.second.nt, kv.second.fuse, kv.second.pf);
   std::fclose(f);
 }
 
@@ -179,7 +180,10 @@ bool tuned_tile(int dtype, int nx, int ny, bool force, int layout, lbm_tile* out
 
 namespace {
 
-int enqueue_step(lbm_ctx_s* c, int src, hipStream_t s, double* hr, double* hx, double* hy) {
+// One launch: the bulk shape (c->tile, one or two steps) or, with `single`
+// or a moment record, the single-step shape.
+int enqueue_step(lbm_ctx_s* c, int src, hipStream_t s, double* hr, double* hx, double* hy,
+                 bool single = false) {
   StepParams p{};
   p.src = c->pop[src];
   p.dst = c->pop[1 - src];
@@ -194,7 +198,14 @@ int enqueue_step(lbm_ctx_s* c, int src, hipStream_t s, double* hr, double* hx, d
   p.rs = c->lay.rs;
   p.omega = 1.0 / c->cfg.tau;
   p.alpha = c->cfg.drag_alpha;
-  return launch_step(c->cfg.dtype, is_forced(c), p, c->tile, s);
+  const lbm_tile& t = (single || hr) ? c->tile1 : c->tile;
+  return launch_step(c->cfg.dtype, is_forced(c), p, t, s);
+}
+
+// Single-step shape to pair with a bulk shape.
+lbm_tile single_for(const lbm_ctx_s* c, const lbm_tile& bulk) {
+  if (steps_per_launch(bulk) == 1) return bulk;
+  return default_tile(c->cfg.dtype, c->cfg.nx, c->cfg.ny, c->cfg.layout);
 }
 
 void drop_graphs(lbm_ctx_s* c) {
@@ -372,6 +383,7 @@ int lbm_init(const lbm_config* cfg, void* ws, size_t ws_bytes, const double* rho
     tune_cache_load();
     auto it = g_tune.find(tune_key(cfg->dtype, cfg->nx, cfg->ny, is_forced(c), cfg->layout));
     c->tile = it != g_tune.end() ? it->second : default_tile(cfg->dtype, cfg->nx, cfg->ny, cfg->layout);
+    c->tile1 = single_for(c, c->tile);
   }
   int rc = launch_init(cfg->dtype, c->pop[0], c->lay, rho0, ux0, uy0, cfg->nx, cfg->ny, c->stream);
   if (rc == LBM_OK && cfg->has_force) {
@@ -391,25 +403,38 @@ int lbm_step(lbm_ctx c, int64_t n) {
   if (n < 0) return fail(LBM_E_INVALID, "n must be >= 0");
   if (n == 0) return LBM_OK;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (c->timing) {
+  const int64_t nhist = n < 2 ? n : 2;
+  const int64_t plain = n - nhist;
+  const int spl = steps_per_launch(c->tile);
+  const int64_t bulk = plain / spl;  // launches of the bulk shape
+  if (c->timing && bulk > 0) {
     e0 = get_event(c);
     e1 = get_event(c);
     if (!e0 || !e1) return fail(LBM_E_HIP, "hipEventCreate failed");
     LBM_HIP(hipEventRecord(e0, c->stream));
   }
-  const int64_t nhist = n < 2 ? n : 2;
-  int64_t plain = n - nhist;
-  if (c->graph_chunk > 0 && plain >= c->graph_chunk) {
-    while (plain >= c->graph_chunk) {
+  int64_t left = bulk;
+  if (c->graph_chunk > 0) {
+    while (left >= c->graph_chunk) {
       if (!c->gexec[c->cur])
         if (int rc = build_graph(c, c->cur)) return rc;
       LBM_HIP(hipGraphLaunch(c->gexec[c->cur], c->stream));
-      plain -= c->graph_chunk;
-      c->t += c->graph_chunk;  // chunk is even: the buffer parity is unchanged
+      left -= c->graph_chunk;
+      c->t += static_cast<int64_t>(c->graph_chunk) * spl;  // chunk is even: parity unchanged
     }
   }
-  for (int64_t i = 0; i < plain; ++i) {
+  for (; left > 0; --left) {
     if (int rc = enqueue_step(c, c->cur, c->stream, nullptr, nullptr, nullptr)) return rc;
+    c->cur ^= 1;
+    c->t += spl;
+  }
+  if (c->timing && bulk > 0) {
+    LBM_HIP(hipEventRecord(e1, c->stream));
+    c->ev_pending.emplace_back(e0, e1);
+    c->pending_launches += bulk;
+  }
+  for (int64_t i = bulk * spl; i < plain; ++i) {
+    if (int rc = enqueue_step(c, c->cur, c->stream, nullptr, nullptr, nullptr, true)) return rc;
     c->cur ^= 1;
     c->t += 1;
   }
@@ -421,11 +446,6 @@ int lbm_step(lbm_ctx c, int64_t n) {
     c->hist_t[slot] = c->t;
     c->cur ^= 1;
     c->t += 1;
-  }
-  if (c->timing) {
-    LBM_HIP(hipEventRecord(e1, c->stream));
-    c->ev_pending.emplace_back(e0, e1);
-    c->pending_launches += n;
   }
   return LBM_OK;
 }
@@ -584,6 +604,7 @@ int lbm_set_tile(lbm_ctx c, const lbm_tile* tile) {
     return fail(LBM_E_INVALID, "tile (%d,%d,vx %d,ry %d,nt %d) not valid for %d x %d", tile->bx,
                 tile->by, tile->vx, tile->ry, tile->nt, c->cfg.nx, c->cfg.ny);
   c->tile = *tile;
+  c->tile1 = single_for(c, c->tile);
   drop_graphs(c);
   return LBM_OK;
 }
@@ -604,8 +625,8 @@ int lbm_autotune(lbm_ctx c, int32_t trial_steps, lbm_tile* chosen) {
   hipEvent_t e0, e1;
   LBM_HIP(hipEventCreate(&e0));
   LBM_HIP(hipEventCreate(&e1));
-  float best = 1e30f;
-  lbm_tile best_t = saved;
+  float best = 1e30f, best1 = 1e30f;  // milliseconds per step: any shape, single-step shapes
+  lbm_tile best_t = saved, best_t1 = c->tile1;
   int rc = LBM_OK;
   for (int i = 0; i < n && i < 512 && rc == LBM_OK; ++i) {
     c->tile = cand[i];
@@ -625,14 +646,20 @@ int lbm_autotune(lbm_ctx c, int32_t trial_steps, lbm_tile* chosen) {
     }
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, e0, e1);
+    ms /= static_cast<float>(steps_per_launch(cand[i]));
     if (ms < best) {
       best = ms;
       best_t = cand[i];
+    }
+    if (steps_per_launch(cand[i]) == 1 && ms < best1) {
+      best1 = ms;
+      best_t1 = cand[i];
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   c->tile = rc == LBM_OK ? best_t : saved;
+  c->tile1 = steps_per_launch(c->tile) == 1 ? c->tile : best_t1;
   drop_graphs(c);
   if (rc) return rc;
   {

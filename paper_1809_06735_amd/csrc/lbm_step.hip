@@ -304,8 +304,9 @@ int dispatch_step(bool force, const StepParams& p, const lbm_tile& t, hipStream_
 }  // namespace
 
 bool tile_ok(const lbm_tile& t, int dtype, int nx, int ny) {
-  (void)dtype;
   (void)ny;
+  if (t.fuse == 2) return fused_tile_ok(t, dtype);
+  if ((t.fuse != 0 && t.fuse != 1) || t.pf != 0) return false;
   const int threads = t.bx * t.by;
   if (t.bx < 1 || t.by < 1 || t.ry < 1 || threads > 1024 || threads % 64 != 0) return false;
   if (t.vx != 1 && t.vx != 2 && t.vx != 4) return false;
@@ -316,6 +317,7 @@ bool tile_ok(const lbm_tile& t, int dtype, int nx, int ny) {
 
 lbm_tile default_tile(int dtype, int nx, int ny, int layout) {
   lbm_tile t{};
+  t.fuse = 1;
   if (layout == LBM_LAYOUT_ROWS) {
     // measured best on MI355X for the row layout: one site per thread, wide
     // workgroups along x, non-temporal stores
@@ -353,7 +355,7 @@ int tile_candidates(int dtype, int nx, int ny, lbm_tile* out, int cap) {
         for (int ry : rys) {
           if (by * ry > ny) continue;
           for (int nt = 0; nt <= 1; ++nt) {
-            lbm_tile t{bx, by, vx, ry, nt};
+            lbm_tile t{bx, by, vx, ry, nt, 1, 0};
             if (!tile_ok(t, dtype, nx, ny)) continue;
             if (n < cap) out[n] = t;
             ++n;
@@ -362,10 +364,27 @@ int tile_candidates(int dtype, int nx, int ny, lbm_tile* out, int cap) {
       }
     }
   }
+  // two steps per launch: strip width W, band height H
+  const int ws[4] = {128, 256, 512, 960};
+  const int hs[4] = {16, 32, 64, 128};
+  for (int w : ws) {
+    if (w > nx + 64 && w > 128) continue;
+    for (int h : hs) {
+      if (h > ny && h > 16) continue;
+      for (int nt = 0; nt <= 1; ++nt)
+        for (int pf = 0; pf <= 1; ++pf) {
+          lbm_tile t{w, 1, 1, h, nt, 2, pf};
+          if (!tile_ok(t, dtype, nx, ny)) continue;
+          if (n < cap) out[n] = t;
+          ++n;
+        }
+    }
+  }
   return n;
 }
 
 int launch_step(int dtype, bool force, const StepParams& p, const lbm_tile& t, hipStream_t s) {
+  if (t.fuse == 2) return launch_step_fused2(dtype, force, p, t, s);
   if (dtype == LBM_F32) return dispatch_step<float>(force, p, t, s);
   return dispatch_step<double>(force, p, t, s);
 }

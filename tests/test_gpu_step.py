@@ -148,6 +148,10 @@ def test_ragged_grids_all_launch_shapes_agree(gpu_lib, shape):
                 for ry in (1, 3):
                     for nt in (0, 1):
                         cand.append((bx, by, vx_, ry, nt))
+        # two steps per launch: strip width, band height, nt, prefetch
+        for (w, h) in ((64, 1), (64, 5), (128, 16), (64, 64)):
+            for nt, pf in ((0, 0), (1, 1)):
+                cand.append((w, 1, 1, h, nt, 2, pf))
         ref_state = None
         checked = 0
         for tile in cand:
@@ -177,6 +181,54 @@ def test_graph_replay_equals_direct_launches(gpu_lib):
     b.step(1)
     b.step(300)
     assert torch.equal(a.save(), b.save())
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("layout", ["rows", "planes"])
+def test_two_step_kernel_equals_single_steps(gpu_lib, dtype, layout):
+    """Two steps per launch (temporal blocking through LDS) give bit-identical states to
+    single-step launches: forced and unforced, ragged strips and bands, even and odd step
+    counts, direct launches and graph replay."""
+    ny, nx = 75, 200
+    rng = np.random.default_rng(21)
+    rho = 1.0 + 0.01 * rng.standard_normal((ny, nx))
+    ux = 0.04 * rng.standard_normal((ny, nx))
+    uy = 0.04 * rng.standard_normal((ny, nx))
+    fx = 2e-5 * rng.standard_normal((ny, nx))
+    fy = 2e-5 * rng.standard_normal((ny, nx))
+    for forced in (False, True):
+        kw = dict(fx=fx, fy=fy, alpha=2e-3) if forced else {}
+        base = Sim(rho, ux, uy, 0.53, dtype=dtype, layout=layout, **kw)
+        base.set_tile(64, 1, 1, 1, 0)
+        base.set_graph(0)
+        base.step(9)
+        s9 = base.save().clone()
+        base.step(52)
+        s61 = base.save().clone()
+        base.close()
+        for (w, h, nt, pf, chunk) in ((64, 16, 0, 0, 0), (128, 7, 1, 1, 0), (256, 75, 0, 1, 4),
+                                      (64, 1, 1, 0, 2), (512, 32, 1, 1, 0)):
+            s = Sim(rho, ux, uy, 0.53, dtype=dtype, layout=layout, **kw)
+            s.set_tile(w, 1, 1, h, nt, 2, pf)
+            s.set_graph(chunk)
+            s.step(9)
+            assert torch.equal(s.save(), s9), (forced, w, h, nt, pf, chunk, 9)
+            s.step(52)
+            assert torch.equal(s.save(), s61), (forced, w, h, nt, pf, chunk, 61)
+            s.close()
+        say(f"two-step kernel {dtype} {layout} forced={forced}: bit-identical")
+
+
+def test_two_step_shapes_rejected_when_invalid(gpu_lib):
+    from paper_1809_06735_amd import LBMError
+    rho, ux, uy = inp.taylor_green(32, 0.01)
+    s = Sim(rho, ux, uy, 0.6, dtype="f64")
+    for bad in ((96, 1, 1, 8, 0, 2, 0), (0, 1, 1, 8, 0, 2, 0), (1024, 1, 1, 8, 0, 2, 0),
+                (64, 2, 1, 8, 0, 2, 0), (64, 1, 2, 8, 0, 2, 0), (64, 1, 1, 0, 0, 2, 0),
+                (64, 1, 1, 8, 0, 3, 0), (64, 1, 1, 8, 0, 1, 1), (960, 1, 1, 8, 0, 2, 0)):
+        with pytest.raises(LBMError):
+            s.set_tile(*bad)
+    s.close()
 
 
 def test_save_load_resume_and_determinism(gpu_lib):
@@ -252,7 +304,13 @@ def test_step_timing_counts_launches(gpu_lib):
     sim.step(100)
     sim.step(5)
     ms, n = sim.step_time(reset=True)
-    assert n == 105 and ms > 0
+    # the bulk launches are timed; the last two steps of each call record history
+    assert n == 98 + 3 and ms > 0
+    sim.set_tile(128, 1, 1, 16, 1, 2, 0)
+    sim.step(100)
+    sim.step(7)
+    ms, n = sim.step_time(reset=True)
+    assert n == 49 + 2 and ms > 0
     ms, n = sim.step_time()
     assert n == 0 and ms == 0
 
