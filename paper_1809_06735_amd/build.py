@@ -2,7 +2,8 @@
 
 Every HIP source under csrc/ is compiled to an object with hipcc and the
 objects are linked into ``paper_1809_06735_amd/libpaper_lbm.so``.  Packed
-FP32 instructions are disabled on every HIP compile.
+FP32 instructions are disabled on every HIP compile, and floating-point
+contraction is limited to single expressions.
 
 Usage: python -m paper_1809_06735_amd.build [-j N] [--verbose]
 """
@@ -24,6 +25,9 @@ ARCH = "gfx950"
 
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",
+    # multiply-adds are fused only within one source expression, so a per-site
+    # formula rounds the same in every kernel that inlines it
+    "-ffp-contract=on",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-fvisibility=hidden", "-Wall", "-Wno-unused-function", "-Wno-unused-result",
     "-I", os.path.join(ROOT, "include"),

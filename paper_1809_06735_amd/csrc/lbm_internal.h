@@ -81,12 +81,14 @@ struct StepParams {
 
 int launch_init(int dtype, void* pop, PopLayout lay, const double* rho0, const double* ux0,
                 const double* uy0, int nx, int ny, hipStream_t s);
-// One launch of the step kernel the tile selects: one step (fuse 0/1) or two
-// steps (fuse 2, no moment history).  Buffers: src -> dst either way.
+// One launch of the step kernel the tile selects: one step (fuse 0/1) or
+// fuse = 2..4 steps (temporal blocking, no moment history).  Buffers: src ->
+// dst either way.
 int launch_step(int dtype, bool force, const StepParams& p, const lbm_tile& t, hipStream_t s);
-int launch_step_fused2(int dtype, bool force, const StepParams& p, const lbm_tile& t, hipStream_t s);
+int launch_step_fused(int dtype, bool force, const StepParams& p, const lbm_tile& t, hipStream_t s);
 bool fused_tile_ok(const lbm_tile& t, int dtype);
-inline int steps_per_launch(const lbm_tile& t) { return t.fuse == 2 ? 2 : 1; }
+size_t fused_lds_bytes(int W, int K, int dtype);
+inline int steps_per_launch(const lbm_tile& t) { return t.fuse >= 2 ? t.fuse : 1; }
 bool tile_ok(const lbm_tile& t, int dtype, int nx, int ny);
 lbm_tile default_tile(int dtype, int nx, int ny, int layout);
 int tile_candidates(int dtype, int nx, int ny, lbm_tile* out, int cap);

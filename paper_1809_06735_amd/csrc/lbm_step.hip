@@ -305,8 +305,8 @@ int dispatch_step(bool force, const StepParams& p, const lbm_tile& t, hipStream_
 
 bool tile_ok(const lbm_tile& t, int dtype, int nx, int ny) {
   (void)ny;
-  if (t.fuse == 2) return fused_tile_ok(t, dtype);
-  if ((t.fuse != 0 && t.fuse != 1) || t.pf != 0) return false;
+  if (t.fuse >= 2) return fused_tile_ok(t, dtype);
+  if (t.fuse < 0 || t.pf != 0) return false;
   const int threads = t.bx * t.by;
   if (t.bx < 1 || t.by < 1 || t.ry < 1 || threads > 1024 || threads % 64 != 0) return false;
   if (t.vx != 1 && t.vx != 2 && t.vx != 4) return false;
@@ -364,16 +364,17 @@ int tile_candidates(int dtype, int nx, int ny, lbm_tile* out, int cap) {
       }
     }
   }
-  // two steps per launch: strip width W, band height H
-  const int ws[4] = {128, 256, 512, 960};
-  const int hs[4] = {16, 32, 64, 128};
+  // K = 2..4 steps per launch: strip width W, band height H
+  const int ws[3] = {128, 256, 512};
+  const int hs[3] = {32, 64, 128};
+  for (int k = 2; k <= 4; ++k)
   for (int w : ws) {
     if (w > nx + 64 && w > 128) continue;
     for (int h : hs) {
-      if (h > ny && h > 16) continue;
+      if (h > ny && h > 32) continue;
       for (int nt = 0; nt <= 1; ++nt)
         for (int pf = 0; pf <= 1; ++pf) {
-          lbm_tile t{w, 1, 1, h, nt, 2, pf};
+          lbm_tile t{w, 1, 1, h, nt, k, pf};
           if (!tile_ok(t, dtype, nx, ny)) continue;
           if (n < cap) out[n] = t;
           ++n;
@@ -384,7 +385,7 @@ int tile_candidates(int dtype, int nx, int ny, lbm_tile* out, int cap) {
 }
 
 int launch_step(int dtype, bool force, const StepParams& p, const lbm_tile& t, hipStream_t s) {
-  if (t.fuse == 2) return launch_step_fused2(dtype, force, p, t, s);
+  if (t.fuse >= 2) return launch_step_fused(dtype, force, p, t, s);
   if (dtype == LBM_F32) return dispatch_step<float>(force, p, t, s);
   return dispatch_step<double>(force, p, t, s);
 }

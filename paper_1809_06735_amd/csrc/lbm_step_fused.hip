@@ -1,0 +1,244 @@
+// K = 2, 3 or 4 D2Q9 BGK steps per launch (temporal blocking through LDS) for
+// gfx950.
+//
+// A workgroup owns a strip of W columns and a band of H rows of the output
+// and marches down its band one row per iteration.  Level s = 1..K of the
+// iteration advances one row by one step: level 1 pulls its populations from
+// the source state in HBM (x - c_l, periodic) and collides them with Eq. 1 /
+// Eq. 2 and Guo forcing, exactly as the single-step kernel does; level s > 1
+// collides the output of level s - 1.  A level's six populations with
+// c_x != 0 go to the neighbouring columns through an LDS row (two rows used
+// alternately, one barrier per level); the three with c_x = 0, and the rows
+// of the previous iterations that the pull also needs (c_y = +1 from two rows
+// back, c_y = 0 from one row back), stay in registers.  Level s runs one row
+// behind level s - 1 and on one column fewer on each side, so level 1 covers
+// the strip plus K - 1 halo columns per side and only level K writes to HBM.
+// The intermediate states never leave the CU: K lattice updates cost one read
+// and one write of every population plus one read of the force field, 80 B
+// per site per launch in FP32.  Results are bit-identical to K single-step
+// launches (same per-site arithmetic, same operand order).
+#include <hip/hip_runtime.h>
+
+#include "lbm_internal.h"
+#include "lbm_site.h"
+
+namespace lbm {
+namespace {
+
+using namespace step_detail;
+
+template <typename T, bool NT>
+__device__ __forceinline__ void put(T* p, T v) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
+// Registers that carry one level's input between rows: the pre-collision
+// values that the pull takes from the row above (c_y = +1: l = 2, 5, 6; two
+// rows of them, a = newer) and from the same row (l = 0, 1, 3).
+template <typename T>
+struct Carry {
+  T c0 = T(0), c1 = T(0), c3 = T(0);
+  T c2a = T(0), c2b = T(0), c5a = T(0), c5b = T(0), c6a = T(0), c6b = T(0);
+};
+
+// Threads [0, W) own the strip columns; threads W + j, j < 2 (K - 1), the halo
+// columns at distance j / 2 + 1 left (j even) or right (j odd) of the strip;
+// blockDim.x = W + 64.  PF issues the next row's loads after the first
+// exchange barrier instead of at the end of the iteration.
+template <typename T, int K, bool FORCE, bool NT, bool PF>
+__global__ void __launch_bounds__(1024) k_step_fused(StepParams p, int W, int H, int strips,
+                                                     int total, int per_xcd) {
+  extern __shared__ unsigned char smem_raw[];
+  T* const lds = reinterpret_cast<T*>(smem_raw);
+  const int stride = W + 2 * (K - 1);
+  const int b = blockIdx.x;
+  const int tile = (b & 7) * per_xcd + (b >> 3);
+  if (tile >= total) return;  // uniform over the workgroup
+  const int nx = p.nx, ny = p.ny;
+  const int x0 = (tile % strips) * W;
+  const int y0 = (tile / strips) * H;
+  const int weff = min(W, nx - x0);
+  const int heff = min(H, ny - y0);
+  const int t = threadIdx.x;
+  // column, LDS index and the highest level this thread takes part in
+  int col = x0, li = 0, top = 0;
+  if (t < weff) {
+    col = x0 + t;
+    li = t + K - 1;
+    top = K;
+  } else if (t >= W && t < W + 2 * (K - 1)) {
+    const int j = t - W;
+    const int dist = j / 2 + 1;
+    top = K - dist;
+    if ((j & 1) == 0) {
+      col = x0 - dist;
+      if (col < 0) col += nx;
+      li = K - 1 - dist;
+    } else {
+      col = x0 + weff - 1 + dist;
+      if (col >= nx) col -= nx;
+      li = K - 2 + weff + dist;
+    }
+  }
+  const T* __restrict__ src = static_cast<const T*>(p.src);
+  T* __restrict__ dst = static_cast<T*>(p.dst);
+  const T* __restrict__ gfx = static_cast<const T*>(p.fx);
+  const T* __restrict__ gfy = static_cast<const T*>(p.fy);
+  const T omega = T(p.omega);
+  const T guo = T(1) - T(0.5) * T(p.omega);
+  const T alpha = T(p.alpha);
+
+  auto wrap_row = [ny](int r) { return r < 0 ? r + ny : (r >= ny ? r - ny : r); };
+  // every thread loads (threads without a site read their strip's first
+  // column), so the loads sit outside any divergent branch
+  auto load_row = [&](int r, T (&d)[9], T& fx, T& fy) {
+    const int rn = r == 0 ? ny - 1 : r - 1;
+    const int rp = r == ny - 1 ? 0 : r + 1;
+    T v[9][1];
+    pull_all<T, 1>(src, p.ps, p.rs, nx, col, r, rn, rp, v);
+#pragma unroll
+    for (int l = 0; l < 9; ++l) d[l] = v[l][0];
+    if constexpr (FORCE) {
+      if (gfx) {
+        const size_t i = static_cast<size_t>(r) * nx + col;
+        fx = gfx[i];
+        fy = gfy[i];
+      } else {
+        fx = fy = T(0);
+      }
+    }
+  };
+
+  Carry<T> cy[K - 1];        // inputs of levels 2..K
+  T fhx[K - 1], fhy[K - 1];  // force at the rows of levels 2..K
+#pragma unroll
+  for (int s = 0; s < K - 1; ++s) fhx[s] = fhy[s] = T(0);
+  T d[9];
+  T fx = T(0), fy = T(0);
+  int par = 0;  // LDS row the next exchange writes
+  load_row(wrap_row(y0 - (K - 1)), d, fx, fy);
+  // iteration k: level s works on row y0 + k - (s - 1) and holds valid data
+  // from k = 2 s - 1 - K on; level K writes rows y0 .. y0 + heff - 1
+  for (int k = 1 - K; k <= heff + K - 2; ++k) {
+    T o[9];
+    if (top >= 1) {
+      SiteMoments<T, FORCE> m(d, FORCE ? fx : T(0), FORCE ? fy : T(0), alpha);
+      collide_site<T, FORCE>(d, m, omega, guo, o);
+    }
+    const T fx1 = fx, fy1 = fy;
+#pragma unroll
+    for (int s = 2; s <= K; ++s) {
+      // exchange level s - 1's x-moving populations
+      T* const slot = lds + par * 6 * stride;
+      if (top >= s - 1) {
+        slot[0 * stride + li] = o[1];
+        slot[1 * stride + li] = o[3];
+        slot[2 * stride + li] = o[5];
+        slot[3 * stride + li] = o[6];
+        slot[4 * stride + li] = o[7];
+        slot[5 * stride + li] = o[8];
+      }
+      par ^= 1;
+      __syncthreads();
+      if constexpr (PF) {
+        if (s == 2 && k < heff + K - 2) load_row(wrap_row(y0 + k + 1), d, fx, fy);
+      }
+      if (k >= 2 * s - 3 - K && top >= s) {  // level s - 1 held valid data
+        Carry<T>& c = cy[s - 2];
+        const T n1 = slot[0 * stride + li - 1];
+        const T n3 = slot[1 * stride + li + 1];
+        const T n5 = slot[2 * stride + li - 1];
+        const T n6 = slot[3 * stride + li + 1];
+        const T n7 = slot[4 * stride + li + 1];
+        const T n8 = slot[5 * stride + li - 1];
+        const T q0 = o[0], q2 = o[2], q4 = o[4];
+        if (k >= 2 * s - 1 - K) {
+          // level s at (col, y0 + k - (s - 1)): d_l = g_l(x - c_l) of level s - 1
+          const T d2[9] = {c.c0, c.c1, c.c2b, c.c3, q4, c.c5b, c.c6b, n7, n8};
+          SiteMoments<T, FORCE> m(d2, FORCE ? fhx[s - 2] : T(0), FORCE ? fhy[s - 2] : T(0), alpha);
+          collide_site<T, FORCE>(d2, m, omega, guo, o);
+          if (s == K) {
+            T* const out = dst + static_cast<size_t>(y0 + k - (K - 1)) * p.rs + col;
+#pragma unroll
+            for (int l = 0; l < 9; ++l) put<T, NT>(out + l * p.ps, o[l]);
+          }
+        }
+        c.c0 = q0;
+        c.c1 = n1;
+        c.c3 = n3;
+        c.c2b = c.c2a;
+        c.c2a = q2;
+        c.c5b = c.c5a;
+        c.c5a = n5;
+        c.c6b = c.c6a;
+        c.c6a = n6;
+      }
+    }
+    // force history: level s + 1 works next iteration on this iteration's level-s row
+#pragma unroll
+    for (int s = K - 2; s >= 1; --s) {
+      fhx[s] = fhx[s - 1];
+      fhy[s] = fhy[s - 1];
+    }
+    fhx[0] = fx1;
+    fhy[0] = fy1;
+    if constexpr (!PF) {
+      if (k < heff + K - 2) load_row(wrap_row(y0 + k + 1), d, fx, fy);
+    }
+  }
+}
+
+template <typename T, int K, bool FORCE, bool NT, bool PF>
+int launch_t(const StepParams& p, const lbm_tile& t, hipStream_t s) {
+  const int W = t.bx, H = t.ry;
+  const int strips = (p.nx + W - 1) / W;
+  const int bands = (p.ny + H - 1) / H;
+  const int total = strips * bands;
+  const int per_xcd = (total + 7) / 8;
+  const size_t lds = fused_lds_bytes(W, K, sizeof(T) == 8 ? LBM_F64 : LBM_F32);
+  hipLaunchKernelGGL((k_step_fused<T, K, FORCE, NT, PF>), dim3(per_xcd * 8), dim3(W + 64), lds, s, p,
+                     W, H, strips, total, per_xcd);
+  LBM_HIP(hipGetLastError());
+  return LBM_OK;
+}
+
+template <typename T, int K, bool FORCE>
+int dispatch_k(const StepParams& p, const lbm_tile& t, hipStream_t s) {
+  if (t.nt)
+    return t.pf ? launch_t<T, K, FORCE, true, true>(p, t, s) : launch_t<T, K, FORCE, true, false>(p, t, s);
+  return t.pf ? launch_t<T, K, FORCE, false, true>(p, t, s) : launch_t<T, K, FORCE, false, false>(p, t, s);
+}
+
+template <typename T, bool FORCE>
+int dispatch(const StepParams& p, const lbm_tile& t, hipStream_t s) {
+  switch (t.fuse) {
+    case 2: return dispatch_k<T, 2, FORCE>(p, t, s);
+    case 3: return dispatch_k<T, 3, FORCE>(p, t, s);
+    default: return dispatch_k<T, 4, FORCE>(p, t, s);
+  }
+}
+
+}  // namespace
+
+size_t fused_lds_bytes(int W, int K, int dtype) {
+  return static_cast<size_t>(2) * 6 * (W + 2 * (K - 1)) * (dtype == LBM_F64 ? 8 : 4);
+}
+
+bool fused_tile_ok(const lbm_tile& t, int dtype) {
+  if (t.fuse < 2 || t.fuse > 4 || t.by != 1 || t.vx != 1) return false;
+  if (t.bx < 64 || t.bx % 64 != 0 || t.bx + 64 > 1024) return false;
+  if (t.ry < 1 || t.ry > 4096) return false;
+  if ((t.nt != 0 && t.nt != 1) || (t.pf != 0 && t.pf != 1)) return false;
+  return fused_lds_bytes(t.bx, t.fuse, dtype) <= 64 * 1024;
+}
+
+int launch_step_fused(int dtype, bool force, const StepParams& p, const lbm_tile& t, hipStream_t s) {
+  if (!fused_tile_ok(t, dtype)) return fail(LBM_E_INVALID, "invalid multi-step launch shape");
+  if (p.h_rho) return fail(LBM_E_INVALID, "the multi-step kernel records no moment history");
+  if (dtype == LBM_F64)
+    return force ? dispatch<double, true>(p, t, s) : dispatch<double, false>(p, t, s);
+  return force ? dispatch<float, true>(p, t, s) : dispatch<float, false>(p, t, s);
+}
+
+}  // namespace lbm

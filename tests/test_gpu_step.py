@@ -148,10 +148,10 @@ def test_ragged_grids_all_launch_shapes_agree(gpu_lib, shape):
                 for ry in (1, 3):
                     for nt in (0, 1):
                         cand.append((bx, by, vx_, ry, nt))
-        # two steps per launch: strip width, band height, nt, prefetch
-        for (w, h) in ((64, 1), (64, 5), (128, 16), (64, 64)):
+        # K steps per launch: strip width, band height, nt, K, prefetch
+        for (w, h, k) in ((64, 1, 2), (64, 5, 3), (128, 16, 4), (64, 64, 2), (64, 2, 4)):
             for nt, pf in ((0, 0), (1, 1)):
-                cand.append((w, 1, 1, h, nt, 2, pf))
+                cand.append((w, 1, 1, h, nt, k, pf))
         ref_state = None
         checked = 0
         for tile in cand:
@@ -185,10 +185,10 @@ def test_graph_replay_equals_direct_launches(gpu_lib):
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 @pytest.mark.parametrize("layout", ["rows", "planes"])
-def test_two_step_kernel_equals_single_steps(gpu_lib, dtype, layout):
-    """Two steps per launch (temporal blocking through LDS) give bit-identical states to
-    single-step launches: forced and unforced, ragged strips and bands, even and odd step
-    counts, direct launches and graph replay."""
+def test_multi_step_kernel_equals_single_steps(gpu_lib, dtype, layout):
+    """K = 2, 3, 4 steps per launch (temporal blocking through LDS) give bit-identical states
+    to single-step launches: forced and unforced, ragged strips and bands (down to one row),
+    step counts that leave remainders, direct launches and graph replay."""
     ny, nx = 75, 200
     rng = np.random.default_rng(21)
     rho = 1.0 + 0.01 * rng.standard_normal((ny, nx))
@@ -206,26 +206,29 @@ def test_two_step_kernel_equals_single_steps(gpu_lib, dtype, layout):
         base.step(52)
         s61 = base.save().clone()
         base.close()
-        for (w, h, nt, pf, chunk) in ((64, 16, 0, 0, 0), (128, 7, 1, 1, 0), (256, 75, 0, 1, 4),
-                                      (64, 1, 1, 0, 2), (512, 32, 1, 1, 0)):
+        for (k, w, h, nt, pf, chunk) in ((2, 64, 16, 0, 0, 0), (2, 128, 7, 1, 1, 0), (2, 256, 75, 0, 1, 4),
+                                         (2, 64, 1, 1, 0, 2), (2, 512, 32, 1, 1, 0),
+                                         (3, 64, 16, 1, 0, 0), (3, 128, 5, 0, 1, 2), (3, 256, 75, 1, 1, 0),
+                                         (4, 64, 3, 0, 0, 0), (4, 192, 40, 1, 1, 4), (4, 512, 64, 1, 0, 0),
+                                         (4, 64, 1, 1, 1, 0)):
             s = Sim(rho, ux, uy, 0.53, dtype=dtype, layout=layout, **kw)
-            s.set_tile(w, 1, 1, h, nt, 2, pf)
+            s.set_tile(w, 1, 1, h, nt, k, pf)
             s.set_graph(chunk)
             s.step(9)
-            assert torch.equal(s.save(), s9), (forced, w, h, nt, pf, chunk, 9)
+            assert torch.equal(s.save(), s9), (forced, k, w, h, nt, pf, chunk, 9)
             s.step(52)
-            assert torch.equal(s.save(), s61), (forced, w, h, nt, pf, chunk, 61)
+            assert torch.equal(s.save(), s61), (forced, k, w, h, nt, pf, chunk, 61)
             s.close()
-        say(f"two-step kernel {dtype} {layout} forced={forced}: bit-identical")
+        say(f"multi-step kernel {dtype} {layout} forced={forced}: bit-identical")
 
 
-def test_two_step_shapes_rejected_when_invalid(gpu_lib):
+def test_multi_step_shapes_rejected_when_invalid(gpu_lib):
     from paper_1809_06735_amd import LBMError
     rho, ux, uy = inp.taylor_green(32, 0.01)
     s = Sim(rho, ux, uy, 0.6, dtype="f64")
     for bad in ((96, 1, 1, 8, 0, 2, 0), (0, 1, 1, 8, 0, 2, 0), (1024, 1, 1, 8, 0, 2, 0),
                 (64, 2, 1, 8, 0, 2, 0), (64, 1, 2, 8, 0, 2, 0), (64, 1, 1, 0, 0, 2, 0),
-                (64, 1, 1, 8, 0, 3, 0), (64, 1, 1, 8, 0, 1, 1), (960, 1, 1, 8, 0, 2, 0)):
+                (64, 1, 1, 8, 0, 5, 0), (64, 1, 1, 8, 0, 1, 1), (960, 1, 1, 8, 0, 2, 0)):
         with pytest.raises(LBMError):
             s.set_tile(*bad)
     s.close()
