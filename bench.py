@@ -6,11 +6,15 @@ forcing and linear drag, the moments at the last step, and the sub-volume
 energy/enstrophy balance at box sizes 8..256 (the workload's diagnostic
 cadence is one balance every 500 steps).  Inputs are resident in HBM before
 the timed region; the timed region is bracketed by torch.cuda.synchronize().
+The step-kernel shape, including how many steps one launch advances
+(temporal blocking), is chosen by the library's autotuner.
 
 Prints ONE JSON line on stdout (everything else goes to stderr):
 value = lattice updates per second of the whole pass (MLUPS), with the
-dominant kernel's roofline (HIP events around the step launches on the
-library's stream) and the FP64 CPU oracle timed on a bounded sample.
+dominant kernel's roofline (HIP events around its launches on the library's
+stream; algorithmic bytes of one launch = every population read and written
+once plus the force field read once, whatever the number of steps fused) and
+the FP64 CPU oracle timed on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--tau T]
                        [--no-cpu-baseline] [--no-extras]
@@ -36,28 +40,63 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def step_source_digest():
-    """Digest of the step kernel's sources (the counters are valid only for it)."""
+KERNEL_SOURCES = {"k_step": ("lbm_step.hip", "lbm_site.h"),
+                  "k_step_fused": ("lbm_step_fused.hip", "lbm_site.h")}
+
+
+def step_source_digest(kernel="k_step_fused"):
+    """Digest of a step kernel's sources (its counters are valid only for them)."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("lbm_step.hip", "lbm_site.h"):
+    for f in KERNEL_SOURCES[kernel]:
         h.update(open(os.path.join(ROOT, "paper_1809_06735_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(kernel_tag):
-    """Per-launch HBM bytes of the step kernel from the committed counter summary,
-    or None when it is missing or was taken on another version of the kernel."""
-    path = os.path.join(ROOT, "profiles", f"{kernel_tag}_traffic.md")
+def traffic_from_profile(kernel, workload, tile):
+    """Per-launch HBM bytes of a step kernel from the committed counter summary, or
+    None when it is missing, was taken on another version of the kernel or on
+    another launch shape."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.md")
     if not os.path.exists(path):
         return None
     rec = None
     for line in open(path):
         if line.startswith("TRAFFIC_JSON:"):
             rec = json.loads(line.split(":", 1)[1])
-    if not rec or rec.get("source_sha256_16") != step_source_digest():
+    if not rec or rec.get("source_sha256_16") != step_source_digest(kernel):
+        return None
+    if rec.get("tile") is not None and list(rec["tile"]) != list(tile):
         return None
     return rec.get("bytes_per_launch")
+
+
+def single_step_kernel(n, tau, alpha, fx, fy, steps=400):
+    """The one-step-per-launch kernel on the same workload, in its tuned shape."""
+    import numpy as np
+    import torch
+    from paper_1809_06735_amd import Simulation
+    z = np.zeros((n, n))
+    s = Simulation(np.ones((n, n)), z, z, tau, dtype="f32", fx=fx, fy=fy, alpha=alpha)
+    best = None
+    for shape in ((512, 1, 1, 1, 1), (256, 1, 1, 1, 1), (512, 1, 1, 1, 0)):
+        s.set_tile(*shape)
+        s.step(22)
+        torch.cuda.synchronize()
+        s.step_time(reset=True)
+        s.step_timing(True)
+        s.step(steps + 2)
+        torch.cuda.synchronize()
+        s.step_timing(False)
+        ms, nl = s.step_time(reset=True)
+        per = ms * 1e-3 / nl
+        if best is None or per < best[1]:
+            best = (shape, per)
+    s.close()
+    shape, per = best
+    gbs = 80 * n * n / per / 1e9
+    return {"shape": list(shape), "avg_launch_us": round(per * 1e6, 2), "GBps": round(gbs, 1),
+            "frac_of_8TBps": round(gbs / HBM_PEAK_GBS, 4), "kernel_MLUPS": round(n * n / per / 1e6, 1)}
 
 
 def cpu_baseline(n, tau, alpha, fx, fy, steps):
@@ -148,14 +187,17 @@ def main():
     kern_ms, launches = sim.step_time(reset=True)
     lu = n * n * STEPS_PER_PASS * a.steps
     mlups = lu / elapsed / 1e6
+    spl = max(tile[5], 1)                     # steps per launch of the bulk shape
+    kernel = "k_step_fused" if spl > 1 else "k_step"
     avg_launch_s = kern_ms * 1e-3 / max(launches, 1)
-    bytes_per_lu = 9 * 4 * 2 + 2 * 4          # 9 reads + 9 writes + 2 force reads, FP32
-    alg_bytes = bytes_per_lu * n * n
+    bytes_per_site = 9 * 4 * 2 + 2 * 4        # 9 reads + 9 writes + 2 force reads, FP32
+    alg_bytes = bytes_per_site * n * n        # per launch, whatever the steps fused
     achieved = alg_bytes / avg_launch_s / 1e9
-    traffic = traffic_from_profile("k_step_forced4096")
+    traffic = traffic_from_profile(kernel, "forced4096", tile)
     st = last["stats"]
-    log(f"[bench] {mlups:.0f} MLUPS whole pass; step kernel {avg_launch_s * 1e6:.1f} us/launch "
-        f"= {achieved:.0f} GB/s ({achieved / HBM_PEAK_GBS:.1%} of 8 TB/s)")
+    log(f"[bench] {mlups:.0f} MLUPS whole pass; {kernel} ({spl} steps/launch) "
+        f"{avg_launch_s * 1e6:.1f} us/launch = {achieved:.0f} GB/s ({achieved / HBM_PEAK_GBS:.1%} "
+        f"of 8 TB/s), {n * n * spl / avg_launch_s / 1e6:.0f} MLUPS in the kernel")
 
     out = {
         "metric": METRIC,
@@ -178,9 +220,15 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": "k_step (fused pull stream + BGK collide + Guo force)",
+                     "traffic": traffic,
+                     "kernel": f"{kernel}<float, K={spl}> (pull stream + BGK collide + Guo force, "
+                               f"{spl} steps per launch)" if spl > 1 else
+                               "k_step (fused pull stream + BGK collide + Guo force)",
+                     "steps_per_launch": spl,
                      "algorithmic_bytes_per_launch": alg_bytes,
-                     "avg_launch_us": round(avg_launch_s * 1e6, 2)},
+                     "bytes_per_lattice_update": bytes_per_site / spl,
+                     "avg_launch_us": round(avg_launch_s * 1e6, 2),
+                     "kernel_MLUPS": round(n * n * spl / avg_launch_s / 1e6, 1)},
         "balance_at_end": {str(s["L"]): {"mean_dE": s["dE"]["mean"], "mean_dZ": s["dZ"]["mean"],
                                          "mean_Ma": s["Ma"]["mean"]} for s in st},
     }
@@ -191,6 +239,10 @@ def main():
     if not a.no_extras:
         extras = {}
         try:
+            extras["single_step_kernel_forced4096"] = single_step_kernel(n, a.tau, w.alpha, fx, fy)
+        except Exception as e:  # noqa: BLE001
+            extras["single_step_kernel_forced4096"] = f"error: {e}"
+        try:
             gbs, _ = copy_bandwidth(1 << 30, iters=10)
             extras["copy_kernel_GBps"] = round(gbs, 1)
         except Exception as e:  # noqa: BLE001
@@ -198,7 +250,7 @@ def main():
         try:
             rho0, ux0, uy0 = inp.spectrum_velocity(n, seed=0, max_mach=0.05)
             plain = Simulation(rho0, ux0, uy0, a.tau, dtype="f32")
-            plain.autotune(trial_steps=5)
+            ptile = plain.autotune(trial_steps=5)
             plain.step(200)
             torch.cuda.synchronize()
             plain.step_timing(True)
@@ -207,9 +259,9 @@ def main():
             torch.cuda.synchronize()
             dtp = time.perf_counter() - t1
             kms, nl = plain.step_time(reset=True)
-            per = kms * 1e-3 / nl
+            per = kms * 1e-3 / nl                  # per launch of ptile[5] steps
             extras["plain_unforced_4096_fp32"] = {
-                "MLUPS": round(n * n * 1000 / dtp / 1e6, 1),
+                "MLUPS": round(n * n * 1000 / dtp / 1e6, 1), "shape": list(ptile),
                 "kernel_GBps": round(72 * n * n / per / 1e9, 1),
                 "frac_of_8TBps": round(72 * n * n / per / 1e9 / HBM_PEAK_GBS, 4)}
             plain.close()

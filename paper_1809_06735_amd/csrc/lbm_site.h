@@ -139,40 +139,54 @@ struct SiteMoments {
 // BGK collision (Eq. 1) towards the equilibrium of Eq. 2, with Guo's forcing
 // term (1 - 1/(2 tau)) w [3 (c - u) + 9 (c.u) c] . F, all in deviation form:
 // f* = (1 - omega) d + omega d^eq + G.  Opposite velocities l, lbar share w
-// and the parts of d^eq and G that are even in c, and see the odd parts with
-// opposite signs:
-//   d^eq = w (b + 4.5 rho (c.u)^2) +- 3 w rho (c.u),  b = drho - 1.5 rho |u|^2,
-//   G    = g w (9 (c.u)(c.F) - 3 u.F) +- 3 g w (c.F),  g = 1 - omega/2,
-// so each pair costs one even and one odd term.
+// and the parts of omega d^eq + G that are even in c, and see the odd parts
+// with opposite signs.  With cu = c.u, cF = c.F, g = 1 - omega/2:
+//   even  S = w B0 + 3 w cu (1.5 omega rho cu + 3 g cF),
+//         B0 = omega (drho - 1.5 rho |u|^2) - 3 g u.F,
+//   odd   A = w (3 omega rho cu + 3 g cF),
+// and f*_l = (1 - omega) d_l + S + A, f*_lbar = (1 - omega) d_lbar + S - A.
+// Without a force F = 0 and the same terms are grouped by powers of cu.
 template <typename T, bool FORCE>
 __device__ __forceinline__ void collide_site(const T (&d)[9], const SiteMoments<T, FORCE>& m,
                                              T omega, T guo, T (&o)[9]) {
   const T ux = m.ux, uy = m.uy;
   const T om1 = T(1) - omega;
   const T b = m.drho - m.rho * (T(1.5) * (ux * ux + uy * uy));
-  const T r45 = T(4.5) * m.rho;
-  const T r3 = T(3) * m.rho;
-  const T uF3 = FORCE ? T(3) * (ux * m.Fx + uy * m.Fy) : T(0);
-  {
-    T e = (omega * T(wq(0))) * b;
-    if constexpr (FORCE) e -= (guo * T(wq(0))) * uF3;
-    o[0] = om1 * d[0] + e;
-  }
-  auto pair = [&](int l, int lb, T cu, T cF, T w) {
-    T S = (omega * w) * (b + r45 * (cu * cu));
-    T A = ((omega * w) * r3) * cu;
-    if constexpr (FORCE) {
-      S += (guo * w) * (T(9) * cu * cF - uF3);
-      A += (T(3) * guo * w) * cF;
-    }
-    o[l] = om1 * d[l] + (S + A);
-    o[lb] = om1 * d[lb] + (S - A);
-  };
   const T wa = T(wq(1)), wd = T(wq(5));
-  pair(1, 3, ux, m.Fx, wa);
-  pair(2, 4, uy, m.Fy, wa);
-  pair(5, 7, ux + uy, m.Fx + m.Fy, wd);
-  pair(6, 8, uy - ux, m.Fy - m.Fx, wd);
+  const T wRa = (T(3) * omega * wa) * m.rho, wRd = (T(3) * omega * wd) * m.rho;
+  if constexpr (FORCE) {
+    const T g3 = T(3) * guo;
+    const T B0 = omega * b - g3 * (ux * m.Fx + uy * m.Fy);
+    const T p3 = (T(1.5) * omega) * m.rho;
+    const T wBa = wa * B0, wBd = wd * B0;
+    o[0] = om1 * d[0] + T(wq(0)) * B0;
+    auto pair = [&](int l, int lb, T cu, T cF, T w, T wB, T wR) {
+      const T gc = g3 * cF;
+      const T S = (T(3) * w) * (cu * (p3 * cu + gc)) + wB;
+      const T A = wR * cu + w * gc;
+      o[l] = om1 * d[l] + (S + A);
+      o[lb] = om1 * d[lb] + (S - A);
+    };
+    pair(1, 3, ux, m.Fx, wa, wBa, wRa);
+    pair(2, 4, uy, m.Fy, wa, wBa, wRa);
+    pair(5, 7, ux + uy, m.Fx + m.Fy, wd, wBd, wRd);
+    pair(6, 8, uy - ux, m.Fy - m.Fx, wd, wBd, wRd);
+  } else {
+    // S = w omega b + 4.5 w omega rho cu^2, A = 3 w omega rho cu
+    const T wBa = (omega * wa) * b, wBd = (omega * wd) * b;
+    const T wKa = (T(4.5) * omega * wa) * m.rho, wKd = (T(4.5) * omega * wd) * m.rho;
+    o[0] = om1 * d[0] + (omega * T(wq(0))) * b;
+    auto pair = [&](int l, int lb, T cu, T wB, T wK, T wR) {
+      const T S = wK * (cu * cu) + wB;
+      const T A = wR * cu;
+      o[l] = om1 * d[l] + (S + A);
+      o[lb] = om1 * d[lb] + (S - A);
+    };
+    pair(1, 3, ux, wBa, wKa, wRa);
+    pair(2, 4, uy, wBa, wKa, wRa);
+    pair(5, 7, ux + uy, wBd, wKd, wRd);
+    pair(6, 8, uy - ux, wBd, wKd, wRd);
+  }
 }
 
 template <int L, typename T, int VX>
