@@ -19,6 +19,8 @@
 // launches (same per-site arithmetic, same operand order).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "lbm_internal.h"
 #include "lbm_site.h"
 
@@ -34,12 +36,14 @@ __device__ __forceinline__ void put(T* p, T v) {
 }
 
 // Registers that carry one level's input between rows: the pre-collision
-// values that the pull takes from the row above (c_y = +1: l = 2, 5, 6; two
-// rows of them, a = newer) and from the same row (l = 0, 1, 3).
+// values that the pull takes from the same row (l = 0, 1, 3) and from the row
+// above (c_y = +1: l = 2, 5, 6), two rows of the latter.  Which of the two
+// holds the older row alternates with the iteration's parity, so no value is
+// moved between registers.
 template <typename T>
 struct Carry {
   T c0 = T(0), c1 = T(0), c3 = T(0);
-  T c2a = T(0), c2b = T(0), c5a = T(0), c5b = T(0), c6a = T(0), c6b = T(0);
+  T c2[2] = {T(0), T(0)}, c5[2] = {T(0), T(0)}, c6[2] = {T(0), T(0)};
 };
 
 // Threads [0, W) own the strip columns; threads W + j, j < 2 (K - 1), the halo
@@ -116,11 +120,17 @@ __global__ void __launch_bounds__(1024) k_step_fused(StepParams p, int W, int H,
   for (int s = 0; s < K - 1; ++s) fhx[s] = fhy[s] = T(0);
   T d[9];
   T fx = T(0), fy = T(0);
-  int par = 0;  // LDS row the next exchange writes
+  const int last = heff + K - 2;
   load_row(wrap_row(y0 - (K - 1)), d, fx, fy);
+
   // iteration k: level s works on row y0 + k - (s - 1) and holds valid data
-  // from k = 2 s - 1 - K on; level K writes rows y0 .. y0 + heff - 1
-  for (int k = 1 - K; k <= heff + K - 2; ++k) {
+  // from k = 2 s - 1 - K on; level K writes rows y0 .. y0 + heff - 1.  E is the
+  // parity of the iteration count, which fixes the LDS rows and carry roles.
+  auto iteration = [&](auto parity, int k) {
+    constexpr int E = decltype(parity)::value;
+    // LDS row of the first exchange: exchanges alternate rows across levels and
+    // iterations, K - 1 of them per iteration
+    constexpr int P0 = ((K - 1) & 1) ? E : 0;
     T o[9];
     if (top >= 1) {
       SiteMoments<T, FORCE> m(d, FORCE ? fx : T(0), FORCE ? fy : T(0), alpha);
@@ -130,7 +140,7 @@ __global__ void __launch_bounds__(1024) k_step_fused(StepParams p, int W, int H,
 #pragma unroll
     for (int s = 2; s <= K; ++s) {
       // exchange level s - 1's x-moving populations
-      T* const slot = lds + par * 6 * stride;
+      T* const slot = lds + ((P0 + s) & 1) * 6 * stride;
       if (top >= s - 1) {
         slot[0 * stride + li] = o[1];
         slot[1 * stride + li] = o[3];
@@ -139,10 +149,9 @@ __global__ void __launch_bounds__(1024) k_step_fused(StepParams p, int W, int H,
         slot[4 * stride + li] = o[7];
         slot[5 * stride + li] = o[8];
       }
-      par ^= 1;
       __syncthreads();
       if constexpr (PF) {
-        if (s == 2 && k < heff + K - 2) load_row(wrap_row(y0 + k + 1), d, fx, fy);
+        if (s == 2 && k < last) load_row(wrap_row(y0 + k + 1), d, fx, fy);
       }
       if (k >= 2 * s - 3 - K && top >= s) {  // level s - 1 held valid data
         Carry<T>& c = cy[s - 2];
@@ -154,8 +163,9 @@ __global__ void __launch_bounds__(1024) k_step_fused(StepParams p, int W, int H,
         const T n8 = slot[5 * stride + li - 1];
         const T q0 = o[0], q2 = o[2], q4 = o[4];
         if (k >= 2 * s - 1 - K) {
-          // level s at (col, y0 + k - (s - 1)): d_l = g_l(x - c_l) of level s - 1
-          const T d2[9] = {c.c0, c.c1, c.c2b, c.c3, q4, c.c5b, c.c6b, n7, n8};
+          // level s at (col, y0 + k - (s - 1)): d_l = g_l(x - c_l) of level s - 1;
+          // c2[E ^ 1] etc. hold the row two back
+          const T d2[9] = {c.c0, c.c1, c.c2[E ^ 1], c.c3, q4, c.c5[E ^ 1], c.c6[E ^ 1], n7, n8};
           SiteMoments<T, FORCE> m(d2, FORCE ? fhx[s - 2] : T(0), FORCE ? fhy[s - 2] : T(0), alpha);
           collide_site<T, FORCE>(d2, m, omega, guo, o);
           if (s == K) {
@@ -167,12 +177,9 @@ __global__ void __launch_bounds__(1024) k_step_fused(StepParams p, int W, int H,
         c.c0 = q0;
         c.c1 = n1;
         c.c3 = n3;
-        c.c2b = c.c2a;
-        c.c2a = q2;
-        c.c5b = c.c5a;
-        c.c5a = n5;
-        c.c6b = c.c6a;
-        c.c6a = n6;
+        c.c2[E ^ 1] = q2;
+        c.c5[E ^ 1] = n5;
+        c.c6[E ^ 1] = n6;
       }
     }
     // force history: level s + 1 works next iteration on this iteration's level-s row
@@ -184,8 +191,13 @@ __global__ void __launch_bounds__(1024) k_step_fused(StepParams p, int W, int H,
     fhx[0] = fx1;
     fhy[0] = fy1;
     if constexpr (!PF) {
-      if (k < heff + K - 2) load_row(wrap_row(y0 + k + 1), d, fx, fy);
+      if (k < last) load_row(wrap_row(y0 + k + 1), d, fx, fy);
     }
+  };
+  for (int k = 1 - K; k <= last; k += 2) {
+    iteration(std::integral_constant<int, 0>(), k);
+    if (k + 1 > last) break;
+    iteration(std::integral_constant<int, 1>(), k + 1);
   }
 }
 
