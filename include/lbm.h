@@ -125,10 +125,10 @@ typedef struct {
  * fuse = 0 or 1: one step per launch.  bx*by threads per workgroup (a
  *   multiple of 64, at most 1024); each thread updates vx consecutive sites
  *   in x (1, 2 or 4; nx must be a multiple of vx) on ry consecutive rows.
- * fuse = 2, 3 or 4: that many steps per launch (temporal blocking; the
+ * fuse = 2..6: that many steps per launch (temporal blocking; the
  *   intermediate states stay in LDS and registers, bit-identical to single
  *   steps).  A workgroup of bx + 64 threads updates a strip of bx columns (a
- *   multiple of 64, at most 960) and a band of ry rows; by = vx = 1; pf = 1
+ *   multiple of 64, at most 512) and a band of ry rows; by = vx = 1; pf = 1
  *   issues the loads of the next row earlier in the row's iteration.
  * nt = 1 writes the new populations with non-temporal stores.  lbm_step runs
  * the two steps that record the moment history (and any remainder of the

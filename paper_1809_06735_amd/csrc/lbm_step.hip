@@ -364,16 +364,17 @@ int tile_candidates(int dtype, int nx, int ny, lbm_tile* out, int cap) {
       }
     }
   }
-  // K = 2..4 steps per launch: strip width W, band height H
+  // K = 2..6 steps per launch: strip width W, band height H; the early loads
+  // (pf = 1) pay off from K = 3 on
   const int ws[3] = {128, 256, 512};
-  const int hs[3] = {32, 64, 128};
-  for (int k = 2; k <= 4; ++k)
+  const int hs[4] = {32, 64, 128, 256};
+  for (int k = 2; k <= 6; ++k)
   for (int w : ws) {
     if (w > nx + 64 && w > 128) continue;
     for (int h : hs) {
       if (h > ny && h > 32) continue;
       for (int nt = 0; nt <= 1; ++nt)
-        for (int pf = 0; pf <= 1; ++pf) {
+        for (int pf = k >= 3 ? 1 : 0; pf <= 1; ++pf) {
           lbm_tile t{w, 1, 1, h, nt, k, pf};
           if (!tile_ok(t, dtype, nx, ny)) continue;
           if (n < cap) out[n] = t;

@@ -1,4 +1,4 @@
-// K = 2, 3 or 4 D2Q9 BGK steps per launch (temporal blocking through LDS) for
+// K = 2..6 D2Q9 BGK steps per launch (temporal blocking through LDS) for
 // gfx950.
 //
 // A workgroup owns a strip of W columns and a band of H rows of the output
@@ -29,6 +29,10 @@ namespace {
 
 using namespace step_detail;
 
+// strips of at most 512 columns (one extra wave for the halo): the register
+// budget of a 576-thread workgroup leaves room for the carries of 6 levels
+constexpr int kFusedMaxThreads = 576;
+
 template <typename T, bool NT>
 __device__ __forceinline__ void put(T* p, T v) {
   if constexpr (NT) __builtin_nontemporal_store(v, p);
@@ -51,7 +55,7 @@ struct Carry {
 // blockDim.x = W + 64.  PF issues the next row's loads after the first
 // exchange barrier instead of at the end of the iteration.
 template <typename T, int K, bool FORCE, bool NT, bool PF>
-__global__ void __launch_bounds__(1024) k_step_fused(StepParams p, int W, int H, int strips,
+__global__ void __launch_bounds__(kFusedMaxThreads) k_step_fused(StepParams p, int W, int H, int strips,
                                                      int total, int per_xcd) {
   extern __shared__ unsigned char smem_raw[];
   T* const lds = reinterpret_cast<T*>(smem_raw);
@@ -227,7 +231,9 @@ int dispatch(const StepParams& p, const lbm_tile& t, hipStream_t s) {
   switch (t.fuse) {
     case 2: return dispatch_k<T, 2, FORCE>(p, t, s);
     case 3: return dispatch_k<T, 3, FORCE>(p, t, s);
-    default: return dispatch_k<T, 4, FORCE>(p, t, s);
+    case 4: return dispatch_k<T, 4, FORCE>(p, t, s);
+    case 5: return dispatch_k<T, 5, FORCE>(p, t, s);
+    default: return dispatch_k<T, 6, FORCE>(p, t, s);
   }
 }
 
@@ -238,8 +244,8 @@ size_t fused_lds_bytes(int W, int K, int dtype) {
 }
 
 bool fused_tile_ok(const lbm_tile& t, int dtype) {
-  if (t.fuse < 2 || t.fuse > 4 || t.by != 1 || t.vx != 1) return false;
-  if (t.bx < 64 || t.bx % 64 != 0 || t.bx + 64 > 1024) return false;
+  if (t.fuse < 2 || t.fuse > 6 || t.by != 1 || t.vx != 1) return false;
+  if (t.bx < 64 || t.bx % 64 != 0 || t.bx + 64 > kFusedMaxThreads) return false;
   if (t.ry < 1 || t.ry > 4096) return false;
   if ((t.nt != 0 && t.nt != 1) || (t.pf != 0 && t.pf != 1)) return false;
   return fused_lds_bytes(t.bx, t.fuse, dtype) <= 64 * 1024;

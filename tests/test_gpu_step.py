@@ -186,7 +186,7 @@ def test_graph_replay_equals_direct_launches(gpu_lib):
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 @pytest.mark.parametrize("layout", ["rows", "planes"])
 def test_multi_step_kernel_equals_single_steps(gpu_lib, dtype, layout):
-    """K = 2, 3, 4 steps per launch (temporal blocking through LDS) give bit-identical states
+    """K = 2..6 steps per launch (temporal blocking through LDS) give bit-identical states
     to single-step launches: forced and unforced, ragged strips and bands (down to one row),
     step counts that leave remainders, direct launches and graph replay."""
     ny, nx = 75, 200
@@ -210,7 +210,8 @@ def test_multi_step_kernel_equals_single_steps(gpu_lib, dtype, layout):
                                          (2, 64, 1, 1, 0, 2), (2, 512, 32, 1, 1, 0),
                                          (3, 64, 16, 1, 0, 0), (3, 128, 5, 0, 1, 2), (3, 256, 75, 1, 1, 0),
                                          (4, 64, 3, 0, 0, 0), (4, 192, 40, 1, 1, 4), (4, 512, 64, 1, 0, 0),
-                                         (4, 64, 1, 1, 1, 0)):
+                                         (4, 64, 1, 1, 1, 0), (5, 128, 20, 1, 1, 0), (5, 64, 75, 0, 1, 2),
+                                         (6, 256, 9, 1, 1, 0), (6, 64, 2, 0, 0, 4)):
             s = Sim(rho, ux, uy, 0.53, dtype=dtype, layout=layout, **kw)
             s.set_tile(w, 1, 1, h, nt, k, pf)
             s.set_graph(chunk)
@@ -228,7 +229,8 @@ def test_multi_step_shapes_rejected_when_invalid(gpu_lib):
     s = Sim(rho, ux, uy, 0.6, dtype="f64")
     for bad in ((96, 1, 1, 8, 0, 2, 0), (0, 1, 1, 8, 0, 2, 0), (1024, 1, 1, 8, 0, 2, 0),
                 (64, 2, 1, 8, 0, 2, 0), (64, 1, 2, 8, 0, 2, 0), (64, 1, 1, 0, 0, 2, 0),
-                (64, 1, 1, 8, 0, 5, 0), (64, 1, 1, 8, 0, 1, 1), (960, 1, 1, 8, 0, 2, 0)):
+                (64, 1, 1, 8, 0, 7, 0), (64, 1, 1, 8, 0, 1, 1), (960, 1, 1, 8, 0, 2, 0),
+                (576, 1, 1, 8, 0, 2, 0)):
         with pytest.raises(LBMError):
             s.set_tile(*bad)
     s.close()
