@@ -261,8 +261,12 @@ LBM_API int lbm_balance_fields(const lbm_balance_input* in, void* ws, size_t ws_
  * workgroups take equal slices of a (run, row-band) work list and meet at a
  * grid-wide barrier between steps; the barrier waits are bounded and report
  * LBM_E_TIMEOUT instead of hanging.  Mode LBM_BATCH_PER_STEP launches one
- * kernel per step over the same work list.  Both are replayed from hipGraphs. */
-enum { LBM_BATCH_PERSISTENT = 0, LBM_BATCH_PER_STEP = 1 };
+ * kernel per step over the same work list.  Mode LBM_BATCH_MULTI_STEP
+ * advances every run by K steps per launch over the (run, strip, band) tiles
+ * of the single-grid multi-step kernel (see lbm_tile.fuse), bit-identical to
+ * single steps; step counts that are not a multiple of K end with single-step
+ * launches.  All modes are replayed from hipGraphs. */
+enum { LBM_BATCH_PERSISTENT = 0, LBM_BATCH_PER_STEP = 1, LBM_BATCH_MULTI_STEP = 2 };
 typedef struct lbm_batch_s* lbm_batch;
 
 /* cfgs[nruns]: per-run configuration; with_balance must be 0, stream is taken
@@ -275,17 +279,24 @@ LBM_API int lbm_batch_init(const lbm_config* cfgs, int32_t nruns, void* ws, size
                    const double* const* rho0, const double* const* ux0,
                    const double* const* uy0, const double* const* fx,
                    const double* const* fy, lbm_batch* out);
-/* mode: LBM_BATCH_PERSISTENT or LBM_BATCH_PER_STEP; chunk: even number of
- * steps per graph replay (2..100000). */
+/* mode: LBM_BATCH_PERSISTENT, LBM_BATCH_PER_STEP or LBM_BATCH_MULTI_STEP;
+ * chunk: even number of steps per graph replay (2..100000). */
 LBM_API int lbm_batch_set_mode(lbm_batch b, int32_t mode, int32_t chunk);
 /* Work-item shape: block_threads (256, 512 or 1024) threads per workgroup;
  * vx (1, 2 or 4, dividing every run's nx) sites per thread; band_rows (1..64)
  * groups of block_threads*vx consecutive sites per work item. */
 LBM_API int lbm_batch_set_tile(lbm_batch b, int32_t block_threads, int32_t vx, int32_t band_rows);
-/* Time every (mode, block_threads, vx, band_rows) candidate over trial_steps
- * (even) steps and keep the fastest; the chosen mode is readable with
- * lbm_batch_get_mode.  The trials are real steps: the ensemble advances by
- * (2 + trial_steps) per candidate and lbm_batch_time says so. */
+/* Shape of the multi-step mode: t->fuse = K (2..4) steps per launch, t->bx =
+ * strip width (a multiple of 64, at most 512), t->ry = band height (>= 8
+ * rows), t->nt = non-temporal stores; by = vx = 1.  The next-row loads are
+ * always issued early (pf = 1). */
+LBM_API int lbm_batch_set_multi(lbm_batch b, const lbm_tile* t);
+LBM_API int lbm_batch_get_multi(lbm_batch b, lbm_tile* t);
+/* Time every (mode, block_threads, vx, band_rows) candidate and every
+ * multi-step shape over about trial_steps (even) steps and keep the fastest
+ * per step; the chosen mode is readable with lbm_batch_get_mode, the
+ * multi-step shape with lbm_batch_get_multi.  The trials are real steps: the
+ * ensemble advances by them and lbm_batch_time says so. */
 LBM_API int lbm_batch_autotune(lbm_batch b, int32_t trial_steps, int32_t* block_threads,
                        int32_t* vx, int32_t* band_rows);
 LBM_API int lbm_batch_get_mode(lbm_batch b, int32_t* mode, int32_t* chunk);

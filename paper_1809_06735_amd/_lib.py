@@ -27,6 +27,7 @@ LBM_LAYOUT_ROWS = 1
 LAYOUTS = {"planes": LBM_LAYOUT_PLANES, "rows": LBM_LAYOUT_ROWS}
 LBM_BATCH_PERSISTENT = 0
 LBM_BATCH_PER_STEP = 1
+LBM_BATCH_MULTI_STEP = 2
 NTERMS = 13
 TERM_NAMES = ("lhs_E", "e1", "e2", "e3", "e4", "e5",
               "lhs_Z", "z1", "z2", "z3", "z4", "z5", "usq")
@@ -116,6 +117,8 @@ SIGNATURES = {
     "lbm_batch_set_tile": (_I, [_P, _I32, _I32, _I32]),
     "lbm_batch_autotune": (_I, [_P, _I32, C.POINTER(_I32), C.POINTER(_I32), C.POINTER(_I32)]),
     "lbm_batch_get_mode": (_I, [_P, C.POINTER(_I32), C.POINTER(_I32)]),
+    "lbm_batch_set_multi": (_I, [_P, C.POINTER(Tile)]),
+    "lbm_batch_get_multi": (_I, [_P, C.POINTER(Tile)]),
     "lbm_batch_step": (_I, [_P, _I64]),
     "lbm_batch_moments": (_I, [_P, _I32, _P, _P, _P, _I32, _DP]),
     "lbm_batch_time": (_I, [_P, C.POINTER(_I64)]),

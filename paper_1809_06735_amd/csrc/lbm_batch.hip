@@ -7,8 +7,11 @@
 // workgroups meet at a grid-wide barrier (an atomic counter with a bounded
 // wait: a wait that runs out sets an error flag and the kernel exits instead
 // of hanging).  Per-step mode: one ordinary launch per step over the same list.
-// Both are captured into hipGraphs and replayed.  The arithmetic per site is
-// the single-grid step's (pull, BGK collide, Guo force, drag).
+// Multi-step mode: one launch advances every run by K steps, its workgroups
+// taking the (run, strip, band) tiles of the single-grid multi-step kernel
+// (temporal blocking through LDS).  All modes are captured into hipGraphs and
+// replayed.  The arithmetic per site is the single-grid step's (pull, BGK
+// collide, Guo force, drag).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -16,6 +19,7 @@
 #include <cstdlib>
 #include <vector>
 
+#include "lbm_fused.h"
 #include "lbm_internal.h"
 #include "lbm_site.h"
 
@@ -187,6 +191,62 @@ __global__ void __launch_bounds__(kBTMax) k_batch_step(BatchArgs a) {
   process_item<T, VX>(a, blockIdx.x, a.parity0);
 }
 
+// Multi-step mode: item it (XCD-aware numbering) is tile item_tile[it] of run
+// item_run[it]; every run advances K steps from buffer `parity`.
+struct FusedArgs {
+  const RunDesc* runs;
+  const int* item_run;
+  const int* item_tile;
+  int nitems;
+  int per_xcd;
+  int W, H;
+  int parity;
+};
+
+template <typename T, int K, bool NT>
+__global__ void __launch_bounds__(fused_detail::kFusedMaxThreads) k_batch_fused(FusedArgs a) {
+  extern __shared__ unsigned char smem_raw[];
+  const int b = blockIdx.x;
+  const int it = (b & 7) * a.per_xcd + (b >> 3);
+  if (it >= a.nitems) return;  // uniform over the workgroup
+  const RunDesc r = a.runs[a.item_run[it]];
+  StepParams p{};
+  p.src = r.pop[a.parity];
+  p.dst = r.pop[a.parity ^ 1];
+  p.fx = r.fx;
+  p.fy = r.fy;
+  p.nx = r.nx;
+  p.ny = r.ny;
+  p.ps = r.ps;
+  p.rs = r.rs;
+  p.omega = r.omega;
+  p.alpha = r.alpha;
+  const int strips = (r.nx + a.W - 1) / a.W;
+  T* const lds = reinterpret_cast<T*>(smem_raw);
+  if (r.forced)
+    fused_detail::fused_tile<T, K, true, NT, true>(p, lds, a.W, a.H, strips, a.item_tile[it]);
+  else
+    fused_detail::fused_tile<T, K, false, NT, true>(p, lds, a.W, a.H, strips, a.item_tile[it]);
+}
+
+template <typename T, int K>
+void launch_batch_fused_k(const FusedArgs& a, bool nt, hipStream_t s) {
+  const size_t lds = fused_lds_bytes(a.W, K, sizeof(T) == 8 ? LBM_F64 : LBM_F32);
+  if (nt)
+    hipLaunchKernelGGL((k_batch_fused<T, K, true>), dim3(a.per_xcd * 8), dim3(a.W + 64), lds, s, a);
+  else
+    hipLaunchKernelGGL((k_batch_fused<T, K, false>), dim3(a.per_xcd * 8), dim3(a.W + 64), lds, s, a);
+}
+
+template <typename T>
+void launch_batch_fused(int K, const FusedArgs& a, bool nt, hipStream_t s) {
+  switch (K) {
+    case 2: launch_batch_fused_k<T, 2>(a, nt, s); break;
+    case 3: launch_batch_fused_k<T, 3>(a, nt, s); break;
+    default: launch_batch_fused_k<T, 4>(a, nt, s); break;
+  }
+}
+
 __global__ void k_batch_reset(unsigned* barrier) {
   for (int i = threadIdx.x; i < kBarrierWords; i += blockDim.x) barrier[i] = 0u;
 }
@@ -245,6 +305,11 @@ struct lbm_batch_s {
   int* d_item_run = nullptr;
   int* d_item_start = nullptr;
   size_t item_cap = 0;
+  int* d_fitem_run = nullptr;    // multi-step work list: (run, tile)
+  int* d_fitem_tile = nullptr;
+  size_t fitem_cap = 0;
+  int nfitems = 0;
+  lbm_tile ftile{256, 1, 1, 64, 1, 4, 1};  // multi-step shape: strip, band, K, nt
   unsigned* d_barrier = nullptr;
   int* d_error = nullptr;
   double* d_partials = nullptr;
@@ -271,6 +336,9 @@ struct BatchLayout {
   RunDesc* runs;
   int* item_run;
   int* item_start;
+  int* fitem_run;
+  int* fitem_tile;
+  size_t fitem_cap;
   unsigned* barrier;
   int* error;
   double* partials;
@@ -286,6 +354,15 @@ size_t max_items(const lbm_config* cfgs, int nruns) {
     const size_t plane = static_cast<size_t>(cfgs[r].nx) * cfgs[r].ny;
     n += (plane + kBT - 1) / kBT;
   }
+  return n;
+}
+
+// multi-step tiles: strips of >= 64 columns, bands of >= 8 rows
+constexpr int kMinFusedBand = 8;
+size_t max_fused_items(const lbm_config* cfgs, int nruns) {
+  size_t n = 0;
+  for (int r = 0; r < nruns; ++r)
+    n += static_cast<size_t>((cfgs[r].nx + 63) / 64) * ((cfgs[r].ny + kMinFusedBand - 1) / kMinFusedBand);
   return n;
 }
 
@@ -311,6 +388,9 @@ BatchLayout carve_batch(const lbm_config* cfgs, int nruns, void* base, size_t ca
   l.item_cap = max_items(cfgs, nruns);
   l.item_run = cv.take<int>(l.item_cap);
   l.item_start = cv.take<int>(l.item_cap);
+  l.fitem_cap = max_fused_items(cfgs, nruns);
+  l.fitem_run = cv.take<int>(l.fitem_cap);
+  l.fitem_tile = cv.take<int>(l.fitem_cap);
   l.barrier = cv.take<unsigned>(kBarrierWords);
   l.error = cv.take<int>(64);
   l.partials = cv.take<double>(static_cast<size_t>(maxblocks) * 8 + 8);
@@ -344,9 +424,25 @@ int build_items(lbm_batch_s* b) {
   }
   if (ir_run.size() > b->item_cap) return fail(LBM_E_INVALID, "work list exceeds its capacity");
   b->nitems = static_cast<int>(ir_run.size());
+  // multi-step tiles of every run
+  std::vector<int> f_run, f_tile;
+  for (int r = 0; r < b->nruns; ++r) {
+    const int strips = (b->cfg[r].nx + b->ftile.bx - 1) / b->ftile.bx;
+    const int bands = (b->cfg[r].ny + b->ftile.ry - 1) / b->ftile.ry;
+    for (int t = 0; t < strips * bands; ++t) {
+      f_run.push_back(r);
+      f_tile.push_back(t);
+    }
+  }
+  if (f_run.size() > b->fitem_cap) return fail(LBM_E_INVALID, "multi-step work list exceeds its capacity");
+  b->nfitems = static_cast<int>(f_run.size());
   LBM_HIP(hipMemcpyAsync(b->d_item_run, ir_run.data(), ir_run.size() * sizeof(int),
                          hipMemcpyHostToDevice, b->stream));
   LBM_HIP(hipMemcpyAsync(b->d_item_start, ir_start.data(), ir_start.size() * sizeof(int),
+                         hipMemcpyHostToDevice, b->stream));
+  LBM_HIP(hipMemcpyAsync(b->d_fitem_run, f_run.data(), f_run.size() * sizeof(int),
+                         hipMemcpyHostToDevice, b->stream));
+  LBM_HIP(hipMemcpyAsync(b->d_fitem_tile, f_tile.data(), f_tile.size() * sizeof(int),
                          hipMemcpyHostToDevice, b->stream));
   LBM_HIP(hipStreamSynchronize(b->stream));
   int occ = 0;
@@ -382,9 +478,42 @@ BatchArgs make_args(lbm_batch_s* b, int parity0, int nsteps) {
   return a;
 }
 
+// Launches (buffer swaps) that n steps take in the current mode.
+int step_launches(const lbm_batch_s* b, int n) {
+  if (b->mode != LBM_BATCH_MULTI_STEP) return n;
+  return n / b->ftile.fuse + n % b->ftile.fuse;
+}
+
 // Enqueue `n` steps starting from buffer parity `par` on stream s.
 int enqueue_steps(lbm_batch_s* b, int par, int n, hipStream_t s) {
   if (n <= 0) return LBM_OK;
+  if (b->mode == LBM_BATCH_MULTI_STEP) {
+    const int K = b->ftile.fuse;
+    FusedArgs f{};
+    f.runs = b->d_runs;
+    f.item_run = b->d_fitem_run;
+    f.item_tile = b->d_fitem_tile;
+    f.nitems = b->nfitems;
+    f.per_xcd = (b->nfitems + 7) / 8;
+    f.W = b->ftile.bx;
+    f.H = b->ftile.ry;
+    int p = par;
+    for (int k = 0; k + K <= n; k += K) {
+      f.parity = p;
+      if (b->dtype == LBM_F32) launch_batch_fused<float>(K, f, b->ftile.nt != 0, s);
+      else launch_batch_fused<double>(K, f, b->ftile.nt != 0, s);
+      LBM_HIP(hipGetLastError());
+      p ^= 1;
+    }
+    for (int k = 0; k < n % K; ++k) {  // the remainder, one step per launch
+      BatchArgs a = make_args(b, p, 1);
+      if (b->dtype == LBM_F32) launch_batch_vx<float>(b->vx, false, a, 0, s);
+      else launch_batch_vx<double>(b->vx, false, a, 0, s);
+      LBM_HIP(hipGetLastError());
+      p ^= 1;
+    }
+    return LBM_OK;
+  }
   if (b->mode == LBM_BATCH_PERSISTENT) {
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, b->d_barrier);
     LBM_HIP(hipGetLastError());
@@ -467,6 +596,9 @@ int lbm_batch_init(const lbm_config* cfgs, int32_t nruns, void* ws, size_t ws_by
   b->d_item_run = l.item_run;
   b->d_item_start = l.item_start;
   b->item_cap = l.item_cap;
+  b->d_fitem_run = l.fitem_run;
+  b->d_fitem_tile = l.fitem_tile;
+  b->fitem_cap = l.fitem_cap;
   b->d_barrier = l.barrier;
   b->d_error = l.error;
   b->d_partials = l.partials;
@@ -521,8 +653,8 @@ int lbm_batch_init(const lbm_config* cfgs, int32_t nruns, void* ws, size_t ws_by
 
 int lbm_batch_set_mode(lbm_batch b, int32_t mode, int32_t chunk) {
   if (!b) return fail(LBM_E_INVALID, "batch is NULL");
-  if (mode != LBM_BATCH_PERSISTENT && mode != LBM_BATCH_PER_STEP)
-    return fail(LBM_E_INVALID, "mode must be LBM_BATCH_PERSISTENT or LBM_BATCH_PER_STEP");
+  if (mode != LBM_BATCH_PERSISTENT && mode != LBM_BATCH_PER_STEP && mode != LBM_BATCH_MULTI_STEP)
+    return fail(LBM_E_INVALID, "mode must be LBM_BATCH_PERSISTENT, _PER_STEP or _MULTI_STEP");
   if (chunk < 2 || chunk % 2 || chunk > 100000) return fail(LBM_E_INVALID, "chunk: even, 2..100000");
   b->mode = mode;
   b->chunk = chunk;
@@ -545,6 +677,23 @@ int lbm_batch_set_tile(lbm_batch b, int32_t block_threads, int32_t vx, int32_t b
   return build_items(b);
 }
 
+int lbm_batch_set_multi(lbm_batch b, const lbm_tile* t) {
+  if (!b || !t) return fail(LBM_E_INVALID, "NULL argument");
+  if (t->fuse < 2 || t->fuse > 4 || !fused_tile_ok(*t, b->dtype) || t->ry < kMinFusedBand)
+    return fail(LBM_E_INVALID, "multi-step shape: fuse 2..4, strip a multiple of 64 up to 512, "
+                               "band >= %d rows", kMinFusedBand);
+  b->ftile = *t;
+  b->ftile.pf = 1;
+  drop_batch_graphs(b);
+  return build_items(b);
+}
+
+int lbm_batch_get_multi(lbm_batch b, lbm_tile* t) {
+  if (!b || !t) return fail(LBM_E_INVALID, "NULL argument");
+  *t = b->ftile;
+  return LBM_OK;
+}
+
 int lbm_batch_step(lbm_batch b, int64_t n) {
   if (!b) return fail(LBM_E_INVALID, "batch is NULL");
   if (n < 0) return fail(LBM_E_INVALID, "n must be >= 0");
@@ -554,10 +703,11 @@ int lbm_batch_step(lbm_batch b, int64_t n) {
     LBM_HIP(hipGraphLaunch(b->gexec[b->cur], b->stream));
     n -= b->chunk;
     b->t += b->chunk;
+    b->cur = (b->cur + step_launches(b, b->chunk)) & 1;
   }
   if (n > 0) {
     if (int rc = enqueue_steps(b, b->cur, static_cast<int>(n), b->stream)) return rc;
-    b->cur = (b->cur + static_cast<int>(n)) & 1;
+    b->cur = (b->cur + step_launches(b, static_cast<int>(n))) & 1;
     b->t += n;
   }
   return LBM_OK;
@@ -569,18 +719,46 @@ int lbm_batch_autotune(lbm_batch b, int32_t trial_steps, int32_t* block_threads,
   if (trial_steps < 2 || trial_steps > 1000 || trial_steps % 2)
     return fail(LBM_E_INVALID, "trial_steps: even, 2..1000");
   const int saved_vx = b->vx, saved_ir = b->ir, saved_bt = b->bt, saved_mode = b->mode;
+  const lbm_tile saved_f = b->ftile;
   hipEvent_t e0, e1;
   LBM_HIP(hipEventCreate(&e0));
   LBM_HIP(hipEventCreate(&e1));
-  float best = 1e30f;
+  float best = 1e30f, best_multi = 1e30f;  // milliseconds per step
   int bvx = saved_vx, bir = saved_ir, bbt = saved_bt, bmode = saved_mode;
+  lbm_tile bf = saved_f;  // fastest multi-step shape, kept whichever mode wins
   int rc = LBM_OK;
+  // one timed trial of the current settings: a warm-up of two steps, then
+  // `steps` steps; the ensemble really advances, the time counter records it
+  auto trial = [&](int steps) -> int {
+    if (int r = build_items(b)) return r;
+    if (int r = enqueue_steps(b, b->cur, 2, b->stream)) return r;
+    b->cur = (b->cur + step_launches(b, 2)) & 1;
+    if (hipEventRecord(e0, b->stream) != hipSuccess) return fail(LBM_E_HIP, "event");
+    if (int r = enqueue_steps(b, b->cur, steps, b->stream)) return r;
+    b->cur = (b->cur + step_launches(b, steps)) & 1;
+    if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+      return fail(LBM_E_HIP, "event");
+    b->t += 2 + steps;
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    ms /= static_cast<float>(steps);
+    if (ms < best) {
+      best = ms;
+      bvx = b->vx;
+      bir = b->ir;
+      bbt = b->bt;
+      bmode = b->mode;
+    }
+    if (b->mode == LBM_BATCH_MULTI_STEP && ms < best_multi) {
+      best_multi = ms;
+      bf = b->ftile;
+    }
+    return LBM_OK;
+  };
   const int modes[2] = {LBM_BATCH_PERSISTENT, LBM_BATCH_PER_STEP};
   const int bts[2] = {256, 1024};
   const int vxs[3] = {1, 2, 4};
   const int irs[3] = {1, 2, 4};
-  // every trial advances the ensemble by 2 + trial_steps real steps (an even
-  // count, so the buffer parity is unchanged) and the time counter records it
   for (int mode : modes) {
     for (int bt : bts) {
       for (int v : vxs) {
@@ -592,30 +770,36 @@ int lbm_batch_autotune(lbm_batch b, int32_t trial_steps, int32_t* block_threads,
           b->bt = bt;
           b->vx = v;
           b->ir = i;
-          if ((rc = build_items(b)) != LBM_OK) break;
-          if ((rc = enqueue_steps(b, b->cur, 2, b->stream)) != LBM_OK) break;
-          if (hipEventRecord(e0, b->stream) != hipSuccess) { rc = fail(LBM_E_HIP, "event"); break; }
-          if ((rc = enqueue_steps(b, b->cur, trial_steps, b->stream)) != LBM_OK) break;
-          if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-            rc = fail(LBM_E_HIP, "event");
-            break;
-          }
-          b->t += 2 + trial_steps;
-          float ms = 0.f;
-          (void)hipEventElapsedTime(&ms, e0, e1);
-          if (ms < best) {
-            best = ms;
-            bvx = v;
-            bir = i;
-            bbt = bt;
-            bmode = mode;
-          }
+          if ((rc = trial(trial_steps)) != LBM_OK) break;
         }
         if (rc) break;
       }
       if (rc) break;
     }
     if (rc) break;
+  }
+  // multi-step shapes (remainder steps use the fastest single-step work list)
+  if (rc == LBM_OK) {
+    const int kbvx = bvx, kbir = bir, kbbt = bbt;
+    b->vx = kbvx;
+    b->ir = kbir;
+    b->bt = kbbt;
+    b->mode = LBM_BATCH_MULTI_STEP;
+    const int ws[3] = {128, 256, 512};
+    const int hs[3] = {32, 64, 128};
+    for (int K = 2; K <= 4 && rc == LBM_OK; ++K)
+      for (int w = 0; w < 3 && rc == LBM_OK; ++w)
+        for (int h : hs) {
+          lbm_tile t{ws[w], 1, 1, h, 1, K, 1};
+          if (!fused_tile_ok(t, b->dtype)) continue;
+          b->ftile = t;
+          // a whole number of K-step launches
+          if ((rc = trial(K * ((trial_steps + K - 1) / K))) != LBM_OK) break;
+          // the single-step work list is the one found above whatever wins here
+          bvx = kbvx;
+          bir = kbir;
+          bbt = kbbt;
+        }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -625,6 +809,7 @@ int lbm_batch_autotune(lbm_batch b, int32_t trial_steps, int32_t* block_threads,
   b->ir = ok ? bir : saved_ir;
   b->bt = ok ? bbt : saved_bt;
   b->mode = ok ? bmode : saved_mode;
+  b->ftile = ok ? bf : saved_f;
   drop_batch_graphs(b);
   if (int r2 = build_items(b)) return rc ? rc : r2;
   if (rc) return rc;

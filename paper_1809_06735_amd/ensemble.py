@@ -10,7 +10,8 @@ import torch
 from . import _lib as L
 from .sim import _dev64, _ptr, _require_gpu, _stream_handle
 
-MODES = {"persistent": L.LBM_BATCH_PERSISTENT, "per_step": L.LBM_BATCH_PER_STEP}
+MODES = {"persistent": L.LBM_BATCH_PERSISTENT, "per_step": L.LBM_BATCH_PER_STEP,
+         "multi_step": L.LBM_BATCH_MULTI_STEP}
 
 
 class Ensemble:
@@ -88,6 +89,17 @@ class Ensemble:
         L.check(self._lib.lbm_batch_set_tile(self._h, int(block_threads), int(vx), int(groups)),
                 "lbm_batch_set_tile")
 
+    def set_multi(self, steps_per_launch, strip, band, nt=1):
+        """Shape of the multi-step mode (K steps per launch over strip x band tiles)."""
+        t = L.Tile(int(strip), 1, 1, int(band), int(nt), int(steps_per_launch), 1)
+        L.check(self._lib.lbm_batch_set_multi(self._h, C.byref(t)), "lbm_batch_set_multi")
+
+    def get_multi(self):
+        """(steps_per_launch, strip, band, nt) of the multi-step mode."""
+        t = L.Tile()
+        L.check(self._lib.lbm_batch_get_multi(self._h, C.byref(t)), "lbm_batch_get_multi")
+        return t.fuse, t.bx, t.ry, t.nt
+
     def get_mode(self):
         m, c = C.c_int32(), C.c_int32()
         L.check(self._lib.lbm_batch_get_mode(self._h, C.byref(m), C.byref(c)), "lbm_batch_get_mode")
@@ -128,8 +140,9 @@ def _timed(fn):
 
 
 def bench_ensemble(nruns=64, steps=500, log=print):
-    """MLUPS of the 64-run decaying ensemble (sizes 256^2..1024^2, FP32): persistent and
-    per-step modes, against the plain single-grid step run member by member."""
+    """MLUPS of the 64-run decaying ensemble (sizes 256^2..1024^2, FP32) in the persistent,
+    per-step and multi-step modes, against the plain single-grid step (autotuned, multi-step
+    shapes included) run member by member."""
     import lbm_inputs as inp
     from .sim import Simulation
 
@@ -137,15 +150,19 @@ def bench_ensemble(nruns=64, steps=500, log=print):
     members = inp.ensemble_members(nruns)
     ens = Ensemble(members, dtype="f32", mode="persistent", chunk=100)
     sites = ens.sites
-    tile = ens.autotune(trial_steps=10)
-    out = {"runs": nruns, "sites": sites, "autotuned": {"mode": ens.mode, "block_threads": tile[0],
-                                                        "vx": tile[1], "groups": tile[2]}}
-    for mode in ("persistent", "per_step"):
+    tile = ens.autotune(trial_steps=12)
+    multi = ens.get_multi()
+    out = {"runs": nruns, "sites": sites,
+           "autotuned": {"mode": ens.mode, "block_threads": tile[0], "vx": tile[1], "groups": tile[2],
+                         "multi_step": {"steps_per_launch": multi[0], "strip": multi[1],
+                                        "band": multi[2], "nt": multi[3]}}}
+    for mode in ("persistent", "per_step", "multi_step"):
         ens.set_mode(mode, 100)
         ens.step(100)                      # warm-up, builds the graph
         dt = _timed(lambda: ens.step(steps))
         out[f"{mode}_MLUPS"] = round(sites * steps / dt / 1e6, 1)
-        log(f"[ensemble] {mode} (tile {tile}): {out[f'{mode}_MLUPS']} MLUPS")
+        shape = multi if mode == "multi_step" else tile
+        log(f"[ensemble] {mode} (shape {shape}): {out[f'{mode}_MLUPS']} MLUPS")
     r, _, _, sc = ens.moments(0)
     out["finite"] = bool(sc["nonfinite"] == 0)
     ens.close()

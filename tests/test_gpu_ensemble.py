@@ -35,7 +35,7 @@ def small_members(seed=0):
     return out
 
 
-@pytest.mark.parametrize("mode", ["persistent", "per_step"])
+@pytest.mark.parametrize("mode", ["persistent", "per_step", "multi_step"])
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_ensemble_matches_single_grid_and_oracle(gpu_lib, mode, dtype):
     from paper_1809_06735_amd import Simulation
@@ -43,6 +43,8 @@ def test_ensemble_matches_single_grid_and_oracle(gpu_lib, mode, dtype):
     say(f"ensemble small {mode} {dtype}")
     mem = small_members()
     ens = Ensemble(mem, dtype=dtype, mode=mode, chunk=8)
+    if mode == "multi_step":
+        ens.set_multi(3, 64, 8)     # several strips and bands per member
     steps = 21                      # two graph replays + an odd remainder
     ens.step(steps)
     assert ens.time == steps
@@ -99,8 +101,45 @@ def test_ensemble_tiles_and_autotune_keep_results(gpu_lib):
     t = Ensemble(mem, mode="persistent", chunk=6)
     bt, vx, g = t.autotune(trial_steps=4)
     assert bt in (256, 1024) and vx in (1, 2, 4) and 1 <= g <= 64
-    assert t.get_mode()[0] in ("persistent", "per_step")
-    assert t.time > 0 and t.time % 2 == 0
+    assert t.get_mode()[0] in ("persistent", "per_step", "multi_step")
+    k, w, h, nt = t.get_multi()
+    assert 2 <= k <= 4 and w in (128, 256, 512) and h in (32, 64, 128)
+    assert t.time > 0
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_multi_step_mode_equals_per_step_bitwise(gpu_lib, dtype):
+    """K steps per launch over (run, strip, band) tiles: bit-identical to one launch per
+    step for every member, with forced and unforced members, ragged tiles, remainders and
+    graph chunks whose launch count is odd (the buffer parity flips per replay)."""
+    from paper_1809_06735_amd import LBMError
+    from paper_1809_06735_amd.ensemble import Ensemble
+    mem = small_members(3)
+    ref_e = Ensemble(mem, dtype=dtype, mode="per_step", chunk=4)
+    ref_e.step(7)
+    r7 = [ref_e.moments(r, scalars=False) for r in range(len(mem))]
+    ref_e.step(30)
+    r37 = [ref_e.moments(r, scalars=False) for r in range(len(mem))]
+    ref_e.close()
+    for (k, w, h, nt, chunk) in ((2, 64, 8, 1, 4), (3, 64, 16, 0, 6), (4, 128, 8, 1, 10),
+                                 (4, 64, 32, 1, 2), (3, 512, 64, 1, 8)):
+        e = Ensemble(mem, dtype=dtype, mode="multi_step", chunk=chunk)
+        e.set_multi(k, w, h, nt)
+        assert e.get_multi() == (k, w, h, nt)
+        e.step(7)
+        for r in range(len(mem)):
+            for x, y in zip(e.moments(r, scalars=False), r7[r]):
+                assert torch.equal(x, y), (k, w, h, chunk, r, 7)
+        e.step(30)
+        for r in range(len(mem)):
+            for x, y in zip(e.moments(r, scalars=False), r37[r]):
+                assert torch.equal(x, y), (k, w, h, chunk, r, 37)
+        e.close()
+    e = Ensemble(mem, dtype=dtype, mode="multi_step", chunk=4)
+    for bad in ((5, 64, 8), (1, 64, 8), (2, 96, 8), (2, 64, 4), (2, 1024, 8)):
+        with pytest.raises(LBMError):
+            e.set_multi(*bad)
+    e.close()
 
 
 def test_ensemble64_workload_sampled(gpu_lib):
