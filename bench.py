@@ -41,7 +41,7 @@ def log(*a):
 
 
 KERNEL_SOURCES = {"k_step": ("lbm_step.hip", "lbm_site.h"),
-                  "k_step_fused": ("lbm_step_fused.hip", "lbm_site.h")}
+                  "k_step_fused": ("lbm_step_fused.hip", "lbm_fused.h", "lbm_site.h")}
 
 
 def step_source_digest(kernel="k_step_fused"):
@@ -60,15 +60,15 @@ def traffic_from_profile(kernel, workload, tile):
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.md")
     if not os.path.exists(path):
         return None
-    rec = None
     for line in open(path):
-        if line.startswith("TRAFFIC_JSON:"):
-            rec = json.loads(line.split(":", 1)[1])
-    if not rec or rec.get("source_sha256_16") != step_source_digest(kernel):
-        return None
-    if rec.get("tile") is not None and list(rec["tile"]) != list(tile):
-        return None
-    return rec.get("bytes_per_launch")
+        if not line.startswith("TRAFFIC_JSON:"):
+            continue
+        rec = json.loads(line.split(":", 1)[1])
+        if rec.get("source_sha256_16") != step_source_digest(kernel):
+            return None
+        if list(rec.get("tile", [])) == list(tile):
+            return rec.get("bytes_per_launch")
+    return None
 
 
 def single_step_kernel(n, tau, alpha, fx, fy, steps=400):
@@ -95,8 +95,10 @@ def single_step_kernel(n, tau, alpha, fx, fy, steps=400):
     s.close()
     shape, per = best
     gbs = 80 * n * n / per / 1e9
-    return {"shape": list(shape), "avg_launch_us": round(per * 1e6, 2), "GBps": round(gbs, 1),
-            "frac_of_8TBps": round(gbs / HBM_PEAK_GBS, 4), "kernel_MLUPS": round(n * n / per / 1e6, 1)}
+    tile = tuple(shape) + (1, 0)
+    return {"shape": list(tile), "avg_launch_us": round(per * 1e6, 2), "GBps": round(gbs, 1),
+            "frac_of_8TBps": round(gbs / HBM_PEAK_GBS, 4), "kernel_MLUPS": round(n * n / per / 1e6, 1),
+            "traffic": traffic_from_profile("k_step", "forced4096", tile)}
 
 
 def cpu_baseline(n, tau, alpha, fx, fy, steps):
