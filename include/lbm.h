@@ -216,6 +216,12 @@ LBM_API int lbm_load(lbm_ctx ctx, const void* src_device);
 LBM_API int lbm_set_tile(lbm_ctx ctx, const lbm_tile* tile);
 LBM_API int lbm_get_tile(lbm_ctx ctx, lbm_tile* tile);
 LBM_API int lbm_autotune(lbm_ctx ctx, int32_t trial_steps, lbm_tile* chosen);
+/* Record `tile` in the same process-wide table (and cache file) for the grid
+ * described by cfg (dtype, nx, ny, forced or not, layout), as if lbm_autotune
+ * had chosen it: later handles of that grid start with it and lbm_adjoint_run
+ * uses it for its first forward pass.  Host call; LBM_E_INVALID for a shape
+ * the grid does not accept. */
+LBM_API int lbm_set_tuned_tile(const lbm_config* cfg, const lbm_tile* tile);
 
 /* hipGraph replay of `chunk` (even, >= 2) step launches for long lbm_step
  * calls; chunk = 0 launches every step directly. */

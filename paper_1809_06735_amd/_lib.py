@@ -103,6 +103,7 @@ SIGNATURES = {
     "lbm_set_tile": (_I, [_P, C.POINTER(Tile)]),
     "lbm_get_tile": (_I, [_P, C.POINTER(Tile)]),
     "lbm_autotune": (_I, [_P, _I32, C.POINTER(Tile)]),
+    "lbm_set_tuned_tile": (_I, [C.POINTER(Config), C.POINTER(Tile)]),
     "lbm_set_graph": (_I, [_P, _I32]),
     "lbm_step_timing": (_I, [_P, _I32]),
     "lbm_step_time": (_I, [_P, _DP, C.POINTER(_I64), _I32]),

@@ -328,7 +328,7 @@ __global__ void __launch_bounds__(512) k_adj_step(const T* __restrict__ g, const
       }
 #pragma unroll
       for (int l = 0; l < 9; ++l)
-        store_aligned<T, VX, true>(aout + l * lay.ps + static_cast<size_t>(y) * lay.rs + x0, o[l]);
+        store_aligned<T, VX, false>(aout + l * lay.ps + static_cast<size_t>(y) * lay.rs + x0, o[l]);
     }
   }
 #pragma unroll
@@ -487,14 +487,16 @@ struct Runner {
   AdjWs w;
   hipStream_t s;
   size_t plane, state_bytes;
-  lbm_tile tile;
+  lbm_tile tile;   // single-step shape (the segments keep every intermediate state)
+  lbm_tile ftile;  // shape of the first forward pass, which keeps only checkpoints
   void* seg_state(int k) const { return static_cast<char*>(w.seg) + k * state_bytes; }
   void* ckpt_state(int64_t k) const { return static_cast<char*>(w.ckpt) + k * state_bytes; }
 
   int step(const void* src, void* dst, double* hr, double* hx, double* hy) {
     return step_on(s, src, dst, hr, hx, hy);
   }
-  int step_on(hipStream_t st, const void* src, void* dst, double* hr, double* hx, double* hy) {
+  int step_on(hipStream_t st, const void* src, void* dst, double* hr, double* hx, double* hy,
+              bool multi = false) {
     StepParams p{};
     p.src = src;
     p.dst = dst;
@@ -508,7 +510,7 @@ struct Runner {
     p.rs = lay.rs;
     p.omega = 1.0 / c.tau;
     p.alpha = 0.0;
-    return launch_step(c.dtype, false, p, tile, st);
+    return launch_step(c.dtype, false, p, multi ? ftile : tile, st);
   }
 };
 
@@ -517,6 +519,7 @@ struct GraphCache {
   hipStream_t cs = nullptr;
   hipStream_t main = nullptr;   // replays go here; synchronised before the graphs are freed
   hipGraphExec_t fwd = nullptr;
+  hipGraphExec_t ffwd = nullptr;  // first pass: K steps, intermediate states not kept
   hipGraphExec_t bwd[2] = {nullptr, nullptr};
   int init() {
     LBM_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
@@ -541,6 +544,7 @@ struct GraphCache {
   ~GraphCache() {
     if (main) (void)hipStreamSynchronize(main);
     if (fwd) (void)hipGraphExecDestroy(fwd);
+    if (ffwd) (void)hipGraphExecDestroy(ffwd);
     for (auto& b : bwd)
       if (b) (void)hipGraphExecDestroy(b);
     if (cs) (void)hipStreamDestroy(cs);
@@ -581,9 +585,16 @@ int lbm_adjoint_run(const lbm_adjoint_config* cfg, void* ws, size_t ws_bytes, co
   R.state_bytes = 9 * R.plane * (cfg->dtype == LBM_F32 ? 4 : 8);
   // the single-step shape tuned for this grid if lbm_autotune has seen it, else the default
   // (the segments keep every intermediate state, so each launch advances one step)
-  if (!tuned_tile(cfg->dtype, cfg->nx, cfg->ny, false, kAdjLayout, &R.tile) ||
-      steps_per_launch(R.tile) != 1)
-    R.tile = default_tile(cfg->dtype, cfg->nx, cfg->ny, kAdjLayout);
+  // and, for the first forward pass, the tuned shape whatever its steps per launch
+  lbm_tile tuned{};
+  const bool have_tuned = tuned_tile(cfg->dtype, cfg->nx, cfg->ny, false, kAdjLayout, &tuned);
+  R.tile = (have_tuned && steps_per_launch(tuned) == 1)
+               ? tuned
+               : default_tile(cfg->dtype, cfg->nx, cfg->ny, kAdjLayout);
+  R.ftile = have_tuned ? tuned : R.tile;
+  // the recomputed states and the adjoint fields are read again within a few
+  // launches: keep their stores cacheable
+  R.tile.nt = 0;
   const int nx = cfg->nx, ny = cfg->ny;
   const int64_t T = cfg->steps;
   const int K = cfg->ckpt_every;
@@ -633,7 +644,36 @@ int lbm_adjoint_run(const lbm_adjoint_config* cfg, void* ws, size_t ws_bytes, co
     }
     return LBM_OK;
   };
+  // First pass over a full segment: only its end state is kept (the next
+  // checkpoint), so it runs in the tuned shape, possibly several steps per
+  // launch, ping-ponging between seg[0] and seg[1]; returns the final buffer.
+  const int spl = steps_per_launch(R.ftile);
+  const int ff_par = (K / spl + K % spl) & 1;
+  auto fast_segment = [&](int64_t sg) -> int {
+    LBM_HIP(hipMemcpyAsync(R.seg_state(0), R.ckpt_state(sg), R.state_bytes, hipMemcpyDeviceToDevice, s));
+    if (!gc.ffwd) {
+      if (int rc = gc.capture(&gc.ffwd, [&](hipStream_t cs) -> int {
+            int p = 0;
+            for (int k = 0; k + spl <= K; k += spl, p ^= 1)
+              if (int r2 = R.step_on(cs, R.seg_state(p), R.seg_state(p ^ 1), nullptr, nullptr, nullptr, true))
+                return r2;
+            for (int k = 0; k < K % spl; ++k, p ^= 1)
+              if (int r2 = R.step_on(cs, R.seg_state(p), R.seg_state(p ^ 1), nullptr, nullptr, nullptr))
+                return r2;
+            return LBM_OK;
+          }))
+        return rc;
+    }
+    LBM_HIP(hipGraphLaunch(gc.ffwd, s));
+    return LBM_OK;
+  };
   for (int64_t sg = 0; sg < nseg; ++sg) {
+    if (seg_plain(sg) && sg + 1 < nseg) {
+      if (int rc = fast_segment(sg)) return rc;
+      LBM_HIP(hipMemcpyAsync(R.ckpt_state(sg + 1), R.seg_state(ff_par), R.state_bytes,
+                             hipMemcpyDeviceToDevice, s));
+      continue;
+    }
     if (int rc = forward_segment(sg, true)) return rc;
     if (sg + 1 < nseg)
       LBM_HIP(hipMemcpyAsync(R.ckpt_state(sg + 1), R.seg_state(static_cast<int>(seg_len(sg))),
@@ -688,7 +728,7 @@ int lbm_adjoint_run(const lbm_adjoint_config* cfg, void* ws, size_t ws_bytes, co
   } else {
     double* sat = R.w.bal.sat;
     if (int rc = sat_build(R.w.r, 1, rmean, sat, nx, ny, s)) return rc;
-    if (int rc = box_map(sat, rmean, 0, L, 0, 1.0 / (double(L) * L), R.w.rmap, nx, ny, s)) return rc;
+    if (int rc = box_map(sat, rmean, 1, 0, L, 0, 1.0 / (double(L) * L), R.w.rmap, nx, ny, s)) return rc;
     hipLaunchKernelGGL(k_sumsq, dim3(g), dim3(256), 0, s, R.w.rmap, R.plane, part);
     LBM_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, part, g, 1.0 / nwin, jdev);
@@ -698,7 +738,7 @@ int lbm_adjoint_run(const lbm_adjoint_config* cfg, void* ws, size_t ws_bytes, co
     if (int rc = field_means(R.w.rmap, 1, nx, ny, R.w.bal.partials + R.w.bal.partials_cap, rmm, s))
       return rc;
     if (int rc = sat_build(R.w.rmap, 1, rmm, sat, nx, ny, s)) return rc;
-    if (int rc = box_map(sat, rmm, 0, L, -(L - 1), 2.0 / (nwin * double(L) * L), R.w.rhat, nx, ny, s))
+    if (int rc = box_map(sat, rmm, 1, 0, L, -(L - 1), 2.0 / (nwin * double(L) * L), R.w.rhat, nx, ny, s))
       return rc;
   }
   LBM_HIP(hipMemcpyAsync(loss, jdev, sizeof(double), hipMemcpyDeviceToHost, s));

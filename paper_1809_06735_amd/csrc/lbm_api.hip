@@ -615,6 +615,19 @@ int lbm_get_tile(lbm_ctx c, lbm_tile* tile) {
   return LBM_OK;
 }
 
+int lbm_set_tuned_tile(const lbm_config* cfg, const lbm_tile* tile) {
+  if (int rc = validate_config(cfg)) return rc;
+  if (!tile) return fail(LBM_E_INVALID, "tile is NULL");
+  if (!tile_ok(*tile, cfg->dtype, cfg->nx, cfg->ny))
+    return fail(LBM_E_INVALID, "tile not valid for %d x %d", cfg->nx, cfg->ny);
+  const bool forced = cfg->has_force || cfg->drag_alpha > 0.0;
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  tune_cache_load();
+  g_tune[tune_key(cfg->dtype, cfg->nx, cfg->ny, forced, cfg->layout)] = *tile;
+  tune_cache_store();
+  return LBM_OK;
+}
+
 int lbm_autotune(lbm_ctx c, int32_t trial_steps, lbm_tile* chosen) {
   if (!c) return fail(LBM_E_INVALID, "ctx is NULL");
   if (trial_steps < 1 || trial_steps > 10000) return fail(LBM_E_INVALID, "trial_steps in [1, 10000]");

@@ -8,12 +8,16 @@
 //             difference, total stencil radius 12)
 //   means   : domain mean of each of the 13 fields (deterministic two-level sum)
 //   SAT     : mean-centred inclusive 2D prefix sums, one (ny+1) x (nx+1) table
-//             per field (row scan, then column scan)
-//   windows : for each box side L and every window corner, 13 box means from
-//             4 table lookups each (periodic wrap through the table totals),
-//             the balancing errors of Eqs. 12-13 and the Mach number of
-//             Eq. 20, reduced to count / mean / M2 / min / max / NaN per block
-//             and merged in a fixed order.
+//             per field, rows of all fields at one y adjacent (row scan, then
+//             column scan)
+//   windows : for each box side L and every window corner, the 13 box means
+//             (differences of the table across the window's top and bottom
+//             rows, periodic wrap through the table totals), the balancing
+//             errors of Eqs. 12-13 and the Mach number of Eq. 20, reduced to
+//             count / sum / sum of squares / min / max / NaN per block and
+//             merged in a fixed order.  Corners are visited along sequences
+//             y0, y0 + L, y0 + 2L, ... so a window's bottom row is the next
+//             window's top row and each table row is read once per side.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -28,7 +32,6 @@ namespace {
 using namespace fd8;
 
 constexpr int NT = LBM_NTERMS;
-constexpr int kMaxFusedSides = 8;
 enum { A_E = 0, A_OM2 = 1, A_W = 2, A_SXX = 3, A_SYY = 4, A_SXY = 5, A_HX = 6, A_HY = 7, NAUX = 8 };
 
 struct PassArgs {
@@ -244,16 +247,16 @@ __global__ void __launch_bounds__(kRedThreads) k_field_means(const double* __res
 // four wavefront totals through LDS) and offset by the running total.
 __global__ void __launch_bounds__(256) k_sat_rows(const double* __restrict__ g,
                                                   const double* __restrict__ means, double* sat,
-                                                  int nx, int ny) {
+                                                  int nx, int ny, int nf) {
   __shared__ double wsum[4];
   const int y = blockIdx.x;
   const int f = blockIdx.y;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const size_t plane = static_cast<size_t>(nx) * ny;
-  const size_t splane = static_cast<size_t>(nx + 1) * (ny + 1);
+  const size_t s = static_cast<size_t>(nx + 1);
   const double mean = means[f];
   const double* row = g + f * plane + static_cast<size_t>(y) * nx;
-  double* out = sat + f * splane + static_cast<size_t>(y + 1) * (nx + 1);
+  double* out = sat + (static_cast<size_t>(y + 1) * nf + f) * s;
   double carry = 0.0;
   for (int x0 = 0; x0 < nx; x0 += 256) {
     const int x = x0 + threadIdx.x;
@@ -274,7 +277,7 @@ __global__ void __launch_bounds__(256) k_sat_rows(const double* __restrict__ g,
   }
   if (threadIdx.x == 0) out[0] = 0.0;
   if (y == 0) {
-    double* top = sat + f * splane;
+    double* top = sat + f * s;
     for (int xx = threadIdx.x; xx <= nx; xx += 256) top[xx] = 0.0;
   }
 }
@@ -283,18 +286,17 @@ __global__ void __launch_bounds__(256) k_sat_rows(const double* __restrict__ g,
 // segment, the group totals are combined in LDS, then each group rewrites its
 // segment as running sums.
 constexpr int kColG = 16;
-__global__ void __launch_bounds__(64 * kColG) k_sat_cols(double* sat, int nx, int ny) {
+__global__ void __launch_bounds__(64 * kColG) k_sat_cols(double* sat, int nx, int ny, int nf) {
   __shared__ double sh[kColG][64];
   const int c = blockIdx.x * 64 + threadIdx.x;
   const int gidx = threadIdx.y;
   const int f = blockIdx.y;
-  const size_t splane = static_cast<size_t>(nx + 1) * (ny + 1);
-  double* P = sat + f * splane;
+  double* P = sat + f * static_cast<size_t>(nx + 1);
   const int seg = (ny + kColG - 1) / kColG;
   const int ya = 1 + gidx * seg;
   const int yb = min(ya + seg, ny + 1);
   const bool active = c <= nx;
-  const size_t s = static_cast<size_t>(nx + 1);
+  const size_t s = static_cast<size_t>(nx + 1) * nf;  // between rows of one field
   double acc = 0.0;
   if (active) {
     int yy = ya;
@@ -333,19 +335,19 @@ __global__ void __launch_bounds__(64 * kColG) k_sat_cols(double* sat, int nx, in
 
 // ---- windows -----------------------------------------------------------------------------------
 struct SatView {
-  const double* P;  // [NT][ny+1][nx+1]
+  const double* P;  // [ny+1][nf][nx+1]
   const double* means;
   int nx, ny;
-  size_t splane;
+  int nf;           // fields per table row
   // Q(y, x) for 0 <= y < 2 ny, 0 <= x < 2 nx: the periodic continuation of the
   // prefix table through its totals.
   __device__ __forceinline__ double Q(int f, int y, int x) const {
-    const double* p = P + f * splane;
+    const size_t s = static_cast<size_t>(nx + 1) * nf;  // between rows of one field
+    const double* p = P + f * static_cast<size_t>(nx + 1);
     const int qy = y > ny ? 1 : 0;
     const int qx = x > nx ? 1 : 0;
     const int ym = y - qy * ny;
     const int xm = x - qx * nx;
-    const size_t s = nx + 1;
     double v = p[ym * s + xm];
     if (qy) v += p[static_cast<size_t>(ny) * s + xm];
     if (qx) v += p[ym * s + nx];
@@ -502,18 +504,7 @@ __global__ void __launch_bounds__(kWinThreads) k_stats_final(const double* __res
   block_stats(r, out);
 }
 
-// All box sides of one call in one pass: each thread takes kCPT window corners
-// (stride 256 along the flattened grid) and, side by side, evaluates 13 box
-// means per side from the table (the corner (y0, x0) lookup is shared by all
-// sides), the balancing errors and Mach number, and accumulates
-// count / sum / sum of squares / min / max / NaN count per side; the
-// workgroup totals go to partials[side][block] and are merged in a fixed order.
-constexpr int kCPT = 4;
 constexpr int kSumVals = 3 * 6;
-struct SideList {
-  int n;
-  int L[kMaxFusedSides];
-};
 
 struct SumStat {
   double n, s1, s2, mn, mx, nan;
@@ -571,57 +562,110 @@ __device__ void sum_stats_block(SumStat (&r)[3], double* out) {
   __syncthreads();
 }
 
-__global__ void __launch_bounds__(256) k_windows_fused(SatView v, SideList sides, double* maps,
-                                                       double* partials) {
-  const size_t plane = static_cast<size_t>(v.nx) * v.ny;
-  const size_t s = static_cast<size_t>(v.nx) + 1;
+// Work split of the windows of one box side L (see k_windows_strided): strips
+// of 256 columns, residues j < L, and segments of at most kStrideSteps corner
+// rows of each residue's sequence.
+constexpr int kStrideSteps = 16;
+struct StrideGrid {
+  int strips, G, S;
+  long long blocks;  // per field group
+};
+StrideGrid stride_grid(int nx, int ny, int L) {
+  StrideGrid g;
+  g.strips = (nx + 255) / 256;
+  const int Q = (ny + L - 1) / L;
+  g.G = (Q + kStrideSteps - 1) / kStrideSteps;
+  g.S = (Q + g.G - 1) / g.G;
+  g.blocks = static_cast<long long>(g.strips) * L * g.G;
+  return g;
+}
+
+// Fields [F0, F0 + NF) of the windows of one workgroup: group 0 (LHS_E and
+// the five energy terms) gives delta^E, group 1 (LHS_Omega and the five
+// enstrophy terms) delta^Omega, group 2 (|u|^2) the Mach number, each into
+// its own statistics slot.
+template <int F0, int NF>
+__device__ __forceinline__ void stride_windows(const SatView& v, int L, int x0, int y0, int S,
+                                               double* maps, SumStat& r) {
   const int nx = v.nx, ny = v.ny;
-  for (int k = 0; k < sides.n; ++k) {
-    const int L = sides.L[k];
-    const double inv = 1.0 / (double(L) * double(L));
-    SumStat r[3];
-    for (int q = 0; q < 3; ++q) r[q].init();
-    for (int c = 0; c < kCPT; ++c) {
-      const size_t i = blockIdx.x * size_t(256 * kCPT) + size_t(c) * 256 + threadIdx.x;
-      if (i >= plane) break;
-      const int x0 = static_cast<int>(i % nx);
-      const int y0 = static_cast<int>(i / nx);
-      const int y1 = y0 + L, x1 = x0 + L;
-      const bool qy = y1 > ny, qx = x1 > nx;
-      const int ym = qy ? y1 - ny : y1, xm = qx ? x1 - nx : x1;
-      double m[NT];
-#pragma unroll 1
-      for (int f = 0; f < NT; ++f) {
-        const double* p = v.P + f * v.splane;
-        const double q00 = p[y0 * s + x0];
-        double q01 = p[y0 * s + xm];
-        double q10 = p[ym * s + x0];
-        double q11 = p[ym * s + xm];
-        if (qx) {
-          q01 += p[y0 * s + nx];
-          q11 += p[ym * s + nx];
-        }
-        if (qy) {
-          q10 += p[ny * s + x0];
-          q11 += p[ny * s + xm];
-          if (qx) q11 += p[ny * s + nx];
-        }
-        m[f] = v.means[f] + ((q11 - q01) - (q10 - q00)) * inv;
-      }
-      double dE, dZ, ma;
-      window_errors(m, dE, dZ, ma);
-      r[0].add(dE);
-      r[1].add(dZ);
-      r[2].add(ma);
-      if (maps) {
-        double* mk = maps + static_cast<size_t>(k) * 3 * plane;
-        mk[i] = dE;
-        mk[plane + i] = dZ;
-        mk[2 * plane + i] = ma;
-      }
+  const unsigned s = static_cast<unsigned>(nx + 1) * v.nf;  // between rows of one field
+  const double inv = 1.0 / (double(L) * double(L));
+  const bool qx = x0 + L > nx;
+  const unsigned xm = qx ? x0 + L - nx : x0 + L;
+  // Q(y, x0 + L) - Q(y, x0) for table row y in [0, 2 ny), continued
+  // periodically through the row and column totals
+  auto diff = [&](int k, int y) -> double {
+    const double* p = v.P + (F0 + k) * static_cast<unsigned>(nx + 1);
+    const bool qy = y > ny;
+    const unsigned ym = qy ? y - ny : y;
+    double b0 = p[ym * s + x0];
+    double b1 = p[ym * s + xm];
+    if (qx) b1 += p[ym * s + nx];
+    if (qy) {
+      b0 += p[ny * s + x0];
+      b1 += p[ny * s + xm];
+      if (qx) b1 += p[ny * s + nx];
     }
-    sum_stats_block(r, partials + (static_cast<size_t>(k) * gridDim.x + blockIdx.x) * kSumVals);
+    return b1 - b0;
+  };
+  // per field, the difference across the current window's top row
+  double dt[NF];
+#pragma unroll
+  for (int k = 0; k < NF; ++k) dt[k] = diff(k, y0);
+  for (int i = 0; i < S && y0 < ny; ++i, y0 += L) {
+    double m[NF];
+#pragma unroll
+    for (int k = 0; k < NF; ++k) {
+      const double db = diff(k, y0 + L);
+      m[k] = v.means[F0 + k] + (db - dt[k]) * inv;
+      dt[k] = db;  // the bottom row is the next window's top row
+    }
+    double val;
+    if constexpr (NF == 1) {
+      val = sqrt(m[0]) * 1.7320508075688772;  // Ma_V = sqrt(<|u|^2>) / c_s, c_s = 1/sqrt(3)
+    } else {
+      // |sum of the five terms - LHS| / largest |term|, as window_errors
+      const double rs = (((m[1] + m[2]) + m[3]) + m[4]) + m[5];
+      const double den =
+          fmax(fmax(fmax(fabs(m[1]), fabs(m[2])), fmax(fabs(m[3]), fabs(m[4]))), fabs(m[5]));
+      val = den > 0.0 ? fabs(rs - m[0]) / den : __builtin_nan("");
+    }
+    r.add(val);
+    if (maps) maps[static_cast<unsigned>(y0) * nx + x0] = val;
   }
+}
+
+// One box side L per launch.  Workgroup (group, strip, j, g) takes one field
+// group and the window corners x0 in its 256-column strip and
+// y0 = j + L q, q = g S .. g S + S - 1: along that sequence the bottom row of a
+// window is the top row of the next, so each table row is loaded once per side
+// (plus one row per segment) and reused from registers.  Workgroups are
+// numbered so that neighbouring strips share an XCD (and its L2, which serves
+// the columns x0 + L past the strip).
+__global__ void __launch_bounds__(256) k_windows_strided(SatView v, int L, int strips, int S, int nblocks,
+                                                         int per_xcd, double* maps, double* partials) {
+  const int b = blockIdx.x;
+  const int logical = (b & 7) * per_xcd + (b >> 3);
+  if (logical >= 3 * nblocks) return;  // uniform over the workgroup
+  const int grp = logical / nblocks;
+  const int wb = logical - grp * nblocks;
+  const int strip = wb % strips;
+  const int rest = wb / strips;
+  const int j = rest % L, g = rest / L;
+  const int x0 = strip * 256 + threadIdx.x;
+  const int y0 = j + L * (g * S);
+  const size_t plane = static_cast<size_t>(v.nx) * v.ny;
+  SumStat r[3];
+  for (int q = 0; q < 3; ++q) r[q].init();
+  if (x0 < v.nx && y0 < v.ny) {
+    if (grp == 0)
+      stride_windows<LBM_T_LHS_E, 6>(v, L, x0, y0, S, maps, r[0]);
+    else if (grp == 1)
+      stride_windows<LBM_T_LHS_Z, 6>(v, L, x0, y0, S, maps ? maps + plane : nullptr, r[1]);
+    else
+      stride_windows<LBM_T_USQ, 1>(v, L, x0, y0, S, maps ? maps + 2 * plane : nullptr, r[2]);
+  }
+  sum_stats_block(r, partials + static_cast<size_t>(logical) * kSumVals);
 }
 
 __global__ void __launch_bounds__(256) k_sum_stats_final(const double* __restrict__ partials,
@@ -684,9 +728,11 @@ BalanceWs carve_balance(Carver& c, int nx, int ny) {
   w.aux = c.take<double>(NAUX * plane);
   w.sat = c.take<double>(NT * splane);
   w.means = c.take<double>(16);
-  const size_t fused_blocks = (plane + 256 * kCPT - 1) / (256 * kCPT);
   size_t np = static_cast<size_t>(kWinMaxBlocks) * kStatVals;
-  if (np < fused_blocks * kMaxFusedSides * kSumVals) np = fused_blocks * kMaxFusedSides * kSumVals;
+  for (int L = 1; L <= (nx < ny ? nx : ny); ++L) {
+    const size_t need = 3 * static_cast<size_t>(stride_grid(nx, ny, L).blocks) * kSumVals;
+    if (np < need) np = need;
+  }
   w.partials = c.take<double>(np + static_cast<size_t>(NT) * kMeanBlocks);
   w.partials_cap = np;
   w.stats = c.take<double>(static_cast<size_t>(kMaxSizes) * kStatVals);
@@ -736,9 +782,9 @@ int field_means(const double* g, int nf, int nx, int ny, double* partials, doubl
 
 int sat_build(const double* g, int nf, const double* means, double* sat, int nx, int ny,
               hipStream_t s) {
-  hipLaunchKernelGGL(k_sat_rows, dim3(ny, nf), dim3(256), 0, s, g, means, sat, nx, ny);
+  hipLaunchKernelGGL(k_sat_rows, dim3(ny, nf), dim3(256), 0, s, g, means, sat, nx, ny, nf);
   LBM_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_sat_cols, dim3((nx + 1 + 63) / 64, nf), dim3(64, kColG), 0, s, sat, nx, ny);
+  hipLaunchKernelGGL(k_sat_cols, dim3((nx + 1 + 63) / 64, nf), dim3(64, kColG), 0, s, sat, nx, ny, nf);
   LBM_HIP(hipGetLastError());
   return LBM_OK;
 }
@@ -760,9 +806,9 @@ __global__ void __launch_bounds__(256) k_box_map(SatView v, int f, int L, int of
 }
 }  // namespace
 
-int box_map(const double* sat, const double* means, int f, int L, int off, double scale,
+int box_map(const double* sat, const double* means, int nf, int f, int L, int off, double scale,
             double* out, int nx, int ny, hipStream_t s) {
-  SatView v{sat, means, nx, ny, static_cast<size_t>(nx + 1) * (ny + 1)};
+  SatView v{sat, means, nx, ny, nf};
   const size_t plane = static_cast<size_t>(nx) * ny;
   int g = static_cast<int>((plane + 255) / 256);
   if (g > 4096) g = 4096;
@@ -785,32 +831,11 @@ int run_balance(const lbm_balance_input& in, const BalanceWs& ws, const int32_t*
     return rc;
   if (int rc = sat_build(ws.terms, NT, ws.means, ws.sat, nx, ny, s)) return rc;
 
-  SatView v{ws.sat, ws.means, nx, ny, static_cast<size_t>(nx + 1) * (ny + 1)};
-  const int fused_blocks = static_cast<int>((plane + 256 * kCPT - 1) / (256 * kCPT));
-  SideList chunk{};
-  int chunk_idx[kMaxFusedSides];
-  auto flush = [&]() -> int {
-    if (chunk.n == 0) return LBM_OK;
-    // maps of a chunk are written contiguously, so give the kernel the chunk's
-    // first map when the requested sizes are consecutive in the chunk
-    double* maps = dmaps ? dmaps + static_cast<size_t>(chunk_idx[0]) * 3 * plane : nullptr;
-    hipLaunchKernelGGL(k_windows_fused, dim3(fused_blocks), dim3(256), 0, s, v, chunk, maps,
-                       ws.partials);
-    LBM_HIP(hipGetLastError());
-    for (int j = 0; j < chunk.n; ++j) {
-      hipLaunchKernelGGL(k_sum_stats_final, dim3(1), dim3(256), 0, s,
-                         ws.partials + static_cast<size_t>(j) * fused_blocks * kSumVals,
-                         fused_blocks, ws.stats + static_cast<size_t>(chunk_idx[j]) * kStatVals);
-      LBM_HIP(hipGetLastError());
-    }
-    chunk.n = 0;
-    return LBM_OK;
-  };
+  SatView v{ws.sat, ws.means, nx, ny, NT};
   for (int k = 0; k < nsizes; ++k) {
     const int L = sizes[k];
+    double* maps = dmaps ? dmaps + static_cast<size_t>(k) * 3 * plane : nullptr;
     if (L == nx && L == ny) {
-      if (int rc = flush()) return rc;
-      double* maps = dmaps ? dmaps + static_cast<size_t>(k) * 3 * plane : nullptr;
       hipLaunchKernelGGL(k_windows, dim3(1), dim3(kWinThreads), 0, s, v, L, 1, maps, ws.partials);
       LBM_HIP(hipGetLastError());
       hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(kWinThreads), 0, s, ws.partials, 1,
@@ -818,12 +843,18 @@ int run_balance(const lbm_balance_input& in, const BalanceWs& ws, const int32_t*
       LBM_HIP(hipGetLastError());
       continue;
     }
-    chunk_idx[chunk.n] = k;
-    chunk.L[chunk.n++] = L;
-    if (chunk.n == kMaxFusedSides)
-      if (int rc = flush()) return rc;
+    const StrideGrid g = stride_grid(nx, ny, L);
+    if (3 * g.blocks * kSumVals > static_cast<long long>(ws.partials_cap))
+      return fail(LBM_E_INVALID, "box side %d: window partials exceed the workspace", L);
+    const int nb = static_cast<int>(g.blocks);
+    const int per_xcd = (3 * nb + 7) / 8;
+    hipLaunchKernelGGL(k_windows_strided, dim3(per_xcd * 8), dim3(256), 0, s, v, L, g.strips, g.S, nb,
+                       per_xcd, maps, ws.partials);
+    LBM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_sum_stats_final, dim3(1), dim3(256), 0, s, ws.partials, 3 * nb,
+                       ws.stats + static_cast<size_t>(k) * kStatVals);
+    LBM_HIP(hipGetLastError());
   }
-  if (int rc = flush()) return rc;
   if (nwin > 0) {
     LBM_HIP(hipMemcpyAsync(ws.windows, windows, sizeof(int32_t) * 3 * nwin, hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_window_terms, dim3((nwin + 63) / 64), dim3(64), 0, s, v, ws.windows, nwin,

@@ -142,14 +142,16 @@ size_t balance_ws_bytes(int nx, int ny);
 BalanceWs carve_balance(Carver& c, int nx, int ny);
 // Pieces of the balance reused by the adjoint: the 13 term fields and the aux
 // fields (E, Omega, omega, sigma_xx, sigma_yy, sigma_xy, H_x, H_y) of passes
-// A-C; domain means of nf consecutive fields; their mean-centred prefix tables;
-// and scaled box sums of one tabulated field for every corner shifted by `off`.
+// A-C; domain means of nf consecutive fields; their mean-centred prefix tables
+// (row-interleaved: table row y of field f starts at (y nf + f)(nx + 1), so the
+// rows of all fields at one y are adjacent); and scaled box sums of field f of
+// such a table for every corner shifted by `off`.
 int balance_terms(const lbm_balance_input& in, const BalanceWs& ws);
 int field_means(const double* g, int nf, int nx, int ny, double* partials, double* means,
                 hipStream_t s);
 int sat_build(const double* g, int nf, const double* means, double* sat, int nx, int ny,
               hipStream_t s);
-int box_map(const double* sat, const double* means, int f, int L, int off, double scale,
+int box_map(const double* sat, const double* means, int nf, int f, int L, int off, double scale,
             double* out, int nx, int ny, hipStream_t s);
 enum { AUX_E = 0, AUX_OM2 = 1, AUX_W = 2, AUX_SXX = 3, AUX_SYY = 4, AUX_SXY = 5, AUX_HX = 6,
        AUX_HY = 7, AUX_N = 8 };

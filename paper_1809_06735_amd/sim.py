@@ -271,3 +271,15 @@ def copy_bandwidth(nbytes=1 << 30, iters=20, device="cuda"):
     e1.synchronize()
     ms = e0.elapsed_time(e1) / iters
     return 2 * nbytes / (ms * 1e-3) / 1e9, ms
+
+
+def set_tuned_tile(nx, ny, dtype="f32", forced=False, layout="rows", tile=(512, 1, 1, 1, 1, 1, 0)):
+    """Record a step-kernel shape for a grid as if the autotuner had chosen it
+    (tile = (bx, by, vx, ry, nt, fuse, pf))."""
+    lib = L.load()
+    cfg = L.Config(nx=int(nx), ny=int(ny), dtype={"f32": L.LBM_F32, "f64": L.LBM_F64}[dtype],
+                   has_force=0, with_balance=0, layout=L.LAYOUTS[layout], tau=0.6,
+                   drag_alpha=1e-3 if forced else 0.0, stream=None)
+    t = L.Tile(*[int(v) for v in tile])
+    L.check(lib.lbm_set_tuned_tile(C.byref(cfg), C.byref(t)), "lbm_set_tuned_tile")
+

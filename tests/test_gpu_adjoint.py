@@ -48,6 +48,22 @@ def test_adjoint_fp64_matches_oracle(gpu_lib, box, ckpt):
     assert gt == pytest.approx(gtr, rel=1e-8)
 
 
+def test_adjoint_first_pass_in_multi_step_shapes_is_bitwise(gpu_lib):
+    """The first forward pass runs in the grid's tuned shape, K steps per launch when that
+    is the tuned choice; the loss and gradients do not change by a bit."""
+    from paper_1809_06735_amd.adjoint import adjoint_run
+    from paper_1809_06735_amd.sim import set_tuned_tile
+    ux, uy = tiny()
+    set_tuned_tile(32, 32, "f64", tile=(64, 1, 1, 1, 0, 1, 0))
+    J0, gx0, gy0, gt0 = adjoint_run(ux, uy, 0.55, 50, 8, 7, dtype="f64")
+    for tile in ((64, 1, 1, 8, 1, 3, 1), (64, 1, 1, 5, 0, 4, 1), (128, 1, 1, 32, 1, 2, 0)):
+        set_tuned_tile(32, 32, "f64", tile=tile)
+        J, gx, gy, gt = adjoint_run(ux, uy, 0.55, 50, 8, 7, dtype="f64")
+        assert J == J0 and gt == gt0, tile
+        assert torch.equal(gx, gx0) and torch.equal(gy, gy0), tile
+    set_tuned_tile(32, 32, "f64", tile=(64, 1, 1, 1, 0, 1, 0))
+
+
 def test_adjoint_matches_central_differences(gpu_lib):
     """dJ along a random direction and dJ/dtau against central differences of the GPU loss
     (FP64, 32^2, 50 steps): 1e-4 relative."""
