@@ -130,6 +130,23 @@ def forcing_field(n: int, seed: int = 0, kmin: float = 4.0, kmax: float = 6.0,
     return fx * scale, fy * scale
 
 
+def paper_forcing(n: int = 256, f0: float = 8e-4, kmin: float = 5.0, kmax: float = 7.0,
+                  phase: float = 0.0):
+    """The turbulent forcing of Sec. 3 (Eqs. 14-15): stream function
+    Psi = f0 sum_{kmin<=|k|<=kmax} cos(2 pi k.x / n + phase) with one phase for every
+    wavevector, F = (d_y Psi, -d_x Psi) analytically, not rescaled.  Returns
+    (fx, fy) float64 [n, n] indexed [y, x]."""
+    w = 2.0 * math.pi / n
+    yy, xx = np.meshgrid(np.arange(n, dtype=np.float64), np.arange(n, dtype=np.float64), indexing="ij")
+    fx = np.zeros((n, n))
+    fy = np.zeros((n, n))
+    for kx, ky in shell_vectors(kmin, kmax):
+        s = np.sin(w * (kx * xx + ky * yy) + phase)
+        fx += -f0 * w * ky * s       # d_y cos(...) = -w k_y sin(...)
+        fy += f0 * w * kx * s        # -d_x cos(...) = w k_x sin(...)
+    return fx, fy
+
+
 ENSEMBLE_SIZES = (256, 384, 512, 768, 1024)
 
 
@@ -221,4 +238,14 @@ WORKLOADS = {
                            taus=(0.5005, 0.501, 0.505, 0.51, 0.55)),
     "adjoint512": Workload("differentiable decaying run 512^2 fp32", 512, "f32", 0.51, 2000,
                            "spectrum", seed=7, sizes=(32,)),
+    # the paper's own set-up (Sec. 3): exact-difference forcing, turbulent force on
+    # 5 <= |k| <= 7 (F0^T = 8e-4, one phase), damping of 1 <= |k| <= 2 with
+    # F0^R = 1e-5 (rate F0^R N^2 per step), tau0 sweep of Sec. 5
+    "paper256": Workload("the paper's forced 2D turbulence 256^2 fp32, exact-difference forcing", 256,
+                         "f32", 0.52, 20000, "rest", seed=0, force=True,
+                         sizes=(4, 8, 16, 32, 64, 128, 181, 256), balance_every=100,
+                         taus=(0.60, 0.54, 0.53, 0.52, 0.515)),
 }
+#: damping of the paper's set-up: F0^R and the shell 1 <= |k| <= 2 of Eq. 16
+PAPER_DAMPING_F0 = 1e-5
+PAPER_DAMPING_SHELL = (1.0, 2.0)

@@ -19,6 +19,11 @@ Parts and where they come from
   2002) with the half-force velocity u = (sum f c + F/2) / rho, and a linear
   drag -alpha rho u folded into the force implicitly.  (The paper itself uses
   the exact-difference method of Kupershtokh; see the readings list.)
+* The paper's own forced set-up (Sec. 3, Eqs. 14-16): the exact-difference
+  forcing (relax to f^eq(rho, j/rho), then add f^eq(rho, j/rho + F/rho) -
+  f^eq(rho, j/rho)), the spectral damping of the wavevectors 1 <= |k| <= 2
+  computed from the bare velocity j/rho with unnormalised transforms, and the
+  physical velocity (j + F/2)/rho of that scheme for the balance.
 * Time derivative: three-level backward formula (Sec. 3, Eq. 17).
 * Space derivatives: 8th-order centred differences (Sec. 3, Eq. 18), periodic.
 * Energy balance terms (Sec. 2, Eqs. 8 and 10), enstrophy balance terms
@@ -434,6 +439,88 @@ def enstrophy_residual_grad(ux0, uy0, tau, nsteps, L):
     j = enstrophy_residual_loss(ux, uy, tt, nsteps, L)
     gx, gy, gt = torch.autograd.grad(j, (ux, uy, tt))
     return float(j.detach()), gx.detach(), gy.detach(), float(gt)
+
+
+# ---------------------------------------------------------------------------
+# The paper's own forced set-up (Sec. 3, Eqs. 14-16): exact-difference-method
+# forcing and the spectral damping of the large scales
+# ---------------------------------------------------------------------------
+def wavevectors(kmin, kmax):
+    """Integer wavevectors k with kmin <= |k| <= kmax."""
+    r = int(math.ceil(kmax))
+    return [(kx, ky) for ky in range(-r, r + 1) for kx in range(-r, r + 1)
+            if kmin * kmin <= kx * kx + ky * ky <= kmax * kmax]
+
+
+def shell_projection(a, kmin=1.0, kmax=2.0):
+    """The part of the periodic field a [ny, nx] on the wavevectors
+    kmin <= |k| <= kmax: ifft2(fft2(a) masked)."""
+    ny, nx = a.shape
+    mask = torch.zeros((ny, nx), dtype=DT)
+    for kx, ky in wavevectors(kmin, kmax):
+        mask[ky % ny, kx % nx] = 1.0
+    return torch.real(torch.fft.ifft2(torch.fft.fft2(a) * mask))
+
+
+def damping_force(ux, uy, amp, kmin=1.0, kmax=2.0):
+    """Eq. 16, F^R = -F0^R sum_{kmin<=|k|<=kmax} u^(k) e^{i 2 pi k.x / N}, read with
+    the imaginary unit restored in the exponent, u^ the unnormalised discrete
+    Fourier transform sum_x u(x) e^{-i 2 pi k.x / N} and the sum over +-k real:
+    F^R = -F0^R N^2 P[u] with P the projection on those wavevectors.  amp is the
+    rate F0^R N^2 (0.65536 for F0^R = 1e-5 at N = 256)."""
+    return -amp * shell_projection(ux, kmin, kmax), -amp * shell_projection(uy, kmin, kmax)
+
+
+def edm_total_force(f, fx_ext=None, fy_ext=None, amp=0.0, kmin=1.0, kmax=2.0):
+    """rho, bare velocity j/rho and the total force F = F_ext + F^R(j/rho) at a time."""
+    rho = density(f)
+    jx, jy = momentum(f)
+    ux, uy = jx / rho, jy / rho
+    fx = torch.zeros_like(rho) if fx_ext is None else fx_ext.clone()
+    fy = torch.zeros_like(rho) if fy_ext is None else fy_ext.clone()
+    if amp != 0.0:
+        rx, ry = damping_force(ux, uy, amp, kmin, kmax)
+        fx, fy = fx + rx, fy + ry
+    return rho, ux, uy, fx, fy
+
+
+def edm_collide(f, tau, fx_ext=None, fy_ext=None, amp=0.0, kmin=1.0, kmax=2.0):
+    """Kupershtokh's exact-difference method: after the BGK relaxation towards
+    f^eq(rho, u), u = j/rho, add f^eq(rho, u + du) - f^eq(rho, u), du = F dt/rho."""
+    rho, ux, uy, fx, fy = edm_total_force(f, fx_ext, fy_ext, amp, kmin, kmax)
+    feq = equilibrium(rho, ux, uy)
+    shifted = equilibrium(rho, ux + fx / rho, uy + fy / rho)
+    return f - (f - feq) / tau + (shifted - feq)
+
+
+def edm_step(f, tau, fx_ext=None, fy_ext=None, amp=0.0, kmin=1.0, kmax=2.0):
+    """One time step with the exact-difference forcing: collide, then stream."""
+    return stream(edm_collide(f, tau, fx_ext, fy_ext, amp, kmin, kmax))
+
+
+def edm_run(f, nsteps, tau, fx_ext=None, fy_ext=None, amp=0.0, kmin=1.0, kmax=2.0):
+    for _ in range(nsteps):
+        f = edm_step(f, tau, fx_ext, fy_ext, amp, kmin, kmax)
+    return f
+
+
+def edm_moments(f, fx_ext=None, fy_ext=None, amp=0.0, kmin=1.0, kmax=2.0):
+    """(rho, ux, uy, Fx, Fy) at the time of f: the physical velocity of the
+    exact-difference scheme, u = (j + F/2)/rho, and the total force."""
+    rho, ux, uy, fx, fy = edm_total_force(f, fx_ext, fy_ext, amp, kmin, kmax)
+    return rho, ux + 0.5 * fx / rho, uy + 0.5 * fy / rho, fx, fy
+
+
+def edm_run_with_history(f, nsteps, tau, fx_ext=None, fy_ext=None, amp=0.0, kmin=1.0, kmax=2.0):
+    """Populations after nsteps and the moments (rho, ux, uy) at t = nsteps-2,
+    nsteps-1, nsteps, plus the total force at nsteps (for the balance)."""
+    hist = []
+    for t in range(nsteps + 1):
+        if t >= nsteps - 2:
+            hist.append(edm_moments(f, fx_ext, fy_ext, amp, kmin, kmax))
+        if t < nsteps:
+            f = edm_step(f, tau, fx_ext, fy_ext, amp, kmin, kmax)
+    return f, hist
 
 
 # ---------------------------------------------------------------------------

@@ -577,3 +577,133 @@ def test_acoustic_wave_pressure_work():
     assert scale > 0
     # BDF2 error on sin^2(W t): (2W)^2/3 ~ 2.7e-4 relative
     assert float((fl["lhs_E"] - fl["e2"]).abs().max()) < 1e-3 * scale
+
+
+# ---------------------------------------------------------------------------
+# The paper's own forced set-up: exact-difference forcing, Eqs. 14-16
+# ---------------------------------------------------------------------------
+def _near_eq_populations(ny, nx, seed):
+    g = torch.Generator().manual_seed(seed)
+    rho = 1 + 0.02 * torch.randn(ny, nx, generator=g, dtype=D)
+    ux = 0.05 * torch.randn(ny, nx, generator=g, dtype=D)
+    uy = 0.05 * torch.randn(ny, nx, generator=g, dtype=D)
+    f = ref.equilibrium(rho, ux, uy) + 1e-3 * torch.randn(9, ny, nx, generator=g, dtype=D)
+    return f, g
+
+
+def test_edm_collision_conserves_mass_and_adds_the_force():
+    """Per site: sum_l (f* - f) = 0 and sum_l c_l (f* - f) = F, the total force (turbulent
+    force plus the damping of the large scales), to rounding."""
+    f, g = _near_eq_populations(24, 32, 5)
+    fx = 1e-3 * torch.randn(24, 32, generator=g, dtype=D)
+    fy = 1e-3 * torch.randn(24, 32, generator=g, dtype=D)
+    post = ref.edm_collide(f, 0.53, fx, fy, amp=0.4)
+    _, _, _, Fx, Fy = ref.edm_total_force(f, fx, fy, amp=0.4)
+    d = post - f
+    assert float(d.sum(0).abs().max()) < 1e-15
+    jx = sum(cx * d[l] for l, (cx, _) in enumerate(ref.C))
+    jy = sum(cy * d[l] for l, (_, cy) in enumerate(ref.C))
+    assert float((jx - Fx).abs().max()) < 1e-15
+    assert float((jy - Fy).abs().max()) < 1e-15
+    # with the damping off the total force is the given field
+    _, _, _, Gx, Gy = ref.edm_total_force(f, fx, fy, amp=0.0)
+    assert torch.equal(Gx, fx) and torch.equal(Gy, fy)
+
+
+def test_edm_equilibrium_is_fixed_without_force():
+    g = torch.Generator().manual_seed(6)
+    rho = 1 + 0.02 * torch.randn(16, 16, generator=g, dtype=D)
+    ux = 0.05 * torch.randn(16, 16, generator=g, dtype=D)
+    uy = 0.05 * torch.randn(16, 16, generator=g, dtype=D)
+    feq = ref.equilibrium(rho, ux, uy)
+    assert float((ref.edm_collide(feq, 0.7) - feq).abs().max()) < 1e-15
+
+
+def test_edm_velocity_shift_is_the_equilibrium_difference():
+    """The forcing term is f^eq(rho, u + F/rho) - f^eq(rho, u) exactly: for tau = 1 the
+    post-collision populations are the equilibrium at the shifted velocity."""
+    f, g = _near_eq_populations(8, 12, 7)
+    fx = 1e-3 * torch.randn(8, 12, generator=g, dtype=D)
+    fy = 1e-3 * torch.randn(8, 12, generator=g, dtype=D)
+    rho = f.sum(0)
+    jx, jy = ref.momentum(f)
+    want = ref.equilibrium(rho, (jx + fx) / rho, (jy + fy) / rho)
+    assert float((ref.edm_collide(f, 1.0, fx, fy) - want).abs().max()) < 1e-15
+
+
+def _count_shell(kmin, kmax):
+    # independent count: for each k_x the k_y range from the circle inequalities
+    n = 0
+    r = int(math.floor(kmax))
+    for kx in range(-r, r + 1):
+        hi = math.floor(math.sqrt(kmax * kmax - kx * kx) + 1e-12)
+        lo2 = kmin * kmin - kx * kx
+        lo = 0 if lo2 <= 0 else math.ceil(math.sqrt(lo2) - 1e-12)
+        n += sum(1 for ky in range(-hi, hi + 1) if abs(ky) >= lo)
+    return n
+
+
+def test_wavevector_shells():
+    """12 wavevectors with 1 <= |k| <= 2 (the damped large scales of Eq. 16) and 80 with
+    5 <= |k| <= 7 (the turbulent forcing of Eq. 14), counted two ways."""
+    assert len(ref.wavevectors(1.0, 2.0)) == _count_shell(1.0, 2.0) == 12
+    assert len(ref.wavevectors(5.0, 7.0)) == _count_shell(5.0, 7.0) == 80
+    assert sorted(ref.wavevectors(5.0, 7.0)) == sorted(inp.shell_vectors(5.0, 7.0))
+
+
+def test_shell_projection_keeps_exactly_the_shell():
+    """A field built from modes inside and outside 1 <= |k| <= 2: the projection returns the
+    inside part, and the damping force is -amp times it."""
+    n = 32
+    y, x = torch.meshgrid(torch.arange(n, dtype=D), torch.arange(n, dtype=D), indexing="ij")
+    w = 2 * math.pi / n
+    inside = 0.3 * torch.cos(w * x) + 0.2 * torch.sin(w * (x + y) + 0.4) - 0.1 * torch.cos(2 * w * y + 1.0)
+    outside = 0.25 * torch.sin(w * (2 * x + y)) + 0.05 * torch.cos(3 * w * x) + 0.7
+    p = ref.shell_projection(inside + outside)
+    assert float((p - inside).abs().max()) < 1e-14
+    fx, fy = ref.damping_force(inside + outside, outside, 0.65536)
+    assert float((fx + 0.65536 * inside).abs().max()) < 1e-14
+    assert float(fy.abs().max()) < 1e-14
+
+
+def test_paper_damping_rate():
+    """F0^R = 1e-5 on a 256^2 grid with unnormalised transforms: rate F0^R N^2 per step."""
+    assert inp.PAPER_DAMPING_F0 * 256 * 256 == pytest.approx(0.65536, rel=1e-15)
+
+
+def test_paper_forcing_is_the_curl_of_its_stream_function():
+    """F^T = (d_y Psi, -d_x Psi) with Psi = F0 sum cos(2 pi k.x/256 + phi) (Eqs. 14-15):
+    checked against spectral derivatives of Psi built independently, and divergence-free."""
+    n, f0, ph = 64, 8e-4, 0.3
+    fx, fy = inp.paper_forcing(n, f0=f0, kmin=5.0, kmax=7.0, phase=ph)
+    y, x = np.meshgrid(np.arange(n, dtype=float), np.arange(n, dtype=float), indexing="ij")
+    psi = np.zeros((n, n))
+    for kx, ky in ref.wavevectors(5.0, 7.0):
+        psi += f0 * np.cos(2 * np.pi * (kx * x + ky * y) / n + ph)
+    assert np.abs(fx - _spec_d(psi, 0)).max() < 1e-12 * np.abs(fx).max()
+    assert np.abs(fy + _spec_d(psi, 1)).max() < 1e-12 * np.abs(fy).max()
+    div = _spec_d(fx, 1) + _spec_d(fy, 0)
+    assert np.abs(div).max() < 1e-12 * np.abs(fx).max()
+
+
+def test_edm_run_with_damping_conserves_global_momentum():
+    """The turbulent force and the damping both have zero domain mean, so the exact-
+    difference scheme keeps the total momentum (and mass) to rounding over many steps."""
+    n = 32
+    fx, fy = inp.paper_forcing(n, f0=1e-4)
+    fx, fy = ref.t64(fx), ref.t64(fy)
+    f, _ = _near_eq_populations(n, n, 8)
+    m0 = float(f.sum())
+    j0 = [float(j.sum()) for j in ref.momentum(f)]
+    f = ref.edm_run(f, 25, 0.56, fx, fy, amp=0.5)
+    assert float(f.sum()) == pytest.approx(m0, rel=1e-13)
+    j1 = [float(j.sum()) for j in ref.momentum(f)]
+    assert abs(j1[0] - j0[0]) < 1e-12 and abs(j1[1] - j0[1]) < 1e-12
+    # and the damping removes energy from the large scales: with amp the k = 1..2 content
+    # of the velocity is smaller than without
+    g, _ = _near_eq_populations(n, n, 8)
+    a = ref.edm_run(g, 25, 0.56, fx, fy, amp=0.5)
+    b = ref.edm_run(g, 25, 0.56, fx, fy, amp=0.0)
+    ua = ref.edm_moments(a, fx, fy, 0.5)[1]
+    ub = ref.edm_moments(b, fx, fy, 0.0)[1]
+    assert float(ref.shell_projection(ua).abs().max()) < 0.5 * float(ref.shell_projection(ub).abs().max())
