@@ -4,7 +4,9 @@
  * The library advances a periodic two-dimensional D2Q9 BGK lattice-Boltzmann
  * model (Tauzin et al., Computers & Fluids 172 (2018), Sec. 1, Eqs. 1-2 and
  * Eq. 5) with an optional static body force (Guo's forcing term) and linear
- * drag, and evaluates the sub-volume averaged kinetic-energy and enstrophy
+ * drag, or with the paper's own forced set-up (Sec. 3, Eqs. 14-16: the
+ * exact-difference forcing and the spectral damping of the large scales), and
+ * evaluates the sub-volume averaged kinetic-energy and enstrophy
  * balances with their balancing errors (Sec. 2, Eqs. 8-13; Sec. 3, Eqs. 17-18
  * and Table 1; Sec. 4, Eq. 20).
  *
@@ -58,6 +60,14 @@ enum {
 enum { LBM_F32 = 0, LBM_F64 = 1 };
 enum { LBM_LAYOUT_PLANES = 0, LBM_LAYOUT_ROWS = 1 };
 
+/* ---- forcing schemes (lbm_config.force_scheme) ----------------------------- */
+enum {
+  LBM_FORCE_GUO = 0, /* Guo's forcing term with the half-force velocity; optional
+                        linear drag                                             */
+  LBM_FORCE_EDM = 1  /* exact-difference method (Kupershtokh), the scheme of
+                        Sec. 3; optional spectral damping of Eq. 16             */
+};
+
 /* ---- indices into the 8 global scalars returned by *_moments -------------- */
 enum {
   LBM_S_MASS = 0,      /* sum rho                                */
@@ -102,7 +112,20 @@ typedef struct {
                           ([9][ny][nx]) or LBM_LAYOUT_ROWS ([ny][9][nx], the nine
                           populations of a grid row contiguous)                    */
   double tau;          /* BGK relaxation time (Eq. 1), > 0.5 (Eq. 5: nu > 0)     */
-  double drag_alpha;   /* linear drag coefficient alpha >= 0: force -alpha rho u */
+  double drag_alpha;   /* linear drag coefficient alpha >= 0: force -alpha rho u
+                          (LBM_FORCE_GUO only)                                   */
+  int32_t force_scheme;/* LBM_FORCE_GUO or LBM_FORCE_EDM                         */
+  int32_t reserved;    /* must be 0                                              */
+  /* Spectral damping of the large scales (Sec. 3, Eq. 16), LBM_FORCE_EDM only:
+   *   F^R(x) = -damp_f0 sum_{kmin <= |k| <= kmax} u^(k) exp(2 pi i (kx x/nx + ky y/ny)),
+   *   u^(k)  = sum_x u(x) exp(-2 pi i (kx x/nx + ky y/ny))   (unnormalised),
+   * over integer wavevectors k, from the bare velocity u = j/rho of the
+   * pre-collision populations of the same step (so F^R = -damp_f0 nx ny P[u],
+   * P the projection on those modes; damp_f0 = 1e-5 on 256^2 damps them at the
+   * rate 0.65536 per step).  damp_f0 = 0: no damping.  Otherwise
+   * 0 < damp_kmin <= damp_kmax <= 4 and 2 damp_kmax < min(nx, ny).          */
+  double damp_f0;
+  double damp_kmin, damp_kmax;
   void* stream;        /* hipStream_t to enqueue on, or NULL                     */
 } lbm_config;
 
@@ -167,11 +190,19 @@ LBM_API int lbm_init(const lbm_config* cfg, void* ws, size_t ws_bytes,
 /* Advance n >= 0 time steps of Eq. 1 (pull streaming fused with BGK collision,
  * Guo forcing with the half-force velocity, implicit linear drag).  The last
  * two steps also record (rho, u) at times t+n-2 and t+n-1 for the time
- * derivative of the balance.  Asynchronous. */
+ * derivative of the balance.  Asynchronous.
+ * With LBM_FORCE_EDM a step is: (damping only) the Fourier coefficients of
+ * the bare velocity over the damped modes, reduced in a fixed order; then
+ * f*_l = f_l - (f_l - f^eq_l(rho, u))/tau + f^eq_l(rho, u + F/rho) - f^eq_l(rho, u)
+ * with u = j/rho and F = F_ext + F^R, pull-streamed like the BGK step; the
+ * recorded velocity is the scheme's physical one, (j + F/2)/rho.  Such a
+ * handle takes single-step shapes with vx = 1 only (lbm_set_tile,
+ * lbm_autotune). */
 LBM_API int lbm_step(lbm_ctx ctx, int64_t n);
 
 /* Moments at the current time t: rho = sum f, u = (sum f c + F/2)/rho with
- * F = F_ext - alpha rho u solved in closed form (u = j/rho when unforced).
+ * F = F_ext - alpha rho u solved in closed form (u = j/rho when unforced);
+ * with LBM_FORCE_EDM, F = F_ext + F^R(j/rho) of the current populations.
  *   rho, ux, uy : device [ny][nx] outputs of type out_dtype (LBM_F32/LBM_F64),
  *                 any of them may be NULL.
  *   scalars8 : host double[8] (LBM_S_* order) or NULL.  When given, the call
@@ -275,7 +306,8 @@ LBM_API int lbm_balance_fields(const lbm_balance_input* in, void* ws, size_t ws_
 enum { LBM_BATCH_PERSISTENT = 0, LBM_BATCH_PER_STEP = 1, LBM_BATCH_MULTI_STEP = 2 };
 typedef struct lbm_batch_s* lbm_batch;
 
-/* cfgs[nruns]: per-run configuration; with_balance must be 0, stream is taken
+/* cfgs[nruns]: per-run configuration; with_balance must be 0 and
+ * force_scheme LBM_FORCE_GUO (LBM_E_UNSUPPORTED otherwise), stream is taken
  * from cfgs[0]. */
 LBM_API int lbm_batch_workspace_bytes(const lbm_config* cfgs, int32_t nruns, size_t* bytes);
 /* rho0/ux0/uy0/fx/fy: host arrays of nruns device FP64 pointers (fx/fy NULL,

@@ -25,6 +25,9 @@ LBM_F64 = 1
 LBM_LAYOUT_PLANES = 0
 LBM_LAYOUT_ROWS = 1
 LAYOUTS = {"planes": LBM_LAYOUT_PLANES, "rows": LBM_LAYOUT_ROWS}
+LBM_FORCE_GUO = 0
+LBM_FORCE_EDM = 1
+SCHEMES = {"guo": LBM_FORCE_GUO, "edm": LBM_FORCE_EDM}
 LBM_BATCH_PERSISTENT = 0
 LBM_BATCH_PER_STEP = 1
 LBM_BATCH_MULTI_STEP = 2
@@ -45,7 +48,10 @@ class LBMError(RuntimeError):
 class Config(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("dtype", C.c_int32),
                 ("has_force", C.c_int32), ("with_balance", C.c_int32), ("layout", C.c_int32),
-                ("tau", C.c_double), ("drag_alpha", C.c_double), ("stream", C.c_void_p)]
+                ("tau", C.c_double), ("drag_alpha", C.c_double),
+                ("force_scheme", C.c_int32), ("reserved", C.c_int32),
+                ("damp_f0", C.c_double), ("damp_kmin", C.c_double), ("damp_kmax", C.c_double),
+                ("stream", C.c_void_p)]
 
 
 class BalanceStats(C.Structure):

@@ -47,6 +47,29 @@ int validate_config(const lbm_config* c) {
     return fail(LBM_E_INVALID, "with_balance must be 0 or 1");
   if (c->layout != LBM_LAYOUT_PLANES && c->layout != LBM_LAYOUT_ROWS)
     return fail(LBM_E_INVALID, "layout must be LBM_LAYOUT_PLANES or LBM_LAYOUT_ROWS");
+  if (c->force_scheme != LBM_FORCE_GUO && c->force_scheme != LBM_FORCE_EDM)
+    return fail(LBM_E_INVALID, "force_scheme must be LBM_FORCE_GUO or LBM_FORCE_EDM");
+  if (c->reserved != 0) return fail(LBM_E_INVALID, "reserved must be 0");
+  if (!(c->damp_f0 >= 0.0) || !std::isfinite(c->damp_f0))
+    return fail(LBM_E_INVALID, "damp_f0 must be finite and >= 0 (got %g)", c->damp_f0);
+  if (c->force_scheme == LBM_FORCE_GUO) {
+    if (c->damp_f0 != 0.0)
+      return fail(LBM_E_INVALID, "the spectral damping needs force_scheme = LBM_FORCE_EDM");
+    return LBM_OK;
+  }
+  if (c->drag_alpha != 0.0)
+    return fail(LBM_E_UNSUPPORTED, "linear drag is not combined with the exact-difference forcing");
+  if (c->damp_f0 > 0.0) {
+    if (!(c->damp_kmin > 0.0) || !(c->damp_kmax >= c->damp_kmin) || !(c->damp_kmax <= kEdmMaxK))
+      return fail(LBM_E_INVALID, "damped shell needs 0 < kmin <= kmax <= %d (got %g, %g)", kEdmMaxK,
+                  c->damp_kmin, c->damp_kmax);
+    const int m = c->nx < c->ny ? c->nx : c->ny;
+    if (!(2.0 * c->damp_kmax < m))
+      return fail(LBM_E_INVALID, "damped shell |k| <= %g does not fit a %d x %d grid", c->damp_kmax,
+                  c->nx, c->ny);
+    EdmModes md;
+    if (int rc = edm_modes(*c, &md)) return rc;
+  }
   return LBM_OK;
 }
 
@@ -84,6 +107,8 @@ struct lbm_ctx_s {
   int64_t pending_launches = 0;
   size_t plane = 0;
   PopLayout lay{};
+  EdmModes edm_md{};  // damped modes (exact-difference scheme)
+  EdmWs edm{};
 };
 
 namespace {
@@ -98,6 +123,7 @@ struct Layout {
   double* partials;
   double* scalars;
   BalanceWs bal;
+  EdmWs edm;
   size_t bytes;
 };
 
@@ -118,6 +144,8 @@ Layout carve_ctx(const lbm_config& c, void* base, size_t cap) {
   l.partials = cv.take<double>(static_cast<size_t>(moment_blocks(c.nx, c.ny)) * 8 + 8);
   l.scalars = cv.take<double>(8);
   if (c.with_balance) l.bal = carve_balance(cv, c.nx, c.ny);
+  EdmModes md;
+  if (edm_modes(c, &md) == LBM_OK) l.edm = carve_edm(cv, c, md);
   l.bytes = cv.used + 256;
   return l;
 }
@@ -125,10 +153,10 @@ Layout carve_ctx(const lbm_config& c, void* base, size_t cap) {
 std::mutex g_tune_mu;
 std::map<std::string, lbm_tile> g_tune;
 
-std::string tune_key(int dtype, int nx, int ny, bool force, int layout) {
-  char b[128];
-  snprintf(b, sizeof(b), "step dtype=%d nx=%d ny=%d force=%d layout=%d", dtype, nx, ny, force ? 1 : 0,
-           layout);
+std::string tune_key(int dtype, int nx, int ny, bool force, int layout, int scheme = LBM_FORCE_GUO) {
+  char b[160];
+  snprintf(b, sizeof(b), "step dtype=%d nx=%d ny=%d force=%d layout=%d scheme=%d", dtype, nx, ny,
+           force ? 1 : 0, layout, scheme);
   return b;
 }
 
@@ -142,12 +170,13 @@ void tune_cache_load() {
   if (!f) return;
   char line[256];
   while (std::fgets(line, sizeof(line), f)) {
-    int dt, nx, ny, fo, lay;
+    int dt, nx, ny, fo, lay, sch;
     lbm_tile t;
-    if (std::sscanf(line, "step dtype=%d nx=%d ny=%d force=%d layout=%d : %d %d %d %d %d %d %d", &dt,
-                    &nx, &ny, &fo, &lay, &t.bx, &t.by, &t.vx, &t.ry, &t.nt, &t.fuse, &t.pf) == 12 &&
-        tile_ok(t, dt, nx, ny))
-      g_tune[tune_key(dt, nx, ny, fo != 0, lay)] = t;
+    if (std::sscanf(line, "step dtype=%d nx=%d ny=%d force=%d layout=%d scheme=%d : %d %d %d %d %d %d %d",
+                    &dt, &nx, &ny, &fo, &lay, &sch, &t.bx, &t.by, &t.vx, &t.ry, &t.nt, &t.fuse,
+                    &t.pf) == 13 &&
+        (sch == LBM_FORCE_EDM ? edm_tile_ok(t, nx, ny) : tile_ok(t, dt, nx, ny)))
+      g_tune[tune_key(dt, nx, ny, fo != 0, lay, sch)] = t;
   }
   std::fclose(f);
 }
@@ -163,7 +192,15 @@ void tune_cache_store() {
   std::fclose(f);
 }
 
-bool is_forced(const lbm_ctx_s* c) { return c->cfg.has_force || c->cfg.drag_alpha > 0.0; }
+bool cfg_forced(const lbm_config& c) { return c.has_force || c.drag_alpha > 0.0 || c.damp_f0 > 0.0; }
+bool is_forced(const lbm_ctx_s* c) { return cfg_forced(c->cfg); }
+bool is_edm(const lbm_ctx_s* c) { return c->cfg.force_scheme == LBM_FORCE_EDM; }
+std::string ctx_key(const lbm_ctx_s* c) {
+  return tune_key(c->cfg.dtype, c->cfg.nx, c->cfg.ny, is_forced(c), c->cfg.layout, c->cfg.force_scheme);
+}
+bool ctx_tile_ok(const lbm_ctx_s* c, const lbm_tile& t) {
+  return is_edm(c) ? edm_tile_ok(t, c->cfg.nx, c->cfg.ny) : tile_ok(t, c->cfg.dtype, c->cfg.nx, c->cfg.ny);
+}
 
 }  // namespace
 
@@ -199,6 +236,7 @@ int enqueue_step(lbm_ctx_s* c, int src, hipStream_t s, double* hr, double* hx, d
   p.omega = 1.0 / c->cfg.tau;
   p.alpha = c->cfg.drag_alpha;
   const lbm_tile& t = (single || hr) ? c->tile1 : c->tile;
+  if (is_edm(c)) return edm_step(c->cfg, c->edm, c->edm_md, p, t, s);
   return launch_step(c->cfg.dtype, is_forced(c), p, t, s);
 }
 
@@ -285,7 +323,8 @@ int moments_into(lbm_ctx_s* c, void* rho, void* ux, void* uy, int out_dtype, dou
   m.ps = c->lay.ps;
   m.rs = c->lay.rs;
   m.alpha = c->cfg.drag_alpha;
-  int rc = launch_moments(c->cfg.dtype, is_forced(c), m, c->stream);
+  int rc = is_edm(c) ? edm_moments(c->cfg, c->edm, c->edm_md, m, c->stream)
+                     : launch_moments(c->cfg.dtype, is_forced(c), m, c->stream);
   if (rc) return rc;
   if (!scalars8) return LBM_OK;
   rc = launch_reduce_scalars(c->partials, moment_blocks(c->cfg.nx, c->cfg.ny), c->scalars_dev,
@@ -378,14 +417,24 @@ int lbm_init(const lbm_config* cfg, void* ws, size_t ws_bytes, const double* rho
   c->bal = l.bal;
   c->plane = static_cast<size_t>(cfg->nx) * cfg->ny;
   c->lay = pop_layout(cfg->layout, cfg->nx, cfg->ny);
+  c->edm = l.edm;
+  if (int rc = edm_modes(*cfg, &c->edm_md)) {
+    delete c;
+    return rc;
+  }
   {
     std::lock_guard<std::mutex> g(g_tune_mu);
     tune_cache_load();
-    auto it = g_tune.find(tune_key(cfg->dtype, cfg->nx, cfg->ny, is_forced(c), cfg->layout));
-    c->tile = it != g_tune.end() ? it->second : default_tile(cfg->dtype, cfg->nx, cfg->ny, cfg->layout);
+    auto it = g_tune.find(ctx_key(c));
+    if (it != g_tune.end())
+      c->tile = it->second;
+    else
+      c->tile = is_edm(c) ? edm_default_tile(cfg->nx)
+                          : default_tile(cfg->dtype, cfg->nx, cfg->ny, cfg->layout);
     c->tile1 = single_for(c, c->tile);
   }
   int rc = launch_init(cfg->dtype, c->pop[0], c->lay, rho0, ux0, uy0, cfg->nx, cfg->ny, c->stream);
+  if (rc == LBM_OK) rc = edm_tables(*cfg, c->edm, c->edm_md, c->stream);
   if (rc == LBM_OK && cfg->has_force) {
     rc = launch_to_storage(cfg->dtype, c->fx, fx, c->plane, c->stream);
     if (rc == LBM_OK) rc = launch_to_storage(cfg->dtype, c->fy, fy, c->plane, c->stream);
@@ -600,9 +649,10 @@ int lbm_load(lbm_ctx c, const void* src) {
 
 int lbm_set_tile(lbm_ctx c, const lbm_tile* tile) {
   if (!c || !tile) return fail(LBM_E_INVALID, "NULL argument");
-  if (!tile_ok(*tile, c->cfg.dtype, c->cfg.nx, c->cfg.ny))
-    return fail(LBM_E_INVALID, "tile (%d,%d,vx %d,ry %d,nt %d) not valid for %d x %d", tile->bx,
-                tile->by, tile->vx, tile->ry, tile->nt, c->cfg.nx, c->cfg.ny);
+  if (!ctx_tile_ok(c, *tile))
+    return fail(LBM_E_INVALID, "tile (%d,%d,vx %d,ry %d,nt %d,fuse %d) not valid for %d x %d%s", tile->bx,
+                tile->by, tile->vx, tile->ry, tile->nt, tile->fuse, c->cfg.nx, c->cfg.ny,
+                is_edm(c) ? " with the exact-difference step" : "");
   c->tile = *tile;
   c->tile1 = single_for(c, c->tile);
   drop_graphs(c);
@@ -618,12 +668,12 @@ int lbm_get_tile(lbm_ctx c, lbm_tile* tile) {
 int lbm_set_tuned_tile(const lbm_config* cfg, const lbm_tile* tile) {
   if (int rc = validate_config(cfg)) return rc;
   if (!tile) return fail(LBM_E_INVALID, "tile is NULL");
-  if (!tile_ok(*tile, cfg->dtype, cfg->nx, cfg->ny))
+  const bool edm = cfg->force_scheme == LBM_FORCE_EDM;
+  if (edm ? !edm_tile_ok(*tile, cfg->nx, cfg->ny) : !tile_ok(*tile, cfg->dtype, cfg->nx, cfg->ny))
     return fail(LBM_E_INVALID, "tile not valid for %d x %d", cfg->nx, cfg->ny);
-  const bool forced = cfg->has_force || cfg->drag_alpha > 0.0;
   std::lock_guard<std::mutex> g(g_tune_mu);
   tune_cache_load();
-  g_tune[tune_key(cfg->dtype, cfg->nx, cfg->ny, forced, cfg->layout)] = *tile;
+  g_tune[tune_key(cfg->dtype, cfg->nx, cfg->ny, cfg_forced(*cfg), cfg->layout, cfg->force_scheme)] = *tile;
   tune_cache_store();
   return LBM_OK;
 }
@@ -632,7 +682,14 @@ int lbm_autotune(lbm_ctx c, int32_t trial_steps, lbm_tile* chosen) {
   if (!c) return fail(LBM_E_INVALID, "ctx is NULL");
   if (trial_steps < 1 || trial_steps > 10000) return fail(LBM_E_INVALID, "trial_steps in [1, 10000]");
   lbm_tile cand[512];
-  const int n = tile_candidates(c->cfg.dtype, c->cfg.nx, c->cfg.ny, cand, 512);
+  int n = tile_candidates(c->cfg.dtype, c->cfg.nx, c->cfg.ny, cand, 512);
+  if (n > 512) n = 512;
+  if (is_edm(c)) {  // the exact-difference step takes single-step, one-site-per-thread shapes
+    int k = 0;
+    for (int i = 0; i < n; ++i)
+      if (edm_tile_ok(cand[i], c->cfg.nx, c->cfg.ny)) cand[k++] = cand[i];
+    n = k;
+  }
   if (n < 1) return fail(LBM_E_UNSUPPORTED, "no step-kernel shape fits this grid");
   const lbm_tile saved = c->tile;
   hipEvent_t e0, e1;
@@ -677,7 +734,7 @@ int lbm_autotune(lbm_ctx c, int32_t trial_steps, lbm_tile* chosen) {
   if (rc) return rc;
   {
     std::lock_guard<std::mutex> g(g_tune_mu);
-    g_tune[tune_key(c->cfg.dtype, c->cfg.nx, c->cfg.ny, is_forced(c), c->cfg.layout)] = best_t;
+    g_tune[ctx_key(c)] = best_t;
     tune_cache_store();
   }
   if (chosen) *chosen = best_t;

@@ -1,0 +1,566 @@
+// The paper's own forcing (Sec. 3, Eqs. 14-16) for gfx950: Kupershtokh's
+// exact-difference method with a static external force plus the spectral
+// damping of the large scales, F^R = -F0^R sum_k u^(k) e^{i k.x} over the
+// damped shell, recomputed every step from the bare velocity j/rho.
+//
+// One damped step is three launches:
+//  1. k_edm_dft: each workgroup pulls the pre-collision populations of a block
+//     of 256 columns and `rows` rows, forms u = j/rho and reduces the Fourier
+//     sums C_k = sum u cos(k.x), S_k = sum u sin(k.x) of both components over
+//     its sites (first along y per column against the y tables, then along x
+//     in LDS against the x tables) into 4 m partials.
+//  2. k_edm_coef: one workgroup adds the partials in a fixed order and turns the
+//     sums into per-row coefficients: with theta = kx phi + ky beta,
+//       F^R(x, y) = sum_{m = 0..km} A_m(y) cos(m phi) + B_m(y) sin(m phi),
+//     A_m = -2 F0 sum_{|kx| = m} (C cos ky beta + S sin ky beta),
+//     B_m = -2 F0 sum_{|kx| = m} sgn(kx) (S cos ky beta - C sin ky beta)
+//     (each mode of the half plane stands for itself and its conjugate -k).
+//  3. k_edm_step: pull, moments, force F = F_ext + F^R, exact-difference
+//     collision, store; same memory traffic as the Guo step.
+// Without damping only the step kernel runs.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "lbm_internal.h"
+#include "lbm_reduce.h"
+#include "lbm_site.h"
+
+namespace lbm {
+namespace {
+
+using namespace step_detail;
+using namespace reduce_detail;
+
+constexpr int kDftThreads = 256;
+constexpr int kDftTargetBlocks = 512;
+
+int dft_xblocks(int nx) { return (nx + kDftThreads - 1) / kDftThreads; }
+int dft_rows(int nx, int ny) {
+  const int chunks = std::max(1, kDftTargetBlocks / dft_xblocks(nx));
+  return (ny + chunks - 1) / chunks;
+}
+int dft_blocks(int nx, int ny) {
+  const int r = dft_rows(nx, ny);
+  return dft_xblocks(nx) * ((ny + r - 1) / r);
+}
+
+// cos and sin of 2 pi m x / n for m = 0..km, from the exact integer residue.
+template <typename T>
+__global__ void __launch_bounds__(256) k_edm_tables(double* __restrict__ tabx, double* __restrict__ taby,
+                                                    T* __restrict__ tabx_t, int nx, int ny, int km) {
+  const int nxx = (km + 1) * nx, total = nxx + (km + 1) * ny;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+    const bool isx = i < nxx;
+    const int j = isx ? i : i - nxx;
+    const int n = isx ? nx : ny;
+    const int m = j / n, x = j % n;
+    const int r = static_cast<int>((static_cast<long long>(m) * x) % n);
+    double sv, cv;
+    sincospi(2.0 * r / n, &sv, &cv);
+    double* tab = isx ? tabx : taby;
+    tab[(2 * m) * n + x] = cv;
+    tab[(2 * m + 1) * n + x] = sv;
+    if (isx) {
+      tabx_t[(2 * m) * n + x] = T(cv);
+      tabx_t[(2 * m + 1) * n + x] = T(sv);
+    }
+  }
+}
+
+// rho, j and 1/rho of one site from the deviations d_l = f_l - w_l (the sums
+// are grouped as in the Guo step).
+template <typename T>
+struct EdmSite {
+  T drho, rho, jx, jy, inv;
+  __device__ __forceinline__ explicit EdmSite(const T (&d)[9]) {
+    drho = ((d[0] + (d[1] + d[3])) + (d[2] + d[4])) + ((d[5] + d[7]) + (d[6] + d[8]));
+    rho = T(1) + drho;
+    jx = (d[1] - d[3]) + ((d[5] - d[7]) + (d[8] - d[6]));
+    jy = (d[2] - d[4]) + ((d[5] - d[7]) + (d[6] - d[8]));
+    inv = recip<T>(rho);
+  }
+};
+
+// F^R at one site from the row's coefficients cr[(m, {Ax, Bx, Ay, By})] and the
+// column's cos(m phi), sin(m phi).
+template <typename T, int KM>
+__device__ __forceinline__ void damp_force(const T* __restrict__ cr, const T (&cm)[KM + 1],
+                                           const T (&sm)[KM + 1], T& fx, T& fy) {
+  T ax = cr[0], ay = cr[2];
+#pragma unroll
+  for (int m = 1; m <= KM; ++m) {
+    ax += cr[4 * m] * cm[m] + cr[4 * m + 1] * sm[m];
+    ay += cr[4 * m + 2] * cm[m] + cr[4 * m + 3] * sm[m];
+  }
+  fx += ax;
+  fy += ay;
+}
+
+// Exact-difference collision in deviation form: with u = j/rho and
+// v = u + F/rho, f* = (1 - omega)(f - f^eq(u)) + f^eq(v), i.e.
+//   f*_l = (1 - omega) d_l + S + A,  f*_lbar = (1 - omega) d_lbar + S - A,
+//   S = w (B + 4.5 rho ((c.v)^2 - (1 - omega)(c.u)^2)),
+//   A = 3 w rho (c.v - (1 - omega) c.u),
+//   B = omega drho - 1.5 rho (|v|^2 - (1 - omega)|u|^2).
+template <typename T>
+__device__ __forceinline__ void edm_collide(const T (&d)[9], const EdmSite<T>& s, T ux, T uy, T vx,
+                                            T vy, T omega, T (&o)[9]) {
+  const T om1 = T(1) - omega;
+  const T B = omega * s.drho - T(1.5) * s.rho * ((vx * vx + vy * vy) - om1 * (ux * ux + uy * uy));
+  const T r45 = T(4.5) * s.rho, r3 = T(3) * s.rho;
+  o[0] = om1 * d[0] + T(wq(0)) * B;
+  auto pair = [&](int l, int lb, T cu, T cv, T w) {
+    const T S = w * (B + r45 * (cv * cv - om1 * (cu * cu)));
+    const T A = (w * r3) * (cv - om1 * cu);
+    o[l] = om1 * d[l] + (S + A);
+    o[lb] = om1 * d[lb] + (S - A);
+  };
+  const T wa = T(wq(1)), wd = T(wq(5));
+  pair(1, 3, ux, vx, wa);
+  pair(2, 4, uy, vy, wa);
+  pair(5, 7, ux + uy, vx + vy, wd);
+  pair(6, 8, uy - ux, vy - vx, wd);
+}
+
+// ---- 1. Fourier sums of the bare velocity ---------------------------------------
+template <typename T, int KM>
+__global__ void __launch_bounds__(kDftThreads) k_edm_dft(const T* __restrict__ pop, size_t ps, size_t rs,
+                                                         int nx, int ny, int rows, int xblocks,
+                                                         const double* __restrict__ tabx,
+                                                         const double* __restrict__ taby, EdmModes md,
+                                                         double* __restrict__ partials) {
+  constexpr int K1 = KM + 1;
+  constexpr int NQ = 4 * K1;  // per column: Uc_x[n], Us_x[n], Uc_y[n], Us_y[n], n = 0..KM
+  __shared__ double sh[NQ][kDftThreads];
+  __shared__ double red[kDftThreads];
+  const int xb = blockIdx.x % xblocks, yc = blockIdx.x / xblocks;
+  const int x = xb * kDftThreads + threadIdx.x;
+  const int y0 = yc * rows, y1 = min(ny, y0 + rows);
+  double acc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+  if (x < nx) {
+    for (int y = y0; y < y1; ++y) {
+      const int yn = (y == 0) ? ny - 1 : y - 1;
+      const int yp = (y == ny - 1) ? 0 : y + 1;
+      T d[9][1];
+      pull_all<T, 1>(pop, ps, rs, nx, x, y, yn, yp, d);
+      T di[9];
+#pragma unroll
+      for (int l = 0; l < 9; ++l) di[l] = d[l][0];
+      const EdmSite<T> s(di);
+      const double ux = double(s.jx * s.inv), uy = double(s.jy * s.inv);
+#pragma unroll
+      for (int n = 0; n < K1; ++n) {
+        const double c = taby[(2 * n) * ny + y], sn = taby[(2 * n + 1) * ny + y];
+        acc[n] += ux * c;
+        acc[K1 + n] += ux * sn;
+        acc[2 * K1 + n] += uy * c;
+        acc[3 * K1 + n] += uy * sn;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) sh[q][threadIdx.x] = acc[q];
+  __syncthreads();
+  // output v = 4 k + comp (comp: C_x, S_x, C_y, S_y); G groups of threads per
+  // output each sum a contiguous run of columns
+  const int V = 4 * md.m;
+  const int G = kDftThreads / V;
+  const int v = threadIdx.x % V, g = threadIdx.x / V;
+  double part = 0.0;
+  if (g < G) {
+    const int k = v >> 2, comp = v & 3;
+    const int kx = md.kx[k], ky = md.ky[k];
+    const int m = kx < 0 ? -kx : kx;
+    const double sg = kx < 0 ? -1.0 : 1.0;
+    const int uq = (comp >> 1) * 2 * K1;
+    const int chunk = (kDftThreads + G - 1) / G;
+    const int i0 = g * chunk, i1 = min(kDftThreads, i0 + chunk);
+    for (int i = i0; i < i1; ++i) {
+      const int xi = xb * kDftThreads + i;
+      if (xi >= nx) break;
+      const double ca = tabx[(2 * m) * nx + xi], sa = sg * tabx[(2 * m + 1) * nx + xi];
+      const double uc = sh[uq + ky][i], us = sh[uq + K1 + ky][i];
+      part += (comp & 1) ? (sa * uc + ca * us) : (ca * uc - sa * us);
+    }
+  }
+  red[threadIdx.x] = part;
+  __syncthreads();
+  if (threadIdx.x < V) {
+    double a = 0.0;
+    for (int q = 0; q < G; ++q) a += red[q * V + threadIdx.x];
+    partials[static_cast<size_t>(blockIdx.x) * V + threadIdx.x] = a;
+  }
+}
+
+// ---- 2. reduction of the partials and per-row coefficients -------------------------
+template <typename T, int KM>
+__global__ void __launch_bounds__(kDftThreads) k_edm_coef(const double* __restrict__ partials, int nparts,
+                                                          const double* __restrict__ taby, EdmModes md,
+                                                          int ny, T* __restrict__ coef) {
+  constexpr int K1 = KM + 1;
+  __shared__ double red[kDftThreads];
+  __shared__ double cf[4 * kEdmMaxModes];
+  const int V = 4 * md.m, R = kDftThreads / V;
+  const int v = threadIdx.x % V, r = threadIdx.x / V;
+  double s = 0.0;
+  if (r < R)
+    for (int b = r; b < nparts; b += R) s += partials[static_cast<size_t>(b) * V + v];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x < V) {
+    double a = 0.0;
+    for (int q = 0; q < R; ++q) a += red[q * V + threadIdx.x];
+    cf[threadIdx.x] = a;
+  }
+  __syncthreads();
+  const double scale = -2.0 * md.f0;
+  for (int y = threadIdx.x; y < ny; y += kDftThreads) {
+    double A[2][K1], B[2][K1];
+#pragma unroll
+    for (int m = 0; m < K1; ++m) A[0][m] = A[1][m] = B[0][m] = B[1][m] = 0.0;
+    for (int k = 0; k < md.m; ++k) {
+      const int kx = md.kx[k], ky = md.ky[k];
+      const int mk = kx < 0 ? -kx : kx;
+      const double sg = kx < 0 ? -1.0 : (kx > 0 ? 1.0 : 0.0);
+      const double cb = taby[(2 * ky) * ny + y], sb = taby[(2 * ky + 1) * ny + y];
+#pragma unroll
+      for (int m = 0; m < K1; ++m) {
+        if (m != mk) continue;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const double C = cf[4 * k + 2 * c], S = cf[4 * k + 2 * c + 1];
+          A[c][m] += C * cb + S * sb;
+          B[c][m] += sg * (S * cb - C * sb);
+        }
+      }
+    }
+    T* out = coef + static_cast<size_t>(y) * K1 * 4;
+#pragma unroll
+    for (int m = 0; m < K1; ++m) {
+      out[4 * m] = T(scale * A[0][m]);
+      out[4 * m + 1] = T(scale * B[0][m]);
+      out[4 * m + 2] = T(scale * A[1][m]);
+      out[4 * m + 3] = T(scale * B[1][m]);
+    }
+  }
+}
+
+// ---- 3. the step ---------------------------------------------------------------------
+// Same tiling as the Guo single step with one site per thread: a workgroup
+// of blockDim.x x blockDim.y threads covers blockDim.x columns and
+// blockDim.y * ry rows; consecutive tiles on one XCD.
+template <typename T, int KM, bool FT, bool DAMP, bool NT>
+__global__ void __launch_bounds__(1024) k_edm_step(StepParams p, const T* __restrict__ tabx_t,
+                                                   const T* __restrict__ coef, int tiles_x, int total,
+                                                   int per_xcd, int ry) {
+  const int b = blockIdx.x;
+  const int tile = (b & 7) * per_xcd + (b >> 3);
+  if (tile >= total) return;
+  const int tx = tile % tiles_x;
+  const int ty = tile / tiles_x;
+  const int x = tx * blockDim.x + threadIdx.x;
+  if (x >= p.nx) return;
+  const int ybase = (ty * blockDim.y + threadIdx.y) * ry;
+  const int nx = p.nx, ny = p.ny;
+  const T* __restrict__ src = static_cast<const T*>(p.src);
+  T* __restrict__ dst = static_cast<T*>(p.dst);
+  const T omega = T(p.omega);
+  T cm[KM + 1], sm[KM + 1];
+  if constexpr (DAMP) {
+#pragma unroll
+    for (int m = 1; m <= KM; ++m) {
+      cm[m] = tabx_t[(2 * m) * nx + x];
+      sm[m] = tabx_t[(2 * m + 1) * nx + x];
+    }
+  }
+  for (int k = 0; k < ry; ++k) {
+    const int y = ybase + k;
+    if (y >= ny) break;
+    const int yn = (y == 0) ? ny - 1 : y - 1;
+    const int yp = (y == ny - 1) ? 0 : y + 1;
+    T d[9][1];
+    pull_all<T, 1>(src, p.ps, p.rs, nx, x, y, yn, yp, d);
+    T di[9];
+#pragma unroll
+    for (int l = 0; l < 9; ++l) di[l] = d[l][0];
+    const size_t i = static_cast<size_t>(y) * nx + x;
+    T Fx = T(0), Fy = T(0);
+    if constexpr (FT) {
+      Fx = static_cast<const T*>(p.fx)[i];
+      Fy = static_cast<const T*>(p.fy)[i];
+    }
+    if constexpr (DAMP) damp_force<T, KM>(coef + static_cast<size_t>(y) * (KM + 1) * 4, cm, sm, Fx, Fy);
+    const EdmSite<T> s(di);
+    const T ux = s.jx * s.inv, uy = s.jy * s.inv;
+    const T vx = (s.jx + Fx) * s.inv, vy = (s.jy + Fy) * s.inv;
+    T o[9];
+    edm_collide<T>(di, s, ux, uy, vx, vy, omega, o);
+#pragma unroll
+    for (int l = 0; l < 9; ++l) {
+      T* q = dst + l * p.ps + static_cast<size_t>(y) * p.rs + x;
+      if constexpr (NT) __builtin_nontemporal_store(o[l], q);
+      else *q = o[l];
+    }
+    if (p.h_rho) {
+      p.h_rho[i] = double(s.rho);
+      p.h_ux[i] = double((s.jx + T(0.5) * Fx) * s.inv);
+      p.h_uy[i] = double((s.jy + T(0.5) * Fy) * s.inv);
+    }
+  }
+}
+
+// ---- moments ---------------------------------------------------------------------------
+template <typename T, typename O, int KM, bool FT, bool DAMP>
+__global__ void __launch_bounds__(kRedThreads) k_edm_moments(MomentParams p, const T* __restrict__ tabx_t,
+                                                             const T* __restrict__ coef) {
+  const int nx = p.nx, ny = p.ny;
+  const size_t plane = static_cast<size_t>(nx) * ny;
+  const T* __restrict__ pop = static_cast<const T*>(p.pop);
+  double acc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 1.0e300, 0.0};
+  for (size_t i = blockIdx.x * size_t(kRedThreads) + threadIdx.x; i < plane;
+       i += size_t(gridDim.x) * kRedThreads) {
+    const int x = static_cast<int>(i % nx);
+    const int y = static_cast<int>(i / nx);
+    T d[9];
+#pragma unroll
+    for (int l = 0; l < 9; ++l) {
+      int xs = x - cxq(l), ys = y - cyq(l);
+      xs += xs < 0 ? nx : 0;
+      xs -= xs >= nx ? nx : 0;
+      ys += ys < 0 ? ny : 0;
+      ys -= ys >= ny ? ny : 0;
+      d[l] = pop[l * p.ps + static_cast<size_t>(ys) * p.rs + xs];
+    }
+    T Fx = T(0), Fy = T(0);
+    if constexpr (FT) {
+      Fx = static_cast<const T*>(p.fx)[i];
+      Fy = static_cast<const T*>(p.fy)[i];
+    }
+    if constexpr (DAMP) {
+      T cm[KM + 1], sm[KM + 1];
+#pragma unroll
+      for (int m = 1; m <= KM; ++m) {
+        cm[m] = tabx_t[(2 * m) * nx + x];
+        sm[m] = tabx_t[(2 * m + 1) * nx + x];
+      }
+      damp_force<T, KM>(coef + static_cast<size_t>(y) * (KM + 1) * 4, cm, sm, Fx, Fy);
+    }
+    const EdmSite<T> s(d);
+    const T ux = (s.jx + T(0.5) * Fx) * s.inv, uy = (s.jy + T(0.5) * Fy) * s.inv;
+    if (p.rho) static_cast<O*>(p.rho)[i] = O(s.rho);
+    if (p.ux) static_cast<O*>(p.ux)[i] = O(ux);
+    if (p.uy) static_cast<O*>(p.uy)[i] = O(uy);
+    const double r = s.rho, vx = ux, vy = uy;
+    if (p.rho64) {
+      p.rho64[i] = r;
+      p.ux64[i] = vx;
+      p.uy64[i] = vy;
+    }
+    if (p.ftx64) {
+      p.ftx64[i] = double(Fx);
+      p.fty64[i] = double(Fy);
+    }
+    const double s2 = vx * vx + vy * vy;
+    const bool finite = isfinite(r) && isfinite(vx) && isfinite(vy);
+    acc[0] += r;
+    acc[1] += r * vx;
+    acc[2] += r * vy;
+    acc[3] += 0.5 * r * s2;
+    acc[4] = fmax(acc[4], sqrt(s2));
+    acc[5] = fmin(acc[5], r);
+    acc[6] += finite ? 0.0 : 1.0;
+  }
+  block_reduce7(acc, p.partials + blockIdx.x * 8);
+}
+
+// ---- host side ---------------------------------------------------------------------------
+size_t esize(int dtype) { return dtype == LBM_F64 ? 8 : 4; }
+
+template <typename T, int KM>
+int launch_fourier(const lbm_config& c, const EdmWs& w, const EdmModes& md, const void* pop, size_t ps,
+                   size_t rs, hipStream_t s) {
+  const int nb = dft_blocks(c.nx, c.ny);
+  hipLaunchKernelGGL((k_edm_dft<T, KM>), dim3(nb), dim3(kDftThreads), 0, s, static_cast<const T*>(pop),
+                     ps, rs, c.nx, c.ny, dft_rows(c.nx, c.ny), dft_xblocks(c.nx), w.tabx, w.taby, md,
+                     w.partials);
+  LBM_HIP(hipGetLastError());
+  hipLaunchKernelGGL((k_edm_coef<T, KM>), dim3(1), dim3(kDftThreads), 0, s, w.partials, nb, w.taby, md,
+                     c.ny, static_cast<T*>(w.coef));
+  LBM_HIP(hipGetLastError());
+  return LBM_OK;
+}
+
+template <typename T, int KM, bool FT, bool DAMP>
+int launch_step_k(const lbm_config& c, const EdmWs& w, const EdmModes& md, const StepParams& p,
+                  const lbm_tile& t, hipStream_t s) {
+  if constexpr (DAMP)
+    if (int rc = launch_fourier<T, KM>(c, w, md, p.src, p.ps, p.rs, s)) return rc;
+  const int tiles_x = (p.nx + t.bx - 1) / t.bx;
+  const int rows_per_tile = t.by * t.ry;
+  const int tiles_y = (p.ny + rows_per_tile - 1) / rows_per_tile;
+  const int total = tiles_x * tiles_y;
+  const int per_xcd = (total + 7) / 8;
+  const T* tabx_t = static_cast<const T*>(w.tabx_t);
+  const T* coef = static_cast<const T*>(w.coef);
+  if (t.nt)
+    hipLaunchKernelGGL((k_edm_step<T, KM, FT, DAMP, true>), dim3(per_xcd * 8), dim3(t.bx, t.by), 0, s, p,
+                       tabx_t, coef, tiles_x, total, per_xcd, t.ry);
+  else
+    hipLaunchKernelGGL((k_edm_step<T, KM, FT, DAMP, false>), dim3(per_xcd * 8), dim3(t.bx, t.by), 0, s, p,
+                       tabx_t, coef, tiles_x, total, per_xcd, t.ry);
+  LBM_HIP(hipGetLastError());
+  return LBM_OK;
+}
+
+template <typename T, int KM, bool FT, bool DAMP>
+int launch_moments_k(const lbm_config& c, const EdmWs& w, const EdmModes& md, const MomentParams& p,
+                     hipStream_t s) {
+  if constexpr (DAMP)
+    if (int rc = launch_fourier<T, KM>(c, w, md, p.pop, p.ps, p.rs, s)) return rc;
+  const int g = moment_blocks(p.nx, p.ny);
+  const T* tabx_t = static_cast<const T*>(w.tabx_t);
+  const T* coef = static_cast<const T*>(w.coef);
+  if (p.out_dtype == LBM_F32)
+    hipLaunchKernelGGL((k_edm_moments<T, float, KM, FT, DAMP>), dim3(g), dim3(kRedThreads), 0, s, p, tabx_t,
+                       coef);
+  else
+    hipLaunchKernelGGL((k_edm_moments<T, double, KM, FT, DAMP>), dim3(g), dim3(kRedThreads), 0, s, p, tabx_t,
+                       coef);
+  LBM_HIP(hipGetLastError());
+  return LBM_OK;
+}
+
+struct StepGo {
+  const lbm_config& c;
+  const EdmWs& w;
+  const EdmModes& md;
+  const StepParams& p;
+  const lbm_tile& t;
+  hipStream_t s;
+  template <typename T, int KM, bool FT, bool DAMP>
+  int run() const {
+    return launch_step_k<T, KM, FT, DAMP>(c, w, md, p, t, s);
+  }
+};
+
+struct MomGo {
+  const lbm_config& c;
+  const EdmWs& w;
+  const EdmModes& md;
+  const MomentParams& p;
+  hipStream_t s;
+  template <typename T, int KM, bool FT, bool DAMP>
+  int run() const {
+    return launch_moments_k<T, KM, FT, DAMP>(c, w, md, p, s);
+  }
+};
+
+// Calls f.run<T, KM, FT, DAMP>() for the handle's variant.
+template <typename F>
+int dispatch(const lbm_config& c, const EdmModes& md, const F& f) {
+  const bool ft = c.has_force != 0;
+  auto by_t = [&](auto tag) -> int {
+    using T = decltype(tag);
+    if (md.m == 0) return ft ? f.template run<T, 0, true, false>() : f.template run<T, 0, false, false>();
+    switch (md.km) {
+      case 1: return ft ? f.template run<T, 1, true, true>() : f.template run<T, 1, false, true>();
+      case 2: return ft ? f.template run<T, 2, true, true>() : f.template run<T, 2, false, true>();
+      case 3: return ft ? f.template run<T, 3, true, true>() : f.template run<T, 3, false, true>();
+      case 4: return ft ? f.template run<T, 4, true, true>() : f.template run<T, 4, false, true>();
+      default: return fail(LBM_E_INVALID, "damped shell reaches |k| = %d > %d", md.km, kEdmMaxK);
+    }
+  };
+  return c.dtype == LBM_F64 ? by_t(double{}) : by_t(float{});
+}
+
+}  // namespace
+
+int edm_modes(const lbm_config& c, EdmModes* out) {
+  EdmModes md;
+  if (c.force_scheme == LBM_FORCE_EDM && c.damp_f0 > 0.0) {
+    md.f0 = c.damp_f0;
+    const double lo = c.damp_kmin * c.damp_kmin, hi = c.damp_kmax * c.damp_kmax;
+    for (int ky = 0; ky <= kEdmMaxK; ++ky)
+      for (int kx = -kEdmMaxK; kx <= kEdmMaxK; ++kx) {
+        if (ky == 0 && kx <= 0) continue;
+        const double k2 = double(kx * kx + ky * ky);
+        if (k2 < lo || k2 > hi) continue;
+        if (md.m == kEdmMaxModes) return fail(LBM_E_INVALID, "more than %d damped modes", kEdmMaxModes);
+        md.kx[md.m] = static_cast<int8_t>(kx);
+        md.ky[md.m] = static_cast<int8_t>(ky);
+        md.km = std::max(md.km, std::max(kx < 0 ? -kx : kx, ky));
+        ++md.m;
+      }
+    if (md.m == 0)
+      return fail(LBM_E_INVALID, "no integer wavevector with %g <= |k| <= %g", c.damp_kmin, c.damp_kmax);
+  }
+  *out = md;
+  return LBM_OK;
+}
+
+EdmWs carve_edm(Carver& cv, const lbm_config& c, const EdmModes& md) {
+  EdmWs w;
+  if (c.force_scheme != LBM_FORCE_EDM || md.m == 0) return w;
+  const size_t k1 = static_cast<size_t>(md.km) + 1, es = esize(c.dtype);
+  w.tabx = cv.take<double>(k1 * 2 * c.nx);
+  w.taby = cv.take<double>(k1 * 2 * c.ny);
+  w.tabx_t = cv.take<char>(k1 * 2 * c.nx * es);
+  w.partials = cv.take<double>(static_cast<size_t>(dft_blocks(c.nx, c.ny)) * 4 * md.m);
+  w.coef = cv.take<char>(static_cast<size_t>(c.ny) * k1 * 4 * es);
+  return w;
+}
+
+int edm_tables(const lbm_config& c, const EdmWs& w, const EdmModes& md, hipStream_t s) {
+  if (md.m == 0) return LBM_OK;
+  const int n = (md.km + 1) * (c.nx + c.ny);
+  const int g = std::min(1024, (n + 255) / 256);
+  if (c.dtype == LBM_F64)
+    hipLaunchKernelGGL(k_edm_tables<double>, dim3(g), dim3(256), 0, s, w.tabx, w.taby,
+                       static_cast<double*>(w.tabx_t), c.nx, c.ny, md.km);
+  else
+    hipLaunchKernelGGL(k_edm_tables<float>, dim3(g), dim3(256), 0, s, w.tabx, w.taby,
+                       static_cast<float*>(w.tabx_t), c.nx, c.ny, md.km);
+  LBM_HIP(hipGetLastError());
+  return LBM_OK;
+}
+
+bool edm_tile_ok(const lbm_tile& t, int nx, int ny) {
+  (void)nx;
+  (void)ny;
+  if (t.fuse < 0 || t.fuse > 1 || t.vx != 1 || t.pf != 0) return false;
+  const int threads = t.bx * t.by;
+  if (t.bx < 1 || t.by < 1 || t.ry < 1 || threads > 1024 || threads % 64 != 0) return false;
+  return t.nt == 0 || t.nt == 1;
+}
+
+lbm_tile edm_default_tile(int nx) {
+  lbm_tile t{};
+  int bx = 64;
+  while (bx < 256 && bx * 2 <= nx) bx *= 2;
+  t.bx = bx;
+  t.by = 256 / bx;
+  t.vx = 1;
+  t.ry = 1;
+  t.nt = 0;
+  t.fuse = 1;
+  t.pf = 0;
+  return t;
+}
+
+int edm_step(const lbm_config& c, const EdmWs& w, const EdmModes& md, const StepParams& p,
+             const lbm_tile& t, hipStream_t s) {
+  if (!edm_tile_ok(t, c.nx, c.ny))
+    return fail(LBM_E_INVALID, "invalid launch shape for the exact-difference step");
+  return dispatch(c, md, StepGo{c, w, md, p, t, s});
+}
+
+int edm_moments(const lbm_config& c, const EdmWs& w, const EdmModes& md, const MomentParams& p,
+                hipStream_t s) {
+  return dispatch(c, md, MomGo{c, w, md, p, s});
+}
+
+}  // namespace lbm

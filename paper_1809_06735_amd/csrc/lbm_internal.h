@@ -124,6 +124,39 @@ int launch_to_storage(int dtype, void* dst, const double* src, size_t n, hipStre
 
 int launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 
+// ---- exact-difference forcing and spectral damping (Sec. 3, Eqs. 14-16) -------
+// Damped modes: the integer wavevectors with kmin <= |k| <= kmax in the half
+// plane ky > 0 or (ky == 0, kx > 0); each stands for itself and -k.
+constexpr int kEdmMaxK = 4;
+constexpr int kEdmMaxModes = 24;
+struct EdmModes {
+  int m = 0;   // number of modes (0: no damping)
+  int km = 0;  // largest |kx| or |ky| among them
+  double f0 = 0.0;
+  int8_t kx[kEdmMaxModes] = {};
+  int8_t ky[kEdmMaxModes] = {};
+};
+int edm_modes(const lbm_config& c, EdmModes* out);
+struct EdmWs {
+  double* tabx = nullptr;  // [km+1][2][nx] cos, sin of 2 pi m x / nx (FP64)
+  double* taby = nullptr;  // [km+1][2][ny] same in y
+  void* tabx_t = nullptr;  // tabx in the storage type
+  double* partials = nullptr;  // [dft blocks][4 m] per-workgroup Fourier sums
+  void* coef = nullptr;    // [ny][km+1][4] per-row force coefficients (storage type)
+};
+EdmWs carve_edm(Carver& cv, const lbm_config& c, const EdmModes& md);
+int edm_tables(const lbm_config& c, const EdmWs& w, const EdmModes& md, hipStream_t s);
+bool edm_tile_ok(const lbm_tile& t, int nx, int ny);
+lbm_tile edm_default_tile(int nx);
+// One step: the damping force's Fourier reduction (when m > 0), then the
+// exact-difference step kernel src -> dst (optional moment record in p.h_*).
+int edm_step(const lbm_config& c, const EdmWs& w, const EdmModes& md, const StepParams& p,
+             const lbm_tile& t, hipStream_t s);
+// Moments of the current populations as launch_moments, with the physical
+// velocity (j + F/2)/rho and the total force F_ext + F^R.
+int edm_moments(const lbm_config& c, const EdmWs& w, const EdmModes& md, const MomentParams& p,
+                hipStream_t s);
+
 // ---- balance --------------------------------------------------------------------
 struct BalanceWs {
   double* terms;     // [13][ny][nx]

@@ -11,12 +11,14 @@
 #include <hip/hip_runtime.h>
 
 #include "lbm_internal.h"
+#include "lbm_reduce.h"
 #include "lbm_site.h"
 
 namespace lbm {
 namespace {
 
 using namespace step_detail;
+using namespace reduce_detail;
 
 // One step over a tile of (blockDim.x * VX) x (blockDim.y * ry) sites.
 // Workgroups are numbered so that consecutive tiles fall on the same XCD
@@ -114,57 +116,8 @@ __global__ void __launch_bounds__(256) k_init(T* __restrict__ pop, PopLayout lay
 }
 
 // ---- moments ------------------------------------------------------------------------
-constexpr int kMomThreads = 256;
+constexpr int kMomThreads = kRedThreads;
 constexpr int kMomMaxBlocks = 1024;
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
-}
-__device__ __forceinline__ double wave_min(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-  return v;
-}
-
-// Reduce 7 per-thread values (sum x4, max, min, sum) over the block; thread 0
-// writes them to out[0..7].
-__device__ void block_reduce7(double (&v)[7], double* out) {
-  __shared__ double sh[kMomThreads / 64][8];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  double r[7];
-  r[0] = wave_sum(v[0]);
-  r[1] = wave_sum(v[1]);
-  r[2] = wave_sum(v[2]);
-  r[3] = wave_sum(v[3]);
-  r[4] = wave_max(v[4]);
-  r[5] = wave_min(v[5]);
-  r[6] = wave_sum(v[6]);
-  if (lane == 0)
-    for (int k = 0; k < 7; ++k) sh[wv][k] = r[k];
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double a[7];
-    for (int k = 0; k < 7; ++k) a[k] = sh[0][k];
-    for (int w = 1; w < kMomThreads / 64; ++w) {
-      a[0] += sh[w][0];
-      a[1] += sh[w][1];
-      a[2] += sh[w][2];
-      a[3] += sh[w][3];
-      a[4] = fmax(a[4], sh[w][4]);
-      a[5] = fmin(a[5], sh[w][5]);
-      a[6] += sh[w][6];
-    }
-    for (int k = 0; k < 7; ++k) out[k] = a[k];
-    out[7] = 0.0;
-  }
-}
 
 template <typename T, typename O, bool FORCE>
 __global__ void __launch_bounds__(kMomThreads) k_moments(MomentParams p) {

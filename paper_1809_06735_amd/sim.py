@@ -80,10 +80,15 @@ class Simulation:
     on the device); fx, fy: optional static external force; alpha: linear drag.
     dtype: "f32" or "f64" population storage.  layout: "rows" (the nine
     populations of a grid row contiguous, the faster one on MI355X) or "planes".
+    scheme: "guo" (Guo's forcing term) or "edm" (the exact-difference method of
+    the paper's Sec. 3); with "edm", damp_f0 > 0 adds the spectral damping
+    F^R = -damp_f0 sum u^(k) e^{i k.x} of the modes damp_shell[0] <= |k| <=
+    damp_shell[1] (Eq. 16, unnormalised transform).
     """
 
     def __init__(self, rho0, ux0, uy0, tau, dtype="f32", fx=None, fy=None, alpha=0.0,
-                 with_balance=False, device="cuda", stream=None, layout="rows"):
+                 with_balance=False, device="cuda", stream=None, layout="rows", scheme="guo",
+                 damp_f0=0.0, damp_shell=(1.0, 2.0)):
         _require_gpu()
         self._lib = L.load()
         self.device = torch.device(device)
@@ -100,7 +105,10 @@ class Simulation:
         self.layout = layout
         cfg = L.Config(nx=self.nx, ny=self.ny, dtype=self.dtype, has_force=int(has_force),
                        with_balance=int(with_balance), layout=L.LAYOUTS[layout], tau=self.tau,
-                       drag_alpha=self.alpha, stream=_stream_handle(stream))
+                       drag_alpha=self.alpha, force_scheme=L.SCHEMES[scheme],
+                       damp_f0=float(damp_f0), damp_kmin=float(damp_shell[0]),
+                       damp_kmax=float(damp_shell[1]), stream=_stream_handle(stream))
+        self.scheme = scheme
         self._cfg = cfg
         nbytes = C.c_size_t()
         L.check(self._lib.lbm_workspace_bytes(C.byref(cfg), C.byref(nbytes)), "lbm_workspace_bytes")
@@ -273,13 +281,18 @@ def copy_bandwidth(nbytes=1 << 30, iters=20, device="cuda"):
     return 2 * nbytes / (ms * 1e-3) / 1e9, ms
 
 
-def set_tuned_tile(nx, ny, dtype="f32", forced=False, layout="rows", tile=(512, 1, 1, 1, 1, 1, 0)):
+def set_tuned_tile(nx, ny, dtype="f32", forced=False, layout="rows", tile=(512, 1, 1, 1, 1, 1, 0),
+                   scheme="guo"):
     """Record a step-kernel shape for a grid as if the autotuner had chosen it
-    (tile = (bx, by, vx, ry, nt, fuse, pf))."""
+    (tile = (bx, by, vx, ry, nt, fuse, pf)); forced with scheme "edm" means a
+    static force or the damping."""
     lib = L.load()
+    edm = scheme == "edm"
     cfg = L.Config(nx=int(nx), ny=int(ny), dtype={"f32": L.LBM_F32, "f64": L.LBM_F64}[dtype],
                    has_force=0, with_balance=0, layout=L.LAYOUTS[layout], tau=0.6,
-                   drag_alpha=1e-3 if forced else 0.0, stream=None)
+                   drag_alpha=1e-3 if forced and not edm else 0.0, force_scheme=L.SCHEMES[scheme],
+                   damp_f0=1e-5 if forced and edm else 0.0, damp_kmin=1.0, damp_kmax=2.0,
+                   stream=None)
     t = L.Tile(*[int(v) for v in tile])
     L.check(lib.lbm_set_tuned_tile(C.byref(cfg), C.byref(t)), "lbm_set_tuned_tile")
 

@@ -89,3 +89,38 @@ def test_balance_workspace_and_adjoint_validation():
     assert lib.lbm_balance_workspace_bytes(8, 64, C.byref(n)) == L.LBM_E_INVALID
     assert lib.lbm_copy(None, None, 16, None) == L.LBM_E_INVALID
     assert lib.lbm_copy(C.c_void_p(256), C.c_void_p(512), 15, None) == L.LBM_E_INVALID
+
+
+def test_exact_difference_config_validation():
+    """The paper's forced set-up: scheme, damping and shell checks happen on the host."""
+    lib = L.load()
+    n = C.c_size_t()
+    edm = dict(force_scheme=L.LBM_FORCE_EDM)
+    ok = [cfg(**edm), cfg(has_force=1, **edm),
+          cfg(damp_f0=1e-5, damp_kmin=1.0, damp_kmax=2.0, **edm),
+          cfg(damp_f0=1e-5, damp_kmin=0.5, damp_kmax=4.0, **edm)]
+    for c in ok:
+        assert lib.lbm_workspace_bytes(C.byref(c), C.byref(n)) == L.LBM_OK, lib.lbm_last_error()
+    plain = C.c_size_t()
+    lib.lbm_workspace_bytes(C.byref(cfg(**edm)), C.byref(plain))
+    damped = C.c_size_t()
+    lib.lbm_workspace_bytes(C.byref(ok[2]), C.byref(damped))
+    assert damped.value > plain.value  # tables, partials and row coefficients
+    bad = [cfg(force_scheme=2), cfg(reserved=1),
+           cfg(damp_f0=1e-5),                                   # damping needs the EDM scheme
+           cfg(damp_f0=-1.0, **edm), cfg(damp_f0=float("inf"), **edm),
+           cfg(damp_f0=1e-5, damp_kmin=0.0, damp_kmax=2.0, **edm),
+           cfg(damp_f0=1e-5, damp_kmin=3.0, damp_kmax=2.0, **edm),
+           cfg(damp_f0=1e-5, damp_kmin=1.0, damp_kmax=5.0, **edm),  # beyond |k| = 4
+           cfg(damp_f0=1e-5, damp_kmin=1.2, damp_kmax=1.3, **edm)]  # no integer vector
+    for c in bad:
+        assert lib.lbm_workspace_bytes(C.byref(c), C.byref(n)) == L.LBM_E_INVALID, (
+            c.force_scheme, c.damp_f0, c.damp_kmin, c.damp_kmax)
+        assert lib.lbm_last_error()
+    # drag is a Guo-scheme option; a batch runs the Guo step only
+    assert lib.lbm_workspace_bytes(C.byref(cfg(drag_alpha=1e-3, **edm)), C.byref(n)) == L.LBM_E_UNSUPPORTED
+    cs = (L.Config * 2)(cfg(), cfg(**edm))
+    assert lib.lbm_batch_workspace_bytes(cs, 2, C.byref(n)) == L.LBM_E_UNSUPPORTED
+    # the exact-difference step takes single-step shapes with one site per thread
+    assert lib.lbm_set_tuned_tile(C.byref(cfg(**edm)), C.byref(L.Tile(256, 1, 1, 64, 0, 2, 0))) == L.LBM_E_INVALID
+    assert lib.lbm_set_tuned_tile(C.byref(cfg(**edm)), C.byref(L.Tile(64, 4, 2, 1, 0, 1, 0))) == L.LBM_E_INVALID

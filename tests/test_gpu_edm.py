@@ -1,0 +1,187 @@
+"""GPU parity of the paper's own forced set-up (Sec. 3, Eqs. 14-16): the exact-difference
+step with a static force (the constant-phase stream-function force of Eqs. 14-15 or a
+random one) and the spectral damping F^R of the modes kmin <= |k| <= kmax (Eq. 16), against
+the FP64 oracle, which projects with FFTs where the library reduces direct Fourier sums.
+
+Tolerances as for the Guo step: FP64 storage 1e-12 and FP32 storage 1e-5, both as
+max |gpu - oracle| / max |oracle| per moment field; balance terms at the level that the
+moment differences imply (perturbation of the oracle's own history).
+"""
+import numpy as np
+import pytest
+import torch
+
+import lbm_inputs as inp
+from helpers import rel_err
+from oracle import ref
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+
+def say(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+def Sim(*a, **k):
+    from paper_1809_06735_amd import Simulation
+    return Simulation(*a, **k)
+
+
+def _fields(ny, nx, seed, mach=0.08):
+    n = max(nx, ny)
+    _, ux, uy = inp.spectrum_velocity(n, seed=seed, max_mach=mach)
+    rng = np.random.default_rng(seed + 100)
+    rho = 1.0 + 0.001 * rng.standard_normal((ny, nx))
+    return rho, ux[:ny, :nx].copy(), uy[:ny, :nx].copy()
+
+
+def _oracle(rho, ux, uy, steps, tau, fx, fy, amp, shell):
+    f = ref.init_populations(rho, ux, uy)
+    fxt = None if fx is None else ref.t64(fx)
+    fyt = None if fy is None else ref.t64(fy)
+    f = ref.edm_run(f, steps, tau, fxt, fyt, amp, *shell)
+    return ref.edm_moments(f, fxt, fyt, amp, *shell)
+
+
+def _check(sim, want, tol, label):
+    r, vx, vy, sc = sim.moments()
+    for name, g, w in zip(("rho", "ux", "uy"), (r, vx, vy), want[:3]):
+        e = rel_err(g, w)
+        say(f"{label} {name} rel err {e:.2e}")
+        assert e < tol, (label, name, e)
+    return sc
+
+
+def _run_case(ny, nx, dtype, steps, tau, amp, shell=(1.0, 2.0), force="random", seed=0, tol=TOL64,
+              label="edm"):
+    rho, ux, uy = _fields(ny, nx, seed)
+    if force == "random":
+        n = max(nx, ny)
+        fx, fy = inp.forcing_field(n, seed=seed + 7, max_force=3e-5)
+        fx, fy = fx[:ny, :nx].copy(), fy[:ny, :nx].copy()
+    elif force == "paper":
+        assert nx == ny
+        fx, fy = inp.paper_forcing(nx)
+    else:
+        fx = fy = None
+    f0 = amp / (nx * ny)
+    say(f"{label}: {ny}x{nx} {dtype} {steps} steps tau {tau} amp {amp} shell {shell} force {force}")
+    sim = Sim(rho, ux, uy, tau, dtype=dtype, fx=fx, fy=fy, scheme="edm", damp_f0=f0, damp_shell=shell)
+    sim.step(steps)
+    want = _oracle(rho, ux, uy, steps, tau, fx, fy, amp, shell)
+    sc = _check(sim, want, tol, label)
+    assert sc["time"] == steps
+    return sim, want
+
+
+def test_edm_damped_fp64_nonsquare(gpu_lib):
+    """FP64, 40 x 48, random static force plus damping of 1 <= |k| <= 2 at rate 0.5 per step."""
+    _run_case(40, 48, "f64", 60, 0.56, 0.5, label="edm64 40x48")
+
+
+def test_edm_paper_set_up_256(gpu_lib):
+    """The paper's configuration on 256^2: F0^T = 8e-4 on 5 <= |k| <= 7 with one phase,
+    F0^R = 1e-5 on 1 <= |k| <= 2 (rate 0.65536), tau0 = 0.52; FP64 and FP32 storage."""
+    amp = inp.PAPER_DAMPING_F0 * 256 * 256
+    _run_case(256, 256, "f64", 30, 0.52, amp, force="paper", seed=3, label="paper256 f64")
+    _run_case(256, 256, "f32", 30, 0.52, amp, force="paper", seed=3, tol=TOL32, label="paper256 f32")
+
+
+@pytest.mark.parametrize("shell", [(1.0, 1.0), (2.0, 3.0), (0.5, 4.0)])
+def test_edm_shells(gpu_lib, shell):
+    """Other damped shells: |k| = 1 (2 modes of the half plane), 2 <= |k| <= 3 and every mode
+    up to |k| = 4 (24 modes, the largest the library takes); odd grid extents."""
+    _run_case(37, 44, "f64", 25, 0.6, 0.3, shell=shell, seed=5, label=f"shell {shell}")
+
+
+def test_edm_without_damping(gpu_lib):
+    """Exact-difference forcing with the static force only, and with no force at all (then
+    it is the plain BGK step); FP64 and FP32."""
+    _run_case(32, 64, "f64", 50, 0.53, 0.0, seed=8, label="edm force only f64")
+    _run_case(32, 64, "f32", 50, 0.53, 0.0, seed=8, tol=TOL32, label="edm force only f32")
+    _run_case(48, 32, "f64", 50, 0.7, 0.0, force=None, seed=9, label="edm unforced f64")
+
+
+def test_edm_shapes_graphs_and_checkpoint_bitwise(gpu_lib):
+    """Launch shapes, hipGraph replay and save/load change nothing: every variant gives the
+    same bits as direct single launches of the default shape."""
+    from paper_1809_06735_amd import _lib as L
+    n = 64
+    rho, ux, uy = _fields(n, n, 11)
+    fx, fy = inp.paper_forcing(n, f0=1e-4)
+    kw = dict(dtype="f32", fx=fx, fy=fy, scheme="edm", damp_f0=0.4 / (n * n))
+
+    def run(tile=None, graph=0, steps=70, split=None):
+        s = Sim(rho, ux, uy, 0.53, **kw)
+        if tile is not None:
+            s.set_tile(*tile)
+        s.set_graph(graph)
+        if split is None:
+            s.step(steps)
+        else:
+            s.step(split)
+            st = s.save()
+            s.step(5)  # moved on, then restored
+            s.load(st)
+            s.step(steps - split)
+        r, vx, vy = s.moments(scalars=False)
+        return torch.stack([r, vx, vy]).cpu()
+
+    base = run()
+    for tile in [(64, 4, 1, 1, 0, 1, 0), (256, 1, 1, 3, 1, 1, 0), (128, 2, 1, 5, 0, 1, 0)]:
+        assert torch.equal(run(tile), base), tile
+    assert torch.equal(run(graph=8), base)
+    assert torch.equal(run(split=31), base)
+    s = Sim(rho, ux, uy, 0.53, **kw)
+    with pytest.raises(L.LBMError):
+        s.set_tile(128, 1, 1, 32, 0, 3, 1)  # multi-step shapes are for the Guo step
+    with pytest.raises(L.LBMError):
+        s.set_tile(64, 4, 2, 1, 0, 1, 0)  # one site per thread
+    t = s.autotune(4)
+    assert t[1] >= 1 and t[2] == 1 and t[5] == 1, t
+
+
+def _edm_kappa(hist, nu, rel, seed=0):
+    lv = [h[:3] for h in hist]
+    fx, fy = hist[2][3], hist[2][4]
+    base = ref.balance_fields([h[0] for h in lv], [h[1] for h in lv], [h[2] for h in lv], fx, fy, nu)
+    rng = np.random.default_rng(seed)
+    pert = [tuple(ref.t64(np.asarray(a) * (1 + rel * rng.standard_normal(a.shape))) for a in h)
+            for h in hist]
+    p2 = ref.balance_fields([h[0] for h in pert], [h[1] for h in pert], [h[2] for h in pert],
+                            pert[2][3], pert[2][4], nu)
+    return base, {k: float((p2[k] - base[k]).abs().max() / (base[k].abs().max() or 1.0))
+                  for k in ref.TERM_NAMES}
+
+
+def test_edm_balance_of_a_run(gpu_lib):
+    """The sub-volume balance of a damped exact-difference run (FP64, 48^2): the handle's
+    history and force are the scheme's physical velocity (j + F/2)/rho and total force
+    F_ext + F^R, checked term by term against the oracle's run."""
+    n, steps, tau = 48, 40, 0.6
+    amp = 0.4
+    rho, ux, uy = _fields(n, n, 13)
+    fx, fy = inp.paper_forcing(n, f0=1e-4)
+    sim = Sim(rho, ux, uy, tau, dtype="f64", fx=fx, fy=fy, scheme="edm", damp_f0=amp / (n * n),
+              with_balance=True)
+    sim.step(steps)
+    res = sim.balance((6, 24, 48), term_fields=True)
+    r, vx, vy, _ = sim.moments()
+    _, hist = ref.edm_run_with_history(ref.init_populations(rho, ux, uy), steps, tau, ref.t64(fx),
+                                       ref.t64(fy), amp)
+    dmom = max(rel_err(g, w) for g, w in zip((r, vx, vy), hist[-1][:3]))
+    say(f"edm balance: moments agree to {dmom:.1e}")
+    assert dmom < TOL64
+    flds, kappa = _edm_kappa(hist, ref.viscosity(tau), max(dmom, 1e-16))
+    for name in ref.TERM_NAMES:
+        e = rel_err(res["terms"][name], flds[name])
+        tol = max(1e-12, 10 * kappa[name])
+        say(f"  {name}: {e:.1e} (tol {tol:.1e})")
+        assert e <= tol, (name, e, tol)
+    want = ref.subvolume_balance(flds, (6, 24, 48))
+    for got, w in zip(res["stats"], want):
+        for q in ("dE", "dZ", "Ma"):
+            assert got[q]["count"] == w[q]["count"], (got["L"], q)
