@@ -4,12 +4,13 @@
 // damped shell, recomputed every step from the bare velocity j/rho.
 //
 // One damped step is three launches:
-//  1. k_edm_dft: each workgroup pulls the pre-collision populations of a block
-//     of 256 columns and `rows` rows, forms u = j/rho and reduces the Fourier
-//     sums C_k = sum u cos(k.x), S_k = sum u sin(k.x) of both components over
-//     its sites (first along y per column against the y tables, then along x
-//     in LDS against the x tables) into 4 m partials.
-//  2. k_edm_coef: one workgroup adds the partials in a fixed order and turns the
+//  1. k_edm_fourier: each workgroup pulls the pre-collision populations of a
+//     block of 256 columns and `rows` rows, forms u = j/rho and reduces the
+//     Fourier sums C_k = sum u cos(k.x), S_k = sum u sin(k.x) of both
+//     components over its sites (first along y per column against the y
+//     tables, then per mode against the column's x tables, summed over the
+//     workgroup) into 4 m partials.
+//  2. k_edm_coef: one workgroup adds the partials in block order and turns the
 //     sums into per-row coefficients: with theta = kx phi + ky beta,
 //       F^R(x, y) = sum_{m = 0..km} A_m(y) cos(m phi) + B_m(y) sin(m phi),
 //     A_m = -2 F0 sum_{|kx| = m} (C cos ky beta + S sin ky beta),
@@ -33,13 +34,16 @@ namespace {
 using namespace step_detail;
 using namespace reduce_detail;
 
-constexpr int kDftThreads = 256;
-constexpr int kDftTargetBlocks = 512;
+// Fourier launch: workgroups of kFourierCols threads, one column each, over
+// `rows` consecutive rows; at most 1024 workgroups.  The coefficient kernel is
+// one workgroup of kCoefThreads threads.
+constexpr int kFourierCols = 256;
+constexpr int kCoefThreads = 1024;
 
-int dft_xblocks(int nx) { return (nx + kDftThreads - 1) / kDftThreads; }
+int dft_xblocks(int nx) { return (nx + kFourierCols - 1) / kFourierCols; }
 int dft_rows(int nx, int ny) {
-  const int chunks = std::max(1, kDftTargetBlocks / dft_xblocks(nx));
-  return (ny + chunks - 1) / chunks;
+  const long long r = (static_cast<long long>(ny) * dft_xblocks(nx) + 1023) / 1024;
+  return static_cast<int>(std::max<long long>(1, r));
 }
 int dft_blocks(int nx, int ny) {
   const int r = dft_rows(nx, ny);
@@ -124,23 +128,37 @@ __device__ __forceinline__ void edm_collide(const T (&d)[9], const EdmSite<T>& s
   pair(6, 8, uy - ux, vy - vx, wd);
 }
 
-// ---- 1. Fourier sums of the bare velocity ---------------------------------------
+// ---- 1. Fourier sums of the bare velocity ----------------------------------------
+// Per thread (one column x, rows y0..y1): Uc[n] = sum_y u cos(n beta_y) and
+// Us[n] = sum_y u sin(n beta_y) for n = 0..KM and both components; then per
+// mode k = (kx, ky), with alpha = kx phi_x,
+//   C_k += cos(alpha) Uc[ky] - sin(alpha) Us[ky],  S_k += sin(alpha) Uc[ky] + cos(alpha) Us[ky],
+// reduced over the wavefront by shuffles and over the workgroup's wavefronts
+// in LDS, both in a fixed order.
 template <typename T, int KM>
-__global__ void __launch_bounds__(kDftThreads) k_edm_dft(const T* __restrict__ pop, size_t ps, size_t rs,
-                                                         int nx, int ny, int rows, int xblocks,
-                                                         const double* __restrict__ tabx,
-                                                         const double* __restrict__ taby, EdmModes md,
-                                                         double* __restrict__ partials) {
+__global__ void __launch_bounds__(kFourierCols) k_edm_fourier(const T* __restrict__ pop, size_t ps, size_t rs,
+                                                              int nx, int ny, int rows, int xblocks,
+                                                              const double* __restrict__ tabx,
+                                                              const double* __restrict__ taby, EdmModes md,
+                                                              double* __restrict__ partials) {
   constexpr int K1 = KM + 1;
-  constexpr int NQ = 4 * K1;  // per column: Uc_x[n], Us_x[n], Uc_y[n], Us_y[n], n = 0..KM
-  __shared__ double sh[NQ][kDftThreads];
-  __shared__ double red[kDftThreads];
+  constexpr int kWaves = kFourierCols / 64;
+  __shared__ double wsum[kWaves][4 * kEdmMaxModes];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int xb = blockIdx.x % xblocks, yc = blockIdx.x / xblocks;
-  const int x = xb * kDftThreads + threadIdx.x;
+  const int x = xb * kFourierCols + tid;
   const int y0 = yc * rows, y1 = min(ny, y0 + rows);
-  double acc[NQ];
+  double ucx[K1], usx[K1], ucy[K1], usy[K1];
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+  for (int n = 0; n < K1; ++n) ucx[n] = usx[n] = ucy[n] = usy[n] = 0.0;
+  double cx[K1], sx[K1];
+  cx[0] = 1.0;
+  sx[0] = 0.0;
+#pragma unroll
+  for (int m = 1; m < K1; ++m) {
+    cx[m] = x < nx ? tabx[(2 * m) * nx + x] : 0.0;
+    sx[m] = x < nx ? tabx[(2 * m + 1) * nx + x] : 0.0;
+  }
   if (x < nx) {
     for (int y = y0; y < y1; ++y) {
       const int yn = (y == 0) ? ny - 1 : y - 1;
@@ -150,75 +168,84 @@ __global__ void __launch_bounds__(kDftThreads) k_edm_dft(const T* __restrict__ p
       T di[9];
 #pragma unroll
       for (int l = 0; l < 9; ++l) di[l] = d[l][0];
-      const EdmSite<T> s(di);
-      const double ux = double(s.jx * s.inv), uy = double(s.jy * s.inv);
+      const EdmSite<T> st(di);
+      const double ux = double(st.jx * st.inv), uy = double(st.jy * st.inv);
 #pragma unroll
       for (int n = 0; n < K1; ++n) {
         const double c = taby[(2 * n) * ny + y], sn = taby[(2 * n + 1) * ny + y];
-        acc[n] += ux * c;
-        acc[K1 + n] += ux * sn;
-        acc[2 * K1 + n] += uy * c;
-        acc[3 * K1 + n] += uy * sn;
+        ucx[n] += ux * c;
+        usx[n] += ux * sn;
+        ucy[n] += uy * c;
+        usy[n] += uy * sn;
       }
     }
   }
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) sh[q][threadIdx.x] = acc[q];
-  __syncthreads();
-  // output v = 4 k + comp (comp: C_x, S_x, C_y, S_y); G groups of threads per
-  // output each sum a contiguous run of columns
-  const int V = 4 * md.m;
-  const int G = kDftThreads / V;
-  const int v = threadIdx.x % V, g = threadIdx.x / V;
-  double part = 0.0;
-  if (g < G) {
-    const int k = v >> 2, comp = v & 3;
+  for (int k = 0; k < md.m; ++k) {
     const int kx = md.kx[k], ky = md.ky[k];
-    const int m = kx < 0 ? -kx : kx;
-    const double sg = kx < 0 ? -1.0 : 1.0;
-    const int uq = (comp >> 1) * 2 * K1;
-    const int chunk = (kDftThreads + G - 1) / G;
-    const int i0 = g * chunk, i1 = min(kDftThreads, i0 + chunk);
-    for (int i = i0; i < i1; ++i) {
-      const int xi = xb * kDftThreads + i;
-      if (xi >= nx) break;
-      const double ca = tabx[(2 * m) * nx + xi], sa = sg * tabx[(2 * m + 1) * nx + xi];
-      const double uc = sh[uq + ky][i], us = sh[uq + K1 + ky][i];
-      part += (comp & 1) ? (sa * uc + ca * us) : (ca * uc - sa * us);
+    const int mk = kx < 0 ? -kx : kx;
+    double ca = 0.0, sa = 0.0, a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0;
+#pragma unroll
+    for (int n = 0; n < K1; ++n) {
+      ca = n == mk ? cx[n] : ca;
+      sa = n == mk ? sx[n] : sa;
+      a0 = n == ky ? ucx[n] : a0;
+      a1 = n == ky ? usx[n] : a1;
+      b0 = n == ky ? ucy[n] : b0;
+      b1 = n == ky ? usy[n] : b1;
+    }
+    if (kx < 0) sa = -sa;
+    double v[4] = {ca * a0 - sa * a1, sa * a0 + ca * a1, ca * b0 - sa * b1, sa * b0 + ca * b1};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      v[q] = wave_sum(v[q]);
+      if (lane == 0) wsum[wave][4 * k + q] = v[q];
     }
   }
-  red[threadIdx.x] = part;
   __syncthreads();
-  if (threadIdx.x < V) {
-    double a = 0.0;
-    for (int q = 0; q < G; ++q) a += red[q * V + threadIdx.x];
-    partials[static_cast<size_t>(blockIdx.x) * V + threadIdx.x] = a;
+  const int V = 4 * md.m;
+  if (tid < V) {
+    double a = wsum[0][tid];
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) a += wsum[w][tid];
+    partials[static_cast<size_t>(blockIdx.x) * V + tid] = a;
   }
 }
 
-// ---- 2. reduction of the partials and per-row coefficients -------------------------
+// One workgroup: add the partials in block order, then the per-row coefficients.
 template <typename T, int KM>
-__global__ void __launch_bounds__(kDftThreads) k_edm_coef(const double* __restrict__ partials, int nparts,
-                                                          const double* __restrict__ taby, EdmModes md,
-                                                          int ny, T* __restrict__ coef) {
+__global__ void __launch_bounds__(kCoefThreads) k_edm_coef(const double* __restrict__ partials, int nparts,
+                                                              const double* __restrict__ taby, EdmModes md,
+                                                              int ny, T* __restrict__ coef) {
   constexpr int K1 = KM + 1;
-  __shared__ double red[kDftThreads];
+  __shared__ double scratch[kCoefThreads];
   __shared__ double cf[4 * kEdmMaxModes];
-  const int V = 4 * md.m, R = kDftThreads / V;
-  const int v = threadIdx.x % V, r = threadIdx.x / V;
-  double s = 0.0;
-  if (r < R)
-    for (int b = r; b < nparts; b += R) s += partials[static_cast<size_t>(b) * V + v];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  if (threadIdx.x < V) {
-    double a = 0.0;
-    for (int q = 0; q < R; ++q) a += red[q * V + threadIdx.x];
-    cf[threadIdx.x] = a;
+  const int tid = threadIdx.x;
+  const int V = 4 * md.m;
+  {
+    const int R = kCoefThreads / V;
+    const int v = tid % V, r = tid / V;
+    double sum = 0.0;
+    if (r < R) {
+#pragma unroll 4
+      for (int b = r; b < nparts; b += R) sum += partials[static_cast<size_t>(b) * V + v];
+    }
+    scratch[tid] = sum;
+    __syncthreads();
+    if (tid < V) {
+      double a = 0.0;
+      for (int q = 0; q < R; ++q) a += scratch[q * V + tid];
+      cf[tid] = a;
+    }
   }
   __syncthreads();
   const double scale = -2.0 * md.f0;
-  for (int y = threadIdx.x; y < ny; y += kDftThreads) {
+  for (int y = tid; y < ny; y += kCoefThreads) {
+    double cb[K1], sb[K1];
+#pragma unroll
+    for (int n = 0; n < K1; ++n) {
+      cb[n] = taby[(2 * n) * ny + y];
+      sb[n] = taby[(2 * n + 1) * ny + y];
+    }
     double A[2][K1], B[2][K1];
 #pragma unroll
     for (int m = 0; m < K1; ++m) A[0][m] = A[1][m] = B[0][m] = B[1][m] = 0.0;
@@ -226,15 +253,20 @@ __global__ void __launch_bounds__(kDftThreads) k_edm_coef(const double* __restri
       const int kx = md.kx[k], ky = md.ky[k];
       const int mk = kx < 0 ? -kx : kx;
       const double sg = kx < 0 ? -1.0 : (kx > 0 ? 1.0 : 0.0);
-      const double cb = taby[(2 * ky) * ny + y], sb = taby[(2 * ky + 1) * ny + y];
+      double c = 0.0, sn = 0.0;
+#pragma unroll
+      for (int n = 0; n < K1; ++n) {
+        c = n == ky ? cb[n] : c;
+        sn = n == ky ? sb[n] : sn;
+      }
 #pragma unroll
       for (int m = 0; m < K1; ++m) {
         if (m != mk) continue;
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-          const double C = cf[4 * k + 2 * c], S = cf[4 * k + 2 * c + 1];
-          A[c][m] += C * cb + S * sb;
-          B[c][m] += sg * (S * cb - C * sb);
+        for (int q = 0; q < 2; ++q) {
+          const double C = cf[4 * k + 2 * q], S = cf[4 * k + 2 * q + 1];
+          A[q][m] += C * c + S * sn;
+          B[q][m] += sg * (S * c - C * sn);
         }
       }
     }
@@ -384,11 +416,11 @@ template <typename T, int KM>
 int launch_fourier(const lbm_config& c, const EdmWs& w, const EdmModes& md, const void* pop, size_t ps,
                    size_t rs, hipStream_t s) {
   const int nb = dft_blocks(c.nx, c.ny);
-  hipLaunchKernelGGL((k_edm_dft<T, KM>), dim3(nb), dim3(kDftThreads), 0, s, static_cast<const T*>(pop),
+  hipLaunchKernelGGL((k_edm_fourier<T, KM>), dim3(nb), dim3(kFourierCols), 0, s, static_cast<const T*>(pop),
                      ps, rs, c.nx, c.ny, dft_rows(c.nx, c.ny), dft_xblocks(c.nx), w.tabx, w.taby, md,
                      w.partials);
   LBM_HIP(hipGetLastError());
-  hipLaunchKernelGGL((k_edm_coef<T, KM>), dim3(1), dim3(kDftThreads), 0, s, w.partials, nb, w.taby, md,
+  hipLaunchKernelGGL((k_edm_coef<T, KM>), dim3(1), dim3(kCoefThreads), 0, s, w.partials, nb, w.taby, md,
                      c.ny, static_cast<T*>(w.coef));
   LBM_HIP(hipGetLastError());
   return LBM_OK;
