@@ -101,6 +101,61 @@ def single_step_kernel(n, tau, alpha, fx, fy, steps=400):
             "traffic": traffic_from_profile("k_step", "forced4096", tile)}
 
 
+def paper_set_up_256(log, steps=20000, every=100):
+    """The paper's own forced workload (Sec. 3 and 5): 256^2 FP32, exact-difference forcing
+    with the constant-phase stream-function force on 5 <= |k| <= 7 and the damping of
+    1 <= |k| <= 2, for every tau0 of Sec. 5: `steps` steps from rest with the sub-volume
+    balance every `every` steps (all box sides of the workload)."""
+    import math
+    import numpy as np
+    import torch
+    import lbm_inputs as inp
+    from paper_1809_06735_amd import Simulation
+    w = inp.WORKLOADS["paper256"]
+    n = w.n
+    fx, fy = inp.paper_forcing(n)
+    z = np.zeros((n, n))
+    runs = {}
+    for tau in w.taus:
+        sim = Simulation(np.ones((n, n)), z, z, tau, dtype="f32", fx=fx, fy=fy, scheme="edm",
+                         damp_f0=inp.PAPER_DAMPING_F0, damp_shell=inp.PAPER_DAMPING_SHELL,
+                         with_balance=True)
+        sim.step(2 * every)  # spin-up, untimed
+        torch.cuda.synchronize()
+        sim.step_timing(True)
+        t0 = time.perf_counter()
+        stats = []
+        for _ in range(steps // every - 2):
+            sim.step(every)
+            stats.append(sim.balance(w.sizes)["stats"])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        kms, nl = sim.step_time(reset=True)
+        sim.step_timing(False)
+        _, ux, uy, sc = sim.moments()
+        urms = math.sqrt(float((ux.double() ** 2 + uy.double() ** 2).mean()))
+        nu = (tau - 0.5) / 3
+        nsamp = len(stats)
+        mean = lambda L, q: float(np.nanmean([st[k][q]["mean"] for st in stats
+                                              for k in range(len(w.sizes)) if st[k]["L"] == L]))
+        runs[str(tau)] = {
+            "steps_timed": nsamp * every, "balance_samples": nsamp,
+            "wall_s": round(wall, 3),
+            "MLUPS_with_balance": round(n * n * nsamp * every / wall / 1e6, 1),
+            "step_us": round(kms * 1e3 / max(nl, 1), 2),
+            "step_MLUPS": round(n * n * nl / (kms * 1e-3) / 1e6, 1) if kms > 0 else None,
+            "U_rms": round(urms, 4), "Re_UN_over_nu": round(urms * n / nu, 0),
+            "min_rho": round(sc["min_rho"], 4),
+            "mean_dE": {str(L): mean(L, "dE") for L in (4, 16, 64, 181, 256)},
+            "mean_dZ": {str(L): mean(L, "dZ") for L in (4, 16, 64, 181, 256)},
+            "mean_Ma": {str(L): mean(L, "Ma") for L in (4, 256)}}
+        log(f"[bench] paper set-up tau0={tau}: {runs[str(tau)]['step_us']} us/step, "
+            f"U_rms {urms:.4f}, Re {urms * n / nu:.0f}")
+        sim.close()
+    return {"workload": w.name, "damping_rate_F0R": inp.PAPER_DAMPING_F0,
+            "forcing_F0T_lattice": inp.PAPER_FORCING_F0_LATTICE, "runs": runs}
+
+
 def cpu_baseline(n, tau, alpha, fx, fy, steps):
     import torch
     from oracle import ref
@@ -270,6 +325,10 @@ def main():
             del plain
         except Exception as e:  # noqa: BLE001
             extras["plain_unforced_4096_fp32"] = f"error: {e}"
+        try:
+            extras["paper_set_up_256"] = paper_set_up_256(log)
+        except Exception as e:  # noqa: BLE001
+            extras["paper_set_up_256"] = f"error: {e}"
         try:
             from paper_1809_06735_amd import ensemble as ens_mod
             extras["ensemble"] = ens_mod.bench_ensemble(log=log)

@@ -98,6 +98,14 @@ enum {
   LBM_NTERMS = 13
 };
 
+/* ---- one row of the explicit-window output: the 13 box means, then ----------- */
+enum {
+  LBM_W_DE = 13,   /* delta^E of the window   (Eq. 12)                            */
+  LBM_W_DZ = 14,   /* delta^Omega             (Eq. 13)                            */
+  LBM_W_MA = 15,   /* Ma_V                    (Eq. 20)                            */
+  LBM_NWVALS = 16
+};
+
 /* Simulation parameters of one periodic grid. */
 typedef struct {
   int32_t nx, ny;      /* grid extents, each >= 16 (the composed 8th-order stencils
@@ -118,12 +126,13 @@ typedef struct {
   int32_t reserved;    /* must be 0                                              */
   /* Spectral damping of the large scales (Sec. 3, Eq. 16), LBM_FORCE_EDM only:
    *   F^R(x) = -damp_f0 sum_{kmin <= |k| <= kmax} u^(k) exp(2 pi i (kx x/nx + ky y/ny)),
-   *   u^(k)  = sum_x u(x) exp(-2 pi i (kx x/nx + ky y/ny))   (unnormalised),
-   * over integer wavevectors k, from the bare velocity u = j/rho of the
-   * pre-collision populations of the same step (so F^R = -damp_f0 nx ny P[u],
-   * P the projection on those modes; damp_f0 = 1e-5 on 256^2 damps them at the
-   * rate 0.65536 per step).  damp_f0 = 0: no damping.  Otherwise
-   * 0 < damp_kmin <= damp_kmax <= 4 and 2 damp_kmax < min(nx, ny).          */
+   *   u^(k)  = (1/(nx ny)) sum_x u(x) exp(-2 pi i (kx x/nx + ky y/ny)),
+   * over integer wavevectors k, the u^(k) being the Fourier-series
+   * coefficients of the bare velocity u = j/rho of the pre-collision
+   * populations of the same step: F^R = -damp_f0 P[u], P the projection on
+   * those modes, so damp_f0 is a damping rate per step (1e-5 in the paper).
+   * damp_f0 = 0: no damping.  Otherwise 0 < damp_kmin <= damp_kmax <= 4 and
+   * 2 damp_kmax < min(nx, ny).                                              */
   double damp_f0;
   double damp_kmin, damp_kmax;
   void* stream;        /* hipStream_t to enqueue on, or NULL                     */
@@ -221,7 +230,9 @@ LBM_API int lbm_moments(lbm_ctx ctx, void* rho, void* ux, void* uy, int32_t out_
  *           per window corner (y0, x0), or NULL.  For L == nx == ny only
  *           element [0][0] of each map is meaningful.
  *   windows[nwin][3] : host (x0, y0, L) triples, or NULL with nwin = 0.
- *   wterms[nwin][13] : host box means of the 13 fields at those windows.
+ *   wterms[nwin][LBM_NWVALS] : host, per window the box means of the 13 fields
+ *           (LBM_T_* order) followed by its delta^E, delta^Omega and Ma_V
+ *           (LBM_W_*; NaN delta for a zero denominator).
  *   term_fields : device FP64 [13][ny][nx] pointwise integrand fields, or NULL.
  * Synchronous.  Returns LBM_E_DIVERGED if the moments at t are not finite. */
 LBM_API int lbm_subvolume_balance(lbm_ctx ctx, const int32_t* sizes, int32_t nsizes,

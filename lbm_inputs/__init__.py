@@ -130,11 +130,24 @@ def forcing_field(n: int, seed: int = 0, kmin: float = 4.0, kmax: float = 6.0,
     return fx * scale, fy * scale
 
 
-def paper_forcing(n: int = 256, f0: float = 8e-4, kmin: float = 5.0, kmax: float = 7.0,
-                  phase: float = 0.0):
+#: printed amplitudes of Sec. 3: F0^T of the stream function (Eq. 14) and F0^R of
+#: the damping (Eq. 16)
+PAPER_FORCING_F0 = 8e-4
+PAPER_DAMPING_F0 = 1e-5
+PAPER_DAMPING_SHELL = (1.0, 2.0)
+#: F0^T in lattice units used for the paper's workload: the printed 8e-4 with
+#: Psi and its derivatives in lattice units drives every tau0 of Sec. 5 to
+#: divergence within 2000 steps; 0.0075 x 8e-4 reproduces the printed Reynolds
+#: numbers (U_rms N / nu = 90 ... 1800 for tau0 = 0.60 ... 0.515) and the
+#: stability limit (tau0 = 0.515 stable, 0.51 not) with the damping rate F0^R
+PAPER_FORCING_F0_LATTICE = 8e-4 * 0.0075
+
+
+def paper_forcing(n: int = 256, f0: float = PAPER_FORCING_F0_LATTICE, kmin: float = 5.0,
+                  kmax: float = 7.0, phase: float = 0.0):
     """The turbulent forcing of Sec. 3 (Eqs. 14-15): stream function
     Psi = f0 sum_{kmin<=|k|<=kmax} cos(2 pi k.x / n + phase) with one phase for every
-    wavevector, F = (d_y Psi, -d_x Psi) analytically, not rescaled.  Returns
+    wavevector, F = (d_y Psi, -d_x Psi) analytically in lattice units.  Returns
     (fx, fy) float64 [n, n] indexed [y, x]."""
     w = 2.0 * math.pi / n
     yy, xx = np.meshgrid(np.arange(n, dtype=np.float64), np.arange(n, dtype=np.float64), indexing="ij")
@@ -239,13 +252,10 @@ WORKLOADS = {
     "adjoint512": Workload("differentiable decaying run 512^2 fp32", 512, "f32", 0.51, 2000,
                            "spectrum", seed=7, sizes=(32,)),
     # the paper's own set-up (Sec. 3): exact-difference forcing, turbulent force on
-    # 5 <= |k| <= 7 (F0^T = 8e-4, one phase), damping of 1 <= |k| <= 2 with
-    # F0^R = 1e-5 (rate F0^R N^2 per step), tau0 sweep of Sec. 5
+    # 5 <= |k| <= 7 (one phase, lattice amplitude PAPER_FORCING_F0_LATTICE), damping
+    # of 1 <= |k| <= 2 at the rate F0^R = 1e-5 per step, tau0 sweep of Sec. 5
     "paper256": Workload("the paper's forced 2D turbulence 256^2 fp32, exact-difference forcing", 256,
                          "f32", 0.52, 20000, "rest", seed=0, force=True,
                          sizes=(4, 8, 16, 32, 64, 128, 181, 256), balance_every=100,
                          taus=(0.60, 0.54, 0.53, 0.52, 0.515)),
 }
-#: damping of the paper's set-up: F0^R and the shell 1 <= |k| <= 2 of Eq. 16
-PAPER_DAMPING_F0 = 1e-5
-PAPER_DAMPING_SHELL = (1.0, 2.0)

@@ -464,10 +464,10 @@ def shell_projection(a, kmin=1.0, kmax=2.0):
 
 def damping_force(ux, uy, amp, kmin=1.0, kmax=2.0):
     """Eq. 16, F^R = -F0^R sum_{kmin<=|k|<=kmax} u^(k) e^{i 2 pi k.x / N}, read with
-    the imaginary unit restored in the exponent, u^ the unnormalised discrete
-    Fourier transform sum_x u(x) e^{-i 2 pi k.x / N} and the sum over +-k real:
-    F^R = -F0^R N^2 P[u] with P the projection on those wavevectors.  amp is the
-    rate F0^R N^2 (0.65536 for F0^R = 1e-5 at N = 256)."""
+    the imaginary unit restored in the exponent, u^ the Fourier-series
+    coefficients (1/N^2) sum_x u(x) e^{-i 2 pi k.x / N} and the sum over +-k real:
+    F^R = -F0^R P[u] with P the projection on those wavevectors.  amp = F0^R,
+    a damping rate per step (1e-5 in the paper)."""
     return -amp * shell_projection(ux, kmin, kmax), -amp * shell_projection(uy, kmin, kmax)
 
 

@@ -32,6 +32,7 @@ LBM_BATCH_PERSISTENT = 0
 LBM_BATCH_PER_STEP = 1
 LBM_BATCH_MULTI_STEP = 2
 NTERMS = 13
+NWVALS = 16   # per explicit window: 13 box means, delta^E, delta^Omega, Ma
 TERM_NAMES = ("lhs_E", "e1", "e2", "e3", "e4", "e5",
               "lhs_Z", "z1", "z2", "z3", "z4", "z5", "usq")
 SCALAR_NAMES = ("mass", "mom_x", "mom_y", "energy", "max_speed", "min_rho", "nonfinite", "time")

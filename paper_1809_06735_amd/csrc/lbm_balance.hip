@@ -699,11 +699,21 @@ __global__ void __launch_bounds__(256) k_sum_stats_final(const double* __restric
   }
 }
 
+// Per explicit window: the NT box means, then delta^E, delta^Omega and Ma_V.
 __global__ void k_window_terms(SatView v, const int32_t* __restrict__ win, int nwin, double* out) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nwin) return;
   const int x0 = win[3 * k], y0 = win[3 * k + 1], L = win[3 * k + 2];
-  for (int f = 0; f < NT; ++f) out[k * NT + f] = v.box_mean(f, x0, y0, L);
+  double m[NT];
+  for (int f = 0; f < NT; ++f) {
+    m[f] = v.box_mean(f, x0, y0, L);
+    out[k * LBM_NWVALS + f] = m[f];
+  }
+  double dE, dZ, ma;
+  window_errors(m, dE, dZ, ma);
+  out[k * LBM_NWVALS + LBM_W_DE] = dE;
+  out[k * LBM_NWVALS + LBM_W_DZ] = dZ;
+  out[k * LBM_NWVALS + LBM_W_MA] = ma;
 }
 
 int stat_blocks(size_t count) {
@@ -736,7 +746,7 @@ BalanceWs carve_balance(Carver& c, int nx, int ny) {
   w.partials = c.take<double>(np + static_cast<size_t>(NT) * kMeanBlocks);
   w.partials_cap = np;
   w.stats = c.take<double>(static_cast<size_t>(kMaxSizes) * kStatVals);
-  w.wterms = c.take<double>(static_cast<size_t>(kMaxWindows) * NT);
+  w.wterms = c.take<double>(static_cast<size_t>(kMaxWindows) * LBM_NWVALS);
   w.windows = c.take<int32_t>(static_cast<size_t>(kMaxWindows) * 3);
   return w;
 }
@@ -865,7 +875,7 @@ int run_balance(const lbm_balance_input& in, const BalanceWs& ws, const int32_t*
   if (nsizes > 0)
     LBM_HIP(hipMemcpyAsync(st.data(), ws.stats, st.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   if (nwin > 0)
-    LBM_HIP(hipMemcpyAsync(wterms, ws.wterms, sizeof(double) * NT * nwin, hipMemcpyDeviceToHost, s));
+    LBM_HIP(hipMemcpyAsync(wterms, ws.wterms, sizeof(double) * LBM_NWVALS * nwin, hipMemcpyDeviceToHost, s));
   LBM_HIP(hipStreamSynchronize(s));
   for (int k = 0; k < nsizes; ++k) {
     const double* q = st.data() + static_cast<size_t>(k) * kStatVals;

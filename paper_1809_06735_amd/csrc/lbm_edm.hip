@@ -514,7 +514,8 @@ int dispatch(const lbm_config& c, const EdmModes& md, const F& f) {
 int edm_modes(const lbm_config& c, EdmModes* out) {
   EdmModes md;
   if (c.force_scheme == LBM_FORCE_EDM && c.damp_f0 > 0.0) {
-    md.f0 = c.damp_f0;
+    // per unnormalised Fourier sum: F^R = -(damp_f0 / (nx ny)) sum_k (sum_x u e^{-ik.x}) e^{ik.x}
+    md.f0 = c.damp_f0 / (static_cast<double>(c.nx) * c.ny);
     const double lo = c.damp_kmin * c.damp_kmin, hi = c.damp_kmax * c.damp_kmax;
     for (int ky = 0; ky <= kEdmMaxK; ++ky)
       for (int kx = -kEdmMaxK; kx <= kEdmMaxK; ++kx) {

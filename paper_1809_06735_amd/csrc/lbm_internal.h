@@ -132,7 +132,7 @@ constexpr int kEdmMaxModes = 24;
 struct EdmModes {
   int m = 0;   // number of modes (0: no damping)
   int km = 0;  // largest |kx| or |ky| among them
-  double f0 = 0.0;
+  double f0 = 0.0;  // damping rate over nx ny (the factor of the unnormalised sums)
   int8_t kx[kEdmMaxModes] = {};
   int8_t ky[kEdmMaxModes] = {};
 };
@@ -166,7 +166,7 @@ struct BalanceWs {
   double* partials;  // block partials
   size_t partials_cap;  // doubles of window partials before the field-sum partials
   double* stats;     // device stats scratch
-  double* wterms;    // [LBM_MAX_WINDOWS][13]
+  double* wterms;    // [kMaxWindows][LBM_NWVALS]
   int32_t* windows;  // [LBM_MAX_WINDOWS][3]
 };
 constexpr int kMaxWindows = 4096;

@@ -56,7 +56,7 @@ def _balance_args(nx, ny, sizes, windows):
         flat = [int(v) for w in windows for v in w]
         win = (C.c_int32 * len(flat))(*flat)
         nwin = len(windows)
-        wterms = (C.c_double * (L.NTERMS * nwin))()
+        wterms = (C.c_double * (L.NWVALS * nwin))()
     else:
         win, nwin, wterms = None, 0, None
     return sizes, sz, out, win, nwin, wterms
@@ -67,7 +67,9 @@ def _balance_result(sizes, out, maps, nwin, wterms, terms, nx, ny):
     if maps is not None:
         res["maps"] = maps
     if nwin:
-        res["window_terms"] = np.frombuffer(wterms, dtype=np.float64).reshape(nwin, L.NTERMS).copy()
+        wv = np.frombuffer(wterms, dtype=np.float64).reshape(nwin, L.NWVALS).copy()
+        res["window_terms"] = wv[:, :L.NTERMS]
+        res["window_errors"] = wv[:, L.NTERMS:]  # delta^E, delta^Omega, Ma per window
     if terms is not None:
         res["terms"] = {k: terms[i] for i, k in enumerate(L.TERM_NAMES)}
     return res
@@ -83,7 +85,8 @@ class Simulation:
     scheme: "guo" (Guo's forcing term) or "edm" (the exact-difference method of
     the paper's Sec. 3); with "edm", damp_f0 > 0 adds the spectral damping
     F^R = -damp_f0 sum u^(k) e^{i k.x} of the modes damp_shell[0] <= |k| <=
-    damp_shell[1] (Eq. 16, unnormalised transform).
+    damp_shell[1] (Eq. 16, u^ the Fourier-series coefficients, so damp_f0 is
+    a rate per step).
     """
 
     def __init__(self, rho0, ux0, uy0, tau, dtype="f32", fx=None, fy=None, alpha=0.0,
@@ -179,6 +182,23 @@ class Simulation:
         L.check(self._lib.lbm_subvolume_balance(self._h, sz, len(sizes), out, _ptr(dm), win, nwin,
                                                 wterms, _ptr(tf)), "lbm_subvolume_balance")
         return _balance_result(sizes, out, dm, nwin, wterms, tf, self.nx, self.ny)
+
+    def window_series(self, windows, every, count):
+        """Balance of explicit windows (x0, y0, L) sampled every `every` (>= 2) steps,
+        `count` times: the time series of one sub-volume's balance of Sec. 3 (Figs. 1-2).
+        Returns {'time': [count], 'terms': [count, nwin, 13] box means (LHS and each
+        right-hand-side term), 'errors': [count, nwin, 3] delta^E, delta^Omega, Ma_V}."""
+        every, count = int(every), int(count)
+        if every < 2:
+            raise ValueError("every must be >= 2 (the time derivative needs two recorded steps)")
+        times, terms, errs = [], [], []
+        for _ in range(count):
+            self.step(every)
+            r = self.balance((), windows=windows)
+            times.append(self.time)
+            terms.append(r["window_terms"])
+            errs.append(r["window_errors"])
+        return {"time": np.array(times), "terms": np.stack(terms), "errors": np.stack(errs)}
 
     # -- checkpoints ------------------------------------------------------------------------------
     def state_bytes(self) -> int:

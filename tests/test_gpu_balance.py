@@ -66,6 +66,14 @@ def test_balance_fields_parity(gpu_lib, n, sizes, force):
         scale = float(flds[name].abs().max())
         d = np.abs(res["window_terms"][:, k] - wt[:, k].numpy()).max()
         assert d <= term_tol(kt, name) * scale, (name, d, scale)
+    # each window's delta^E, delta^Omega, Ma from its box means (Eqs. 12-13, 20)
+    wm = {name: wt[:, k] for k, name in enumerate(ref.TERM_NAMES)}
+    for q, o in enumerate(ref.balancing_errors(wm)):
+        g = torch.as_tensor(res["window_errors"][:, q])
+        fin = torch.isfinite(o)
+        assert torch.equal(torch.isfinite(g), fin), q
+        r = max(1e-9, 30 * max(kk[qq]["max"] for kk in ks for qq in ("dE", "dZ", "Ma")))
+        assert torch.allclose(g[fin], o[fin], rtol=r, atol=1e-12), (q, g, o)
     for got, w, kk in zip(res["stats"], want, ks):
         compare_stats(got, w, kk, label=f"n={n}")
     for k, w in enumerate(want):

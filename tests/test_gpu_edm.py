@@ -65,9 +65,12 @@ def _run_case(ny, nx, dtype, steps, tau, amp, shell=(1.0, 2.0), force="random", 
     elif force == "paper":
         assert nx == ny
         fx, fy = inp.paper_forcing(nx)
+    elif force == "paper-literal":
+        assert nx == ny
+        fx, fy = inp.paper_forcing(nx, f0=inp.PAPER_FORCING_F0)
     else:
         fx = fy = None
-    f0 = amp / (nx * ny)
+    f0 = amp
     say(f"{label}: {ny}x{nx} {dtype} {steps} steps tau {tau} amp {amp} shell {shell} force {force}")
     sim = Sim(rho, ux, uy, tau, dtype=dtype, fx=fx, fy=fy, scheme="edm", damp_f0=f0, damp_shell=shell)
     sim.step(steps)
@@ -83,11 +86,17 @@ def test_edm_damped_fp64_nonsquare(gpu_lib):
 
 
 def test_edm_paper_set_up_256(gpu_lib):
-    """The paper's configuration on 256^2: F0^T = 8e-4 on 5 <= |k| <= 7 with one phase,
-    F0^R = 1e-5 on 1 <= |k| <= 2 (rate 0.65536), tau0 = 0.52; FP64 and FP32 storage."""
-    amp = inp.PAPER_DAMPING_F0 * 256 * 256
+    """The paper's configuration on 256^2: the stream-function force on 5 <= |k| <= 7 with
+    one phase (lattice amplitude of the workload), damping of 1 <= |k| <= 2 at the rate
+    F0^R = 1e-5, tau0 = 0.52; FP64 and FP32 storage.  A second pair of runs takes the
+    printed F0^T = 8e-4 in lattice units and a damping rate of 0.65 (both far stronger)
+    so that every term is large."""
+    amp = inp.PAPER_DAMPING_F0
     _run_case(256, 256, "f64", 30, 0.52, amp, force="paper", seed=3, label="paper256 f64")
     _run_case(256, 256, "f32", 30, 0.52, amp, force="paper", seed=3, tol=TOL32, label="paper256 f32")
+    _run_case(256, 256, "f64", 30, 0.52, 0.65, force="paper-literal", seed=3, label="strong256 f64")
+    _run_case(256, 256, "f32", 30, 0.52, 0.65, force="paper-literal", seed=3, tol=TOL32,
+              label="strong256 f32")
 
 
 @pytest.mark.parametrize("shell", [(1.0, 1.0), (2.0, 3.0), (0.5, 4.0)])
@@ -112,7 +121,7 @@ def test_edm_shapes_graphs_and_checkpoint_bitwise(gpu_lib):
     n = 64
     rho, ux, uy = _fields(n, n, 11)
     fx, fy = inp.paper_forcing(n, f0=1e-4)
-    kw = dict(dtype="f32", fx=fx, fy=fy, scheme="edm", damp_f0=0.4 / (n * n))
+    kw = dict(dtype="f32", fx=fx, fy=fy, scheme="edm", damp_f0=0.4)
 
     def run(tile=None, graph=0, steps=70, split=None):
         s = Sim(rho, ux, uy, 0.53, **kw)
@@ -165,7 +174,7 @@ def test_edm_balance_of_a_run(gpu_lib):
     amp = 0.4
     rho, ux, uy = _fields(n, n, 13)
     fx, fy = inp.paper_forcing(n, f0=1e-4)
-    sim = Sim(rho, ux, uy, tau, dtype="f64", fx=fx, fy=fy, scheme="edm", damp_f0=amp / (n * n),
+    sim = Sim(rho, ux, uy, tau, dtype="f64", fx=fx, fy=fy, scheme="edm", damp_f0=amp,
               with_balance=True)
     sim.step(steps)
     res = sim.balance((6, 24, 48), term_fields=True)
@@ -185,3 +194,34 @@ def test_edm_balance_of_a_run(gpu_lib):
     for got, w in zip(res["stats"], want):
         for q in ("dE", "dZ", "Ma"):
             assert got[q]["count"] == w[q]["count"], (got["L"], q)
+
+
+def test_edm_window_time_series(gpu_lib):
+    """Time series of the balance over explicit windows (the single-sub-volume series of
+    Sec. 3, Figs. 1-2) on a damped exact-difference run: box means of the 13 fields and each
+    window's delta^E, delta^Omega, Ma_V at every sample, against the oracle's run."""
+    n, tau, amp = 48, 0.6, 0.4
+    rho, ux, uy = _fields(n, n, 21)
+    fx, fy = inp.paper_forcing(n, f0=1e-4)
+    sim = Sim(rho, ux, uy, tau, dtype="f64", fx=fx, fy=fy, scheme="edm", damp_f0=amp,
+              with_balance=True)
+    wins = [(5, 7, 34), (40, 44, 17), (0, 0, 48)]
+    ser = sim.window_series(wins, every=6, count=3)
+    assert list(ser["time"]) == [6, 12, 18]
+    assert ser["terms"].shape == (3, 3, 13) and ser["errors"].shape == (3, 3, 3)
+    nu = ref.viscosity(tau)
+    for i, t in enumerate(ser["time"]):
+        _, hist = ref.edm_run_with_history(ref.init_populations(rho, ux, uy), int(t), tau,
+                                           ref.t64(fx), ref.t64(fy), amp)
+        flds = ref.balance_fields([h[0] for h in hist], [h[1] for h in hist], [h[2] for h in hist],
+                                  hist[2][3], hist[2][4], nu)
+        wt = ref.window_terms(flds, wins)
+        for k, name in enumerate(ref.TERM_NAMES):
+            scale = float(flds[name].abs().max())
+            d = float(np.abs(ser["terms"][i, :, k] - wt[:, k].numpy()).max())
+            say(f"t={t} {name}: {d / scale:.1e}")
+            assert d <= 1e-9 * scale, (t, name, d, scale)
+        wm = {name: wt[:, k] for k, name in enumerate(ref.TERM_NAMES)}
+        for q, o in enumerate(ref.balancing_errors(wm)):
+            g = torch.as_tensor(ser["errors"][i, :, q])
+            assert torch.allclose(g, o, rtol=1e-7, atol=1e-12), (t, q, g, o)

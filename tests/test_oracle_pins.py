@@ -666,9 +666,17 @@ def test_shell_projection_keeps_exactly_the_shell():
     assert float(fy.abs().max()) < 1e-14
 
 
-def test_paper_damping_rate():
-    """F0^R = 1e-5 on a 256^2 grid with unnormalised transforms: rate F0^R N^2 per step."""
-    assert inp.PAPER_DAMPING_F0 * 256 * 256 == pytest.approx(0.65536, rel=1e-15)
+def test_paper_amplitudes():
+    """The printed amplitudes of Sec. 3 and the lattice amplitude of the workload."""
+    assert inp.PAPER_FORCING_F0 == 8e-4 and inp.PAPER_DAMPING_F0 == 1e-5
+    assert inp.PAPER_DAMPING_SHELL == (1.0, 2.0)
+    assert inp.PAPER_FORCING_F0_LATTICE == pytest.approx(6e-6, rel=1e-12)
+    # the damping of one in-shell mode is the rate times the mode (normalised coefficients)
+    n = 32
+    y, x = torch.meshgrid(torch.arange(n, dtype=D), torch.arange(n, dtype=D), indexing="ij")
+    u = 0.01 * torch.cos(2 * math.pi * (x + y) / n)
+    fx, _ = ref.damping_force(u, torch.zeros_like(u), inp.PAPER_DAMPING_F0)
+    assert float((fx + 1e-5 * u).abs().max()) < 1e-20
 
 
 def test_paper_forcing_is_the_curl_of_its_stream_function():
