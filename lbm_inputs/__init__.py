@@ -160,6 +160,44 @@ def paper_forcing(n: int = 256, f0: float = PAPER_FORCING_F0_LATTICE, kmin: floa
     return fx, fy
 
 
+def table1_count(L: int, n: int = 256) -> int:
+    """Sub-volumes processed per side L on an n x n grid (Sec. 3, Table 1): the whole
+    domain once, 1000 for 100 <= L < 256, 5000 for 10 <= L < 100, 10000 below, the
+    thresholds scaled by n / 256 on other grids."""
+    if L >= n:
+        return 1
+    if L * 256 >= 100 * n:
+        return 1000
+    if L * 256 >= 10 * n:
+        return 5000
+    return 10000
+
+
+def table1_corners(n: int, sizes, seed: int = 0):
+    """Random lower corners (x0, y0) of the sub-volumes of Table 1 for each side in
+    `sizes`, uniform over the grid, drawn with default_rng(seed) in the order of
+    `sizes`; the whole-domain box has the corner (0, 0).  Returns (corners int32
+    [total, 2], counts list) with the corners of sizes[k] in the k-th run."""
+    rng = np.random.default_rng(seed)
+    parts, counts = [], []
+    for L in sizes:
+        c = table1_count(int(L), n)
+        if c == 1:
+            xy = np.zeros((1, 2), dtype=np.int64)
+        else:
+            xy = rng.integers(0, n, size=(c, 2))
+        parts.append(xy)
+        counts.append(c)
+    return np.ascontiguousarray(np.concatenate(parts).astype(np.int32)), counts
+
+
+def log_edges(lo: float = 1e-6, hi: float = 10.0, per_decade: int = 10):
+    """Logarithmic bin edges lo * 10^(i / per_decade) up to hi (for the PDFs of the
+    balancing errors, Figs. 6-7 and 11-12)."""
+    nd = int(round(np.log10(hi / lo) * per_decade))
+    return lo * 10.0 ** (np.arange(nd + 1) / per_decade)
+
+
 ENSEMBLE_SIZES = (256, 384, 512, 768, 1024)
 
 

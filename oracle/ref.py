@@ -31,6 +31,10 @@ Parts and where they come from
   balancing errors (Sec. 2, Eqs. 12-13), sub-volume Mach number (Sec. 4,
   Eq. 20), sub-volume means over L x L boxes (Sec. 3, Fig. 3 and Table 1)
   with periodic wrap, statistics mu_l, sigma_l (Sec. 3).
+* Statistics as presented (Sec. 3, Table 1; Figs. 5-13): histograms of
+  delta^E, delta^Omega, Ma_V on given bin edges, the errors of windows at given
+  random corners, pooling over configurations, and the shell-summed energy
+  spectrum from FFTs.
 * Adjoint (gradient of a sub-volume enstrophy-balance residual loss with
   respect to the initial velocity and tau): torch.autograd through the very
   same forward functions.  Pinned by central finite differences.
@@ -521,6 +525,65 @@ def edm_run_with_history(f, nsteps, tau, fx_ext=None, fy_ext=None, amp=0.0, kmin
         if t < nsteps:
             f = edm_step(f, tau, fx_ext, fy_ext, amp, kmin, kmax)
     return f, hist
+
+
+# ---------------------------------------------------------------------------
+# Statistics as the paper presents them (Sec. 3, Table 1; Figs. 6-13)
+# ---------------------------------------------------------------------------
+def histogram(values, edges):
+    """Counts of the finite values per bin: bin 0 below edges[0], bin i in
+    [edges[i-1], edges[i]), bin n at or above edges[-1] (n = len(edges))."""
+    v = t64(values).reshape(-1)
+    v = v[torch.isfinite(v)]
+    e = t64(edges)
+    idx = torch.bucketize(v, e, right=True)  # number of edges <= v
+    return torch.bincount(idx, minlength=len(e) + 1)
+
+
+def sampled_errors(fields, L, corners):
+    """delta^E, delta^Omega, Ma_V (Eqs. 12-13, 20) of the L x L windows whose lower
+    corners (x0, y0) are given, taken modulo the grid (the randomly placed
+    sub-volumes of Sec. 3, Fig. 3)."""
+    ny, nx = next(iter(fields.values())).shape
+    c = torch.as_tensor(corners, dtype=torch.int64).reshape(-1, 2)
+    xs = torch.remainder(c[:, 0], nx)
+    ys = torch.remainder(c[:, 1], ny)
+    means = {k: v[ys, xs] for k, v in window_means(fields, L).items()}
+    return balancing_errors(means)
+
+
+def pooled_stats(value_sets):
+    """Statistics (as _stats) of the union of several sets of values: the pooling
+    over configurations of Sec. 4-5 (25 configurations per ensemble)."""
+    return _stats(torch.cat([t64(v).reshape(-1) for v in value_sets]))
+
+
+def shell_index(kx, ky):
+    """Shell s of integer wavevectors: (2s - 1)^2 <= 4 |k|^2 < (2s + 1)^2 (shell 0:
+    4 |k|^2 < 1), i.e. |k| rounded half up, decided in integer arithmetic."""
+    k2 = 4 * (kx * kx + ky * ky)
+    s = torch.floor(torch.sqrt(k2.to(DT)) / 2.0 + 0.5).to(torch.int64)
+    s = torch.where((s > 0) & ((2 * s - 1) ** 2 > k2), s - 1, s)
+    s = torch.where((2 * s + 1) ** 2 <= k2, s + 1, s)
+    return s
+
+
+def energy_spectrum(ux, uy, nshells):
+    """Shell-summed kinetic energy spectrum (Figs. 5 and 10): E(s) = 1/2 sum over the
+    wavevectors of shell s of |u^x(k)|^2 + |u^y(k)|^2, with u^ = fft2(u) / (nx ny) the
+    Fourier-series coefficients and k the signed integer frequencies; s < nshells."""
+    ux, uy = t64(ux), t64(uy)
+    ny, nx = ux.shape
+    ax = torch.fft.fft2(ux) / (nx * ny)
+    ay = torch.fft.fft2(uy) / (nx * ny)
+    p = 0.5 * (ax.abs() ** 2 + ay.abs() ** 2)
+    kx = torch.round(torch.fft.fftfreq(nx, dtype=DT) * nx).to(torch.int64)
+    ky = torch.round(torch.fft.fftfreq(ny, dtype=DT) * ny).to(torch.int64)
+    s = shell_index(kx[None, :], ky[:, None])
+    e = torch.zeros(nshells, dtype=DT)
+    keep = s < nshells
+    e.index_add_(0, s[keep], p[keep])
+    return e
 
 
 # ---------------------------------------------------------------------------

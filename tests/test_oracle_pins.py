@@ -715,3 +715,121 @@ def test_edm_run_with_damping_conserves_global_momentum():
     ua = ref.edm_moments(a, fx, fy, 0.5)[1]
     ub = ref.edm_moments(b, fx, fy, 0.0)[1]
     assert float(ref.shell_projection(ua).abs().max()) < 0.5 * float(ref.shell_projection(ub).abs().max())
+
+
+# ---------------------------------------------------------------------------
+# Statistics as presented: histograms, Table-1 sampling, pooling, spectra
+# ---------------------------------------------------------------------------
+def test_histogram_bins_against_a_loop():
+    """Bin 0 below the first edge, bin i in [e_{i-1}, e_i), the last bin at or above the
+    last edge, NaN not counted; values exactly on an edge go to the bin it opens."""
+    edges = [1e-3, 1e-2, 0.1, 1.0]
+    g = torch.Generator().manual_seed(3)
+    v = torch.cat([10 ** (-4 + 5 * torch.rand(500, generator=g, dtype=D)),
+                   torch.tensor(edges, dtype=D), torch.tensor([float("nan"), 0.0, 5.0], dtype=D)])
+    want = [0] * (len(edges) + 1)
+    for x in v.tolist():
+        if x != x:
+            continue
+        b = 0
+        while b < len(edges) and x >= edges[b]:
+            b += 1
+        want[b] += 1
+    got = ref.histogram(v, torch.tensor(edges, dtype=D))
+    assert got.tolist() == want
+    assert int(got.sum()) == 506
+
+
+def test_sampled_window_errors_against_brute_force():
+    """Errors of windows at random corners (modulo the grid) equal the errors of box means
+    taken by a double loop."""
+    lv = inp.balance_levels(24, seed=4)
+    f = ref.balance_fields(lv["rho"], lv["ux"], lv["uy"], lv["fx"], lv["fy"], 0.004)
+    corners = [(0, 0), (23, 5), (7, 19), (24 + 3, -2)]
+    dE, dZ, ma = ref.sampled_errors(f, 6, corners)
+    for i, (x0, y0) in enumerate(corners):
+        m = {k: torch.tensor(ref.box_mean_brute(v, 6, y0 % 24, x0 % 24), dtype=D) for k, v in f.items()}
+        e, z, a = ref.balancing_errors(m)
+        assert float(abs(dE[i] - e)) <= 1e-12 * float(e) and float(abs(dZ[i] - z)) <= 1e-12 * float(z)
+        assert float(abs(ma[i] - a)) <= 1e-13 * float(a)
+
+
+def test_table1_counts_and_corners():
+    """Table 1 on 256^2: 1 whole-domain box, 1000 for 100 <= L < 256, 5000 for 10 <= L < 100,
+    10000 below; corners uniform on the grid and reproducible from the seed."""
+    assert [inp.table1_count(L) for L in (256, 255, 100, 99, 10, 9, 1)] == \
+        [1, 1000, 1000, 5000, 5000, 10000, 10000]
+    c, n = inp.table1_corners(256, (3, 181, 256), seed=5)
+    assert n == [10000, 1000, 1] and c.shape == (11001, 2) and c.dtype == np.int32
+    assert c.min() >= 0 and c.max() < 256 and tuple(c[-1]) == (0, 0)
+    c2, _ = inp.table1_corners(256, (3, 181, 256), seed=5)
+    assert np.array_equal(c, c2)
+    assert abs(c[:10000].mean() - 127.5) < 3  # uniform over [0, 256)
+
+
+def test_pooled_statistics_merge():
+    """Pooling two configurations equals the pairwise merge of their counts, means and
+    second moments (Chan et al.'s formula, written out here)."""
+    g = torch.Generator().manual_seed(8)
+    a = torch.rand(300, generator=g, dtype=D)
+    b = 2 + torch.rand(500, generator=g, dtype=D)
+    b[7] = float("nan")
+    p = ref.pooled_stats([a, b])
+    bf = b[torch.isfinite(b)]
+    na, nb = a.numel(), bf.numel()
+    ma, mb = float(a.mean()), float(bf.mean())
+    m2a = float(((a - ma) ** 2).sum())
+    m2b = float(((bf - mb) ** 2).sum())
+    n = na + nb
+    mean = (na * ma + nb * mb) / n
+    m2 = m2a + m2b + (mb - ma) ** 2 * na * nb / n
+    assert p["count"] == n and p["n_nan"] == 1
+    assert p["mean"] == pytest.approx(mean, rel=1e-14)
+    assert p["std"] == pytest.approx(math.sqrt(m2 / n), rel=1e-13)
+
+
+def test_shell_index_rounds_half_up_exactly():
+    for kx in range(-40, 41):
+        for ky in range(-40, 41):
+            k2 = kx * kx + ky * ky
+            s = int(ref.shell_index(torch.tensor(kx), torch.tensor(ky)))
+            assert (2 * s - 1) ** 2 <= 4 * k2 < (2 * s + 1) ** 2 or (s == 0 and k2 == 0)
+
+
+def test_energy_spectrum_single_modes_parseval_and_direct_sum():
+    """A single mode puts its energy in its shell; the spectrum sums to half the mean |u|^2
+    (Parseval); on an 8 x 12 grid it equals the spectrum from an explicit double-loop DFT."""
+    n = 32
+    y, x = torch.meshgrid(torch.arange(n, dtype=D), torch.arange(n, dtype=D), indexing="ij")
+    ux = 0.3 * torch.cos(2 * math.pi * (3 * x + 4 * y) / n)   # |k| = 5
+    uy = 0.2 * torch.sin(2 * math.pi * 7 * x / n)             # |k| = 7
+    e = ref.energy_spectrum(ux, uy, 30)
+    assert float(e[5]) == pytest.approx(0.3 ** 2 / 4, rel=1e-13)
+    assert float(e[7]) == pytest.approx(0.2 ** 2 / 4, rel=1e-13)
+    assert float(e.sum() - e[5] - e[7]) < 1e-28
+    g = torch.Generator().manual_seed(9)
+    vx = torch.randn(n, n, generator=g, dtype=D)
+    vy = torch.randn(n, n, generator=g, dtype=D)
+    e = ref.energy_spectrum(vx, vy, 40)
+    assert float(e.sum()) == pytest.approx(0.5 * float((vx ** 2 + vy ** 2).mean()), rel=1e-13)
+    ny, nx = 8, 12
+    vx, vy = vx[:ny, :nx], vy[:ny, :nx]
+    want = [0.0] * 12
+    for ky in range(ny):
+        for kx in range(nx):
+            fx = kx if kx < nx / 2 else kx - nx   # signed frequencies (nx/2 counts as -nx/2)
+            fy = ky if ky < ny / 2 else ky - ny
+            cx = sum(complex(math.cos(-2 * math.pi * (kx * i / nx + ky * j / ny)),
+                             math.sin(-2 * math.pi * (kx * i / nx + ky * j / ny))) * float(vx[j, i])
+                     for j in range(ny) for i in range(nx)) / (nx * ny)
+            cy = sum(complex(math.cos(-2 * math.pi * (kx * i / nx + ky * j / ny)),
+                             math.sin(-2 * math.pi * (kx * i / nx + ky * j / ny))) * float(vy[j, i])
+                     for j in range(ny) for i in range(nx)) / (nx * ny)
+            k2 = fx * fx + fy * fy
+            s = 0
+            while (2 * s + 1) ** 2 <= 4 * k2:
+                s += 1
+            want[s] += 0.5 * (abs(cx) ** 2 + abs(cy) ** 2)
+    got = ref.energy_spectrum(vx, vy, 12)
+    for s in range(12):
+        assert float(got[s]) == pytest.approx(want[s], rel=1e-12, abs=1e-17), s
