@@ -240,6 +240,44 @@ LBM_API int lbm_subvolume_balance(lbm_ctx ctx, const int32_t* sizes, int32_t nsi
                           const int32_t* windows, int32_t nwin, double* wterms,
                           double* term_fields);
 
+/* Optional outputs of the balance for the statistics as the paper presents
+ * them (Sec. 3, Table 1; PDFs of Figs. 6-8 and 11-13; pooling over the 25
+ * configurations of Sec. 4-5).  Zero-initialise and set what is wanted. */
+#define LBM_MAX_EDGES 1024
+typedef struct {
+  const double* edges;           /* host [3][nedges] bin edges of delta^E, delta^Omega and
+                                    Ma_V, each row finite and strictly increasing; NULL:
+                                    no histograms                                        */
+  int32_t nedges;                /* 1..LBM_MAX_EDGES when edges is given                  */
+  int32_t accumulate;            /* 0: statistics and histograms of this call's windows,
+                                    starting a new pool; 1: pooled with every call since
+                                    the last one with accumulate = 0, size slot k with size
+                                    slot k (the caller keeps the sizes in the same order).
+                                    The pool lives in the balance workspace.             */
+  int64_t* hist;                 /* host [nsizes][3][nedges + 1] counts over all corners
+                                    (needs out): bin 0 below edges[0], bin i in
+                                    [edges[i-1], edges[i]), bin nedges at or above the last
+                                    edge; NaN values are not counted (see nan_*).  NULL:
+                                    none                                                  */
+  const int32_t* sample_xy;      /* device [total][2] lower corners (x0, y0) of randomly
+                                    placed windows, taken modulo (nx, ny); the first
+                                    sample_counts[0] have side sizes[0], the next
+                                    sample_counts[1] side sizes[1], ...                   */
+  const int32_t* sample_counts;  /* host [nsizes] counts >= 0, or NULL: no sampled windows */
+  lbm_balance_stats* sample_out; /* host [nsizes] statistics over the sampled windows
+                                    (required with sample_counts)                         */
+  int64_t* sample_hist;          /* host [nsizes][3][nedges + 1] over the sampled windows,
+                                    or NULL                                               */
+} lbm_balance_extra;
+
+/* lbm_subvolume_balance with optional extras; `out` may be NULL (no all-corner
+ * evaluation, then hist must be NULL) when extra is given.  extra = NULL is
+ * lbm_subvolume_balance.  Synchronous. */
+LBM_API int lbm_subvolume_balance_ex(lbm_ctx ctx, const int32_t* sizes, int32_t nsizes,
+                             lbm_balance_stats* out, double* dmaps, const int32_t* windows,
+                             int32_t nwin, double* wterms, double* term_fields,
+                             const lbm_balance_extra* extra);
+
 /* Current time step. */
 LBM_API int lbm_time(lbm_ctx ctx, int64_t* t);
 
@@ -301,6 +339,12 @@ LBM_API int lbm_balance_fields(const lbm_balance_input* in, void* ws, size_t ws_
                        const int32_t* sizes, int32_t nsizes, lbm_balance_stats* out,
                        double* dmaps, const int32_t* windows, int32_t nwin,
                        double* wterms, double* term_fields);
+/* lbm_balance_fields with the extras of lbm_subvolume_balance_ex (the pool of
+ * accumulate = 1 lives in ws). */
+LBM_API int lbm_balance_fields_ex(const lbm_balance_input* in, void* ws, size_t ws_bytes,
+                          const int32_t* sizes, int32_t nsizes, lbm_balance_stats* out,
+                          double* dmaps, const int32_t* windows, int32_t nwin,
+                          double* wterms, double* term_fields, const lbm_balance_extra* extra);
 
 /* ---- batched ensemble ---------------------------------------------------------- */
 /* Many independent grids (sizes, tau, drag and force may differ per run; the

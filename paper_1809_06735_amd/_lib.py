@@ -78,6 +78,16 @@ class BalanceInput(C.Structure):
                 ("fx", C.c_void_p), ("fy", C.c_void_p), ("stream", C.c_void_p)]
 
 
+LBM_MAX_EDGES = 1024
+
+
+class BalanceExtra(C.Structure):
+    _fields_ = [("edges", C.POINTER(C.c_double)), ("nedges", C.c_int32), ("accumulate", C.c_int32),
+                ("hist", C.POINTER(C.c_int64)), ("sample_xy", C.c_void_p),
+                ("sample_counts", C.POINTER(C.c_int32)), ("sample_out", C.POINTER(BalanceStats)),
+                ("sample_hist", C.POINTER(C.c_int64))]
+
+
 class AdjointConfig(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("dtype", C.c_int32), ("box", C.c_int32),
                 ("ckpt_every", C.c_int32), ("reserved", C.c_int32), ("steps", C.c_int64),
@@ -103,6 +113,8 @@ SIGNATURES = {
     "lbm_moments": (_I, [_P, _P, _P, _P, _I32, _DP]),
     "lbm_subvolume_balance": (_I, [_P, C.POINTER(_I32), _I32, C.POINTER(BalanceStats), _P,
                                    C.POINTER(_I32), _I32, _DP, _P]),
+    "lbm_subvolume_balance_ex": (_I, [_P, C.POINTER(_I32), _I32, C.POINTER(BalanceStats), _P,
+                                      C.POINTER(_I32), _I32, _DP, _P, C.POINTER(BalanceExtra)]),
     "lbm_time": (_I, [_P, C.POINTER(_I64)]),
     "lbm_state_bytes": (_I, [_P, C.POINTER(_SZ)]),
     "lbm_save": (_I, [_P, _P]),
@@ -118,6 +130,9 @@ SIGNATURES = {
     "lbm_balance_workspace_bytes": (_I, [_I32, _I32, C.POINTER(_SZ)]),
     "lbm_balance_fields": (_I, [C.POINTER(BalanceInput), _P, _SZ, C.POINTER(_I32), _I32,
                                 C.POINTER(BalanceStats), _P, C.POINTER(_I32), _I32, _DP, _P]),
+    "lbm_balance_fields_ex": (_I, [C.POINTER(BalanceInput), _P, _SZ, C.POINTER(_I32), _I32,
+                                   C.POINTER(BalanceStats), _P, C.POINTER(_I32), _I32, _DP, _P,
+                                   C.POINTER(BalanceExtra)]),
     "lbm_batch_workspace_bytes": (_I, [C.POINTER(Config), _I32, C.POINTER(_SZ)]),
     "lbm_batch_init": (_I, [C.POINTER(Config), _I32, _P, _SZ, _PP, _PP, _PP, _PP, _PP,
                             C.POINTER(_P)]),

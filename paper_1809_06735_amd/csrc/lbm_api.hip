@@ -509,10 +509,13 @@ int lbm_moments(lbm_ctx c, void* rho, void* ux, void* uy, int32_t out_dtype, dou
 
 static int validate_balance_request(int nx, int ny, const int32_t* sizes, int32_t nsizes,
                                     lbm_balance_stats* out, const int32_t* windows, int32_t nwin,
-                                    double* wterms) {
+                                    double* wterms, const lbm_balance_extra* extra = nullptr) {
   if (nsizes < 0 || nsizes > kMaxSizes)
     return fail(LBM_E_INVALID, "nsizes must be in [0, %d]", kMaxSizes);
-  if (nsizes > 0 && (!sizes || !out)) return fail(LBM_E_INVALID, "sizes/out must not be NULL");
+  if (nsizes > 0 && !sizes) return fail(LBM_E_INVALID, "sizes must not be NULL");
+  if (nsizes > 0 && !out && !(extra && extra->sample_counts))
+    return fail(LBM_E_INVALID, "out must not be NULL (without sampled windows)");
+  if (int rc = validate_balance_extra(nsizes, out, extra)) return rc;
   const int m = nx < ny ? nx : ny;
   for (int k = 0; k < nsizes; ++k)
     if (sizes[k] < 1 || sizes[k] > m)
@@ -531,10 +534,17 @@ static int validate_balance_request(int nx, int ny, const int32_t* sizes, int32_
 int lbm_subvolume_balance(lbm_ctx c, const int32_t* sizes, int32_t nsizes, lbm_balance_stats* out,
                           double* dmaps, const int32_t* windows, int32_t nwin, double* wterms,
                           double* term_fields) {
+  return lbm_subvolume_balance_ex(c, sizes, nsizes, out, dmaps, windows, nwin, wterms, term_fields,
+                                  nullptr);
+}
+
+int lbm_subvolume_balance_ex(lbm_ctx c, const int32_t* sizes, int32_t nsizes, lbm_balance_stats* out,
+                             double* dmaps, const int32_t* windows, int32_t nwin, double* wterms,
+                             double* term_fields, const lbm_balance_extra* extra) {
   if (!c) return fail(LBM_E_INVALID, "ctx is NULL");
   if (!c->cfg.with_balance) return fail(LBM_E_STATE, "handle was created with with_balance = 0");
   if (int rc = validate_balance_request(c->cfg.nx, c->cfg.ny, sizes, nsizes, out, windows, nwin,
-                                        wterms))
+                                        wterms, extra))
     return rc;
   const int64_t t = c->t;
   if (t < 2 || c->hist_t[(t - 1) & 1] != t - 1 || c->hist_t[(t - 2) & 1] != t - 2)
@@ -561,7 +571,7 @@ int lbm_subvolume_balance(lbm_ctx c, const int32_t* sizes, int32_t nsizes, lbm_b
   in.fx = forced ? c->ftot[0] : nullptr;
   in.fy = forced ? c->ftot[1] : nullptr;
   in.stream = c->stream;
-  return run_balance(in, c->bal, sizes, nsizes, out, dmaps, windows, nwin, wterms, term_fields);
+  return run_balance(in, c->bal, sizes, nsizes, out, dmaps, windows, nwin, wterms, term_fields, extra);
 }
 
 int lbm_balance_workspace_bytes(int32_t nx, int32_t ny, size_t* bytes) {
@@ -575,6 +585,14 @@ int lbm_balance_workspace_bytes(int32_t nx, int32_t ny, size_t* bytes) {
 int lbm_balance_fields(const lbm_balance_input* in, void* ws, size_t ws_bytes, const int32_t* sizes,
                        int32_t nsizes, lbm_balance_stats* out, double* dmaps,
                        const int32_t* windows, int32_t nwin, double* wterms, double* term_fields) {
+  return lbm_balance_fields_ex(in, ws, ws_bytes, sizes, nsizes, out, dmaps, windows, nwin, wterms,
+                               term_fields, nullptr);
+}
+
+int lbm_balance_fields_ex(const lbm_balance_input* in, void* ws, size_t ws_bytes, const int32_t* sizes,
+                          int32_t nsizes, lbm_balance_stats* out, double* dmaps,
+                          const int32_t* windows, int32_t nwin, double* wterms, double* term_fields,
+                          const lbm_balance_extra* extra) {
   if (!in) return fail(LBM_E_INVALID, "input is NULL");
   size_t need = 0;
   if (int rc = lbm_balance_workspace_bytes(in->nx, in->ny, &need)) return rc;
@@ -587,11 +605,11 @@ int lbm_balance_fields(const lbm_balance_input* in, void* ws, size_t ws_bytes, c
   if ((in->fx == nullptr) != (in->fy == nullptr))
     return fail(LBM_E_INVALID, "fx and fy must both be given or both be NULL");
   if (!std::isfinite(in->nu) || in->nu < 0.0) return fail(LBM_E_INVALID, "nu must be finite, >= 0");
-  if (int rc = validate_balance_request(in->nx, in->ny, sizes, nsizes, out, windows, nwin, wterms))
+  if (int rc = validate_balance_request(in->nx, in->ny, sizes, nsizes, out, windows, nwin, wterms, extra))
     return rc;
   Carver cv(ws, ws_bytes);
   BalanceWs b = carve_balance(cv, in->nx, in->ny);
-  return run_balance(*in, b, sizes, nsizes, out, dmaps, windows, nwin, wterms, term_fields);
+  return run_balance(*in, b, sizes, nsizes, out, dmaps, windows, nwin, wterms, term_fields, extra);
 }
 
 int lbm_time(lbm_ctx c, int64_t* t) {

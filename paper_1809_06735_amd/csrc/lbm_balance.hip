@@ -20,6 +20,7 @@
 //             window's top row and each table row is read once per side.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -375,6 +376,39 @@ __device__ void window_errors(const double (&m)[NT], double& dE, double& dZ, dou
 }
 
 // Running statistics: n, mean, M2, min, max, nan count.
+// ---- histograms ---------------------------------------------------------------------------
+// Bin of a finite value: the number of edges <= v (0 .. n).
+__device__ __forceinline__ int hist_bin(const double* e, int n, double v) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (e[mid] <= v)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// A workgroup's histogram of one quantity in LDS, flushed to the device counts
+// with integer atomics (exact: the totals do not depend on the order).
+struct LdsHist {
+  unsigned* bins;
+  const double* e;
+  int n;
+  __device__ __forceinline__ void add(double v) const {
+    if (isfinite(v)) atomicAdd(&bins[hist_bin(e, n, v)], 1u);
+  }
+};
+__device__ void lds_hist_init(unsigned* bins, double* e_lds, const double* e, int n) {
+  for (int i = threadIdx.x; i <= n; i += blockDim.x) bins[i] = 0u;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) e_lds[i] = e[i];
+}
+__device__ void lds_hist_flush(const unsigned* bins, int n, unsigned long long* g) {
+  for (int i = threadIdx.x; i <= n; i += blockDim.x)
+    if (bins[i]) atomicAdd(&g[i], static_cast<unsigned long long>(bins[i]));
+}
+
 struct RS {
   double n, mean, m2, mn, mx, nan;
   __device__ void init() {
@@ -464,16 +498,39 @@ __device__ void block_stats(RS (&r)[3], double* out) {
 constexpr int kWinThreads = 256;
 constexpr int kWinMaxBlocks = 1024;
 
-__global__ void __launch_bounds__(kWinThreads) k_windows(SatView v, int L, int single,
-                                                         double* maps, double* partials) {
+// Windows of side L at every corner (xy == nullptr: corner i = (i % nx, i / nx),
+// i < count) or at the corners xy[i] (taken modulo the grid); optional maps
+// (enumerated corners only) and histograms of the three quantities.
+template <bool HIST>
+__global__ void __launch_bounds__(kWinThreads) k_windows(SatView v, int L, const int32_t* __restrict__ xy,
+                                                         size_t count, double* maps, double* partials,
+                                                         const double* __restrict__ edges, int nedges,
+                                                         unsigned long long* hist) {
   RS r[3];
   for (int q = 0; q < 3; ++q) r[q].init();
+  LdsHist hh[3] = {};
+  if constexpr (HIST) {
+    __shared__ unsigned bins[3][LBM_MAX_EDGES + 1];
+    __shared__ double e[3][LBM_MAX_EDGES];
+    for (int q = 0; q < 3; ++q) {
+      lds_hist_init(bins[q], e[q], edges + q * nedges, nedges);
+      hh[q] = LdsHist{bins[q], e[q], nedges};
+    }
+    __syncthreads();
+  }
   const size_t plane = static_cast<size_t>(v.nx) * v.ny;
-  const size_t count = single ? 1 : plane;
   for (size_t i = blockIdx.x * size_t(kWinThreads) + threadIdx.x; i < count;
        i += size_t(gridDim.x) * kWinThreads) {
-    const int x0 = static_cast<int>(i % v.nx);
-    const int y0 = static_cast<int>(i / v.nx);
+    int x0, y0;
+    if (xy) {
+      x0 = xy[2 * i] % v.nx;
+      y0 = xy[2 * i + 1] % v.ny;
+      x0 += x0 < 0 ? v.nx : 0;
+      y0 += y0 < 0 ? v.ny : 0;
+    } else {
+      x0 = static_cast<int>(i % v.nx);
+      y0 = static_cast<int>(i / v.nx);
+    }
     double m[NT];
 #pragma unroll
     for (int f = 0; f < NT; ++f) m[f] = v.box_mean(f, x0, y0, L);
@@ -482,11 +539,20 @@ __global__ void __launch_bounds__(kWinThreads) k_windows(SatView v, int L, int s
     r[0].add(dE);
     r[1].add(dZ);
     r[2].add(ma);
-    if (maps) {
+    if constexpr (HIST) {
+      hh[0].add(dE);
+      hh[1].add(dZ);
+      hh[2].add(ma);
+    }
+    if (maps && !xy) {
       maps[i] = dE;
       maps[plane + i] = dZ;
       maps[2 * plane + i] = ma;
     }
+  }
+  if constexpr (HIST) {
+    __syncthreads();
+    for (int q = 0; q < 3; ++q) lds_hist_flush(hh[q].bins, nedges, hist + q * (nedges + 1));
   }
   block_stats(r, partials + blockIdx.x * kStatVals);
 }
@@ -502,6 +568,32 @@ __global__ void __launch_bounds__(kWinThreads) k_stats_final(const double* __res
       r[q].merge(o);
     }
   block_stats(r, out);
+}
+
+// Pool slot i = (size, quantity): the statistics of this call, or merged with
+// the slot's earlier contents (Chan's pairwise update).
+__global__ void k_stats_pool(const double* __restrict__ cur, double* pool, int nslots, int accumulate) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nslots) return;
+  const double* c = cur + static_cast<size_t>(i) * kRS;
+  double* p = pool + static_cast<size_t>(i) * kRS;
+  RS a{c[0], c[1], c[2], c[3], c[4], c[5]};
+  if (accumulate) {
+    RS b{p[0], p[1], p[2], p[3], p[4], p[5]};
+    b.merge(a);
+    a = b;
+  }
+  p[0] = a.n;
+  p[1] = a.mean;
+  p[2] = a.m2;
+  p[3] = a.mn;
+  p[4] = a.mx;
+  p[5] = a.nan;
+}
+
+__global__ void k_zero_u64(unsigned long long* p, size_t n) {
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
+    p[i] = 0ull;
 }
 
 constexpr int kSumVals = 3 * 6;
@@ -586,7 +678,7 @@ StrideGrid stride_grid(int nx, int ny, int L) {
 // its own statistics slot.
 template <int F0, int NF>
 __device__ __forceinline__ void stride_windows(const SatView& v, int L, int x0, int y0, int S,
-                                               double* maps, SumStat& r) {
+                                               double* maps, SumStat& r, const LdsHist* h) {
   const int nx = v.nx, ny = v.ny;
   const unsigned s = static_cast<unsigned>(nx + 1) * v.nf;  // between rows of one field
   const double inv = 1.0 / (double(L) * double(L));
@@ -631,6 +723,7 @@ __device__ __forceinline__ void stride_windows(const SatView& v, int L, int x0, 
       val = den > 0.0 ? fabs(rs - m[0]) / den : __builtin_nan("");
     }
     r.add(val);
+    if (h) h->add(val);
     if (maps) maps[static_cast<unsigned>(y0) * nx + x0] = val;
   }
 }
@@ -642,8 +735,11 @@ __device__ __forceinline__ void stride_windows(const SatView& v, int L, int x0, 
 // (plus one row per segment) and reused from registers.  Workgroups are
 // numbered so that neighbouring strips share an XCD (and its L2, which serves
 // the columns x0 + L past the strip).
+template <bool HIST>
 __global__ void __launch_bounds__(256) k_windows_strided(SatView v, int L, int strips, int S, int nblocks,
-                                                         int per_xcd, double* maps, double* partials) {
+                                                         int per_xcd, double* maps, double* partials,
+                                                         const double* __restrict__ edges, int nedges,
+                                                         unsigned long long* hist) {
   const int b = blockIdx.x;
   const int logical = (b & 7) * per_xcd + (b >> 3);
   if (logical >= 3 * nblocks) return;  // uniform over the workgroup
@@ -657,13 +753,26 @@ __global__ void __launch_bounds__(256) k_windows_strided(SatView v, int L, int s
   const size_t plane = static_cast<size_t>(v.nx) * v.ny;
   SumStat r[3];
   for (int q = 0; q < 3; ++q) r[q].init();
+  LdsHist hh{nullptr, nullptr, 0};
+  if constexpr (HIST) {
+    __shared__ unsigned bins[LBM_MAX_EDGES + 1];
+    __shared__ double e[LBM_MAX_EDGES];
+    lds_hist_init(bins, e, edges + grp * nedges, nedges);
+    hh = LdsHist{bins, e, nedges};
+    __syncthreads();
+  }
+  const LdsHist* h = HIST ? &hh : nullptr;
   if (x0 < v.nx && y0 < v.ny) {
     if (grp == 0)
-      stride_windows<LBM_T_LHS_E, 6>(v, L, x0, y0, S, maps, r[0]);
+      stride_windows<LBM_T_LHS_E, 6>(v, L, x0, y0, S, maps, r[0], h);
     else if (grp == 1)
-      stride_windows<LBM_T_LHS_Z, 6>(v, L, x0, y0, S, maps ? maps + plane : nullptr, r[1]);
+      stride_windows<LBM_T_LHS_Z, 6>(v, L, x0, y0, S, maps ? maps + plane : nullptr, r[1], h);
     else
-      stride_windows<LBM_T_USQ, 1>(v, L, x0, y0, S, maps ? maps + 2 * plane : nullptr, r[2]);
+      stride_windows<LBM_T_USQ, 1>(v, L, x0, y0, S, maps ? maps + 2 * plane : nullptr, r[2], h);
+  }
+  if constexpr (HIST) {
+    __syncthreads();
+    lds_hist_flush(hh.bins, nedges, hist + grp * (nedges + 1));
   }
   sum_stats_block(r, partials + static_cast<size_t>(logical) * kSumVals);
 }
@@ -746,6 +855,10 @@ BalanceWs carve_balance(Carver& c, int nx, int ny) {
   w.partials = c.take<double>(np + static_cast<size_t>(NT) * kMeanBlocks);
   w.partials_cap = np;
   w.stats = c.take<double>(static_cast<size_t>(kMaxSizes) * kStatVals);
+  w.sstats = c.take<double>(static_cast<size_t>(kMaxSizes) * kStatVals);
+  w.pool = c.take<double>(2 * static_cast<size_t>(kMaxSizes) * kStatVals);
+  w.edges = c.take<double>(3 * static_cast<size_t>(LBM_MAX_EDGES));
+  w.hist = c.take<unsigned long long>(2 * static_cast<size_t>(kMaxSizes) * 3 * (LBM_MAX_EDGES + 1));
   w.wterms = c.take<double>(static_cast<size_t>(kMaxWindows) * LBM_NWVALS);
   w.windows = c.take<int32_t>(static_cast<size_t>(kMaxWindows) * 3);
   return w;
@@ -827,9 +940,77 @@ int box_map(const double* sat, const double* means, int nf, int f, int L, int of
   return LBM_OK;
 }
 
+namespace {
+void fill_stats(const double* q, int L, lbm_balance_stats& o) {
+  o = lbm_balance_stats{};
+  o.L = L;
+  auto fill = [](const double* r, int64_t& cnt, int64_t* nan, double& mean, double& sd, double& mn,
+                 double& mx) {
+    cnt = static_cast<int64_t>(r[0]);
+    if (nan) *nan = static_cast<int64_t>(r[5]);
+    if (cnt > 0) {
+      mean = r[1];
+      sd = std::sqrt(r[2] / r[0]);
+      mn = r[3];
+      mx = r[4];
+    } else {
+      mean = sd = mn = mx = NAN;
+    }
+  };
+  fill(q + 0 * kRS, o.count_dE, &o.nan_dE, o.mean_dE, o.std_dE, o.min_dE, o.max_dE);
+  fill(q + 1 * kRS, o.count_dZ, &o.nan_dZ, o.mean_dZ, o.std_dZ, o.min_dZ, o.max_dZ);
+  fill(q + 2 * kRS, o.count_Ma, nullptr, o.mean_Ma, o.std_Ma, o.min_Ma, o.max_Ma);
+}
+
+int launch_windows(bool hist, const SatView& v, int L, const int32_t* xy, size_t count, int blocks,
+                   double* maps, double* partials, const double* edges, int nedges,
+                   unsigned long long* h, hipStream_t s) {
+  if (hist)
+    hipLaunchKernelGGL(k_windows<true>, dim3(blocks), dim3(kWinThreads), 0, s, v, L, xy, count, maps, partials,
+                       edges, nedges, h);
+  else
+    hipLaunchKernelGGL(k_windows<false>, dim3(blocks), dim3(kWinThreads), 0, s, v, L, xy, count, maps,
+                       partials, edges, nedges, h);
+  LBM_HIP(hipGetLastError());
+  return LBM_OK;
+}
+}  // namespace
+
+int validate_balance_extra(int nsizes, const lbm_balance_stats* out, const lbm_balance_extra* x) {
+  if (!x) return LBM_OK;
+  if (x->accumulate != 0 && x->accumulate != 1) return fail(LBM_E_INVALID, "accumulate must be 0 or 1");
+  if (x->edges) {
+    if (x->nedges < 1 || x->nedges > LBM_MAX_EDGES)
+      return fail(LBM_E_INVALID, "nedges must be in [1, %d]", LBM_MAX_EDGES);
+    for (int q = 0; q < 3; ++q)
+      for (int i = 0; i < x->nedges; ++i) {
+        const double e = x->edges[q * x->nedges + i];
+        if (!std::isfinite(e)) return fail(LBM_E_INVALID, "histogram edge %d of quantity %d not finite", i, q);
+        if (i > 0 && !(e > x->edges[q * x->nedges + i - 1]))
+          return fail(LBM_E_INVALID, "histogram edges of quantity %d not strictly increasing", q);
+      }
+  } else if (x->hist || x->sample_hist) {
+    return fail(LBM_E_INVALID, "histograms need edges");
+  }
+  if (x->hist && !out) return fail(LBM_E_INVALID, "hist needs the all-corner statistics (out)");
+  if (x->sample_counts) {
+    if (!x->sample_out) return fail(LBM_E_INVALID, "sample_counts needs sample_out");
+    long long tot = 0;
+    for (int k = 0; k < nsizes; ++k) {
+      if (x->sample_counts[k] < 0) return fail(LBM_E_INVALID, "sample count %d is negative", k);
+      tot += x->sample_counts[k];
+    }
+    if (tot > 0x7fffffffLL) return fail(LBM_E_INVALID, "too many sampled windows");
+    if (tot > 0 && !x->sample_xy) return fail(LBM_E_INVALID, "sample_xy is NULL");
+  } else if (x->sample_out || x->sample_hist || x->sample_xy) {
+    return fail(LBM_E_INVALID, "sampled windows need sample_counts");
+  }
+  return LBM_OK;
+}
+
 int run_balance(const lbm_balance_input& in, const BalanceWs& ws, const int32_t* sizes,
                 int nsizes, lbm_balance_stats* out, double* dmaps, const int32_t* windows,
-                int nwin, double* wterms, double* term_fields) {
+                int nwin, double* wterms, double* term_fields, const lbm_balance_extra* extra) {
   hipStream_t s = static_cast<hipStream_t>(in.stream);
   const int nx = in.nx, ny = in.ny;
   const size_t plane = static_cast<size_t>(nx) * ny;
@@ -841,29 +1022,78 @@ int run_balance(const lbm_balance_input& in, const BalanceWs& ws, const int32_t*
     return rc;
   if (int rc = sat_build(ws.terms, NT, ws.means, ws.sat, nx, ny, s)) return rc;
 
-  SatView v{ws.sat, ws.means, nx, ny, NT};
-  for (int k = 0; k < nsizes; ++k) {
-    const int L = sizes[k];
-    double* maps = dmaps ? dmaps + static_cast<size_t>(k) * 3 * plane : nullptr;
-    if (L == nx && L == ny) {
-      hipLaunchKernelGGL(k_windows, dim3(1), dim3(kWinThreads), 0, s, v, L, 1, maps, ws.partials);
+  const bool hist = extra && extra->edges;
+  const int ne = hist ? extra->nedges : 0;
+  const int acc = extra ? extra->accumulate : 0;
+  const bool sampled = extra && extra->sample_counts;
+  const size_t hslot = 3 * static_cast<size_t>(LBM_MAX_EDGES + 1);  // per size: [3][ne + 1]
+  unsigned long long* hall = ws.hist;
+  unsigned long long* hsmp = ws.hist + static_cast<size_t>(kMaxSizes) * hslot;
+  if (hist) {
+    LBM_HIP(hipMemcpyAsync(ws.edges, extra->edges, sizeof(double) * 3 * ne, hipMemcpyHostToDevice, s));
+    if (!acc) {
+      hipLaunchKernelGGL(k_zero_u64, dim3(256), dim3(256), 0, s, ws.hist, 2 * static_cast<size_t>(kMaxSizes) * hslot);
       LBM_HIP(hipGetLastError());
-      hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(kWinThreads), 0, s, ws.partials, 1,
+    }
+  }
+
+  SatView v{ws.sat, ws.means, nx, ny, NT};
+  if (out) {
+    for (int k = 0; k < nsizes; ++k) {
+      const int L = sizes[k];
+      double* maps = dmaps ? dmaps + static_cast<size_t>(k) * 3 * plane : nullptr;
+      unsigned long long* hk = hall + static_cast<size_t>(k) * hslot;
+      if (L == nx && L == ny) {
+        if (int rc = launch_windows(hist, v, L, nullptr, 1, 1, maps, ws.partials, ws.edges, ne, hk, s))
+          return rc;
+        hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(kWinThreads), 0, s, ws.partials, 1,
+                           ws.stats + static_cast<size_t>(k) * kStatVals);
+        LBM_HIP(hipGetLastError());
+        continue;
+      }
+      const StrideGrid g = stride_grid(nx, ny, L);
+      if (3 * g.blocks * kSumVals > static_cast<long long>(ws.partials_cap))
+        return fail(LBM_E_INVALID, "box side %d: window partials exceed the workspace", L);
+      const int nb = static_cast<int>(g.blocks);
+      const int per_xcd = (3 * nb + 7) / 8;
+      if (hist)
+        hipLaunchKernelGGL(k_windows_strided<true>, dim3(per_xcd * 8), dim3(256), 0, s, v, L, g.strips, g.S,
+                           nb, per_xcd, maps, ws.partials, ws.edges, ne, hk);
+      else
+        hipLaunchKernelGGL(k_windows_strided<false>, dim3(per_xcd * 8), dim3(256), 0, s, v, L, g.strips, g.S,
+                           nb, per_xcd, maps, ws.partials, ws.edges, ne, hk);
+      LBM_HIP(hipGetLastError());
+      hipLaunchKernelGGL(k_sum_stats_final, dim3(1), dim3(256), 0, s, ws.partials, 3 * nb,
                          ws.stats + static_cast<size_t>(k) * kStatVals);
       LBM_HIP(hipGetLastError());
-      continue;
     }
-    const StrideGrid g = stride_grid(nx, ny, L);
-    if (3 * g.blocks * kSumVals > static_cast<long long>(ws.partials_cap))
-      return fail(LBM_E_INVALID, "box side %d: window partials exceed the workspace", L);
-    const int nb = static_cast<int>(g.blocks);
-    const int per_xcd = (3 * nb + 7) / 8;
-    hipLaunchKernelGGL(k_windows_strided, dim3(per_xcd * 8), dim3(256), 0, s, v, L, g.strips, g.S, nb,
-                       per_xcd, maps, ws.partials);
-    LBM_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_sum_stats_final, dim3(1), dim3(256), 0, s, ws.partials, 3 * nb,
-                       ws.stats + static_cast<size_t>(k) * kStatVals);
-    LBM_HIP(hipGetLastError());
+    if (nsizes > 0) {
+      hipLaunchKernelGGL(k_stats_pool, dim3((3 * nsizes + 63) / 64), dim3(64), 0, s, ws.stats, ws.pool,
+                         3 * nsizes, acc);
+      LBM_HIP(hipGetLastError());
+    }
+  }
+  if (sampled) {
+    size_t off = 0;
+    for (int k = 0; k < nsizes; ++k) {
+      const size_t cnt = static_cast<size_t>(extra->sample_counts[k]);
+      int nb = 0;
+      if (cnt > 0) {
+        nb = static_cast<int>(std::min<size_t>(kWinMaxBlocks, (cnt + kWinThreads - 1) / kWinThreads));
+        if (int rc = launch_windows(hist, v, sizes[k], extra->sample_xy + 2 * off, cnt, nb, nullptr,
+                                    ws.partials, ws.edges, ne, hsmp + static_cast<size_t>(k) * hslot, s))
+          return rc;
+      }
+      hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(kWinThreads), 0, s, ws.partials, nb,
+                         ws.sstats + static_cast<size_t>(k) * kStatVals);
+      LBM_HIP(hipGetLastError());
+      off += cnt;
+    }
+    if (nsizes > 0) {
+      hipLaunchKernelGGL(k_stats_pool, dim3((3 * nsizes + 63) / 64), dim3(64), 0, s, ws.sstats,
+                         ws.pool + static_cast<size_t>(kMaxSizes) * kStatVals, 3 * nsizes, acc);
+      LBM_HIP(hipGetLastError());
+    }
   }
   if (nwin > 0) {
     LBM_HIP(hipMemcpyAsync(ws.windows, windows, sizeof(int32_t) * 3 * nwin, hipMemcpyHostToDevice, s));
@@ -871,33 +1101,32 @@ int run_balance(const lbm_balance_input& in, const BalanceWs& ws, const int32_t*
                        ws.wterms);
     LBM_HIP(hipGetLastError());
   }
-  std::vector<double> st(static_cast<size_t>(nsizes) * kStatVals);
-  if (nsizes > 0)
-    LBM_HIP(hipMemcpyAsync(st.data(), ws.stats, st.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  const size_t sv = static_cast<size_t>(nsizes) * kStatVals;
+  std::vector<double> st(out ? sv : 0), sst(sampled ? sv : 0);
+  std::vector<unsigned long long> hh(hist && extra->hist ? nsizes * hslot : 0);
+  std::vector<unsigned long long> hs(hist && extra->sample_hist ? nsizes * hslot : 0);
+  if (!st.empty()) LBM_HIP(hipMemcpyAsync(st.data(), ws.pool, sv * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (!sst.empty())
+    LBM_HIP(hipMemcpyAsync(sst.data(), ws.pool + static_cast<size_t>(kMaxSizes) * kStatVals,
+                           sv * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (!hh.empty())
+    LBM_HIP(hipMemcpyAsync(hh.data(), hall, hh.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  if (!hs.empty())
+    LBM_HIP(hipMemcpyAsync(hs.data(), hsmp, hs.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
   if (nwin > 0)
     LBM_HIP(hipMemcpyAsync(wterms, ws.wterms, sizeof(double) * LBM_NWVALS * nwin, hipMemcpyDeviceToHost, s));
   LBM_HIP(hipStreamSynchronize(s));
   for (int k = 0; k < nsizes; ++k) {
-    const double* q = st.data() + static_cast<size_t>(k) * kStatVals;
-    lbm_balance_stats& o = out[k];
-    o = lbm_balance_stats{};
-    o.L = sizes[k];
-    auto fill = [](const double* r, int64_t& cnt, int64_t* nan, double& mean, double& sd, double& mn,
-                   double& mx) {
-      cnt = static_cast<int64_t>(r[0]);
-      if (nan) *nan = static_cast<int64_t>(r[5]);
-      if (cnt > 0) {
-        mean = r[1];
-        sd = std::sqrt(r[2] / r[0]);
-        mn = r[3];
-        mx = r[4];
-      } else {
-        mean = sd = mn = mx = NAN;
-      }
+    if (out) fill_stats(st.data() + static_cast<size_t>(k) * kStatVals, sizes[k], out[k]);
+    if (sampled) fill_stats(sst.data() + static_cast<size_t>(k) * kStatVals, sizes[k], extra->sample_out[k]);
+    auto unpack = [&](const std::vector<unsigned long long>& src, int64_t* dst) {
+      for (int q = 0; q < 3; ++q)
+        for (int i = 0; i <= ne; ++i)
+          dst[(static_cast<size_t>(k) * 3 + q) * (ne + 1) + i] =
+              static_cast<int64_t>(src[static_cast<size_t>(k) * hslot + q * (ne + 1) + i]);
     };
-    fill(q + 0 * kRS, o.count_dE, &o.nan_dE, o.mean_dE, o.std_dE, o.min_dE, o.max_dE);
-    fill(q + 1 * kRS, o.count_dZ, &o.nan_dZ, o.mean_dZ, o.std_dZ, o.min_dZ, o.max_dZ);
-    fill(q + 2 * kRS, o.count_Ma, nullptr, o.mean_Ma, o.std_Ma, o.min_Ma, o.max_Ma);
+    if (!hh.empty()) unpack(hh, extra->hist);
+    if (!hs.empty()) unpack(hs, extra->sample_hist);
   }
   return LBM_OK;
 }

@@ -165,9 +165,13 @@ struct BalanceWs {
   double* means;     // [16]
   double* partials;  // block partials
   size_t partials_cap;  // doubles of window partials before the field-sum partials
-  double* stats;     // device stats scratch
+  double* stats;     // [kMaxSizes][3][6] per-size statistics of this call (all corners)
+  double* sstats;    // same over the sampled windows
+  double* pool;      // [2][kMaxSizes][3][6] pooled statistics (all corners, sampled)
+  double* edges;     // [3][LBM_MAX_EDGES] histogram edges
+  unsigned long long* hist;  // [2][kMaxSizes][3][LBM_MAX_EDGES + 1] counts
   double* wterms;    // [kMaxWindows][LBM_NWVALS]
-  int32_t* windows;  // [LBM_MAX_WINDOWS][3]
+  int32_t* windows;  // [kMaxWindows][3]
 };
 constexpr int kMaxWindows = 4096;
 constexpr int kMaxSizes = 64;
@@ -190,6 +194,7 @@ enum { AUX_E = 0, AUX_OM2 = 1, AUX_W = 2, AUX_SXX = 3, AUX_SYY = 4, AUX_SXY = 5,
        AUX_HY = 7, AUX_N = 8 };
 int run_balance(const lbm_balance_input& in, const BalanceWs& ws, const int32_t* sizes,
                 int nsizes, lbm_balance_stats* out, double* dmaps, const int32_t* windows,
-                int nwin, double* wterms, double* term_fields);
+                int nwin, double* wterms, double* term_fields, const lbm_balance_extra* extra);
+int validate_balance_extra(int nsizes, const lbm_balance_stats* out, const lbm_balance_extra* extra);
 
 }  // namespace lbm

@@ -62,8 +62,61 @@ def _balance_args(nx, ny, sizes, windows):
     return sizes, sz, out, win, nwin, wterms
 
 
+class _Extra:
+    """Marshalling of the optional balance outputs (histograms on given edges,
+    randomly placed windows, pooling over calls) into lbm_balance_extra."""
+
+    def __init__(self, nsizes, edges=None, accumulate=False, sample=None, device="cuda",
+                 all_corners=True):
+        self.x = L.BalanceExtra()
+        self.nsizes = nsizes
+        self.ne = 0
+        self.keep = []
+        self.x.accumulate = int(bool(accumulate))
+        if edges is not None:
+            e = np.ascontiguousarray(edges, dtype=np.float64)
+            if e.ndim == 1:
+                e = np.stack([e, e, e])
+            if e.shape[0] != 3:
+                raise ValueError("edges: one row per quantity (delta^E, delta^Omega, Ma) or one row for all")
+            self.ne = e.shape[1]
+            self.e = np.ascontiguousarray(e)
+            self.x.edges = self.e.ctypes.data_as(C.POINTER(C.c_double))
+            self.x.nedges = self.ne
+            if all_corners:
+                self.h = np.zeros((nsizes, 3, self.ne + 1), dtype=np.int64)
+                self.x.hist = self.h.ctypes.data_as(C.POINTER(C.c_int64))
+        self.sample = sample is not None
+        if self.sample:
+            corners, counts = sample
+            xy = torch.as_tensor(np.ascontiguousarray(corners, dtype=np.int32) if not
+                                 isinstance(corners, torch.Tensor) else corners,
+                                 dtype=torch.int32, device=device).contiguous()
+            if len(counts) != nsizes or xy.dim() != 2 or xy.shape[1] != 2 or \
+                    xy.shape[0] != sum(int(c) for c in counts):
+                raise ValueError("sample: corners [sum(counts), 2] and one count per size")
+            self.keep.append(xy)
+            self.cnt = (C.c_int32 * max(1, nsizes))(*[int(c) for c in counts])
+            self.sout = (L.BalanceStats * max(1, nsizes))()
+            self.x.sample_xy = C.c_void_p(xy.data_ptr())
+            self.x.sample_counts = self.cnt
+            self.x.sample_out = self.sout
+            if edges is not None:
+                self.sh = np.zeros((nsizes, 3, self.ne + 1), dtype=np.int64)
+                self.x.sample_hist = self.sh.ctypes.data_as(C.POINTER(C.c_int64))
+
+    def into(self, res):
+        if self.ne and hasattr(self, "h"):
+            res["hist"] = self.h
+        if self.sample:
+            res["sample_stats"] = [stats_to_dict(self.sout[k]) for k in range(self.nsizes)]
+            if self.ne:
+                res["sample_hist"] = self.sh
+        return res
+
+
 def _balance_result(sizes, out, maps, nwin, wterms, terms, nx, ny):
-    res = {"stats": [stats_to_dict(out[k]) for k in range(len(sizes))]}
+    res = {"stats": [stats_to_dict(out[k]) for k in range(len(sizes))] if out is not None else []}
     if maps is not None:
         res["maps"] = maps
     if nwin:
@@ -172,16 +225,31 @@ class Simulation:
         L.check(self._lib.lbm_moments(self._h, _ptr(rho), _ptr(ux), _ptr(uy), od, None), "lbm_moments")
         return rho, ux, uy
 
-    def balance(self, sizes, windows=None, maps=False, term_fields=False):
-        """Sub-volume balance statistics at the current time (needs with_balance)."""
+    def balance(self, sizes, windows=None, maps=False, term_fields=False, edges=None,
+                accumulate=False, sample=None, all_corners=True):
+        """Sub-volume balance statistics at the current time (needs with_balance).
+
+        edges: bin edges (one row, or one per quantity delta^E, delta^Omega, Ma) for
+        histograms over the windows of each size; sample: (corners [total, 2], counts per
+        size) of randomly placed windows (Table 1), statistics in 'sample_stats';
+        accumulate: pool with the earlier calls since the last one without it;
+        all_corners=False skips the all-corner statistics (sampled windows only)."""
         sizes, sz, out, win, nwin, wterms = _balance_args(self.nx, self.ny, sizes, windows)
+        if not all_corners:
+            out = None
         dm = torch.empty((len(sizes), 3, self.ny, self.nx), dtype=torch.float64,
                          device=self.device) if maps else None
         tf = torch.empty((L.NTERMS, self.ny, self.nx), dtype=torch.float64,
                          device=self.device) if term_fields else None
-        L.check(self._lib.lbm_subvolume_balance(self._h, sz, len(sizes), out, _ptr(dm), win, nwin,
-                                                wterms, _ptr(tf)), "lbm_subvolume_balance")
-        return _balance_result(sizes, out, dm, nwin, wterms, tf, self.nx, self.ny)
+        if edges is None and not accumulate and sample is None:
+            L.check(self._lib.lbm_subvolume_balance(self._h, sz, len(sizes), out, _ptr(dm), win, nwin,
+                                                    wterms, _ptr(tf)), "lbm_subvolume_balance")
+            return _balance_result(sizes, out, dm, nwin, wterms, tf, self.nx, self.ny)
+        ex = _Extra(len(sizes), edges, accumulate, sample, self.device, all_corners)
+        L.check(self._lib.lbm_subvolume_balance_ex(self._h, sz, len(sizes), out, _ptr(dm), win, nwin,
+                                                   wterms, _ptr(tf), C.byref(ex.x)),
+                "lbm_subvolume_balance_ex")
+        return ex.into(_balance_result(sizes, out, dm, nwin, wterms, tf, self.nx, self.ny))
 
     def window_series(self, windows, every, count):
         """Balance of explicit windows (x0, y0, L) sampled every `every` (>= 2) steps,
@@ -251,8 +319,11 @@ class Simulation:
 
 
 def balance_fields(rho, ux, uy, nu, sizes, fx=None, fy=None, windows=None, maps=False,
-                   term_fields=False, device="cuda", stream=None):
-    """Sub-volume balance of given fields: rho/ux/uy are three levels (n-2, n-1, n)."""
+                   term_fields=False, device="cuda", stream=None, edges=None, sample=None,
+                   all_corners=True, workspace=None, accumulate=False):
+    """Sub-volume balance of given fields: rho/ux/uy are three levels (n-2, n-1, n).
+    edges / sample / accumulate / all_corners as Simulation.balance; pooling needs the
+    same `workspace` (a uint8 device tensor of lbm_balance_workspace_bytes) across calls."""
     _require_gpu()
     lib = L.load()
     dev = torch.device(device)
@@ -273,13 +344,23 @@ def balance_fields(rho, ux, uy, nu, sizes, fx=None, fy=None, windows=None, maps=
     inp.stream = _stream_handle(stream).value
     nbytes = C.c_size_t()
     L.check(lib.lbm_balance_workspace_bytes(nx, ny, C.byref(nbytes)), "lbm_balance_workspace_bytes")
-    ws = torch.empty(nbytes.value, dtype=torch.uint8, device=dev)
+    ws = workspace if workspace is not None else torch.empty(nbytes.value, dtype=torch.uint8, device=dev)
+    if ws.numel() < nbytes.value:
+        raise ValueError("balance workspace too small")
     sizes, sz, out, win, nwin, wterms = _balance_args(nx, ny, sizes, windows)
+    if not all_corners:
+        out = None
     dm = torch.empty((len(sizes), 3, ny, nx), dtype=torch.float64, device=dev) if maps else None
     tf = torch.empty((L.NTERMS, ny, nx), dtype=torch.float64, device=dev) if term_fields else None
-    L.check(lib.lbm_balance_fields(C.byref(inp), _ptr(ws), nbytes.value, sz, len(sizes), out, _ptr(dm),
-                                   win, nwin, wterms, _ptr(tf)), "lbm_balance_fields")
-    return _balance_result(sizes, out, dm, nwin, wterms, tf, nx, ny)
+    if edges is None and sample is None and not accumulate:
+        L.check(lib.lbm_balance_fields(C.byref(inp), _ptr(ws), nbytes.value, sz, len(sizes), out,
+                                       _ptr(dm), win, nwin, wterms, _ptr(tf)), "lbm_balance_fields")
+        return _balance_result(sizes, out, dm, nwin, wterms, tf, nx, ny)
+    ex = _Extra(len(sizes), edges, accumulate, sample, dev, all_corners)
+    L.check(lib.lbm_balance_fields_ex(C.byref(inp), _ptr(ws), ws.numel(), sz, len(sizes), out,
+                                      _ptr(dm), win, nwin, wterms, _ptr(tf), C.byref(ex.x)),
+            "lbm_balance_fields_ex")
+    return ex.into(_balance_result(sizes, out, dm, nwin, wterms, tf, nx, ny))
 
 
 def copy_bandwidth(nbytes=1 << 30, iters=20, device="cuda"):

@@ -226,3 +226,98 @@ def test_balance_of_a_forced_run_fp64(gpu_lib):
     tau, alpha = 0.56, 5e-3
     sim = Simulation(rho, ux, uy, tau, dtype="f64", fx=fx, fy=fy, alpha=alpha, with_balance=True)
     _run_balance_check(sim, 60, rho, ux, uy, tau, (6, 24, 48), fx, fy, alpha)
+
+
+# ---------------------------------------------------------------------------
+# Statistics as the paper presents them: PDFs, Table-1 random windows, pooling
+# ---------------------------------------------------------------------------
+def _edges():
+    e = inp.log_edges(1e-6, 10.0, 10)
+    return np.stack([e, e, np.linspace(0.0, 0.1, len(e))])
+
+
+def _check_hist(got, values, edges, label):
+    """Counts equal the oracle's histogram of its own values; a value within 1e-9 of an edge
+    (relative) may sit on either side of it in the other implementation."""
+    want = ref.histogram(values, torch.as_tensor(edges)).numpy()
+    v = ref.t64(values).reshape(-1)
+    v = v[torch.isfinite(v)]
+    e = torch.as_tensor(edges)
+    amb = int(((v[:, None] - e[None, :]).abs() <= 1e-9 * e.abs()[None, :]).any(1).sum())
+    assert int(got.sum()) == int(want.sum()), (label, int(got.sum()), int(want.sum()))
+    assert int(np.abs(got - want).sum()) <= 2 * amb, (label, got, want, amb)
+
+
+def test_balance_histograms_and_random_windows(gpu_lib):
+    """PDFs of delta^E, delta^Omega, Ma_V over all corners and over Table-1 random windows
+    (corners from the seeded sampler, 1 to 10000 per side), against the oracle's maps and
+    its errors at the same corners; side 96 = N is the single whole-domain window."""
+    from paper_1809_06735_amd import balance_fields
+    n = 96
+    sizes = (3, 16, 40, 96)
+    lv = inp.balance_levels(n, seed=5)
+    nu = 0.01 / 3
+    corners, counts = inp.table1_corners(n, sizes, seed=3)
+    assert counts == [10000, 5000, 1000, 1]
+    E = _edges()
+    res = balance_fields(lv["rho"], lv["ux"], lv["uy"], nu, sizes, fx=lv["fx"], fy=lv["fy"],
+                         edges=E, sample=(corners, counts))
+    flds, want, kt, ks = balance_sensitivity(lv, nu, sizes, lv["fx"], lv["fy"])
+    off = 0
+    for k, L in enumerate(sizes):
+        compare_stats(res["stats"][k], want[k], ks[k], label=f"all L={L}")
+        for q, m in enumerate(want[k]["maps"]):
+            _check_hist(res["hist"][k, q], m, E[q], f"all L={L} q={q}")
+        c = corners[off:off + counts[k]]
+        off += counts[k]
+        sv = ref.sampled_errors(flds, L, c)
+        ws = {"L": L}
+        for q, name in enumerate(("dE", "dZ", "Ma")):
+            ws[name] = ref._stats(sv[q])
+            _check_hist(res["sample_hist"][k, q], sv[q], E[q], f"sampled L={L} q={q}")
+        compare_stats(res["sample_stats"][k], ws, ks[k], label=f"sampled L={L}")
+        say(f"L={L}: {counts[k]} random windows, mean dE {ws['dE']['mean']:.3e}")
+
+
+def test_balance_pooled_over_configurations(gpu_lib):
+    """Pooling over configurations: three calls (the first starting the pool) give the
+    statistics and histograms of the union of their windows, all corners and sampled."""
+    from paper_1809_06735_amd import balance_fields, _lib as L
+    n, sizes, nu = 64, (4, 16, 64), 0.004
+    import ctypes as C
+    lib = L.load()
+    sz = C.c_size_t()
+    L.check(lib.lbm_balance_workspace_bytes(n, n, C.byref(sz)))
+    ws = torch.empty(sz.value, dtype=torch.uint8, device="cuda")
+    E = _edges()
+    vals = {k: {q: [] for q in range(3)} for k in range(len(sizes))}
+    svals = {k: {q: [] for q in range(3)} for k in range(len(sizes))}
+    kmax = [{q: {m: 0.0 for m in ("mean", "std", "min", "max")} for q in ("dE", "dZ", "Ma")}
+            for _ in sizes]
+    for i, seed in enumerate((11, 12, 13)):
+        lv = inp.balance_levels(n, seed=seed)
+        corners, counts = inp.table1_corners(n, sizes, seed=seed)
+        res = balance_fields(lv["rho"], lv["ux"], lv["uy"], nu, sizes, fx=lv["fx"], fy=lv["fy"],
+                             edges=E, sample=(corners, counts), workspace=ws, accumulate=i > 0)
+        flds, st, _, ks = balance_sensitivity(lv, nu, sizes, lv["fx"], lv["fy"])
+        for k in range(len(sizes)):
+            for q in ("dE", "dZ", "Ma"):
+                for m in ("mean", "std", "min", "max"):
+                    kmax[k][q][m] = max(kmax[k][q][m], ks[k][q][m])
+        off = 0
+        for k, Lk in enumerate(sizes):
+            for q in range(3):
+                vals[k][q].append(st[k]["maps"][q].reshape(-1))
+            sv = ref.sampled_errors(flds, Lk, corners[off:off + counts[k]])
+            off += counts[k]
+            for q in range(3):
+                svals[k][q].append(sv[q])
+    for k, Lk in enumerate(sizes):
+        for kind, got_st, got_h, src in (("all", res["stats"], res["hist"], vals),
+                                         ("sampled", res["sample_stats"], res["sample_hist"], svals)):
+            w = {"L": Lk}
+            for q, name in enumerate(("dE", "dZ", "Ma")):
+                w[name] = ref.pooled_stats(src[k][q])
+                _check_hist(got_h[k, q], torch.cat([ref.t64(v).reshape(-1) for v in src[k][q]]), E[q],
+                            f"pooled {kind} L={Lk} q={q}")
+            compare_stats(got_st[k], w, kmax[k], label=f"pooled {kind} L={Lk}")
