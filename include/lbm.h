@@ -278,6 +278,25 @@ LBM_API int lbm_subvolume_balance_ex(lbm_ctx ctx, const int32_t* sizes, int32_t 
                              int32_t nwin, double* wterms, double* term_fields,
                              const lbm_balance_extra* extra);
 
+/* Kinetic-energy spectrum of the current velocity (the u of lbm_moments), as
+ * in Sec. 4, Fig. 5 and Sec. 5, Fig. 10:
+ *   E(s) = 1/2 sum_{k in shell s} |u^(k)|^2,  u^(k) = (1/(nx ny)) sum_x u(x) e^{-ik.x},
+ * k the signed integer frequencies (-n/2 .. n/2 - 1 per axis), shell s the
+ * wavevectors with (2s - 1)^2 <= 4|k|^2 < (2s + 1)^2 (|k| rounded half up).
+ *   spectrum : host double[nshells], 1 <= nshells <= LBM_MAX_SHELLS; shells no
+ *              wavevector reaches are 0.
+ * nx and ny must be powers of two in [16, 4096] (else LBM_E_UNSUPPORTED).
+ * Needs the handle created with with_balance = 1: the balance scratch holds the
+ * transforms (the next balance call recomputes its fields).  Synchronous.  The
+ * shell sums are FP64 atomics: their last bits may differ between calls. */
+#define LBM_MAX_SHELLS 4096
+LBM_API int lbm_energy_spectrum(lbm_ctx ctx, double* spectrum, int32_t nshells);
+/* The same for caller fields ux, uy (device FP64 [ny][nx]) on `stream`, with a
+ * device workspace of lbm_spectrum_workspace_bytes.  Synchronous. */
+LBM_API int lbm_spectrum_workspace_bytes(int32_t nx, int32_t ny, size_t* bytes);
+LBM_API int lbm_spectrum_fields(int32_t nx, int32_t ny, const double* ux, const double* uy, void* ws,
+                        size_t ws_bytes, double* spectrum, int32_t nshells, void* stream);
+
 /* Current time step. */
 LBM_API int lbm_time(lbm_ctx ctx, int64_t* t);
 

@@ -79,6 +79,7 @@ class BalanceInput(C.Structure):
 
 
 LBM_MAX_EDGES = 1024
+LBM_MAX_SHELLS = 4096
 
 
 class BalanceExtra(C.Structure):
@@ -115,6 +116,9 @@ SIGNATURES = {
                                    C.POINTER(_I32), _I32, _DP, _P]),
     "lbm_subvolume_balance_ex": (_I, [_P, C.POINTER(_I32), _I32, C.POINTER(BalanceStats), _P,
                                       C.POINTER(_I32), _I32, _DP, _P, C.POINTER(BalanceExtra)]),
+    "lbm_energy_spectrum": (_I, [_P, _DP, _I32]),
+    "lbm_spectrum_workspace_bytes": (_I, [_I32, _I32, C.POINTER(_SZ)]),
+    "lbm_spectrum_fields": (_I, [_I32, _I32, _P, _P, _P, _SZ, _DP, _I32, _P]),
     "lbm_time": (_I, [_P, C.POINTER(_I64)]),
     "lbm_state_bytes": (_I, [_P, C.POINTER(_SZ)]),
     "lbm_save": (_I, [_P, _P]),

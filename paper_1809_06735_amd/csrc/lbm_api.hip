@@ -612,6 +612,39 @@ int lbm_balance_fields_ex(const lbm_balance_input* in, void* ws, size_t ws_bytes
   return run_balance(*in, b, sizes, nsizes, out, dmaps, windows, nwin, wterms, term_fields, extra);
 }
 
+int lbm_energy_spectrum(lbm_ctx c, double* spectrum, int32_t nshells) {
+  if (!c) return fail(LBM_E_INVALID, "ctx is NULL");
+  if (!c->cfg.with_balance) return fail(LBM_E_STATE, "handle was created with with_balance = 0");
+  if (!spectrum_size_ok(c->cfg.nx, c->cfg.ny))
+    return fail(LBM_E_UNSUPPORTED, "spectrum needs power-of-two extents in [16, 4096]");
+  if (!spectrum) return fail(LBM_E_INVALID, "spectrum is NULL");
+  if (nshells < 1 || nshells > LBM_MAX_SHELLS)
+    return fail(LBM_E_INVALID, "nshells must be in [1, %d]", LBM_MAX_SHELLS);
+  if (int rc = moments_into(c, nullptr, nullptr, nullptr, LBM_F64, c->mom[0], c->mom[1], c->mom[2],
+                            nullptr, nullptr, nullptr))
+    return rc;
+  // the balance's term, aux and table fields are free between balance calls
+  char* base = reinterpret_cast<char*>(c->bal.terms);
+  const size_t room = static_cast<size_t>(reinterpret_cast<char*>(c->bal.means) - base);
+  return run_spectrum(c->cfg.nx, c->cfg.ny, c->mom[1], c->mom[2], base, room, spectrum, nshells,
+                      c->stream);
+}
+
+int lbm_spectrum_workspace_bytes(int32_t nx, int32_t ny, size_t* bytes) {
+  if (!bytes) return fail(LBM_E_INVALID, "bytes is NULL");
+  if (!spectrum_size_ok(nx, ny))
+    return fail(LBM_E_UNSUPPORTED, "spectrum needs power-of-two extents in [16, 4096] (got %d x %d)", nx, ny);
+  *bytes = spectrum_ws_bytes(nx, ny);
+  return LBM_OK;
+}
+
+int lbm_spectrum_fields(int32_t nx, int32_t ny, const double* ux, const double* uy, void* ws, size_t ws_bytes,
+                        double* spectrum, int32_t nshells, void* stream) {
+  if (!ws || reinterpret_cast<uintptr_t>(ws) % 256 != 0)
+    return fail(LBM_E_INVALID, "workspace must be non-NULL and 256-byte aligned");
+  return run_spectrum(nx, ny, ux, uy, ws, ws_bytes, spectrum, nshells, static_cast<hipStream_t>(stream));
+}
+
 int lbm_time(lbm_ctx c, int64_t* t) {
   if (!c || !t) return fail(LBM_E_INVALID, "NULL argument");
   *t = c->t;

@@ -124,6 +124,13 @@ int launch_to_storage(int dtype, void* dst, const double* src, size_t n, hipStre
 
 int launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 
+// ---- energy spectrum -------------------------------------------------------------
+bool spectrum_size_ok(int nx, int ny);
+size_t spectrum_ws_bytes(int nx, int ny);
+// Synchronous; ux, uy device FP64 [ny][nx]; spectrum host [nshells].
+int run_spectrum(int nx, int ny, const double* ux, const double* uy, void* ws, size_t ws_bytes,
+                 double* spectrum, int nshells, hipStream_t s);
+
 // ---- exact-difference forcing and spectral damping (Sec. 3, Eqs. 14-16) -------
 // Damped modes: the integer wavevectors with kmin <= |k| <= kmax in the half
 // plane ky > 0 or (ky == 0, kx > 0); each stands for itself and -k.

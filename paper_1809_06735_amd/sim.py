@@ -268,6 +268,14 @@ class Simulation:
             errs.append(r["window_errors"])
         return {"time": np.array(times), "terms": np.stack(terms), "errors": np.stack(errs)}
 
+    def energy_spectrum(self, nshells=None):
+        """Shell-summed kinetic-energy spectrum E(s) of the current velocity (Figs. 5 and 10),
+        s = 0 .. nshells - 1 (default: up to the shell of (nx/2, ny/2)); needs with_balance."""
+        ns = int(nshells) if nshells is not None else _default_shells(self.nx, self.ny)
+        out = (C.c_double * ns)()
+        L.check(self._lib.lbm_energy_spectrum(self._h, out, ns), "lbm_energy_spectrum")
+        return np.frombuffer(out, dtype=np.float64).copy()
+
     # -- checkpoints ------------------------------------------------------------------------------
     def state_bytes(self) -> int:
         n = C.c_size_t()
@@ -361,6 +369,27 @@ def balance_fields(rho, ux, uy, nu, sizes, fx=None, fy=None, windows=None, maps=
                                       _ptr(dm), win, nwin, wterms, _ptr(tf), C.byref(ex.x)),
             "lbm_balance_fields_ex")
     return ex.into(_balance_result(sizes, out, dm, nwin, wterms, tf, nx, ny))
+
+
+def _default_shells(nx, ny):
+    return int(np.floor(np.hypot(nx // 2, ny // 2) + 0.5)) + 1
+
+
+def energy_spectrum(ux, uy, nshells=None, device="cuda", stream=None):
+    """Shell-summed kinetic-energy spectrum of given [ny, nx] velocity fields (powers of two)."""
+    _require_gpu()
+    lib = L.load()
+    dev = torch.device(device)
+    vx, vy = _dev64(ux, dev), _dev64(uy, dev)
+    ny, nx = vx.shape
+    ns = int(nshells) if nshells is not None else _default_shells(nx, ny)
+    nbytes = C.c_size_t()
+    L.check(lib.lbm_spectrum_workspace_bytes(nx, ny, C.byref(nbytes)), "lbm_spectrum_workspace_bytes")
+    ws = torch.empty(nbytes.value, dtype=torch.uint8, device=dev)
+    out = (C.c_double * ns)()
+    L.check(lib.lbm_spectrum_fields(nx, ny, _ptr(vx), _ptr(vy), _ptr(ws), nbytes.value, out, ns,
+                                    _stream_handle(stream)), "lbm_spectrum_fields")
+    return np.frombuffer(out, dtype=np.float64).copy()
 
 
 def copy_bandwidth(nbytes=1 << 30, iters=20, device="cuda"):

@@ -321,3 +321,51 @@ def test_balance_pooled_over_configurations(gpu_lib):
                 _check_hist(got_h[k, q], torch.cat([ref.t64(v).reshape(-1) for v in src[k][q]]), E[q],
                             f"pooled {kind} L={Lk} q={q}")
             compare_stats(got_st[k], w, kmax[k], label=f"pooled {kind} L={Lk}")
+
+
+# ---------------------------------------------------------------------------
+# Energy spectrum (Figs. 5 and 10)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("ny,nx", [(64, 64), (32, 128), (256, 256)])
+def test_energy_spectrum_fields(gpu_lib, ny, nx):
+    """Shell-summed spectrum of random-phase fields against the oracle's FFT spectrum:
+    every shell within 1e-12 of the largest shell; the sum is half the mean |u|^2."""
+    from paper_1809_06735_amd import energy_spectrum
+    g = np.random.default_rng(nx + ny)
+    ux = g.standard_normal((ny, nx)) * 0.01
+    uy = g.standard_normal((ny, nx)) * 0.01
+    ns = int(np.floor(np.hypot(nx // 2, ny // 2) + 0.5)) + 3
+    got = energy_spectrum(ux, uy, ns)
+    want = ref.energy_spectrum(ux, uy, ns).numpy()
+    err = np.abs(got - want).max() / want.max()
+    say(f"spectrum {ny}x{nx}: rel err {err:.1e}")
+    assert err < 1e-12
+    assert got[-2:].tolist() == [0.0, 0.0]
+    assert got.sum() == pytest.approx(0.5 * float((ux ** 2 + uy ** 2).mean()), rel=1e-12)
+
+
+def test_energy_spectrum_of_a_run(gpu_lib):
+    """The spectrum of a handle's velocity (the paper's forced set-up, 256^2 FP64, 200 steps)
+    equals the oracle's spectrum of the oracle's velocity; a single-mode field puts all of
+    its energy in its shell."""
+    from paper_1809_06735_amd import Simulation, energy_spectrum
+    n = 64
+    y, x = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    ux = 0.02 * np.cos(2 * np.pi * (3 * x + 4 * y) / n)
+    e = energy_spectrum(ux, np.zeros_like(ux), 40)
+    assert e[5] == pytest.approx(0.02 ** 2 / 4, rel=1e-13)
+    assert abs(e.sum() - e[5]) < 1e-25
+    n, steps, tau = 256, 200, 0.6
+    fx, fy = inp.paper_forcing(n)
+    _, vx0, vy0 = inp.spectrum_velocity(n, seed=4, max_mach=0.05)
+    rho = np.ones((n, n))
+    sim = Simulation(rho, vx0, vy0, tau, dtype="f64", fx=fx, fy=fy, scheme="edm", damp_f0=1e-5,
+                     with_balance=True)
+    sim.step(steps)
+    got = sim.energy_spectrum(120)
+    f = ref.edm_run(ref.init_populations(rho, vx0, vy0), steps, tau, ref.t64(fx), ref.t64(fy), 1e-5)
+    _, u, v, _, _ = ref.edm_moments(f, ref.t64(fx), ref.t64(fy), 1e-5)
+    want = ref.energy_spectrum(u, v, 120).numpy()
+    err = np.abs(got - want).max() / want.max()
+    say(f"run spectrum rel err {err:.1e}")
+    assert err < 1e-11
