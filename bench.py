@@ -156,6 +156,54 @@ def paper_set_up_256(log, steps=20000, every=100):
             "forcing_F0T_lattice": inp.PAPER_FORCING_F0_LATTICE, "runs": runs}
 
 
+def paper_statistics_256(log, tau=0.52, nconf=25, every=100, spin_up=4000):
+    """The statistics of Sec. 5 as the paper presents them, on the paper's set-up at
+    tau0 = 0.52: 25 configurations every `every` steps after a spin-up, each restarted from
+    its checkpoint; all-corner statistics and PDFs at ~40 box sides (l = L/256 from 1/256
+    to 1), the Table-1 random windows with their own PDFs, pooled over the configurations,
+    and the energy spectrum of every configuration."""
+    import numpy as np
+    import torch
+    import lbm_inputs as inp
+    from paper_1809_06735_amd import Simulation, configuration_statistics, sample_configurations
+    n = 256
+    fx, fy = inp.paper_forcing(n)
+    z = np.zeros((n, n))
+    sim = Simulation(np.ones((n, n)), z, z, tau, dtype="f32", fx=fx, fy=fy, scheme="edm",
+                     damp_f0=inp.PAPER_DAMPING_F0, with_balance=True)
+    sim.step(spin_up)
+    cfgs = sample_configurations(sim, nconf, every)
+    sizes = tuple(sorted({int(v) for v in np.round(np.logspace(0, np.log10(n), 40))} | {181}))
+    e = inp.log_edges(1e-7, 10.0, 10)
+    edges = np.stack([e, e, np.linspace(0.0, 0.5, len(e))])
+    samples = [inp.table1_corners(n, sizes, seed=i) for i in range(nconf)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = configuration_statistics(sim, cfgs, sizes, edges=edges, sample=lambda i: samples[i],
+                                   spectrum_shells=182)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    nwin_all = nconf * n * n * (len(sizes) - 1) + nconf
+    nwin_smp = nconf * sum(samples[0][1])
+    sim.close()
+    pick = {3: "l~0.01", 181: "l~0.707", 256: "l=1"}
+    out = {"tau0": tau, "configurations": nconf, "box_sides": len(sizes),
+           "seconds_for_all_configurations": round(dt, 3),
+           "ms_per_configuration": round(dt * 1e3 / nconf, 2),
+           "all_corner_windows": nwin_all, "table1_windows": nwin_smp,
+           "windows_per_s": round((nwin_all + nwin_smp) / dt, 0)}
+    for L, tag in pick.items():
+        k = sizes.index(L)
+        out[tag] = {"all_mean_dE": res["stats"][k]["dE"]["mean"], "all_mean_dZ": res["stats"][k]["dZ"]["mean"],
+                    "table1_mean_dE": res["sample_stats"][k]["dE"]["mean"],
+                    "table1_count": res["sample_stats"][k]["dE"]["count"],
+                    "mean_Ma": res["stats"][k]["Ma"]["mean"]}
+    spec = res["spectra"].mean(0)
+    out["spectrum_k1_k6_k32"] = [float(spec[1]), float(spec[6]), float(spec[32])]
+    log(f"[bench] paper statistics: {nconf} configurations x {len(sizes)} sides in {dt:.2f} s")
+    return out
+
+
 def cpu_baseline(n, tau, alpha, fx, fy, steps):
     import torch
     from oracle import ref
@@ -329,6 +377,10 @@ def main():
             extras["paper_set_up_256"] = paper_set_up_256(log)
         except Exception as e:  # noqa: BLE001
             extras["paper_set_up_256"] = f"error: {e}"
+        try:
+            extras["paper_statistics_256"] = paper_statistics_256(log)
+        except Exception as e:  # noqa: BLE001
+            extras["paper_statistics_256"] = f"error: {e}"
         try:
             from paper_1809_06735_amd import ensemble as ens_mod
             extras["ensemble"] = ens_mod.bench_ensemble(log=log)

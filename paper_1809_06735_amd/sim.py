@@ -371,6 +371,42 @@ def balance_fields(rho, ux, uy, nu, sizes, fx=None, fy=None, windows=None, maps=
     return ex.into(_balance_result(sizes, out, dm, nwin, wterms, tf, nx, ny))
 
 
+def sample_configurations(sim, count, every):
+    """Advance `sim` and keep `count` configurations `every` (>= 2) steps apart, the way a
+    statistically stationary run is sampled into configurations (Sec. 4-5, Figs. 4 and 9):
+    a list of (time, device checkpoint); Simulation.load restarts from any of them with
+    the moment history the balance needs."""
+    if int(every) < 2:
+        raise ValueError("every must be >= 2 (the balance needs the two preceding steps)")
+    out = []
+    for _ in range(int(count)):
+        sim.step(int(every))
+        out.append((sim.time, sim.save()))
+    return out
+
+
+def configuration_statistics(sim, configs, sizes, edges=None, sample=None, spectrum_shells=None):
+    """Balance statistics pooled over configurations (Sec. 4-5: 25 configurations per
+    ensemble): `sim` is restarted from each checkpoint of `configs` (as returned by
+    sample_configurations) and its balance evaluated with pooling; sample is None,
+    (corners, counts) for every configuration, or a callable i -> (corners, counts).
+    Returns the pooled balance result (as Simulation.balance) plus 'times' and, with
+    spectrum_shells, 'spectra' [nconf, spectrum_shells]."""
+    res, spectra, times = None, [], []
+    for i, (t, state) in enumerate(configs):
+        sim.load(state)
+        smp = sample(i) if callable(sample) else sample
+        res = sim.balance(sizes, edges=edges, accumulate=i > 0, sample=smp)
+        times.append(int(t))
+        if spectrum_shells:
+            spectra.append(sim.energy_spectrum(spectrum_shells))
+    res = dict(res or {})
+    res["times"] = times
+    if spectrum_shells:
+        res["spectra"] = np.stack(spectra)
+    return res
+
+
 def _default_shells(nx, ny):
     return int(np.floor(np.hypot(nx // 2, ny // 2) + 0.5)) + 1
 

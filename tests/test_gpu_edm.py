@@ -225,3 +225,56 @@ def test_edm_window_time_series(gpu_lib):
         for q, o in enumerate(ref.balancing_errors(wm)):
             g = torch.as_tensor(ser["errors"][i, :, q])
             assert torch.allclose(g, o, rtol=1e-7, atol=1e-12), (t, q, g, o)
+
+
+def test_configuration_sampling_and_pooled_statistics(gpu_lib):
+    """The 25-configuration workflow of Sec. 4-5 in small: a damped exact-difference run is
+    sampled into configurations, each restarted from its checkpoint; the pooled all-corner
+    and Table-1 statistics, the pooled histograms and the per-configuration spectra equal the
+    oracle's run sampled at the same times."""
+    from paper_1809_06735_amd import configuration_statistics, sample_configurations
+    n, tau, amp = 32, 0.6, 0.3
+    rho, ux, uy = _fields(n, n, 31)
+    fx, fy = inp.paper_forcing(n, f0=1e-4)
+    sim = Sim(rho, ux, uy, tau, dtype="f64", fx=fx, fy=fy, scheme="edm", damp_f0=amp,
+              with_balance=True)
+    sim.step(10)
+    cfgs = sample_configurations(sim, 3, every=7)
+    assert [t for t, _ in cfgs] == [17, 24, 31]
+    sim.step(50)  # moved on: the statistics restart from the checkpoints
+    sizes = (3, 8, 32)
+    edges = inp.log_edges(1e-6, 10.0, 5)
+    smp = lambda i: inp.table1_corners(n, sizes, seed=100 + i)
+    res = configuration_statistics(sim, cfgs, sizes, edges=edges, sample=smp, spectrum_shells=24)
+    assert res["times"] == [17, 24, 31] and res["spectra"].shape == (3, 24)
+    nu = ref.viscosity(tau)
+    pools = {k: [[], [], []] for k in range(len(sizes))}
+    spools = {k: [[], [], []] for k in range(len(sizes))}
+    for i, (t, _) in enumerate(cfgs):
+        f, hist = ref.edm_run_with_history(ref.init_populations(rho, ux, uy), t, tau, ref.t64(fx),
+                                           ref.t64(fy), amp)
+        flds = ref.balance_fields([h[0] for h in hist], [h[1] for h in hist], [h[2] for h in hist],
+                                  hist[2][3], hist[2][4], nu)
+        st = ref.subvolume_balance(flds, sizes)
+        corners, counts = smp(i)
+        off = 0
+        for k, L in enumerate(sizes):
+            sv = ref.sampled_errors(flds, L, corners[off:off + counts[k]])
+            off += counts[k]
+            for q in range(3):
+                pools[k][q].append(st[k]["maps"][q].reshape(-1))
+                spools[k][q].append(sv[q])
+        want_spec = ref.energy_spectrum(hist[2][1], hist[2][2], 24).numpy()
+        assert np.abs(res["spectra"][i] - want_spec).max() <= 1e-10 * want_spec.max()
+    for k, L in enumerate(sizes):
+        for kind, got, gh, src in (("all", res["stats"][k], res["hist"][k], pools),
+                                   ("sampled", res["sample_stats"][k], res["sample_hist"][k], spools)):
+            for q, name in enumerate(("dE", "dZ", "Ma")):
+                vals = torch.cat([ref.t64(v).reshape(-1) for v in src[k][q]])
+                w = ref.pooled_stats(src[k][q])
+                g = got[name]
+                assert g["count"] == w["count"], (kind, L, name)
+                for m in ("mean", "std", "min", "max"):
+                    assert g[m] == pytest.approx(w[m], rel=1e-7), (kind, L, name, m)
+                hw = ref.histogram(vals, torch.as_tensor(edges)).numpy()
+                assert int(np.abs(gh[q] - hw).sum()) <= 2, (kind, L, name, gh[q], hw)
