@@ -31,6 +31,10 @@ Parts and where they come from
   balancing errors (Sec. 2, Eqs. 12-13), sub-volume Mach number (Sec. 4,
   Eq. 20), sub-volume means over L x L boxes (Sec. 3, Fig. 3 and Table 1)
   with periodic wrap, statistics mu_l, sigma_l (Sec. 3).
+* Entropic LBM (Sec. 1, Eq. 6 and tau_eff = 2 tau0 / alpha): the closed-form
+  minimiser of H at fixed rho, rho u on D2Q9, alpha as the root of the entropy
+  equality H(f + alpha (f^eq - f)) = H(f) by bisection, nu_eff = c_s^2 (tau_eff - 1/2);
+  the balance takes the viscosity as a field.
 * Statistics as presented (Sec. 3, Table 1; Figs. 5-13): histograms of
   delta^E, delta^Omega, Ma_V on given bin edges, the errors of windows at given
   random corners, pooling over configurations, and the shell-summed energy
@@ -237,7 +241,8 @@ def balance_fields(rho, ux, uy, fx, fy, nu, p=None):
     """Pointwise integrands of the sub-volume balances at time level n.
 
     rho, ux, uy: sequences of three fields at levels (n-2, n-1, n).
-    fx, fy: total body force at level n.  nu: kinematic viscosity.
+    fx, fy: total body force at level n.  nu: kinematic viscosity, a number or a
+    field at level n (the effective viscosity of the entropic scheme).
     p: pressure at level n; default the LBGK equation of state p = c_s^2 rho.
 
     Returns a dict with the 13 fields of TERM_NAMES:
@@ -525,6 +530,107 @@ def edm_run_with_history(f, nsteps, tau, fx_ext=None, fy_ext=None, amp=0.0, kmin
         if t < nsteps:
             f = edm_step(f, tau, fx_ext, fy_ext, amp, kmin, kmax)
     return f, hist
+
+
+# ---------------------------------------------------------------------------
+# Entropic LBM (Sec. 1: the H-functional of Eq. 6 and the effective relaxation
+# time tau_eff = 2 tau0 / alpha towards the minimiser of H)
+# ---------------------------------------------------------------------------
+def h_function(f):
+    """Eq. 6 per site: H(f) = sum_l f_l log(f_l / t_l)."""
+    w = torch.tensor(W, dtype=DT).reshape(9, 1, 1)
+    return (f * torch.log(f / w)).sum(0)
+
+
+def entropic_equilibrium(rho, ux, uy):
+    """The minimiser of H at fixed rho and rho u on D2Q9, in closed form:
+    f_l = t_l rho prod_a (2 - s_a) ((2 u_a + s_a) / (1 - u_a))^{c_la},
+    s_a = sqrt(1 + 3 u_a^2), a = x, y."""
+    rho, ux, uy = t64(rho), t64(ux), t64(uy)
+    sx = torch.sqrt(1.0 + 3.0 * ux * ux)
+    sy = torch.sqrt(1.0 + 3.0 * uy * uy)
+    zx = (2.0 * ux + sx) / (1.0 - ux)
+    zy = (2.0 * uy + sy) / (1.0 - uy)
+    base = rho * (2.0 - sx) * (2.0 - sy)
+    return torch.stack([W[l] * base * zx ** C[l][0] * zy ** C[l][1] for l in range(9)])
+
+
+def entropic_gain(f, delta, a):
+    """H(f + a delta) - H(f) per site for delta = f^eq - f, f^eq the minimiser of H with
+    the moments of f.  With t = a delta / f and phi(t) = (1 + t) log1p(t) - t,
+    H(f + a delta) - H(f) = sum_l f_l phi(t_l) + a sum_l delta_l (1 + log(f_l / t_l));
+    delta conserves mass and momentum and log(f^eq_l / t_l) is affine in c_l, so the
+    second sum equals a sum_l delta_l log(f_l / f^eq_l) = -a sum_l delta_l log1p(delta_l / f_l):
+    the same quantity with every first-order term cancelled analytically."""
+    t = a * delta / f
+    phi = (1.0 + t) * torch.log1p(t) - t
+    return (f * phi).sum(0) - a * (delta * torch.log1p(delta / f)).sum(0)
+
+
+#: below this max_l |feq_l - f_l| / f_l the populations count as equilibrium (alpha = 2)
+ENTROPIC_NEAR_EQ = 1e-8
+
+
+def entropic_alpha(f, feq, iters=200):
+    """alpha of the entropic step per site: the root alpha > 1 of
+    H(f + alpha (feq - f)) = H(f), by bisection on [1, alpha_max) with
+    alpha_max the largest step keeping every population positive; alpha = 2 at
+    equilibrium (max |feq - f| / f below ENTROPIC_NEAR_EQ), alpha = the top of the
+    bracket when H is still below H(f) there (no root)."""
+    delta = feq - f
+    near = (delta.abs() / f).amax(0) < ENTROPIC_NEAR_EQ
+    ratio = torch.where(delta < 0, -f / torch.where(delta < 0, delta, -torch.ones_like(delta)),
+                        torch.full_like(f, float("inf")))
+    amax = ratio.amin(0)
+    hi = torch.where(torch.isfinite(amax), amax * (1.0 - 1e-12), torch.full_like(amax, 1e6))
+    lo = torch.ones_like(hi)
+    ghi = entropic_gain(f, delta, hi)
+    for _ in range(iters):
+        mid = 0.5 * (lo + hi)
+        below = entropic_gain(f, delta, mid) < 0
+        lo = torch.where(below, mid, lo)
+        hi = torch.where(below, hi, mid)
+    alpha = 0.5 * (lo + hi)
+    alpha = torch.where(ghi < 0, hi, alpha)
+    return torch.where(near, torch.full_like(alpha, 2.0), alpha)
+
+
+def entropic_collide(f, tau0):
+    """f* = f + alpha beta (f^eq - f), beta = 1 / (2 tau0): the relaxation time is
+    tau_eff = 2 tau0 / alpha (tau0 for alpha = 2, the LBGK step); returns (f*, alpha)."""
+    rho = density(f)
+    jx, jy = momentum(f)
+    feq = entropic_equilibrium(rho, jx / rho, jy / rho)
+    alpha = entropic_alpha(f, feq)
+    return f + alpha * (0.5 / tau0) * (feq - f), alpha
+
+
+def entropic_step(f, tau0):
+    return stream(entropic_collide(f, tau0)[0])
+
+
+def entropic_run(f, nsteps, tau0):
+    for _ in range(nsteps):
+        f = entropic_step(f, tau0)
+    return f
+
+
+def effective_viscosity(alpha, tau0):
+    """nu_eff = c_s^2 (tau_eff - 1/2), tau_eff = 2 tau0 / alpha (Eq. 5 with tau_eff)."""
+    return CS2 * (2.0 * tau0 / t64(alpha) - 0.5)
+
+
+def entropic_run_with_history(f, nsteps, tau0):
+    """Populations after nsteps, the moments (rho, u) at nsteps-2, nsteps-1, nsteps and
+    the effective viscosity field at nsteps (from the alpha of the populations then)."""
+    hist = []
+    for t in range(nsteps + 1):
+        if t >= nsteps - 2:
+            hist.append(moments(f))
+        if t < nsteps:
+            f = entropic_step(f, tau0)
+    _, alpha = entropic_collide(f, tau0)
+    return f, hist, effective_viscosity(alpha, tau0)
 
 
 # ---------------------------------------------------------------------------

@@ -833,3 +833,108 @@ def test_energy_spectrum_single_modes_parseval_and_direct_sum():
     got = ref.energy_spectrum(vx, vy, 12)
     for s in range(12):
         assert float(got[s]) == pytest.approx(want[s], rel=1e-12, abs=1e-17), s
+
+
+# ---------------------------------------------------------------------------
+# Entropic LBM: minimiser of H, alpha from the entropy equality, variable viscosity
+# ---------------------------------------------------------------------------
+def test_entropic_equilibrium_is_the_constrained_minimiser():
+    """Moments rho, rho u exactly; log(f_l / t_l) affine in c_l (the conditions for a minimum
+    of Eq. 6 under mass and momentum constraints); the textbook polynomial equilibrium to
+    second order in u (difference O(u^3))."""
+    g = torch.Generator().manual_seed(12)
+    rho = 1 + 0.05 * torch.randn(6, 7, generator=g, dtype=D)
+    ux = 0.1 * torch.randn(6, 7, generator=g, dtype=D)
+    uy = 0.1 * torch.randn(6, 7, generator=g, dtype=D)
+    f = ref.entropic_equilibrium(rho, ux, uy)
+    assert float((f.sum(0) - rho).abs().max()) < 1e-15
+    jx, jy = ref.momentum(f)
+    assert float((jx - rho * ux).abs().max()) < 1e-15 and float((jy - rho * uy).abs().max()) < 1e-15
+    lg = [torch.log(f[l] / ref.W[l]) for l in range(9)]
+    bx, by = lg[1] - lg[0], lg[2] - lg[0]
+    for l, (cx, cy) in enumerate(ref.C):
+        assert float((lg[l] - lg[0] - cx * bx - cy * by).abs().max()) < 1e-14, l
+    for s in (1e-2, 2e-2, 4e-2):
+        d = float((ref.entropic_equilibrium(rho, s * ux / 0.1, s * uy / 0.1)
+                   - ref.equilibrium(rho, s * ux / 0.1, s * uy / 0.1)).abs().max())
+        if s == 1e-2:
+            d1 = d
+    assert d / d1 == pytest.approx(64, rel=0.05)  # cubic: 4x the velocity, 64x the difference
+
+
+def test_entropic_gain_equals_the_literal_h_difference():
+    """The rearranged H(f + a delta) - H(f) equals the difference of Eq. 6 summed exactly
+    (math.fsum of the 18 per-population terms) at every site."""
+    rho, ux, uy = inp.spectrum_velocity(16, seed=2, max_mach=0.15)
+    f = ref.run(ref.init_populations(rho, ux, uy), 15, 0.52)
+    feq = ref.entropic_equilibrium(ref.density(f), *[j / ref.density(f) for j in ref.momentum(f)])
+    delta = feq - f
+    for a in (0.7, 1.9, 2.3):
+        got = ref.entropic_gain(f, delta, a)
+        for (y, x) in [(0, 0), (3, 11), (15, 7), (8, 8)]:
+            terms = []
+            for l in range(9):
+                fl, dl = float(f[l, y, x]), float(delta[l, y, x])
+                terms.append((fl + a * dl) * math.log((fl + a * dl) / ref.W[l]))
+                terms.append(-fl * math.log(fl / ref.W[l]))
+            want = math.fsum(terms)
+            assert float(got[y, x]) == pytest.approx(want, rel=1e-6, abs=1e-17), (a, y, x)
+
+
+def test_entropic_alpha_entropy_equality_and_limits():
+    """alpha solves the entropy equality, exceeds 1, is 2 at equilibrium and tends to 2 as
+    the populations approach it (|alpha - 2| = O(epsilon))."""
+    rho, ux, uy = inp.spectrum_velocity(16, seed=3, max_mach=0.15)
+    f = ref.run(ref.init_populations(rho, ux, uy), 15, 0.51)
+    r = ref.density(f)
+    jx, jy = ref.momentum(f)
+    feq = ref.entropic_equilibrium(r, jx / r, jy / r)
+    a = ref.entropic_alpha(f, feq)
+    assert float(a.min()) > 1.0
+    scale = float((((feq - f) ** 2) / f).sum(0).max())
+    assert float(ref.entropic_gain(f, feq - f, a).abs().max()) < 1e-12 * scale
+    assert torch.equal(ref.entropic_alpha(feq, feq), torch.full_like(a, 2.0))
+    devs = []
+    for eps in (1e-2, 1e-3, 1e-4):
+        fe = feq + eps * (f - feq)
+        devs.append(float((ref.entropic_alpha(fe, feq) - 2).abs().max()))
+    assert devs[1] < 0.2 * devs[0] and devs[2] < 0.2 * devs[1]
+
+
+def test_entropic_collision_conserves_and_reduces_to_lbgk():
+    rho, ux, uy = inp.spectrum_velocity(16, seed=4, max_mach=0.15)
+    f = ref.run(ref.init_populations(rho, ux, uy), 10, 0.53)
+    fp, a = ref.entropic_collide(f, 0.53)
+    assert float((fp.sum(0) - f.sum(0)).abs().max()) < 1e-15
+    for jp, j in zip(ref.momentum(fp), ref.momentum(f)):
+        assert float((jp - j).abs().max()) < 1e-15
+    r = ref.density(f)
+    jx, jy = ref.momentum(f)
+    feq = ref.entropic_equilibrium(r, jx / r, jy / r)
+    # the step along feq - f is alpha / (2 tau0) of it; alpha = 2 is the LBGK step
+    assert float((fp - (f + a * (feq - f) / (2 * 0.53))).abs().max()) < 1e-16
+    assert ref.effective_viscosity(torch.tensor(2.0, dtype=D), 0.53) == pytest.approx(0.01, rel=1e-13)
+    assert float(ref.effective_viscosity(a, 0.53).max()) > 0
+
+
+def test_balance_with_a_viscosity_field():
+    """A constant field equals the scalar; with a varying field, e4 + e5 = u . div(sigma)
+    and z4 + z5 = omega curl(div(sigma) / rho) by spectral derivatives (sigma = rho nu(x) (du + du^T))."""
+    rho, ux, uy = _smooth_compressible_fields(64, seed=6)
+    lv = {"rho": [rho] * 3, "ux": [ux] * 3, "uy": [uy] * 3}
+    a = ref.balance_fields(lv["rho"], lv["ux"], lv["uy"], None, None, 0.004)
+    b = ref.balance_fields(lv["rho"], lv["ux"], lv["uy"], None, None, torch.full((64, 64), 0.004, dtype=D))
+    for k in ref.TERM_NAMES:
+        assert torch.equal(a[k], b[k]), k
+    y, x = np.meshgrid(np.arange(64.0), np.arange(64.0), indexing="ij")
+    nu = 0.004 * (1 + 0.3 * np.sin(2 * np.pi * (x + 2 * y) / 64))
+    t = ref.balance_fields(lv["rho"], lv["ux"], lv["uy"], None, None, ref.t64(nu))
+    r, u, v = [np.asarray(q, dtype=float) for q in (rho, ux, uy)]
+    sxx = 2 * nu * r * _spec_d(u, 1)
+    syy = 2 * nu * r * _spec_d(v, 0)
+    sxy = nu * r * (_spec_d(v, 1) + _spec_d(u, 0))
+    divx = _spec_d(sxx, 1) + _spec_d(sxy, 0)
+    divy = _spec_d(sxy, 1) + _spec_d(syy, 0)
+    want = u * divx + v * divy
+    got = (t["e4"] + t["e5"]).numpy()
+    assert np.abs(got - want).max() < 1e-5 * np.abs(want).max()
