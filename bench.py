@@ -204,6 +204,41 @@ def paper_statistics_256(log, tau=0.52, nconf=25, every=100, spin_up=4000):
     return out
 
 
+def entropic_1024(log, n=1024, tau0=0.5005, steps=400):
+    """The entropic collision (Sec. 1) on a decaying 1024^2 FP32 field at tau0 = 0.5005,
+    autotuned single-step shape, against the BGK step on the same field: the cost of the
+    per-site alpha solve (FP64 Newton iterations on the entropy equality)."""
+    import torch
+    import lbm_inputs as inp
+    from paper_1809_06735_amd import Simulation
+    rho, ux, uy = inp.spectrum_velocity(n, seed=0, max_mach=0.1)
+    out = {"grid": n, "tau0": tau0, "dtype": "f32"}
+    for coll in ("entropic", "bgk"):
+        sim = Simulation(rho, ux, uy, tau0, dtype="f32", collision=coll)
+        tile = sim.autotune(trial_steps=4) if coll == "entropic" else None
+        sim.step(20)
+        torch.cuda.synchronize()
+        sim.step_timing(True)
+        t0 = time.perf_counter()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        kms, nl = sim.step_time(reset=True)
+        rec = {"MLUPS": round(n * n * steps / dt / 1e6, 1)}
+        if nl:
+            rec["kernel_MLUPS"] = round(n * n * nl * max(sim.get_tile()[5], 1) / (kms * 1e-3) / 1e6, 1)
+        if coll == "entropic":
+            a, _ = sim.relaxation()
+            rec["shape"] = list(tile)
+            rec["alpha_min"], rec["alpha_max"] = float(a.min()), float(a.max())
+            _, _, _, sc = sim.moments()
+            rec["finite"] = sc["nonfinite"] == 0
+        out[coll] = rec
+        sim.close()
+    log(f"[bench] entropic {out['entropic']['MLUPS']} MLUPS vs BGK {out['bgk']['MLUPS']} at {n}^2")
+    return out
+
+
 def cpu_baseline(n, tau, alpha, fx, fy, steps):
     import torch
     from oracle import ref
@@ -381,6 +416,10 @@ def main():
             extras["paper_statistics_256"] = paper_statistics_256(log)
         except Exception as e:  # noqa: BLE001
             extras["paper_statistics_256"] = f"error: {e}"
+        try:
+            extras["entropic_1024"] = entropic_1024(log)
+        except Exception as e:  # noqa: BLE001
+            extras["entropic_1024"] = f"error: {e}"
         try:
             from paper_1809_06735_amd import ensemble as ens_mod
             extras["ensemble"] = ens_mod.bench_ensemble(log=log)

@@ -68,6 +68,15 @@ enum {
                         Sec. 3; optional spectral damping of Eq. 16             */
 };
 
+/* ---- collision operators (lbm_config.collision) ---------------------------- */
+enum {
+  LBM_COLLISION_BGK = 0,      /* Eq. 1: relaxation time tau                              */
+  LBM_COLLISION_ENTROPIC = 1  /* the entropic scheme of Sec. 1: relaxation time
+                                 tau_eff = 2 tau / alpha towards the minimiser of H (Eq. 6)
+                                 at the site's rho, rho u; alpha per site from
+                                 H(f + alpha (f^eq - f)) = H(f).  Unforced only.         */
+};
+
 /* ---- indices into the 8 global scalars returned by *_moments -------------- */
 enum {
   LBM_S_MASS = 0,      /* sum rho                                */
@@ -123,7 +132,9 @@ typedef struct {
   double drag_alpha;   /* linear drag coefficient alpha >= 0: force -alpha rho u
                           (LBM_FORCE_GUO only)                                   */
   int32_t force_scheme;/* LBM_FORCE_GUO or LBM_FORCE_EDM                         */
-  int32_t reserved;    /* must be 0                                              */
+  int32_t collision;   /* LBM_COLLISION_BGK or LBM_COLLISION_ENTROPIC (the latter
+                          needs has_force = 0, drag_alpha = 0, damp_f0 = 0 and
+                          LBM_FORCE_GUO; else LBM_E_UNSUPPORTED)                  */
   /* Spectral damping of the large scales (Sec. 3, Eq. 16), LBM_FORCE_EDM only:
    *   F^R(x) = -damp_f0 sum_{kmin <= |k| <= kmax} u^(k) exp(2 pi i (kx x/nx + ky y/ny)),
    *   u^(k)  = (1/(nx ny)) sum_x u(x) exp(-2 pi i (kx x/nx + ky y/ny)),
@@ -297,6 +308,13 @@ LBM_API int lbm_spectrum_workspace_bytes(int32_t nx, int32_t ny, size_t* bytes);
 LBM_API int lbm_spectrum_fields(int32_t nx, int32_t ny, const double* ux, const double* uy, void* ws,
                         size_t ws_bytes, double* spectrum, int32_t nshells, void* stream);
 
+/* Relaxation of the current populations: alpha (device FP64 [ny][nx], or NULL)
+ * of the entropic collision they would undergo now, and the effective viscosity
+ * nu_eff = c_s^2 (2 tau / alpha - 1/2) (Eq. 5 with tau_eff = 2 tau / alpha).  For
+ * the BGK collision alpha = 2 and nu_eff = nu.  On an entropic handle the
+ * balance uses this nu_eff field at level n.  Asynchronous. */
+LBM_API int lbm_relaxation(lbm_ctx ctx, double* alpha, double* nu_eff);
+
 /* Current time step. */
 LBM_API int lbm_time(lbm_ctx ctx, int64_t* t);
 
@@ -347,6 +365,8 @@ typedef struct {
   const double* fx;         /* device FP64 [ny][nx] total body force at level n, */
   const double* fy;         /* or NULL for none                                 */
   void* stream;
+  const double* nu_field;   /* device FP64 [ny][nx] kinematic viscosity at level n
+                               (in the stress of Eqs. 8-11), or NULL: nu everywhere */
 } lbm_balance_input;
 
 /* Device workspace of lbm_balance_fields for an nx x ny grid. */
@@ -380,9 +400,9 @@ LBM_API int lbm_balance_fields_ex(const lbm_balance_input* in, void* ws, size_t 
 enum { LBM_BATCH_PERSISTENT = 0, LBM_BATCH_PER_STEP = 1, LBM_BATCH_MULTI_STEP = 2 };
 typedef struct lbm_batch_s* lbm_batch;
 
-/* cfgs[nruns]: per-run configuration; with_balance must be 0 and
- * force_scheme LBM_FORCE_GUO (LBM_E_UNSUPPORTED otherwise), stream is taken
- * from cfgs[0]. */
+/* cfgs[nruns]: per-run configuration; with_balance must be 0, force_scheme
+ * LBM_FORCE_GUO and collision LBM_COLLISION_BGK (LBM_E_UNSUPPORTED otherwise),
+ * stream is taken from cfgs[0]. */
 LBM_API int lbm_batch_workspace_bytes(const lbm_config* cfgs, int32_t nruns, size_t* bytes);
 /* rho0/ux0/uy0/fx/fy: host arrays of nruns device FP64 pointers (fx/fy NULL,
  * or entries NULL for runs without force).  Every run starts at f^eq of its

@@ -28,6 +28,9 @@ LAYOUTS = {"planes": LBM_LAYOUT_PLANES, "rows": LBM_LAYOUT_ROWS}
 LBM_FORCE_GUO = 0
 LBM_FORCE_EDM = 1
 SCHEMES = {"guo": LBM_FORCE_GUO, "edm": LBM_FORCE_EDM}
+LBM_COLLISION_BGK = 0
+LBM_COLLISION_ENTROPIC = 1
+COLLISIONS = {"bgk": LBM_COLLISION_BGK, "entropic": LBM_COLLISION_ENTROPIC}
 LBM_BATCH_PERSISTENT = 0
 LBM_BATCH_PER_STEP = 1
 LBM_BATCH_MULTI_STEP = 2
@@ -50,7 +53,7 @@ class Config(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("dtype", C.c_int32),
                 ("has_force", C.c_int32), ("with_balance", C.c_int32), ("layout", C.c_int32),
                 ("tau", C.c_double), ("drag_alpha", C.c_double),
-                ("force_scheme", C.c_int32), ("reserved", C.c_int32),
+                ("force_scheme", C.c_int32), ("collision", C.c_int32),
                 ("damp_f0", C.c_double), ("damp_kmin", C.c_double), ("damp_kmax", C.c_double),
                 ("stream", C.c_void_p)]
 
@@ -75,7 +78,8 @@ class Tile(C.Structure):
 class BalanceInput(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nu", C.c_double),
                 ("rho", C.c_void_p * 3), ("ux", C.c_void_p * 3), ("uy", C.c_void_p * 3),
-                ("fx", C.c_void_p), ("fy", C.c_void_p), ("stream", C.c_void_p)]
+                ("fx", C.c_void_p), ("fy", C.c_void_p), ("stream", C.c_void_p),
+                ("nu_field", C.c_void_p)]
 
 
 LBM_MAX_EDGES = 1024
@@ -117,6 +121,7 @@ SIGNATURES = {
     "lbm_subvolume_balance_ex": (_I, [_P, C.POINTER(_I32), _I32, C.POINTER(BalanceStats), _P,
                                       C.POINTER(_I32), _I32, _DP, _P, C.POINTER(BalanceExtra)]),
     "lbm_energy_spectrum": (_I, [_P, _DP, _I32]),
+    "lbm_relaxation": (_I, [_P, _P, _P]),
     "lbm_spectrum_workspace_bytes": (_I, [_I32, _I32, C.POINTER(_SZ)]),
     "lbm_spectrum_fields": (_I, [_I32, _I32, _P, _P, _P, _SZ, _DP, _I32, _P]),
     "lbm_time": (_I, [_P, C.POINTER(_I64)]),

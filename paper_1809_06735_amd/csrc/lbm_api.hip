@@ -49,7 +49,11 @@ int validate_config(const lbm_config* c) {
     return fail(LBM_E_INVALID, "layout must be LBM_LAYOUT_PLANES or LBM_LAYOUT_ROWS");
   if (c->force_scheme != LBM_FORCE_GUO && c->force_scheme != LBM_FORCE_EDM)
     return fail(LBM_E_INVALID, "force_scheme must be LBM_FORCE_GUO or LBM_FORCE_EDM");
-  if (c->reserved != 0) return fail(LBM_E_INVALID, "reserved must be 0");
+  if (c->collision != LBM_COLLISION_BGK && c->collision != LBM_COLLISION_ENTROPIC)
+    return fail(LBM_E_INVALID, "collision must be LBM_COLLISION_BGK or LBM_COLLISION_ENTROPIC");
+  if (c->collision == LBM_COLLISION_ENTROPIC &&
+      (c->has_force || c->drag_alpha != 0.0 || c->damp_f0 != 0.0 || c->force_scheme != LBM_FORCE_GUO))
+    return fail(LBM_E_UNSUPPORTED, "the entropic collision runs unforced");
   if (!(c->damp_f0 >= 0.0) || !std::isfinite(c->damp_f0))
     return fail(LBM_E_INVALID, "damp_f0 must be finite and >= 0 (got %g)", c->damp_f0);
   if (c->force_scheme == LBM_FORCE_GUO) {
@@ -175,7 +179,7 @@ void tune_cache_load() {
     if (std::sscanf(line, "step dtype=%d nx=%d ny=%d force=%d layout=%d scheme=%d : %d %d %d %d %d %d %d",
                     &dt, &nx, &ny, &fo, &lay, &sch, &t.bx, &t.by, &t.vx, &t.ry, &t.nt, &t.fuse,
                     &t.pf) == 13 &&
-        (sch == LBM_FORCE_EDM ? edm_tile_ok(t, nx, ny) : tile_ok(t, dt, nx, ny)))
+        (sch != LBM_FORCE_GUO ? edm_tile_ok(t, nx, ny) : tile_ok(t, dt, nx, ny)))
       g_tune[tune_key(dt, nx, ny, fo != 0, lay, sch)] = t;
   }
   std::fclose(f);
@@ -195,11 +199,16 @@ void tune_cache_store() {
 bool cfg_forced(const lbm_config& c) { return c.has_force || c.drag_alpha > 0.0 || c.damp_f0 > 0.0; }
 bool is_forced(const lbm_ctx_s* c) { return cfg_forced(c->cfg); }
 bool is_edm(const lbm_ctx_s* c) { return c->cfg.force_scheme == LBM_FORCE_EDM; }
+bool is_entropic(const lbm_ctx_s* c) { return c->cfg.collision == LBM_COLLISION_ENTROPIC; }
+// single-step, one-site-per-thread shapes only
+bool one_site_kernel(const lbm_ctx_s* c) { return is_edm(c) || is_entropic(c); }
+int scheme_code(const lbm_config& c) { return c.force_scheme + 2 * c.collision; }
 std::string ctx_key(const lbm_ctx_s* c) {
-  return tune_key(c->cfg.dtype, c->cfg.nx, c->cfg.ny, is_forced(c), c->cfg.layout, c->cfg.force_scheme);
+  return tune_key(c->cfg.dtype, c->cfg.nx, c->cfg.ny, is_forced(c), c->cfg.layout, scheme_code(c->cfg));
 }
 bool ctx_tile_ok(const lbm_ctx_s* c, const lbm_tile& t) {
-  return is_edm(c) ? edm_tile_ok(t, c->cfg.nx, c->cfg.ny) : tile_ok(t, c->cfg.dtype, c->cfg.nx, c->cfg.ny);
+  return one_site_kernel(c) ? edm_tile_ok(t, c->cfg.nx, c->cfg.ny)
+                            : tile_ok(t, c->cfg.dtype, c->cfg.nx, c->cfg.ny);
 }
 
 }  // namespace
@@ -237,6 +246,7 @@ int enqueue_step(lbm_ctx_s* c, int src, hipStream_t s, double* hr, double* hx, d
   p.alpha = c->cfg.drag_alpha;
   const lbm_tile& t = (single || hr) ? c->tile1 : c->tile;
   if (is_edm(c)) return edm_step(c->cfg, c->edm, c->edm_md, p, t, s);
+  if (is_entropic(c)) return entropic_step(c->cfg.dtype, p, t, s);
   return launch_step(c->cfg.dtype, is_forced(c), p, t, s);
 }
 
@@ -429,8 +439,8 @@ int lbm_init(const lbm_config* cfg, void* ws, size_t ws_bytes, const double* rho
     if (it != g_tune.end())
       c->tile = it->second;
     else
-      c->tile = is_edm(c) ? edm_default_tile(cfg->nx)
-                          : default_tile(cfg->dtype, cfg->nx, cfg->ny, cfg->layout);
+      c->tile = one_site_kernel(c) ? edm_default_tile(cfg->nx)
+                                   : default_tile(cfg->dtype, cfg->nx, cfg->ny, cfg->layout);
     c->tile1 = single_for(c, c->tile);
   }
   int rc = launch_init(cfg->dtype, c->pop[0], c->lay, rho0, ux0, uy0, cfg->nx, cfg->ny, c->stream);
@@ -571,6 +581,12 @@ int lbm_subvolume_balance_ex(lbm_ctx c, const int32_t* sizes, int32_t nsizes, lb
   in.fx = forced ? c->ftot[0] : nullptr;
   in.fy = forced ? c->ftot[1] : nullptr;
   in.stream = c->stream;
+  if (is_entropic(c)) {  // the effective viscosity at t (the handle is unforced: ftot is free)
+    if (int rc2 = relaxation_fields(c->cfg.dtype, true, c->pop[c->cur], c->lay, c->cfg.nx, c->cfg.ny,
+                                    c->cfg.tau, nullptr, c->ftot[0], c->stream))
+      return rc2;
+    in.nu_field = c->ftot[0];
+  }
   return run_balance(in, c->bal, sizes, nsizes, out, dmaps, windows, nwin, wterms, term_fields, extra);
 }
 
@@ -610,6 +626,13 @@ int lbm_balance_fields_ex(const lbm_balance_input* in, void* ws, size_t ws_bytes
   Carver cv(ws, ws_bytes);
   BalanceWs b = carve_balance(cv, in->nx, in->ny);
   return run_balance(*in, b, sizes, nsizes, out, dmaps, windows, nwin, wterms, term_fields, extra);
+}
+
+int lbm_relaxation(lbm_ctx c, double* alpha, double* nu_eff) {
+  if (!c) return fail(LBM_E_INVALID, "ctx is NULL");
+  if (!alpha && !nu_eff) return LBM_OK;
+  return relaxation_fields(c->cfg.dtype, is_entropic(c), c->pop[c->cur], c->lay, c->cfg.nx, c->cfg.ny,
+                           c->cfg.tau, alpha, nu_eff, c->stream);
 }
 
 int lbm_energy_spectrum(lbm_ctx c, double* spectrum, int32_t nshells) {
@@ -719,12 +742,12 @@ int lbm_get_tile(lbm_ctx c, lbm_tile* tile) {
 int lbm_set_tuned_tile(const lbm_config* cfg, const lbm_tile* tile) {
   if (int rc = validate_config(cfg)) return rc;
   if (!tile) return fail(LBM_E_INVALID, "tile is NULL");
-  const bool edm = cfg->force_scheme == LBM_FORCE_EDM;
-  if (edm ? !edm_tile_ok(*tile, cfg->nx, cfg->ny) : !tile_ok(*tile, cfg->dtype, cfg->nx, cfg->ny))
+  const bool one_site = cfg->force_scheme == LBM_FORCE_EDM || cfg->collision == LBM_COLLISION_ENTROPIC;
+  if (one_site ? !edm_tile_ok(*tile, cfg->nx, cfg->ny) : !tile_ok(*tile, cfg->dtype, cfg->nx, cfg->ny))
     return fail(LBM_E_INVALID, "tile not valid for %d x %d", cfg->nx, cfg->ny);
   std::lock_guard<std::mutex> g(g_tune_mu);
   tune_cache_load();
-  g_tune[tune_key(cfg->dtype, cfg->nx, cfg->ny, cfg_forced(*cfg), cfg->layout, cfg->force_scheme)] = *tile;
+  g_tune[tune_key(cfg->dtype, cfg->nx, cfg->ny, cfg_forced(*cfg), cfg->layout, scheme_code(*cfg))] = *tile;
   tune_cache_store();
   return LBM_OK;
 }
@@ -735,7 +758,7 @@ int lbm_autotune(lbm_ctx c, int32_t trial_steps, lbm_tile* chosen) {
   lbm_tile cand[512];
   int n = tile_candidates(c->cfg.dtype, c->cfg.nx, c->cfg.ny, cand, 512);
   if (n > 512) n = 512;
-  if (is_edm(c)) {  // the exact-difference step takes single-step, one-site-per-thread shapes
+  if (one_site_kernel(c)) {  // single-step, one-site-per-thread shapes
     int k = 0;
     for (int i = 0; i < n; ++i)
       if (edm_tile_ok(cand[i], c->cfg.nx, c->cfg.ny)) cand[k++] = cand[i];

@@ -42,6 +42,7 @@ struct PassArgs {
   const double* fx;
   const double* fy;
   double nu;
+  const double* nu_field;  // per-site viscosity at level n, or null
   int nx, ny;
   double* terms;
   double* aux;
@@ -91,7 +92,7 @@ __global__ void __launch_bounds__(256) k_bal_a(PassArgs a) {
   const double r = a.rho[2][i], vx = a.ux[2][i], vy = a.uy[2][i];
   const double dxp = dxr / 3.0;
   const double dyp = dyr / 3.0;
-  const double nu = a.nu;
+  const double nu = a.nu_field ? a.nu_field[i] : a.nu;
   const double sxx = 2.0 * nu * r * dxux;
   const double syy = 2.0 * nu * r * dyuy;
   const double sxy = nu * r * (dxuy_n + dyux_n);
@@ -876,6 +877,7 @@ int balance_terms(const lbm_balance_input& in, const BalanceWs& ws) {
   a.fx = in.fx;
   a.fy = in.fy;
   a.nu = in.nu;
+  a.nu_field = in.nu_field;
   a.nx = nx;
   a.ny = ny;
   a.terms = ws.terms;

@@ -406,8 +406,8 @@ int validate_batch(const lbm_config* cfgs, int32_t nruns) {
     if (int rc = validate_config(&c)) return rc;
     if (c.dtype != cfgs[0].dtype) return fail(LBM_E_INVALID, "run %d: all runs need one dtype", r);
     if (c.with_balance) return fail(LBM_E_INVALID, "run %d: with_balance must be 0 in a batch", r);
-    if (c.force_scheme != LBM_FORCE_GUO)
-      return fail(LBM_E_UNSUPPORTED, "run %d: a batch runs the Guo-forced step only", r);
+    if (c.force_scheme != LBM_FORCE_GUO || c.collision != LBM_COLLISION_BGK)
+      return fail(LBM_E_UNSUPPORTED, "run %d: a batch runs the Guo-forced BGK step only", r);
     if (static_cast<size_t>(c.nx) * c.ny > 0x7fffffffu)
       return fail(LBM_E_INVALID, "run %d: grid too large for a batch", r);
   }

@@ -124,6 +124,14 @@ int launch_to_storage(int dtype, void* dst, const double* src, size_t n, hipStre
 
 int launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 
+// ---- entropic collision -----------------------------------------------------------
+// One entropic step src -> dst (single-step shapes with one site per thread).
+int entropic_step(int dtype, const StepParams& p, const lbm_tile& t, hipStream_t s);
+// alpha and nu_eff of the populations `pop` (either output may be null); for the
+// BGK collision alpha = 2 and nu_eff = (tau0 - 1/2) / 3 everywhere.
+int relaxation_fields(int dtype, bool entropic, const void* pop, PopLayout lay, int nx, int ny, double tau0,
+                      double* alpha, double* nu, hipStream_t s);
+
 // ---- energy spectrum -------------------------------------------------------------
 bool spectrum_size_ok(int nx, int ny);
 size_t spectrum_ws_bytes(int nx, int ny);

@@ -139,12 +139,14 @@ class Simulation:
     the paper's Sec. 3); with "edm", damp_f0 > 0 adds the spectral damping
     F^R = -damp_f0 sum u^(k) e^{i k.x} of the modes damp_shell[0] <= |k| <=
     damp_shell[1] (Eq. 16, u^ the Fourier-series coefficients, so damp_f0 is
-    a rate per step).
+    a rate per step).  collision: "bgk" (Eq. 1) or "entropic" (the entropic
+    scheme of Sec. 1, unforced: relaxation time 2 tau / alpha towards the
+    minimiser of H, alpha per site from the entropy equality).
     """
 
     def __init__(self, rho0, ux0, uy0, tau, dtype="f32", fx=None, fy=None, alpha=0.0,
                  with_balance=False, device="cuda", stream=None, layout="rows", scheme="guo",
-                 damp_f0=0.0, damp_shell=(1.0, 2.0)):
+                 damp_f0=0.0, damp_shell=(1.0, 2.0), collision="bgk"):
         _require_gpu()
         self._lib = L.load()
         self.device = torch.device(device)
@@ -163,8 +165,10 @@ class Simulation:
                        with_balance=int(with_balance), layout=L.LAYOUTS[layout], tau=self.tau,
                        drag_alpha=self.alpha, force_scheme=L.SCHEMES[scheme],
                        damp_f0=float(damp_f0), damp_kmin=float(damp_shell[0]),
-                       damp_kmax=float(damp_shell[1]), stream=_stream_handle(stream))
+                       damp_kmax=float(damp_shell[1]), collision=L.COLLISIONS[collision],
+                       stream=_stream_handle(stream))
         self.scheme = scheme
+        self.collision = collision
         self._cfg = cfg
         nbytes = C.c_size_t()
         L.check(self._lib.lbm_workspace_bytes(C.byref(cfg), C.byref(nbytes)), "lbm_workspace_bytes")
@@ -268,6 +272,15 @@ class Simulation:
             errs.append(r["window_errors"])
         return {"time": np.array(times), "terms": np.stack(terms), "errors": np.stack(errs)}
 
+    def relaxation(self):
+        """(alpha, nu_eff) FP64 [ny, nx] of the current populations: the entropic
+        collision's alpha and nu_eff = c_s^2 (2 tau / alpha - 1/2) (alpha = 2, nu_eff = nu
+        for the BGK collision)."""
+        a = torch.empty((self.ny, self.nx), dtype=torch.float64, device=self.device)
+        v = torch.empty_like(a)
+        L.check(self._lib.lbm_relaxation(self._h, _ptr(a), _ptr(v)), "lbm_relaxation")
+        return a, v
+
     def energy_spectrum(self, nshells=None):
         """Shell-summed kinetic-energy spectrum E(s) of the current velocity (Figs. 5 and 10),
         s = 0 .. nshells - 1 (default: up to the shell of (nx/2, ny/2)); needs with_balance."""
@@ -342,7 +355,15 @@ def balance_fields(rho, ux, uy, nu, sizes, fx=None, fy=None, windows=None, maps=
     f_x = _dev64(fx, dev) if fx is not None else None
     f_y = _dev64(fy, dev) if fy is not None else None
     inp = L.BalanceInput()
-    inp.nx, inp.ny, inp.nu = nx, ny, float(nu)
+    nu_f = None
+    if np.ndim(nu) == 0 and not (isinstance(nu, torch.Tensor) and nu.dim() > 0):
+        inp.nx, inp.ny, inp.nu = nx, ny, float(nu)
+    else:  # a viscosity field at level n
+        nu_f = _dev64(nu, dev)
+        if tuple(nu_f.shape) != (ny, nx):
+            raise ValueError("nu field must be [ny, nx]")
+        inp.nx, inp.ny, inp.nu = nx, ny, 0.0
+        inp.nu_field = nu_f.data_ptr()
     for k in range(3):
         inp.rho[k] = rs[k].data_ptr()
         inp.ux[k] = xs[k].data_ptr()

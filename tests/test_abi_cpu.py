@@ -106,7 +106,7 @@ def test_exact_difference_config_validation():
     damped = C.c_size_t()
     lib.lbm_workspace_bytes(C.byref(ok[2]), C.byref(damped))
     assert damped.value > plain.value  # tables, partials and row coefficients
-    bad = [cfg(force_scheme=2), cfg(reserved=1),
+    bad = [cfg(force_scheme=2), cfg(collision=2),
            cfg(damp_f0=1e-5),                                   # damping needs the EDM scheme
            cfg(damp_f0=-1.0, **edm), cfg(damp_f0=float("inf"), **edm),
            cfg(damp_f0=1e-5, damp_kmin=0.0, damp_kmax=2.0, **edm),
@@ -120,6 +120,13 @@ def test_exact_difference_config_validation():
     # drag is a Guo-scheme option; a batch runs the Guo step only
     assert lib.lbm_workspace_bytes(C.byref(cfg(drag_alpha=1e-3, **edm)), C.byref(n)) == L.LBM_E_UNSUPPORTED
     cs = (L.Config * 2)(cfg(), cfg(**edm))
+    assert lib.lbm_batch_workspace_bytes(cs, 2, C.byref(n)) == L.LBM_E_UNSUPPORTED
+    # the entropic collision: unforced only, not in a batch
+    ent = dict(collision=L.LBM_COLLISION_ENTROPIC)
+    assert lib.lbm_workspace_bytes(C.byref(cfg(**ent)), C.byref(n)) == L.LBM_OK
+    for extra in (dict(has_force=1), dict(drag_alpha=1e-3), dict(force_scheme=L.LBM_FORCE_EDM)):
+        assert lib.lbm_workspace_bytes(C.byref(cfg(**ent, **extra)), C.byref(n)) == L.LBM_E_UNSUPPORTED
+    cs = (L.Config * 2)(cfg(), cfg(**ent))
     assert lib.lbm_batch_workspace_bytes(cs, 2, C.byref(n)) == L.LBM_E_UNSUPPORTED
     # the exact-difference step takes single-step shapes with one site per thread
     assert lib.lbm_set_tuned_tile(C.byref(cfg(**edm)), C.byref(L.Tile(256, 1, 1, 64, 0, 2, 0))) == L.LBM_E_INVALID
