@@ -179,7 +179,7 @@ void tune_cache_load() {
     if (std::sscanf(line, "step dtype=%d nx=%d ny=%d force=%d layout=%d scheme=%d : %d %d %d %d %d %d %d",
                     &dt, &nx, &ny, &fo, &lay, &sch, &t.bx, &t.by, &t.vx, &t.ry, &t.nt, &t.fuse,
                     &t.pf) == 13 &&
-        (sch != LBM_FORCE_GUO ? edm_tile_ok(t, nx, ny) : tile_ok(t, dt, nx, ny)))
+        (sch >= 2 ? entropic_tile_ok(t, nx, ny) : sch == 1 ? edm_tile_ok(t, nx, ny) : tile_ok(t, dt, nx, ny)))
       g_tune[tune_key(dt, nx, ny, fo != 0, lay, sch)] = t;
   }
   std::fclose(f);
@@ -207,8 +207,12 @@ std::string ctx_key(const lbm_ctx_s* c) {
   return tune_key(c->cfg.dtype, c->cfg.nx, c->cfg.ny, is_forced(c), c->cfg.layout, scheme_code(c->cfg));
 }
 bool ctx_tile_ok(const lbm_ctx_s* c, const lbm_tile& t) {
-  return one_site_kernel(c) ? edm_tile_ok(t, c->cfg.nx, c->cfg.ny)
-                            : tile_ok(t, c->cfg.dtype, c->cfg.nx, c->cfg.ny);
+  if (is_entropic(c)) return entropic_tile_ok(t, c->cfg.nx, c->cfg.ny);
+  return is_edm(c) ? edm_tile_ok(t, c->cfg.nx, c->cfg.ny) : tile_ok(t, c->cfg.dtype, c->cfg.nx, c->cfg.ny);
+}
+bool cfg_tile_ok(const lbm_config& c, const lbm_tile& t) {
+  if (c.collision == LBM_COLLISION_ENTROPIC) return entropic_tile_ok(t, c.nx, c.ny);
+  return c.force_scheme == LBM_FORCE_EDM ? edm_tile_ok(t, c.nx, c.ny) : tile_ok(t, c.dtype, c.nx, c.ny);
 }
 
 }  // namespace
@@ -742,9 +746,7 @@ int lbm_get_tile(lbm_ctx c, lbm_tile* tile) {
 int lbm_set_tuned_tile(const lbm_config* cfg, const lbm_tile* tile) {
   if (int rc = validate_config(cfg)) return rc;
   if (!tile) return fail(LBM_E_INVALID, "tile is NULL");
-  const bool one_site = cfg->force_scheme == LBM_FORCE_EDM || cfg->collision == LBM_COLLISION_ENTROPIC;
-  if (one_site ? !edm_tile_ok(*tile, cfg->nx, cfg->ny) : !tile_ok(*tile, cfg->dtype, cfg->nx, cfg->ny))
-    return fail(LBM_E_INVALID, "tile not valid for %d x %d", cfg->nx, cfg->ny);
+  if (!cfg_tile_ok(*cfg, *tile)) return fail(LBM_E_INVALID, "tile not valid for %d x %d", cfg->nx, cfg->ny);
   std::lock_guard<std::mutex> g(g_tune_mu);
   tune_cache_load();
   g_tune[tune_key(cfg->dtype, cfg->nx, cfg->ny, cfg_forced(*cfg), cfg->layout, scheme_code(*cfg))] = *tile;
@@ -761,7 +763,7 @@ int lbm_autotune(lbm_ctx c, int32_t trial_steps, lbm_tile* chosen) {
   if (one_site_kernel(c)) {  // single-step, one-site-per-thread shapes
     int k = 0;
     for (int i = 0; i < n; ++i)
-      if (edm_tile_ok(cand[i], c->cfg.nx, c->cfg.ny)) cand[k++] = cand[i];
+      if (ctx_tile_ok(c, cand[i])) cand[k++] = cand[i];
     n = k;
   }
   if (n < 1) return fail(LBM_E_UNSUPPORTED, "no step-kernel shape fits this grid");

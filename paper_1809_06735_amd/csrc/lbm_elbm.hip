@@ -5,9 +5,10 @@
 // site's rho and rho u in closed form,
 //   f^eq_l = t_l rho prod_a (2 - s_a) ((2 u_a + s_a) / (1 - u_a))^{c_la},  s_a = sqrt(1 + 3 u_a^2),
 // delta = f^eq - f, and alpha the root alpha > 1 of the entropy equality
-// H(f + alpha delta) = H(f), found by Newton's method from alpha = 2 inside a
-// bracket [1, alpha_max) kept by bisection (alpha_max: the largest step keeping
-// every population positive).  The entropy gain is evaluated as
+// H(f + alpha delta) = H(f), found by Newton's method inside a bracket
+// [1, alpha_max) kept by bisection (alpha_max: the largest step keeping every
+// population positive), started from the root of the gain expanded to fourth
+// order in delta / f around alpha = 2.  The entropy gain is evaluated as
 //   g(a) = sum_l f_l phi(a delta_l / f_l) - a sum_l delta_l log1p(delta_l / f_l),
 //   phi(t) = (1 + t) log1p(t) - t,
 // which is H(f + a delta) - H(f) with the first-order terms cancelled
@@ -29,9 +30,12 @@ using namespace step_detail;
 
 // below this max_l |delta_l| / f_l the site counts as at equilibrium: alpha = 2
 constexpr double kNearEq = 1e-8;
+// workgroups of at most this many threads, so the FP64 site state stays in registers
+constexpr int kEntropicMaxThreads = 256;
 
 struct EntropicSite {
-  double f[9], dl[9];
+  double f[9];
+  double x[9];  // delta / f, delta = f^eq - f
   double rho, ux, uy;
 };
 
@@ -59,7 +63,7 @@ __device__ __forceinline__ void entropic_site(const T (&d)[9], EntropicSite& s) 
     if (cxq(l) == -1) e /= zx;
     if (cyq(l) == 1) e *= zy;
     if (cyq(l) == -1) e /= zy;
-    s.dl[l] = e - s.f[l];
+    s.x[l] = (e - s.f[l]) / s.f[l];
   }
 }
 
@@ -68,28 +72,39 @@ __device__ __forceinline__ double entropy_gain(const EntropicSite& s, double c1,
   double g = 0.0, gd = 0.0;
 #pragma unroll
   for (int l = 0; l < 9; ++l) {
-    const double t = a * s.dl[l] / s.f[l];
+    const double t = a * s.x[l];
     const double lp = log1p(t);
     g += s.f[l] * ((1.0 + t) * lp - t);
-    gd += s.dl[l] * lp;
+    gd += s.f[l] * s.x[l] * lp;
   }
   dg = gd - c1;
   return g - a * c1;
 }
 
 __device__ double entropic_alpha(const EntropicSite& s) {
-  double mr = 0.0, amax = 1e300;
+  double mr = 0.0, xmin = 0.0;
+  double s2 = 0.0, s3 = 0.0, s4 = 0.0;  // sum f x^k: the expansion of the gain in x = delta / f
 #pragma unroll
   for (int l = 0; l < 9; ++l) {
-    mr = fmax(mr, fabs(s.dl[l]) / s.f[l]);
-    if (s.dl[l] < 0.0) amax = fmin(amax, -s.f[l] / s.dl[l]);
+    const double x = s.x[l];
+    mr = fmax(mr, fabs(x));
+    xmin = fmin(xmin, x);
+    const double fx2 = s.f[l] * x * x;
+    s2 += fx2;
+    s3 += fx2 * x;
+    s4 += fx2 * x * x;
   }
   if (mr < kNearEq) return 2.0;
+  const double amax = xmin < 0.0 ? -1.0 / xmin : 1e300;  // every f + a delta > 0 below it
   double c1 = 0.0;
 #pragma unroll
-  for (int l = 0; l < 9; ++l) c1 += s.dl[l] * log1p(s.dl[l] / s.f[l]);
+  for (int l = 0; l < 9; ++l) c1 += s.f[l] * s.x[l] * log1p(s.x[l]);
   double lo = 1.0, hi = amax < 1e300 ? amax * (1.0 - 1e-12) : 1e6;
-  double a = 2.0 < hi ? 2.0 : 0.5 * (lo + hi);
+  // start from the root of the gain expanded to fourth order around a = 2:
+  // g(2 + e) / (2 + e) = e S2 / 2 - S3 / 6 + S4 / 3 + ... = 0
+  // (the expansion is only trusted close to 2: far from equilibrium start at 2)
+  double a = 2.0 + (s3 - 2.0 * s4) / (3.0 * s2);
+  if (!(fabs(a - 2.0) < 0.25 && a > lo && a < hi)) a = 2.0 < hi ? 2.0 : 0.5 * (lo + hi);
   double dg;
   double ga = entropy_gain(s, c1, a, dg);
   if (ga < 0.0) {
@@ -101,8 +116,11 @@ __device__ double entropic_alpha(const EntropicSite& s) {
   }
   for (int it = 0; it < 64; ++it) {
     double an = a - ga / dg;
-    if (!(an > lo && an < hi)) an = 0.5 * (lo + hi);
-    if (fabs(an - a) <= 1e-15 * a || hi - lo <= 1e-15 * hi) return an;
+    const bool newton = an > lo && an < hi;
+    if (!newton) an = 0.5 * (lo + hi);
+    // quadratic convergence: after a Newton step below 1e-10 the iterate is within
+    // ~1e-20 of the root; bisection steps run until the bracket itself is that small
+    if (newton ? fabs(an - a) <= 1e-10 * a : hi - lo <= 1e-15 * hi) return an;
     a = an;
     ga = entropy_gain(s, c1, a, dg);
     if (ga < 0.0)
@@ -114,7 +132,8 @@ __device__ double entropic_alpha(const EntropicSite& s) {
 }
 
 template <typename T, bool NT>
-__global__ void __launch_bounds__(1024) k_elbm_step(StepParams p, int tiles_x, int total, int per_xcd, int ry) {
+__global__ void __launch_bounds__(kEntropicMaxThreads) k_elbm_step(StepParams p, int tiles_x, int total,
+                                                                    int per_xcd, int ry) {
   const int b = blockIdx.x;
   const int tile = (b & 7) * per_xcd + (b >> 3);
   if (tile >= total) return;
@@ -142,7 +161,7 @@ __global__ void __launch_bounds__(1024) k_elbm_step(StepParams p, int tiles_x, i
     const double ab = entropic_alpha(s) * beta;
 #pragma unroll
     for (int l = 0; l < 9; ++l) {
-      const T o = T(double(di[l]) + ab * s.dl[l]);
+      const T o = T(double(di[l]) + ab * (s.f[l] * s.x[l]));
       T* q = dst + l * p.ps + static_cast<size_t>(y) * p.rs + x;
       if constexpr (NT) __builtin_nontemporal_store(o, q);
       else *q = o;
@@ -207,8 +226,12 @@ int launch_t(const StepParams& p, const lbm_tile& t, hipStream_t s) {
 
 }  // namespace
 
+bool entropic_tile_ok(const lbm_tile& t, int nx, int ny) {
+  return edm_tile_ok(t, nx, ny) && t.bx * t.by <= kEntropicMaxThreads;
+}
+
 int entropic_step(int dtype, const StepParams& p, const lbm_tile& t, hipStream_t s) {
-  if (!edm_tile_ok(t, p.nx, p.ny)) return fail(LBM_E_INVALID, "invalid launch shape for the entropic step");
+  if (!entropic_tile_ok(t, p.nx, p.ny)) return fail(LBM_E_INVALID, "invalid launch shape for the entropic step");
   return dtype == LBM_F64 ? launch_t<double>(p, t, s) : launch_t<float>(p, t, s);
 }
 

@@ -127,6 +127,7 @@ int launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 // ---- entropic collision -----------------------------------------------------------
 // One entropic step src -> dst (single-step shapes with one site per thread).
 int entropic_step(int dtype, const StepParams& p, const lbm_tile& t, hipStream_t s);
+bool entropic_tile_ok(const lbm_tile& t, int nx, int ny);  // one site per thread, <= 256 threads
 // alpha and nu_eff of the populations `pop` (either output may be null); for the
 // BGK collision alpha = 2 and nu_eff = (tau0 - 1/2) / 3 everywhere.
 int relaxation_fields(int dtype, bool entropic, const void* pop, PopLayout lay, int nx, int ny, double tau0,
