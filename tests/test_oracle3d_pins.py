@@ -1,0 +1,168 @@
+"""Pins of the 3D oracle (oracle/ref3d.py) against what the lattice, the mathematics and the
+2D oracle fix: D3Q19 isotropy, equilibrium and forcing moments, the Taylor-Green decay rate
+(Eq. 5), the z-invariant limit equal to the 2D balance, the vortex-stretching term and the
+viscous identities by spectral derivatives, cube means by brute force."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import ref, ref3d
+
+D = torch.float64
+
+
+def _spec_d(a, axis):
+    a = np.asarray(a)
+    n = a.shape[axis]
+    k = 2 * np.pi * np.fft.fftfreq(n)
+    shape = [1] * a.ndim
+    shape[axis] = n
+    return np.real(np.fft.ifft(1j * k.reshape(shape) * np.fft.fft(a, axis=axis), axis=axis))
+
+
+def _smooth3(n, seed):
+    rng = np.random.default_rng(seed)
+    z, y, x = np.meshgrid(*[np.arange(n)] * 3, indexing="ij")
+    w = 2 * np.pi / n
+
+    def trig():
+        out = np.zeros((n, n, n))
+        for _ in range(6):
+            k = rng.integers(-2, 3, size=3)
+            out += rng.standard_normal() * np.cos(w * (k[0] * x + k[1] * y + k[2] * z) + rng.uniform(0, 6.28))
+        return out
+
+    u = [0.02 * trig() for _ in range(3)]
+    rho = 1 + 0.01 * trig()
+    return rho, u
+
+
+def test_d3q19_isotropy():
+    w = np.array(ref3d.W)
+    c = np.array(ref3d.C, dtype=float)
+    assert w.sum() == pytest.approx(1.0, rel=1e-15)
+    assert np.abs(w @ c).max() < 1e-16
+    m2 = np.einsum("l,la,lb->ab", w, c, c)
+    assert np.abs(m2 - np.eye(3) / 3).max() < 1e-15
+    assert np.abs(np.einsum("l,la,lb,lc->abc", w, c, c, c)).max() < 1e-16
+    m4 = np.einsum("l,la,lb,lc,ld->abcd", w, c, c, c, c)
+    d = np.eye(3)
+    want = (np.einsum("ab,cd->abcd", d, d) + np.einsum("ac,bd->abcd", d, d) + np.einsum("ad,bc->abcd", d, d)) / 9
+    assert np.abs(m4 - want).max() < 1e-15
+    # opposite velocities come in pairs, the rest velocity first
+    assert ref3d.C[0] == (0, 0, 0) and all(tuple(-v for v in ref3d.C[l]) in ref3d.C for l in range(19))
+
+
+def test_equilibrium_and_guo_moments():
+    g = torch.Generator().manual_seed(1)
+    shp = (4, 5, 6)
+    rho = 1 + 0.05 * torch.randn(*shp, generator=g, dtype=D)
+    u = [0.05 * torch.randn(*shp, generator=g, dtype=D) for _ in range(3)]
+    f = ref3d.equilibrium(rho, *u)
+    assert float((f.sum(0) - rho).abs().max()) < 1e-15
+    for j, ui in zip(ref3d.momentum(f), u):
+        assert float((j - rho * ui).abs().max()) < 1e-15
+    c = ref3d.C
+    for a in range(3):
+        for b in range(3):
+            p = sum(c[l][a] * c[l][b] * f[l] for l in range(19))
+            want = rho * u[a] * u[b] + (rho / 3 if a == b else 0)
+            assert float((p - want).abs().max()) < 1e-15
+    # Guo's term: no mass, momentum change F per collision
+    F = [1e-4 * torch.randn(*shp, generator=g, dtype=D) for _ in range(3)]
+    fneq = f + 1e-3 * torch.randn(19, *shp, generator=g, dtype=D)
+    post = ref3d.collide(fneq, 0.7, *F)
+    dlt = post - fneq
+    assert float(dlt.sum(0).abs().max()) < 1e-15
+    for j, Fi in zip(ref3d.momentum(dlt), F):
+        assert float((j - Fi).abs().max()) < 1e-15
+
+
+def test_taylor_green_3d_decay_rate():
+    """u = u0 (sin kx cos ky cos kz, -cos kx sin ky cos kz, 0) decays like exp(-3 nu k^2 t) in
+    the linear regime (Eq. 5: nu = (tau - 1/2) / 3)."""
+    n, tau, u0 = 32, 0.8, 1e-5
+    k = 2 * np.pi / n
+    z, y, x = np.meshgrid(*[np.arange(n)] * 3, indexing="ij")
+    ux = u0 * np.sin(k * x) * np.cos(k * y) * np.cos(k * z)
+    uy = -u0 * np.cos(k * x) * np.sin(k * y) * np.cos(k * z)
+    uz = np.zeros_like(ux)
+    f = ref3d.init_populations(np.ones_like(ux), ux, uy, uz)
+    f = ref3d.run(f, 20, tau)  # let the initial non-equilibrium adjust
+    a0 = float(ref3d.macroscopic(f)[1].abs().max())
+    steps = 100
+    f = ref3d.run(f, steps, tau)
+    a1 = float(ref3d.macroscopic(f)[1].abs().max())
+    nu = (tau - 0.5) / 3
+    rate = -math.log(a1 / a0) / steps
+    assert rate == pytest.approx(3 * nu * k * k, rel=0.01)
+
+
+def test_z_invariant_limit_equals_the_2d_balance():
+    """For a z-invariant flow with u_z = 0 every 3D term equals the 2D oracle's term on a slice
+    and the stretching term vanishes."""
+    n = 16
+    rng = np.random.default_rng(4)
+    y, x = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    lv2 = {"rho": [], "ux": [], "uy": []}
+    for k in range(3):
+        ph = rng.uniform(0, 6.28, size=4)
+        lv2["rho"].append(1 + 0.01 * np.cos(2 * np.pi * x / n + ph[0]) * (1 + 0.01 * k))
+        lv2["ux"].append(0.03 * np.sin(2 * np.pi * (x + 2 * y) / n + ph[1]) * (1 + 0.02 * k))
+        lv2["uy"].append(0.02 * np.cos(2 * np.pi * (2 * x - y) / n + ph[2]) * (1 - 0.01 * k))
+    fx = 1e-5 * np.sin(2 * np.pi * 3 * y / n)
+    fy = 1e-5 * np.cos(2 * np.pi * 2 * x / n)
+    t2 = ref.balance_fields(lv2["rho"], lv2["ux"], lv2["uy"], fx, fy, 0.004)
+    ext = lambda a: np.broadcast_to(a, (5, n, n)).copy()  # noqa: E731
+    t3 = ref3d.balance_fields([ext(a) for a in lv2["rho"]], [ext(a) for a in lv2["ux"]],
+                              [ext(a) for a in lv2["uy"]], [np.zeros((5, n, n))] * 3, ext(fx), ext(fy),
+                              np.zeros((5, n, n)), 0.004)
+    for name in ref.TERM_NAMES:
+        for zi in range(5):
+            assert float((t3[name][zi] - t2[name]).abs().max()) <= 1e-15 * max(1e-30, float(t2[name].abs().max())) + 1e-30, name
+    assert float(t3["z6"].abs().max()) < 1e-30  # rounding of the z differences of constants
+
+
+def test_stretching_and_viscous_identities_by_spectral_derivatives():
+    """z6 = omega_i omega_j d_j u_i, e4 + e5 = u . div(sigma) and z4 + z5 = omega . curl(H) with
+    exact (spectral) derivatives of a smooth 3D field; the divergence terms vanish over the
+    whole domain."""
+    n = 64
+    rho, u = _smooth3(n, 7)
+    lv = {"rho": [rho] * 3, "u": [u] * 3}
+    nu = 0.01
+    t = ref3d.balance_fields(lv["rho"], [q[0] for q in lv["u"]], [q[1] for q in lv["u"]],
+                             [q[2] for q in lv["u"]], None, None, None, nu)
+    ax = {0: 2, 1: 1, 2: 0}  # component direction -> array axis
+    du = [[_spec_d(u[i], ax[j]) for j in range(3)] for i in range(3)]
+    om = [du[2][1] - du[1][2], du[0][2] - du[2][0], du[1][0] - du[0][1]]
+    z6 = sum(om[i] * om[j] * du[i][j] for i in range(3) for j in range(3))
+    z6s = sum(np.abs(om[i] * om[j] * du[i][j]) for i in range(3) for j in range(3))
+    # FD8 against spectral derivatives: the fields hold modes |k_a| <= 2 on 64 points, the
+    # products inside e5 and H up to |k_a| = 6 (FD8 error ~1e-5 there); tolerances are
+    # relative to the terms of the sums, which cancel to a smaller total
+    assert np.abs(t["z6"].numpy() - z6).max() < 1e-5 * z6s.max()
+    sig = [[nu * rho * (du[i][j] + du[j][i]) for j in range(3)] for i in range(3)]
+    divs = [sum(_spec_d(sig[i][j], ax[j]) for j in range(3)) for i in range(3)]
+    w = sum(u[i] * divs[i] for i in range(3))
+    ws = sum(np.abs(u[i] * divs[i]) for i in range(3))
+    assert np.abs((t["e4"] + t["e5"]).numpy() - w).max() < 1e-4 * ws.max()
+    h = [divs[i] / rho for i in range(3)]
+    ch = [_spec_d(h[2], 1) - _spec_d(h[1], 0), _spec_d(h[0], 0) - _spec_d(h[2], 2), _spec_d(h[1], 2) - _spec_d(h[0], 1)]
+    w = sum(om[i] * ch[i] for i in range(3))
+    ws = sum(np.abs(om[i] * ch[i]) for i in range(3))
+    assert np.abs((t["z4"] + t["z5"]).numpy() - w).max() < 1e-3 * ws.max()
+    for name in ("e1", "e5", "z1", "z5"):
+        assert abs(float(t[name].sum())) < 1e-12 * float(t[name].abs().sum()), name
+
+
+def test_cube_means_against_brute_force():
+    g = torch.Generator().manual_seed(3)
+    a = torch.randn(5, 6, 7, generator=g, dtype=D)
+    m = ref3d.box_mean_map(a, 3)
+    for (z0, y0, x0) in [(0, 0, 0), (4, 5, 6), (2, 0, 5)]:
+        assert float(m[z0, y0, x0]) == pytest.approx(ref3d.box_mean_brute(a, 3, z0, y0, x0), rel=1e-13)
+    m5 = ref3d.box_mean_map(a, 5)
+    assert float(m5[1, 2, 3]) == pytest.approx(ref3d.box_mean_brute(a, 5, 1, 2, 3), rel=1e-13)
