@@ -239,6 +239,45 @@ def entropic_1024(log, n=1024, tau0=0.5005, steps=400):
     return out
 
 
+def d3q19_256(log, n=256, tau=0.52, steps=200):
+    """The three-dimensional extension: a forced 256^3 D3Q19 FP32 run (one launch per step,
+    164 algorithmic bytes per site: 19 populations read and written, 3 force values read),
+    timed with HIP events on the handle's stream, then the 3D balance with the stretching
+    term at L = 16, 64, 256 over every cube corner."""
+    import torch
+    import lbm_inputs as inp
+    from paper_1809_06735_amd import Simulation3D
+    shape = (n, n, n)
+    rho, ux, uy, uz = inp.fields3(shape, seed=0, max_mach=0.1)
+    fx, fy, fz = inp.force3(shape, seed=0, amp=1e-6)
+    sim = Simulation3D(rho, ux, uy, uz, tau, dtype="f32", fx=fx, fy=fy, fz=fz, with_balance=True)
+    del rho, ux, uy, uz, fx, fy, fz
+    sim.step(10)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    sim.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    sites = n ** 3
+    gbs = 164 * sites / (ms * 1e-3) / 1e9
+    out = {"grid": [n, n, n], "dtype": "f32", "steps": steps, "ms_per_step": round(ms, 4),
+           "MLUPS": round(sites / (ms * 1e-3) / 1e6, 1), "kernel_GBps": round(gbs, 1),
+           "frac_of_8TBps": round(gbs / HBM_PEAK_GBS, 4)}
+    sizes = (16, 64, 256)
+    t0 = time.perf_counter()
+    res = sim.balance(sizes)
+    out["balance_s"] = round(time.perf_counter() - t0, 3)
+    out["balance"] = {str(st["L"]): {"mean_dE": st["dE"]["mean"], "mean_dZ": st["dZ"]["mean"],
+                                     "mean_Ma": st["Ma"]["mean"]} for st in res["stats"]}
+    _, _, _, _, sc = sim.moments()
+    out["finite"] = sc["nonfinite"] == 0
+    sim.close()
+    log(f"[bench] d3q19 {n}^3: {out['MLUPS']} MLUPS ({out['kernel_GBps']} GB/s), balance {out['balance_s']} s")
+    return out
+
+
 def cpu_baseline(n, tau, alpha, fx, fy, steps):
     import torch
     from oracle import ref
@@ -420,6 +459,10 @@ def main():
             extras["entropic_1024"] = entropic_1024(log)
         except Exception as e:  # noqa: BLE001
             extras["entropic_1024"] = f"error: {e}"
+        try:
+            extras["d3q19_256"] = d3q19_256(log)
+        except Exception as e:  # noqa: BLE001
+            extras["d3q19_256"] = f"error: {e}"
         try:
             from paper_1809_06735_amd import ensemble as ens_mod
             extras["ensemble"] = ens_mod.bench_ensemble(log=log)

@@ -472,6 +472,89 @@ LBM_API int lbm_adjoint_run(const lbm_adjoint_config* cfg, void* ws, size_t ws_b
                     const double* ux0, const double* uy0, double* loss,
                     double* grad_ux0, double* grad_uy0, double* grad_tau);
 
+/* ---- three dimensions: D3Q19 ------------------------------------------------------- */
+/* The same method in three dimensions: the LBGK update of Eq. 1 with the
+ * equilibrium of Eq. 2 on the D3Q19 lattice (rest weight 1/3, six axis
+ * velocities of weight 1/18, twelve edge diagonals of weight 1/36,
+ * c_s^2 = 1/3), Guo's forcing term with the half-force velocity, and the
+ * balances of Sec. 2 in index form over cubic sub-volumes L^3.  In 3D the
+ * enstrophy equation keeps the vortex-stretching term omega_i omega_j d_j u_i
+ * (Sec. 2 drops it only because it vanishes in 2D).
+ * Fields are row-major [nz][ny][nx] (x fastest), periodic in x, y and z. */
+typedef struct {
+  int32_t nx, ny, nz;  /* 16..4096 each                                         */
+  int32_t dtype;       /* LBM_F32 or LBM_F64 population storage and step arithmetic */
+  int32_t has_force;   /* 1: static body force (fx, fy, fz given to lbm3_init)   */
+  int32_t with_balance;/* 1: reserve the balance scratch (lbm3_subvolume_balance) */
+  double tau;          /* relaxation time > 1/2; nu = (tau - 1/2)/3              */
+  void* stream;        /* hipStream_t to enqueue on, or NULL                     */
+} lbm3_config;
+
+typedef struct lbm3_ctx_s* lbm3_ctx;
+
+/* Scalars of lbm3_moments, in this order. */
+enum {
+  LBM3_S_MASS = 0, LBM3_S_MOMX = 1, LBM3_S_MOMY = 2, LBM3_S_MOMZ = 3, LBM3_S_ENERGY = 4,
+  LBM3_S_MAXU = 5, LBM3_S_MINRHO = 6, LBM3_S_NONFINITE = 7, LBM3_S_TIME = 8, LBM3_NSCALARS = 9
+};
+
+/* Pointwise integrand fields of the 3D balance, in this order (term_fields):
+ * d_t E, -div(E u), -u.grad p (p = rho/3), u.F, -sigma_ij d_j u_i,
+ * d_j(u_i sigma_ij); d_t Omega, -div(Omega u), -Omega div u,
+ * omega.curl(F/rho), H.curl(omega), div(H x omega), omega_i omega_j d_j u_i
+ * (vortex stretching); |u|^2.  E = rho|u|^2/2, Omega = |omega|^2/2,
+ * omega = curl u, sigma_ij = nu rho (d_j u_i + d_i u_j), H_i = d_j sigma_ij/rho;
+ * space derivatives by Eq. 18 along each axis, d_t by Eq. 17. */
+enum {
+  LBM3_T_LHS_E = 0, LBM3_T_E1, LBM3_T_E2, LBM3_T_E3, LBM3_T_E4, LBM3_T_E5,
+  LBM3_T_LHS_Z, LBM3_T_Z1, LBM3_T_Z2, LBM3_T_Z3, LBM3_T_Z4, LBM3_T_Z5, LBM3_T_Z6,
+  LBM3_T_USQ, LBM3_NTERMS
+};
+
+/* Bytes of device workspace lbm3_init needs for cfg.  Host call. */
+LBM_API int lbm3_workspace_bytes(const lbm3_config* cfg, size_t* bytes);
+
+/* Create a 3D handle with f_l(x, 0) = f^eq_l(rho0(x), u0(x)).
+ *   ws, ws_bytes : device workspace, 256-byte aligned, >= lbm3_workspace_bytes.
+ *   rho0, ux0, uy0, uz0 : device FP64 [nz][ny][nx] initial fields.
+ *   fx, fy, fz : device FP64 [nz][ny][nx] static force when cfg->has_force,
+ *                else NULL; copied into the workspace.
+ * Asynchronous on cfg->stream. */
+LBM_API int lbm3_init(const lbm3_config* cfg, void* ws, size_t ws_bytes, const double* rho0,
+                      const double* ux0, const double* uy0, const double* uz0, const double* fx,
+                      const double* fy, const double* fz, lbm3_ctx* out);
+
+/* Advance n >= 0 steps (pull streaming fused with the BGK collision and Guo's
+ * term, one launch per step); the last two steps record (rho, u) for the time
+ * derivative of the balance.  Asynchronous. */
+LBM_API int lbm3_step(lbm3_ctx ctx, int64_t n);
+
+/* Moments at the current time: rho = sum f, u = (sum f c + F/2)/rho, evaluated
+ * in the storage type and written as FP64.
+ *   rho, ux, uy, uz : device FP64 [nz][ny][nx], any may be NULL.
+ *   scalars9 : host double[LBM3_NSCALARS] or NULL; when given the call
+ *              synchronises and returns LBM_E_DIVERGED for a non-finite
+ *              moment or rho <= 0 (the scalars are still filled). */
+LBM_API int lbm3_moments(lbm3_ctx ctx, double* rho, double* ux, double* uy, double* uz,
+                         double* scalars9);
+
+LBM_API int lbm3_time(lbm3_ctx ctx, int64_t* t);
+
+/* The 3D sub-volume balance at the current time t (handle with
+ * with_balance = 1, t >= 2 with the two preceding steps recorded, else
+ * LBM_E_STATE).  For every box side L in sizes[nsizes] (host, 1 <= L <=
+ * min(nx, ny, nz)) the statistics of delta^E, delta^Omega (Eqs. 12-13 with
+ * the stretching term among the enstrophy terms) and Ma_V = sqrt(<|u|^2>)/c_s
+ * over the L^3 cubes at every corner (z0, y0, x0), periodic; L == nx == ny == nz
+ * is the single whole-domain cube.  out[nsizes] : host.
+ *   term_fields : device FP64 [LBM3_NTERMS][nz][ny][nx] integrands, or NULL.
+ * Synchronous. */
+LBM_API int lbm3_subvolume_balance(lbm3_ctx ctx, const int32_t* sizes, int32_t nsizes,
+                                   lbm_balance_stats* out, double* term_fields);
+
+/* Release the handle (after the stream has drained); the workspace is the caller's. */
+LBM_API int lbm3_destroy(lbm3_ctx ctx);
+
 /* ---- bandwidth reference ----------------------------------------------------------- */
 /* Plain device-to-device copy of `bytes` (a multiple of 16) with 16-byte
  * vector loads and stores, on `stream`: the achievable-bandwidth reference

@@ -14,6 +14,8 @@ configurations are not available, so the workloads below stand in for them:
 * A random-phase isotropic velocity field with energy spectrum
   E(k) ~ k^4 exp(-2 (k/8)^2), scaled to a given maximum Mach number, for the
   decaying-turbulence, ensemble and differentiable workloads.
+* For the three-dimensional extension: sums of a few random low-wavenumber
+  cosine modes (periodic on any box) for rho, u and a static force.
 * A divergence-free stream-function force built like Sec. 3, Eqs. 14-15 (a sum
   of cosines over a shell of integer wavevectors, force = (d_y Psi, -d_x Psi)),
   with independent seeded phases, for the forced workload.
@@ -27,7 +29,8 @@ import numpy as np
 
 __all__ = [
     "CS", "taylor_green", "spectrum_velocity", "forcing_field", "shell_vectors",
-    "ensemble_members", "balance_levels", "WORKLOADS", "Workload",
+    "ensemble_members", "balance_levels", "WORKLOADS", "Workload", "random_modes3", "fields3",
+    "force3",
 ]
 
 #: lattice speed of sound of D2Q9 (used only to turn a Mach number into a speed)
@@ -297,3 +300,37 @@ WORKLOADS = {
                          sizes=(4, 8, 16, 32, 64, 128, 181, 256), balance_every=100,
                          taus=(0.60, 0.54, 0.53, 0.52, 0.515)),
 }
+
+
+# ---------------------------------------------------------------------------
+# three dimensions ([nz, ny, nx] arrays)
+# ---------------------------------------------------------------------------
+def random_modes3(shape, rng: np.random.Generator, nmodes: int = 8, kmax: int = 2):
+    """Sum of nmodes cosines cos(2 pi (a x / nx + b y / ny + c z / nz) + phase) with
+    integer (a, b, c) in [-kmax, kmax] and standard-normal amplitudes, scaled to a
+    maximum |value| of 1; [nz, ny, nx] FP64."""
+    nz, ny, nx = shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    out = np.zeros(shape)
+    for _ in range(nmodes):
+        a, b, c = rng.integers(-kmax, kmax + 1, size=3)
+        ph = rng.uniform(0.0, 2.0 * math.pi)
+        out += rng.standard_normal() * np.cos(2.0 * math.pi * (a * x / nx + b * y / ny + c * z / nz) + ph)
+    m = np.abs(out).max()
+    return out / m if m > 0 else out
+
+
+def fields3(shape, seed: int = 0, max_mach: float = 0.05, drho: float = 0.01, nmodes: int = 8,
+            kmax: int = 2):
+    """Seeded smooth 3D initial fields (rho, ux, uy, uz), each velocity component with
+    maximum |u| = max_mach c_s and rho = 1 + drho * (modes of max 1)."""
+    rng = np.random.default_rng(seed)
+    u = [max_mach * CS * random_modes3(shape, rng, nmodes, kmax) for _ in range(3)]
+    rho = 1.0 + drho * random_modes3(shape, rng, nmodes, kmax)
+    return rho, u[0], u[1], u[2]
+
+
+def force3(shape, seed: int = 0, amp: float = 1e-5, nmodes: int = 4, kmax: int = 2):
+    """Seeded static 3D force (fx, fy, fz), each component of maximum |value| amp."""
+    rng = np.random.default_rng(seed + 7919)
+    return tuple(amp * random_modes3(shape, rng, nmodes, kmax) for _ in range(3))

@@ -39,6 +39,11 @@ NWVALS = 16   # per explicit window: 13 box means, delta^E, delta^Omega, Ma
 TERM_NAMES = ("lhs_E", "e1", "e2", "e3", "e4", "e5",
               "lhs_Z", "z1", "z2", "z3", "z4", "z5", "usq")
 SCALAR_NAMES = ("mass", "mom_x", "mom_y", "energy", "max_speed", "min_rho", "nonfinite", "time")
+NTERMS3 = 14
+TERM_NAMES3 = ("lhs_E", "e1", "e2", "e3", "e4", "e5",
+               "lhs_Z", "z1", "z2", "z3", "z4", "z5", "z6", "usq")
+SCALAR_NAMES3 = ("mass", "mom_x", "mom_y", "mom_z", "energy", "max_speed", "min_rho", "nonfinite",
+                 "time")
 
 
 class LBMError(RuntimeError):
@@ -102,6 +107,12 @@ class AdjointConfig(C.Structure):
 _P = C.c_void_p
 _I = C.c_int
 _I32 = C.c_int32
+class Config3(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("dtype", C.c_int32),
+                ("has_force", C.c_int32), ("with_balance", C.c_int32), ("tau", C.c_double),
+                ("stream", C.c_void_p)]
+
+
 _I64 = C.c_int64
 _SZ = C.c_size_t
 _DP = C.POINTER(C.c_double)
@@ -159,6 +170,13 @@ SIGNATURES = {
     "lbm_adjoint_workspace_bytes": (_I, [C.POINTER(AdjointConfig), C.POINTER(_SZ)]),
     "lbm_adjoint_run": (_I, [C.POINTER(AdjointConfig), _P, _SZ, _P, _P, _DP, _P, _P, _DP]),
     "lbm_copy": (_I, [_P, _P, _SZ, _P]),
+    "lbm3_workspace_bytes": (_I, [C.POINTER(Config3), C.POINTER(_SZ)]),
+    "lbm3_init": (_I, [C.POINTER(Config3), _P, _SZ, _P, _P, _P, _P, _P, _P, _P, C.POINTER(_P)]),
+    "lbm3_step": (_I, [_P, _I64]),
+    "lbm3_moments": (_I, [_P, _P, _P, _P, _P, _DP]),
+    "lbm3_time": (_I, [_P, C.POINTER(_I64)]),
+    "lbm3_subvolume_balance": (_I, [_P, C.POINTER(_I32), _I32, C.POINTER(BalanceStats), _P]),
+    "lbm3_destroy": (_I, [_P]),
 }
 
 _lock = threading.Lock()

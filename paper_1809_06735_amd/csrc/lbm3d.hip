@@ -1,0 +1,1010 @@
+// Three-dimensional extension for gfx950: D3Q19 LBGK step (Eq. 1 with the
+// D3Q19 equilibrium of Eq. 2 and Guo's forcing term), moments, and the
+// sub-volume kinetic-energy and enstrophy balances in 3D, where the enstrophy
+// equation gains the vortex-stretching term omega_i omega_j d_j u_i (Sec. 2
+// notes that 3D keeps it), averaged over cubes L^3 at every corner.
+//
+// Populations: nine-teen planes [19][nz][ny][nx], deviations from the weights,
+// kept un-streamed (plane l at x holds f_l(x + c_l)): one step pulls from
+// x - c_l, collides and writes at x, 19 + 19 values per update (152 B FP32).
+// Balance: pass A (first derivatives at level n and the vorticity at the three
+// levels) gives the pointwise terms and the stress, vorticity and F / rho;
+// pass B differences products and the stress (e1, e5, z1, z3, H = div sigma / rho);
+// pass C the terms through H (z4 = H . curl omega, z5 = div(H x omega)).  Each
+// field is mean-centred into an FP64 summed-volume table (scans along x, y, z),
+// and every cube's box mean is eight table lookups (each continued
+// periodically through the table's totals).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "lbm_internal.h"
+#include "lbm_reduce.h"
+
+namespace lbm {
+namespace {
+
+using namespace reduce_detail;
+
+constexpr int Q3 = 19;
+__host__ __device__ constexpr int c3(int l, int a) {
+  // rest; +-x, +-y, +-z; (+-1, +-1, 0), (+-1, 0, +-1), (0, +-1, +-1), opposite pairs adjacent
+  constexpr int t[19][3] = {{0, 0, 0},  {1, 0, 0},   {-1, 0, 0}, {0, 1, 0},  {0, -1, 0},
+                            {0, 0, 1},  {0, 0, -1},  {1, 1, 0},  {-1, -1, 0}, {1, -1, 0},
+                            {-1, 1, 0}, {1, 0, 1},   {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+                            {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+  return t[l][a];
+}
+__host__ __device__ constexpr double w3(int l) { return l == 0 ? 1.0 / 3.0 : (l <= 6 ? 1.0 / 18.0 : 1.0 / 36.0); }
+
+__device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// ---- step ---------------------------------------------------------------------------------
+struct Step3 {
+  const void* src;
+  void* dst;
+  const void* fx;
+  const void* fy;
+  const void* fz;
+  double* h[4];  // optional FP64 record of rho, ux, uy, uz (pre-collision, time t)
+  int nx, ny, nz;
+  double omega;
+};
+
+template <typename T, bool FORCE>
+__global__ void __launch_bounds__(256) k3_step(Step3 p) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= p.nx) return;
+  const int y = blockIdx.y, z = blockIdx.z;
+  const int nx = p.nx, ny = p.ny, nz = p.nz;
+  const size_t plane = static_cast<size_t>(nx) * ny * nz;
+  const T* __restrict__ src = static_cast<const T*>(p.src);
+  T* __restrict__ dst = static_cast<T*>(p.dst);
+  T d[Q3];
+#pragma unroll
+  for (int l = 0; l < Q3; ++l) {
+    const int xs = wrap(x - c3(l, 0), nx), ys = wrap(y - c3(l, 1), ny), zs = wrap(z - c3(l, 2), nz);
+    d[l] = src[l * plane + (static_cast<size_t>(zs) * ny + ys) * nx + xs];
+  }
+  T drho = T(0), jx = T(0), jy = T(0), jz = T(0);
+#pragma unroll
+  for (int l = 0; l < Q3; ++l) {
+    drho += d[l];
+    if (c3(l, 0)) jx += c3(l, 0) * d[l];
+    if (c3(l, 1)) jy += c3(l, 1) * d[l];
+    if (c3(l, 2)) jz += c3(l, 2) * d[l];
+  }
+  const T rho = T(1) + drho;
+  const size_t i = (static_cast<size_t>(z) * ny + y) * nx + x;
+  T Fx = T(0), Fy = T(0), Fz = T(0);
+  if constexpr (FORCE) {
+    Fx = static_cast<const T*>(p.fx)[i];
+    Fy = static_cast<const T*>(p.fy)[i];
+    Fz = static_cast<const T*>(p.fz)[i];
+  }
+  const T inv = T(1) / rho;
+  const T ux = (jx + T(0.5) * Fx) * inv, uy = (jy + T(0.5) * Fy) * inv, uz = (jz + T(0.5) * Fz) * inv;
+  const T om = T(p.omega);
+  const T usq15 = T(1.5) * (ux * ux + uy * uy + uz * uz);
+  const T g = T(1) - T(0.5) * om;
+#pragma unroll
+  for (int l = 0; l < Q3; ++l) {
+    const T cx = T(c3(l, 0)), cy = T(c3(l, 1)), cz = T(c3(l, 2));
+    const T cu = cx * ux + cy * uy + cz * uz;
+    const T w = T(w3(l));
+    const T deq = w * (drho + rho * (T(3) * cu + T(4.5) * cu * cu - usq15));
+    T o = d[l] - om * (d[l] - deq);
+    if constexpr (FORCE) {
+      const T gx = T(3) * (cx - ux) + T(9) * cu * cx;
+      const T gy = T(3) * (cy - uy) + T(9) * cu * cy;
+      const T gz = T(3) * (cz - uz) + T(9) * cu * cz;
+      o += g * w * (gx * Fx + gy * Fy + gz * Fz);
+    }
+    dst[l * plane + i] = o;
+  }
+  if (p.h[0]) {
+    p.h[0][i] = double(rho);
+    p.h[1][i] = double(ux);
+    p.h[2][i] = double(uy);
+    p.h[3][i] = double(uz);
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k3_init(T* __restrict__ pop, const double* __restrict__ r0,
+                                               const double* __restrict__ u0, const double* __restrict__ v0,
+                                               const double* __restrict__ w0, int nx, int ny, int nz) {
+  const size_t plane = static_cast<size_t>(nx) * ny * nz;
+  for (size_t i = blockIdx.x * size_t(256) + threadIdx.x; i < plane; i += size_t(gridDim.x) * 256) {
+    const int x = static_cast<int>(i % nx);
+    const int y = static_cast<int>((i / nx) % ny);
+    const int z = static_cast<int>(i / (static_cast<size_t>(nx) * ny));
+    const double rho = r0[i], ux = u0[i], uy = v0[i], uz = w0[i];
+    const double usq15 = 1.5 * (ux * ux + uy * uy + uz * uz);
+#pragma unroll
+    for (int l = 0; l < Q3; ++l) {
+      const double cu = c3(l, 0) * ux + c3(l, 1) * uy + c3(l, 2) * uz;
+      const double dev = w3(l) * ((rho - 1.0) + rho * (3.0 * cu + 4.5 * cu * cu - usq15));
+      const int xs = wrap(x - c3(l, 0), nx), ys = wrap(y - c3(l, 1), ny), zs = wrap(z - c3(l, 2), nz);
+      pop[l * plane + (static_cast<size_t>(zs) * ny + ys) * nx + xs] = T(dev);
+    }
+  }
+}
+
+template <typename T>
+__global__ void k3_to_storage(T* __restrict__ dst, const double* __restrict__ src, size_t n) {
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
+    dst[i] = T(src[i]);
+}
+
+// ---- moments ---------------------------------------------------------------------------------
+constexpr int kS3 = 8;  // mass, momx, momy, momz, energy, max |u|, min rho, non-finite
+template <typename T, bool FORCE>
+__global__ void __launch_bounds__(kRedThreads) k3_moments(const T* __restrict__ pop, const T* __restrict__ fx,
+                                                          const T* __restrict__ fy, const T* __restrict__ fz,
+                                                          int nx, int ny, int nz, double* r, double* u,
+                                                          double* v, double* w, double* partials) {
+  const size_t plane = static_cast<size_t>(nx) * ny * nz;
+  double acc[kS3] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 1e300, 0.0};
+  for (size_t i = blockIdx.x * size_t(kRedThreads) + threadIdx.x; i < plane;
+       i += size_t(gridDim.x) * kRedThreads) {
+    const int x = static_cast<int>(i % nx);
+    const int y = static_cast<int>((i / nx) % ny);
+    const int z = static_cast<int>(i / (static_cast<size_t>(nx) * ny));
+    // the same rounding as the step: moments in the storage type
+    T tr = T(0), tx = T(0), ty = T(0), tz = T(0);
+#pragma unroll
+    for (int l = 0; l < Q3; ++l) {
+      const int xs = wrap(x - c3(l, 0), nx), ys = wrap(y - c3(l, 1), ny), zs = wrap(z - c3(l, 2), nz);
+      const T dl = pop[l * plane + (static_cast<size_t>(zs) * ny + ys) * nx + xs];
+      tr += dl;
+      if (c3(l, 0)) tx += c3(l, 0) * dl;
+      if (c3(l, 1)) ty += c3(l, 1) * dl;
+      if (c3(l, 2)) tz += c3(l, 2) * dl;
+    }
+    const T rho = T(1) + tr;
+    T Fx = T(0), Fy = T(0), Fz = T(0);
+    if constexpr (FORCE) {
+      Fx = fx[i];
+      Fy = fy[i];
+      Fz = fz[i];
+    }
+    const T inv = T(1) / rho;
+    const double R = double(rho);
+    const double U = double((tx + T(0.5) * Fx) * inv), V = double((ty + T(0.5) * Fy) * inv),
+                 Wv = double((tz + T(0.5) * Fz) * inv);
+    if (r) r[i] = R;
+    if (u) u[i] = U;
+    if (v) v[i] = V;
+    if (w) w[i] = Wv;
+    const double s2 = U * U + V * V + Wv * Wv;
+    acc[0] += R;
+    acc[1] += R * U;
+    acc[2] += R * V;
+    acc[3] += R * Wv;
+    acc[4] += 0.5 * R * s2;
+    acc[5] = fmax(acc[5], sqrt(s2));
+    acc[6] = fmin(acc[6], R);
+    acc[7] += (isfinite(R) && isfinite(U) && isfinite(V) && isfinite(Wv)) ? 0.0 : 1.0;
+  }
+  __shared__ double sh[kRedThreads / 64][kS3];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double red[kS3];
+#pragma unroll
+  for (int k = 0; k < kS3; ++k) red[k] = k == 5 ? wave_max(acc[k]) : (k == 6 ? wave_min(acc[k]) : wave_sum(acc[k]));
+  if (lane == 0)
+    for (int k = 0; k < kS3; ++k) sh[wv][k] = red[k];
+  __syncthreads();
+  if (threadIdx.x < kS3) {
+    const int k = threadIdx.x;
+    double a = sh[0][k];
+    for (int q = 1; q < kRedThreads / 64; ++q) a = k == 5 ? fmax(a, sh[q][k]) : (k == 6 ? fmin(a, sh[q][k]) : a + sh[q][k]);
+    partials[blockIdx.x * kS3 + k] = a;
+  }
+}
+
+__global__ void __launch_bounds__(kRedThreads) k3_reduce_scalars(const double* __restrict__ part, int nb,
+                                                                 double* out) {
+  __shared__ double sh[kS3];
+  if (threadIdx.x < kS3) {
+    const int k = threadIdx.x;
+    double a = k == 6 ? 1e300 : 0.0;
+    for (int b = 0; b < nb; ++b) {
+      const double q = part[b * kS3 + k];
+      a = k == 5 ? fmax(a, q) : (k == 6 ? fmin(a, q) : a + q);
+    }
+    sh[k] = a;
+  }
+  __syncthreads();
+  if (threadIdx.x < kS3) out[threadIdx.x] = sh[threadIdx.x];
+}
+
+// ---- balance --------------------------------------------------------------------------------
+constexpr int NT3 = 14;  // lhs_E, e1..e5, lhs_Z, z1..z6, usq
+static_assert(NT3 == LBM3_NTERMS, "term count");
+enum { T3_LHS_E = 0, T3_E1, T3_E2, T3_E3, T3_E4, T3_E5, T3_LHS_Z, T3_Z1, T3_Z2, T3_Z3, T3_Z4, T3_Z5, T3_Z6,
+       T3_USQ };
+// aux: E, Omega, omega (3), sigma xx yy zz xy xz yz, F / rho (3), H (3)
+enum { A3_E = 0, A3_OM2, A3_WX, A3_WY, A3_WZ, A3_SXX, A3_SYY, A3_SZZ, A3_SXY, A3_SXZ, A3_SYZ, A3_GX, A3_GY,
+       A3_GZ, A3_HX, A3_HY, A3_HZ, NA3 };
+
+struct Bal3 {
+  const double* rho[3];
+  const double* u[3][3];  // [level][component]
+  const double* F[3];     // total force at n (or null)
+  double nu;
+  int nx, ny, nz;
+  double* terms;  // [NT3][plane]
+  double* aux;    // [NA3][plane]
+};
+
+struct Site3 {
+  int x, y, z, nx, ny, nz;
+  size_t i;
+  __device__ size_t at(int dx, int dy, int dz) const {
+    return (static_cast<size_t>(wrap(z + dz, nz)) * ny + wrap(y + dy, ny)) * nx + wrap(x + dx, nx);
+  }
+};
+
+// Eq. 18 along axis a of the value that `val(j)` returns at linear index j.
+template <typename Fn>
+__device__ __forceinline__ double fd8(const Site3& s, int a, Fn val) {
+  auto d = [&](int m) {
+    return val(s.at(a == 0 ? m : 0, a == 1 ? m : 0, a == 2 ? m : 0)) -
+           val(s.at(a == 0 ? -m : 0, a == 1 ? -m : 0, a == 2 ? -m : 0));
+  };
+  const double d1 = d(1), d2 = d(2), d3 = d(3), d4 = d(4);
+  return (4.0 * d1 - d2 + (4.0 / 21.0) * d3 - (1.0 / 56.0) * d4) / 5.0;
+}
+
+__device__ __forceinline__ bool site3(int nx, int ny, int nz, Site3& s) {
+  s.x = blockIdx.x * blockDim.x + threadIdx.x;
+  s.y = blockIdx.y;
+  s.z = blockIdx.z;
+  s.nx = nx;
+  s.ny = ny;
+  s.nz = nz;
+  if (s.x >= nx) return false;
+  s.i = (static_cast<size_t>(s.z) * ny + s.y) * nx + s.x;
+  return true;
+}
+
+__global__ void __launch_bounds__(256) k3_bal_a(Bal3 a) {
+  Site3 s;
+  if (!site3(a.nx, a.ny, a.nz, s)) return;
+  const size_t plane = static_cast<size_t>(a.nx) * a.ny * a.nz;
+  const size_t i = s.i;
+  double du[3][3];  // d_j u_i at level n
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const double* f = a.u[2][c];
+      du[c][j] = fd8(s, j, [&](size_t k) { return f[k]; });
+    }
+  double dr[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const double* f = a.rho[2];
+    dr[j] = fd8(s, j, [&](size_t k) { return f[k]; });
+  }
+  double en[3], ens[3];
+  double wn[3];
+#pragma unroll
+  for (int lv = 0; lv < 3; ++lv) {
+    double w[3];
+    if (lv == 2) {
+      w[0] = du[2][1] - du[1][2];
+      w[1] = du[0][2] - du[2][0];
+      w[2] = du[1][0] - du[0][1];
+      wn[0] = w[0];
+      wn[1] = w[1];
+      wn[2] = w[2];
+    } else {
+      const double* ux = a.u[lv][0];
+      const double* uy = a.u[lv][1];
+      const double* uz = a.u[lv][2];
+      w[0] = fd8(s, 1, [&](size_t k) { return uz[k]; }) - fd8(s, 2, [&](size_t k) { return uy[k]; });
+      w[1] = fd8(s, 2, [&](size_t k) { return ux[k]; }) - fd8(s, 0, [&](size_t k) { return uz[k]; });
+      w[2] = fd8(s, 0, [&](size_t k) { return uy[k]; }) - fd8(s, 1, [&](size_t k) { return ux[k]; });
+    }
+    const double vx = a.u[lv][0][i], vy = a.u[lv][1][i], vz = a.u[lv][2][i];
+    en[lv] = 0.5 * a.rho[lv][i] * (vx * vx + vy * vy + vz * vz);
+    ens[lv] = 0.5 * (w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+  }
+  const double r = a.rho[2][i];
+  const double v[3] = {a.u[2][0][i], a.u[2][1][i], a.u[2][2][i]};
+  double F[3] = {0.0, 0.0, 0.0};
+  if (a.F[0]) {
+    F[0] = a.F[0][i];
+    F[1] = a.F[1][i];
+    F[2] = a.F[2][i];
+  }
+  const double nu = a.nu;
+  double sg[3][3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) sg[c][j] = nu * r * (du[c][j] + du[j][c]);
+  double e4 = 0.0, z6 = 0.0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      e4 -= sg[c][j] * du[c][j];
+      z6 += wn[c] * wn[j] * du[c][j];
+    }
+  double* t = a.terms;
+  t[T3_LHS_E * plane + i] = (3.0 * en[2] - 4.0 * en[1] + en[0]) / 2.0;
+  t[T3_E2 * plane + i] = -(v[0] * dr[0] + v[1] * dr[1] + v[2] * dr[2]) / 3.0;
+  t[T3_E3 * plane + i] = v[0] * F[0] + v[1] * F[1] + v[2] * F[2];
+  t[T3_E4 * plane + i] = e4;
+  t[T3_LHS_Z * plane + i] = (3.0 * ens[2] - 4.0 * ens[1] + ens[0]) / 2.0;
+  t[T3_Z2 * plane + i] = -ens[2] * (du[0][0] + du[1][1] + du[2][2]);
+  t[T3_Z6 * plane + i] = z6;
+  t[T3_USQ * plane + i] = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+  double* x = a.aux;
+  x[A3_E * plane + i] = en[2];
+  x[A3_OM2 * plane + i] = ens[2];
+  x[A3_WX * plane + i] = wn[0];
+  x[A3_WY * plane + i] = wn[1];
+  x[A3_WZ * plane + i] = wn[2];
+  x[A3_SXX * plane + i] = sg[0][0];
+  x[A3_SYY * plane + i] = sg[1][1];
+  x[A3_SZZ * plane + i] = sg[2][2];
+  x[A3_SXY * plane + i] = sg[0][1];
+  x[A3_SXZ * plane + i] = sg[0][2];
+  x[A3_SYZ * plane + i] = sg[1][2];
+  x[A3_GX * plane + i] = F[0] / r;
+  x[A3_GY * plane + i] = F[1] / r;
+  x[A3_GZ * plane + i] = F[2] / r;
+}
+
+__device__ __forceinline__ int sig_index(int c, int j) {
+  // symmetric stress component (c, j) in the aux layout
+  if (c == j) return A3_SXX + c;
+  const int lo = c < j ? c : j, hi = c < j ? j : c;
+  return lo == 0 ? (hi == 1 ? A3_SXY : A3_SXZ) : A3_SYZ;
+}
+
+__global__ void __launch_bounds__(256) k3_bal_b(Bal3 a) {
+  Site3 s;
+  if (!site3(a.nx, a.ny, a.nz, s)) return;
+  const size_t plane = static_cast<size_t>(a.nx) * a.ny * a.nz;
+  const size_t i = s.i;
+  const double* ax = a.aux;
+  const double* const* u = a.u[2];
+  double e1 = 0.0, e5 = 0.0, z1 = 0.0;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const double* uj = u[j];
+    e1 -= fd8(s, j, [&](size_t k) { return ax[A3_E * plane + k] * uj[k]; });
+    z1 -= fd8(s, j, [&](size_t k) { return ax[A3_OM2 * plane + k] * uj[k]; });
+    const double* s0 = ax + sig_index(0, j) * plane;
+    const double* s1 = ax + sig_index(1, j) * plane;
+    const double* s2 = ax + sig_index(2, j) * plane;
+    e5 += fd8(s, j, [&](size_t k) { return u[0][k] * s0[k] + u[1][k] * s1[k] + u[2][k] * s2[k]; });
+  }
+  // curl(F / rho)
+  const double* gx = ax + A3_GX * plane;
+  const double* gy = ax + A3_GY * plane;
+  const double* gz = ax + A3_GZ * plane;
+  const double cg[3] = {fd8(s, 1, [&](size_t k) { return gz[k]; }) - fd8(s, 2, [&](size_t k) { return gy[k]; }),
+                        fd8(s, 2, [&](size_t k) { return gx[k]; }) - fd8(s, 0, [&](size_t k) { return gz[k]; }),
+                        fd8(s, 0, [&](size_t k) { return gy[k]; }) - fd8(s, 1, [&](size_t k) { return gx[k]; })};
+  const double w[3] = {ax[A3_WX * plane + i], ax[A3_WY * plane + i], ax[A3_WZ * plane + i]};
+  const double r = a.rho[2][i];
+  double h[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    double dv = 0.0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const double* sc = ax + sig_index(c, j) * plane;
+      dv += fd8(s, j, [&](size_t k) { return sc[k]; });
+    }
+    h[c] = dv / r;
+  }
+  double* t = a.terms;
+  t[T3_E1 * plane + i] = e1;
+  t[T3_E5 * plane + i] = e5;
+  t[T3_Z1 * plane + i] = z1;
+  t[T3_Z3 * plane + i] = w[0] * cg[0] + w[1] * cg[1] + w[2] * cg[2];
+  double* x = a.aux;
+  x[A3_HX * plane + i] = h[0];
+  x[A3_HY * plane + i] = h[1];
+  x[A3_HZ * plane + i] = h[2];
+}
+
+__global__ void __launch_bounds__(256) k3_bal_c(Bal3 a) {
+  Site3 s;
+  if (!site3(a.nx, a.ny, a.nz, s)) return;
+  const size_t plane = static_cast<size_t>(a.nx) * a.ny * a.nz;
+  const size_t i = s.i;
+  const double* ax = a.aux;
+  const double* wx = ax + A3_WX * plane;
+  const double* wy = ax + A3_WY * plane;
+  const double* wz = ax + A3_WZ * plane;
+  const double* hx = ax + A3_HX * plane;
+  const double* hy = ax + A3_HY * plane;
+  const double* hz = ax + A3_HZ * plane;
+  const double cw[3] = {fd8(s, 1, [&](size_t k) { return wz[k]; }) - fd8(s, 2, [&](size_t k) { return wy[k]; }),
+                        fd8(s, 2, [&](size_t k) { return wx[k]; }) - fd8(s, 0, [&](size_t k) { return wz[k]; }),
+                        fd8(s, 0, [&](size_t k) { return wy[k]; }) - fd8(s, 1, [&](size_t k) { return wx[k]; })};
+  // div(H x omega), (H x omega) = (hy wz - hz wy, hz wx - hx wz, hx wy - hy wx)
+  const double z5 = fd8(s, 0, [&](size_t k) { return hy[k] * wz[k] - hz[k] * wy[k]; }) +
+                    fd8(s, 1, [&](size_t k) { return hz[k] * wx[k] - hx[k] * wz[k]; }) +
+                    fd8(s, 2, [&](size_t k) { return hx[k] * wy[k] - hy[k] * wx[k]; });
+  double* t = a.terms;
+  t[T3_Z4 * plane + i] = hx[i] * cw[0] + hy[i] * cw[1] + hz[i] * cw[2];
+  t[T3_Z5 * plane + i] = z5;
+}
+
+// ---- summed-volume tables ---------------------------------------------------------------------
+// P[f][z][y][x] over (nz+1)(ny+1)(nx+1): sum of (g_f - mean_f) over z' < z, y' < y, x' < x.
+struct Vol {
+  double* P;
+  const double* means;
+  int nx, ny, nz;
+  __host__ __device__ size_t sx() const { return static_cast<size_t>(nx) + 1; }
+  __host__ __device__ size_t sy() const { return (static_cast<size_t>(ny) + 1) * sx(); }
+  __host__ __device__ size_t sf() const { return (static_cast<size_t>(nz) + 1) * sy(); }
+  __device__ double get(int f, int z, int y, int x) const { return P[f * sf() + z * sy() + y * sx() + x]; }
+  // the periodic continuation to 0 <= z <= 2 nz (and y, x): each axis index is its
+  // remainder plus, past the grid, one full period
+  __device__ double Q(int f, int z, int y, int x) const {
+    const int zs[2] = {z > nz ? z - nz : z, nz}, ys[2] = {y > ny ? y - ny : y, ny},
+              xs[2] = {x > nx ? x - nx : x, nx};
+    const int cz = z > nz ? 2 : 1, cy = y > ny ? 2 : 1, cx = x > nx ? 2 : 1;
+    double v = 0.0;
+    for (int a = 0; a < cz; ++a)
+      for (int b = 0; b < cy; ++b)
+        for (int c = 0; c < cx; ++c) v += get(f, zs[a], ys[b], xs[c]);
+    return v;
+  }
+  __device__ double box_mean(int f, int x0, int y0, int z0, int L) const {
+    const int x1 = x0 + L, y1 = y0 + L, z1 = z0 + L;
+    const double s = Q(f, z1, y1, x1) - Q(f, z0, y1, x1) - Q(f, z1, y0, x1) - Q(f, z1, y1, x0) +
+                     Q(f, z0, y0, x1) + Q(f, z0, y1, x0) + Q(f, z1, y0, x0) - Q(f, z0, y0, x0);
+    return means[f] + s / (double(L) * double(L) * double(L));
+  }
+};
+
+// x scan: one workgroup per (y, z, field) row, coalesced 256-value segments.
+__global__ void __launch_bounds__(256) k3_sat_x(const double* __restrict__ g, Vol v) {
+  __shared__ double wsum[4];
+  const int y = blockIdx.x, z = blockIdx.y, f = blockIdx.z;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const size_t plane = static_cast<size_t>(v.nx) * v.ny * v.nz;
+  const double mean = v.means[f];
+  const double* row = g + f * plane + (static_cast<size_t>(z) * v.ny + y) * v.nx;
+  double* out = v.P + f * v.sf() + (z + 1) * v.sy() + (y + 1) * v.sx();
+  double carry = 0.0;
+  for (int x0 = 0; x0 < v.nx; x0 += 256) {
+    const int x = x0 + threadIdx.x;
+    double val = x < v.nx ? row[x] - mean : 0.0;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const double t = __shfl_up(val, off, 64);
+      if (lane >= off) val += t;
+    }
+    if (lane == 63) wsum[wv] = val;
+    __syncthreads();
+    double before = 0.0;
+    for (int w = 0; w < wv; ++w) before += wsum[w];
+    const double total = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
+    if (x < v.nx) out[x + 1] = carry + (before + val);
+    carry += total;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = 0.0;
+}
+
+// zero faces: z = 0 planes and y = 0 rows of every field
+__global__ void k3_sat_faces(Vol v, int nf) {
+  const size_t face = v.sy();                                 // one z = 0 plane
+  const size_t rows = static_cast<size_t>(v.nz) * v.sx();     // y = 0 rows of z >= 1
+  const size_t per = face + rows;
+  for (size_t k = blockIdx.x * size_t(blockDim.x) + threadIdx.x; k < per * nf; k += size_t(gridDim.x) * blockDim.x) {
+    const size_t f = k / per, r = k % per;
+    double* base = v.P + f * v.sf();
+    if (r < face)
+      base[r] = 0.0;
+    else {
+      const size_t q = r - face;
+      base[(q / v.sx() + 1) * v.sy() + q % v.sx()] = 0.0;
+    }
+  }
+}
+
+// running sums along y, then along z: one thread per x column (coalesced), sequential in y / z
+__global__ void __launch_bounds__(256) k3_sat_y(Vol v) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x > v.nx) return;
+  const int z = blockIdx.y + 1, f = blockIdx.z;
+  double* col = v.P + f * v.sf() + z * v.sy() + x;
+  double run = 0.0;
+  for (int y = 1; y <= v.ny; ++y) {
+    run += col[y * v.sx()];
+    col[y * v.sx()] = run;
+  }
+}
+
+__global__ void __launch_bounds__(256) k3_sat_z(Vol v) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x > v.nx) return;
+  const int y = blockIdx.y, f = blockIdx.z;
+  double* col = v.P + f * v.sf() + y * v.sx() + x;
+  double run = 0.0;
+  for (int z = 1; z <= v.nz; ++z) {
+    run += col[z * v.sy()];
+    col[z * v.sy()] = run;
+  }
+}
+
+// ---- windows -----------------------------------------------------------------------------------
+constexpr int kW3Threads = 256;
+constexpr int kW3MaxBlocks = 2048;
+constexpr int kW3Vals = 18;  // 3 quantities x (n, mean, m2, min, max, nan)
+
+__device__ void w3_errors(const double (&m)[NT3], double& dE, double& dZ, double& ma) {
+  const double rE = (((m[T3_E1] + m[T3_E2]) + m[T3_E3]) + m[T3_E4]) + m[T3_E5];
+  const double denE = fmax(fmax(fmax(fabs(m[T3_E1]), fabs(m[T3_E2])), fmax(fabs(m[T3_E3]), fabs(m[T3_E4]))),
+                           fabs(m[T3_E5]));
+  const double rZ = ((((m[T3_Z1] + m[T3_Z2]) + m[T3_Z3]) + m[T3_Z4]) + m[T3_Z5]) + m[T3_Z6];
+  const double denZ = fmax(fmax(fmax(fabs(m[T3_Z1]), fabs(m[T3_Z2])), fmax(fabs(m[T3_Z3]), fabs(m[T3_Z4]))),
+                           fmax(fabs(m[T3_Z5]), fabs(m[T3_Z6])));
+  dE = denE > 0.0 ? fabs(rE - m[T3_LHS_E]) / denE : __builtin_nan("");
+  dZ = denZ > 0.0 ? fabs(rZ - m[T3_LHS_Z]) / denZ : __builtin_nan("");
+  ma = sqrt(m[T3_USQ]) * 1.7320508075688772;  // / c_s, c_s = 1/sqrt(3)
+}
+
+// Running count, mean and sum of squared deviations (Welford), merged pairwise
+// by Chan's formula; min, max and the count of NaN values beside them.
+struct Run3 {
+  double n, mean, m2, mn, mx, nan;
+  __device__ void init() {
+    n = mean = m2 = nan = 0.0;
+    mn = 1e300;
+    mx = -1e300;
+  }
+  __device__ void add(double v) {
+    if (!isfinite(v)) {
+      nan += 1.0;
+      return;
+    }
+    n += 1.0;
+    const double d = v - mean;
+    mean += d / n;
+    m2 += d * (v - mean);
+    mn = fmin(mn, v);
+    mx = fmax(mx, v);
+  }
+  __device__ void merge(const Run3& b) {
+    if (b.n > 0.0) {
+      const double nn = n + b.n, d = b.mean - mean;
+      mean += d * (b.n / nn);
+      m2 += b.m2 + d * d * (n * b.n / nn);
+      n = nn;
+      mn = fmin(mn, b.mn);
+      mx = fmax(mx, b.mx);
+    }
+    nan += b.nan;
+  }
+  __device__ void load(const double* p) { n = p[0], mean = p[1], m2 = p[2], mn = p[3], mx = p[4], nan = p[5]; }
+  __device__ void store(double* p) const { p[0] = n, p[1] = mean, p[2] = m2, p[3] = mn, p[4] = mx, p[5] = nan; }
+};
+
+__global__ void __launch_bounds__(kW3Threads) k3_windows(Vol v, int L, size_t count, double* partials) {
+  Run3 r[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) r[q].init();
+  for (size_t k = blockIdx.x * size_t(kW3Threads) + threadIdx.x; k < count; k += size_t(gridDim.x) * kW3Threads) {
+    const int x0 = static_cast<int>(k % v.nx);
+    const int y0 = static_cast<int>((k / v.nx) % v.ny);
+    const int z0 = static_cast<int>(k / (static_cast<size_t>(v.nx) * v.ny));
+    double m[NT3];
+    for (int f = 0; f < NT3; ++f) m[f] = v.box_mean(f, x0, y0, z0, L);
+    double val[3];
+    w3_errors(m, val[0], val[1], val[2]);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) r[q].add(val[q]);
+  }
+  // wavefront: butterfly merges in a lane-independent order (both lanes of a pair end equal)
+#pragma unroll
+  for (int q = 0; q < 3; ++q)
+    for (int off = 1; off < 64; off <<= 1) {
+      Run3 o;
+      o.n = __shfl_xor(r[q].n, off, 64);
+      o.mean = __shfl_xor(r[q].mean, off, 64);
+      o.m2 = __shfl_xor(r[q].m2, off, 64);
+      o.mn = __shfl_xor(r[q].mn, off, 64);
+      o.mx = __shfl_xor(r[q].mx, off, 64);
+      o.nan = __shfl_xor(r[q].nan, off, 64);
+      if ((threadIdx.x & off) == 0) {
+        r[q].merge(o);
+      } else {
+        o.merge(r[q]);
+        r[q] = o;
+      }
+    }
+  __shared__ double sh[kW3Threads / 64][kW3Vals];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0)
+    for (int q = 0; q < 3; ++q) r[q].store(&sh[wv][q * 6]);
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    const int q = threadIdx.x;
+    Run3 acc, b;
+    acc.load(&sh[0][q * 6]);
+    for (int w = 1; w < kW3Threads / 64; ++w) {
+      b.load(&sh[w][q * 6]);
+      acc.merge(b);
+    }
+    acc.store(partials + static_cast<size_t>(blockIdx.x) * kW3Vals + q * 6);
+  }
+}
+
+__global__ void __launch_bounds__(64) k3_windows_final(const double* __restrict__ partials, int nb, double* out) {
+  if (threadIdx.x >= 3) return;
+  const int q = threadIdx.x;
+  Run3 acc, b;
+  acc.init();
+  for (int k = 0; k < nb; ++k) {
+    b.load(partials + static_cast<size_t>(k) * kW3Vals + q * 6);
+    acc.merge(b);
+  }
+  acc.store(out + q * 6);
+}
+
+int grid1(size_t n, int cap) { return static_cast<int>(std::max<size_t>(1, std::min<size_t>(cap, (n + 255) / 256))); }
+
+}  // namespace
+}  // namespace lbm
+
+// ==== handle ====================================================================================
+using namespace lbm;
+
+struct lbm3_ctx_s {
+  lbm3_config cfg{};
+  hipStream_t stream = nullptr;
+  void* pop[2] = {nullptr, nullptr};
+  int cur = 0;
+  void* f[3] = {nullptr, nullptr, nullptr};  // force, storage type
+  double* f64[3] = {nullptr, nullptr, nullptr};
+  double* hist[2][4] = {{nullptr}};
+  int64_t hist_t[2] = {-1, -1};
+  double* mom[4] = {nullptr};
+  double* partials = nullptr;
+  double* scalars = nullptr;
+  double* terms = nullptr;
+  double* aux = nullptr;
+  double* sat = nullptr;
+  double* means = nullptr;
+  double* wpart = nullptr;
+  double* wstat = nullptr;
+  int64_t t = 0;
+  size_t plane = 0;
+};
+
+namespace {
+
+struct Layout3 {
+  void* pop[2];
+  void* f[3];
+  double* f64[3];
+  double* hist[2][4];
+  double* mom[4];
+  double *partials, *scalars, *terms, *aux, *sat, *means, *wpart, *wstat;
+  size_t bytes;
+};
+
+int moment_blocks3(size_t plane) { return grid1(plane, 1024); }
+
+Layout3 carve3(const lbm3_config& c, void* base, size_t cap) {
+  Carver cv(base, cap);
+  const size_t plane = static_cast<size_t>(c.nx) * c.ny * c.nz;
+  const size_t es = c.dtype == LBM_F64 ? 8 : 4;
+  Layout3 l{};
+  for (int b = 0; b < 2; ++b) l.pop[b] = cv.take<char>(Q3 * plane * es);
+  if (c.has_force)
+    for (int k = 0; k < 3; ++k) {
+      l.f[k] = cv.take<char>(plane * es);
+      l.f64[k] = cv.take<double>(plane);
+    }
+  for (int s = 0; s < 2; ++s)
+    for (int k = 0; k < 4; ++k) l.hist[s][k] = cv.take<double>(plane);
+  for (int k = 0; k < 4; ++k) l.mom[k] = cv.take<double>(plane);
+  l.partials = cv.take<double>(static_cast<size_t>(moment_blocks3(plane)) * kS3 + 8);
+  l.scalars = cv.take<double>(8);
+  if (c.with_balance) {
+    const size_t vol = (static_cast<size_t>(c.nx) + 1) * (c.ny + 1) * (c.nz + 1);
+    l.terms = cv.take<double>(NT3 * plane);
+    l.aux = cv.take<double>(NA3 * plane);
+    l.sat = cv.take<double>(NT3 * vol);
+    l.means = cv.take<double>(16);
+    l.wpart = cv.take<double>(std::max<size_t>(static_cast<size_t>(kW3MaxBlocks) * kW3Vals, NT3 * 512));
+    l.wstat = cv.take<double>(static_cast<size_t>(kMaxSizes) * kW3Vals);
+  }
+  l.bytes = cv.used + 256;
+  return l;
+}
+
+int validate3(const lbm3_config* c) {
+  if (!c) return fail(LBM_E_INVALID, "config is NULL");
+  if (c->nx < 16 || c->ny < 16 || c->nz < 16 || c->nx > 4096 || c->ny > 4096 || c->nz > 4096)
+    return fail(LBM_E_INVALID, "3D grid %d x %d x %d outside [16, 4096]^3", c->nx, c->ny, c->nz);
+  if (c->ny > 65535 || c->nz > 65535) return fail(LBM_E_INVALID, "grid too large");
+  if (c->dtype != LBM_F32 && c->dtype != LBM_F64) return fail(LBM_E_INVALID, "dtype must be LBM_F32 or LBM_F64");
+  if (!(c->tau > 0.5) || !std::isfinite(c->tau)) return fail(LBM_E_INVALID, "tau must be a finite number > 0.5");
+  if (c->has_force != 0 && c->has_force != 1) return fail(LBM_E_INVALID, "has_force must be 0 or 1");
+  if (c->with_balance != 0 && c->with_balance != 1) return fail(LBM_E_INVALID, "with_balance must be 0 or 1");
+  return LBM_OK;
+}
+
+int launch3_step(lbm3_ctx_s* c, bool record) {
+  Step3 p{};
+  p.src = c->pop[c->cur];
+  p.dst = c->pop[1 - c->cur];
+  p.fx = c->f[0];
+  p.fy = c->f[1];
+  p.fz = c->f[2];
+  const int slot = static_cast<int>(c->t & 1);
+  if (record)
+    for (int k = 0; k < 4; ++k) p.h[k] = c->hist[slot][k];
+  p.nx = c->cfg.nx;
+  p.ny = c->cfg.ny;
+  p.nz = c->cfg.nz;
+  p.omega = 1.0 / c->cfg.tau;
+  const dim3 grid((p.nx + 255) / 256, p.ny, p.nz), block(256);
+  const bool force = c->cfg.has_force != 0;
+  if (c->cfg.dtype == LBM_F64) {
+    if (force)
+      hipLaunchKernelGGL((k3_step<double, true>), grid, block, 0, c->stream, p);
+    else
+      hipLaunchKernelGGL((k3_step<double, false>), grid, block, 0, c->stream, p);
+  } else {
+    if (force)
+      hipLaunchKernelGGL((k3_step<float, true>), grid, block, 0, c->stream, p);
+    else
+      hipLaunchKernelGGL((k3_step<float, false>), grid, block, 0, c->stream, p);
+  }
+  LBM_HIP(hipGetLastError());
+  if (record) c->hist_t[slot] = c->t;
+  c->cur ^= 1;
+  c->t += 1;
+  return LBM_OK;
+}
+
+int moments3(lbm3_ctx_s* c, double* r, double* u, double* v, double* w, double* scalars) {
+  const size_t plane = c->plane;
+  const int nb = moment_blocks3(plane);
+  const int nx = c->cfg.nx, ny = c->cfg.ny, nz = c->cfg.nz;
+  const bool force = c->cfg.has_force != 0;
+  if (c->cfg.dtype == LBM_F64) {
+    const double* pop = static_cast<const double*>(c->pop[c->cur]);
+    if (force)
+      hipLaunchKernelGGL((k3_moments<double, true>), dim3(nb), dim3(kRedThreads), 0, c->stream, pop,
+                         static_cast<const double*>(c->f[0]), static_cast<const double*>(c->f[1]),
+                         static_cast<const double*>(c->f[2]), nx, ny, nz, r, u, v, w, c->partials);
+    else
+      hipLaunchKernelGGL((k3_moments<double, false>), dim3(nb), dim3(kRedThreads), 0, c->stream, pop, nullptr,
+                         nullptr, nullptr, nx, ny, nz, r, u, v, w, c->partials);
+  } else {
+    const float* pop = static_cast<const float*>(c->pop[c->cur]);
+    if (force)
+      hipLaunchKernelGGL((k3_moments<float, true>), dim3(nb), dim3(kRedThreads), 0, c->stream, pop,
+                         static_cast<const float*>(c->f[0]), static_cast<const float*>(c->f[1]),
+                         static_cast<const float*>(c->f[2]), nx, ny, nz, r, u, v, w, c->partials);
+    else
+      hipLaunchKernelGGL((k3_moments<float, false>), dim3(nb), dim3(kRedThreads), 0, c->stream, pop, nullptr,
+                         nullptr, nullptr, nx, ny, nz, r, u, v, w, c->partials);
+  }
+  LBM_HIP(hipGetLastError());
+  if (!scalars) return LBM_OK;
+  hipLaunchKernelGGL(k3_reduce_scalars, dim3(1), dim3(kRedThreads), 0, c->stream, c->partials, nb, c->scalars);
+  LBM_HIP(hipGetLastError());
+  LBM_HIP(hipMemcpyAsync(scalars, c->scalars, kS3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  LBM_HIP(hipStreamSynchronize(c->stream));
+  scalars[8] = static_cast<double>(c->t);
+  if (scalars[7] > 0.0 || !(scalars[6] > 0.0))
+    return fail(LBM_E_DIVERGED, "3D run diverged: %.0f non-finite sites, min rho %g at step %lld", scalars[7],
+                scalars[6], static_cast<long long>(c->t));
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm3_workspace_bytes(const lbm3_config* cfg, size_t* bytes) {
+  if (int rc = validate3(cfg)) return rc;
+  if (!bytes) return fail(LBM_E_INVALID, "bytes is NULL");
+  *bytes = carve3(*cfg, nullptr, 0).bytes;
+  return LBM_OK;
+}
+
+int lbm3_init(const lbm3_config* cfg, void* ws, size_t ws_bytes, const double* rho0, const double* ux0,
+              const double* uy0, const double* uz0, const double* fx, const double* fy, const double* fz,
+              lbm3_ctx* out) {
+  if (int rc = validate3(cfg)) return rc;
+  if (!out) return fail(LBM_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!ws || reinterpret_cast<uintptr_t>(ws) % 256 != 0)
+    return fail(LBM_E_INVALID, "workspace must be non-NULL and 256-byte aligned");
+  if (!rho0 || !ux0 || !uy0 || !uz0) return fail(LBM_E_INVALID, "initial fields must not be NULL");
+  if (cfg->has_force && (!fx || !fy || !fz)) return fail(LBM_E_INVALID, "has_force = 1 needs fx, fy, fz");
+  if (!cfg->has_force && (fx || fy || fz)) return fail(LBM_E_INVALID, "force given but has_force = 0");
+  Layout3 l = carve3(*cfg, nullptr, 0);
+  if (ws_bytes < l.bytes) return fail(LBM_E_NOMEM, "workspace %zu bytes < %zu required", ws_bytes, l.bytes);
+  l = carve3(*cfg, ws, ws_bytes);
+  lbm3_ctx_s* c = new lbm3_ctx_s();
+  c->cfg = *cfg;
+  c->stream = static_cast<hipStream_t>(cfg->stream);
+  c->plane = static_cast<size_t>(cfg->nx) * cfg->ny * cfg->nz;
+  for (int b = 0; b < 2; ++b) c->pop[b] = l.pop[b];
+  for (int k = 0; k < 3; ++k) {
+    c->f[k] = l.f[k];
+    c->f64[k] = l.f64[k];
+  }
+  for (int s = 0; s < 2; ++s)
+    for (int k = 0; k < 4; ++k) c->hist[s][k] = l.hist[s][k];
+  for (int k = 0; k < 4; ++k) c->mom[k] = l.mom[k];
+  c->partials = l.partials;
+  c->scalars = l.scalars;
+  c->terms = l.terms;
+  c->aux = l.aux;
+  c->sat = l.sat;
+  c->means = l.means;
+  c->wpart = l.wpart;
+  c->wstat = l.wstat;
+  const int g = grid1(c->plane, 4096);
+  if (cfg->dtype == LBM_F64)
+    hipLaunchKernelGGL(k3_init<double>, dim3(g), dim3(256), 0, c->stream, static_cast<double*>(c->pop[0]), rho0,
+                       ux0, uy0, uz0, cfg->nx, cfg->ny, cfg->nz);
+  else
+    hipLaunchKernelGGL(k3_init<float>, dim3(g), dim3(256), 0, c->stream, static_cast<float*>(c->pop[0]), rho0,
+                       ux0, uy0, uz0, cfg->nx, cfg->ny, cfg->nz);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && cfg->has_force) {
+    const double* src[3] = {fx, fy, fz};
+    for (int k = 0; k < 3 && e == hipSuccess; ++k) {
+      if (cfg->dtype == LBM_F64)
+        hipLaunchKernelGGL(k3_to_storage<double>, dim3(g), dim3(256), 0, c->stream, static_cast<double*>(c->f[k]),
+                           src[k], c->plane);
+      else
+        hipLaunchKernelGGL(k3_to_storage<float>, dim3(g), dim3(256), 0, c->stream, static_cast<float*>(c->f[k]),
+                           src[k], c->plane);
+      e = hipGetLastError();
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(c->f64[k], src[k], c->plane * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+    }
+  }
+  if (e != hipSuccess) {
+    delete c;
+    return hip_fail(e, "lbm3_init");
+  }
+  *out = c;
+  return LBM_OK;
+}
+
+int lbm3_step(lbm3_ctx c, int64_t n) {
+  if (!c) return fail(LBM_E_INVALID, "ctx is NULL");
+  if (n < 0) return fail(LBM_E_INVALID, "n must be >= 0");
+  for (int64_t k = 0; k < n; ++k)
+    if (int rc = launch3_step(c, k >= n - 2)) return rc;
+  return LBM_OK;
+}
+
+int lbm3_moments(lbm3_ctx c, double* rho, double* ux, double* uy, double* uz, double* scalars9) {
+  if (!c) return fail(LBM_E_INVALID, "ctx is NULL");
+  return moments3(c, rho, ux, uy, uz, scalars9);
+}
+
+int lbm3_time(lbm3_ctx c, int64_t* t) {
+  if (!c || !t) return fail(LBM_E_INVALID, "NULL argument");
+  *t = c->t;
+  return LBM_OK;
+}
+
+int lbm3_subvolume_balance(lbm3_ctx c, const int32_t* sizes, int32_t nsizes, lbm_balance_stats* out,
+                           double* term_fields) {
+  if (!c) return fail(LBM_E_INVALID, "ctx is NULL");
+  if (!c->cfg.with_balance) return fail(LBM_E_STATE, "handle was created with with_balance = 0");
+  if (nsizes < 0 || nsizes > kMaxSizes) return fail(LBM_E_INVALID, "nsizes must be in [0, %d]", kMaxSizes);
+  if (nsizes > 0 && (!sizes || !out)) return fail(LBM_E_INVALID, "sizes/out must not be NULL");
+  const int nx = c->cfg.nx, ny = c->cfg.ny, nz = c->cfg.nz;
+  const int m = std::min(nx, std::min(ny, nz));
+  for (int k = 0; k < nsizes; ++k)
+    if (sizes[k] < 1 || sizes[k] > m) return fail(LBM_E_INVALID, "box size %d outside [1, %d]", sizes[k], m);
+  const int64_t t = c->t;
+  if (t < 2 || c->hist_t[(t - 1) & 1] != t - 1 || c->hist_t[(t - 2) & 1] != t - 2)
+    return fail(LBM_E_STATE, "balance at t = %lld needs the moments of steps t-1 and t-2",
+                static_cast<long long>(t));
+  double sc[9];
+  if (int rc = moments3(c, c->mom[0], c->mom[1], c->mom[2], c->mom[3], sc)) return rc;
+  hipStream_t s = c->stream;
+  const size_t plane = c->plane;
+  Bal3 a{};
+  const int s2 = static_cast<int>((t - 2) & 1), s1 = static_cast<int>((t - 1) & 1);
+  a.rho[0] = c->hist[s2][0];
+  a.rho[1] = c->hist[s1][0];
+  a.rho[2] = c->mom[0];
+  for (int k = 0; k < 3; ++k) {
+    a.u[0][k] = c->hist[s2][k + 1];
+    a.u[1][k] = c->hist[s1][k + 1];
+    a.u[2][k] = c->mom[k + 1];
+    a.F[k] = c->cfg.has_force ? c->f64[k] : nullptr;
+  }
+  a.nu = (c->cfg.tau - 0.5) / 3.0;
+  a.nx = nx;
+  a.ny = ny;
+  a.nz = nz;
+  a.terms = c->terms;
+  a.aux = c->aux;
+  const dim3 grid((nx + 255) / 256, ny, nz), block(256);
+  hipLaunchKernelGGL(k3_bal_a, grid, block, 0, s, a);
+  LBM_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k3_bal_b, grid, block, 0, s, a);
+  LBM_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k3_bal_c, grid, block, 0, s, a);
+  LBM_HIP(hipGetLastError());
+  if (term_fields)
+    LBM_HIP(hipMemcpyAsync(term_fields, c->terms, NT3 * plane * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (int rc = field_means(c->terms, NT3, nx, ny * nz, c->wpart, c->means, s)) return rc;
+  Vol v{c->sat, c->means, nx, ny, nz};
+  hipLaunchKernelGGL(k3_sat_x, dim3(ny, nz, NT3), dim3(256), 0, s, c->terms, v);
+  LBM_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k3_sat_faces, dim3(grid1(v.sy() * NT3, 4096)), dim3(256), 0, s, v, NT3);
+  LBM_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k3_sat_y, dim3((nx + 1 + 255) / 256, nz, NT3), dim3(256), 0, s, v);
+  LBM_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k3_sat_z, dim3((nx + 1 + 255) / 256, ny + 1, NT3), dim3(256), 0, s, v);
+  LBM_HIP(hipGetLastError());
+  for (int k = 0; k < nsizes; ++k) {
+    const int L = sizes[k];
+    const size_t count = (L == nx && L == ny && L == nz) ? 1 : plane;
+    const int nb = grid1(count, kW3MaxBlocks);
+    hipLaunchKernelGGL(k3_windows, dim3(nb), dim3(kW3Threads), 0, s, v, L, count, c->wpart);
+    LBM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k3_windows_final, dim3(1), dim3(64), 0, s, c->wpart, nb, c->wstat + k * kW3Vals);
+    LBM_HIP(hipGetLastError());
+  }
+  std::vector<double> st(static_cast<size_t>(nsizes) * kW3Vals);
+  if (nsizes > 0)
+    LBM_HIP(hipMemcpyAsync(st.data(), c->wstat, st.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  LBM_HIP(hipStreamSynchronize(s));
+  for (int k = 0; k < nsizes; ++k) {
+    lbm_balance_stats& o = out[k];
+    o = lbm_balance_stats{};
+    o.L = sizes[k];
+    auto fill = [&](int q, int64_t& cnt, int64_t* nan, double& mean, double& sd, double& mn, double& mx) {
+      const double* r = st.data() + static_cast<size_t>(k) * kW3Vals + q * 6;
+      cnt = static_cast<int64_t>(r[0]);
+      if (nan) *nan = static_cast<int64_t>(r[5]);
+      if (cnt > 0) {
+        mean = r[1];
+        sd = std::sqrt(r[2] / r[0]);
+        mn = r[3];
+        mx = r[4];
+      } else {
+        mean = sd = mn = mx = NAN;
+      }
+    };
+    fill(0, o.count_dE, &o.nan_dE, o.mean_dE, o.std_dE, o.min_dE, o.max_dE);
+    fill(1, o.count_dZ, &o.nan_dZ, o.mean_dZ, o.std_dZ, o.min_dZ, o.max_dZ);
+    fill(2, o.count_Ma, nullptr, o.mean_Ma, o.std_Ma, o.min_Ma, o.max_Ma);
+  }
+  return LBM_OK;
+}
+
+int lbm3_destroy(lbm3_ctx c) {
+  if (!c) return LBM_OK;
+  (void)hipStreamSynchronize(c->stream);
+  delete c;
+  return LBM_OK;
+}
+
+}  // extern "C"

@@ -6,6 +6,7 @@ Classes / functions
 Simulation      one periodic D2Q9 grid (lbm_init / lbm_step / lbm_moments /
                 lbm_subvolume_balance and the checkpoint, tuning and timing calls)
 balance_fields  the sub-volume balance of caller-given (rho, u) levels
+Simulation3D    one periodic D3Q19 grid with the 3D balance (lbm3_*)
 """
 from __future__ import annotations
 
@@ -483,3 +484,91 @@ def set_tuned_tile(nx, ny, dtype="f32", forced=False, layout="rows", tile=(512, 
     t = L.Tile(*[int(v) for v in tile])
     L.check(lib.lbm_set_tuned_tile(C.byref(cfg), C.byref(t)), "lbm_set_tuned_tile")
 
+
+
+class Simulation3D:
+    """One periodic D3Q19 BGK grid on the current GPU (the method of Sec. 1 in three
+    dimensions, with the 3D balance of Sec. 2 and its vortex-stretching term).
+
+    rho0, ux0, uy0, uz0: [nz, ny, nx] initial fields; fx, fy, fz: optional static force;
+    dtype: "f32" or "f64" population storage.
+    """
+
+    def __init__(self, rho0, ux0, uy0, uz0, tau, dtype="f32", fx=None, fy=None, fz=None,
+                 with_balance=False, device="cuda", stream=None):
+        _require_gpu()
+        self._lib = L.load()
+        self.device = torch.device(device)
+        r, vx, vy, vz = (_dev64(a, self.device) for a in (rho0, ux0, uy0, uz0))
+        self.nz, self.ny, self.nx = r.shape
+        self.dtype = {"f32": L.LBM_F32, "f64": L.LBM_F64}[dtype]
+        self.dtype_name = dtype
+        self.tau = float(tau)
+        has_force = fx is not None
+        cfg = L.Config3(nx=self.nx, ny=self.ny, nz=self.nz, dtype=self.dtype, has_force=int(has_force),
+                        with_balance=int(with_balance), tau=self.tau, stream=_stream_handle(stream))
+        self._cfg = cfg
+        nbytes = C.c_size_t()
+        L.check(self._lib.lbm3_workspace_bytes(C.byref(cfg), C.byref(nbytes)), "lbm3_workspace_bytes")
+        self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        f = [_dev64(a, self.device) if has_force else None for a in (fx, fy, fz)]
+        h = C.c_void_p()
+        L.check(self._lib.lbm3_init(C.byref(cfg), _ptr(self.workspace), nbytes.value, _ptr(r), _ptr(vx),
+                                    _ptr(vy), _ptr(vz), _ptr(f[0]), _ptr(f[1]), _ptr(f[2]), C.byref(h)),
+                "lbm3_init")
+        self._h = h
+        torch.cuda.current_stream(self.device).synchronize() if stream is None else stream.synchronize()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.check(self._lib.lbm3_destroy(self._h), "lbm3_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def sites(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    def step(self, n: int = 1):
+        L.check(self._lib.lbm3_step(self._h, int(n)), "lbm3_step")
+        return self
+
+    @property
+    def time(self) -> int:
+        t = C.c_int64()
+        L.check(self._lib.lbm3_time(self._h, C.byref(t)), "lbm3_time")
+        return t.value
+
+    def moments(self, scalars=True):
+        """(rho, ux, uy, uz[, scalars dict]) at the current time, FP64 [nz, ny, nx]."""
+        shape = (self.nz, self.ny, self.nx)
+        out = [torch.empty(shape, dtype=torch.float64, device=self.device) for _ in range(4)]
+        if not scalars:
+            L.check(self._lib.lbm3_moments(self._h, *(_ptr(t) for t in out), None), "lbm3_moments")
+            return tuple(out)
+        sc = (C.c_double * 9)()
+        rc = self._lib.lbm3_moments(self._h, *(_ptr(t) for t in out), sc)
+        if rc == L.LBM_E_DIVERGED:
+            raise L.LBMError(rc, self._lib.lbm_last_error().decode())
+        L.check(rc, "lbm3_moments")
+        return (*out, dict(zip(L.SCALAR_NAMES3, list(sc))))
+
+    def balance(self, sizes, term_fields=False):
+        """Statistics of delta^E, delta^Omega and Ma_V over the L^3 cubes at every corner
+        for each L in sizes (needs with_balance and two recorded steps)."""
+        sizes = [int(v) for v in sizes]
+        sz = (C.c_int32 * max(1, len(sizes)))(*sizes)
+        out = (L.BalanceStats * max(1, len(sizes)))()
+        tf = torch.empty((L.NTERMS3, self.nz, self.ny, self.nx), dtype=torch.float64,
+                         device=self.device) if term_fields else None
+        L.check(self._lib.lbm3_subvolume_balance(self._h, sz, len(sizes), out, _ptr(tf)),
+                "lbm3_subvolume_balance")
+        res = {"stats": [stats_to_dict(out[k]) for k in range(len(sizes))]}
+        if tf is not None:
+            res["terms"] = {name: tf[k] for k, name in enumerate(L.TERM_NAMES3)}
+        return res

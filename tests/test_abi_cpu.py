@@ -13,12 +13,13 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def declared_functions():
     src = open(os.path.join(ROOT, "include", "lbm.h")).read()
-    return re.findall(r"^LBM_API\s+[\w\s\*]+?\b(lbm_\w+)\s*\(", src, flags=re.M)
+    return re.findall(r"^LBM_API\s+[\w\s\*]+?\b(lbm3?_\w+)\s*\(", src, flags=re.M)
 
 
 def test_header_declares_the_core_calls():
     names = declared_functions()
-    for core in ("lbm_init", "lbm_step", "lbm_moments", "lbm_subvolume_balance"):
+    for core in ("lbm_init", "lbm_step", "lbm_moments", "lbm_subvolume_balance", "lbm3_init",
+                 "lbm3_step", "lbm3_moments", "lbm3_subvolume_balance"):
         assert core in names
     assert len(names) == len(set(names))
 
@@ -131,3 +132,33 @@ def test_exact_difference_config_validation():
     # the exact-difference step takes single-step shapes with one site per thread
     assert lib.lbm_set_tuned_tile(C.byref(cfg(**edm)), C.byref(L.Tile(256, 1, 1, 64, 0, 2, 0))) == L.LBM_E_INVALID
     assert lib.lbm_set_tuned_tile(C.byref(cfg(**edm)), C.byref(L.Tile(64, 4, 2, 1, 0, 1, 0))) == L.LBM_E_INVALID
+
+
+def test_3d_config_validation():
+    """lbm3_workspace_bytes and lbm3_init validate the D3Q19 configuration on the host."""
+    lib = L.load()
+
+    def c3(**kw):
+        base = dict(nx=32, ny=24, nz=16, dtype=L.LBM_F32, has_force=0, with_balance=0, tau=0.6, stream=None)
+        base.update(kw)
+        return L.Config3(**base)
+
+    n = C.c_size_t()
+    assert lib.lbm3_workspace_bytes(C.byref(c3()), C.byref(n)) == L.LBM_OK
+    plane = 32 * 24 * 16
+    assert n.value >= 2 * 19 * plane * 4
+    n64, nb, nf = C.c_size_t(), C.c_size_t(), C.c_size_t()
+    lib.lbm3_workspace_bytes(C.byref(c3(dtype=L.LBM_F64)), C.byref(n64))
+    lib.lbm3_workspace_bytes(C.byref(c3(with_balance=1)), C.byref(nb))
+    lib.lbm3_workspace_bytes(C.byref(c3(has_force=1)), C.byref(nf))
+    assert n64.value > n.value and nb.value > n.value + 14 * plane * 8 and nf.value > n.value
+    for bad in (dict(nx=8), dict(nz=5000), dict(dtype=7), dict(tau=0.5), dict(tau=float("nan")),
+                dict(has_force=2), dict(with_balance=-1)):
+        assert lib.lbm3_workspace_bytes(C.byref(c3(**bad)), C.byref(n)) == L.LBM_E_INVALID, bad
+    assert lib.lbm3_workspace_bytes(None, C.byref(n)) == L.LBM_E_INVALID
+    h = C.c_void_p()
+    # invalid arguments are rejected before anything touches the device
+    assert lib.lbm3_init(C.byref(c3()), None, 0, None, None, None, None, None, None, None,
+                         C.byref(h)) == L.LBM_E_INVALID
+    assert lib.lbm3_step(None, 1) == L.LBM_E_INVALID
+    assert lib.lbm3_destroy(None) == L.LBM_OK
