@@ -295,6 +295,10 @@ def cpu_baseline(n, tau, alpha, fx, fy, steps):
                       f"{dt:.1f} s; step only, no balance"}
 
 
+EXTRAS = {"paper_set_up_256": paper_set_up_256, "paper_statistics_256": paper_statistics_256,
+          "entropic_1024": entropic_1024, "d3q19_256": d3q19_256}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -307,7 +311,24 @@ def main():
     ap.add_argument("--kernels-only", action="store_true",
                     help="only launch the step kernel of the workload (20 times, autotuned shape) "
                          "and the 1 GiB copy kernel (5 times), for hardware-counter runs")
+    ap.add_argument("--only-extra", choices=sorted(EXTRAS),
+                    help="run one extra measurement alone and print its JSON (profiling runs)")
+    ap.add_argument("--with-copy", action="store_true",
+                    help="with --only-extra: also run the 1 GiB copy kernel 5 times (counter scale)")
     a = ap.parse_args()
+    if a.only_extra:
+        import torch
+        res = EXTRAS[a.only_extra](log)
+        if a.with_copy:
+            from paper_1809_06735_amd import _lib as L
+            lib = L.load()
+            buf = torch.empty(2 << 30, dtype=torch.uint8, device="cuda")
+            for _ in range(5):
+                L.check(lib.lbm_copy(buf[1 << 30:].data_ptr(), buf[:1 << 30].data_ptr(), 1 << 30,
+                                     torch.cuda.current_stream().cuda_stream), "lbm_copy")
+            torch.cuda.synchronize()
+        print(json.dumps({a.only_extra: res}), flush=True)
+        return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); the multi-GPU layout is "
               "described in the design notes but not built", file=sys.stderr)

@@ -207,18 +207,29 @@ __global__ void __launch_bounds__(kRedThreads) k3_moments(const T* __restrict__ 
 
 __global__ void __launch_bounds__(kRedThreads) k3_reduce_scalars(const double* __restrict__ part, int nb,
                                                                  double* out) {
-  __shared__ double sh[kS3];
-  if (threadIdx.x < kS3) {
-    const int k = threadIdx.x;
-    double a = k == 6 ? 1e300 : 0.0;
-    for (int b = 0; b < nb; ++b) {
+  double a[kS3];
+#pragma unroll
+  for (int k = 0; k < kS3; ++k) a[k] = k == 6 ? 1e300 : 0.0;
+  for (int b = threadIdx.x; b < nb; b += kRedThreads)
+#pragma unroll
+    for (int k = 0; k < kS3; ++k) {
       const double q = part[b * kS3 + k];
-      a = k == 5 ? fmax(a, q) : (k == 6 ? fmin(a, q) : a + q);
+      a[k] = k == 5 ? fmax(a[k], q) : (k == 6 ? fmin(a[k], q) : a[k] + q);
     }
-    sh[k] = a;
+  __shared__ double sh[kRedThreads / 64][kS3];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < kS3; ++k) {
+    const double r = k == 5 ? wave_max(a[k]) : (k == 6 ? wave_min(a[k]) : wave_sum(a[k]));
+    if (lane == 0) sh[wv][k] = r;
   }
   __syncthreads();
-  if (threadIdx.x < kS3) out[threadIdx.x] = sh[threadIdx.x];
+  if (threadIdx.x < kS3) {
+    const int k = threadIdx.x;
+    double r = sh[0][k];
+    for (int w = 1; w < kRedThreads / 64; ++w) r = k == 5 ? fmax(r, sh[w][k]) : (k == 6 ? fmin(r, sh[w][k]) : r + sh[w][k]);
+    out[k] = r;
+  }
 }
 
 // ---- balance --------------------------------------------------------------------------------
@@ -647,16 +658,34 @@ __global__ void __launch_bounds__(kW3Threads) k3_windows(Vol v, int L, size_t co
   }
 }
 
-__global__ void __launch_bounds__(64) k3_windows_final(const double* __restrict__ partials, int nb, double* out) {
-  if (threadIdx.x >= 3) return;
-  const int q = threadIdx.x;
-  Run3 acc, b;
-  acc.init();
-  for (int k = 0; k < nb; ++k) {
-    b.load(partials + static_cast<size_t>(k) * kW3Vals + q * 6);
-    acc.merge(b);
+// Fixed-order merge of the workgroup partials: thread t takes partials t, t + 256, ...;
+// then pairs of threads, four wavefronts, in a fixed tree.
+__global__ void __launch_bounds__(256) k3_windows_final(const double* __restrict__ partials, int nb, double* out) {
+  __shared__ double sh[256][kW3Vals];
+  Run3 r[3], o;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) r[q].init();
+  for (int k = threadIdx.x; k < nb; k += 256)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      o.load(partials + static_cast<size_t>(k) * kW3Vals + q * 6);
+      r[q].merge(o);
+    }
+#pragma unroll
+  for (int q = 0; q < 3; ++q) r[q].store(&sh[threadIdx.x][q * 6]);
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        o.load(&sh[threadIdx.x + h][q * 6]);
+        r[q].merge(o);
+        r[q].store(&sh[threadIdx.x][q * 6]);
+      }
+    __syncthreads();
   }
-  acc.store(out + q * 6);
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 3; ++q) r[q].store(out + q * 6);
 }
 
 int grid1(size_t n, int cap) { return static_cast<int>(std::max<size_t>(1, std::min<size_t>(cap, (n + 255) / 256))); }
@@ -969,7 +998,7 @@ int lbm3_subvolume_balance(lbm3_ctx c, const int32_t* sizes, int32_t nsizes, lbm
     const int nb = grid1(count, kW3MaxBlocks);
     hipLaunchKernelGGL(k3_windows, dim3(nb), dim3(kW3Threads), 0, s, v, L, count, c->wpart);
     LBM_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k3_windows_final, dim3(1), dim3(64), 0, s, c->wpart, nb, c->wstat + k * kW3Vals);
+    hipLaunchKernelGGL(k3_windows_final, dim3(1), dim3(256), 0, s, c->wpart, nb, c->wstat + k * kW3Vals);
     LBM_HIP(hipGetLastError());
   }
   std::vector<double> st(static_cast<size_t>(nsizes) * kW3Vals);
