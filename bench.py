@@ -41,7 +41,8 @@ def log(*a):
 
 
 KERNEL_SOURCES = {"k_step": ("lbm_step.hip", "lbm_site.h"),
-                  "k_step_fused": ("lbm_step_fused.hip", "lbm_fused.h", "lbm_site.h")}
+                  "k_step_fused": ("lbm_step_fused.hip", "lbm_fused.h", "lbm_site.h"),
+                  "k3_step": ("lbm3d.hip",)}
 
 
 def step_source_digest(kernel="k_step_fused"):
@@ -243,7 +244,8 @@ def d3q19_256(log, n=256, tau=0.52, steps=200):
     """The three-dimensional extension: a forced 256^3 D3Q19 FP32 run (one launch per step,
     164 algorithmic bytes per site: 19 populations read and written, 3 force values read),
     timed with HIP events on the handle's stream, then the 3D balance with the stretching
-    term at L = 16, 64, 256 over every cube corner."""
+    term at L = 16, 64, 256 over every cube corner.  `traffic`: HBM bytes per launch from
+    the committed counter summary, if it was taken on the current kernel source."""
     import torch
     import lbm_inputs as inp
     from paper_1809_06735_amd import Simulation3D
@@ -264,7 +266,8 @@ def d3q19_256(log, n=256, tau=0.52, steps=200):
     gbs = 164 * sites / (ms * 1e-3) / 1e9
     out = {"grid": [n, n, n], "dtype": "f32", "steps": steps, "ms_per_step": round(ms, 4),
            "MLUPS": round(sites / (ms * 1e-3) / 1e6, 1), "kernel_GBps": round(gbs, 1),
-           "frac_of_8TBps": round(gbs / HBM_PEAK_GBS, 4)}
+           "frac_of_8TBps": round(gbs / HBM_PEAK_GBS, 4),
+           "traffic": traffic_from_profile("k3_step", "d3q19_256", ["rows", "nt"])}
     sizes = (16, 64, 256)
     t0 = time.perf_counter()
     res = sim.balance(sizes)

@@ -4,9 +4,11 @@
 // equation gains the vortex-stretching term omega_i omega_j d_j u_i (Sec. 2
 // notes that 3D keeps it), averaged over cubes L^3 at every corner.
 //
-// Populations: nine-teen planes [19][nz][ny][nx], deviations from the weights,
-// kept un-streamed (plane l at x holds f_l(x + c_l)): one step pulls from
-// x - c_l, collides and writes at x, 19 + 19 values per update (152 B FP32).
+// Populations: row-interleaved [nz][ny][19][nx] (the 19 population rows of one
+// (y, z) row of sites are contiguous), deviations from the weights, kept
+// un-streamed (population l stored at x is f_l(x + c_l)): one step pulls from
+// x - c_l, collides and writes at x, 19 + 19 values per update (152 B FP32),
+// both streams non-temporal (each value is touched once per step).
 // Balance: pass A (first derivatives at level n and the vorticity at the three
 // levels) gives the pointwise terms and the stress, vorticity and F / rho;
 // pass B differences products and the stress (e1, e5, z1, z3, H = div sigma / rho);
@@ -41,6 +43,11 @@ __host__ __device__ constexpr double w3(int l) { return l == 0 ? 1.0 / 3.0 : (l 
 
 __device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
+// Element (l, z, y, x) of the row-interleaved population array.
+__device__ __forceinline__ size_t pop_at(int l, int z, int y, int x, int ny, int nx) {
+  return ((static_cast<size_t>(z) * ny + y) * Q3 + l) * nx + x;
+}
+
 // ---- step ---------------------------------------------------------------------------------
 struct Step3 {
   const void* src;
@@ -59,14 +66,13 @@ __global__ void __launch_bounds__(256) k3_step(Step3 p) {
   if (x >= p.nx) return;
   const int y = blockIdx.y, z = blockIdx.z;
   const int nx = p.nx, ny = p.ny, nz = p.nz;
-  const size_t plane = static_cast<size_t>(nx) * ny * nz;
   const T* __restrict__ src = static_cast<const T*>(p.src);
   T* __restrict__ dst = static_cast<T*>(p.dst);
   T d[Q3];
 #pragma unroll
   for (int l = 0; l < Q3; ++l) {
     const int xs = wrap(x - c3(l, 0), nx), ys = wrap(y - c3(l, 1), ny), zs = wrap(z - c3(l, 2), nz);
-    d[l] = src[l * plane + (static_cast<size_t>(zs) * ny + ys) * nx + xs];
+    d[l] = __builtin_nontemporal_load(src + pop_at(l, zs, ys, xs, ny, nx));
   }
   T drho = T(0), jx = T(0), jy = T(0), jz = T(0);
 #pragma unroll
@@ -102,7 +108,7 @@ __global__ void __launch_bounds__(256) k3_step(Step3 p) {
       const T gz = T(3) * (cz - uz) + T(9) * cu * cz;
       o += g * w * (gx * Fx + gy * Fy + gz * Fz);
     }
-    dst[l * plane + i] = o;
+    __builtin_nontemporal_store(o, dst + pop_at(l, z, y, x, ny, nx));
   }
   if (p.h[0]) {
     p.h[0][i] = double(rho);
@@ -128,7 +134,7 @@ __global__ void __launch_bounds__(256) k3_init(T* __restrict__ pop, const double
       const double cu = c3(l, 0) * ux + c3(l, 1) * uy + c3(l, 2) * uz;
       const double dev = w3(l) * ((rho - 1.0) + rho * (3.0 * cu + 4.5 * cu * cu - usq15));
       const int xs = wrap(x - c3(l, 0), nx), ys = wrap(y - c3(l, 1), ny), zs = wrap(z - c3(l, 2), nz);
-      pop[l * plane + (static_cast<size_t>(zs) * ny + ys) * nx + xs] = T(dev);
+      pop[pop_at(l, zs, ys, xs, ny, nx)] = T(dev);
     }
   }
 }
@@ -158,7 +164,7 @@ __global__ void __launch_bounds__(kRedThreads) k3_moments(const T* __restrict__ 
 #pragma unroll
     for (int l = 0; l < Q3; ++l) {
       const int xs = wrap(x - c3(l, 0), nx), ys = wrap(y - c3(l, 1), ny), zs = wrap(z - c3(l, 2), nz);
-      const T dl = pop[l * plane + (static_cast<size_t>(zs) * ny + ys) * nx + xs];
+      const T dl = pop[pop_at(l, zs, ys, xs, ny, nx)];
       tr += dl;
       if (c3(l, 0)) tx += c3(l, 0) * dl;
       if (c3(l, 1)) ty += c3(l, 1) * dl;
