@@ -170,15 +170,21 @@ typedef struct {
  *   in x (1, 2 or 4; nx must be a multiple of vx) on ry consecutive rows.
  * fuse = 2..6: that many steps per launch (temporal blocking; the
  *   intermediate states stay in LDS and registers, bit-identical to single
- *   steps).  A workgroup of bx + 64 threads updates a strip of bx columns (a
- *   multiple of 64, at most 512) and a band of ry rows; by = vx = 1; pf = 1
- *   issues the loads of the next row earlier in the row's iteration.
- * nt = 1 writes the new populations with non-temporal stores.  lbm_step runs
- * the two steps that record the moment history (and any remainder of the
- * bulk that is not a multiple of fuse) with the single-step kernel. */
+ *   steps).  A workgroup updates a strip of columns and a band of ry rows;
+ *   by = vx = 1; pf = 1 issues the loads of the next row earlier in the row's
+ *   iteration.  The fuse - 1 halo columns on each side of the strip are
+ *   recomputed: halo = 0 gives them an extra wavefront (bx + 64 threads, a
+ *   strip of bx columns, bx a multiple of 64 up to 512); halo = 1 packs them
+ *   into the bx threads (a strip of bx - 2 (fuse - 1) columns, bx a multiple of
+ *   64 up to 512), which spends no issue slots on a mostly idle wavefront.
+ * nt = 1 writes the new populations with non-temporal stores.  halo must be 0
+ * for single-step shapes.  lbm_step runs the two steps that record the moment
+ * history (and any remainder of the bulk that is not a multiple of fuse) with
+ * the single-step kernel. */
 typedef struct {
   int32_t bx, by, vx, ry, nt;
   int32_t fuse, pf;
+  int32_t halo;
 } lbm_tile;
 
 /* ---- library information --------------------------------------------------- */

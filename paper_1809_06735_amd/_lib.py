@@ -77,7 +77,7 @@ class BalanceStats(C.Structure):
 
 class Tile(C.Structure):
     _fields_ = [("bx", C.c_int32), ("by", C.c_int32), ("vx", C.c_int32), ("ry", C.c_int32),
-                ("nt", C.c_int32), ("fuse", C.c_int32), ("pf", C.c_int32)]
+                ("nt", C.c_int32), ("fuse", C.c_int32), ("pf", C.c_int32), ("halo", C.c_int32)]
 
 
 class BalanceInput(C.Structure):

@@ -176,9 +176,9 @@ void tune_cache_load() {
   while (std::fgets(line, sizeof(line), f)) {
     int dt, nx, ny, fo, lay, sch;
     lbm_tile t;
-    if (std::sscanf(line, "step dtype=%d nx=%d ny=%d force=%d layout=%d scheme=%d : %d %d %d %d %d %d %d",
+    if (std::sscanf(line, "step dtype=%d nx=%d ny=%d force=%d layout=%d scheme=%d : %d %d %d %d %d %d %d %d",
                     &dt, &nx, &ny, &fo, &lay, &sch, &t.bx, &t.by, &t.vx, &t.ry, &t.nt, &t.fuse,
-                    &t.pf) == 13 &&
+                    &t.pf, &t.halo) == 14 &&
         (sch >= 2 ? entropic_tile_ok(t, nx, ny) : sch == 1 ? edm_tile_ok(t, nx, ny) : tile_ok(t, dt, nx, ny)))
       g_tune[tune_key(dt, nx, ny, fo != 0, lay, sch)] = t;
   }
@@ -191,8 +191,8 @@ void tune_cache_store() {
   FILE* f = std::fopen(path, "w");
   if (!f) return;
   for (auto& kv : g_tune)
-    std::fprintf(f, "%s : %d %d %d %d %d %d %d\n", kv.first.c_str(), kv.second.bx, kv.second.by,
-                 kv.second.vx, kv.second.ry, kv.second.nt, kv.second.fuse, kv.second.pf);
+    std::fprintf(f, "%s : %d %d %d %d %d %d %d %d\n", kv.first.c_str(), kv.second.bx, kv.second.by,
+                 kv.second.vx, kv.second.ry, kv.second.nt, kv.second.fuse, kv.second.pf, kv.second.halo);
   std::fclose(f);
 }
 
@@ -728,8 +728,9 @@ int lbm_load(lbm_ctx c, const void* src) {
 int lbm_set_tile(lbm_ctx c, const lbm_tile* tile) {
   if (!c || !tile) return fail(LBM_E_INVALID, "NULL argument");
   if (!ctx_tile_ok(c, *tile))
-    return fail(LBM_E_INVALID, "tile (%d,%d,vx %d,ry %d,nt %d,fuse %d) not valid for %d x %d%s", tile->bx,
-                tile->by, tile->vx, tile->ry, tile->nt, tile->fuse, c->cfg.nx, c->cfg.ny,
+    return fail(LBM_E_INVALID, "tile (%d,%d,vx %d,ry %d,nt %d,fuse %d,pf %d,halo %d) not valid for %d x %d%s",
+                tile->bx, tile->by, tile->vx, tile->ry, tile->nt, tile->fuse, tile->pf, tile->halo, c->cfg.nx,
+                c->cfg.ny,
                 is_edm(c) ? " with the exact-difference step" : "");
   c->tile = *tile;
   c->tile1 = single_for(c, c->tile);
@@ -757,9 +758,10 @@ int lbm_set_tuned_tile(const lbm_config* cfg, const lbm_tile* tile) {
 int lbm_autotune(lbm_ctx c, int32_t trial_steps, lbm_tile* chosen) {
   if (!c) return fail(LBM_E_INVALID, "ctx is NULL");
   if (trial_steps < 1 || trial_steps > 10000) return fail(LBM_E_INVALID, "trial_steps in [1, 10000]");
-  lbm_tile cand[512];
-  int n = tile_candidates(c->cfg.dtype, c->cfg.nx, c->cfg.ny, cand, 512);
-  if (n > 512) n = 512;
+  constexpr int kCap = 1024;
+  std::vector<lbm_tile> cand(kCap);
+  int n = tile_candidates(c->cfg.dtype, c->cfg.nx, c->cfg.ny, cand.data(), kCap);
+  if (n > kCap) n = kCap;
   if (one_site_kernel(c)) {  // single-step, one-site-per-thread shapes
     int k = 0;
     for (int i = 0; i < n; ++i)
@@ -774,7 +776,7 @@ int lbm_autotune(lbm_ctx c, int32_t trial_steps, lbm_tile* chosen) {
   float best = 1e30f, best1 = 1e30f;  // milliseconds per step: any shape, single-step shapes
   lbm_tile best_t = saved, best_t1 = c->tile1;
   int rc = LBM_OK;
-  for (int i = 0; i < n && i < 512 && rc == LBM_OK; ++i) {
+  for (int i = 0; i < n && rc == LBM_OK; ++i) {
     c->tile = cand[i];
     // src -> dst repeatedly: the state (src) is never modified
     rc = enqueue_step(c, c->cur, c->stream, nullptr, nullptr, nullptr);

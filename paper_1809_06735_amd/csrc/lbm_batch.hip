@@ -224,9 +224,9 @@ __global__ void __launch_bounds__(fused_detail::kFusedMaxThreads) k_batch_fused(
   const int strips = (r.nx + a.W - 1) / a.W;
   T* const lds = reinterpret_cast<T*>(smem_raw);
   if (r.forced)
-    fused_detail::fused_tile<T, K, true, NT, true>(p, lds, a.W, a.H, strips, a.item_tile[it]);
+    fused_detail::fused_tile<T, K, true, NT, true>(p, lds, a.W, a.H, strips, a.item_tile[it], false);
   else
-    fused_detail::fused_tile<T, K, false, NT, true>(p, lds, a.W, a.H, strips, a.item_tile[it]);
+    fused_detail::fused_tile<T, K, false, NT, true>(p, lds, a.W, a.H, strips, a.item_tile[it], false);
 }
 
 template <typename T, int K>
@@ -681,7 +681,7 @@ int lbm_batch_set_tile(lbm_batch b, int32_t block_threads, int32_t vx, int32_t b
 
 int lbm_batch_set_multi(lbm_batch b, const lbm_tile* t) {
   if (!b || !t) return fail(LBM_E_INVALID, "NULL argument");
-  if (t->fuse < 2 || t->fuse > 4 || !fused_tile_ok(*t, b->dtype) || t->ry < kMinFusedBand)
+  if (t->fuse < 2 || t->fuse > 4 || t->halo != 0 || !fused_tile_ok(*t, b->dtype) || t->ry < kMinFusedBand)
     return fail(LBM_E_INVALID, "multi-step shape: fuse 2..4, strip a multiple of 64 up to 512, "
                                "band >= %d rows", kMinFusedBand);
   b->ftile = *t;

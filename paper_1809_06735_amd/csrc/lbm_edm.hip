@@ -564,7 +564,7 @@ int edm_tables(const lbm_config& c, const EdmWs& w, const EdmModes& md, hipStrea
 bool edm_tile_ok(const lbm_tile& t, int nx, int ny) {
   (void)nx;
   (void)ny;
-  if (t.fuse < 0 || t.fuse > 1 || t.vx != 1 || t.pf != 0) return false;
+  if (t.fuse < 0 || t.fuse > 1 || t.vx != 1 || t.pf != 0 || t.halo != 0) return false;
   const int threads = t.bx * t.by;
   if (t.bx < 1 || t.by < 1 || t.ry < 1 || threads > 1024 || threads % 64 != 0) return false;
   return t.nt == 0 || t.nt == 1;

@@ -53,15 +53,18 @@ struct Carry {
 };
 
 // One tile (strip `tile % strips`, band `tile / strips`) of a K-step update of
-// the grid p (src -> dst).  Threads [0, W) own the strip columns; threads
-// W + j, j < 2 (K - 1), the halo columns at distance j / 2 + 1 left (j even)
-// or right (j odd) of the strip; blockDim.x = W + 64; lds holds
-// 2 * 6 * (W + 2 (K - 1)) values.  PF issues the next row's loads after the
-// first exchange barrier instead of at the end of the iteration.  Every
-// thread of the workgroup must call it (it contains barriers).
+// the grid p (src -> dst), strips of W columns.  Separate halo (packed =
+// false): threads [0, W) own the strip columns, threads W + j, j < 2 (K - 1),
+// the halo columns at distance j / 2 + 1 left (j even) or right (j odd) of the
+// strip, blockDim.x = W + 64.  Packed halo: thread t owns column
+// x0 - (K - 1) + t, so the strip and both halos are one contiguous run of
+// W + 2 (K - 1) = blockDim.x lanes.  Either way lds holds 2 * 6 * (W + 2 (K - 1))
+// values, indexed by the column's position in that run.  PF issues the next
+// row's loads after the first exchange barrier instead of at the end of the
+// iteration.  Every thread of the workgroup must call it (it contains barriers).
 template <typename T, int K, bool FORCE, bool NT, bool PF>
 __device__ __forceinline__ void fused_tile(const StepParams& p, T* const lds, int W, int H,
-                                           int strips, int tile) {
+                                           int strips, int tile, bool packed) {
   const int stride = W + 2 * (K - 1);
   const int nx = p.nx, ny = p.ny;
   const int x0 = (tile % strips) * W;
@@ -71,7 +74,17 @@ __device__ __forceinline__ void fused_tile(const StepParams& p, T* const lds, in
   const int t = threadIdx.x;
   // column, LDS index and the highest level this thread takes part in
   int col = x0, li = 0, top = 0;
-  if (t < weff) {
+  if (packed) {
+    // a level-s value exists on the columns at least s - 1 away from both ends
+    const int n_act = weff + 2 * (K - 1);
+    if (t < n_act) {
+      top = min(min(t, n_act - 1 - t) + 1, K);
+      col = x0 - (K - 1) + t;
+      if (col < 0) col += nx;
+      if (col >= nx) col -= nx;
+      li = t;
+    }
+  } else if (t < weff) {
     col = x0 + t;
     li = t + K - 1;
     top = K;

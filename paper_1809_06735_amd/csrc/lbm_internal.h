@@ -87,6 +87,8 @@ int launch_init(int dtype, void* pop, PopLayout lay, const double* rho0, const d
 int launch_step(int dtype, bool force, const StepParams& p, const lbm_tile& t, hipStream_t s);
 int launch_step_fused(int dtype, bool force, const StepParams& p, const lbm_tile& t, hipStream_t s);
 bool fused_tile_ok(const lbm_tile& t, int dtype);
+// columns of output per strip of a multi-step shape (bx, or bx - 2 (fuse - 1) with halo = 1)
+int fused_strip_width(const lbm_tile& t);
 size_t fused_lds_bytes(int W, int K, int dtype);
 inline int steps_per_launch(const lbm_tile& t) { return t.fuse >= 2 ? t.fuse : 1; }
 bool tile_ok(const lbm_tile& t, int dtype, int nx, int ny);

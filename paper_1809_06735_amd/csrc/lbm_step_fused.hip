@@ -16,24 +16,26 @@ using fused_detail::kFusedMaxThreads;
 // Workgroups are numbered so that consecutive tiles fall on the same XCD.
 template <typename T, int K, bool FORCE, bool NT, bool PF>
 __global__ void __launch_bounds__(kFusedMaxThreads) k_step_fused(StepParams p, int W, int H, int strips,
-                                                                 int total, int per_xcd) {
+                                                                 int total, int per_xcd, int packed) {
   extern __shared__ unsigned char smem_raw[];
   const int b = blockIdx.x;
   const int tile = (b & 7) * per_xcd + (b >> 3);
   if (tile >= total) return;  // uniform over the workgroup
-  fused_detail::fused_tile<T, K, FORCE, NT, PF>(p, reinterpret_cast<T*>(smem_raw), W, H, strips, tile);
+  fused_detail::fused_tile<T, K, FORCE, NT, PF>(p, reinterpret_cast<T*>(smem_raw), W, H, strips, tile,
+                                                packed != 0);
 }
 
 template <typename T, int K, bool FORCE, bool NT, bool PF>
 int launch_t(const StepParams& p, const lbm_tile& t, hipStream_t s) {
-  const int W = t.bx, H = t.ry;
+  const int W = fused_strip_width(t), H = t.ry;
+  const int threads = t.halo ? t.bx : t.bx + 64;
   const int strips = (p.nx + W - 1) / W;
   const int bands = (p.ny + H - 1) / H;
   const int total = strips * bands;
   const int per_xcd = (total + 7) / 8;
   const size_t lds = fused_lds_bytes(W, K, sizeof(T) == 8 ? LBM_F64 : LBM_F32);
-  hipLaunchKernelGGL((k_step_fused<T, K, FORCE, NT, PF>), dim3(per_xcd * 8), dim3(W + 64), lds, s, p,
-                     W, H, strips, total, per_xcd);
+  hipLaunchKernelGGL((k_step_fused<T, K, FORCE, NT, PF>), dim3(per_xcd * 8), dim3(threads), lds, s, p,
+                     W, H, strips, total, per_xcd, t.halo);
   LBM_HIP(hipGetLastError());
   return LBM_OK;
 }
@@ -57,18 +59,6 @@ int dispatch(const StepParams& p, const lbm_tile& t, hipStream_t s) {
 }
 
 }  // namespace
-
-size_t fused_lds_bytes(int W, int K, int dtype) {
-  return static_cast<size_t>(2) * 6 * (W + 2 * (K - 1)) * (dtype == LBM_F64 ? 8 : 4);
-}
-
-bool fused_tile_ok(const lbm_tile& t, int dtype) {
-  if (t.fuse < 2 || t.fuse > 6 || t.by != 1 || t.vx != 1) return false;
-  if (t.bx < 64 || t.bx % 64 != 0 || t.bx + 64 > kFusedMaxThreads) return false;
-  if (t.ry < 1 || t.ry > 4096) return false;
-  if ((t.nt != 0 && t.nt != 1) || (t.pf != 0 && t.pf != 1)) return false;
-  return fused_lds_bytes(t.bx, t.fuse, dtype) <= 64 * 1024;
-}
 
 int launch_step_fused(int dtype, bool force, const StepParams& p, const lbm_tile& t, hipStream_t s) {
   if (!fused_tile_ok(t, dtype)) return fail(LBM_E_INVALID, "invalid multi-step launch shape");

@@ -307,23 +307,24 @@ class Simulation:
         return self
 
     # -- launch shape / graphs / timing ---------------------------------------------------------
-    def set_tile(self, bx, by, vx, ry, nt=0, fuse=1, pf=0):
-        """Step-kernel shape; fuse=2 selects the two-steps-per-launch kernel
-        (bx = strip width, ry = band height, by = vx = 1)."""
-        t = L.Tile(bx, by, vx, ry, nt, fuse, pf)
+    def set_tile(self, bx, by, vx, ry, nt=0, fuse=1, pf=0, halo=0):
+        """Step-kernel shape; fuse = 2..6 selects the multi-step kernel (ry = band
+        height, by = vx = 1; halo = 0: strip of bx columns plus a halo wavefront,
+        halo = 1: bx threads holding the strip and its halo columns)."""
+        t = L.Tile(bx, by, vx, ry, nt, fuse, pf, halo)
         L.check(self._lib.lbm_set_tile(self._h, C.byref(t)), "lbm_set_tile")
 
     def get_tile(self):
         t = L.Tile()
         L.check(self._lib.lbm_get_tile(self._h, C.byref(t)), "lbm_get_tile")
-        return (t.bx, t.by, t.vx, t.ry, t.nt, max(t.fuse, 1), t.pf)
+        return (t.bx, t.by, t.vx, t.ry, t.nt, max(t.fuse, 1), t.pf, t.halo)
 
     def autotune(self, trial_steps=10):
         """Time every candidate shape (per step) and keep the fastest; returns it
-        as (bx, by, vx, ry, nt, fuse, pf)."""
+        as (bx, by, vx, ry, nt, fuse, pf, halo)."""
         t = L.Tile()
         L.check(self._lib.lbm_autotune(self._h, int(trial_steps), C.byref(t)), "lbm_autotune")
-        return (t.bx, t.by, t.vx, t.ry, t.nt, max(t.fuse, 1), t.pf)
+        return (t.bx, t.by, t.vx, t.ry, t.nt, max(t.fuse, 1), t.pf, t.halo)
 
     def set_graph(self, chunk):
         L.check(self._lib.lbm_set_graph(self._h, int(chunk)), "lbm_set_graph")

@@ -152,6 +152,9 @@ def test_ragged_grids_all_launch_shapes_agree(gpu_lib, shape):
         for (w, h, k) in ((64, 1, 2), (64, 5, 3), (128, 16, 4), (64, 64, 2), (64, 2, 4)):
             for nt, pf in ((0, 0), (1, 1)):
                 cand.append((w, 1, 1, h, nt, k, pf))
+        # packed halo: the strip and its halo columns in the same lanes
+        for (w, h, k) in ((64, 1, 4), (64, 5, 6), (128, 16, 5), (64, 3, 2)):
+            cand.append((w, 1, 1, h, 1, k, 1, 1))
         ref_state = None
         checked = 0
         for tile in cand:
@@ -206,19 +209,25 @@ def test_multi_step_kernel_equals_single_steps(gpu_lib, dtype, layout):
         base.step(52)
         s61 = base.save().clone()
         base.close()
-        for (k, w, h, nt, pf, chunk) in ((2, 64, 16, 0, 0, 0), (2, 128, 7, 1, 1, 0), (2, 256, 75, 0, 1, 4),
-                                         (2, 64, 1, 1, 0, 2), (2, 512, 32, 1, 1, 0),
-                                         (3, 64, 16, 1, 0, 0), (3, 128, 5, 0, 1, 2), (3, 256, 75, 1, 1, 0),
-                                         (4, 64, 3, 0, 0, 0), (4, 192, 40, 1, 1, 4), (4, 512, 64, 1, 0, 0),
-                                         (4, 64, 1, 1, 1, 0), (5, 128, 20, 1, 1, 0), (5, 64, 75, 0, 1, 2),
-                                         (6, 256, 9, 1, 1, 0), (6, 64, 2, 0, 0, 4)):
+        # last field: halo = 1 packs the halo columns into the workgroup (strip of
+        # w - 2 (k - 1) columns: 58, 122, 182, 54, 246 here, ragged on 200 columns or
+        # wider than the grid)
+        for (k, w, h, nt, pf, chunk, halo) in (
+                (2, 64, 16, 0, 0, 0, 0), (2, 128, 7, 1, 1, 0, 0), (2, 256, 75, 0, 1, 4, 0),
+                (2, 64, 1, 1, 0, 2, 0), (2, 512, 32, 1, 1, 0, 0),
+                (3, 64, 16, 1, 0, 0, 0), (3, 128, 5, 0, 1, 2, 0), (3, 256, 75, 1, 1, 0, 0),
+                (4, 64, 3, 0, 0, 0, 0), (4, 192, 40, 1, 1, 4, 0), (4, 512, 64, 1, 0, 0, 0),
+                (4, 64, 1, 1, 1, 0, 0), (5, 128, 20, 1, 1, 0, 0), (5, 64, 75, 0, 1, 2, 0),
+                (6, 256, 9, 1, 1, 0, 0), (6, 64, 2, 0, 0, 4, 0),
+                (4, 64, 3, 0, 0, 0, 1), (4, 128, 40, 1, 1, 4, 1), (5, 192, 20, 1, 1, 0, 1),
+                (6, 64, 2, 0, 0, 4, 1), (6, 256, 9, 1, 1, 0, 1), (2, 512, 32, 1, 1, 0, 1)):
             s = Sim(rho, ux, uy, 0.53, dtype=dtype, layout=layout, **kw)
-            s.set_tile(w, 1, 1, h, nt, k, pf)
+            s.set_tile(w, 1, 1, h, nt, k, pf, halo)
             s.set_graph(chunk)
             s.step(9)
-            assert torch.equal(s.save(), s9), (forced, k, w, h, nt, pf, chunk, 9)
+            assert torch.equal(s.save(), s9), (forced, k, w, h, nt, pf, chunk, halo, 9)
             s.step(52)
-            assert torch.equal(s.save(), s61), (forced, k, w, h, nt, pf, chunk, 61)
+            assert torch.equal(s.save(), s61), (forced, k, w, h, nt, pf, chunk, halo, 61)
             s.close()
         say(f"multi-step kernel {dtype} {layout} forced={forced}: bit-identical")
 
@@ -230,7 +239,8 @@ def test_multi_step_shapes_rejected_when_invalid(gpu_lib):
     for bad in ((96, 1, 1, 8, 0, 2, 0), (0, 1, 1, 8, 0, 2, 0), (1024, 1, 1, 8, 0, 2, 0),
                 (64, 2, 1, 8, 0, 2, 0), (64, 1, 2, 8, 0, 2, 0), (64, 1, 1, 0, 0, 2, 0),
                 (64, 1, 1, 8, 0, 7, 0), (64, 1, 1, 8, 0, 1, 1), (960, 1, 1, 8, 0, 2, 0),
-                (576, 1, 1, 8, 0, 2, 0)):
+                (576, 1, 1, 8, 0, 2, 0), (64, 1, 1, 8, 0, 2, 0, 2), (64, 1, 1, 8, 0, 1, 0, 1),
+                (64, 1, 1, 1, 0, 0, 0, 1), (576, 1, 1, 8, 0, 4, 1, 1)):
         with pytest.raises(LBMError):
             s.set_tile(*bad)
     s.close()
