@@ -96,7 +96,7 @@ def single_step_kernel(n, tau, alpha, fx, fy, steps=400):
     s.close()
     shape, per = best
     gbs = 80 * n * n / per / 1e9
-    tile = tuple(shape) + (1, 0)
+    tile = tuple(shape) + (1, 0, 0)
     return {"shape": list(tile), "avg_launch_us": round(per * 1e6, 2), "GBps": round(gbs, 1),
             "frac_of_8TBps": round(gbs / HBM_PEAK_GBS, 4), "kernel_MLUPS": round(n * n / per / 1e6, 1),
             "traffic": traffic_from_profile("k_step", "forced4096", tile)}
