@@ -367,14 +367,28 @@ def main():
         log("[bench] kernels-only run done: 20 step launches, 5 copies of 1 GiB")
         return
 
+    # One pass: STEPS_PER_PASS steps, then the balance of that time.  The balance runs on the
+    # library's second stream beside the next pass's steps (lbm_balance_begin); its statistics
+    # are collected once the next pass's steps are enqueued, and the last one before the clock
+    # stops, so every pass's balance is inside the timed region.
+    pending = [False]
+
     def one_pass():
         sim.step(STEPS_PER_PASS)
-        res = sim.balance(SIZES)
+        res = sim.balance_end() if pending[0] else None
+        sim.balance_begin(SIZES)
+        pending[0] = True
         return res
+
+    def drain():
+        pending[0] = False
+        return sim.balance_end()
 
     log(f"[bench] warmup {a.warmup} passes")
     for _ in range(a.warmup):
         one_pass()
+    if pending[0]:
+        drain()
     torch.cuda.synchronize()
     sim.step_time(reset=True)
     sim.step_timing(True)
@@ -383,7 +397,8 @@ def main():
     t0 = time.perf_counter()
     last = None
     for _ in range(a.steps):
-        last = one_pass()
+        one_pass()
+    last = drain()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     sim.step_timing(False)
@@ -397,6 +412,15 @@ def main():
     alg_bytes = bytes_per_site * n * n        # per launch, whatever the steps fused
     achieved = alg_bytes / avg_launch_s / 1e9
     traffic = traffic_from_profile(kernel, "forced4096", tile)
+    # the same kernel alone on the GPU (no balance beside it): 60 bulk launches
+    torch.cuda.synchronize()
+    sim.step_time(reset=True)
+    sim.step_timing(True)
+    sim.step(60 * spl + 2)
+    torch.cuda.synchronize()
+    sim.step_timing(False)
+    alone_ms, alone_n = sim.step_time(reset=True)
+    alone_s = alone_ms * 1e-3 / max(alone_n, 1)
     st = last["stats"]
     log(f"[bench] {mlups:.0f} MLUPS whole pass; {kernel} ({spl} steps/launch) "
         f"{avg_launch_s * 1e6:.1f} us/launch = {achieved:.0f} GB/s ({achieved / HBM_PEAK_GBS:.1%} "
@@ -417,7 +441,8 @@ def main():
         "data": "synthetic: fluid at rest, seeded random-phase divergence-free force on shells 4<=|k|<=6",
         "config": {"workload": f"forced4096: D2Q9 BGK {n}x{n} periodic FP32, Guo force + drag "
                                f"alpha={w.alpha}, tau={a.tau}; one step = {STEPS_PER_PASS} LBGK "
-                               f"steps + moments + sub-volume balance at L={list(SIZES)}",
+                               f"steps + moments + sub-volume balance at L={list(SIZES)} (the balance on a second "
+                               f"stream, beside the next pass's steps)",
                    "grid": n, "tau": a.tau, "lbgk_steps_per_step": STEPS_PER_PASS,
                    "balance_sizes": list(SIZES), "step_kernel_shape": list(tile),
                    "parallelism": "single GPU"},
@@ -431,7 +456,12 @@ def main():
                      "algorithmic_bytes_per_launch": alg_bytes,
                      "bytes_per_lattice_update": bytes_per_site / spl,
                      "avg_launch_us": round(avg_launch_s * 1e6, 2),
-                     "kernel_MLUPS": round(n * n * spl / avg_launch_s / 1e6, 1)},
+                     "kernel_MLUPS": round(n * n * spl / avg_launch_s / 1e6, 1),
+                     "alone": {"avg_launch_us": round(alone_s * 1e6, 2),
+                               "achieved": round(alg_bytes / alone_s / 1e9, 1),
+                               "frac": round(alg_bytes / alone_s / 1e9 / HBM_PEAK_GBS, 4),
+                               "kernel_MLUPS": round(n * n * spl / alone_s / 1e6, 1),
+                               "note": "the same kernel timed without the balance running beside it"}},
         "balance_at_end": {str(s["L"]): {"mean_dE": s["dE"]["mean"], "mean_dZ": s["dZ"]["mean"],
                                          "mean_Ma": s["Ma"]["mean"]} for s in st},
     }

@@ -257,6 +257,21 @@ LBM_API int lbm_subvolume_balance(lbm_ctx ctx, const int32_t* sizes, int32_t nsi
                           const int32_t* windows, int32_t nwin, double* wterms,
                           double* term_fields);
 
+/* The statistics of lbm_subvolume_balance (all corners, no maps, windows or
+ * term fields) computed beside the following steps instead of in line with
+ * them: lbm_balance_begin takes the moments of the current time t (as
+ * lbm_subvolume_balance does: same preconditions, same errors, and it
+ * synchronises cfg->stream to check them), then enqueues the balance on a
+ * second stream of the library (default priority) and returns; steps enqueued
+ * afterwards run concurrently with it.  lbm_balance_end waits for it and fills
+ * out[nsizes] with exactly what lbm_subvolume_balance would have returned at t.
+ * Until lbm_balance_end, work that would overwrite what the balance reads (the
+ * two history-recording steps of lbm_step, another balance, lbm_energy_spectrum,
+ * lbm_load) waits for it on the device; a second lbm_balance_begin gives
+ * LBM_E_STATE.  sizes[nsizes] : host, 1 <= nsizes <= 64. */
+LBM_API int lbm_balance_begin(lbm_ctx ctx, const int32_t* sizes, int32_t nsizes);
+LBM_API int lbm_balance_end(lbm_ctx ctx, lbm_balance_stats* out);
+
 /* Optional outputs of the balance for the statistics as the paper presents
  * them (Sec. 3, Table 1; PDFs of Figs. 6-8 and 11-13; pooling over the 25
  * configurations of Sec. 4-5).  Zero-initialise and set what is wanted. */

@@ -131,6 +131,8 @@ SIGNATURES = {
                                    C.POINTER(_I32), _I32, _DP, _P]),
     "lbm_subvolume_balance_ex": (_I, [_P, C.POINTER(_I32), _I32, C.POINTER(BalanceStats), _P,
                                       C.POINTER(_I32), _I32, _DP, _P, C.POINTER(BalanceExtra)]),
+    "lbm_balance_begin": (_I, [_P, C.POINTER(_I32), _I32]),
+    "lbm_balance_end": (_I, [_P, C.POINTER(BalanceStats)]),
     "lbm_energy_spectrum": (_I, [_P, _DP, _I32]),
     "lbm_relaxation": (_I, [_P, _P, _P]),
     "lbm_spectrum_workspace_bytes": (_I, [_I32, _I32, C.POINTER(_SZ)]),

@@ -113,6 +113,12 @@ struct lbm_ctx_s {
   PopLayout lay{};
   EdmModes edm_md{};  // damped modes (exact-difference scheme)
   EdmWs edm{};
+  // balance running beside the steps (lbm_balance_begin / lbm_balance_end)
+  hipStream_t bal_stream = nullptr;
+  hipEvent_t bal_snap = nullptr, bal_done = nullptr;
+  double* bal_host = nullptr;  // pinned statistics of the running balance
+  bool bal_pending = false;
+  std::vector<int32_t> bal_sizes;
 };
 
 namespace {
@@ -316,6 +322,16 @@ int collect_timing(lbm_ctx_s* c) {
   return LBM_OK;
 }
 
+// Work on c->stream after this point waits for a running balance: for calls that
+// write the moment history, the current FP64 moments, the total force or the
+// balance workspace, which the balance stream reads.
+int wait_balance(lbm_ctx_s* c) {
+  if (c->bal_pending) LBM_HIP(hipStreamWaitEvent(c->stream, c->bal_done, 0));
+  return LBM_OK;
+}
+
+int balance_input(lbm_ctx_s* c, lbm_balance_input* out);
+
 int moments_into(lbm_ctx_s* c, void* rho, void* ux, void* uy, int out_dtype, double* r64,
                  double* ux64, double* uy64, double* ftx, double* fty, double* scalars8) {
   MomentParams m{};
@@ -501,6 +517,8 @@ int lbm_step(lbm_ctx c, int64_t n) {
     c->cur ^= 1;
     c->t += 1;
   }
+  if (nhist > 0)
+    if (int rc = wait_balance(c)) return rc;
   for (int64_t i = 0; i < nhist; ++i) {
     const int slot = static_cast<int>(c->t & 1);
     if (int rc = enqueue_step(c, c->cur, c->stream, c->hist[slot][0], c->hist[slot][1],
@@ -560,6 +578,57 @@ int lbm_subvolume_balance_ex(lbm_ctx c, const int32_t* sizes, int32_t nsizes, lb
   if (int rc = validate_balance_request(c->cfg.nx, c->cfg.ny, sizes, nsizes, out, windows, nwin,
                                         wterms, extra))
     return rc;
+  if (int rc = wait_balance(c)) return rc;
+  lbm_balance_input in{};
+  if (int rc = balance_input(c, &in)) return rc;
+  return run_balance(in, c->bal, sizes, nsizes, out, dmaps, windows, nwin, wterms, term_fields, extra);
+}
+
+int lbm_balance_begin(lbm_ctx c, const int32_t* sizes, int32_t nsizes) {
+  if (!c) return fail(LBM_E_INVALID, "ctx is NULL");
+  if (!c->cfg.with_balance) return fail(LBM_E_STATE, "handle was created with with_balance = 0");
+  if (c->bal_pending) return fail(LBM_E_STATE, "a balance is running: lbm_balance_end first");
+  if (nsizes < 1) return fail(LBM_E_INVALID, "nsizes must be in [1, %d]", kMaxSizes);
+  lbm_balance_stats dummy{};
+  if (int rc = validate_balance_request(c->cfg.nx, c->cfg.ny, sizes, nsizes, &dummy, nullptr, 0, nullptr))
+    return rc;
+  if (!c->bal_stream) {
+    LBM_HIP(hipStreamCreateWithFlags(&c->bal_stream, hipStreamNonBlocking));
+    LBM_HIP(hipEventCreateWithFlags(&c->bal_snap, hipEventDisableTiming));
+    LBM_HIP(hipEventCreateWithFlags(&c->bal_done, hipEventDisableTiming));
+    LBM_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->bal_host), balance_stats_doubles() * sizeof(double),
+                          hipHostMallocDefault));
+  }
+  lbm_balance_input in{};
+  if (int rc = balance_input(c, &in)) return rc;
+  in.stream = c->bal_stream;
+  LBM_HIP(hipEventRecord(c->bal_snap, c->stream));
+  LBM_HIP(hipStreamWaitEvent(c->bal_stream, c->bal_snap, 0));
+  if (int rc = run_balance_async(in, c->bal, sizes, nsizes, c->bal_host)) return rc;
+  LBM_HIP(hipEventRecord(c->bal_done, c->bal_stream));
+  c->bal_sizes.assign(sizes, sizes + nsizes);
+  c->bal_pending = true;
+  return LBM_OK;
+}
+
+int lbm_balance_end(lbm_ctx c, lbm_balance_stats* out) {
+  if (!c) return fail(LBM_E_INVALID, "ctx is NULL");
+  if (!c->bal_pending) return fail(LBM_E_STATE, "no balance is running");
+  if (!out) return fail(LBM_E_INVALID, "out is NULL");
+  LBM_HIP(hipEventSynchronize(c->bal_done));
+  c->bal_pending = false;
+  fill_balance_stats(c->bal_host, c->bal_sizes.data(), static_cast<int>(c->bal_sizes.size()), out);
+  return LBM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+// The balance input at the current time t: FP64 moments of t (with the total
+// force and, for the entropic collision, the effective viscosity), the recorded
+// moments of t-1 and t-2.  Enqueued on c->stream; synchronises to check the
+// moments (LBM_E_DIVERGED).
+int balance_input(lbm_ctx_s* c, lbm_balance_input* out) {
   const int64_t t = c->t;
   if (t < 2 || c->hist_t[(t - 1) & 1] != t - 1 || c->hist_t[(t - 2) & 1] != t - 2)
     return fail(LBM_E_STATE, "balance at t = %lld needs the moments of steps t-1 and t-2",
@@ -569,7 +638,7 @@ int lbm_subvolume_balance_ex(lbm_ctx c, const int32_t* sizes, int32_t nsizes, lb
   int rc = moments_into(c, nullptr, nullptr, nullptr, LBM_F64, c->mom[0], c->mom[1], c->mom[2],
                         forced ? c->ftot[0] : nullptr, forced ? c->ftot[1] : nullptr, sc);
   if (rc) return rc;
-  lbm_balance_input in{};
+  lbm_balance_input& in = *out;
   in.nx = c->cfg.nx;
   in.ny = c->cfg.ny;
   in.nu = (c->cfg.tau - 0.5) / 3.0;
@@ -591,8 +660,11 @@ int lbm_subvolume_balance_ex(lbm_ctx c, const int32_t* sizes, int32_t nsizes, lb
       return rc2;
     in.nu_field = c->ftot[0];
   }
-  return run_balance(in, c->bal, sizes, nsizes, out, dmaps, windows, nwin, wterms, term_fields, extra);
+  return LBM_OK;
 }
+}  // namespace
+
+extern "C" {
 
 int lbm_balance_workspace_bytes(int32_t nx, int32_t ny, size_t* bytes) {
   if (nx < 16 || ny < 16 || nx > 65536 || ny > 65536)
@@ -647,6 +719,7 @@ int lbm_energy_spectrum(lbm_ctx c, double* spectrum, int32_t nshells) {
   if (!spectrum) return fail(LBM_E_INVALID, "spectrum is NULL");
   if (nshells < 1 || nshells > LBM_MAX_SHELLS)
     return fail(LBM_E_INVALID, "nshells must be in [1, %d]", LBM_MAX_SHELLS);
+  if (int rc = wait_balance(c)) return rc;
   if (int rc = moments_into(c, nullptr, nullptr, nullptr, LBM_F64, c->mom[0], c->mom[1], c->mom[2],
                             nullptr, nullptr, nullptr))
     return rc;
@@ -709,6 +782,7 @@ int lbm_load(lbm_ctx c, const void* src) {
   LBM_HIP(hipMemcpyAsync(h, d, sizeof(h), hipMemcpyDeviceToHost, c->stream));
   LBM_HIP(hipStreamSynchronize(c->stream));
   if (h[0] != 0x4c424d32) return fail(LBM_E_INVALID, "not a saved state of this library");
+  if (int rc = wait_balance(c)) return rc;
   const size_t pb = 9 * c->plane * elem_size(c->cfg.dtype);
   LBM_HIP(hipMemcpyAsync(c->pop[0], d + kHeader, pb, hipMemcpyDeviceToDevice, c->stream));
   size_t off = kHeader + pb;
@@ -848,6 +922,7 @@ int lbm_step_time(lbm_ctx c, double* ms, int64_t* launches, int32_t reset) {
 
 int lbm_destroy(lbm_ctx c) {
   if (!c) return LBM_OK;
+  if (c->bal_stream) (void)hipStreamSynchronize(c->bal_stream);
   (void)hipStreamSynchronize(c->stream);
   drop_graphs(c);
   for (auto& pr : c->ev_pending) {
@@ -856,6 +931,12 @@ int lbm_destroy(lbm_ctx c) {
   }
   for (auto e : c->ev_free) (void)hipEventDestroy(e);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  if (c->bal_stream) {
+    (void)hipEventDestroy(c->bal_snap);
+    (void)hipEventDestroy(c->bal_done);
+    (void)hipStreamDestroy(c->bal_stream);
+    (void)hipHostFree(c->bal_host);
+  }
   delete c;
   return LBM_OK;
 }

@@ -1010,6 +1010,71 @@ int validate_balance_extra(int nsizes, const lbm_balance_stats* out, const lbm_b
   return LBM_OK;
 }
 
+namespace {
+
+// Statistics over every corner for each box side: window kernels, the merge of
+// their partials into ws.stats, then the pool (started anew unless acc).
+int corner_stats(const SatView& v, const BalanceWs& ws, const int32_t* sizes, int nsizes, double* dmaps,
+                 bool hist, int ne, unsigned long long* hall, size_t hslot, int acc, hipStream_t s) {
+  const int nx = v.nx, ny = v.ny;
+  const size_t plane = static_cast<size_t>(nx) * ny;
+  for (int k = 0; k < nsizes; ++k) {
+    const int L = sizes[k];
+    double* maps = dmaps ? dmaps + static_cast<size_t>(k) * 3 * plane : nullptr;
+    unsigned long long* hk = hall + static_cast<size_t>(k) * hslot;
+    if (L == nx && L == ny) {
+      if (int rc = launch_windows(hist, v, L, nullptr, 1, 1, maps, ws.partials, ws.edges, ne, hk, s))
+        return rc;
+      hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(kWinThreads), 0, s, ws.partials, 1,
+                         ws.stats + static_cast<size_t>(k) * kStatVals);
+      LBM_HIP(hipGetLastError());
+      continue;
+    }
+    const StrideGrid g = stride_grid(nx, ny, L);
+    if (3 * g.blocks * kSumVals > static_cast<long long>(ws.partials_cap))
+      return fail(LBM_E_INVALID, "box side %d: window partials exceed the workspace", L);
+    const int nb = static_cast<int>(g.blocks);
+    const int per_xcd = (3 * nb + 7) / 8;
+    if (hist)
+      hipLaunchKernelGGL(k_windows_strided<true>, dim3(per_xcd * 8), dim3(256), 0, s, v, L, g.strips, g.S,
+                         nb, per_xcd, maps, ws.partials, ws.edges, ne, hk);
+    else
+      hipLaunchKernelGGL(k_windows_strided<false>, dim3(per_xcd * 8), dim3(256), 0, s, v, L, g.strips, g.S,
+                         nb, per_xcd, maps, ws.partials, ws.edges, ne, hk);
+    LBM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_sum_stats_final, dim3(1), dim3(256), 0, s, ws.partials, 3 * nb,
+                       ws.stats + static_cast<size_t>(k) * kStatVals);
+    LBM_HIP(hipGetLastError());
+  }
+  if (nsizes > 0) {
+    hipLaunchKernelGGL(k_stats_pool, dim3((3 * nsizes + 63) / 64), dim3(64), 0, s, ws.stats, ws.pool,
+                       3 * nsizes, acc);
+    LBM_HIP(hipGetLastError());
+  }
+  return LBM_OK;
+}
+
+}  // namespace
+
+int run_balance_async(const lbm_balance_input& in, const BalanceWs& ws, const int32_t* sizes, int nsizes,
+                      double* host_stats) {
+  hipStream_t s = static_cast<hipStream_t>(in.stream);
+  if (int rc = balance_terms(in, ws)) return rc;
+  if (int rc = field_means(ws.terms, NT, in.nx, in.ny, ws.partials + ws.partials_cap, ws.means, s)) return rc;
+  if (int rc = sat_build(ws.terms, NT, ws.means, ws.sat, in.nx, in.ny, s)) return rc;
+  SatView v{ws.sat, ws.means, in.nx, in.ny, NT};
+  if (int rc = corner_stats(v, ws, sizes, nsizes, nullptr, false, 0, ws.hist, 0, 0, s)) return rc;
+  LBM_HIP(hipMemcpyAsync(host_stats, ws.pool, static_cast<size_t>(nsizes) * kStatVals * sizeof(double),
+                         hipMemcpyDeviceToHost, s));
+  return LBM_OK;
+}
+
+void fill_balance_stats(const double* host_stats, const int32_t* sizes, int nsizes, lbm_balance_stats* out) {
+  for (int k = 0; k < nsizes; ++k) fill_stats(host_stats + static_cast<size_t>(k) * kStatVals, sizes[k], out[k]);
+}
+
+size_t balance_stats_doubles() { return static_cast<size_t>(kMaxSizes) * kStatVals; }
+
 int run_balance(const lbm_balance_input& in, const BalanceWs& ws, const int32_t* sizes,
                 int nsizes, lbm_balance_stats* out, double* dmaps, const int32_t* windows,
                 int nwin, double* wterms, double* term_fields, const lbm_balance_extra* extra) {
@@ -1040,41 +1105,8 @@ int run_balance(const lbm_balance_input& in, const BalanceWs& ws, const int32_t*
   }
 
   SatView v{ws.sat, ws.means, nx, ny, NT};
-  if (out) {
-    for (int k = 0; k < nsizes; ++k) {
-      const int L = sizes[k];
-      double* maps = dmaps ? dmaps + static_cast<size_t>(k) * 3 * plane : nullptr;
-      unsigned long long* hk = hall + static_cast<size_t>(k) * hslot;
-      if (L == nx && L == ny) {
-        if (int rc = launch_windows(hist, v, L, nullptr, 1, 1, maps, ws.partials, ws.edges, ne, hk, s))
-          return rc;
-        hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(kWinThreads), 0, s, ws.partials, 1,
-                           ws.stats + static_cast<size_t>(k) * kStatVals);
-        LBM_HIP(hipGetLastError());
-        continue;
-      }
-      const StrideGrid g = stride_grid(nx, ny, L);
-      if (3 * g.blocks * kSumVals > static_cast<long long>(ws.partials_cap))
-        return fail(LBM_E_INVALID, "box side %d: window partials exceed the workspace", L);
-      const int nb = static_cast<int>(g.blocks);
-      const int per_xcd = (3 * nb + 7) / 8;
-      if (hist)
-        hipLaunchKernelGGL(k_windows_strided<true>, dim3(per_xcd * 8), dim3(256), 0, s, v, L, g.strips, g.S,
-                           nb, per_xcd, maps, ws.partials, ws.edges, ne, hk);
-      else
-        hipLaunchKernelGGL(k_windows_strided<false>, dim3(per_xcd * 8), dim3(256), 0, s, v, L, g.strips, g.S,
-                           nb, per_xcd, maps, ws.partials, ws.edges, ne, hk);
-      LBM_HIP(hipGetLastError());
-      hipLaunchKernelGGL(k_sum_stats_final, dim3(1), dim3(256), 0, s, ws.partials, 3 * nb,
-                         ws.stats + static_cast<size_t>(k) * kStatVals);
-      LBM_HIP(hipGetLastError());
-    }
-    if (nsizes > 0) {
-      hipLaunchKernelGGL(k_stats_pool, dim3((3 * nsizes + 63) / 64), dim3(64), 0, s, ws.stats, ws.pool,
-                         3 * nsizes, acc);
-      LBM_HIP(hipGetLastError());
-    }
-  }
+  if (out)
+    if (int rc = corner_stats(v, ws, sizes, nsizes, dmaps, hist, ne, hall, hslot, acc, s)) return rc;
   if (sampled) {
     size_t off = 0;
     for (int k = 0; k < nsizes; ++k) {

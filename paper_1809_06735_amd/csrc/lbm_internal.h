@@ -214,5 +214,12 @@ int run_balance(const lbm_balance_input& in, const BalanceWs& ws, const int32_t*
                 int nsizes, lbm_balance_stats* out, double* dmaps, const int32_t* windows,
                 int nwin, double* wterms, double* term_fields, const lbm_balance_extra* extra);
 int validate_balance_extra(int nsizes, const lbm_balance_stats* out, const lbm_balance_extra* extra);
+// The all-corner statistics of run_balance, enqueued on in.stream without waiting: the
+// statistics (kMaxSizes x 18 doubles at most) land in host_stats (pinned) when the stream
+// reaches the end; fill_balance_stats turns them into lbm_balance_stats.
+int run_balance_async(const lbm_balance_input& in, const BalanceWs& ws, const int32_t* sizes, int nsizes,
+                      double* host_stats);
+void fill_balance_stats(const double* host_stats, const int32_t* sizes, int nsizes, lbm_balance_stats* out);
+size_t balance_stats_doubles();
 
 }  // namespace lbm

@@ -256,6 +256,19 @@ class Simulation:
                 "lbm_subvolume_balance_ex")
         return ex.into(_balance_result(sizes, out, dm, nwin, wterms, tf, self.nx, self.ny))
 
+    def balance_begin(self, sizes):
+        """Start the all-corner balance statistics of the current time on the library's
+        second stream; steps issued afterwards overlap with it.  balance_end() returns
+        {'stats': [...]} exactly as balance(sizes) would have."""
+        self._bal_sizes = [int(v) for v in sizes]
+        sz = (C.c_int32 * max(1, len(self._bal_sizes)))(*self._bal_sizes)
+        L.check(self._lib.lbm_balance_begin(self._h, sz, len(self._bal_sizes)), "lbm_balance_begin")
+
+    def balance_end(self):
+        out = (L.BalanceStats * max(1, len(self._bal_sizes)))()
+        L.check(self._lib.lbm_balance_end(self._h, out), "lbm_balance_end")
+        return {"stats": [stats_to_dict(out[k]) for k in range(len(self._bal_sizes))]}
+
     def window_series(self, windows, every, count):
         """Balance of explicit windows (x0, y0, L) sampled every `every` (>= 2) steps,
         `count` times: the time series of one sub-volume's balance of Sec. 3 (Figs. 1-2).

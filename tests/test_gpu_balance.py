@@ -369,3 +369,50 @@ def test_energy_spectrum_of_a_run(gpu_lib):
     err = np.abs(got - want).max() / want.max()
     say(f"run spectrum rel err {err:.1e}")
     assert err < 1e-11
+
+
+def test_balance_beside_the_steps_equals_the_balance_in_line(gpu_lib):
+    """lbm_balance_begin / lbm_balance_end: the statistics computed on the second stream while
+    the next steps run are bit-identical to lbm_subvolume_balance at the same time, the steps
+    are not disturbed, and the calls keep their order rules."""
+    from paper_1809_06735_amd import Simulation, _lib as L
+    n, sizes = 256, (4, 16, 64, 255, 256)
+    fx, fy = inp.forcing_field(n, seed=2, max_force=2e-5)
+    rho, ux, uy = np.ones((n, n)), np.zeros((n, n)), np.zeros((n, n))
+
+    def make():
+        return Simulation(rho, ux, uy, 0.52, dtype="f32", fx=fx, fy=fy, alpha=1e-4, with_balance=True)
+
+    a, b, c = make(), make(), make()
+    with pytest.raises(L.LBMError) as e:
+        a.balance_begin(sizes)  # no recorded history yet
+    assert e.value.code == L.LBM_E_STATE
+    with pytest.raises(L.LBMError) as e:
+        a.balance_end()
+    assert e.value.code == L.LBM_E_STATE
+    got, want = [], []
+    for k in range(3):
+        a.step(40 + 10 * k)
+        b.step(40 + 10 * k)
+        c.step(40 + 10 * k)
+        if k:
+            got.append(a.balance_end())
+        a.balance_begin(sizes)
+        if k == 1:
+            with pytest.raises(L.LBMError) as e:
+                a.balance_begin(sizes)
+            assert e.value.code == L.LBM_E_STATE
+        want.append(b.balance(sizes))
+    a.step(7)  # history-recording steps wait for the running balance
+    got.append(a.balance_end())
+    b.step(7)
+    c.step(7)
+    for g, w in zip(got, want):
+        assert g["stats"] == w["stats"]
+    assert torch.equal(a.save(), c.save())
+    # a balance in line while one runs beside: both correct
+    a.balance_begin(sizes)
+    r_sync = a.balance(sizes)
+    r_async = a.balance_end()
+    assert r_sync["stats"] == r_async["stats"] == b.balance(sizes)["stats"]
+    say("balance beside the steps: bit-identical statistics, undisturbed state")
