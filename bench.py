@@ -412,11 +412,11 @@ def main():
     alg_bytes = bytes_per_site * n * n        # per launch, whatever the steps fused
     achieved = alg_bytes / avg_launch_s / 1e9
     traffic = traffic_from_profile(kernel, "forced4096", tile)
-    # the same kernel alone on the GPU (no balance beside it): 60 bulk launches
+    # the same kernel alone on the GPU (no balance beside it): 64 bulk launches, one graph
     torch.cuda.synchronize()
     sim.step_time(reset=True)
     sim.step_timing(True)
-    sim.step(60 * spl + 2)
+    sim.step(64 * spl + 2)
     torch.cuda.synchronize()
     sim.step_timing(False)
     alone_ms, alone_n = sim.step_time(reset=True)
