@@ -254,6 +254,7 @@ def d3q19_256(log, n=256, tau=0.52, steps=200):
     fx, fy, fz = inp.force3(shape, seed=0, amp=1e-6)
     sim = Simulation3D(rho, ux, uy, uz, tau, dtype="f32", fx=fx, fy=fy, fz=fz, with_balance=True)
     del rho, ux, uy, uz, fx, fy, fz
+    tile = sim.autotune(3)  # one step per launch, or 2..4 steps per launch (temporal blocking)
     sim.step(10)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -264,10 +265,10 @@ def d3q19_256(log, n=256, tau=0.52, steps=200):
     ms = e0.elapsed_time(e1) / steps
     sites = n ** 3
     gbs = 164 * sites / (ms * 1e-3) / 1e9
-    out = {"grid": [n, n, n], "dtype": "f32", "steps": steps, "ms_per_step": round(ms, 4),
+    out = {"grid": [n, n, n], "dtype": "f32", "steps": steps, "shape": list(tile), "ms_per_step": round(ms, 4),
            "MLUPS": round(sites / (ms * 1e-3) / 1e6, 1), "kernel_GBps": round(gbs, 1),
            "frac_of_8TBps": round(gbs / HBM_PEAK_GBS, 4),
-           "traffic": traffic_from_profile("k3_step", "d3q19_256", ["rows", "nt"])}
+           "traffic": traffic_from_profile("k3_step", "d3q19_256", ["rows", "nt"]) if tile[0] == 1 else None}
     sizes = (16, 64, 256)
     t0 = time.perf_counter()
     res = sim.balance(sizes)

@@ -532,6 +532,16 @@ enum {
   LBM3_T_USQ, LBM3_NTERMS
 };
 
+/* Launch shape of the bulk of lbm3_step.  fuse = 1: one step per launch (the
+ * other fields are ignored).  fuse = 2..4: that many steps per launch
+ * (temporal blocking; bit-identical to one-step launches): workgroups of
+ * bx * by lanes (a multiple of 64, at most 512, with 2 * 16 * bx * by values of
+ * LDS at most 64 KiB) each update a tile of (bx - 2 (fuse - 1)) x
+ * (by - 2 (fuse - 1)) columns over a band of bz planes. */
+typedef struct {
+  int32_t fuse, bx, by, bz;
+} lbm3_tile;
+
 /* Bytes of device workspace lbm3_init needs for cfg.  Host call. */
 LBM_API int lbm3_workspace_bytes(const lbm3_config* cfg, size_t* bytes);
 
@@ -546,7 +556,8 @@ LBM_API int lbm3_init(const lbm3_config* cfg, void* ws, size_t ws_bytes, const d
                       const double* fy, const double* fz, lbm3_ctx* out);
 
 /* Advance n >= 0 steps (pull streaming fused with the BGK collision and Guo's
- * term, one launch per step); the last two steps record (rho, u) for the time
+ * term; the bulk in launches of the lbm3_tile shape, the remainder and the last
+ * two steps one per launch); the last two steps record (rho, u) for the time
  * derivative of the balance.  Asynchronous. */
 LBM_API int lbm3_step(lbm3_ctx ctx, int64_t n);
 
@@ -560,6 +571,13 @@ LBM_API int lbm3_moments(lbm3_ctx ctx, double* rho, double* ux, double* uy, doub
                          double* scalars9);
 
 LBM_API int lbm3_time(lbm3_ctx ctx, int64_t* t);
+
+/* Bulk launch shape (lbm3_tile); LBM_E_INVALID for a shape that does not fit. */
+LBM_API int lbm3_set_tile(lbm3_ctx ctx, const lbm3_tile* tile);
+LBM_API int lbm3_get_tile(lbm3_ctx ctx, lbm3_tile* tile);
+/* Time every candidate shape (trial_launches launches each, per step, from the
+ * current state without changing it) and keep the fastest.  Synchronous. */
+LBM_API int lbm3_autotune(lbm3_ctx ctx, int32_t trial_launches, lbm3_tile* chosen);
 
 /* The 3D sub-volume balance at the current time t (handle with
  * with_balance = 1, t >= 2 with the two preceding steps recorded, else

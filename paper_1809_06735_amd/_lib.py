@@ -107,6 +107,10 @@ class AdjointConfig(C.Structure):
 _P = C.c_void_p
 _I = C.c_int
 _I32 = C.c_int32
+class Tile3(C.Structure):
+    _fields_ = [("fuse", C.c_int32), ("bx", C.c_int32), ("by", C.c_int32), ("bz", C.c_int32)]
+
+
 class Config3(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("dtype", C.c_int32),
                 ("has_force", C.c_int32), ("with_balance", C.c_int32), ("tau", C.c_double),
@@ -179,6 +183,9 @@ SIGNATURES = {
     "lbm3_time": (_I, [_P, C.POINTER(_I64)]),
     "lbm3_subvolume_balance": (_I, [_P, C.POINTER(_I32), _I32, C.POINTER(BalanceStats), _P]),
     "lbm3_destroy": (_I, [_P]),
+    "lbm3_set_tile": (_I, [_P, C.POINTER(Tile3)]),
+    "lbm3_get_tile": (_I, [_P, C.POINTER(Tile3)]),
+    "lbm3_autotune": (_I, [_P, _I32, C.POINTER(Tile3)]),
 }
 
 _lock = threading.Lock()

@@ -20,6 +20,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 #include "lbm_internal.h"
@@ -60,6 +61,85 @@ struct Step3 {
   double omega;
 };
 
+// 1/x: IEEE division in FP64; in FP32 the hardware reciprocal refined by one
+// Newton step (within an ulp of the quotient, a third of the instructions).
+template <typename T>
+__device__ __forceinline__ T recip3(T x) {
+  if constexpr (sizeof(T) == 4) {
+    const float r = __builtin_amdgcn_rcpf(x);
+    return __builtin_fmaf(r, __builtin_fmaf(-x, r, 1.0f), r);
+  } else {
+    return T(1) / x;
+  }
+}
+
+// Moments and BGK collision with Guo's term of one site in deviation form,
+// shared by the one-step and the multi-step kernels (same operations in the
+// same order, so both give the same bits).  Opposite velocities l, lbar (stored
+// next to each other) share the weight and the parts of omega d^eq + G that are
+// even in c, and see the odd parts with opposite signs.  With cu = c.u,
+// cF = c.F and g = 1 - omega/2:
+//   even  S = w B0 + 3 w cu (1.5 omega rho cu + 3 g cF),
+//         B0 = omega (drho - 1.5 rho |u|^2) - 3 g u.F,
+//   odd   A = w (3 omega rho cu + 3 g cF),
+// f*_l = (1 - omega) d_l + S + A, f*_lbar = (1 - omega) d_lbar + S - A.
+template <typename T, bool FORCE>
+__device__ __forceinline__ void collide3(const T (&d)[Q3], T Fx, T Fy, T Fz, T om, T (&o)[Q3], T& rho, T& ux,
+                                         T& uy, T& uz) {
+  const T drho = (((d[0] + (d[1] + d[2])) + ((d[3] + d[4]) + (d[5] + d[6]))) +
+                  (((d[7] + d[8]) + (d[9] + d[10])) + ((d[11] + d[12]) + (d[13] + d[14])))) +
+                 ((d[15] + d[16]) + (d[17] + d[18]));
+  const T jx = ((d[1] - d[2]) + (d[7] - d[8])) + (((d[9] - d[10]) + (d[11] - d[12])) + (d[13] - d[14]));
+  const T jy = ((d[3] - d[4]) + (d[7] - d[8])) + (((d[10] - d[9]) + (d[15] - d[16])) + (d[17] - d[18]));
+  const T jz = ((d[5] - d[6]) + (d[11] - d[12])) + (((d[14] - d[13]) + (d[15] - d[16])) + (d[18] - d[17]));
+  rho = T(1) + drho;
+  const T inv = recip3<T>(rho);
+  if constexpr (FORCE) {
+    ux = (jx + T(0.5) * Fx) * inv;
+    uy = (jy + T(0.5) * Fy) * inv;
+    uz = (jz + T(0.5) * Fz) * inv;
+  } else {
+    ux = jx * inv;
+    uy = jy * inv;
+    uz = jz * inv;
+  }
+  const T om1 = T(1) - om;
+  const T b = drho - rho * (T(1.5) * ((ux * ux + uy * uy) + uz * uz));
+  const T wa = T(w3(1)), we = T(w3(7));
+  const T p3 = (T(1.5) * om) * rho;
+  const T wRa = (T(3) * om * wa) * rho, wRe = (T(3) * om * we) * rho;
+  T B0 = om * b;
+  T g3 = T(0);
+  if constexpr (FORCE) {
+    g3 = T(3) * (T(1) - T(0.5) * om);
+    B0 = B0 - g3 * ((ux * Fx + uy * Fy) + uz * Fz);
+  }
+  const T wBa = wa * B0, wBe = we * B0;
+  o[0] = om1 * d[0] + T(w3(0)) * B0;
+  auto pair = [&](int l, int lb, T cu, T cF, T w, T wB, T wR) {
+    T S, A;
+    if constexpr (FORCE) {
+      const T gc = g3 * cF;
+      S = (T(3) * w) * (cu * (p3 * cu + gc)) + wB;
+      A = wR * cu + w * gc;
+    } else {
+      S = (T(3) * w) * (cu * (p3 * cu)) + wB;
+      A = wR * cu;
+    }
+    o[l] = om1 * d[l] + (S + A);
+    o[lb] = om1 * d[lb] + (S - A);
+  };
+  pair(1, 2, ux, Fx, wa, wBa, wRa);
+  pair(3, 4, uy, Fy, wa, wBa, wRa);
+  pair(5, 6, uz, Fz, wa, wBa, wRa);
+  pair(7, 8, ux + uy, Fx + Fy, we, wBe, wRe);
+  pair(9, 10, ux - uy, Fx - Fy, we, wBe, wRe);
+  pair(11, 12, ux + uz, Fx + Fz, we, wBe, wRe);
+  pair(13, 14, ux - uz, Fx - Fz, we, wBe, wRe);
+  pair(15, 16, uy + uz, Fy + Fz, we, wBe, wRe);
+  pair(17, 18, uy - uz, Fy - Fz, we, wBe, wRe);
+}
+
 template <typename T, bool FORCE>
 __global__ void __launch_bounds__(256) k3_step(Step3 p) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -74,15 +154,6 @@ __global__ void __launch_bounds__(256) k3_step(Step3 p) {
     const int xs = wrap(x - c3(l, 0), nx), ys = wrap(y - c3(l, 1), ny), zs = wrap(z - c3(l, 2), nz);
     d[l] = __builtin_nontemporal_load(src + pop_at(l, zs, ys, xs, ny, nx));
   }
-  T drho = T(0), jx = T(0), jy = T(0), jz = T(0);
-#pragma unroll
-  for (int l = 0; l < Q3; ++l) {
-    drho += d[l];
-    if (c3(l, 0)) jx += c3(l, 0) * d[l];
-    if (c3(l, 1)) jy += c3(l, 1) * d[l];
-    if (c3(l, 2)) jz += c3(l, 2) * d[l];
-  }
-  const T rho = T(1) + drho;
   const size_t i = (static_cast<size_t>(z) * ny + y) * nx + x;
   T Fx = T(0), Fy = T(0), Fz = T(0);
   if constexpr (FORCE) {
@@ -90,31 +161,191 @@ __global__ void __launch_bounds__(256) k3_step(Step3 p) {
     Fy = static_cast<const T*>(p.fy)[i];
     Fz = static_cast<const T*>(p.fz)[i];
   }
-  const T inv = T(1) / rho;
-  const T ux = (jx + T(0.5) * Fx) * inv, uy = (jy + T(0.5) * Fy) * inv, uz = (jz + T(0.5) * Fz) * inv;
-  const T om = T(p.omega);
-  const T usq15 = T(1.5) * (ux * ux + uy * uy + uz * uz);
-  const T g = T(1) - T(0.5) * om;
+  T o[Q3], rho, ux, uy, uz;
+  collide3<T, FORCE>(d, Fx, Fy, Fz, T(p.omega), o, rho, ux, uy, uz);
 #pragma unroll
-  for (int l = 0; l < Q3; ++l) {
-    const T cx = T(c3(l, 0)), cy = T(c3(l, 1)), cz = T(c3(l, 2));
-    const T cu = cx * ux + cy * uy + cz * uz;
-    const T w = T(w3(l));
-    const T deq = w * (drho + rho * (T(3) * cu + T(4.5) * cu * cu - usq15));
-    T o = d[l] - om * (d[l] - deq);
-    if constexpr (FORCE) {
-      const T gx = T(3) * (cx - ux) + T(9) * cu * cx;
-      const T gy = T(3) * (cy - uy) + T(9) * cu * cy;
-      const T gz = T(3) * (cz - uz) + T(9) * cu * cz;
-      o += g * w * (gx * Fx + gy * Fy + gz * Fz);
-    }
-    __builtin_nontemporal_store(o, dst + pop_at(l, z, y, x, ny, nx));
-  }
+  for (int l = 0; l < Q3; ++l) __builtin_nontemporal_store(o[l], dst + pop_at(l, z, y, x, ny, nx));
   if (p.h[0]) {
     p.h[0][i] = double(rho);
     p.h[1][i] = double(ux);
     p.h[2][i] = double(uy);
     p.h[3][i] = double(uz);
+  }
+}
+
+// ---- K steps per launch (temporal blocking) ---------------------------------------------
+// A workgroup of bx * by lanes owns an (x, y) tile of (bx - 2 (K - 1)) x (by - 2 (K - 1))
+// output columns and a band of bz planes, and marches up the band one plane per
+// iteration; lane (lx, ly) holds column (x0 - (K - 1) + lx, y0 - (K - 1) + ly), so the
+// tile and its K - 1 halo columns on every side are one run of lanes.  Level s = 1..K of
+// an iteration advances one plane by one step: level 1 pulls from the source state in
+// HBM exactly as the one-step kernel does, level s > 1 collides the output of level
+// s - 1.  A level's 16 populations with c_x or c_y != 0 reach the neighbouring lanes
+// through LDS (two buffers used alternately, one barrier per level); the pull in z is
+// a delay in registers: level s works one plane below level s - 1, takes the c_z = -1
+// populations of level s - 1's current plane, the c_z = 0 ones of its previous plane and
+// the c_z = +1 ones of the plane before (two register sets whose roles alternate with the
+// iteration's parity).  Level s exists on the lanes at least s - 1 away from the edges of
+// the tile's run, and only level K writes to HBM: K updates cost one read and one write
+// of every population and one read of the force, with the same per-site arithmetic as K
+// one-step launches (bit-identical results).
+struct Fused3 {
+  const void* src;
+  void* dst;
+  const void* fx;
+  const void* fy;
+  const void* fz;
+  int nx, ny, nz;
+  int bx, by, bz;         // lanes in x and y, band height
+  int tiles_x, tiles_y;   // output tiles of (bx - 2 (K - 1)) x (by - 2 (K - 1)) columns
+  int total;              // tiles_x * tiles_y * bands
+  double omega;
+};
+
+// the 16 populations with c_x or c_y != 0, in LDS slot order
+__host__ __device__ constexpr int kXY[16] = {1, 2, 3, 4, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18};
+// c_z = 0 (carried one iteration) and c_z = +1 (carried two iterations)
+__host__ __device__ constexpr int kZ0[9] = {0, 1, 2, 3, 4, 7, 8, 9, 10};
+__host__ __device__ constexpr int kZP[5] = {5, 11, 14, 15, 18};
+
+template <typename T, int K>
+struct Carry3 {
+  T z0[9];       // level s - 1, previous plane, c_z = 0 populations (pulled in x, y)
+  T zp[2][5];    // level s - 1, the two previous planes, c_z = +1 populations
+  T f[3];        // force at level s's plane
+};
+
+template <typename T, int K, bool FORCE>
+__global__ void __launch_bounds__(512) k3_step_fused(Fused3 p) {
+  extern __shared__ unsigned char smem3[];
+  T* const lds = reinterpret_cast<T*>(smem3);
+  const int lanes = p.bx * p.by;
+  const int ox = p.bx - 2 * (K - 1), oy = p.by - 2 * (K - 1);
+  int b = blockIdx.x;
+  if (b >= p.total) return;  // uniform over the workgroup
+  const int tx = b % p.tiles_x;
+  b /= p.tiles_x;
+  const int ty = b % p.tiles_y;
+  const int tz = b / p.tiles_y;
+  const int nx = p.nx, ny = p.ny, nz = p.nz;
+  const int x0 = tx * ox, y0 = ty * oy, z0 = tz * p.bz;
+  const int weff = min(ox, nx - x0), heff = min(oy, ny - y0), deff = min(p.bz, nz - z0);
+  const int nax = weff + 2 * (K - 1), nay = heff + 2 * (K - 1);
+  const int t = threadIdx.x;
+  const int lx = t % p.bx, ly = t / p.bx;
+  int top = 0, x = x0, y = y0;
+  if (lx < nax && ly < nay) {
+    top = min(min(min(lx, nax - 1 - lx), min(ly, nay - 1 - ly)) + 1, K);
+    x = wrap(x0 - (K - 1) + lx, nx);
+    y = wrap(y0 - (K - 1) + ly, ny);
+  }
+  const int xm = wrap(x - 1, nx), xp = wrap(x + 1, nx), ym = wrap(y - 1, ny), yp = wrap(y + 1, ny);
+  const T* __restrict__ src = static_cast<const T*>(p.src);
+  T* __restrict__ dst = static_cast<T*>(p.dst);
+  const T* __restrict__ gfx = static_cast<const T*>(p.fx);
+  const T* __restrict__ gfy = static_cast<const T*>(p.fy);
+  const T* __restrict__ gfz = static_cast<const T*>(p.fz);
+  const T om = T(p.omega);
+
+  // level 1 input of plane zl: f_l(x - c_l) of the source state, and the force there
+  auto load_plane = [&](int zl, T (&d)[Q3], T (&f)[3]) {
+    const int z = wrap(zl, nz), zmn = wrap(zl - 1, nz), zpl = wrap(zl + 1, nz);
+#pragma unroll
+    for (int l = 0; l < Q3; ++l) {
+      const int cx = c3(l, 0), cy = c3(l, 1), cz = c3(l, 2);
+      const int xs = cx == 1 ? xm : (cx == -1 ? xp : x);
+      const int ys = cy == 1 ? ym : (cy == -1 ? yp : y);
+      const int zs = cz == 1 ? zmn : (cz == -1 ? zpl : z);
+      d[l] = __builtin_nontemporal_load(src + pop_at(l, zs, ys, xs, ny, nx));
+    }
+    if constexpr (FORCE) {
+      const size_t i = (static_cast<size_t>(z) * ny + y) * nx + x;
+      f[0] = gfx[i];
+      f[1] = gfy[i];
+      f[2] = gfz[i];
+    } else {
+      f[0] = f[1] = f[2] = T(0);
+    }
+  };
+
+  Carry3<T, K> cy[K - 1];  // inputs of levels 2..K
+#pragma unroll
+  for (int s = 0; s < K - 1; ++s) {
+#pragma unroll
+    for (int j = 0; j < 9; ++j) cy[s].z0[j] = T(0);
+#pragma unroll
+    for (int j = 0; j < 5; ++j) cy[s].zp[0][j] = cy[s].zp[1][j] = T(0);
+    cy[s].f[0] = cy[s].f[1] = cy[s].f[2] = T(0);
+  }
+  T d[Q3], f1[3];
+  const int last = deff + K - 2;
+  load_plane(z0 - (K - 1), d, f1);
+
+  // iteration k: level s works on plane z0 + k - (s - 1), with valid input from
+  // k = 2 s - 1 - K on; level K writes planes z0 .. z0 + deff - 1.  E is the parity
+  // of the iteration count (LDS buffers and the two c_z = +1 register sets).
+  auto iteration = [&](auto parity, int k) {
+    constexpr int E = decltype(parity)::value;
+    constexpr int P0 = ((K - 1) & 1) ? E : 0;
+    T o[Q3], rho, ux, uy, uz;
+    if (top >= 1) collide3<T, FORCE>(d, f1[0], f1[1], f1[2], om, o, rho, ux, uy, uz);
+    T fprev[3] = {f1[0], f1[1], f1[2]};
+    // the next plane's level-1 input: its loads fly while levels 2..K run
+    if (k < last) load_plane(z0 + k + 1, d, f1);
+#pragma unroll
+    for (int s = 2; s <= K; ++s) {
+      T* const slot = lds + ((P0 + s) & 1) * 16 * lanes;
+      if (top >= s - 1) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) slot[j * lanes + t] = o[kXY[j]];
+      }
+      __syncthreads();
+      Carry3<T, K>& c = cy[s - 2];
+      // force of level s's plane: level s - 1's force of the previous iteration
+      const T fs[3] = {c.f[0], c.f[1], c.f[2]};
+      c.f[0] = fprev[0];
+      c.f[1] = fprev[1];
+      c.f[2] = fprev[2];
+      fprev[0] = fs[0];
+      fprev[1] = fs[1];
+      fprev[2] = fs[2];
+      if (k >= 2 * s - 3 - K && top >= s) {  // level s - 1 held valid data
+        // g_l: level s - 1's value of the current plane at (x - c_x, y - c_y)
+        T g[Q3];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          const int l = kXY[j];
+          g[l] = slot[j * lanes + t - c3(l, 0) - c3(l, 1) * p.bx];
+        }
+        g[0] = o[0];
+        g[5] = o[5];
+        g[6] = o[6];
+        if (k >= 2 * s - 1 - K) {
+          T dn[Q3];
+#pragma unroll
+          for (int l = 0; l < Q3; ++l) dn[l] = g[l];  // c_z = -1: the current plane
+#pragma unroll
+          for (int j = 0; j < 9; ++j) dn[kZ0[j]] = c.z0[j];
+#pragma unroll
+          for (int j = 0; j < 5; ++j) dn[kZP[j]] = c.zp[E ^ 1][j];
+          collide3<T, FORCE>(dn, fs[0], fs[1], fs[2], om, o, rho, ux, uy, uz);
+          if (s == K) {
+            const int zo = z0 + k - (K - 1);
+#pragma unroll
+            for (int l = 0; l < Q3; ++l) __builtin_nontemporal_store(o[l], dst + pop_at(l, zo, y, x, ny, nx));
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < 9; ++j) c.z0[j] = g[kZ0[j]];
+#pragma unroll
+        for (int j = 0; j < 5; ++j) c.zp[E ^ 1][j] = g[kZP[j]];
+      }
+    }
+  };
+  for (int k = 1 - K; k <= last; k += 2) {
+    iteration(std::integral_constant<int, 0>(), k);
+    if (k + 1 > last) break;
+    iteration(std::integral_constant<int, 1>(), k + 1);
   }
 }
 
@@ -722,6 +953,7 @@ struct lbm3_ctx_s {
   double* wstat = nullptr;
   int64_t t = 0;
   size_t plane = 0;
+  lbm3_tile tile{1, 0, 0, 0};  // bulk steps: one per launch, or fuse per launch
 };
 
 namespace {
@@ -810,6 +1042,70 @@ int launch3_step(lbm3_ctx_s* c, bool record) {
   if (record) c->hist_t[slot] = c->t;
   c->cur ^= 1;
   c->t += 1;
+  return LBM_OK;
+}
+
+size_t fused3_lds_bytes(const lbm3_tile& t, int dtype) {
+  return static_cast<size_t>(2) * 16 * t.bx * t.by * (dtype == LBM_F64 ? 8 : 4);
+}
+
+bool tile3_ok(const lbm3_tile& t, int dtype) {
+  if (t.fuse == 1) return true;
+  if (t.fuse < 2 || t.fuse > 4) return false;
+  const int lanes = t.bx * t.by;
+  if (t.bx <= 2 * (t.fuse - 1) || t.by <= 2 * (t.fuse - 1) || t.bz < 1 || t.bz > 65536) return false;
+  if (lanes < 64 || lanes > 512 || lanes % 64 != 0) return false;
+  return fused3_lds_bytes(t, dtype) <= 64 * 1024;
+}
+
+template <typename T, int K, bool FORCE>
+void launch_fused3_t(const Fused3& p, size_t lds, hipStream_t s) {
+  hipLaunchKernelGGL((k3_step_fused<T, K, FORCE>), dim3(p.total), dim3(p.bx * p.by), lds, s, p);
+}
+
+template <typename T, bool FORCE>
+void launch_fused3_k(int K, const Fused3& p, size_t lds, hipStream_t s) {
+  switch (K) {
+    case 2: launch_fused3_t<T, 2, FORCE>(p, lds, s); break;
+    case 3: launch_fused3_t<T, 3, FORCE>(p, lds, s); break;
+    default: launch_fused3_t<T, 4, FORCE>(p, lds, s); break;
+  }
+}
+
+// One launch of `tile.fuse` steps (no moment record).
+int launch3_fused(lbm3_ctx_s* c, const lbm3_tile& tl) {
+  const int K = tl.fuse;
+  Fused3 p{};
+  p.src = c->pop[c->cur];
+  p.dst = c->pop[1 - c->cur];
+  p.fx = c->f[0];
+  p.fy = c->f[1];
+  p.fz = c->f[2];
+  p.nx = c->cfg.nx;
+  p.ny = c->cfg.ny;
+  p.nz = c->cfg.nz;
+  p.bx = tl.bx;
+  p.by = tl.by;
+  p.bz = tl.bz;
+  const int ox = tl.bx - 2 * (K - 1), oy = tl.by - 2 * (K - 1);
+  p.tiles_x = (p.nx + ox - 1) / ox;
+  p.tiles_y = (p.ny + oy - 1) / oy;
+  const long long total = static_cast<long long>(p.tiles_x) * p.tiles_y * ((p.nz + tl.bz - 1) / tl.bz);
+  if (total > 0x7fffffffLL) return fail(LBM_E_INVALID, "too many workgroups for this shape");
+  p.total = static_cast<int>(total);
+  p.omega = 1.0 / c->cfg.tau;
+  const size_t lds = fused3_lds_bytes(tl, c->cfg.dtype);
+  const bool force = c->cfg.has_force != 0;
+  if (c->cfg.dtype == LBM_F64) {
+    if (force) launch_fused3_k<double, true>(K, p, lds, c->stream);
+    else launch_fused3_k<double, false>(K, p, lds, c->stream);
+  } else {
+    if (force) launch_fused3_k<float, true>(K, p, lds, c->stream);
+    else launch_fused3_k<float, false>(K, p, lds, c->stream);
+  }
+  LBM_HIP(hipGetLastError());
+  c->cur ^= 1;
+  c->t += K;
   return LBM_OK;
 }
 
@@ -928,8 +1224,83 @@ int lbm3_init(const lbm3_config* cfg, void* ws, size_t ws_bytes, const double* r
 int lbm3_step(lbm3_ctx c, int64_t n) {
   if (!c) return fail(LBM_E_INVALID, "ctx is NULL");
   if (n < 0) return fail(LBM_E_INVALID, "n must be >= 0");
-  for (int64_t k = 0; k < n; ++k)
-    if (int rc = launch3_step(c, k >= n - 2)) return rc;
+  const int64_t nhist = n < 2 ? n : 2;
+  const int64_t plain = n - nhist;
+  const int K = c->tile.fuse;
+  const int64_t bulk = K > 1 ? plain / K : 0;
+  for (int64_t k = 0; k < bulk; ++k)
+    if (int rc = launch3_fused(c, c->tile)) return rc;
+  for (int64_t k = bulk * (K > 1 ? K : 1); k < n; ++k)
+    if (int rc = launch3_step(c, k >= n - nhist)) return rc;
+  return LBM_OK;
+}
+
+int lbm3_set_tile(lbm3_ctx c, const lbm3_tile* tile) {
+  if (!c || !tile) return fail(LBM_E_INVALID, "NULL argument");
+  if (!tile3_ok(*tile, c->cfg.dtype))
+    return fail(LBM_E_INVALID, "3D shape (fuse %d, %d x %d lanes, band %d) not valid", tile->fuse, tile->bx,
+                tile->by, tile->bz);
+  c->tile = *tile;
+  if (c->tile.fuse == 1) c->tile.bx = c->tile.by = c->tile.bz = 0;
+  return LBM_OK;
+}
+
+int lbm3_get_tile(lbm3_ctx c, lbm3_tile* tile) {
+  if (!c || !tile) return fail(LBM_E_INVALID, "NULL argument");
+  *tile = c->tile;
+  return LBM_OK;
+}
+
+int lbm3_autotune(lbm3_ctx c, int32_t trial_launches, lbm3_tile* chosen) {
+  if (!c) return fail(LBM_E_INVALID, "ctx is NULL");
+  if (trial_launches < 1 || trial_launches > 1000) return fail(LBM_E_INVALID, "trial_launches in [1, 1000]");
+  std::vector<lbm3_tile> cand{{1, 0, 0, 0}};
+  const int shapes[6][2] = {{64, 4}, {64, 8}, {32, 8}, {32, 16}, {128, 4}, {16, 16}};
+  const int bands[3] = {16, 32, 64};
+  for (int K = 2; K <= 4; ++K)
+    for (auto& sh : shapes)
+      for (int bz : bands) {
+        lbm3_tile t{K, sh[0], sh[1], bz};
+        if (tile3_ok(t, c->cfg.dtype) && (bz <= c->cfg.nz || bz == 16)) cand.push_back(t);
+      }
+  hipEvent_t e0, e1;
+  LBM_HIP(hipEventCreate(&e0));
+  LBM_HIP(hipEventCreate(&e1));
+  const lbm3_tile saved = c->tile;
+  const int cur = c->cur;
+  const int64_t t0 = c->t;
+  float best = 1e30f;
+  lbm3_tile best_t = saved;
+  int rc = LBM_OK;
+  for (const auto& t : cand) {
+    // src -> dst repeatedly: the state (src) is never modified
+    auto one = [&]() {
+      c->cur = cur;
+      return t.fuse == 1 ? launch3_step(c, false) : launch3_fused(c, t);
+    };
+    if ((rc = one())) break;
+    if (hipEventRecord(e0, c->stream) != hipSuccess) { rc = fail(LBM_E_HIP, "hipEventRecord"); break; }
+    for (int k = 0; k < trial_launches && rc == LBM_OK; ++k) rc = one();
+    if (rc) break;
+    if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+      rc = fail(LBM_E_HIP, "hipEventRecord/Synchronize");
+      break;
+    }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    ms /= static_cast<float>(trial_launches * t.fuse);
+    if (ms < best) {
+      best = ms;
+      best_t = t;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->cur = cur;
+  c->t = t0;
+  c->tile = rc == LBM_OK ? best_t : saved;
+  if (rc) return rc;
+  if (chosen) *chosen = best_t;
   return LBM_OK;
 }
 

@@ -558,6 +558,23 @@ class Simulation3D:
         L.check(self._lib.lbm3_time(self._h, C.byref(t)), "lbm3_time")
         return t.value
 
+    def set_tile(self, fuse, bx=0, by=0, bz=0):
+        """Bulk launch shape: fuse = 1 one step per launch; fuse = 2..4 steps per launch on
+        workgroups of bx x by lanes (tiles of (bx - 2 (fuse - 1)) x (by - 2 (fuse - 1))
+        columns) over bands of bz planes."""
+        t = L.Tile3(int(fuse), int(bx), int(by), int(bz))
+        L.check(self._lib.lbm3_set_tile(self._h, C.byref(t)), "lbm3_set_tile")
+
+    def get_tile(self):
+        t = L.Tile3()
+        L.check(self._lib.lbm3_get_tile(self._h, C.byref(t)), "lbm3_get_tile")
+        return (t.fuse, t.bx, t.by, t.bz)
+
+    def autotune(self, trial_launches=5):
+        t = L.Tile3()
+        L.check(self._lib.lbm3_autotune(self._h, int(trial_launches), C.byref(t)), "lbm3_autotune")
+        return (t.fuse, t.bx, t.by, t.bz)
+
     def moments(self, scalars=True):
         """(rho, ux, uy, uz[, scalars dict]) at the current time, FP64 [nz, ny, nx]."""
         shape = (self.nz, self.ny, self.nx)

@@ -210,3 +210,52 @@ def test_3d_errors(gpu_lib):
     with pytest.raises(L.LBMError) as e:
         plain.balance((4,))
     assert e.value.code == L.LBM_E_STATE
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_3d_multistep_kernel_equals_single_steps(gpu_lib, dtype):
+    """K = 2..4 steps per launch (tiles of lanes marching in z, levels exchanged through LDS)
+    give bit-identical moments to one-step launches: forced and unforced, ragged tiles and
+    bands (one plane), tiles wider than the grid, step counts that leave remainders."""
+    from paper_1809_06735_amd import _lib as L
+    shapes32 = [(2, 64, 4, 16), (2, 32, 8, 5), (3, 32, 8, 7), (3, 16, 16, 1), (4, 32, 16, 9), (4, 16, 16, 64),
+                (2, 128, 4, 3), (3, 64, 8, 2)]
+    shapes64 = [(2, 64, 4, 16), (2, 32, 8, 5), (3, 32, 8, 7), (3, 16, 16, 1), (4, 16, 16, 9)]
+    for shape in ((16, 20, 24), (17, 16, 66)):
+        fields = inp.fields3(shape, seed=41 + shape[2], max_mach=0.2)
+        force = inp.force3(shape, seed=5, amp=3e-5)
+        for forced in (False, True):
+            kw = dict(fx=force[0], fy=force[1], fz=force[2]) if forced else {}
+            base = Sim3(*fields, 0.54, dtype=dtype, **kw)
+            base.step(13)
+            want = base.moments(scalars=False)
+            base.close()
+            for tile in (shapes32 if dtype == "f32" else shapes64):
+                s = Sim3(*fields, 0.54, dtype=dtype, **kw)
+                s.set_tile(*tile)
+                s.step(13)
+                got = s.moments(scalars=False)
+                for g, w in zip(got, want):
+                    assert torch.equal(g, w), (shape, forced, tile)
+                s.close()
+            say(f"3d multi-step {dtype} {shape} forced={forced}: bit-identical")
+    s = Sim3(*inp.fields3((16, 16, 16), seed=1), 0.6, dtype=dtype)
+    for bad in ((5, 32, 8, 4), (2, 2, 64, 4), (4, 64, 4, 4), (2, 64, 4, 0), (2, 48, 1, 4), (2, 64, 16, 4)):
+        with pytest.raises(L.LBMError):
+            s.set_tile(*bad)
+
+
+def test_3d_autotune_keeps_the_state(gpu_lib):
+    shape = (32, 32, 64)
+    fields = inp.fields3(shape, seed=8, max_mach=0.1)
+    force = inp.force3(shape, seed=8, amp=1e-5)
+    a = Sim3(*fields, 0.55, dtype="f32", fx=force[0], fy=force[1], fz=force[2])
+    b = Sim3(*fields, 0.55, dtype="f32", fx=force[0], fy=force[1], fz=force[2])
+    a.step(5)
+    tile = a.autotune(2)
+    say(f"3d autotuned shape {tile}")
+    assert a.get_tile() == tile and 1 <= tile[0] <= 4
+    a.step(20)
+    b.step(25)
+    for g, w in zip(a.moments(scalars=False), b.moments(scalars=False)):
+        assert torch.equal(g, w)
