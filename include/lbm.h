@@ -238,6 +238,11 @@ LBM_API int lbm_step(lbm_ctx ctx, int64_t n);
 LBM_API int lbm_moments(lbm_ctx ctx, void* rho, void* ux, void* uy, int32_t out_dtype,
                 double* scalars8);
 
+/* Global enstrophy of the current moments: 1/2 sum_x omega(x)^2 with
+ * omega = d_x u_y - d_y u_x by Eq. 18 on the periodic grid (FP64, fixed
+ * summation order).  Synchronous. */
+LBM_API int lbm_enstrophy(lbm_ctx ctx, double* enstrophy);
+
 /* Sub-volume energy and enstrophy balance at the current time t (needs the
  * handle created with with_balance = 1 and the two preceding steps recorded:
  * t >= 2 and the last lbm_step / lbm_load left them, else LBM_E_STATE).

@@ -195,6 +195,12 @@ def global_scalars(rho, ux, uy):
     }
 
 
+def global_enstrophy(ux, uy):
+    """Domain total of the enstrophy density, 1/2 sum omega^2, omega by Eq. 18."""
+    w = vorticity(t64(ux), t64(uy))
+    return float(0.5 * (w * w).sum())
+
+
 # ---------------------------------------------------------------------------
 # Discrete derivatives (Eqs. 17-18)
 # ---------------------------------------------------------------------------

@@ -138,6 +138,7 @@ SIGNATURES = {
     "lbm_balance_begin": (_I, [_P, C.POINTER(_I32), _I32]),
     "lbm_balance_end": (_I, [_P, C.POINTER(BalanceStats)]),
     "lbm_energy_spectrum": (_I, [_P, _DP, _I32]),
+    "lbm_enstrophy": (_I, [_P, _DP]),
     "lbm_relaxation": (_I, [_P, _P, _P]),
     "lbm_spectrum_workspace_bytes": (_I, [_I32, _I32, C.POINTER(_SZ)]),
     "lbm_spectrum_fields": (_I, [_I32, _I32, _P, _P, _P, _SZ, _DP, _I32, _P]),

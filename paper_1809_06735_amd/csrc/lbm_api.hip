@@ -704,6 +704,16 @@ int lbm_balance_fields_ex(const lbm_balance_input* in, void* ws, size_t ws_bytes
   return run_balance(*in, b, sizes, nsizes, out, dmaps, windows, nwin, wterms, term_fields, extra);
 }
 
+int lbm_enstrophy(lbm_ctx c, double* enstrophy) {
+  if (!c || !enstrophy) return fail(LBM_E_INVALID, "NULL argument");
+  if (int rc = wait_balance(c)) return rc;
+  if (int rc = moments_into(c, nullptr, nullptr, nullptr, LBM_F64, c->mom[0], c->mom[1], c->mom[2], nullptr,
+                            nullptr, nullptr))
+    return rc;
+  return global_enstrophy(c->mom[1], c->mom[2], c->cfg.nx, c->cfg.ny, c->partials,
+                          moment_blocks(c->cfg.nx, c->cfg.ny) * 8, c->scalars_dev, enstrophy, c->stream);
+}
+
 int lbm_relaxation(lbm_ctx c, double* alpha, double* nu_eff) {
   if (!c) return fail(LBM_E_INVALID, "ctx is NULL");
   if (!alpha && !nu_eff) return LBM_OK;

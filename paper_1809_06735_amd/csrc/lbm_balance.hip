@@ -1056,6 +1056,47 @@ int corner_stats(const SatView& v, const BalanceWs& ws, const int32_t* sizes, in
 
 }  // namespace
 
+namespace {
+
+// Per-workgroup sums of omega^2 / 2, omega = d_x u_y - d_y u_x by Eq. 18.
+__global__ void __launch_bounds__(kRedThreads) k_enstrophy(const double* __restrict__ ux,
+                                                            const double* __restrict__ uy, int nx, int ny,
+                                                            double* partials) {
+  __shared__ double sh[kRedThreads / 64];
+  const size_t plane = static_cast<size_t>(nx) * ny;
+  const fd8::F1 gx{ux, nx}, gy{uy, nx};
+  double acc = 0.0;
+  for (size_t i = blockIdx.x * size_t(kRedThreads) + threadIdx.x; i < plane; i += size_t(gridDim.x) * kRedThreads) {
+    const int x = static_cast<int>(i % nx), y = static_cast<int>(i / nx);
+    const double w = fd8::fd8_x(gy, x, y, nx) - fd8::fd8_y(gx, x, y, ny);
+    acc += 0.5 * w * w;
+  }
+  acc = wsum(acc);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < kRedThreads / 64; ++w) s += sh[w];
+    partials[blockIdx.x] = s;
+  }
+}
+
+}  // namespace
+
+int global_enstrophy(const double* ux, const double* uy, int nx, int ny, double* partials, int max_blocks,
+                     double* dev_out, double* host_out, hipStream_t s) {
+  const size_t plane = static_cast<size_t>(nx) * ny;
+  const int nb = static_cast<int>(std::max<size_t>(1, std::min<size_t>(max_blocks, (plane + kRedThreads - 1) / kRedThreads)));
+  hipLaunchKernelGGL(k_enstrophy, dim3(nb), dim3(kRedThreads), 0, s, ux, uy, nx, ny, partials);
+  LBM_HIP(hipGetLastError());
+  // one fixed-order sum of the partials (the field-mean kernel with weight 1)
+  hipLaunchKernelGGL(k_field_means, dim3(1), dim3(kRedThreads), 0, s, partials, nb, 1.0, dev_out);
+  LBM_HIP(hipGetLastError());
+  LBM_HIP(hipMemcpyAsync(host_out, dev_out, sizeof(double), hipMemcpyDeviceToHost, s));
+  LBM_HIP(hipStreamSynchronize(s));
+  return LBM_OK;
+}
+
 int run_balance_async(const lbm_balance_input& in, const BalanceWs& ws, const int32_t* sizes, int nsizes,
                       double* host_stats) {
   hipStream_t s = static_cast<hipStream_t>(in.stream);

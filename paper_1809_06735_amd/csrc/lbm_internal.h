@@ -221,5 +221,9 @@ int run_balance_async(const lbm_balance_input& in, const BalanceWs& ws, const in
                       double* host_stats);
 void fill_balance_stats(const double* host_stats, const int32_t* sizes, int nsizes, lbm_balance_stats* out);
 size_t balance_stats_doubles();
+// Omega = 1/2 sum omega^2 of FP64 fields [ny][nx] (omega by Eq. 18); partials holds
+// max_blocks doubles, dev_out one.  Synchronous.
+int global_enstrophy(const double* ux, const double* uy, int nx, int ny, double* partials, int max_blocks,
+                     double* dev_out, double* host_out, hipStream_t s);
 
 }  // namespace lbm

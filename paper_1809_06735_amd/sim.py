@@ -286,6 +286,12 @@ class Simulation:
             errs.append(r["window_errors"])
         return {"time": np.array(times), "terms": np.stack(terms), "errors": np.stack(errs)}
 
+    def enstrophy(self):
+        """Global enstrophy 1/2 sum omega^2 of the current moments (omega by Eq. 18)."""
+        v = C.c_double()
+        L.check(self._lib.lbm_enstrophy(self._h, C.byref(v)), "lbm_enstrophy")
+        return v.value
+
     def relaxation(self):
         """(alpha, nu_eff) FP64 [ny, nx] of the current populations: the entropic
         collision's alpha and nu_eff = c_s^2 (2 tau / alpha - 1/2) (alpha = 2, nu_eff = nu

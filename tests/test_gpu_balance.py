@@ -416,3 +416,19 @@ def test_balance_beside_the_steps_equals_the_balance_in_line(gpu_lib):
     r_async = a.balance_end()
     assert r_sync["stats"] == r_async["stats"] == b.balance(sizes)["stats"]
     say("balance beside the steps: bit-identical statistics, undisturbed state")
+
+
+def test_global_enstrophy_of_a_run(gpu_lib):
+    """lbm_enstrophy (1/2 sum omega^2 with omega by Eq. 18) of an FP64 Taylor-Green run and of a
+    decaying spectrum run against the oracle's runs."""
+    from paper_1809_06735_amd import Simulation
+    for name, (rho, ux, uy), tau, steps in (("tg64", inp.taylor_green(64, 0.01), 0.6, 200),
+                                             ("spec96", inp.spectrum_velocity(96, seed=4, max_mach=0.1), 0.52, 60)):
+        sim = Simulation(rho, ux, uy, tau, dtype="f64")
+        sim.step(steps)
+        got = sim.enstrophy()
+        f = ref.run(ref.init_populations(rho, ux, uy), steps, tau)
+        _, vx, vy = ref.moments(f)
+        want = ref.global_enstrophy(vx, vy)
+        say(f"enstrophy {name}: {got:.15e} vs {want:.15e}")
+        assert abs(got - want) <= 1e-11 * abs(want), (name, got, want)

@@ -938,3 +938,20 @@ def test_balance_with_a_viscosity_field():
     want = u * divx + v * divy
     got = (t["e4"] + t["e5"]).numpy()
     assert np.abs(got - want).max() < 1e-5 * np.abs(want).max()
+
+
+def test_global_enstrophy_of_a_taylor_green_field():
+    """1/2 sum omega^2 for u = u0 (-cos kx sin ky, sin kx cos ky): omega = 2 u0 k* cos kx cos ky
+    with the modified wavenumber of Eq. 18, k* = (2/5)(4 sin k - sin 2k + (4/21) sin 3k
+    - (1/56) sin 4k), so the total is u0^2 k*^2 N^2 / 2; a uniform flow has none."""
+    n, u0 = 48, 0.02
+    k = 2 * math.pi / n
+    kstar = 0.4 * (4 * math.sin(k) - math.sin(2 * k) + (4 / 21) * math.sin(3 * k) - math.sin(4 * k) / 56)
+    y, x = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    ux = -u0 * np.cos(k * x) * np.sin(k * y)
+    uy = u0 * np.sin(k * x) * np.cos(k * y)
+    got = ref.global_enstrophy(ux, uy)
+    assert got == pytest.approx(0.5 * u0 ** 2 * kstar ** 2 * n * n, rel=1e-12)
+    assert ref.global_enstrophy(np.full((n, n), 0.03), np.full((n, n), -0.01)) == pytest.approx(0.0, abs=1e-25)
+    # a shifted field has the same total
+    assert ref.global_enstrophy(np.roll(ux, 5, 1), np.roll(uy, 5, 1)) == pytest.approx(got, rel=1e-13)
