@@ -162,3 +162,32 @@ def test_3d_config_validation():
                          C.byref(h)) == L.LBM_E_INVALID
     assert lib.lbm3_step(None, 1) == L.LBM_E_INVALID
     assert lib.lbm3_destroy(None) == L.LBM_OK
+
+
+def test_tuned_shape_cache_file_round_trip(tmp_path):
+    """lbm_set_tuned_tile writes the process table to LBM_TUNE_CACHE (one line per grid and
+    scheme, the eight shape fields including halo) and a new process reads it back (a second
+    store from that process keeps the first line).  Host calls only."""
+    import subprocess
+    import sys
+    cache = tmp_path / "tune.txt"
+    code = (
+        "import ctypes as C, sys\n"
+        "from paper_1809_06735_amd import _lib as L\n"
+        "lib = L.load()\n"
+        "cfg = L.Config(nx=%d, ny=256, dtype=L.LBM_F32, has_force=1, with_balance=0, layout=1, tau=0.6,"
+        " drag_alpha=1e-3, stream=None)\n"
+        "t = L.Tile(%s)\n"
+        "sys.exit(lib.lbm_set_tuned_tile(C.byref(cfg), C.byref(t)))\n")
+    env = dict(os.environ, LBM_TUNE_CACHE=str(cache))
+    r = subprocess.run([sys.executable, "-c", code % (512, "256, 1, 1, 48, 1, 6, 1, 1")], env=env, cwd=ROOT)
+    assert r.returncode == 0
+    lines = cache.read_text().strip().splitlines()
+    assert len(lines) == 1 and lines[0].endswith(": 256 1 1 48 1 6 1 1"), lines
+    r = subprocess.run([sys.executable, "-c", code % (1024, "512, 1, 1, 1, 1, 1, 0, 0")], env=env, cwd=ROOT)
+    assert r.returncode == 0
+    lines = cache.read_text().strip().splitlines()
+    assert len(lines) == 2 and any(l.endswith(": 256 1 1 48 1 6 1 1") for l in lines), lines
+    # an invalid shape is refused and leaves the file alone
+    r = subprocess.run([sys.executable, "-c", code % (512, "256, 1, 1, 48, 1, 1, 0, 1")], env=env, cwd=ROOT)
+    assert r.returncode != 0 and len(cache.read_text().strip().splitlines()) == 2
