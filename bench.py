@@ -240,6 +240,45 @@ def entropic_1024(log, n=1024, tau0=0.5005, steps=400):
     return out
 
 
+def decay1024(log, passes=20):
+    """The decaying-turbulence workload (1024^2 FP32, tau = 0.51, spectrum field of max Mach
+    0.05, the balance at L = 8..256 every 100 steps): `passes` passes of 100 steps and one
+    balance each, the balance beside the next pass's steps as in the main measurement.  The
+    populations (75.5 MB) stay in the 256 MB Infinity Cache, so this rate is not an HBM
+    figure."""
+    import torch
+    import lbm_inputs as inp
+    from paper_1809_06735_amd import Simulation
+    w = inp.WORKLOADS["decay1024"]
+    _, ux, uy = inp.spectrum_velocity(w.n, seed=w.seed, max_mach=0.05)
+    import numpy as np
+    sim = Simulation(np.ones((w.n, w.n)), ux, uy, w.tau, dtype="f32", with_balance=True)
+    tile = sim.autotune(trial_steps=5)
+    sim.step(w.balance_every)
+    sim.balance(w.sizes)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pending = False
+    for _ in range(passes):
+        sim.step(w.balance_every)
+        if pending:
+            sim.balance_end()
+        sim.balance_begin(w.sizes)
+        pending = True
+    res = sim.balance_end()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    mlups = w.n * w.n * w.balance_every * passes / dt / 1e6
+    _, _, _, sc = sim.moments()
+    out = {"grid": w.n, "dtype": "f32", "tau": w.tau, "steps": w.balance_every * passes,
+           "balance_every": w.balance_every, "sizes": list(w.sizes), "shape": list(tile),
+           "MLUPS_with_balance": round(mlups, 1), "finite": sc["nonfinite"] == 0,
+           "mean_dE": {str(st["L"]): st["dE"]["mean"] for st in res["stats"]}}
+    sim.close()
+    log(f"[bench] decay1024: {out['MLUPS_with_balance']} MLUPS with the balance every {w.balance_every} steps")
+    return out
+
+
 def d3q19_256(log, n=256, tau=0.52, steps=200):
     """The three-dimensional extension: a forced 256^3 D3Q19 FP32 run (one launch per step,
     164 algorithmic bytes per site: 19 populations read and written, 3 force values read),
@@ -300,7 +339,7 @@ def cpu_baseline(n, tau, alpha, fx, fy, steps):
 
 
 EXTRAS = {"paper_set_up_256": paper_set_up_256, "paper_statistics_256": paper_statistics_256,
-          "entropic_1024": entropic_1024, "d3q19_256": d3q19_256}
+          "entropic_1024": entropic_1024, "d3q19_256": d3q19_256, "decay1024": decay1024}
 
 
 def main():
@@ -514,6 +553,10 @@ def main():
             extras["entropic_1024"] = entropic_1024(log)
         except Exception as e:  # noqa: BLE001
             extras["entropic_1024"] = f"error: {e}"
+        try:
+            extras["decay1024"] = decay1024(log)
+        except Exception as e:  # noqa: BLE001
+            extras["decay1024"] = f"error: {e}"
         try:
             extras["d3q19_256"] = d3q19_256(log)
         except Exception as e:  # noqa: BLE001
