@@ -265,11 +265,13 @@ LBM_API int lbm_subvolume_balance(lbm_ctx ctx, const int32_t* sizes, int32_t nsi
 /* The statistics of lbm_subvolume_balance (all corners, no maps, windows or
  * term fields) computed beside the following steps instead of in line with
  * them: lbm_balance_begin takes the moments of the current time t (as
- * lbm_subvolume_balance does: same preconditions, same errors, and it
- * synchronises cfg->stream to check them), then enqueues the balance on a
- * second stream of the library (default priority) and returns; steps enqueued
- * afterwards run concurrently with it.  lbm_balance_end waits for it and fills
- * out[nsizes] with exactly what lbm_subvolume_balance would have returned at t.
+ * lbm_subvolume_balance does, with the same preconditions), then enqueues the
+ * balance on a second stream of the library (default priority) and returns
+ * without waiting for the device; steps enqueued afterwards run concurrently
+ * with it.  lbm_balance_end waits for it and fills out[nsizes] with exactly
+ * what lbm_subvolume_balance would have returned at t, and returns
+ * LBM_E_DIVERGED (with the statistics filled) if the moments of t were not
+ * finite or had rho <= 0 somewhere.
  * Until lbm_balance_end, work that would overwrite what the balance reads (the
  * two history-recording steps of lbm_step, another balance, lbm_energy_spectrum,
  * lbm_load) waits for it on the device; a second lbm_balance_begin gives

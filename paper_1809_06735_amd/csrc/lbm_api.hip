@@ -116,8 +116,9 @@ struct lbm_ctx_s {
   // balance running beside the steps (lbm_balance_begin / lbm_balance_end)
   hipStream_t bal_stream = nullptr;
   hipEvent_t bal_snap = nullptr, bal_done = nullptr;
-  double* bal_host = nullptr;  // pinned statistics of the running balance
+  double* bal_host = nullptr;  // pinned statistics of the running balance, then its 8 moment scalars
   bool bal_pending = false;
+  int64_t bal_t = 0;
   std::vector<int32_t> bal_sizes;
 };
 
@@ -330,7 +331,7 @@ int wait_balance(lbm_ctx_s* c) {
   return LBM_OK;
 }
 
-int balance_input(lbm_ctx_s* c, lbm_balance_input* out);
+int balance_input(lbm_ctx_s* c, lbm_balance_input* out, double* deferred_scalars = nullptr);
 
 int moments_into(lbm_ctx_s* c, void* rho, void* ux, void* uy, int out_dtype, double* r64,
                  double* ux64, double* uy64, double* ftx, double* fty, double* scalars8) {
@@ -596,11 +597,11 @@ int lbm_balance_begin(lbm_ctx c, const int32_t* sizes, int32_t nsizes) {
     LBM_HIP(hipStreamCreateWithFlags(&c->bal_stream, hipStreamNonBlocking));
     LBM_HIP(hipEventCreateWithFlags(&c->bal_snap, hipEventDisableTiming));
     LBM_HIP(hipEventCreateWithFlags(&c->bal_done, hipEventDisableTiming));
-    LBM_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->bal_host), balance_stats_doubles() * sizeof(double),
+    LBM_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->bal_host), (balance_stats_doubles() + 8) * sizeof(double),
                           hipHostMallocDefault));
   }
   lbm_balance_input in{};
-  if (int rc = balance_input(c, &in)) return rc;
+  if (int rc = balance_input(c, &in, c->bal_host + balance_stats_doubles())) return rc;
   in.stream = c->bal_stream;
   LBM_HIP(hipEventRecord(c->bal_snap, c->stream));
   LBM_HIP(hipStreamWaitEvent(c->bal_stream, c->bal_snap, 0));
@@ -608,6 +609,7 @@ int lbm_balance_begin(lbm_ctx c, const int32_t* sizes, int32_t nsizes) {
   LBM_HIP(hipEventRecord(c->bal_done, c->bal_stream));
   c->bal_sizes.assign(sizes, sizes + nsizes);
   c->bal_pending = true;
+  c->bal_t = c->t;
   return LBM_OK;
 }
 
@@ -618,6 +620,11 @@ int lbm_balance_end(lbm_ctx c, lbm_balance_stats* out) {
   LBM_HIP(hipEventSynchronize(c->bal_done));
   c->bal_pending = false;
   fill_balance_stats(c->bal_host, c->bal_sizes.data(), static_cast<int>(c->bal_sizes.size()), out);
+  // the moment check of lbm_balance_begin (its scalars were copied before the balance started)
+  const double* sc = c->bal_host + balance_stats_doubles();
+  if (sc[LBM_S_NONFINITE] > 0.0 || !(sc[LBM_S_MINRHO] > 0.0))
+    return fail(LBM_E_DIVERGED, "run diverged: %.0f non-finite sites, min rho %g at step %lld", sc[LBM_S_NONFINITE],
+                sc[LBM_S_MINRHO], static_cast<long long>(c->bal_t));
   return LBM_OK;
 }
 
@@ -627,8 +634,9 @@ namespace {
 // The balance input at the current time t: FP64 moments of t (with the total
 // force and, for the entropic collision, the effective viscosity), the recorded
 // moments of t-1 and t-2.  Enqueued on c->stream; synchronises to check the
-// moments (LBM_E_DIVERGED).
-int balance_input(lbm_ctx_s* c, lbm_balance_input* out) {
+// moments (LBM_E_DIVERGED), or, with deferred_scalars (pinned host double[8]),
+// only enqueues the copy of the moment scalars there for a later check.
+int balance_input(lbm_ctx_s* c, lbm_balance_input* out, double* deferred_scalars) {
   const int64_t t = c->t;
   if (t < 2 || c->hist_t[(t - 1) & 1] != t - 1 || c->hist_t[(t - 2) & 1] != t - 2)
     return fail(LBM_E_STATE, "balance at t = %lld needs the moments of steps t-1 and t-2",
@@ -636,8 +644,16 @@ int balance_input(lbm_ctx_s* c, lbm_balance_input* out) {
   const bool forced = is_forced(c);
   double sc[8];
   int rc = moments_into(c, nullptr, nullptr, nullptr, LBM_F64, c->mom[0], c->mom[1], c->mom[2],
-                        forced ? c->ftot[0] : nullptr, forced ? c->ftot[1] : nullptr, sc);
+                        forced ? c->ftot[0] : nullptr, forced ? c->ftot[1] : nullptr,
+                        deferred_scalars ? nullptr : sc);
   if (rc) return rc;
+  if (deferred_scalars) {
+    if (int rc2 = launch_reduce_scalars(c->partials, moment_blocks(c->cfg.nx, c->cfg.ny), c->scalars_dev,
+                                        c->stream))
+      return rc2;
+    LBM_HIP(hipMemcpyAsync(deferred_scalars, c->scalars_dev, 8 * sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream));
+  }
   lbm_balance_input& in = *out;
   in.nx = c->cfg.nx;
   in.ny = c->cfg.ny;

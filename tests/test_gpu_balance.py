@@ -432,3 +432,23 @@ def test_global_enstrophy_of_a_run(gpu_lib):
         want = ref.global_enstrophy(vx, vy)
         say(f"enstrophy {name}: {got:.15e} vs {want:.15e}")
         assert abs(got - want) <= 1e-11 * abs(want), (name, got, want)
+
+
+def test_balance_beside_reports_divergence_at_the_end(gpu_lib):
+    """lbm_balance_begin does not wait for the device; a non-finite state at t comes back from
+    lbm_balance_end as LBM_E_DIVERGED (with the statistics filled)."""
+    from paper_1809_06735_amd import Simulation, _lib as L
+    n = 64
+    rho, ux, uy = inp.taylor_green(n, 0.01)
+    ux = ux.copy()
+    ux[3, 4] = np.nan
+    sim = Simulation(rho, ux, uy, 0.6, dtype="f32", with_balance=True)
+    sim.step(4)
+    sim.balance_begin((8, 64))
+    with pytest.raises(L.LBMError) as e:
+        sim.balance_end()
+    assert e.value.code == L.LBM_E_DIVERGED
+    good = Simulation(*inp.taylor_green(n, 0.01), 0.6, dtype="f32", with_balance=True)
+    good.step(4)
+    good.balance_begin((8, 64))
+    assert good.balance_end()["stats"][1]["L"] == 64
