@@ -87,7 +87,7 @@ int tile_candidates(int dtype, int nx, int ny, lbm_tile* out, int cap) {
   // width (packed halo), band height H; the early loads (pf = 1) pay off from
   // K = 3 on, the packed halo from K = 4 on
   const int ws[4] = {128, 192, 256, 512};
-  const int hs[6] = {24, 32, 48, 64, 128, 256};
+  const int hs[8] = {8, 16, 24, 32, 48, 64, 128, 256};
   for (int k = 2; k <= 6; ++k)
   for (int halo = 0; halo <= (k >= 4 ? 1 : 0); ++halo)
   for (int w : ws) {
