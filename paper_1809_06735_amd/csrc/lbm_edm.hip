@@ -180,25 +180,41 @@ __global__ void __launch_bounds__(kFourierCols) k_edm_fourier(const T* __restric
       }
     }
   }
-  for (int k = 0; k < md.m; ++k) {
-    const int kx = md.kx[k], ky = md.ky[k];
-    const int mk = kx < 0 ? -kx : kx;
-    double ca = 0.0, sa = 0.0, a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0;
+  // modes in groups of four: the 16 wavefront reductions of a group are independent
+  // chains of shuffles that the compiler interleaves
+  for (int k0 = 0; k0 < md.m; k0 += 4) {
+    double v[4][4];
 #pragma unroll
-    for (int n = 0; n < K1; ++n) {
-      ca = n == mk ? cx[n] : ca;
-      sa = n == mk ? sx[n] : sa;
-      a0 = n == ky ? ucx[n] : a0;
-      a1 = n == ky ? usx[n] : a1;
-      b0 = n == ky ? ucy[n] : b0;
-      b1 = n == ky ? usy[n] : b1;
+    for (int j = 0; j < 4; ++j) {
+      const int k = k0 + j < md.m ? k0 + j : k0;
+      const int kx = md.kx[k], ky = md.ky[k];
+      const int mk = kx < 0 ? -kx : kx;
+      double ca = 0.0, sa = 0.0, a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0;
+#pragma unroll
+      for (int n = 0; n < K1; ++n) {
+        ca = n == mk ? cx[n] : ca;
+        sa = n == mk ? sx[n] : sa;
+        a0 = n == ky ? ucx[n] : a0;
+        a1 = n == ky ? usx[n] : a1;
+        b0 = n == ky ? ucy[n] : b0;
+        b1 = n == ky ? usy[n] : b1;
+      }
+      if (kx < 0) sa = -sa;
+      v[j][0] = ca * a0 - sa * a1;
+      v[j][1] = sa * a0 + ca * a1;
+      v[j][2] = ca * b0 - sa * b1;
+      v[j][3] = sa * b0 + ca * b1;
     }
-    if (kx < 0) sa = -sa;
-    double v[4] = {ca * a0 - sa * a1, sa * a0 + ca * a1, ca * b0 - sa * b1, sa * b0 + ca * b1};
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      v[q] = wave_sum(v[q]);
-      if (lane == 0) wsum[wave][4 * k + q] = v[q];
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[j][q] = wave_sum(v[j][q]);
+    if (lane == 0) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (k0 + j < md.m)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) wsum[wave][4 * (k0 + j) + q] = v[j][q];
     }
   }
   __syncthreads();
