@@ -860,7 +860,7 @@ int lbm_autotune(lbm_ctx c, int32_t trial_steps, lbm_tile* chosen) {
   if (trial_steps < 1 || trial_steps > 10000) return fail(LBM_E_INVALID, "trial_steps in [1, 10000]");
   constexpr int kCap = 1024;
   std::vector<lbm_tile> cand(kCap);
-  int n = tile_candidates(c->cfg.dtype, c->cfg.nx, c->cfg.ny, cand.data(), kCap);
+  int n = tile_candidates(c->cfg.dtype, c->cfg.nx, c->cfg.ny, is_forced(c), cand.data(), kCap);
   if (n > kCap) n = kCap;
   if (one_site_kernel(c)) {  // single-step, one-site-per-thread shapes
     int k = 0;

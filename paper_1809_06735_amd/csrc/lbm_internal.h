@@ -82,10 +82,13 @@ struct StepParams {
 int launch_init(int dtype, void* pop, PopLayout lay, const double* rho0, const double* ux0,
                 const double* uy0, int nx, int ny, hipStream_t s);
 // One launch of the step kernel the tile selects: one step (fuse 0/1) or
-// fuse = 2..4 steps (temporal blocking, no moment history).  Buffers: src ->
+// fuse = 2..6 steps (temporal blocking, no moment history).  Buffers: src ->
 // dst either way.
 int launch_step(int dtype, bool force, const StepParams& p, const lbm_tile& t, hipStream_t s);
 int launch_step_fused(int dtype, bool force, const StepParams& p, const lbm_tile& t, hipStream_t s);
+// Workgroups of a multi-step shape that the current device holds at once (its
+// occupancy per CU times the CU count).
+int fused_resident_groups(int dtype, bool force, const lbm_tile& t, int* groups);
 bool fused_tile_ok(const lbm_tile& t, int dtype);
 // columns of output per strip of a multi-step shape (bx, or bx - 2 (fuse - 1) with halo = 1)
 int fused_strip_width(const lbm_tile& t);
@@ -93,7 +96,8 @@ size_t fused_lds_bytes(int W, int K, int dtype);
 inline int steps_per_launch(const lbm_tile& t) { return t.fuse >= 2 ? t.fuse : 1; }
 bool tile_ok(const lbm_tile& t, int dtype, int nx, int ny);
 lbm_tile default_tile(int dtype, int nx, int ny, int layout);
-int tile_candidates(int dtype, int nx, int ny, lbm_tile* out, int cap);
+// Shapes lbm_autotune times; returns how many there are (at most cap stored).
+int tile_candidates(int dtype, int nx, int ny, bool force, lbm_tile* out, int cap);
 // Step-kernel shape chosen by lbm_autotune for this grid (process table or the
 // LBM_TUNE_CACHE file), if any.
 bool tuned_tile(int dtype, int nx, int ny, bool force, int layout, lbm_tile* out);

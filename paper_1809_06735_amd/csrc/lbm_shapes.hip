@@ -3,6 +3,8 @@
 // kernels so that the kernels' sources change only with their device code).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "lbm_internal.h"
 
 namespace lbm {
@@ -60,8 +62,12 @@ lbm_tile default_tile(int dtype, int nx, int ny, int layout) {
   return t;
 }
 
-int tile_candidates(int dtype, int nx, int ny, lbm_tile* out, int cap) {
+int tile_candidates(int dtype, int nx, int ny, bool force, lbm_tile* out, int cap) {
   int n = 0;
+  auto add = [&](const lbm_tile& t) {
+    if (n < cap) out[n] = t;
+    ++n;
+  };
   const int vxs[3] = {1, 2, 4};
   const int threads[3] = {128, 256, 512};
   const int rys[4] = {1, 2, 4, 8};
@@ -75,9 +81,7 @@ int tile_candidates(int dtype, int nx, int ny, lbm_tile* out, int cap) {
           if (by * ry > ny) continue;
           for (int nt = 0; nt <= 1; ++nt) {
             lbm_tile t{bx, by, vx, ry, nt, 1, 0};
-            if (!tile_ok(t, dtype, nx, ny)) continue;
-            if (n < cap) out[n] = t;
-            ++n;
+            if (tile_ok(t, dtype, nx, ny)) add(t);
           }
         }
       }
@@ -85,23 +89,40 @@ int tile_candidates(int dtype, int nx, int ny, lbm_tile* out, int cap) {
   }
   // K = 2..6 steps per launch: strip width W (halo wavefront) or workgroup
   // width (packed halo), band height H; the early loads (pf = 1) pay off from
-  // K = 3 on, the packed halo from K = 4 on
+  // K = 3 on, the packed halo from K = 4 on.  Besides the fixed heights, the
+  // heights whose workgroup count fills the device's resident workgroup slots
+  // in one or two whole rounds: a band costs its H rows plus a fixed K - 1 rows
+  // of pipeline fill, and a launch lasts as many rounds as its busiest CU
+  // takes, so these avoid a partly filled last round.
   const int ws[4] = {128, 192, 256, 512};
   const int hs[8] = {8, 16, 24, 32, 48, 64, 128, 256};
   for (int k = 2; k <= 6; ++k)
   for (int halo = 0; halo <= (k >= 4 ? 1 : 0); ++halo)
   for (int w : ws) {
     if (w > nx + 64 && w > 128) continue;
-    for (int h : hs) {
-      if (h > ny && h > 32) continue;
-      for (int nt = 0; nt <= 1; ++nt)
-        for (int pf = k >= 3 ? 1 : 0; pf <= 1; ++pf) {
-          lbm_tile t{w, 1, 1, h, nt, k, pf, halo};
-          if (!tile_ok(t, dtype, nx, ny)) continue;
-          if (n < cap) out[n] = t;
-          ++n;
+    for (int nt = 0; nt <= 1; ++nt)
+      for (int pf = k >= 3 ? 1 : 0; pf <= 1; ++pf) {
+        lbm_tile t{w, 1, 1, 8, nt, k, pf, halo};
+        if (!tile_ok(t, dtype, nx, ny)) continue;
+        for (int h : hs) {
+          if (h > ny && h > 32) continue;
+          t.ry = h;
+          add(t);
         }
-    }
+        int slots = 0;
+        if (fused_resident_groups(dtype, force, t, &slots) != LBM_OK || slots < 1) continue;
+        const int strips = (nx + fused_strip_width(t) - 1) / fused_strip_width(t);
+        int prev = 0;
+        for (int rounds = 1; rounds <= 2; ++rounds) {
+          const int bands = rounds * slots / strips;
+          if (bands < 1) continue;
+          const int h = (ny + bands - 1) / bands;
+          if (h < 8 || h == prev || std::find(hs, hs + 8, h) != hs + 8) continue;
+          t.ry = h;
+          add(t);
+          prev = h;
+        }
+      }
   }
   return n;
 }

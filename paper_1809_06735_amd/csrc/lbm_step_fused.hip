@@ -25,15 +25,26 @@ __global__ void __launch_bounds__(kFusedMaxThreads) k_step_fused(StepParams p, i
                                                 packed != 0);
 }
 
+// Either launches the kernel (resident == nullptr) or stores in *resident the
+// number of its workgroups that the device holds at once over all CUs.
 template <typename T, int K, bool FORCE, bool NT, bool PF>
-int launch_t(const StepParams& p, const lbm_tile& t, hipStream_t s) {
+int launch_t(const StepParams& p, const lbm_tile& t, hipStream_t s, int* resident) {
   const int W = fused_strip_width(t), H = t.ry;
   const int threads = t.halo ? t.bx : t.bx + 64;
+  const size_t lds = fused_lds_bytes(W, K, sizeof(T) == 8 ? LBM_F64 : LBM_F32);
+  if (resident) {
+    int per_cu = 0, dev = 0, cus = 0;
+    LBM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_fused<T, K, FORCE, NT, PF>,
+                                                         threads, lds));
+    LBM_HIP(hipGetDevice(&dev));
+    LBM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    *resident = per_cu * cus;
+    return LBM_OK;
+  }
   const int strips = (p.nx + W - 1) / W;
   const int bands = (p.ny + H - 1) / H;
   const int total = strips * bands;
   const int per_xcd = (total + 7) / 8;
-  const size_t lds = fused_lds_bytes(W, K, sizeof(T) == 8 ? LBM_F64 : LBM_F32);
   hipLaunchKernelGGL((k_step_fused<T, K, FORCE, NT, PF>), dim3(per_xcd * 8), dim3(threads), lds, s, p,
                      W, H, strips, total, per_xcd, t.halo);
   LBM_HIP(hipGetLastError());
@@ -41,21 +52,26 @@ int launch_t(const StepParams& p, const lbm_tile& t, hipStream_t s) {
 }
 
 template <typename T, int K, bool FORCE>
-int dispatch_k(const StepParams& p, const lbm_tile& t, hipStream_t s) {
+int dispatch_k(const StepParams& p, const lbm_tile& t, hipStream_t s, int* r) {
   if (t.nt)
-    return t.pf ? launch_t<T, K, FORCE, true, true>(p, t, s) : launch_t<T, K, FORCE, true, false>(p, t, s);
-  return t.pf ? launch_t<T, K, FORCE, false, true>(p, t, s) : launch_t<T, K, FORCE, false, false>(p, t, s);
+    return t.pf ? launch_t<T, K, FORCE, true, true>(p, t, s, r) : launch_t<T, K, FORCE, true, false>(p, t, s, r);
+  return t.pf ? launch_t<T, K, FORCE, false, true>(p, t, s, r) : launch_t<T, K, FORCE, false, false>(p, t, s, r);
 }
 
 template <typename T, bool FORCE>
-int dispatch(const StepParams& p, const lbm_tile& t, hipStream_t s) {
+int dispatch(const StepParams& p, const lbm_tile& t, hipStream_t s, int* r) {
   switch (t.fuse) {
-    case 2: return dispatch_k<T, 2, FORCE>(p, t, s);
-    case 3: return dispatch_k<T, 3, FORCE>(p, t, s);
-    case 4: return dispatch_k<T, 4, FORCE>(p, t, s);
-    case 5: return dispatch_k<T, 5, FORCE>(p, t, s);
-    default: return dispatch_k<T, 6, FORCE>(p, t, s);
+    case 2: return dispatch_k<T, 2, FORCE>(p, t, s, r);
+    case 3: return dispatch_k<T, 3, FORCE>(p, t, s, r);
+    case 4: return dispatch_k<T, 4, FORCE>(p, t, s, r);
+    case 5: return dispatch_k<T, 5, FORCE>(p, t, s, r);
+    default: return dispatch_k<T, 6, FORCE>(p, t, s, r);
   }
+}
+
+int dispatch_dtype(int dtype, bool force, const StepParams& p, const lbm_tile& t, hipStream_t s, int* r) {
+  if (dtype == LBM_F64) return force ? dispatch<double, true>(p, t, s, r) : dispatch<double, false>(p, t, s, r);
+  return force ? dispatch<float, true>(p, t, s, r) : dispatch<float, false>(p, t, s, r);
 }
 
 }  // namespace
@@ -63,9 +79,13 @@ int dispatch(const StepParams& p, const lbm_tile& t, hipStream_t s) {
 int launch_step_fused(int dtype, bool force, const StepParams& p, const lbm_tile& t, hipStream_t s) {
   if (!fused_tile_ok(t, dtype)) return fail(LBM_E_INVALID, "invalid multi-step launch shape");
   if (p.h_rho) return fail(LBM_E_INVALID, "the multi-step kernel records no moment history");
-  if (dtype == LBM_F64)
-    return force ? dispatch<double, true>(p, t, s) : dispatch<double, false>(p, t, s);
-  return force ? dispatch<float, true>(p, t, s) : dispatch<float, false>(p, t, s);
+  return dispatch_dtype(dtype, force, p, t, s, nullptr);
+}
+
+int fused_resident_groups(int dtype, bool force, const lbm_tile& t, int* groups) {
+  *groups = 0;
+  if (!fused_tile_ok(t, dtype)) return fail(LBM_E_INVALID, "invalid multi-step launch shape");
+  return dispatch_dtype(dtype, force, StepParams{}, t, nullptr, groups);
 }
 
 }  // namespace lbm
