@@ -321,6 +321,50 @@ def d3q19_256(log, n=256, tau=0.52, steps=200):
     return out
 
 
+# Algorithmic HBM bytes per site of one balance call (FP64 fields, 13 term fields): the term
+# passes (levels n-2..n of rho, u and the force in, 13 terms + 8 auxiliary fields out, the
+# auxiliary fields read back), the field means (13 reads), the two table passes (13 reads +
+# 13 writes each) and one read of the table per box side.
+BAL_BYTES_TERMS = (11 * 8 + 13 * 8) + (11 * 8 + 7 * 8) + (3 * 8 + 8)
+BAL_BYTES_TABLES = 13 * 8 + 2 * (13 * 8 + 13 * 8)
+BAL_BYTES_PER_SIDE = 13 * 8
+
+
+def balance4096(log, calls=5):
+    """Workload forced4096's diagnostic alone: the balance at L = 8..256 of a 4096^2 FP32
+    run after 600 steps, in line (nothing beside it), time per call against the algorithmic
+    bytes of its passes."""
+    import numpy as np
+    import torch
+    import lbm_inputs as inp
+    from paper_1809_06735_amd import Simulation
+    w = inp.WORKLOADS["forced4096"]
+    n = w.n
+    fx, fy = inp.forcing_field(n, seed=w.seed, alpha=w.alpha)
+    z = np.zeros((n, n))
+    sim = Simulation(np.ones((n, n)), z, z, 0.51, dtype="f32", fx=fx, fy=fy, alpha=w.alpha,
+                     with_balance=True)
+    sim.step(600)
+    sim.balance(SIZES)
+    ts = []
+    for _ in range(calls):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.balance(SIZES)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    sim.close()
+    ms = float(np.median(ts)) * 1e3
+    per_site = BAL_BYTES_TERMS + BAL_BYTES_TABLES + len(SIZES) * BAL_BYTES_PER_SIDE
+    gbs = per_site * n * n / (ms * 1e-3) / 1e9
+    out = {"grid": n, "sizes": list(SIZES), "calls": calls, "ms_per_call": round(ms, 3),
+           "algorithmic_bytes_per_site": per_site, "GBps": round(gbs, 1),
+           "frac_of_8TBps": round(gbs / HBM_PEAK_GBS, 4)}
+    log(f"[bench] balance at 4096^2 alone: {ms:.2f} ms per call, {gbs:.0f} GB/s of algorithmic bytes "
+        f"({100 * gbs / HBM_PEAK_GBS:.1f}% of 8 TB/s)")
+    return out
+
+
 def cpu_baseline(n, tau, alpha, fx, fy, steps):
     import torch
     from oracle import ref
@@ -339,7 +383,8 @@ def cpu_baseline(n, tau, alpha, fx, fy, steps):
 
 
 EXTRAS = {"paper_set_up_256": paper_set_up_256, "paper_statistics_256": paper_statistics_256,
-          "entropic_1024": entropic_1024, "d3q19_256": d3q19_256, "decay1024": decay1024}
+          "entropic_1024": entropic_1024, "d3q19_256": d3q19_256, "decay1024": decay1024,
+          "balance4096": balance4096}
 
 
 def main():
@@ -557,6 +602,10 @@ def main():
             extras["decay1024"] = decay1024(log)
         except Exception as e:  # noqa: BLE001
             extras["decay1024"] = f"error: {e}"
+        try:
+            extras["balance4096"] = balance4096(log)
+        except Exception as e:  # noqa: BLE001
+            extras["balance4096"] = f"error: {e}"
         try:
             extras["d3q19_256"] = d3q19_256(log)
         except Exception as e:  # noqa: BLE001

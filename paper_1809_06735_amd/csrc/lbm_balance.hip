@@ -22,6 +22,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <vector>
 
 #include "lbm_fd8.h"
@@ -195,6 +196,362 @@ __global__ void __launch_bounds__(256) k_bal_c(PassArgs a) {
   const double* hx = a.aux + A_HX * plane;
   const double* hy = a.aux + A_HY * plane;
   a.terms[LBM_T_Z5 * plane + i] = fd8_x(F2{W, hy, nx}, x, y, nx) - fd8_y(F2{W, hx, nx}, x, y, ny);
+}
+
+// ---- the same passes on two sites per thread ----------------------------------------------
+// Thread (x / 2, y) evaluates sites x and x + 1 (x even, nx even, every field
+// 16-byte aligned) with 16-byte loads: a row segment x - 4 .. x + 5 serves both
+// sites' x-differences, one pair per row their y-differences.  Each site's
+// arithmetic is the one-site kernels' expression for expression, so the
+// results are bitwise the same; the passes take about half as many vector
+// memory instructions per site, which is what limits the one-site kernels.
+__device__ __forceinline__ double2 ld2(const double* f, size_t row, int x) {
+  return *reinterpret_cast<const double2*>(f + row + x);
+}
+__device__ __forceinline__ void st2(double* f, size_t i, double a, double b) {
+  *reinterpret_cast<double2*>(f + i) = make_double2(a, b);
+}
+// values at columns x - 4 .. x + 5 of one row (x and nx even)
+__device__ __forceinline__ void seg10(const double* f, size_t row, int x, int nx, double (&v)[10]) {
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    int xx = x - 4 + 2 * q;
+    xx += xx < 0 ? nx : 0;
+    xx -= xx >= nx ? nx : 0;
+    const double2 p = ld2(f, row, xx);
+    v[2 * q] = p.x;
+    v[2 * q + 1] = p.y;
+  }
+}
+// Eq. 18 along x at the pair's two sites from a 10-value segment, accumulated
+// offset by offset as in the one-site kernels
+__device__ __forceinline__ void dx_pair(const double (&v)[10], double (&d)[2]) {
+#pragma unroll
+  for (int m = 1; m <= 4; ++m) {
+    const double c = kFd8[m - 1];
+    d[0] += c * (v[4 + m] - v[4 - m]);
+    d[1] += c * (v[5 + m] - v[5 - m]);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_bal_a2(PassArgs a) {
+  const int nx = a.nx, ny = a.ny;
+  const int x = 2 * (blockIdx.x * blockDim.x + threadIdx.x);
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  if (x >= nx || y >= ny) return;
+  const size_t plane = static_cast<size_t>(nx) * ny;
+  const size_t row = static_cast<size_t>(y) * nx;
+  const size_t i = row + x;
+  double dxuy[3][2] = {}, dyux[3][2] = {};
+  double dxux[2] = {}, dyuy[2] = {}, dxr[2] = {}, dyr[2] = {};
+  double cux[3][2], cuy[3][2], crho[3][2];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    double v[10];
+    seg10(a.uy[k], row, x, nx, v);
+    dx_pair(v, dxuy[k]);
+    cuy[k][0] = v[4];
+    cuy[k][1] = v[5];
+  }
+  {
+    double v[10];
+    seg10(a.ux[2], row, x, nx, v);
+    dx_pair(v, dxux);
+    cux[2][0] = v[4];
+    cux[2][1] = v[5];
+    seg10(a.rho[2], row, x, nx, v);
+    dx_pair(v, dxr);
+    crho[2][0] = v[4];
+    crho[2][1] = v[5];
+  }
+#pragma unroll 1
+  for (int m = 1; m <= 4; ++m) {
+    const double c = kFd8[m - 1];
+    const size_t rp = static_cast<size_t>(wrap_add(y, m, ny)) * nx;
+    const size_t rm = static_cast<size_t>(wrap_add(y, -m, ny)) * nx;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double2 p = ld2(a.ux[k], rp, x), q = ld2(a.ux[k], rm, x);
+      dyux[k][0] += c * (p.x - q.x);
+      dyux[k][1] += c * (p.y - q.y);
+    }
+    {
+      const double2 p = ld2(a.uy[2], rp, x), q = ld2(a.uy[2], rm, x);
+      dyuy[0] += c * (p.x - q.x);
+      dyuy[1] += c * (p.y - q.y);
+    }
+    {
+      const double2 p = ld2(a.rho[2], rp, x), q = ld2(a.rho[2], rm, x);
+      dyr[0] += c * (p.x - q.x);
+      dyr[1] += c * (p.y - q.y);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const double2 u = ld2(a.ux[k], row, x), r = ld2(a.rho[k], row, x);
+    cux[k][0] = u.x;
+    cux[k][1] = u.y;
+    crho[k][0] = r.x;
+    crho[k][1] = r.y;
+  }
+  double fxv[2] = {0.0, 0.0}, fyv[2] = {0.0, 0.0}, nuv[2] = {a.nu, a.nu};
+  if (a.fx) {
+    const double2 p = ld2(a.fx, row, x), q = ld2(a.fy, row, x);
+    fxv[0] = p.x;
+    fxv[1] = p.y;
+    fyv[0] = q.x;
+    fyv[1] = q.y;
+  }
+  if (a.nu_field) {
+    const double2 p = ld2(a.nu_field, row, x);
+    nuv[0] = p.x;
+    nuv[1] = p.y;
+  }
+  double o[13][2];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    double om[3], en[3], ens[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      om[k] = dxuy[k][s] - dyux[k][s];
+      ens[k] = 0.5 * om[k] * om[k];
+      const double vx = cux[k][s], vy = cuy[k][s];
+      en[k] = 0.5 * crho[k][s] * (vx * vx + vy * vy);
+    }
+    const double dyux_n = dyux[2][s], dxuy_n = dxuy[2][s];
+    const double r = crho[2][s], vx = cux[2][s], vy = cuy[2][s];
+    const double dxp = dxr[s] / 3.0;
+    const double dyp = dyr[s] / 3.0;
+    const double nu = nuv[s];
+    const double sxx = 2.0 * nu * r * dxux[s];
+    const double syy = 2.0 * nu * r * dyuy[s];
+    const double sxy = nu * r * (dxuy_n + dyux_n);
+    o[0][s] = (3.0 * en[2] - 4.0 * en[1] + en[0]) / 2.0;
+    o[1][s] = -(vx * dxp + vy * dyp);
+    o[2][s] = vx * fxv[s] + vy * fyv[s];
+    o[3][s] = -(sxx * dxux[s] + sxy * dyux_n + sxy * dxuy_n + syy * dyuy[s]);
+    o[4][s] = (3.0 * ens[2] - 4.0 * ens[1] + ens[0]) / 2.0;
+    o[5][s] = -ens[2] * (dxux[s] + dyuy[s]);
+    o[6][s] = vx * vx + vy * vy;
+    o[7][s] = en[2];
+    o[8][s] = ens[2];
+    o[9][s] = om[2];
+    o[10][s] = sxx;
+    o[11][s] = syy;
+    o[12][s] = sxy;
+  }
+  double* t = a.terms;
+  st2(t, LBM_T_LHS_E * plane + i, o[0][0], o[0][1]);
+  st2(t, LBM_T_E2 * plane + i, o[1][0], o[1][1]);
+  st2(t, LBM_T_E3 * plane + i, o[2][0], o[2][1]);
+  st2(t, LBM_T_E4 * plane + i, o[3][0], o[3][1]);
+  st2(t, LBM_T_LHS_Z * plane + i, o[4][0], o[4][1]);
+  st2(t, LBM_T_Z2 * plane + i, o[5][0], o[5][1]);
+  st2(t, LBM_T_USQ * plane + i, o[6][0], o[6][1]);
+  double* ax = a.aux;
+  st2(ax, A_E * plane + i, o[7][0], o[7][1]);
+  st2(ax, A_OM2 * plane + i, o[8][0], o[8][1]);
+  st2(ax, A_W * plane + i, o[9][0], o[9][1]);
+  st2(ax, A_SXX * plane + i, o[10][0], o[10][1]);
+  st2(ax, A_SYY * plane + i, o[11][0], o[11][1]);
+  st2(ax, A_SXY * plane + i, o[12][0], o[12][1]);
+}
+
+__global__ void __launch_bounds__(256) k_bal_b2(PassArgs a) {
+  const int nx = a.nx, ny = a.ny;
+  const int x = 2 * (blockIdx.x * blockDim.x + threadIdx.x);
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  if (x >= nx || y >= ny) return;
+  const size_t plane = static_cast<size_t>(nx) * ny;
+  const size_t row = static_cast<size_t>(y) * nx;
+  const size_t i = row + x;
+  const double* ux = a.ux[2];
+  const double* uy = a.uy[2];
+  const double* rho = a.rho[2];
+  const double* ax = a.aux;
+  const double* E = ax + A_E * plane;
+  const double* Om = ax + A_OM2 * plane;
+  const double* W = ax + A_W * plane;
+  const double* sxx = ax + A_SXX * plane;
+  const double* syy = ax + A_SYY * plane;
+  const double* sxy = ax + A_SXY * plane;
+  const bool forced = a.fx != nullptr;
+  double dEx[2] = {}, dEy[2] = {}, dSx[2] = {}, dSy[2] = {}, dOx[2] = {}, dOy[2] = {};
+  double dxsxx[2] = {}, dysxy[2] = {}, dxsxy[2] = {}, dysyy[2] = {}, dxw[2] = {}, dyw[2] = {};
+  double dxf[2] = {}, dyf[2] = {};
+  double cw[2], cr[2];
+  // x-derivatives from 10-value row segments, a few fields at a time
+  {
+    double vux[10];
+    seg10(ux, row, x, nx, vux);
+    {
+      double vuy[10], vsxx[10], vsxy[10];
+      seg10(uy, row, x, nx, vuy);
+      seg10(sxx, row, x, nx, vsxx);
+      seg10(sxy, row, x, nx, vsxy);
+#pragma unroll
+      for (int m = 1; m <= 4; ++m) {
+        const double c = kFd8[m - 1];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+          const int p = 4 + s + m, q = 4 + s - m;
+          dSx[s] += c * ((vux[p] * vsxx[p] + vuy[p] * vsxy[p]) - (vux[q] * vsxx[q] + vuy[q] * vsxy[q]));
+          dxsxx[s] += c * (vsxx[p] - vsxx[q]);
+          dxsxy[s] += c * (vsxy[p] - vsxy[q]);
+        }
+      }
+    }
+    {
+      double v[10];
+      seg10(E, row, x, nx, v);
+#pragma unroll
+      for (int m = 1; m <= 4; ++m) {
+        const double c = kFd8[m - 1];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+          const int p = 4 + s + m, q = 4 + s - m;
+          dEx[s] += c * (v[p] * vux[p] - v[q] * vux[q]);
+        }
+      }
+      seg10(Om, row, x, nx, v);
+#pragma unroll
+      for (int m = 1; m <= 4; ++m) {
+        const double c = kFd8[m - 1];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+          const int p = 4 + s + m, q = 4 + s - m;
+          dOx[s] += c * (v[p] * vux[p] - v[q] * vux[q]);
+        }
+      }
+    }
+  }
+  {
+    double v[10];
+    seg10(W, row, x, nx, v);
+    dx_pair(v, dxw);
+    cw[0] = v[4];
+    cw[1] = v[5];
+  }
+  if (forced) {
+    double vf[10], vr[10];
+    seg10(a.fy, row, x, nx, vf);
+    seg10(rho, row, x, nx, vr);
+#pragma unroll
+    for (int m = 1; m <= 4; ++m) {
+      const double c = kFd8[m - 1];
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const int p = 4 + s + m, q = 4 + s - m;
+        dxf[s] += c * (vf[p] / vr[p] - vf[q] / vr[q]);
+      }
+    }
+    cr[0] = vr[4];
+    cr[1] = vr[5];
+  } else {
+    const double2 r = ld2(rho, row, x);
+    cr[0] = r.x;
+    cr[1] = r.y;
+  }
+  // y-derivatives, offset by offset from pairs in rows y + m and y - m
+#pragma unroll 1
+  for (int m = 1; m <= 4; ++m) {
+    const double c = kFd8[m - 1];
+    const size_t rp = static_cast<size_t>(wrap_add(y, m, ny)) * nx;
+    const size_t rm = static_cast<size_t>(wrap_add(y, -m, ny)) * nx;
+    const double2 uxp = ld2(ux, rp, x), uxm = ld2(ux, rm, x), uyp = ld2(uy, rp, x), uym = ld2(uy, rm, x);
+    const double2 sxyp = ld2(sxy, rp, x), sxym = ld2(sxy, rm, x), syyp = ld2(syy, rp, x), syym = ld2(syy, rm, x);
+    const double2 Ep = ld2(E, rp, x), Em = ld2(E, rm, x), Op = ld2(Om, rp, x), Omm = ld2(Om, rm, x);
+    const double2 Wp = ld2(W, rp, x), Wm = ld2(W, rm, x);
+    const double pux[2] = {uxp.x, uxp.y}, mux[2] = {uxm.x, uxm.y}, puy[2] = {uyp.x, uyp.y}, muy[2] = {uym.x, uym.y};
+    const double psxy[2] = {sxyp.x, sxyp.y}, msxy[2] = {sxym.x, sxym.y};
+    const double psyy[2] = {syyp.x, syyp.y}, msyy[2] = {syym.x, syym.y};
+    const double pE[2] = {Ep.x, Ep.y}, mE[2] = {Em.x, Em.y}, pO[2] = {Op.x, Op.y}, mO[2] = {Omm.x, Omm.y};
+    const double pW[2] = {Wp.x, Wp.y}, mW[2] = {Wm.x, Wm.y};
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      dEy[s] += c * (pE[s] * puy[s] - mE[s] * muy[s]);
+      dSy[s] += c * ((pux[s] * psxy[s] + puy[s] * psyy[s]) - (mux[s] * msxy[s] + muy[s] * msyy[s]));
+      dOy[s] += c * (pO[s] * puy[s] - mO[s] * muy[s]);
+      dysxy[s] += c * (psxy[s] - msxy[s]);
+      dysyy[s] += c * (psyy[s] - msyy[s]);
+      dyw[s] += c * (pW[s] - mW[s]);
+    }
+    if (forced) {
+      const double2 fp = ld2(a.fx, rp, x), fm = ld2(a.fx, rm, x), rpp = ld2(rho, rp, x), rmm = ld2(rho, rm, x);
+      const double pf[2] = {fp.x, fp.y}, mf[2] = {fm.x, fm.y}, pr[2] = {rpp.x, rpp.y}, mr[2] = {rmm.x, rmm.y};
+#pragma unroll
+      for (int s = 0; s < 2; ++s) dyf[s] += c * (pf[s] / pr[s] - mf[s] / mr[s]);
+    }
+  }
+  double o[7][2];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const double r = cr[s];
+    const double hx = (dxsxx[s] + dysxy[s]) / r;
+    const double hy = (dxsxy[s] + dysyy[s]) / r;
+    const double w = cw[s];
+    o[0][s] = -(dEx[s] + dEy[s]);
+    o[1][s] = dSx[s] + dSy[s];
+    o[2][s] = -(dOx[s] + dOy[s]);
+    o[3][s] = forced ? w * (dxf[s] - dyf[s]) : 0.0;
+    o[4][s] = hx * dyw[s] - hy * dxw[s];
+    o[5][s] = hx;
+    o[6][s] = hy;
+  }
+  double* t = a.terms;
+  st2(t, LBM_T_E1 * plane + i, o[0][0], o[0][1]);
+  st2(t, LBM_T_E5 * plane + i, o[1][0], o[1][1]);
+  st2(t, LBM_T_Z1 * plane + i, o[2][0], o[2][1]);
+  st2(t, LBM_T_Z3 * plane + i, o[3][0], o[3][1]);
+  st2(t, LBM_T_Z4 * plane + i, o[4][0], o[4][1]);
+  st2(a.aux, A_HX * plane + i, o[5][0], o[5][1]);
+  st2(a.aux, A_HY * plane + i, o[6][0], o[6][1]);
+}
+
+__global__ void __launch_bounds__(256) k_bal_c2(PassArgs a) {
+  const int nx = a.nx, ny = a.ny;
+  const int x = 2 * (blockIdx.x * blockDim.x + threadIdx.x);
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  if (x >= nx || y >= ny) return;
+  const size_t plane = static_cast<size_t>(nx) * ny;
+  const size_t row = static_cast<size_t>(y) * nx;
+  const double* W = a.aux + A_W * plane;
+  const double* hx = a.aux + A_HX * plane;
+  const double* hy = a.aux + A_HY * plane;
+  // Eq. 18 along x of W h_y and along y of W h_x, written as fd8_x / fd8_y
+  double g[10];
+  {
+    double vw[10], vh[10];
+    seg10(W, row, x, nx, vw);
+    seg10(hy, row, x, nx, vh);
+#pragma unroll
+    for (int q = 0; q < 10; ++q) g[q] = vw[q] * vh[q];
+  }
+  double gy[2][9];  // rows y - 4 .. y + 4 of W h_x at the pair
+#pragma unroll
+  for (int m = -4; m <= 4; ++m) {
+    if (m == 0) continue;
+    const size_t r = static_cast<size_t>(wrap_add(y, m, ny)) * nx;
+    const double2 w = ld2(W, r, x), h = ld2(hx, r, x);
+    gy[0][m + 4] = w.x * h.x;
+    gy[1][m + 4] = w.y * h.y;
+  }
+  double out[2];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const double d1 = g[5 + s] - g[3 + s];
+    const double d2 = g[6 + s] - g[2 + s];
+    const double d3 = g[7 + s] - g[1 + s];
+    const double d4 = g[8 + s] - g[0 + s];
+    const double fx = (4.0 * d1 - d2 + (4.0 / 21.0) * d3 - (1.0 / 56.0) * d4) / 5.0;
+    const double e1 = gy[s][5] - gy[s][3];
+    const double e2 = gy[s][6] - gy[s][2];
+    const double e3 = gy[s][7] - gy[s][1];
+    const double e4 = gy[s][8] - gy[s][0];
+    const double fy = (4.0 * e1 - e2 + (4.0 / 21.0) * e3 - (1.0 / 56.0) * e4) / 5.0;
+    out[s] = fx - fy;
+  }
+  st2(a.terms, LBM_T_Z5 * plane + row + x, out[0], out[1]);
 }
 
 // ---- field means ---------------------------------------------------------------------
@@ -682,36 +1039,78 @@ __device__ __forceinline__ void stride_windows(const SatView& v, int L, int x0, 
                                                double* maps, SumStat& r, const LdsHist* h) {
   const int nx = v.nx, ny = v.ny;
   const unsigned s = static_cast<unsigned>(nx + 1) * v.nf;  // between rows of one field
+  const unsigned fs = static_cast<unsigned>(nx + 1);        // between fields of one row
   const double inv = 1.0 / (double(L) * double(L));
   const bool qx = x0 + L > nx;
   const unsigned xm = qx ? x0 + L - nx : x0 + L;
-  // Q(y, x0 + L) - Q(y, x0) for table row y in [0, 2 ny), continued
-  // periodically through the row and column totals
-  auto diff = [&](int k, int y) -> double {
-    const double* p = v.P + (F0 + k) * static_cast<unsigned>(nx + 1);
-    const bool qy = y > ny;
-    const unsigned ym = qy ? y - ny : y;
-    double b0 = p[ym * s + x0];
-    double b1 = p[ym * s + xm];
-    if (qx) b1 += p[ym * s + nx];
-    if (qy) {
-      b0 += p[ny * s + x0];
-      b1 += p[ny * s + xm];
-      if (qx) b1 += p[ny * s + nx];
-    }
-    return b1 - b0;
-  };
-  // per field, the difference across the current window's top row
-  double dt[NF];
+  const double* P = v.P + F0 * fs;
+  // uniform over the workgroup: some window of the strip wraps in x, some
+  // window of the sequence wraps in y
+  const bool any_qx = (x0 - static_cast<int>(threadIdx.x)) + 255 + L > nx;
+  const bool any_qy = y0 + S * L > ny;
+  // the table's last row (column totals) at the window's columns, for rows
+  // continued past y = ny
+  double t0[NF], t1[NF], tn[NF];
 #pragma unroll
-  for (int k = 0; k < NF; ++k) dt[k] = diff(k, y0);
-  for (int i = 0; i < S && y0 < ny; ++i, y0 += L) {
-    double m[NF];
+  for (int k = 0; k < NF; ++k) t0[k] = t1[k] = tn[k] = 0.0;
+  if (any_qy) {
 #pragma unroll
     for (int k = 0; k < NF; ++k) {
-      const double db = diff(k, y0 + L);
-      m[k] = v.means[F0 + k] + (db - dt[k]) * inv;
-      dt[k] = db;  // the bottom row is the next window's top row
+      t0[k] = P[k * fs + ny * s + x0];
+      t1[k] = P[k * fs + ny * s + xm];
+      tn[k] = P[k * fs + ny * s + nx];
+    }
+  }
+  // Q(y, x0 + L) - Q(y, x0) for table row y in [0, 2 ny), continued
+  // periodically through the row and column totals, in two parts: the raw
+  // loads of a row, and the differences.  The next row's loads are issued
+  // before the current window is evaluated, so they are in flight during its
+  // arithmetic.
+  struct Raw {
+    double b0[NF], b1[NF], bn[NF];
+  };
+  auto load = [&](int y, Raw& w) {
+    const unsigned ym = y > ny ? y - ny : y;
+#pragma unroll
+    for (int k = 0; k < NF; ++k) {
+      const double* p = P + k * fs;
+      w.b0[k] = p[ym * s + x0];
+      w.b1[k] = p[ym * s + xm];
+      w.bn[k] = any_qx ? p[ym * s + nx] : 0.0;
+    }
+  };
+  auto finish = [&](int y, const Raw& w, double (&d)[NF]) {
+    const bool qy = y > ny;
+#pragma unroll
+    for (int k = 0; k < NF; ++k) {
+      double c0 = w.b0[k];
+      double c1 = qx ? w.b1[k] + w.bn[k] : w.b1[k];
+      if (qy) {
+        c0 += t0[k];
+        c1 += t1[k];
+        c1 = qx ? c1 + tn[k] : c1;
+      }
+      d[k] = c1 - c0;
+    }
+  };
+  // the field means in registers (a load inside the loop would sit behind the
+  // next row's loads and wait for them)
+  double mu[NF];
+#pragma unroll
+  for (int k = 0; k < NF; ++k) mu[k] = v.means[F0 + k];
+  double dt[NF];  // per field, the difference across the current window's top row
+  Raw rn;
+  load(y0, rn);
+  finish(y0, rn, dt);
+  if (S > 0 && y0 < ny) load(y0 + L, rn);
+  for (int i = 0; i < S && y0 < ny; ++i, y0 += L) {
+    double db[NF], m[NF];
+    finish(y0 + L, rn, db);
+    if (i + 1 < S && y0 + L < ny) load(y0 + 2 * L, rn);
+#pragma unroll
+    for (int k = 0; k < NF; ++k) {
+      m[k] = mu[k] + (db[k] - dt[k]) * inv;
+      dt[k] = db[k];  // the bottom row is the next window's top row
     }
     double val;
     if constexpr (NF == 1) {
@@ -882,7 +1281,24 @@ int balance_terms(const lbm_balance_input& in, const BalanceWs& ws) {
   a.ny = ny;
   a.terms = ws.terms;
   a.aux = ws.aux;
-  dim3 blk(64, 4), grd((nx + 63) / 64, (ny + 3) / 4);
+  // two sites per thread where the grid width is even and every field is
+  // 16-byte aligned (bitwise the same results), else one site per thread
+  auto al16 = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+  bool paired = nx % 2 == 0 && al16(a.terms) && al16(a.aux) && al16(a.fx) && al16(a.fy) &&
+                al16(a.nu_field);
+  for (int k = 0; k < 3; ++k) paired = paired && al16(a.rho[k]) && al16(a.ux[k]) && al16(a.uy[k]);
+  dim3 blk(64, 4);
+  if (paired) {
+    dim3 grd((nx / 2 + 63) / 64, (ny + 3) / 4);
+    hipLaunchKernelGGL(k_bal_a2, grd, blk, 0, s, a);
+    LBM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_bal_b2, grd, blk, 0, s, a);
+    LBM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_bal_c2, grd, blk, 0, s, a);
+    LBM_HIP(hipGetLastError());
+    return LBM_OK;
+  }
+  dim3 grd((nx + 63) / 64, (ny + 3) / 4);
   hipLaunchKernelGGL(k_bal_a, grd, blk, 0, s, a);
   LBM_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_bal_b, grd, blk, 0, s, a);

@@ -88,17 +88,21 @@ def test_balance_fields_parity(gpu_lib, n, sizes, force):
             assert torch.allclose(g[fin], o[fin], rtol=r, atol=1e-12 * float(o[fin].abs().max()))
 
 
-def test_balance_fields_nonsquare(gpu_lib):
+@pytest.mark.parametrize("ny,nx", [(48, 80), (47, 81)])
+def test_balance_fields_nonsquare(gpu_lib, ny, nx):
+    """Even widths take the two-sites-per-thread term passes, odd widths the one-site ones."""
     from paper_1809_06735_amd import balance_fields
+    say(f"balance_fields {ny}x{nx}")
     lv = inp.balance_levels(96, seed=9)
-    cut = {k: ([a[:48, :80] for a in v] if isinstance(v, list) else v[:48, :80]) for k, v in lv.items()}
-    res = balance_fields(cut["rho"], cut["ux"], cut["uy"], 0.002, (4, 16, 48), fx=cut["fx"],
+    cut = {k: ([a[:ny, :nx] for a in v] if isinstance(v, list) else v[:ny, :nx]) for k, v in lv.items()}
+    sizes = (4, 16, min(ny, nx))
+    res = balance_fields(cut["rho"], cut["ux"], cut["uy"], 0.002, sizes, fx=cut["fx"],
                          fy=cut["fy"], term_fields=True)
-    flds, want, kt, ks = balance_sensitivity(cut, 0.002, (4, 16, 48), cut["fx"], cut["fy"])
+    flds, want, kt, ks = balance_sensitivity(cut, 0.002, sizes, cut["fx"], cut["fy"])
     for name in ref.TERM_NAMES:
         assert rel_err(res["terms"][name], flds[name]) < term_tol(kt, name), name
     for got, w, kk in zip(res["stats"], want, ks):
-        compare_stats(got, w, kk, label="48x80")
+        compare_stats(got, w, kk, label=f"{ny}x{nx}")
 
 
 def test_balance_1024_parity(gpu_lib):
