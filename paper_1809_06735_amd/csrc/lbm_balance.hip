@@ -641,54 +641,52 @@ __global__ void __launch_bounds__(256) k_sat_rows(const double* __restrict__ g,
   }
 }
 
-// Column pass: 64 columns x kColG row-groups per workgroup; each group sums its
-// segment, the group totals are combined in LDS, then each group rewrites its
-// segment as running sums.
-constexpr int kColG = 16;
+// Column pass: a workgroup of 64 columns x kColG row groups walks the table
+// down in chunks of kColG x kColR rows.  Each thread holds its kColR rows of
+// one column in registers; the group totals go through LDS, and each thread
+// writes its rows back as running sums offset by the column's carry from the
+// chunks above and by the totals of the groups above it in the chunk.  The
+// table is read once and written once.
+constexpr int kColG = 8;
+constexpr int kColR = 16;
 __global__ void __launch_bounds__(64 * kColG) k_sat_cols(double* sat, int nx, int ny, int nf) {
   __shared__ double sh[kColG][64];
   const int c = blockIdx.x * 64 + threadIdx.x;
-  const int gidx = threadIdx.y;
+  const int g = threadIdx.y;
   const int f = blockIdx.y;
   double* P = sat + f * static_cast<size_t>(nx + 1);
-  const int seg = (ny + kColG - 1) / kColG;
-  const int ya = 1 + gidx * seg;
-  const int yb = min(ya + seg, ny + 1);
-  const bool active = c <= nx;
   const size_t s = static_cast<size_t>(nx + 1) * nf;  // between rows of one field
-  double acc = 0.0;
-  if (active) {
-    int yy = ya;
-    for (; yy + 4 <= yb; yy += 4) {
-      const double a0 = P[yy * s + c], a1 = P[(yy + 1) * s + c];
-      const double a2 = P[(yy + 2) * s + c], a3 = P[(yy + 3) * s + c];
-      acc += (a0 + a1) + (a2 + a3);
+  const bool active = c <= nx;
+  double carry = 0.0;  // this column's sum over the rows above the chunk
+  for (int y0 = 1; y0 <= ny; y0 += kColG * kColR) {
+    const int ya = y0 + g * kColR;
+    double v[kColR];
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < kColR; ++q) {
+      const int y = ya + q;
+      v[q] = (active && y <= ny) ? P[y * s + c] : 0.0;
+      acc += v[q];
     }
-    for (; yy < yb; ++yy) acc += P[yy * s + c];
-  }
-  sh[gidx][threadIdx.x] = acc;
-  __syncthreads();
-  double off = 0.0;
-  for (int k = 0; k < gidx; ++k) off += sh[k][threadIdx.x];
-  if (active) {
-    double run = off;
-    int yy = ya;
-    for (; yy + 4 <= yb; yy += 4) {
-      const double a0 = P[yy * s + c], a1 = P[(yy + 1) * s + c];
-      const double a2 = P[(yy + 2) * s + c], a3 = P[(yy + 3) * s + c];
-      run += a0;
-      P[yy * s + c] = run;
-      run += a1;
-      P[(yy + 1) * s + c] = run;
-      run += a2;
-      P[(yy + 2) * s + c] = run;
-      run += a3;
-      P[(yy + 3) * s + c] = run;
+    sh[g][threadIdx.x] = acc;
+    __syncthreads();
+    double off = carry, tot = carry;
+    for (int k = 0; k < kColG; ++k) {
+      const double t = sh[k][threadIdx.x];
+      if (k < g) off += t;
+      tot += t;
     }
-    for (; yy < yb; ++yy) {
-      run += P[yy * s + c];
-      P[yy * s + c] = run;
+    __syncthreads();  // sh is rewritten by the next chunk
+    if (active) {
+      double run = off;
+#pragma unroll
+      for (int q = 0; q < kColR; ++q) {
+        const int y = ya + q;
+        run += v[q];
+        if (y <= ny) P[y * s + c] = run;
+      }
     }
+    carry = tot;
   }
 }
 
