@@ -1032,6 +1032,20 @@ StrideGrid stride_grid(int nx, int ny, int L) {
 // the five energy terms) gives delta^E, group 1 (LHS_Omega and the five
 // enstrophy terms) delta^Omega, group 2 (|u|^2) the Mach number, each into
 // its own statistics slot.
+// The window's statistic from its box means: Ma_V (one field, |u|^2) or the
+// balancing error |sum of the five terms - LHS| / largest |term| (six fields),
+// as window_errors.
+template <int NF>
+__device__ __forceinline__ double window_value(const double (&m)[NF]) {
+  if constexpr (NF == 1) {
+    return sqrt(m[0]) * 1.7320508075688772;  // Ma_V = sqrt(<|u|^2>) / c_s, c_s = 1/sqrt(3)
+  } else {
+    const double rs = (((m[1] + m[2]) + m[3]) + m[4]) + m[5];
+    const double den = fmax(fmax(fmax(fabs(m[1]), fabs(m[2])), fmax(fabs(m[3]), fabs(m[4]))), fabs(m[5]));
+    return den > 0.0 ? fabs(rs - m[0]) / den : __builtin_nan("");
+  }
+}
+
 template <int F0, int NF>
 __device__ __forceinline__ void stride_windows(const SatView& v, int L, int x0, int y0, int S,
                                                double* maps, SumStat& r, const LdsHist* h) {
@@ -1110,16 +1124,7 @@ __device__ __forceinline__ void stride_windows(const SatView& v, int L, int x0, 
       m[k] = mu[k] + (db[k] - dt[k]) * inv;
       dt[k] = db[k];  // the bottom row is the next window's top row
     }
-    double val;
-    if constexpr (NF == 1) {
-      val = sqrt(m[0]) * 1.7320508075688772;  // Ma_V = sqrt(<|u|^2>) / c_s, c_s = 1/sqrt(3)
-    } else {
-      // |sum of the five terms - LHS| / largest |term|, as window_errors
-      const double rs = (((m[1] + m[2]) + m[3]) + m[4]) + m[5];
-      const double den =
-          fmax(fmax(fmax(fabs(m[1]), fabs(m[2])), fmax(fabs(m[3]), fabs(m[4]))), fabs(m[5]));
-      val = den > 0.0 ? fabs(rs - m[0]) / den : __builtin_nan("");
-    }
+    const double val = window_value<NF>(m);
     r.add(val);
     if (h) h->add(val);
     if (maps) maps[static_cast<unsigned>(y0) * nx + x0] = val;
@@ -1173,6 +1178,139 @@ __global__ void __launch_bounds__(256) k_windows_strided(SatView v, int L, int s
     lds_hist_flush(hh.bins, nedges, hist + grp * (nedges + 1));
   }
   sum_stats_block(r, partials + static_cast<size_t>(logical) * kSumVals);
+}
+
+// Sides L and 2 L at the same corners in one walk (no histograms, no maps):
+// along the sequence y0, y0 + L, ... a row's raw values at x0, x0 + L and
+// x0 + 2 L give both sides' differences; the side-L window whose top is row
+// j - 1 and the side-2L window whose top is row j - 2 both end at row j.
+// The table rows are read once for the two sides.
+template <int F0, int NF>
+__device__ __forceinline__ void stride_windows2(const SatView& v, int L, int x0, int y0, int S,
+                                                SumStat& r1, SumStat& r2) {
+  const int nx = v.nx, ny = v.ny;
+  const unsigned s = static_cast<unsigned>(nx + 1) * v.nf;
+  const unsigned fs = static_cast<unsigned>(nx + 1);
+  const int L2 = 2 * L;
+  const double inv1 = 1.0 / (double(L) * double(L));
+  const double inv2 = 1.0 / (double(L2) * double(L2));
+  const bool qx1 = x0 + L > nx, qx2 = x0 + L2 > nx;
+  const unsigned xm1 = qx1 ? x0 + L - nx : x0 + L;
+  const unsigned xm2 = qx2 ? x0 + L2 - nx : x0 + L2;
+  const double* P = v.P + F0 * fs;
+  const int nwin = min(S, (ny - y0 + L - 1) / L);  // corners y0 + w L < ny, w < S
+  const bool any_qx = (x0 - static_cast<int>(threadIdx.x)) + 255 + L2 > nx;
+  const bool any_qy = y0 + (nwin + 1) * L > ny;
+  double t0[NF], t1[NF], t2[NF], tn[NF];
+#pragma unroll
+  for (int k = 0; k < NF; ++k) t0[k] = t1[k] = t2[k] = tn[k] = 0.0;
+  if (any_qy) {
+#pragma unroll
+    for (int k = 0; k < NF; ++k) {
+      const double* p = P + k * fs + ny * s;
+      t0[k] = p[x0];
+      t1[k] = p[xm1];
+      t2[k] = p[xm2];
+      tn[k] = p[nx];
+    }
+  }
+  struct Raw {
+    double b0[NF], b1[NF], b2[NF], bn[NF];
+  };
+  auto load = [&](int y, Raw& w) {
+    const unsigned ym = y > ny ? y - ny : y;
+#pragma unroll
+    for (int k = 0; k < NF; ++k) {
+      const double* p = P + k * fs + ym * s;
+      w.b0[k] = p[x0];
+      w.b1[k] = p[xm1];
+      w.b2[k] = p[xm2];
+      w.bn[k] = any_qx ? p[nx] : 0.0;
+    }
+  };
+  // the same operations as the one-side walk, for each side
+  auto finish = [&](int y, const Raw& w, double (&d1)[NF], double (&d2)[NF]) {
+    const bool qy = y > ny;
+#pragma unroll
+    for (int k = 0; k < NF; ++k) {
+      double c0 = w.b0[k];
+      double c1 = qx1 ? w.b1[k] + w.bn[k] : w.b1[k];
+      double c2 = qx2 ? w.b2[k] + w.bn[k] : w.b2[k];
+      if (qy) {
+        c0 += t0[k];
+        c1 += t1[k];
+        c1 = qx1 ? c1 + tn[k] : c1;
+        c2 += t2[k];
+        c2 = qx2 ? c2 + tn[k] : c2;
+      }
+      d1[k] = c1 - c0;
+      d2[k] = c2 - c0;
+    }
+  };
+  double mu[NF];
+#pragma unroll
+  for (int k = 0; k < NF; ++k) mu[k] = v.means[F0 + k];
+  double a1[NF];          // side L: difference of the row above (top of window j - 1)
+  double a2[NF], b2[NF];  // side 2 L: differences of rows j - 2 and j - 1
+  Raw rn;
+  load(y0, rn);
+  finish(y0, rn, a1, b2);
+  load(y0 + L, rn);
+  for (int j = 1; j <= nwin + 1; ++j) {
+    const int y = y0 + j * L;
+    double d1[NF], d2[NF];
+    finish(y, rn, d1, d2);
+    if (j <= nwin) load(y + L, rn);
+    if (j - 1 < nwin) {
+      double m[NF];
+#pragma unroll
+      for (int k = 0; k < NF; ++k) m[k] = mu[k] + (d1[k] - a1[k]) * inv1;
+      r1.add(window_value<NF>(m));
+    }
+    if (j >= 2) {
+      double m[NF];
+#pragma unroll
+      for (int k = 0; k < NF; ++k) m[k] = mu[k] + (d2[k] - a2[k]) * inv2;
+      r2.add(window_value<NF>(m));
+    }
+#pragma unroll
+    for (int k = 0; k < NF; ++k) {
+      a1[k] = d1[k];
+      a2[k] = b2[k];
+      b2[k] = d2[k];
+    }
+  }
+}
+
+// Sides L and 2 L per launch, the work split of k_windows_strided for side L;
+// the partials of side 2 L follow those of side L.
+__global__ void __launch_bounds__(256) k_windows_pair(SatView v, int L, int strips, int S, int nblocks,
+                                                      int per_xcd, double* partials) {
+  const int b = blockIdx.x;
+  const int logical = (b & 7) * per_xcd + (b >> 3);
+  if (logical >= 3 * nblocks) return;  // uniform over the workgroup
+  const int grp = logical / nblocks;
+  const int wb = logical - grp * nblocks;
+  const int strip = wb % strips;
+  const int rest = wb / strips;
+  const int j = rest % L, g = rest / L;
+  const int x0 = strip * 256 + threadIdx.x;
+  const int y0 = j + L * (g * S);
+  SumStat r1[3], r2[3];
+  for (int q = 0; q < 3; ++q) {
+    r1[q].init();
+    r2[q].init();
+  }
+  if (x0 < v.nx && y0 < v.ny) {
+    if (grp == 0)
+      stride_windows2<LBM_T_LHS_E, 6>(v, L, x0, y0, S, r1[0], r2[0]);
+    else if (grp == 1)
+      stride_windows2<LBM_T_LHS_Z, 6>(v, L, x0, y0, S, r1[1], r2[1]);
+    else
+      stride_windows2<LBM_T_USQ, 1>(v, L, x0, y0, S, r1[2], r2[2]);
+  }
+  sum_stats_block(r1, partials + static_cast<size_t>(logical) * kSumVals);
+  sum_stats_block(r2, partials + (static_cast<size_t>(3) * nblocks + logical) * kSumVals);
 }
 
 __global__ void __launch_bounds__(256) k_sum_stats_final(const double* __restrict__ partials,
@@ -1247,7 +1385,9 @@ BalanceWs carve_balance(Carver& c, int nx, int ny) {
   w.means = c.take<double>(16);
   size_t np = static_cast<size_t>(kWinMaxBlocks) * kStatVals;
   for (int L = 1; L <= (nx < ny ? nx : ny); ++L) {
-    const size_t need = 3 * static_cast<size_t>(stride_grid(nx, ny, L).blocks) * kSumVals;
+    // sides paired with 2 L keep both sides' partials
+    const size_t sides = 2 * L <= (nx < ny ? nx : ny) ? 2 : 1;
+    const size_t need = sides * 3 * static_cast<size_t>(stride_grid(nx, ny, L).blocks) * kSumVals;
     if (np < need) np = need;
   }
   w.partials = c.take<double>(np + static_cast<size_t>(NT) * kMeanBlocks);
@@ -1432,8 +1572,43 @@ int corner_stats(const SatView& v, const BalanceWs& ws, const int32_t* sizes, in
                  bool hist, int ne, unsigned long long* hall, size_t hslot, int acc, hipStream_t s) {
   const int nx = v.nx, ny = v.ny;
   const size_t plane = static_cast<size_t>(nx) * ny;
+  // Without histograms or maps, a side L whose double 2 L is also asked for (and
+  // is not the whole domain) shares one walk of the tables with it.
+  std::vector<int> twin(nsizes, -1);  // index of side 2 L, or -2 for a side done with its half
+  if (!hist && !dmaps) {
+    for (int k = 0; k < nsizes; ++k) {
+      if (twin[k] != -1) continue;
+      const int L = sizes[k];
+      if (2 * L > (nx < ny ? nx : ny) || (2 * L == nx && 2 * L == ny)) continue;
+      for (int k2 = 0; k2 < nsizes; ++k2)
+        if (k2 != k && twin[k2] == -1 && sizes[k2] == 2 * L) {
+          twin[k] = k2;
+          twin[k2] = -2;
+          break;
+        }
+    }
+  }
   for (int k = 0; k < nsizes; ++k) {
     const int L = sizes[k];
+    if (twin[k] == -2) continue;
+    if (twin[k] >= 0) {
+      const StrideGrid g = stride_grid(nx, ny, L);
+      if (2 * 3 * g.blocks * kSumVals > static_cast<long long>(ws.partials_cap))
+        return fail(LBM_E_INVALID, "box sides %d, %d: window partials exceed the workspace", L, 2 * L);
+      const int nb = static_cast<int>(g.blocks);
+      const int per_xcd = (3 * nb + 7) / 8;
+      hipLaunchKernelGGL(k_windows_pair, dim3(per_xcd * 8), dim3(256), 0, s, v, L, g.strips, g.S, nb,
+                         per_xcd, ws.partials);
+      LBM_HIP(hipGetLastError());
+      hipLaunchKernelGGL(k_sum_stats_final, dim3(1), dim3(256), 0, s, ws.partials, 3 * nb,
+                         ws.stats + static_cast<size_t>(k) * kStatVals);
+      LBM_HIP(hipGetLastError());
+      hipLaunchKernelGGL(k_sum_stats_final, dim3(1), dim3(256), 0, s,
+                         ws.partials + static_cast<size_t>(3) * nb * kSumVals, 3 * nb,
+                         ws.stats + static_cast<size_t>(twin[k]) * kStatVals);
+      LBM_HIP(hipGetLastError());
+      continue;
+    }
     double* maps = dmaps ? dmaps + static_cast<size_t>(k) * 3 * plane : nullptr;
     unsigned long long* hk = hall + static_cast<size_t>(k) * hslot;
     if (L == nx && L == ny) {
