@@ -456,3 +456,26 @@ def test_balance_beside_reports_divergence_at_the_end(gpu_lib):
     good.step(4)
     good.balance_begin((8, 64))
     assert good.balance_end()["stats"][1]["L"] == 64
+
+
+def test_paired_walk_equals_separate_sides(gpu_lib):
+    """Sides L and 2 L asked for together share one walk over the corners; asked for one
+    at a time each has its own.  The windows and their values are the same, so counts,
+    NaN counts, minima and maxima agree exactly and means and deviations to rounding."""
+    from paper_1809_06735_amd import balance_fields
+    n = 128
+    lv = inp.balance_levels(n, seed=21)
+    args = (lv["rho"], lv["ux"], lv["uy"], 0.004)
+    kw = dict(fx=lv["fx"], fy=lv["fy"])
+    together = balance_fields(*args, (8, 16, 32, 64), **kw)["stats"]
+    alone = [balance_fields(*args, (L,), **kw)["stats"][0] for L in (8, 16, 32, 64)]
+    for got, want in zip(together, alone):
+        assert got["L"] == want["L"]
+        for q in ("dE", "dZ", "Ma"):
+            g, w = got[q], want[q]
+            for k in ("count", "n_nan", "min", "max"):
+                if k in w:
+                    assert g[k] == w[k], (got["L"], q, k, g[k], w[k])
+            for k, tol in (("mean", 1e-11), ("std", 1e-9)):
+                assert abs(g[k] - w[k]) <= tol * max(abs(w[k]), 1e-300), (got["L"], q, k, g[k], w[k])
+    say(f"paired walks at L = 8..64 on {n}^2 equal the separate ones")
