@@ -54,10 +54,9 @@ def step_source_digest(kernel="k_step_fused"):
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(kernel, workload, tile):
-    """Per-launch HBM bytes of a step kernel from the committed counter summary, or
-    None when it is missing, was taken on another version of the kernel or on
-    another launch shape."""
+def profile_record(kernel, workload, tile):
+    """The committed counter record of a step kernel in this launch shape, or None when
+    it is missing or was taken on another version of the kernel."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.md")
     if not os.path.exists(path):
         return None
@@ -68,8 +67,19 @@ def traffic_from_profile(kernel, workload, tile):
         if rec.get("source_sha256_16") != step_source_digest(kernel):
             return None
         if list(rec.get("tile", [])) == list(tile):
-            return rec.get("bytes_per_launch")
+            return rec
     return None
+
+
+def traffic_from_profile(kernel, workload, tile):
+    """Per-launch HBM bytes of a step kernel from the committed counter summary, or None."""
+    rec = profile_record(kernel, workload, tile)
+    return rec.get("bytes_per_launch") if rec else None
+
+
+# VALU issue of the chip: one wavefront instruction per CU and clock, 256 CUs at 2.4 GHz,
+# 64 lanes (FP32 without packed instructions, which this library does not use).
+VALU_LANE_OPS_PER_S = 256 * 2.4e9 * 64
 
 
 def single_step_kernel(n, tau, alpha, fx, fy, steps=400):
@@ -513,6 +523,18 @@ def main():
     alg_bytes = bytes_per_site * n * n        # per launch, whatever the steps fused
     achieved = alg_bytes / avg_launch_s / 1e9
     traffic = traffic_from_profile(kernel, "forced4096", tile)
+    # the VALU-issue view of the same kernel: its VALU instructions per lattice update
+    # (halo recomputation included) from the committed counters, against the chip's issue rate
+    rec = profile_record(kernel, "forced4096", tile)
+    vpl = rec.get("valu_lane_instructions_per_update") if rec else None
+    valu_view = None
+    if vpl:
+        ceil_mlups = VALU_LANE_OPS_PER_S / vpl / 1e6
+        valu_view = {"bound": "alu", "valu_per_lattice_update": vpl,
+                     "peak": round(VALU_LANE_OPS_PER_S / 1e12, 2), "unit": "T VALU lane-instr/s",
+                     "ceiling_MLUPS": round(ceil_mlups, 1),
+                     "note": "kernel MLUPS x VALU per update over 256 CUs x 64 lanes x 2.4 GHz; "
+                             "frac and frac_alone filled in below"}
     # the same kernel alone on the GPU (no balance beside it): 64 bulk launches, one graph
     torch.cuda.synchronize()
     sim.step_time(reset=True)
@@ -522,6 +544,10 @@ def main():
     sim.step_timing(False)
     alone_ms, alone_n = sim.step_time(reset=True)
     alone_s = alone_ms * 1e-3 / max(alone_n, 1)
+    if valu_view:
+        valu_view["frac"] = round(n * n * spl / avg_launch_s / 1e6 / valu_view["ceiling_MLUPS"], 4)
+        valu_view["frac_alone"] = round(n * n * spl / alone_s / 1e6 / valu_view["ceiling_MLUPS"], 4)
+        valu_view["note"] = "kernel MLUPS x VALU per update over 256 CUs x 64 lanes x 2.4 GHz"
     st = last["stats"]
     log(f"[bench] {mlups:.0f} MLUPS whole pass; {kernel} ({spl} steps/launch) "
         f"{avg_launch_s * 1e6:.1f} us/launch = {achieved:.0f} GB/s ({achieved / HBM_PEAK_GBS:.1%} "
@@ -562,7 +588,8 @@ def main():
                                "achieved": round(alg_bytes / alone_s / 1e9, 1),
                                "frac": round(alg_bytes / alone_s / 1e9 / HBM_PEAK_GBS, 4),
                                "kernel_MLUPS": round(n * n * spl / alone_s / 1e6, 1),
-                               "note": "the same kernel timed without the balance running beside it"}},
+                               "note": "the same kernel timed without the balance running beside it"},
+                     "valu": valu_view},
         "balance_at_end": {str(s["L"]): {"mean_dE": s["dE"]["mean"], "mean_dZ": s["dZ"]["mean"],
                                          "mean_Ma": s["Ma"]["mean"]} for s in st},
     }
