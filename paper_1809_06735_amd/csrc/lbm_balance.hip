@@ -6,10 +6,12 @@
 //   pass B  : terms that difference products of pass-A fields
 //   pass C  : the diffusion term of the enstrophy balance (third composed
 //             difference, total stencil radius 12)
+//             (passes A-C on two sites per thread with 16-byte loads where the
+//             width is even and the fields aligned, bitwise the same results)
 //   means   : domain mean of each of the 13 fields (deterministic two-level sum)
 //   SAT     : mean-centred inclusive 2D prefix sums, one (ny+1) x (nx+1) table
 //             per field, rows of all fields at one y adjacent (row scan, then
-//             column scan)
+//             column scan; each reads the table once)
 //   windows : for each box side L and every window corner, the 13 box means
 //             (differences of the table across the window's top and bottom
 //             rows, periodic wrap through the table totals), the balancing
@@ -17,7 +19,8 @@
 //             count / sum / sum of squares / min / max / NaN per block and
 //             merged in a fixed order.  Corners are visited along sequences
 //             y0, y0 + L, y0 + 2L, ... so a window's bottom row is the next
-//             window's top row and each table row is read once per side.
+//             window's top row and each table row is read once per side; a
+//             side L and its double 2L share one walk when both are asked for.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
