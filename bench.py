@@ -413,6 +413,20 @@ EXTRAS = {"paper_set_up_256": paper_set_up_256, "paper_statistics_256": paper_st
           "balance4096": balance4096}
 
 
+def _ensemble_extra(log):
+    from paper_1809_06735_amd import ensemble as ens_mod
+    return ens_mod.bench_ensemble(log=log)
+
+
+def _adjoint_extra(log):
+    from paper_1809_06735_amd import adjoint as adj_mod
+    return adj_mod.bench_adjoint(log=log)
+
+
+EXTRAS["ensemble"] = _ensemble_extra
+EXTRAS["adjoint"] = _adjoint_extra
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)

@@ -446,10 +446,11 @@ LBM_API int lbm_batch_set_mode(lbm_batch b, int32_t mode, int32_t chunk);
  * vx (1, 2 or 4, dividing every run's nx) sites per thread; band_rows (1..64)
  * groups of block_threads*vx consecutive sites per work item. */
 LBM_API int lbm_batch_set_tile(lbm_batch b, int32_t block_threads, int32_t vx, int32_t band_rows);
-/* Shape of the multi-step mode: t->fuse = K (2..4) steps per launch, t->bx =
- * strip width (a multiple of 64, at most 512), t->ry = band height (>= 8
- * rows), t->nt = non-temporal stores; by = vx = 1.  The next-row loads are
- * always issued early (pf = 1). */
+/* Shape of the multi-step mode: t->fuse = K (2..6) steps per launch, t->bx =
+ * workgroup width (a multiple of 64, at most 512: the strip width with
+ * t->halo = 0, the strip plus its 2 (K - 1) halo columns with t->halo = 1, as
+ * in lbm_tile), t->ry = band height (>= 8 rows), t->nt = non-temporal stores;
+ * by = vx = 1.  The next-row loads are always issued early (pf = 1). */
 LBM_API int lbm_batch_set_multi(lbm_batch b, const lbm_tile* t);
 LBM_API int lbm_batch_get_multi(lbm_batch b, lbm_tile* t);
 /* Time every (mode, block_threads, vx, band_rows) candidate and every

@@ -199,7 +199,9 @@ struct FusedArgs {
   const int* item_tile;
   int nitems;
   int per_xcd;
-  int W, H;
+  int W, H;     // strip width (output columns) and band height
+  int threads;  // W + 64 (halo wavefront) or W + 2 (K - 1) (packed halo)
+  int halo;
   int parity;
 };
 
@@ -224,18 +226,18 @@ __global__ void __launch_bounds__(fused_detail::kFusedMaxThreads) k_batch_fused(
   const int strips = (r.nx + a.W - 1) / a.W;
   T* const lds = reinterpret_cast<T*>(smem_raw);
   if (r.forced)
-    fused_detail::fused_tile<T, K, true, NT, true>(p, lds, a.W, a.H, strips, a.item_tile[it], false);
+    fused_detail::fused_tile<T, K, true, NT, true>(p, lds, a.W, a.H, strips, a.item_tile[it], a.halo != 0);
   else
-    fused_detail::fused_tile<T, K, false, NT, true>(p, lds, a.W, a.H, strips, a.item_tile[it], false);
+    fused_detail::fused_tile<T, K, false, NT, true>(p, lds, a.W, a.H, strips, a.item_tile[it], a.halo != 0);
 }
 
 template <typename T, int K>
 void launch_batch_fused_k(const FusedArgs& a, bool nt, hipStream_t s) {
   const size_t lds = fused_lds_bytes(a.W, K, sizeof(T) == 8 ? LBM_F64 : LBM_F32);
   if (nt)
-    hipLaunchKernelGGL((k_batch_fused<T, K, true>), dim3(a.per_xcd * 8), dim3(a.W + 64), lds, s, a);
+    hipLaunchKernelGGL((k_batch_fused<T, K, true>), dim3(a.per_xcd * 8), dim3(a.threads), lds, s, a);
   else
-    hipLaunchKernelGGL((k_batch_fused<T, K, false>), dim3(a.per_xcd * 8), dim3(a.W + 64), lds, s, a);
+    hipLaunchKernelGGL((k_batch_fused<T, K, false>), dim3(a.per_xcd * 8), dim3(a.threads), lds, s, a);
 }
 
 template <typename T>
@@ -243,7 +245,9 @@ void launch_batch_fused(int K, const FusedArgs& a, bool nt, hipStream_t s) {
   switch (K) {
     case 2: launch_batch_fused_k<T, 2>(a, nt, s); break;
     case 3: launch_batch_fused_k<T, 3>(a, nt, s); break;
-    default: launch_batch_fused_k<T, 4>(a, nt, s); break;
+    case 4: launch_batch_fused_k<T, 4>(a, nt, s); break;
+    case 5: launch_batch_fused_k<T, 5>(a, nt, s); break;
+    default: launch_batch_fused_k<T, 6>(a, nt, s); break;
   }
 }
 
@@ -357,12 +361,15 @@ size_t max_items(const lbm_config* cfgs, int nruns) {
   return n;
 }
 
-// multi-step tiles: strips of >= 64 columns, bands of >= 8 rows
+// multi-step tiles: strips of >= 54 columns (64 lanes less 2 (K - 1) packed halo
+// columns at K = 6), bands of >= 8 rows
 constexpr int kMinFusedBand = 8;
+constexpr int kMinFusedStrip = 64 - 2 * 5;
 size_t max_fused_items(const lbm_config* cfgs, int nruns) {
   size_t n = 0;
   for (int r = 0; r < nruns; ++r)
-    n += static_cast<size_t>((cfgs[r].nx + 63) / 64) * ((cfgs[r].ny + kMinFusedBand - 1) / kMinFusedBand);
+    n += static_cast<size_t>((cfgs[r].nx + kMinFusedStrip - 1) / kMinFusedStrip) *
+         ((cfgs[r].ny + kMinFusedBand - 1) / kMinFusedBand);
   return n;
 }
 
@@ -429,7 +436,8 @@ int build_items(lbm_batch_s* b) {
   // multi-step tiles of every run
   std::vector<int> f_run, f_tile;
   for (int r = 0; r < b->nruns; ++r) {
-    const int strips = (b->cfg[r].nx + b->ftile.bx - 1) / b->ftile.bx;
+    const int W = fused_strip_width(b->ftile);
+    const int strips = (b->cfg[r].nx + W - 1) / W;
     const int bands = (b->cfg[r].ny + b->ftile.ry - 1) / b->ftile.ry;
     for (int t = 0; t < strips * bands; ++t) {
       f_run.push_back(r);
@@ -497,8 +505,10 @@ int enqueue_steps(lbm_batch_s* b, int par, int n, hipStream_t s) {
     f.item_tile = b->d_fitem_tile;
     f.nitems = b->nfitems;
     f.per_xcd = (b->nfitems + 7) / 8;
-    f.W = b->ftile.bx;
+    f.W = fused_strip_width(b->ftile);
     f.H = b->ftile.ry;
+    f.halo = b->ftile.halo;
+    f.threads = f.halo ? b->ftile.bx : f.W + 64;
     int p = par;
     for (int k = 0; k + K <= n; k += K) {
       f.parity = p;
@@ -681,9 +691,9 @@ int lbm_batch_set_tile(lbm_batch b, int32_t block_threads, int32_t vx, int32_t b
 
 int lbm_batch_set_multi(lbm_batch b, const lbm_tile* t) {
   if (!b || !t) return fail(LBM_E_INVALID, "NULL argument");
-  if (t->fuse < 2 || t->fuse > 4 || t->halo != 0 || !fused_tile_ok(*t, b->dtype) || t->ry < kMinFusedBand)
-    return fail(LBM_E_INVALID, "multi-step shape: fuse 2..4, strip a multiple of 64 up to 512, "
-                               "band >= %d rows", kMinFusedBand);
+  if (!fused_tile_ok(*t, b->dtype) || t->ry < kMinFusedBand)
+    return fail(LBM_E_INVALID, "multi-step shape: fuse 2..6, halo 0 or 1, width a multiple of 64 up "
+                               "to 512, band >= %d rows", kMinFusedBand);
   b->ftile = *t;
   b->ftile.pf = 1;
   drop_batch_graphs(b);
@@ -789,10 +799,12 @@ int lbm_batch_autotune(lbm_batch b, int32_t trial_steps, int32_t* block_threads,
     b->mode = LBM_BATCH_MULTI_STEP;
     const int ws[3] = {128, 256, 512};
     const int hs[3] = {32, 64, 128};
-    for (int K = 2; K <= 4 && rc == LBM_OK; ++K)
+    // the packed halo (halo = 1) from K = 4 on, as for one grid
+    for (int K = 2; K <= 6 && rc == LBM_OK; ++K)
+      for (int halo = 0; halo <= (K >= 4 ? 1 : 0) && rc == LBM_OK; ++halo)
       for (int w = 0; w < 3 && rc == LBM_OK; ++w)
         for (int h : hs) {
-          lbm_tile t{ws[w], 1, 1, h, 1, K, 1};
+          lbm_tile t{ws[w], 1, 1, h, 1, K, 1, halo};
           if (!fused_tile_ok(t, b->dtype)) continue;
           b->ftile = t;
           // a whole number of K-step launches

@@ -89,16 +89,17 @@ class Ensemble:
         L.check(self._lib.lbm_batch_set_tile(self._h, int(block_threads), int(vx), int(groups)),
                 "lbm_batch_set_tile")
 
-    def set_multi(self, steps_per_launch, strip, band, nt=1):
-        """Shape of the multi-step mode (K steps per launch over strip x band tiles)."""
-        t = L.Tile(int(strip), 1, 1, int(band), int(nt), int(steps_per_launch), 1)
+    def set_multi(self, steps_per_launch, strip, band, nt=1, halo=0):
+        """Shape of the multi-step mode (K steps per launch over strip x band tiles; halo=1
+        packs the 2 (K - 1) halo columns into the `strip` lanes of a workgroup)."""
+        t = L.Tile(int(strip), 1, 1, int(band), int(nt), int(steps_per_launch), 1, int(halo))
         L.check(self._lib.lbm_batch_set_multi(self._h, C.byref(t)), "lbm_batch_set_multi")
 
     def get_multi(self):
-        """(steps_per_launch, strip, band, nt) of the multi-step mode."""
+        """(steps_per_launch, strip, band, nt, halo) of the multi-step mode."""
         t = L.Tile()
         L.check(self._lib.lbm_batch_get_multi(self._h, C.byref(t)), "lbm_batch_get_multi")
-        return t.fuse, t.bx, t.ry, t.nt
+        return t.fuse, t.bx, t.ry, t.nt, t.halo
 
     def get_mode(self):
         m, c = C.c_int32(), C.c_int32()
@@ -155,7 +156,7 @@ def bench_ensemble(nruns=64, steps=500, log=print):
     out = {"runs": nruns, "sites": sites,
            "autotuned": {"mode": ens.mode, "block_threads": tile[0], "vx": tile[1], "groups": tile[2],
                          "multi_step": {"steps_per_launch": multi[0], "strip": multi[1],
-                                        "band": multi[2], "nt": multi[3]}}}
+                                        "band": multi[2], "nt": multi[3], "halo": multi[4]}}}
     for mode in ("persistent", "per_step", "multi_step"):
         ens.set_mode(mode, 100)
         ens.step(100)                      # warm-up, builds the graph

@@ -102,8 +102,8 @@ def test_ensemble_tiles_and_autotune_keep_results(gpu_lib):
     bt, vx, g = t.autotune(trial_steps=4)
     assert bt in (256, 1024) and vx in (1, 2, 4) and 1 <= g <= 64
     assert t.get_mode()[0] in ("persistent", "per_step", "multi_step")
-    k, w, h, nt = t.get_multi()
-    assert 2 <= k <= 4 and w in (128, 256, 512) and h in (32, 64, 128)
+    k, w, h, nt, halo = t.get_multi()
+    assert 2 <= k <= 6 and w in (128, 256, 512) and h in (32, 64, 128) and halo in (0, 1)
     assert t.time > 0
 
 
@@ -121,11 +121,12 @@ def test_multi_step_mode_equals_per_step_bitwise(gpu_lib, dtype):
     ref_e.step(30)
     r37 = [ref_e.moments(r, scalars=False) for r in range(len(mem))]
     ref_e.close()
-    for (k, w, h, nt, chunk) in ((2, 64, 8, 1, 4), (3, 64, 16, 0, 6), (4, 128, 8, 1, 10),
-                                 (4, 64, 32, 1, 2), (3, 512, 64, 1, 8)):
+    for (k, w, h, nt, chunk, halo) in ((2, 64, 8, 1, 4, 0), (3, 64, 16, 0, 6, 0), (4, 128, 8, 1, 10, 0),
+                                       (4, 64, 32, 1, 2, 0), (3, 512, 64, 1, 8, 0), (4, 64, 8, 1, 4, 1),
+                                       (5, 128, 16, 0, 10, 1), (6, 256, 32, 1, 6, 1), (6, 64, 8, 1, 2, 1)):
         e = Ensemble(mem, dtype=dtype, mode="multi_step", chunk=chunk)
-        e.set_multi(k, w, h, nt)
-        assert e.get_multi() == (k, w, h, nt)
+        e.set_multi(k, w, h, nt, halo)
+        assert e.get_multi() == (k, w, h, nt, halo)
         e.step(7)
         for r in range(len(mem)):
             for x, y in zip(e.moments(r, scalars=False), r7[r]):
@@ -136,7 +137,7 @@ def test_multi_step_mode_equals_per_step_bitwise(gpu_lib, dtype):
                 assert torch.equal(x, y), (k, w, h, chunk, r, 37)
         e.close()
     e = Ensemble(mem, dtype=dtype, mode="multi_step", chunk=4)
-    for bad in ((5, 64, 8), (1, 64, 8), (2, 96, 8), (2, 64, 4), (2, 1024, 8)):
+    for bad in ((7, 64, 8), (1, 64, 8), (2, 96, 8), (2, 64, 4), (2, 1024, 8), (4, 64, 8, 1, 2)):
         with pytest.raises(LBMError):
             e.set_multi(*bad)
     e.close()
