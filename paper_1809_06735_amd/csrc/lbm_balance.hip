@@ -383,6 +383,38 @@ __global__ void __launch_bounds__(256) k_bal_b2(PassArgs a) {
   double dxsxx[2] = {}, dysxy[2] = {}, dxsxy[2] = {}, dysyy[2] = {}, dxw[2] = {}, dyw[2] = {};
   double dxf[2] = {}, dyf[2] = {};
   double cw[2], cr[2];
+  // y-derivatives first (fewer registers live across the x part), offset by
+  // offset from pairs in rows y + m and y - m
+#pragma unroll 1
+  for (int m = 1; m <= 4; ++m) {
+    const double c = kFd8[m - 1];
+    const size_t rp = static_cast<size_t>(wrap_add(y, m, ny)) * nx;
+    const size_t rm = static_cast<size_t>(wrap_add(y, -m, ny)) * nx;
+    const double2 uxp = ld2(ux, rp, x), uxm = ld2(ux, rm, x), uyp = ld2(uy, rp, x), uym = ld2(uy, rm, x);
+    const double2 sxyp = ld2(sxy, rp, x), sxym = ld2(sxy, rm, x), syyp = ld2(syy, rp, x), syym = ld2(syy, rm, x);
+    const double2 Ep = ld2(E, rp, x), Em = ld2(E, rm, x), Op = ld2(Om, rp, x), Omm = ld2(Om, rm, x);
+    const double2 Wp = ld2(W, rp, x), Wm = ld2(W, rm, x);
+    const double pux[2] = {uxp.x, uxp.y}, mux[2] = {uxm.x, uxm.y}, puy[2] = {uyp.x, uyp.y}, muy[2] = {uym.x, uym.y};
+    const double psxy[2] = {sxyp.x, sxyp.y}, msxy[2] = {sxym.x, sxym.y};
+    const double psyy[2] = {syyp.x, syyp.y}, msyy[2] = {syym.x, syym.y};
+    const double pE[2] = {Ep.x, Ep.y}, mE[2] = {Em.x, Em.y}, pO[2] = {Op.x, Op.y}, mO[2] = {Omm.x, Omm.y};
+    const double pW[2] = {Wp.x, Wp.y}, mW[2] = {Wm.x, Wm.y};
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      dEy[s] += c * (pE[s] * puy[s] - mE[s] * muy[s]);
+      dSy[s] += c * ((pux[s] * psxy[s] + puy[s] * psyy[s]) - (mux[s] * msxy[s] + muy[s] * msyy[s]));
+      dOy[s] += c * (pO[s] * puy[s] - mO[s] * muy[s]);
+      dysxy[s] += c * (psxy[s] - msxy[s]);
+      dysyy[s] += c * (psyy[s] - msyy[s]);
+      dyw[s] += c * (pW[s] - mW[s]);
+    }
+    if (forced) {
+      const double2 fp = ld2(a.fx, rp, x), fm = ld2(a.fx, rm, x), rpp = ld2(rho, rp, x), rmm = ld2(rho, rm, x);
+      const double pf[2] = {fp.x, fp.y}, mf[2] = {fm.x, fm.y}, pr[2] = {rpp.x, rpp.y}, mr[2] = {rmm.x, rmm.y};
+#pragma unroll
+      for (int s = 0; s < 2; ++s) dyf[s] += c * (pf[s] / pr[s] - mf[s] / mr[s]);
+    }
+  }
   // x-derivatives from 10-value row segments, a few fields at a time
   {
     double vux[10];
@@ -454,37 +486,6 @@ __global__ void __launch_bounds__(256) k_bal_b2(PassArgs a) {
     const double2 r = ld2(rho, row, x);
     cr[0] = r.x;
     cr[1] = r.y;
-  }
-  // y-derivatives, offset by offset from pairs in rows y + m and y - m
-#pragma unroll 1
-  for (int m = 1; m <= 4; ++m) {
-    const double c = kFd8[m - 1];
-    const size_t rp = static_cast<size_t>(wrap_add(y, m, ny)) * nx;
-    const size_t rm = static_cast<size_t>(wrap_add(y, -m, ny)) * nx;
-    const double2 uxp = ld2(ux, rp, x), uxm = ld2(ux, rm, x), uyp = ld2(uy, rp, x), uym = ld2(uy, rm, x);
-    const double2 sxyp = ld2(sxy, rp, x), sxym = ld2(sxy, rm, x), syyp = ld2(syy, rp, x), syym = ld2(syy, rm, x);
-    const double2 Ep = ld2(E, rp, x), Em = ld2(E, rm, x), Op = ld2(Om, rp, x), Omm = ld2(Om, rm, x);
-    const double2 Wp = ld2(W, rp, x), Wm = ld2(W, rm, x);
-    const double pux[2] = {uxp.x, uxp.y}, mux[2] = {uxm.x, uxm.y}, puy[2] = {uyp.x, uyp.y}, muy[2] = {uym.x, uym.y};
-    const double psxy[2] = {sxyp.x, sxyp.y}, msxy[2] = {sxym.x, sxym.y};
-    const double psyy[2] = {syyp.x, syyp.y}, msyy[2] = {syym.x, syym.y};
-    const double pE[2] = {Ep.x, Ep.y}, mE[2] = {Em.x, Em.y}, pO[2] = {Op.x, Op.y}, mO[2] = {Omm.x, Omm.y};
-    const double pW[2] = {Wp.x, Wp.y}, mW[2] = {Wm.x, Wm.y};
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      dEy[s] += c * (pE[s] * puy[s] - mE[s] * muy[s]);
-      dSy[s] += c * ((pux[s] * psxy[s] + puy[s] * psyy[s]) - (mux[s] * msxy[s] + muy[s] * msyy[s]));
-      dOy[s] += c * (pO[s] * puy[s] - mO[s] * muy[s]);
-      dysxy[s] += c * (psxy[s] - msxy[s]);
-      dysyy[s] += c * (psyy[s] - msyy[s]);
-      dyw[s] += c * (pW[s] - mW[s]);
-    }
-    if (forced) {
-      const double2 fp = ld2(a.fx, rp, x), fm = ld2(a.fx, rm, x), rpp = ld2(rho, rp, x), rmm = ld2(rho, rm, x);
-      const double pf[2] = {fp.x, fp.y}, mf[2] = {fm.x, fm.y}, pr[2] = {rpp.x, rpp.y}, mr[2] = {rmm.x, rmm.y};
-#pragma unroll
-      for (int s = 0; s < 2; ++s) dyf[s] += c * (pf[s] / pr[s] - mf[s] / mr[s]);
-    }
   }
   double o[7][2];
 #pragma unroll
