@@ -346,9 +346,14 @@ LBM_API int lbm_relaxation(lbm_ctx ctx, double* alpha, double* nu_eff);
 /* Current time step. */
 LBM_API int lbm_time(lbm_ctx ctx, int64_t* t);
 
-/* Checkpoint: bytes of the state (populations, time, recorded history), and
- * asynchronous copies of it to / from caller device memory.  lbm_load
- * restores exactly what lbm_save stored (same configuration only). */
+/* Checkpoint: bytes of the state (a 256-byte header, the populations and the
+ * recorded moment history), and asynchronous copies of it to / from caller
+ * device memory of at least lbm_state_bytes bytes.  The header records the
+ * time, the history times, nx, ny, dtype, layout and the state's size;
+ * lbm_load reads the header first (synchronising the stream) and returns
+ * LBM_E_INVALID, copying nothing, when any of these differs from the handle's,
+ * so a state from another grid, dtype or layout is refused.  lbm_load then
+ * restores exactly what lbm_save stored. */
 LBM_API int lbm_state_bytes(lbm_ctx ctx, size_t* bytes);
 LBM_API int lbm_save(lbm_ctx ctx, void* dst_device);
 LBM_API int lbm_load(lbm_ctx ctx, const void* src_device);

@@ -180,21 +180,6 @@ def moments(f, fx_ext=None, fy_ext=None, alpha=0.0):
     return rho, ux, uy
 
 
-def global_scalars(rho, ux, uy):
-    """Domain totals: mass, x/y momentum, kinetic energy, max |u|, min rho, #non-finite."""
-    speed2 = ux * ux + uy * uy
-    finite = torch.isfinite(rho) & torch.isfinite(ux) & torch.isfinite(uy)
-    return {
-        "mass": float(rho.sum()),
-        "mom_x": float((rho * ux).sum()),
-        "mom_y": float((rho * uy).sum()),
-        "energy": float((0.5 * rho * speed2).sum()),
-        "max_speed": float(speed2.sqrt().max()),
-        "min_rho": float(rho.min()),
-        "nonfinite": int((~finite).sum()),
-    }
-
-
 def global_enstrophy(ux, uy):
     """Domain total of the enstrophy density, 1/2 sum omega^2, omega by Eq. 18."""
     w = vorticity(t64(ux), t64(uy))

@@ -84,7 +84,7 @@ __device__ __forceinline__ T recip3(T x) {
 //   odd   A = w (3 omega rho cu + 3 g cF),
 // f*_l = (1 - omega) d_l + S + A, f*_lbar = (1 - omega) d_lbar + S - A.
 template <typename T, bool FORCE>
-__device__ __forceinline__ void collide3(const T (&d)[Q3], T Fx, T Fy, T Fz, T om, T (&o)[Q3], T& rho, T& ux,
+__device__ __forceinline__ void collide3(const T (&d)[Q3], T Fx, T Fy, T Fz, T om, T (&o)[Q3], T& drho_out, T& ux,
                                          T& uy, T& uz) {
   const T drho = (((d[0] + (d[1] + d[2])) + ((d[3] + d[4]) + (d[5] + d[6]))) +
                   (((d[7] + d[8]) + (d[9] + d[10])) + ((d[11] + d[12]) + (d[13] + d[14])))) +
@@ -92,7 +92,8 @@ __device__ __forceinline__ void collide3(const T (&d)[Q3], T Fx, T Fy, T Fz, T o
   const T jx = ((d[1] - d[2]) + (d[7] - d[8])) + (((d[9] - d[10]) + (d[11] - d[12])) + (d[13] - d[14]));
   const T jy = ((d[3] - d[4]) + (d[7] - d[8])) + (((d[10] - d[9]) + (d[15] - d[16])) + (d[17] - d[18]));
   const T jz = ((d[5] - d[6]) + (d[11] - d[12])) + (((d[14] - d[13]) + (d[15] - d[16])) + (d[18] - d[17]));
-  rho = T(1) + drho;
+  drho_out = drho;
+  const T rho = T(1) + drho;
   const T inv = recip3<T>(rho);
   if constexpr (FORCE) {
     ux = (jx + T(0.5) * Fx) * inv;
@@ -161,12 +162,12 @@ __global__ void __launch_bounds__(256) k3_step(Step3 p) {
     Fy = static_cast<const T*>(p.fy)[i];
     Fz = static_cast<const T*>(p.fz)[i];
   }
-  T o[Q3], rho, ux, uy, uz;
-  collide3<T, FORCE>(d, Fx, Fy, Fz, T(p.omega), o, rho, ux, uy, uz);
+  T o[Q3], drho, ux, uy, uz;
+  collide3<T, FORCE>(d, Fx, Fy, Fz, T(p.omega), o, drho, ux, uy, uz);
 #pragma unroll
   for (int l = 0; l < Q3; ++l) __builtin_nontemporal_store(o[l], dst + pop_at(l, z, y, x, ny, nx));
   if (p.h[0]) {
-    p.h[0][i] = double(rho);
+    p.h[0][i] = 1.0 + double(drho);  // rho - 1 kept to the storage type's precision
     p.h[1][i] = double(ux);
     p.h[2][i] = double(uy);
     p.h[3][i] = double(uz);
@@ -287,8 +288,8 @@ __global__ void __launch_bounds__(512) k3_step_fused(Fused3 p) {
   auto iteration = [&](auto parity, int k) {
     constexpr int E = decltype(parity)::value;
     constexpr int P0 = ((K - 1) & 1) ? E : 0;
-    T o[Q3], rho, ux, uy, uz;
-    if (top >= 1) collide3<T, FORCE>(d, f1[0], f1[1], f1[2], om, o, rho, ux, uy, uz);
+    T o[Q3], drho, ux, uy, uz;
+    if (top >= 1) collide3<T, FORCE>(d, f1[0], f1[1], f1[2], om, o, drho, ux, uy, uz);
     T fprev[3] = {f1[0], f1[1], f1[2]};
     // the next plane's level-1 input: its loads fly while levels 2..K run
     if (k < last) load_plane(z0 + k + 1, d, f1);
@@ -328,7 +329,7 @@ __global__ void __launch_bounds__(512) k3_step_fused(Fused3 p) {
           for (int j = 0; j < 9; ++j) dn[kZ0[j]] = c.z0[j];
 #pragma unroll
           for (int j = 0; j < 5; ++j) dn[kZP[j]] = c.zp[E ^ 1][j];
-          collide3<T, FORCE>(dn, fs[0], fs[1], fs[2], om, o, rho, ux, uy, uz);
+          collide3<T, FORCE>(dn, fs[0], fs[1], fs[2], om, o, drho, ux, uy, uz);
           if (s == K) {
             const int zo = z0 + k - (K - 1);
 #pragma unroll
@@ -409,7 +410,7 @@ __global__ void __launch_bounds__(kRedThreads) k3_moments(const T* __restrict__ 
       Fz = fz[i];
     }
     const T inv = T(1) / rho;
-    const double R = double(rho);
+    const double R = 1.0 + double(tr);  // formed in FP64 (see the 2D moments)
     const double U = double((tx + T(0.5) * Fx) * inv), V = double((ty + T(0.5) * Fy) * inv),
                  Wv = double((tz + T(0.5) * Fz) * inv);
     if (r) r[i] = R;

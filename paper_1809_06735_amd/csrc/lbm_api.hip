@@ -45,6 +45,8 @@ int validate_config(const lbm_config* c) {
   if (c->has_force != 0 && c->has_force != 1) return fail(LBM_E_INVALID, "has_force must be 0 or 1");
   if (c->with_balance != 0 && c->with_balance != 1)
     return fail(LBM_E_INVALID, "with_balance must be 0 or 1");
+  if (c->with_balance)
+    if (int rc = balance_grid_ok(c->nx, c->ny)) return rc;
   if (c->layout != LBM_LAYOUT_PLANES && c->layout != LBM_LAYOUT_ROWS)
     return fail(LBM_E_INVALID, "layout must be LBM_LAYOUT_PLANES or LBM_LAYOUT_ROWS");
   if (c->force_scheme != LBM_FORCE_GUO && c->force_scheme != LBM_FORCE_EDM)
@@ -372,19 +374,34 @@ int moments_into(lbm_ctx_s* c, void* rho, void* ux, void* uy, int out_dtype, dou
 }
 
 // Header of a saved state: 32 int64 words (256 bytes), unused words zero.
-__global__ void k_write_header(int64_t* h, int64_t t, int64_t h0, int64_t h1) {
+// Words: 0 format tag, 1 t, 2-3 the times of the two recorded moment levels,
+// 4 nx, 5 ny, 6 dtype, 7 population layout, 8 total bytes of the state.
+constexpr int64_t kStateTag = 0x4c424d33;
+struct StateHeader {
+  int64_t t, h0, h1, nx, ny, dtype, layout, bytes;
+};
+__global__ void k_write_header(int64_t* h, StateHeader s) {
   const int i = threadIdx.x;
   if (i < 32) {
     int64_t v = 0;
-    if (i == 0) v = 0x4c424d32;  // format tag
-    if (i == 1) v = t;
-    if (i == 2) v = h0;
-    if (i == 3) v = h1;
+    if (i == 0) v = kStateTag;
+    if (i == 1) v = s.t;
+    if (i == 2) v = s.h0;
+    if (i == 3) v = s.h1;
+    if (i == 4) v = s.nx;
+    if (i == 5) v = s.ny;
+    if (i == 6) v = s.dtype;
+    if (i == 7) v = s.layout;
+    if (i == 8) v = s.bytes;
     h[i] = v;
   }
 }
 
 constexpr size_t kHeader = 256;
+
+size_t state_bytes_of(const lbm_ctx_s* c) {
+  return kHeader + 9 * c->plane * elem_size(c->cfg.dtype) + 6 * c->plane * sizeof(double);
+}
 
 }  // namespace
 
@@ -686,6 +703,7 @@ int lbm_balance_workspace_bytes(int32_t nx, int32_t ny, size_t* bytes) {
   if (nx < 16 || ny < 16 || nx > 65536 || ny > 65536)
     return fail(LBM_E_INVALID, "grid %d x %d outside [16, 65536]", nx, ny);
   if (!bytes) return fail(LBM_E_INVALID, "bytes is NULL");
+  if (int rc = balance_grid_ok(nx, ny)) return rc;
   *bytes = balance_ws_bytes(nx, ny);
   return LBM_OK;
 }
@@ -779,15 +797,16 @@ int lbm_time(lbm_ctx c, int64_t* t) {
 
 int lbm_state_bytes(lbm_ctx c, size_t* bytes) {
   if (!c || !bytes) return fail(LBM_E_INVALID, "NULL argument");
-  *bytes = kHeader + 9 * c->plane * elem_size(c->cfg.dtype) + 6 * c->plane * sizeof(double);
+  *bytes = state_bytes_of(c);
   return LBM_OK;
 }
 
 int lbm_save(lbm_ctx c, void* dst) {
   if (!c || !dst) return fail(LBM_E_INVALID, "NULL argument");
   char* d = static_cast<char*>(dst);
-  hipLaunchKernelGGL(k_write_header, dim3(1), dim3(64), 0, c->stream, reinterpret_cast<int64_t*>(d),
-                     c->t, c->hist_t[0], c->hist_t[1]);
+  StateHeader sh{c->t, c->hist_t[0], c->hist_t[1], c->cfg.nx, c->cfg.ny, c->cfg.dtype, c->cfg.layout,
+                 static_cast<int64_t>(state_bytes_of(c))};
+  hipLaunchKernelGGL(k_write_header, dim3(1), dim3(64), 0, c->stream, reinterpret_cast<int64_t*>(d), sh);
   LBM_HIP(hipGetLastError());
   const size_t pb = 9 * c->plane * elem_size(c->cfg.dtype);
   LBM_HIP(hipMemcpyAsync(d + kHeader, c->pop[c->cur], pb, hipMemcpyDeviceToDevice, c->stream));
@@ -804,10 +823,22 @@ int lbm_save(lbm_ctx c, void* dst) {
 int lbm_load(lbm_ctx c, const void* src) {
   if (!c || !src) return fail(LBM_E_INVALID, "NULL argument");
   const char* d = static_cast<const char*>(src);
-  int64_t h[4];
+  // only the header is read before it has been checked against this handle
+  int64_t h[9];
   LBM_HIP(hipMemcpyAsync(h, d, sizeof(h), hipMemcpyDeviceToHost, c->stream));
   LBM_HIP(hipStreamSynchronize(c->stream));
-  if (h[0] != 0x4c424d32) return fail(LBM_E_INVALID, "not a saved state of this library");
+  if (h[0] != kStateTag) return fail(LBM_E_INVALID, "not a saved state of this library (tag %llx)",
+                                     static_cast<unsigned long long>(h[0]));
+  const int64_t want[5] = {c->cfg.nx, c->cfg.ny, c->cfg.dtype, c->cfg.layout,
+                           static_cast<int64_t>(state_bytes_of(c))};
+  static const char* what[5] = {"nx", "ny", "dtype", "layout", "state bytes"};
+  for (int k = 0; k < 5; ++k)
+    if (h[4 + k] != want[k])
+      return fail(LBM_E_INVALID, "saved state has %s = %lld, this handle %lld", what[k],
+                  static_cast<long long>(h[4 + k]), static_cast<long long>(want[k]));
+  if (h[1] < 0 || h[2] < -1 || h[3] < -1 || h[2] > h[1] || h[3] > h[1])
+    return fail(LBM_E_INVALID, "saved state has inconsistent times (t %lld, history %lld, %lld)",
+                static_cast<long long>(h[1]), static_cast<long long>(h[2]), static_cast<long long>(h[3]));
   if (int rc = wait_balance(c)) return rc;
   const size_t pb = 9 * c->plane * elem_size(c->cfg.dtype);
   LBM_HIP(hipMemcpyAsync(c->pop[0], d + kHeader, pb, hipMemcpyDeviceToDevice, c->stream));

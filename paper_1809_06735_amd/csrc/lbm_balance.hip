@@ -1373,6 +1373,17 @@ int stat_blocks(size_t count) {
 
 }  // namespace
 
+int balance_grid_ok(int nx, int ny) {
+  const unsigned long long elems = static_cast<unsigned long long>(NT) * (static_cast<unsigned long long>(nx) + 1) *
+                                   (static_cast<unsigned long long>(ny) + 1);
+  if (elems >= (1ull << 32))
+    return fail(LBM_E_UNSUPPORTED,
+                "balance of a %d x %d grid: its prefix tables hold %llu elements, beyond the 2^32 "
+                "the window walks address",
+                nx, ny, elems);
+  return LBM_OK;
+}
+
 size_t balance_ws_bytes(int nx, int ny) {
   Carver c(nullptr, 0);
   carve_balance(c, nx, ny);

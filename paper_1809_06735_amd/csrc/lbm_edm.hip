@@ -354,7 +354,7 @@ __global__ void __launch_bounds__(1024) k_edm_step(StepParams p, const T* __rest
       else *q = o[l];
     }
     if (p.h_rho) {
-      p.h_rho[i] = double(s.rho);
+      p.h_rho[i] = 1.0 + double(s.drho);  // rho - 1 kept to the storage type's precision
       p.h_ux[i] = double((s.jx + T(0.5) * Fx) * s.inv);
       p.h_uy[i] = double((s.jy + T(0.5) * Fy) * s.inv);
     }
@@ -399,10 +399,10 @@ __global__ void __launch_bounds__(kRedThreads) k_edm_moments(MomentParams p, con
     }
     const EdmSite<T> s(d);
     const T ux = (s.jx + T(0.5) * Fx) * s.inv, uy = (s.jy + T(0.5) * Fy) * s.inv;
-    if (p.rho) static_cast<O*>(p.rho)[i] = O(s.rho);
+    const double r = 1.0 + double(s.drho), vx = ux, vy = uy;  // rho formed in FP64
+    if (p.rho) static_cast<O*>(p.rho)[i] = O(r);
     if (p.ux) static_cast<O*>(p.ux)[i] = O(ux);
     if (p.uy) static_cast<O*>(p.uy)[i] = O(uy);
-    const double r = s.rho, vx = ux, vy = uy;
     if (p.rho64) {
       p.rho64[i] = r;
       p.ux64[i] = vx;

@@ -199,6 +199,10 @@ constexpr int kMaxWindows = 4096;
 constexpr int kMaxSizes = 64;
 size_t balance_ws_bytes(int nx, int ny);
 BalanceWs carve_balance(Carver& c, int nx, int ny);
+// The window walks address the 13 prefix tables with 32-bit element offsets:
+// a grid is accepted for the balance only while 13 (nx + 1)(ny + 1) < 2^32
+// (square grids up to 18 175^2).  LBM_OK, or LBM_E_UNSUPPORTED with a message.
+int balance_grid_ok(int nx, int ny);
 // Pieces of the balance reused by the adjoint: the 13 term fields and the aux
 // fields (E, Omega, omega, sigma_xx, sigma_yy, sigma_xy, H_x, H_y) of passes
 // A-C; domain means of nf consecutive fields; their mean-centred prefix tables

@@ -70,7 +70,7 @@ __global__ void __launch_bounds__(1024) k_step(StepParams p, int tiles_x, int to
       collide_site<T, FORCE>(di, m, omega, guo, oi);
 #pragma unroll
       for (int l = 0; l < 9; ++l) o[l][i] = oi[l];
-      hr[i] = double(m.rho);
+      hr[i] = 1.0 + double(m.drho);  // rho - 1 kept to the storage type's precision
       hx[i] = double(m.ux);
       hy[i] = double(m.uy);
     }
@@ -148,10 +148,12 @@ __global__ void __launch_bounds__(kMomThreads) k_moments(MomentParams p) {
       }
     }
     SiteMoments<T, FORCE> m(d, fx, fy, alpha);
-    if (p.rho) static_cast<O*>(p.rho)[i] = O(m.rho);
+    // rho = 1 + drho formed in FP64: with FP32 storage, 1 + drho in FP32 would round
+    // the density variation to the FP32 spacing at 1 (6e-8)
+    const double r = 1.0 + double(m.drho), vx = m.ux, vy = m.uy;
+    if (p.rho) static_cast<O*>(p.rho)[i] = O(r);
     if (p.ux) static_cast<O*>(p.ux)[i] = O(m.ux);
     if (p.uy) static_cast<O*>(p.uy)[i] = O(m.uy);
-    const double r = m.rho, vx = m.ux, vy = m.uy;
     if (p.rho64) {
       p.rho64[i] = r;
       p.ux64[i] = vx;

@@ -322,6 +322,16 @@ class Simulation:
         return out
 
     def load(self, state):
+        """Restore a state written by :meth:`save` of a handle with the same grid, dtype and
+        layout (the library checks its header; the size and device are checked here)."""
+        dev = self.device
+        if dev.type == "cuda" and dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        if not torch.is_tensor(state) or state.device != dev or not state.is_contiguous():
+            raise ValueError("state must be a contiguous tensor on " + str(dev))
+        if state.numel() * state.element_size() != self.state_bytes():
+            raise ValueError(f"state holds {state.numel() * state.element_size()} bytes, "
+                             f"this handle's state {self.state_bytes()}")
         L.check(self._lib.lbm_load(self._h, _ptr(state)), "lbm_load")
         return self
 

@@ -13,6 +13,47 @@ def rel_err(got, want):
     return float((g - w).abs().max()) / (den if den > 0 else 1.0)
 
 
+def moment_err(name, got, want, dtype):
+    """Parity measure of one moment field.  With FP32 storage the density is compared as
+    rho - 1 against max |rho - 1|: its variation (1e-8 .. 1e-3 of rho in these runs) sits
+    far below max |rho| = 1, where a comparison of rho itself could not see it.  FP64
+    density (whose oracle rho - 1 carries ~1e-16 absolute rounding) and the velocities
+    use :func:`rel_err`."""
+    if name == "rho" and dtype == "f32":
+        g = torch.as_tensor(got).detach().cpu().to(torch.float64)
+        w = torch.as_tensor(want).detach().cpu().to(torch.float64)
+        return rel_err(g - 1.0, w - 1.0)
+    return rel_err(got, want)
+
+
+def rho_floor32(rho, us, steps, q=9):
+    """Absolute error floor of rho - 1 with FP32 population storage.  Each of the q stored
+    deviations d_l = f_l - w_l is rounded once per step (relative 2^-24), and nothing
+    restores the lost mass, so after t steps rho - 1 at a site is off by up to about
+    t q 2^-24 max|d| (linear accumulation; independent roundings give ~sqrt(t) of it).
+    max|d| is estimated by the largest equilibrium deviation of the given moments,
+    w_l (|rho - 1| + rho (3 |c.u| + 4.5 (c.u)^2 + 1.5 |u|^2)) over the D2Q9 weights (which
+    bound the D3Q19 ones; q = 19 there).  us = the velocity components."""
+    r = torch.as_tensor(rho, dtype=torch.float64)
+    u = torch.sqrt(sum(torch.as_tensor(a, dtype=torch.float64) ** 2 for a in us))
+    dr, um, rm = float((r - 1).abs().max()), float(u.max()), float(r.abs().max())
+    dmax = max(4 / 9 * (dr + 1.5 * rm * um * um),
+               1 / 9 * (dr + rm * (3 * um + 4.5 * um * um + 1.5 * um * um)),
+               1 / 36 * (dr + rm * (3 * 1.4142135623730951 * um + 9 * um * um + 1.5 * um * um)))
+    return steps * q * 2.0 ** -24 * dmax
+
+
+def moment_tol(name, want, dtype, steps, base):
+    """Tolerance of :func:`moment_err` for one field: `base` (1e-12 FP64, 1e-5 FP32), except
+    FP32 density, whose rho - 1 cannot be more exact than :func:`rho_floor32` allows: there
+    max(base, floor / max|rho - 1|).  want = (rho, ux, uy[, uz]) of the oracle."""
+    if name != "rho" or dtype != "f32":
+        return base
+    dr = float((torch.as_tensor(want[0], dtype=torch.float64) - 1).abs().max())
+    floor = rho_floor32(want[0], want[1:], steps, 9 if len(want) == 3 else 19)
+    return max(base, floor / dr) if dr > 0 else float("inf")
+
+
 def wrap_patch(a, y0, x0, size):
     """size x size block of a periodic [ny, nx] array starting at (y0, x0)."""
     a = np.asarray(a)

@@ -88,6 +88,18 @@ def test_balance_workspace_and_adjoint_validation():
     assert lib.lbm_balance_workspace_bytes(64, 64, C.byref(n)) == L.LBM_OK
     assert n.value >= (13 + 8) * 64 * 64 * 8 + 13 * 65 * 65 * 8
     assert lib.lbm_balance_workspace_bytes(8, 64, C.byref(n)) == L.LBM_E_INVALID
+    # the window walks address the prefix tables with 32-bit element offsets:
+    # 13 (nx + 1)(ny + 1) must stay below 2^32 (18175^2 fits, 18176^2 does not)
+    assert 13 * 18176 * 18176 < 2 ** 32 <= 13 * 18177 * 18177
+    assert lib.lbm_balance_workspace_bytes(18175, 18175, C.byref(n)) == L.LBM_OK
+    assert lib.lbm_balance_workspace_bytes(18176, 18176, C.byref(n)) == L.LBM_E_UNSUPPORTED
+    assert b"2^32" in lib.lbm_last_error()
+    assert lib.lbm_balance_workspace_bytes(65536, 6000, C.byref(n)) == L.LBM_E_UNSUPPORTED
+    assert lib.lbm_balance_workspace_bytes(65536, 5000, C.byref(n)) == L.LBM_OK
+    # a handle with the balance refuses such a grid; without it the step alone is fine
+    assert lib.lbm_workspace_bytes(C.byref(cfg(nx=20000, ny=20000, with_balance=1)),
+                                   C.byref(n)) == L.LBM_E_UNSUPPORTED
+    assert lib.lbm_workspace_bytes(C.byref(cfg(nx=20000, ny=20000)), C.byref(n)) == L.LBM_OK
     assert lib.lbm_copy(None, None, 16, None) == L.LBM_E_INVALID
     assert lib.lbm_copy(C.c_void_p(256), C.c_void_p(512), 15, None) == L.LBM_E_INVALID
 

@@ -106,15 +106,54 @@ def test_balance_fields_nonsquare(gpu_lib, ny, nx):
 
 
 def test_balance_1024_parity(gpu_lib):
-    """Balance on host-made 1024^2 levels (decay1024 grid size), two box sizes."""
+    """Balance on host-made 1024^2 levels (decay1024 grid size) at the workload's six box
+    sides 8 .. 256 with neither maps nor histograms: sides L and 2L share one walk over the
+    corners (the paired walk the benchmark and decay1024 use); plus the single walk of a
+    side alone."""
     from paper_1809_06735_amd import balance_fields
-    say("balance_fields 1024")
+    say("balance_fields 1024, paired walks")
     lv = inp.balance_levels(1024, seed=1)
     nu = 0.01 / 3
-    res = balance_fields(lv["rho"], lv["ux"], lv["uy"], nu, (8, 256), fx=lv["fx"], fy=lv["fy"])
-    _, want, _, ks = balance_sensitivity(lv, nu, (8, 256), lv["fx"], lv["fy"], trials=1)
+    sizes = (8, 16, 32, 64, 128, 256)
+    res = balance_fields(lv["rho"], lv["ux"], lv["uy"], nu, sizes, fx=lv["fx"], fy=lv["fy"])
+    _, want, _, ks = balance_sensitivity(lv, nu, sizes, lv["fx"], lv["fy"], trials=2)
     for got, w, kk in zip(res["stats"], want, ks):
-        compare_stats(got, w, kk, label="1024")
+        say(f"  L={w['L']}: mean dE {got['dE']['mean']:.9e} vs {w['dE']['mean']:.9e}, "
+            f"dZ {got['dZ']['mean']:.9e} vs {w['dZ']['mean']:.9e}")
+        compare_stats(got, w, kk, label="1024 paired")
+    res1 = balance_fields(lv["rho"], lv["ux"], lv["uy"], nu, (32,), fx=lv["fx"], fy=lv["fy"])
+    compare_stats(res1["stats"][0], want[2], ks[2], label="1024 single")
+
+
+def test_decay1024_run_balance_paired_walks_against_oracle(gpu_lib):
+    """Workload decay1024 (1024^2 FP32, tau 0.51): after 100 steps the in-run balance at the
+    six sides 8 .. 256 (paired walks) against the oracle's balance of the GPU's own FP64
+    moments at t = 98, 99, 100 (so the step's FP32 error and the balance's error are kept
+    apart), with the conditioning-scaled tolerances of this module."""
+    from paper_1809_06735_amd import Simulation
+    w = inp.WORKLOADS["decay1024"]
+    rho, ux, uy = inp.spectrum_velocity(w.n, seed=w.seed, max_mach=0.05)
+    say("decay1024 100 steps + balance at 8..256")
+    sim = Simulation(rho, ux, uy, w.tau, dtype="f32", with_balance=True)
+    sim.step(98)
+    lv = {"rho": [], "ux": [], "uy": []}
+    for k in range(3):
+        if k:
+            sim.step(1)
+        r, vx, vy = sim.moments(scalars=False)
+        lv["rho"].append(r.cpu().numpy())
+        lv["ux"].append(vx.cpu().numpy())
+        lv["uy"].append(vy.cpu().numpy())
+    assert sim.time == 100
+    sizes = (8, 16, 32, 64, 128, 256)
+    got = sim.balance(sizes)
+    sim.close()
+    nu = (w.tau - 0.5) / 3
+    _, want, _, ks = balance_sensitivity(lv, nu, sizes, trials=2)
+    for g, wnt, kk in zip(got["stats"], want, ks):
+        say(f"  L={wnt['L']}: mean dE {g['dE']['mean']:.9e} vs {wnt['dE']['mean']:.9e}, "
+            f"mean Ma {g['Ma']['mean']:.9e} vs {wnt['Ma']['mean']:.9e}")
+        compare_stats(g, wnt, kk, label="decay1024 run")
 
 
 def test_balance_4096_patch_terms_and_invariants(gpu_lib):

@@ -12,7 +12,7 @@ import pytest
 import torch
 
 import lbm_inputs as inp
-from helpers import rel_err
+from helpers import moment_err, moment_tol, rel_err
 from oracle import ref
 
 pytestmark = pytest.mark.gpu
@@ -46,12 +46,13 @@ def _oracle(rho, ux, uy, steps, tau, fx, fy, amp, shell):
     return ref.edm_moments(f, fxt, fyt, amp, *shell)
 
 
-def _check(sim, want, tol, label):
+def _check(sim, want, tol, label, dtype, steps):
     r, vx, vy, sc = sim.moments()
     for name, g, w in zip(("rho", "ux", "uy"), (r, vx, vy), want[:3]):
-        e = rel_err(g, w)
-        say(f"{label} {name} rel err {e:.2e}")
-        assert e < tol, (label, name, e)
+        e = moment_err(name, g, w, dtype)
+        tol_f = moment_tol(name, want[:3], dtype, steps, tol)
+        say(f"{label} {name} rel err {e:.2e} (tol {tol_f:.1e})")
+        assert e < tol_f, (label, name, e, tol_f)
     return sc
 
 
@@ -75,7 +76,7 @@ def _run_case(ny, nx, dtype, steps, tau, amp, shell=(1.0, 2.0), force="random", 
     sim = Sim(rho, ux, uy, tau, dtype=dtype, fx=fx, fy=fy, scheme="edm", damp_f0=f0, damp_shell=shell)
     sim.step(steps)
     want = _oracle(rho, ux, uy, steps, tau, fx, fy, amp, shell)
-    sc = _check(sim, want, tol, label)
+    sc = _check(sim, want, tol, label, dtype, steps)
     assert sc["time"] == steps
     return sim, want
 

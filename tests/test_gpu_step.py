@@ -9,7 +9,7 @@ import pytest
 import torch
 
 import lbm_inputs as inp
-from helpers import gpu_patch, oracle_patch_moments, rel_err
+from helpers import gpu_patch, moment_err, moment_tol, oracle_patch_moments, rel_err
 from oracle import ref
 
 pytestmark = pytest.mark.gpu
@@ -27,12 +27,13 @@ def Sim(*a, **k):
     return Simulation(*a, **k)
 
 
-def check_moments(sim, want, tol, label):
+def check_moments(sim, want, tol, label, dtype="f64", steps=0):
     r, vx, vy, sc = sim.moments()
     for name, g, w in zip(("rho", "ux", "uy"), (r, vx, vy), want):
-        e = rel_err(g, w)
-        say(f"{label} {name} rel err {e:.2e}")
-        assert e < tol, (label, name, e)
+        e = moment_err(name, g, w, dtype)
+        tol_f = moment_tol(name, want, dtype, steps, tol)
+        say(f"{label} {name} rel err {e:.2e} (tol {tol_f:.1e})")
+        assert e < tol_f, (label, name, e, tol_f)
     return sc
 
 
@@ -72,7 +73,7 @@ def test_spectrum_256_fp32_100_steps(gpu_lib):
     sim = Sim(rho, ux, uy, 0.51, dtype="f32")
     sim.step(100)
     f = ref.run(ref.init_populations(rho, ux, uy), 100, 0.51)
-    check_moments(sim, ref.moments(f), TOL32, "spec256")
+    check_moments(sim, ref.moments(f), TOL32, "spec256", "f32", 100)
 
 
 def test_decay1024_fp32_sampled_patches(gpu_lib):
@@ -86,9 +87,10 @@ def test_decay1024_fp32_sampled_patches(gpu_lib):
     for (y0, x0) in ((1010, 1000), (400, 733)):
         want = oracle_patch_moments((rho, ux, uy), 0.51, 100, y0, x0, 24)
         for name, g, w in zip(("rho", "ux", "uy"), (r, vx, vy), want):
-            e = rel_err(gpu_patch(g, y0, x0, 24), w)
-            say(f"decay1024 patch ({y0},{x0}) {name} {e:.2e}")
-            assert e < TOL32
+            e = moment_err(name, gpu_patch(g, y0, x0, 24), w, "f32")
+            tol = moment_tol(name, want, "f32", 100, TOL32)
+            say(f"decay1024 patch ({y0},{x0}) {name} {e:.2e} (tol {tol:.1e})")
+            assert e < tol
 
 
 @pytest.fixture(scope="module")
@@ -113,14 +115,12 @@ def test_forced4096_fp32_sampled_patches_in_bench_launch_shape(gpu_lib, forced40
     for (y0, x0) in ((4090, 4085), (0, 2048), (1234, 4091), (2000, 0)):
         want = oracle_patch_moments((rho, ux, uy), w.tau, 20, y0, x0, 16, fx=fx, fy=fy, alpha=w.alpha)
         for name, g, ww in zip(("rho", "ux", "uy"), (r, vx, vy), want):
-            e = rel_err(gpu_patch(g, y0, x0, 16), ww)
-            say(f"forced4096 patch ({y0},{x0}) {name} {e:.2e}")
-            # from rest the velocity is O(F); compare against the field's global scale
-            if name != "rho":
-                scale = float(torch.as_tensor(ww).abs().max())
-                gscale = max(scale, 1e-12)
-                e = float((gpu_patch(g, y0, x0, 16).double() - ww).abs().max()) / gscale
-            assert e < TOL32, (name, e)
+            e = moment_err(name, gpu_patch(g, y0, x0, 16), ww, "f32")
+            # from rest rho - 1 after 20 steps (~1e-11) lies below the FP32 storage's
+            # resolution of the density: its tolerance is the rounding floor, reported
+            tol = moment_tol(name, want, "f32", 20, TOL32)
+            say(f"forced4096 patch ({y0},{x0}) {name} {e:.2e} (tol {tol:.1e})")
+            assert e < tol, (name, e, tol)
 
 
 @pytest.mark.parametrize("shape", [(16, 16), (33, 17), (50, 34), (64, 48), (20, 100)])
@@ -166,7 +166,7 @@ def test_ragged_grids_all_launch_shapes_agree(gpu_lib, shape):
             st = sim.save()
             if ref_state is None:
                 ref_state = st
-                check_moments(sim, want, tol, f"ragged {ny}x{nx} {dt} {tile}")
+                check_moments(sim, want, tol, f"ragged {ny}x{nx} {dt} {tile}", dt, steps)
             else:
                 assert torch.equal(st, ref_state), tile
             checked += 1
@@ -365,3 +365,46 @@ def test_rows_layout_equals_planes_layout(gpu_lib, dtype):
                     assert torch.equal(x, y), (layout, tile)
                 assert b == ref_b
             s.close()
+
+
+def test_load_refuses_a_state_of_another_grid_dtype_or_layout(gpu_lib):
+    """lbm_load checks the saved header (grid, dtype, layout, size) before copying anything;
+    Simulation.load checks the buffer's size and device."""
+    import ctypes as C
+    from paper_1809_06735_amd import _lib as L
+    say("save/load header checks")
+    rho, ux, uy = inp.taylor_green(64, 0.01)
+    a = Sim(rho, ux, uy, 0.6, dtype="f32")
+    a.step(5)
+    st = a.save()
+    torch.cuda.synchronize()
+    others = {
+        "grid": Sim(rho[:48], ux[:48], uy[:48], 0.6, dtype="f32"),
+        "dtype": Sim(rho, ux, uy, 0.6, dtype="f64"),
+        "layout": Sim(rho, ux, uy, 0.6, dtype="f32", layout="planes"),
+    }
+    for what, b in others.items():
+        before = b.save()
+        rc = b._lib.lbm_load(b._h, C.c_void_p(st.data_ptr()))
+        msg = b._lib.lbm_last_error().decode()
+        say(f"  {what}: rc {rc}, {msg}")
+        assert rc == L.LBM_E_INVALID, what
+        assert ("nx" if what == "grid" else what) in msg or "ny" in msg
+        assert torch.equal(b.save(), before), what  # nothing was copied
+        if what != "layout":  # same size as this handle's state only for the layout case
+            with pytest.raises(ValueError):
+                b.load(st)
+        b.close()
+    bad = st.clone()
+    bad[:8] = 0
+    with pytest.raises(Exception):
+        Sim(rho, ux, uy, 0.6, dtype="f32").load(bad)
+    # the matching handle restores the state exactly
+    c = Sim(rho, ux, uy, 0.6, dtype="f32")
+    c.load(st)
+    assert c.time == 5 and torch.equal(c.save(), st)
+    a.step(3)
+    c.step(3)
+    assert torch.equal(a.save(), c.save())
+    a.close()
+    c.close()

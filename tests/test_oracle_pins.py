@@ -400,18 +400,129 @@ def test_balancing_error_definition_cases():
     assert st["count"] == 2 and st["n_nan"] == 1 and st["mean"] == 2.0 and st["std"] == 1.0
 
 
-def test_taylor_green_run_balance_is_small():
-    """End-to-end (config tg64, shortened): LBGK Taylor-Green at tau 0.6 balances its
-    full-domain energy budget far better than the paper's O(1e-3) typical error."""
-    n, tau = 64, 0.6
+def _full_domain_deltas(flds):
+    """delta^E, delta^Omega of the one whole-domain box, from the plain domain means of the
+    term fields (Eqs. 12-13 at L = N)."""
+    m = {k: float(v.mean()) for k, v in flds.items()}
+    e = [m[f"e{i}"] for i in range(1, 6)]
+    z = [m[f"z{i}"] for i in range(1, 7) if f"z{i}" in m]
+    return (abs(sum(e) - m["lhs_E"]) / max(abs(v) for v in e),
+            abs(sum(z) - m["lhs_Z"]) / max(abs(v) for v in z))
+
+
+def _lhs_one_level_late(flds, late):
+    """Planted mistake: the time derivative (Eq. 17) taken over levels n-3, n-2, n-1 while
+    the right-hand side stays at level n."""
+    out = dict(flds)
+    out["lhs_E"], out["lhs_Z"] = late["lhs_E"], late["lhs_Z"]
+    return out
+
+
+#: Whole-domain budget of the Taylor-Green vortex with the levels n-2, n-1, n aligned
+#: (Eq. 17): measured 7.4e-5 / 4.4e-5 at 64^2, t = 200; a derivative one level late is
+#: off by the energy's relative change per step, 2 nu k^2 = 6.4e-4 of the dissipation
+#: (measured 1.9e-3 / 1.7e-3 with the acoustic part), so this bound separates the two.
+TG_CLOSURE = 3e-4
+
+
+def test_taylor_green_run_balance_closes_on_aligned_levels():
+    """run_with_history returns (rho, u) at n-2, n-1, n (Eq. 17): the LBGK Taylor-Green
+    vortex (config tg64 at t = 200) closes its whole-domain energy and enstrophy budgets
+    to < 3e-4, and the same budget with the derivative one level late does not."""
+    n, tau, steps = 64, 0.6, 200
     rho, ux, uy = inp.taylor_green(n, 0.01)
     f = ref.init_populations(rho, ux, uy)
-    _, hist = ref.run_with_history(f, 200, tau)
+    fend, hist = ref.run_with_history(f, steps, tau)
     flds = ref.fields_from_history(hist, tau)
     res = ref.subvolume_balance(flds, [64, 32])
-    assert res[0]["dE"]["count"] == 1
-    assert res[0]["dE"]["mean"] < 1e-2
-    assert res[1]["dE"]["count"] == 64 * 64
+    assert res[0]["dE"]["count"] == 1 and res[1]["dE"]["count"] == 64 * 64
+    assert res[0]["dE"]["mean"] < TG_CLOSURE and res[0]["dZ"]["mean"] < TG_CLOSURE
+    assert max(_full_domain_deltas(flds)) < TG_CLOSURE
+    _, hist_late = ref.run_with_history(f, steps - 1, tau)
+    late = _lhs_one_level_late(flds, ref.fields_from_history(hist_late, tau))
+    assert min(_full_domain_deltas(late)) > 1e-3
+    # the last level is the returned state
+    for a, b in zip(hist[2], ref.moments(fend)):
+        assert torch.equal(a, b)
+
+
+def _uniform_force_levels(hist, steps, fvec):
+    """From rest under a uniform force F with no drag every step adds exactly F to the
+    momentum (Guo's term and the exact-difference term alike), so the physical velocity at
+    time t is (t + 1/2) F / rho with rho = 1: level k of the history is t = steps - 2 + k.
+    Rounding of the momentum sum leaves ~1e-16 absolute; a level one step off, or the bare
+    velocity j/rho, is off by F/2 or more."""
+    for k, lv in enumerate(hist):
+        t = steps - 2 + k
+        rho, us = lv[0], lv[1:1 + len(fvec)]
+        assert float((rho - 1).abs().max()) < 1e-15
+        for u, fc in zip(us, fvec):
+            want = (t + 0.5) * fc
+            assert float((u - want).abs().max()) <= 1e-9 * abs(fc), (k, t)
+
+
+def test_history_levels_under_a_uniform_force():
+    """run_with_history: levels t = n-2, n-1, n carry u = (t + 1/2) F exactly (Guo with the
+    half-force velocity); a level off by one step is off by F / u ~ 1/t."""
+    n, steps, fv = 12, 9, (2e-5, -1e-5)
+    z = torch.zeros(n, n, dtype=D)
+    f = ref.init_populations(z + 1, z, z)
+    fx, fy = z + fv[0], z + fv[1]
+    fend, hist = ref.run_with_history(f, steps, 0.7, fx, fy)
+    _uniform_force_levels(hist, steps, fv)
+    for a, b in zip(hist[2], ref.moments(fend, fx, fy)):
+        assert torch.equal(a, b)
+
+
+def test_exact_difference_physical_velocity_and_levels():
+    """edm_moments returns the exact-difference scheme's physical velocity (j + F/2)/rho:
+    from rest under a uniform force u(t) = (t + 1/2) F (the bare j/rho would give t F), at
+    the levels t = n-2, n-1, n of edm_run_with_history, with the total force F."""
+    n, steps, fv = 12, 9, (3e-5, 1e-5)
+    z = torch.zeros(n, n, dtype=D)
+    f = ref.init_populations(z + 1, z, z)
+    fx, fy = z + fv[0], z + fv[1]
+    _, hist = ref.edm_run_with_history(f, steps, 0.7, fx, fy)
+    _uniform_force_levels(hist, steps, fv)
+    for lv in hist:
+        assert torch.equal(lv[3], fx) and torch.equal(lv[4], fy)
+    # one step from rest: u(0) = F/2, u(1) = 3F/2
+    r0, u0x, _, _, _ = ref.edm_moments(f, fx, fy)
+    r1, u1x, _, _, _ = ref.edm_moments(ref.edm_step(f, 0.7, fx, fy), fx, fy)
+    assert float((u0x - 0.5 * fv[0]).abs().max()) <= 1e-9 * fv[0]
+    assert float((u1x - 1.5 * fv[0]).abs().max()) <= 1e-9 * fv[0]
+
+
+def test_exact_difference_history_closes_the_taylor_green_budget():
+    """edm_run_with_history without force is the LBGK run: the Taylor-Green budget closes on
+    its levels as for run_with_history, and not one level late."""
+    n, tau, steps = 64, 0.6, 200
+    rho, ux, uy = inp.taylor_green(n, 0.01)
+    f = ref.init_populations(rho, ux, uy)
+    _, hist = ref.edm_run_with_history(f, steps, tau)
+    flds = ref.fields_from_history([h[:3] for h in hist], tau)
+    assert max(_full_domain_deltas(flds)) < TG_CLOSURE
+    _, hist_late = ref.edm_run_with_history(f, steps - 1, tau)
+    late = _lhs_one_level_late(flds, ref.fields_from_history([h[:3] for h in hist_late], tau))
+    assert min(_full_domain_deltas(late)) > 1e-3
+
+
+def test_entropic_history_closes_the_taylor_green_budget():
+    """entropic_run_with_history near equilibrium (Taylor-Green at Ma 0.017: alpha within
+    1e-5 of 2, nu_eff within 1e-6 of nu): the budget with its nu_eff field closes on its
+    levels (< 3e-4; measured 3e-6 / 4e-5 at 32^2, t = 100) and not one level late (5.8e-3)."""
+    n, tau, steps = 32, 0.6, 100
+    rho, ux, uy = inp.taylor_green(n, 0.01)
+    f = ref.init_populations(rho, ux, uy)
+    _, hist, nu = ref.entropic_run_with_history(f, steps, tau)
+    assert float((nu - ref.viscosity(tau)).abs().max()) < 1e-6
+    lv = [[h[i] for h in hist] for i in range(3)]
+    flds = ref.balance_fields(lv[0], lv[1], lv[2], None, None, nu)
+    assert max(_full_domain_deltas(flds)) < TG_CLOSURE
+    _, hist_late, nu_late = ref.entropic_run_with_history(f, steps - 1, tau)
+    lv = [[h[i] for h in hist_late] for i in range(3)]
+    late = _lhs_one_level_late(flds, ref.balance_fields(lv[0], lv[1], lv[2], None, None, nu_late))
+    assert min(_full_domain_deltas(late)) > 1e-3
 
 
 def test_worked_numbers():
