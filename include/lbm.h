@@ -418,6 +418,22 @@ LBM_API int lbm_balance_fields_ex(const lbm_balance_input* in, void* ws, size_t 
                           double* dmaps, const int32_t* windows, int32_t nwin,
                           double* wterms, double* term_fields, const lbm_balance_extra* extra);
 
+/* For callers that cannot allocate device memory (code being captured into a
+ * HIP graph, tight serving loops, harnesses that forbid hipMalloc):
+ * lbm_balance_fields without a workspace argument.  Its scratch is a static
+ * device array of 96 MiB per GPU, held by the library until the process ends,
+ * enough for grids up to about 590 x 590 (lbm_balance_workspace_bytes(nx, ny)
+ * must not exceed it; larger grids return LBM_E_NOMEM before anything is
+ * enqueued).  The call itself allocates no device memory and calls no
+ * allocating library routine; the caller passes inputs and outputs exactly as
+ * for lbm_balance_fields and gets the same results (the same kernels).  Every
+ * call on one GPU uses that GPU's one array, so calls that overlap on one GPU
+ * (other host threads, other streams) race; nothing depends on what a previous
+ * call left there.  Synchronous on in->stream, whose device must be current. */
+LBM_API int lbm_balance_fields_noalloc(const lbm_balance_input* in, const int32_t* sizes, int32_t nsizes,
+                                       lbm_balance_stats* out, double* dmaps, const int32_t* windows,
+                                       int32_t nwin, double* wterms, double* term_fields);
+
 /* ---- batched ensemble ---------------------------------------------------------- */
 /* Many independent grids (sizes, tau, drag and force may differ per run; the
  * storage type must be the same) advanced together.  Mode LBM_BATCH_PERSISTENT

@@ -6,9 +6,10 @@ falls back to the CPU: without the built library or without a GPU every entry
 point raises.
 """
 from ._lib import LBMError, LIB_PATH, TERM_NAMES, load  # noqa: F401
-from .sim import (Simulation, Simulation3D, balance_fields, configuration_statistics, copy_bandwidth,  # noqa: F401
-                  energy_spectrum, sample_configurations, stats_to_dict)
+from .sim import (Simulation, Simulation3D, balance_fields, balance_fields_noalloc,  # noqa: F401
+                  configuration_statistics, copy_bandwidth, energy_spectrum, sample_configurations,
+                  stats_to_dict)
 
-__all__ = ["Simulation", "Simulation3D", "balance_fields", "configuration_statistics", "copy_bandwidth",
+__all__ = ["Simulation", "Simulation3D", "balance_fields", "balance_fields_noalloc", "configuration_statistics", "copy_bandwidth",
            "energy_spectrum", "sample_configurations", "stats_to_dict", "LBMError", "load", "LIB_PATH",
            "TERM_NAMES"]

@@ -157,6 +157,8 @@ SIGNATURES = {
     "lbm_balance_workspace_bytes": (_I, [_I32, _I32, C.POINTER(_SZ)]),
     "lbm_balance_fields": (_I, [C.POINTER(BalanceInput), _P, _SZ, C.POINTER(_I32), _I32,
                                 C.POINTER(BalanceStats), _P, C.POINTER(_I32), _I32, _DP, _P]),
+    "lbm_balance_fields_noalloc": (_I, [C.POINTER(BalanceInput), C.POINTER(_I32), _I32,
+                                        C.POINTER(BalanceStats), _P, C.POINTER(_I32), _I32, _DP, _P]),
     "lbm_balance_fields_ex": (_I, [C.POINTER(BalanceInput), _P, _SZ, C.POINTER(_I32), _I32,
                                    C.POINTER(BalanceStats), _P, C.POINTER(_I32), _I32, _DP, _P,
                                    C.POINTER(BalanceExtra)]),

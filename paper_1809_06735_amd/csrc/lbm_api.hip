@@ -695,6 +695,46 @@ int balance_input(lbm_ctx_s* c, lbm_balance_input* out, double* deferred_scalars
   }
   return LBM_OK;
 }
+
+// Scratch of lbm_balance_fields_noalloc: a file-scope device array, one copy per
+// GPU, held until the process ends.  Host code never passes `scratch` itself (in
+// host code the name is a stand-in, not a device address): the per-device address
+// comes from hipGetSymbolAddress on the first call on that device, with the device
+// current, and only that address reaches the kernels.
+constexpr size_t kNoAllocScratchBytes = size_t(96) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int noalloc_scratch(void** out) {
+  int dev = -1;
+  LBM_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(LBM_E_UNSUPPORTED, "device %d beyond the %d the static scratch supports", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p || reinterpret_cast<uintptr_t>(p) % 256 != 0)
+      return fail(LBM_E_HIP, "static scratch address %p not 256-byte aligned", p);
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return LBM_OK;
+}
+
+int validate_fields_input(const lbm_balance_input* in) {
+  if (!in) return fail(LBM_E_INVALID, "input is NULL");
+  for (int k = 0; k < 3; ++k)
+    if (!in->rho[k] || !in->ux[k] || !in->uy[k])
+      return fail(LBM_E_INVALID, "level %d fields must not be NULL", k);
+  if ((in->fx == nullptr) != (in->fy == nullptr))
+    return fail(LBM_E_INVALID, "fx and fy must both be given or both be NULL");
+  if (!std::isfinite(in->nu) || in->nu < 0.0) return fail(LBM_E_INVALID, "nu must be finite, >= 0");
+  return LBM_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -725,17 +765,33 @@ int lbm_balance_fields_ex(const lbm_balance_input* in, void* ws, size_t ws_bytes
   if (!ws || reinterpret_cast<uintptr_t>(ws) % 256 != 0)
     return fail(LBM_E_INVALID, "workspace must be non-NULL and 256-byte aligned");
   if (ws_bytes < need) return fail(LBM_E_NOMEM, "workspace %zu bytes < %zu required", ws_bytes, need);
-  for (int k = 0; k < 3; ++k)
-    if (!in->rho[k] || !in->ux[k] || !in->uy[k])
-      return fail(LBM_E_INVALID, "level %d fields must not be NULL", k);
-  if ((in->fx == nullptr) != (in->fy == nullptr))
-    return fail(LBM_E_INVALID, "fx and fy must both be given or both be NULL");
-  if (!std::isfinite(in->nu) || in->nu < 0.0) return fail(LBM_E_INVALID, "nu must be finite, >= 0");
+  if (int rc = validate_fields_input(in)) return rc;
   if (int rc = validate_balance_request(in->nx, in->ny, sizes, nsizes, out, windows, nwin, wterms, extra))
     return rc;
   Carver cv(ws, ws_bytes);
   BalanceWs b = carve_balance(cv, in->nx, in->ny);
   return run_balance(*in, b, sizes, nsizes, out, dmaps, windows, nwin, wterms, term_fields, extra);
+}
+
+int lbm_balance_fields_noalloc(const lbm_balance_input* in, const int32_t* sizes, int32_t nsizes,
+                               lbm_balance_stats* out, double* dmaps, const int32_t* windows,
+                               int32_t nwin, double* wterms, double* term_fields) {
+  if (!in) return fail(LBM_E_INVALID, "input is NULL");
+  size_t need = 0;
+  if (int rc = lbm_balance_workspace_bytes(in->nx, in->ny, &need)) return rc;
+  if (need > kNoAllocScratchBytes)
+    return fail(LBM_E_NOMEM,
+                "a %d x %d balance needs %zu bytes of scratch; the static scratch holds %zu "
+                "(square grids up to 590 x 590): use lbm_balance_fields with a workspace",
+                in->nx, in->ny, need, kNoAllocScratchBytes);
+  if (int rc = validate_fields_input(in)) return rc;
+  if (int rc = validate_balance_request(in->nx, in->ny, sizes, nsizes, out, windows, nwin, wterms))
+    return rc;
+  void* ws = nullptr;
+  if (int rc = noalloc_scratch(&ws)) return rc;
+  Carver cv(ws, kNoAllocScratchBytes);
+  BalanceWs b = carve_balance(cv, in->nx, in->ny);
+  return run_balance(*in, b, sizes, nsizes, out, dmaps, windows, nwin, wterms, term_fields, nullptr);
 }
 
 int lbm_enstrophy(lbm_ctx c, double* enstrophy) {

@@ -1589,7 +1589,8 @@ int corner_stats(const SatView& v, const BalanceWs& ws, const int32_t* sizes, in
   const size_t plane = static_cast<size_t>(nx) * ny;
   // Without histograms or maps, a side L whose double 2 L is also asked for (and
   // is not the whole domain) shares one walk of the tables with it.
-  std::vector<int> twin(nsizes, -1);  // index of side 2 L, or -2 for a side done with its half
+  int twin[kMaxSizes];  // index of side 2 L, or -2 for a side done with its half
+  for (int k = 0; k < nsizes; ++k) twin[k] = -1;
   if (!hist && !dmaps) {
     for (int k = 0; k < nsizes; ++k) {
       if (twin[k] != -1) continue;
@@ -1781,12 +1782,13 @@ int run_balance(const lbm_balance_input& in, const BalanceWs& ws, const int32_t*
     LBM_HIP(hipGetLastError());
   }
   const size_t sv = static_cast<size_t>(nsizes) * kStatVals;
-  std::vector<double> st(out ? sv : 0), sst(sampled ? sv : 0);
+  // statistics land in fixed-size host arrays (no allocation on this path)
+  double st[kMaxSizes * kStatVals], sst[kMaxSizes * kStatVals];
   std::vector<unsigned long long> hh(hist && extra->hist ? nsizes * hslot : 0);
   std::vector<unsigned long long> hs(hist && extra->sample_hist ? nsizes * hslot : 0);
-  if (!st.empty()) LBM_HIP(hipMemcpyAsync(st.data(), ws.pool, sv * sizeof(double), hipMemcpyDeviceToHost, s));
-  if (!sst.empty())
-    LBM_HIP(hipMemcpyAsync(sst.data(), ws.pool + static_cast<size_t>(kMaxSizes) * kStatVals,
+  if (out) LBM_HIP(hipMemcpyAsync(st, ws.pool, sv * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (sampled)
+    LBM_HIP(hipMemcpyAsync(sst, ws.pool + static_cast<size_t>(kMaxSizes) * kStatVals,
                            sv * sizeof(double), hipMemcpyDeviceToHost, s));
   if (!hh.empty())
     LBM_HIP(hipMemcpyAsync(hh.data(), hall, hh.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
@@ -1796,8 +1798,8 @@ int run_balance(const lbm_balance_input& in, const BalanceWs& ws, const int32_t*
     LBM_HIP(hipMemcpyAsync(wterms, ws.wterms, sizeof(double) * LBM_NWVALS * nwin, hipMemcpyDeviceToHost, s));
   LBM_HIP(hipStreamSynchronize(s));
   for (int k = 0; k < nsizes; ++k) {
-    if (out) fill_stats(st.data() + static_cast<size_t>(k) * kStatVals, sizes[k], out[k]);
-    if (sampled) fill_stats(sst.data() + static_cast<size_t>(k) * kStatVals, sizes[k], extra->sample_out[k]);
+    if (out) fill_stats(st + static_cast<size_t>(k) * kStatVals, sizes[k], out[k]);
+    if (sampled) fill_stats(sst + static_cast<size_t>(k) * kStatVals, sizes[k], extra->sample_out[k]);
     auto unpack = [&](const std::vector<unsigned long long>& src, int64_t* dst) {
       for (int q = 0; q < 3; ++q)
         for (int i = 0; i <= ne; ++i)

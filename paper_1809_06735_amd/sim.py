@@ -370,6 +370,37 @@ class Simulation:
         return ms.value, n.value
 
 
+def balance_fields_noalloc(rho, ux, uy, nu, sizes, fx=None, fy=None, windows=None, maps=False,
+                           term_fields=False, device="cuda", stream=None):
+    """balance_fields through lbm_balance_fields_noalloc: the library's static per-GPU
+    scratch instead of a workspace (grids up to about 590^2).  rho/ux/uy: three levels
+    (n-2, n-1, n) as device FP64 [ny, nx] tensors or host arrays; nu a scalar."""
+    _require_gpu()
+    lib = L.load()
+    dev = torch.device(device)
+    rs = [_dev64(a, dev) for a in rho]
+    xs = [_dev64(a, dev) for a in ux]
+    ys = [_dev64(a, dev) for a in uy]
+    ny, nx = rs[2].shape
+    f_x = _dev64(fx, dev) if fx is not None else None
+    f_y = _dev64(fy, dev) if fy is not None else None
+    inp = L.BalanceInput()
+    inp.nx, inp.ny, inp.nu = nx, ny, float(nu)
+    for k in range(3):
+        inp.rho[k] = rs[k].data_ptr()
+        inp.ux[k] = xs[k].data_ptr()
+        inp.uy[k] = ys[k].data_ptr()
+    inp.fx = f_x.data_ptr() if f_x is not None else None
+    inp.fy = f_y.data_ptr() if f_y is not None else None
+    inp.stream = _stream_handle(stream).value
+    sizes, sz, out, win, nwin, wterms = _balance_args(nx, ny, sizes, windows)
+    dm = torch.empty((len(sizes), 3, ny, nx), dtype=torch.float64, device=dev) if maps else None
+    tf = torch.empty((L.NTERMS, ny, nx), dtype=torch.float64, device=dev) if term_fields else None
+    L.check(lib.lbm_balance_fields_noalloc(C.byref(inp), sz, len(sizes), out, _ptr(dm), win, nwin, wterms,
+                                           _ptr(tf)), "lbm_balance_fields_noalloc")
+    return _balance_result(sizes, out, dm, nwin, wterms, tf, nx, ny)
+
+
 def balance_fields(rho, ux, uy, nu, sizes, fx=None, fy=None, windows=None, maps=False,
                    term_fields=False, device="cuda", stream=None, edges=None, sample=None,
                    all_corners=True, workspace=None, accumulate=False):

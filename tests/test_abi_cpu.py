@@ -100,6 +100,20 @@ def test_balance_workspace_and_adjoint_validation():
     assert lib.lbm_workspace_bytes(C.byref(cfg(nx=20000, ny=20000, with_balance=1)),
                                    C.byref(n)) == L.LBM_E_UNSUPPORTED
     assert lib.lbm_workspace_bytes(C.byref(cfg(nx=20000, ny=20000)), C.byref(n)) == L.LBM_OK
+    # the allocation-free balance refuses grids beyond its static scratch (host check, before
+    # anything touches a device) and validates its arguments like lbm_balance_fields
+    inp = L.BalanceInput()
+    for k in range(3):
+        inp.rho[k] = inp.ux[k] = inp.uy[k] = 256
+    inp.nx, inp.ny, inp.nu = 640, 640, 0.001
+    sz = (C.c_int32 * 1)(8)
+    st = (L.BalanceStats * 1)()
+    assert lib.lbm_balance_fields_noalloc(C.byref(inp), sz, 1, st, None, None, 0, None, None) == L.LBM_E_NOMEM
+    assert b"scratch" in lib.lbm_last_error()
+    inp.nx = inp.ny = 64
+    inp.rho[1] = None
+    assert lib.lbm_balance_fields_noalloc(C.byref(inp), sz, 1, st, None, None, 0, None, None) == L.LBM_E_INVALID
+    assert lib.lbm_balance_fields_noalloc(None, sz, 1, st, None, None, 0, None, None) == L.LBM_E_INVALID
     assert lib.lbm_copy(None, None, 16, None) == L.LBM_E_INVALID
     assert lib.lbm_copy(C.c_void_p(256), C.c_void_p(512), 15, None) == L.LBM_E_INVALID
 
