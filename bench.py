@@ -66,7 +66,12 @@ def profile_record(kernel, workload, tile):
         rec = json.loads(line.split(":", 1)[1])
         if rec.get("source_sha256_16") != step_source_digest(kernel):
             return None
-        if list(rec.get("tile", [])) == list(tile):
+        rt, tl = list(rec.get("tile", [])), list(tile)
+        if rt == tl:
+            return rec
+        # band heights that give the same number of bands are the same launch
+        lo, hi = rec.get("ry_range", (None, None))
+        if lo is not None and len(rt) == len(tl) == 8 and rt[:3] + rt[4:] == tl[:3] + tl[4:] and lo <= tl[3] <= hi:
             return rec
     return None
 
@@ -80,6 +85,27 @@ def traffic_from_profile(kernel, workload, tile):
 # VALU issue of the chip: one wavefront instruction per CU and clock, 256 CUs at 2.4 GHz,
 # 64 lanes (FP32 without packed instructions, which this library does not use).
 VALU_LANE_OPS_PER_S = 256 * 2.4e9 * 64
+
+
+def method_valu_per_update(workload="forced4096"):
+    """VALU lane-instructions per lattice update of the method itself: the counted
+    instructions of the one-step kernel (one collision per site, no halo recomputation),
+    the leanest shape among the committed counter records of the current source; None if
+    no record is current."""
+    path = os.path.join(ROOT, "profiles", f"k_step_{workload}_traffic.md")
+    if not os.path.exists(path):
+        return None, None
+    best = (None, None)
+    for line in open(path):
+        if not line.startswith("TRAFFIC_JSON:"):
+            continue
+        rec = json.loads(line.split(":", 1)[1])
+        v = rec.get("valu_lane_instructions_per_update")
+        if rec.get("source_sha256_16") != step_source_digest("k_step") or not v:
+            continue
+        if best[0] is None or v < best[0]:
+            best = (v, rec.get("tile"))
+    return best
 
 
 def single_step_kernel(n, tau, alpha, fx, fy, steps=400):
@@ -391,6 +417,61 @@ def balance4096(log, calls=5):
     return out
 
 
+def tau_sweep_4096(log, tile=None, steps=5000, every=500):
+    """The forced 4096^2 workload's tau sweep {0.5005, 0.501, 0.505, 0.51, 0.55}: from rest,
+    `steps` steps per tau with the balance at L = 8..256 every `every` steps (in line), in
+    the launch shape of the headline run.  Per tau: MLUPS of the whole run, U_rms and max
+    Mach at the end, mean delta^E / delta^Omega at L = 8 and 256, and, if the run diverges,
+    the step at which the library reported it (LBM_E_DIVERGED), as data."""
+    import numpy as np
+    import torch
+    import lbm_inputs as inp
+    from paper_1809_06735_amd import LBMError, Simulation
+    from paper_1809_06735_amd import _lib as L
+    w = inp.WORKLOADS["forced4096"]
+    n = w.n
+    fx, fy = inp.forcing_field(n, seed=w.seed, alpha=w.alpha)
+    z = np.zeros((n, n))
+    out = {"grid": n, "steps_per_tau": steps, "balance_every": every, "balance_sizes": list(SIZES),
+           "shape": list(tile) if tile else None, "runs": {}}
+    for tau in w.taus:
+        sim = Simulation(np.ones((n, n)), z, z, tau, dtype="f32", fx=fx, fy=fy, alpha=w.alpha,
+                         with_balance=True)
+        if tile:
+            sim.set_tile(*tile)
+        rec = {"diverged_at": None}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = None
+        try:
+            for _ in range(steps // every):
+                sim.step(every)
+                res = sim.balance(SIZES)
+            torch.cuda.synchronize()
+        except LBMError as e:
+            if e.code != L.LBM_E_DIVERGED:
+                raise
+            rec["diverged_at"] = sim.time
+            rec["error"] = str(e)
+        dt = time.perf_counter() - t0
+        rec["MLUPS_with_balance"] = round(n * n * sim.time / dt / 1e6, 1)
+        rec["steps_run"] = sim.time
+        if rec["diverged_at"] is None:
+            _, _, _, sc = sim.moments()
+            rec["U_rms"] = float(np.sqrt(2 * sc["energy"] / sc["mass"]))
+            rec["max_Mach"] = float(sc["max_speed"] * np.sqrt(3.0))
+            st = {s["L"]: s for s in res["stats"]}
+            rec["mean_dE"] = {str(k): st[k]["dE"]["mean"] for k in (SIZES[0], SIZES[-1])}
+            rec["mean_dZ"] = {str(k): st[k]["dZ"]["mean"] for k in (SIZES[0], SIZES[-1])}
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+        out["runs"][str(tau)] = rec
+        log(f"[bench] tau sweep {tau}: {rec['MLUPS_with_balance']} MLUPS, diverged_at {rec['diverged_at']}, "
+            f"U_rms {rec.get('U_rms')}")
+    return out
+
+
 def cpu_baseline(n, tau, alpha, fx, fy, steps):
     import torch
     from oracle import ref
@@ -410,12 +491,13 @@ def cpu_baseline(n, tau, alpha, fx, fy, steps):
 
 EXTRAS = {"paper_set_up_256": paper_set_up_256, "paper_statistics_256": paper_statistics_256,
           "entropic_1024": entropic_1024, "d3q19_256": d3q19_256, "decay1024": decay1024,
+          "tau_sweep_4096": tau_sweep_4096,
           "balance4096": balance4096}
 
 
-def _ensemble_extra(log):
+def _ensemble_extra(log, steps=500):
     from paper_1809_06735_amd import ensemble as ens_mod
-    return ens_mod.bench_ensemble(log=log)
+    return ens_mod.bench_ensemble(steps=steps, log=log)
 
 
 def _adjoint_extra(log):
@@ -443,10 +525,21 @@ def main():
                     help="run one extra measurement alone and print its JSON (profiling runs)")
     ap.add_argument("--with-copy", action="store_true",
                     help="with --only-extra: also run the 1 GiB copy kernel 5 times (counter scale)")
+    ap.add_argument("--extra-steps", type=int, default=None,
+                    help="with --only-extra: the extra's step count (shorter profiling runs of the "
+                         "extras that take one)")
     a = ap.parse_args()
     if a.only_extra:
+        import inspect
         import torch
-        res = EXTRAS[a.only_extra](log)
+        fn = EXTRAS[a.only_extra]
+        kw = {}
+        if a.extra_steps is not None:
+            if "steps" not in inspect.signature(fn).parameters:
+                print(f"--extra-steps: {a.only_extra} takes no step count", file=sys.stderr)
+                sys.exit(2)
+            kw["steps"] = a.extra_steps
+        res = fn(log, **kw)
         if a.with_copy:
             from paper_1809_06735_amd import _lib as L
             lib = L.load()
@@ -537,18 +630,12 @@ def main():
     alg_bytes = bytes_per_site * n * n        # per launch, whatever the steps fused
     achieved = alg_bytes / avg_launch_s / 1e9
     traffic = traffic_from_profile(kernel, "forced4096", tile)
-    # the VALU-issue view of the same kernel: its VALU instructions per lattice update
-    # (halo recomputation included) from the committed counters, against the chip's issue rate
+    # VALU instructions per lattice update: of this kernel in this shape (halo recomputation
+    # and LDS addressing included) and of the method alone (the one-step kernel), from the
+    # committed counters of the current sources
     rec = profile_record(kernel, "forced4096", tile)
     vpl = rec.get("valu_lane_instructions_per_update") if rec else None
-    valu_view = None
-    if vpl:
-        ceil_mlups = VALU_LANE_OPS_PER_S / vpl / 1e6
-        valu_view = {"bound": "alu", "valu_per_lattice_update": vpl,
-                     "peak": round(VALU_LANE_OPS_PER_S / 1e12, 2), "unit": "T VALU lane-instr/s",
-                     "ceiling_MLUPS": round(ceil_mlups, 1),
-                     "note": "kernel MLUPS x VALU per update over 256 CUs x 64 lanes x 2.4 GHz; "
-                             "frac and frac_alone filled in below"}
+    vpl_method, vpl_method_tile = method_valu_per_update()
     # the same kernel alone on the GPU (no balance beside it): 64 bulk launches, one graph
     torch.cuda.synchronize()
     sim.step_time(reset=True)
@@ -558,10 +645,9 @@ def main():
     sim.step_timing(False)
     alone_ms, alone_n = sim.step_time(reset=True)
     alone_s = alone_ms * 1e-3 / max(alone_n, 1)
-    if valu_view:
-        valu_view["frac"] = round(n * n * spl / avg_launch_s / 1e6 / valu_view["ceiling_MLUPS"], 4)
-        valu_view["frac_alone"] = round(n * n * spl / alone_s / 1e6 / valu_view["ceiling_MLUPS"], 4)
-        valu_view["note"] = "kernel MLUPS x VALU per update over 256 CUs x 64 lanes x 2.4 GHz"
+    kern_mlups = n * n * spl / avg_launch_s / 1e6
+    alone_mlups = n * n * spl / alone_s / 1e6
+    peak_valu = VALU_LANE_OPS_PER_S / 1e12
     st = last["stats"]
     log(f"[bench] {mlups:.0f} MLUPS whole pass; {kernel} ({spl} steps/launch) "
         f"{avg_launch_s * 1e6:.1f} us/launch = {achieved:.0f} GB/s ({achieved / HBM_PEAK_GBS:.1%} "
@@ -587,23 +673,45 @@ def main():
                    "grid": n, "tau": a.tau, "lbgk_steps_per_step": STEPS_PER_PASS,
                    "balance_sizes": list(SIZES), "step_kernel_shape": list(tile),
                    "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+        # With K steps per launch (temporal blocking) the kernel moves 80/K B per lattice
+        # update and is limited by VALU issue, not HBM: the headline view is the method's
+        # VALU instructions (the one-step kernel's count per update) issued per second
+        # against the chip's issue rate; the HBM views per launch and per update follow.
+        "roofline": {"bound": "alu",
+                     "achieved": round(kern_mlups * vpl_method / 1e6, 3) if vpl_method else None,
+                     "peak": round(peak_valu, 3), "unit": "T VALU lane-instr/s",
+                     "frac": round(kern_mlups * vpl_method / 1e6 / peak_valu, 4) if vpl_method else None,
                      "traffic": traffic,
                      "kernel": f"{kernel}<float, K={spl}> (pull stream + BGK collide + Guo force, "
                                f"{spl} steps per launch)" if spl > 1 else
                                "k_step (fused pull stream + BGK collide + Guo force)",
                      "steps_per_launch": spl,
-                     "algorithmic_bytes_per_launch": alg_bytes,
-                     "bytes_per_lattice_update": bytes_per_site / spl,
                      "avg_launch_us": round(avg_launch_s * 1e6, 2),
-                     "kernel_MLUPS": round(n * n * spl / avg_launch_s / 1e6, 1),
+                     "kernel_MLUPS": round(kern_mlups, 1),
+                     "method_valu_per_lattice_update": vpl_method,
+                     "method_valu_counted_on": vpl_method_tile,
+                     "kernel_valu_per_lattice_update": vpl,
+                     "kernel_valu_frac": round(kern_mlups * vpl / 1e6 / peak_valu, 4) if vpl else None,
+                     "peak_derivation": "256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = one wave64 VALU "
+                                        "instruction per CU and clock (FP32 without packed "
+                                        "instructions)",
+                     "hbm_per_launch": {"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                        "frac": round(achieved / HBM_PEAK_GBS, 4),
+                                        "algorithmic_bytes_per_launch": alg_bytes,
+                                        "note": "80 B per site per launch (9 populations read and "
+                                                "written, the force read), whatever K"},
+                     "hbm_per_lattice_update": {
+                         "bytes_per_lattice_update": bytes_per_site,
+                         "achieved": round(bytes_per_site * kern_mlups * 1e6 / 1e9, 1),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(bytes_per_site * kern_mlups * 1e6 / 1e9 / HBM_PEAK_GBS, 4),
+                         "note": "the single-step roofline (80 B per lattice update); above 1 because "
+                                 "temporal blocking advances K steps per HBM round trip"},
                      "alone": {"avg_launch_us": round(alone_s * 1e6, 2),
-                               "achieved": round(alg_bytes / alone_s / 1e9, 1),
-                               "frac": round(alg_bytes / alone_s / 1e9 / HBM_PEAK_GBS, 4),
-                               "kernel_MLUPS": round(n * n * spl / alone_s / 1e6, 1),
-                               "note": "the same kernel timed without the balance running beside it"},
-                     "valu": valu_view},
+                               "kernel_MLUPS": round(alone_mlups, 1),
+                               "frac": round(alone_mlups * vpl_method / 1e6 / peak_valu, 4) if vpl_method else None,
+                               "hbm_per_launch_frac": round(alg_bytes / alone_s / 1e9 / HBM_PEAK_GBS, 4),
+                               "note": "the same kernel timed without the balance running beside it"}},
         "balance_at_end": {str(s["L"]): {"mean_dE": s["dE"]["mean"], "mean_dZ": s["dZ"]["mean"],
                                          "mean_Ma": s["Ma"]["mean"]} for s in st},
     }
@@ -663,6 +771,10 @@ def main():
             extras["balance4096"] = balance4096(log)
         except Exception as e:  # noqa: BLE001
             extras["balance4096"] = f"error: {e}"
+        try:
+            extras["tau_sweep_4096"] = tau_sweep_4096(log, tile=tile)
+        except Exception as e:  # noqa: BLE001
+            extras["tau_sweep_4096"] = f"error: {e}"
         try:
             extras["d3q19_256"] = d3q19_256(log)
         except Exception as e:  # noqa: BLE001
