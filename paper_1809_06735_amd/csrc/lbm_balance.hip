@@ -23,6 +23,8 @@
 //             side L and its double 2L share one walk when both are asked for.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -50,6 +52,7 @@ struct PassArgs {
   int nx, ny;
   double* terms;
   double* aux;
+  double* psum;  // paired passes: [13][blocks] workgroup sums of each term field
 };
 
 // Weights of Eq. 18 per offset m = 1..4 (the difference g(i+m) - g(i-m) is
@@ -237,11 +240,46 @@ __device__ __forceinline__ void dx_pair(const double (&v)[10], double (&d)[2]) {
   }
 }
 
+// Workgroup sums of the term fields a paired pass writes, for the field means
+// of the tables: the 256 threads' values go through LDS, 32 threads per field add
+// eight each and a 32-lane butterfly adds those, so the order is fixed.
+// psum[field * blocks + block], block = blockIdx.y * gridDim.x + blockIdx.x.
+template <int... F>
+__device__ __forceinline__ void block_field_sums(const double (&v)[sizeof...(F)], double* psum) {
+  constexpr int NF = sizeof...(F);
+  static_assert(NF * 32 <= 256, "32 threads per field");
+  constexpr int fld[NF] = {F...};
+  __shared__ double sh[NF][256];
+  const int t = threadIdx.y * 64 + threadIdx.x;
+#pragma unroll
+  for (int f = 0; f < NF; ++f) sh[f][t] = v[f];
+  __syncthreads();
+  const int f = t >> 5, l = t & 31;
+  double acc = 0.0;
+  if (f < NF) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc += sh[f][l + 32 * j];
+  }
+#pragma unroll
+  for (int o = 16; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 32);
+  if (l == 0 && f < NF) {
+    int field = fld[0];
+#pragma unroll
+    for (int k = 1; k < NF; ++k) field = f == k ? fld[k] : field;
+    const size_t blocks = static_cast<size_t>(gridDim.x) * gridDim.y;
+    psum[field * blocks + blockIdx.y * gridDim.x + blockIdx.x] = acc;
+  }
+}
+
 __global__ void __launch_bounds__(256) k_bal_a2(PassArgs a) {
   const int nx = a.nx, ny = a.ny;
-  const int x = 2 * (blockIdx.x * blockDim.x + threadIdx.x);
-  const int y = blockIdx.y * blockDim.y + threadIdx.y;
-  if (x >= nx || y >= ny) return;
+  // threads past the grid's edge evaluate the last pair of their row (or the
+  // last row) and store nothing: every thread takes part in the workgroup sums
+  const int xt = 2 * (blockIdx.x * blockDim.x + threadIdx.x);
+  const int yt = blockIdx.y * blockDim.y + threadIdx.y;
+  const bool live = xt < nx && yt < ny;
+  const int x = xt < nx ? xt : nx - 2;
+  const int y = yt < ny ? yt : ny - 1;
   const size_t plane = static_cast<size_t>(nx) * ny;
   const size_t row = static_cast<size_t>(y) * nx;
   const size_t i = row + x;
@@ -343,28 +381,38 @@ __global__ void __launch_bounds__(256) k_bal_a2(PassArgs a) {
     o[11][s] = syy;
     o[12][s] = sxy;
   }
-  double* t = a.terms;
-  st2(t, LBM_T_LHS_E * plane + i, o[0][0], o[0][1]);
-  st2(t, LBM_T_E2 * plane + i, o[1][0], o[1][1]);
-  st2(t, LBM_T_E3 * plane + i, o[2][0], o[2][1]);
-  st2(t, LBM_T_E4 * plane + i, o[3][0], o[3][1]);
-  st2(t, LBM_T_LHS_Z * plane + i, o[4][0], o[4][1]);
-  st2(t, LBM_T_Z2 * plane + i, o[5][0], o[5][1]);
-  st2(t, LBM_T_USQ * plane + i, o[6][0], o[6][1]);
-  double* ax = a.aux;
-  st2(ax, A_E * plane + i, o[7][0], o[7][1]);
-  st2(ax, A_OM2 * plane + i, o[8][0], o[8][1]);
-  st2(ax, A_W * plane + i, o[9][0], o[9][1]);
-  st2(ax, A_SXX * plane + i, o[10][0], o[10][1]);
-  st2(ax, A_SYY * plane + i, o[11][0], o[11][1]);
-  st2(ax, A_SXY * plane + i, o[12][0], o[12][1]);
+  if (live) {
+    double* t = a.terms;
+    st2(t, LBM_T_LHS_E * plane + i, o[0][0], o[0][1]);
+    st2(t, LBM_T_E2 * plane + i, o[1][0], o[1][1]);
+    st2(t, LBM_T_E3 * plane + i, o[2][0], o[2][1]);
+    st2(t, LBM_T_E4 * plane + i, o[3][0], o[3][1]);
+    st2(t, LBM_T_LHS_Z * plane + i, o[4][0], o[4][1]);
+    st2(t, LBM_T_Z2 * plane + i, o[5][0], o[5][1]);
+    st2(t, LBM_T_USQ * plane + i, o[6][0], o[6][1]);
+    double* ax = a.aux;
+    st2(ax, A_E * plane + i, o[7][0], o[7][1]);
+    st2(ax, A_OM2 * plane + i, o[8][0], o[8][1]);
+    st2(ax, A_W * plane + i, o[9][0], o[9][1]);
+    st2(ax, A_SXX * plane + i, o[10][0], o[10][1]);
+    st2(ax, A_SYY * plane + i, o[11][0], o[11][1]);
+    st2(ax, A_SXY * plane + i, o[12][0], o[12][1]);
+  }
+  double v[7];
+#pragma unroll
+  for (int k = 0; k < 7; ++k) v[k] = live ? o[k][0] + o[k][1] : 0.0;
+  block_field_sums<LBM_T_LHS_E, LBM_T_E2, LBM_T_E3, LBM_T_E4, LBM_T_LHS_Z, LBM_T_Z2, LBM_T_USQ>(v, a.psum);
 }
 
 __global__ void __launch_bounds__(256) k_bal_b2(PassArgs a) {
   const int nx = a.nx, ny = a.ny;
-  const int x = 2 * (blockIdx.x * blockDim.x + threadIdx.x);
-  const int y = blockIdx.y * blockDim.y + threadIdx.y;
-  if (x >= nx || y >= ny) return;
+  // threads past the grid's edge evaluate the last pair of their row (or the
+  // last row) and store nothing: every thread takes part in the workgroup sums
+  const int xt = 2 * (blockIdx.x * blockDim.x + threadIdx.x);
+  const int yt = blockIdx.y * blockDim.y + threadIdx.y;
+  const bool live = xt < nx && yt < ny;
+  const int x = xt < nx ? xt : nx - 2;
+  const int y = yt < ny ? yt : ny - 1;
   const size_t plane = static_cast<size_t>(nx) * ny;
   const size_t row = static_cast<size_t>(y) * nx;
   const size_t i = row + x;
@@ -502,21 +550,31 @@ __global__ void __launch_bounds__(256) k_bal_b2(PassArgs a) {
     o[5][s] = hx;
     o[6][s] = hy;
   }
-  double* t = a.terms;
-  st2(t, LBM_T_E1 * plane + i, o[0][0], o[0][1]);
-  st2(t, LBM_T_E5 * plane + i, o[1][0], o[1][1]);
-  st2(t, LBM_T_Z1 * plane + i, o[2][0], o[2][1]);
-  st2(t, LBM_T_Z3 * plane + i, o[3][0], o[3][1]);
-  st2(t, LBM_T_Z4 * plane + i, o[4][0], o[4][1]);
-  st2(a.aux, A_HX * plane + i, o[5][0], o[5][1]);
-  st2(a.aux, A_HY * plane + i, o[6][0], o[6][1]);
+  if (live) {
+    double* t = a.terms;
+    st2(t, LBM_T_E1 * plane + i, o[0][0], o[0][1]);
+    st2(t, LBM_T_E5 * plane + i, o[1][0], o[1][1]);
+    st2(t, LBM_T_Z1 * plane + i, o[2][0], o[2][1]);
+    st2(t, LBM_T_Z3 * plane + i, o[3][0], o[3][1]);
+    st2(t, LBM_T_Z4 * plane + i, o[4][0], o[4][1]);
+    st2(a.aux, A_HX * plane + i, o[5][0], o[5][1]);
+    st2(a.aux, A_HY * plane + i, o[6][0], o[6][1]);
+  }
+  double v[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) v[k] = live ? o[k][0] + o[k][1] : 0.0;
+  block_field_sums<LBM_T_E1, LBM_T_E5, LBM_T_Z1, LBM_T_Z3, LBM_T_Z4>(v, a.psum);
 }
 
 __global__ void __launch_bounds__(256) k_bal_c2(PassArgs a) {
   const int nx = a.nx, ny = a.ny;
-  const int x = 2 * (blockIdx.x * blockDim.x + threadIdx.x);
-  const int y = blockIdx.y * blockDim.y + threadIdx.y;
-  if (x >= nx || y >= ny) return;
+  // threads past the grid's edge evaluate the last pair of their row (or the
+  // last row) and store nothing: every thread takes part in the workgroup sums
+  const int xt = 2 * (blockIdx.x * blockDim.x + threadIdx.x);
+  const int yt = blockIdx.y * blockDim.y + threadIdx.y;
+  const bool live = xt < nx && yt < ny;
+  const int x = xt < nx ? xt : nx - 2;
+  const int y = yt < ny ? yt : ny - 1;
   const size_t plane = static_cast<size_t>(nx) * ny;
   const size_t row = static_cast<size_t>(y) * nx;
   const double* W = a.aux + A_W * plane;
@@ -555,7 +613,9 @@ __global__ void __launch_bounds__(256) k_bal_c2(PassArgs a) {
     const double fy = (4.0 * e1 - e2 + (4.0 / 21.0) * e3 - (1.0 / 56.0) * e4) / 5.0;
     out[s] = fx - fy;
   }
-  st2(a.terms, LBM_T_Z5 * plane + row + x, out[0], out[1]);
+  if (live) st2(a.terms, LBM_T_Z5 * plane + row + x, out[0], out[1]);
+  const double v[1] = {live ? out[0] + out[1] : 0.0};
+  block_field_sums<LBM_T_Z5>(v, a.psum);
 }
 
 // ---- field means ---------------------------------------------------------------------
@@ -587,12 +647,22 @@ __global__ void __launch_bounds__(kRedThreads) k_field_sums(const double* __rest
   }
 }
 
+// means[f] = inv_n times the sum of partials[f][0 .. nblocks); each thread keeps
+// eight loads in flight (eight running sums, added in a fixed order at the end)
 __global__ void __launch_bounds__(kRedThreads) k_field_means(const double* __restrict__ partials,
                                                               int nblocks, double inv_n,
                                                               double* means) {
   __shared__ double sh[kRedThreads / 64];
-  double acc = 0.0;
-  for (int b = threadIdx.x; b < nblocks; b += kRedThreads) acc += partials[blockIdx.x * nblocks + b];
+  const double* p = partials + static_cast<size_t>(blockIdx.x) * nblocks;
+  double a8[8] = {};
+  for (int b0 = threadIdx.x; b0 < nblocks; b0 += 8 * kRedThreads) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int b = b0 + q * kRedThreads;
+      a8[q] += b < nblocks ? p[b] : 0.0;
+    }
+  }
+  double acc = ((a8[0] + a8[1]) + (a8[2] + a8[3])) + ((a8[4] + a8[5]) + (a8[6] + a8[7]));
   acc = wsum(acc);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
   __syncthreads();
@@ -965,16 +1035,30 @@ struct SumStat {
     mn = 1e300;
     mx = -1e300;
   }
-  __device__ void add(double v) {
-    if (!isfinite(v)) {
-      nan += 1.0;
-      return;
-    }
-    n += 1.0;
-    s1 += v;
-    s2 += v * v;
-    mn = fmin(mn, v);
-    mx = fmax(mx, v);
+  // add(v) when c (wave-uniform in the walks) holds, else nothing.  Both adds
+  // are without branches (a lane-divergent branch costs exec-mask bookkeeping
+  // and register copies on every window) and give the same values as skipping
+  // v when it is not finite.
+  __device__ __forceinline__ void add_if(double v, bool c) {
+    const bool fin = isfinite(v);
+    const bool ok = c && fin;
+    const double w = ok ? v : 0.0;
+    n += ok ? 1.0 : 0.0;
+    nan += (c && !fin) ? 1.0 : 0.0;
+    s1 += w;
+    s2 += w * w;
+    mn = ok ? fmin(mn, v) : mn;
+    mx = ok ? fmax(mx, v) : mx;
+  }
+  __device__ __forceinline__ void add(double v) {
+    const bool ok = isfinite(v);
+    const double w = ok ? v : 0.0;
+    n += ok ? 1.0 : 0.0;
+    nan += ok ? 0.0 : 1.0;
+    s1 += w;
+    s2 += w * w;
+    mn = ok ? fmin(mn, v) : mn;
+    mx = ok ? fmax(mx, v) : mx;
   }
 };
 
@@ -1286,44 +1370,203 @@ __device__ __forceinline__ void stride_windows2(const SatView& v, int L, int x0,
   }
 }
 
+// Buffer resource over `bytes` bytes from a wave-uniform address (raw buffer,
+// 32-bit elements format word of the gfx9 family).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void* p, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, static_cast<int>(bytes), 0x00020000);
+}
+__device__ __forceinline__ double buf_load_f64(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, static_cast<int>(voff),
+                                                                         static_cast<int>(soff), 0));
+}
+
+// stride_windows2 for a workgroup whose windows neither wrap in x (every lane's
+// x0 + 2 L <= nx) nor in y (the sequence's last row y0 + (nwin + 1) L <= ny):
+// no totals rows or columns, no selects.  A table row's fields are read through a
+// buffer resource built per row from its wave-uniform address (scalar
+// registers), with each lane's byte offsets x0, x0 + L, x0 + 2 L fixed for the
+// walk and the field offsets as scalar offsets, so no address arithmetic runs on
+// the vector units.  The raw loads of rows j + 1 and j + 2 are in flight while
+// row j's windows are evaluated (two buffers by the parity of j, and the
+// differences of the two previous rows kept by parity as well).  The walk is
+// unrolled completely (nwin <= kStrideSteps): loads past the sequence's last row
+// re-read that row and the windows that do not exist are masked out, so there
+// are no branches and every value keeps its registers.  The window values are
+// computed exactly as in stride_windows2.
+template <int F0, int NF>
+__device__ __forceinline__ void stride_windows2_inner(const SatView& v, int L, int x0, int y0, int nwin,
+                                                      SumStat& r1, SumStat& r2) {
+  const unsigned fsb = static_cast<unsigned>(v.nx + 1) * 8u;  // bytes between fields of one row
+  const double* base = v.P + static_cast<size_t>(F0) * (v.nx + 1);
+  const size_t rs = static_cast<size_t>(v.nx + 1) * v.nf;     // doubles between table rows
+  const unsigned o0 = static_cast<unsigned>(x0) * 8u;
+  const unsigned o1 = static_cast<unsigned>(x0 + L) * 8u;
+  const unsigned o2 = static_cast<unsigned>(x0 + 2 * L) * 8u;
+  const double inv1 = 1.0 / (double(L) * double(L));
+  const double inv2 = 1.0 / (double(2 * L) * double(2 * L));
+  double mu[NF];
+#pragma unroll
+  for (int k = 0; k < NF; ++k) mu[k] = v.means[F0 + k];
+  struct Raw {
+    double b0[NF], b1[NF], b2[NF];
+  };
+  const int last = nwin + 1;  // rows 0 .. last of the sequence are read
+  auto load = [&](int j, Raw& w) {
+    const int y = y0 + min(j, last) * L;
+    __amdgpu_buffer_rsrc_t r = raw_rsrc(base + static_cast<size_t>(y) * rs, NF * fsb);
+#pragma unroll
+    for (int k = 0; k < NF; ++k) {
+      w.b0[k] = buf_load_f64(r, o0, k * fsb);
+      w.b1[k] = buf_load_f64(r, o1, k * fsb);
+      w.b2[k] = buf_load_f64(r, o2, k * fsb);
+    }
+  };
+  Raw rw[2];
+  double h1[2][NF], h2[2][NF];  // differences of the rows j - 1, j - 2 by parity
+  load(0, rw[0]);
+  load(1, rw[1]);
+#pragma unroll
+  for (int k = 0; k < NF; ++k) {
+    h1[0][k] = rw[0].b1[k] - rw[0].b0[k];
+    h2[0][k] = rw[0].b2[k] - rw[0].b0[k];
+  }
+  load(2, rw[0]);
+  auto row_step = [&](auto parity, int j) {
+    constexpr int P = decltype(parity)::value;
+    double d1[NF], d2[NF];
+#pragma unroll
+    for (int k = 0; k < NF; ++k) {
+      d1[k] = rw[P].b1[k] - rw[P].b0[k];
+      d2[k] = rw[P].b2[k] - rw[P].b0[k];
+    }
+    load(j + 2, rw[P]);
+    double m1[NF], m2[NF];
+#pragma unroll
+    for (int k = 0; k < NF; ++k) {
+      m1[k] = mu[k] + (d1[k] - h1[P ^ 1][k]) * inv1;
+      m2[k] = mu[k] + (d2[k] - h2[P][k]) * inv2;
+    }
+    r1.add_if(window_value<NF>(m1), j - 1 < nwin);
+    r2.add_if(window_value<NF>(m2), j >= 2 && j <= last);
+#pragma unroll
+    for (int k = 0; k < NF; ++k) {
+      h1[P][k] = d1[k];
+      h2[P][k] = d2[k];
+    }
+  };
+#pragma unroll
+  for (int jj = 0; jj < (kStrideSteps + 2) / 2; ++jj) {
+    row_step(std::integral_constant<int, 1>{}, 2 * jj + 1);
+    row_step(std::integral_constant<int, 0>{}, 2 * jj + 2);
+  }
+}
+
 // Sides L and 2 L per launch, the work split of k_windows_strided for side L;
 // the partials of side 2 L follow those of side L.
-__global__ void __launch_bounds__(256) k_windows_pair(SatView v, int L, int strips, int S, int nblocks,
-                                                      int per_xcd, double* partials) {
+struct PairWork {
+  int grp, strip, y0, x0, nwin;
+  bool live;
+};
+__device__ __forceinline__ PairWork pair_work(const SatView& v, int L, int strips, int S, int nblocks,
+                                              int per_xcd) {
   const int b = blockIdx.x;
   const int logical = (b & 7) * per_xcd + (b >> 3);
-  if (logical >= 3 * nblocks) return;  // uniform over the workgroup
-  const int grp = logical / nblocks;
-  const int wb = logical - grp * nblocks;
-  const int strip = wb % strips;
+  PairWork w{};
+  w.live = logical < 3 * nblocks;
+  if (!w.live) return w;
+  w.grp = logical / nblocks;
+  const int wb = logical - w.grp * nblocks;
+  w.strip = wb % strips;
   const int rest = wb / strips;
   const int j = rest % L, g = rest / L;
-  const int x0 = strip * 256 + threadIdx.x;
-  const int y0 = j + L * (g * S);
+  w.x0 = w.strip * 256 + threadIdx.x;
+  w.y0 = j + L * (g * S);
+  w.nwin = min(S, (v.ny - w.y0 + L - 1) / L);
+  return w;
+}
+
+// Whether a pair-walk workgroup's windows stay inside the table (no lane's
+// windows wrap in x, its sequence does not wrap in y): uniform over the workgroup.
+__device__ __forceinline__ bool pair_inner(const SatView& v, int L, const PairWork& w) {
+  return w.strip * 256 + 255 + 2 * L <= v.nx && w.y0 + (w.nwin + 1) * L <= v.ny && w.y0 < v.ny;
+}
+
+__global__ void __launch_bounds__(256) k_windows_pair(SatView v, int L, int strips, int S, int nblocks,
+                                                      int per_xcd, double* partials) {
+  const PairWork w = pair_work(v, L, strips, S, nblocks, per_xcd);
+  if (!w.live) return;  // uniform over the workgroup
+  const int logical = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
   SumStat r1[3], r2[3];
   for (int q = 0; q < 3; ++q) {
     r1[q].init();
     r2[q].init();
   }
-  if (x0 < v.nx && y0 < v.ny) {
-    if (grp == 0)
-      stride_windows2<LBM_T_LHS_E, 6>(v, L, x0, y0, S, r1[0], r2[0]);
-    else if (grp == 1)
-      stride_windows2<LBM_T_LHS_Z, 6>(v, L, x0, y0, S, r1[1], r2[1]);
+  if (pair_inner(v, L, w)) {
+    if (w.grp == 0)
+      stride_windows2_inner<LBM_T_LHS_E, 6>(v, L, w.x0, w.y0, w.nwin, r1[0], r2[0]);
+    else if (w.grp == 1)
+      stride_windows2_inner<LBM_T_LHS_Z, 6>(v, L, w.x0, w.y0, w.nwin, r1[1], r2[1]);
     else
-      stride_windows2<LBM_T_USQ, 1>(v, L, x0, y0, S, r1[2], r2[2]);
+      stride_windows2_inner<LBM_T_USQ, 1>(v, L, w.x0, w.y0, w.nwin, r1[2], r2[2]);
+  } else if (w.x0 < v.nx && w.y0 < v.ny) {
+    if (w.grp == 0)
+      stride_windows2<LBM_T_LHS_E, 6>(v, L, w.x0, w.y0, S, r1[0], r2[0]);
+    else if (w.grp == 1)
+      stride_windows2<LBM_T_LHS_Z, 6>(v, L, w.x0, w.y0, S, r1[1], r2[1]);
+    else
+      stride_windows2<LBM_T_USQ, 1>(v, L, w.x0, w.y0, S, r1[2], r2[2]);
   }
   sum_stats_block(r1, partials + static_cast<size_t>(logical) * kSumVals);
   sum_stats_block(r2, partials + (static_cast<size_t>(3) * nblocks + logical) * kSumVals);
 }
 
-__global__ void __launch_bounds__(256) k_sum_stats_final(const double* __restrict__ partials,
-                                                         int nblocks, double* out) {
+// The window walks' partials are merged in two stages.  First stage: set
+// blockIdx.y of partial blocks (nblocks blocks of kSumVals values each, sets
+// one after the other) is cut into kStatMid contiguous chunks; workgroup g
+// reads chunk g with 252 threads as 14 rows x 18 values, so that consecutive
+// threads read consecutive doubles, and combines its rows in a fixed order
+// into mid[set][g].
+constexpr int kStatMid = 64;
+constexpr int kStatRows = 256 / kSumVals;
+__global__ void __launch_bounds__(256) k_sum_stats_mid(const double* __restrict__ partials, int nblocks,
+                                                       double* __restrict__ mid) {
+  __shared__ double sh[kStatRows][kSumVals];
+  const int t = threadIdx.x;
+  const int row = t / kSumVals, j = t - row * kSumVals;
+  const int kind = j % 6;
+  const double* p = partials + static_cast<size_t>(blockIdx.y) * nblocks * kSumVals;
+  const int per = (nblocks + kStatMid - 1) / kStatMid;
+  const int b0 = blockIdx.x * per;
+  const int b1 = min(nblocks, b0 + per);
+  double acc = kind == 3 ? 1e300 : (kind == 4 ? -1e300 : 0.0);
+  if (row < kStatRows) {
+    for (int b = b0 + row; b < b1; b += kStatRows) {
+      const double v = p[static_cast<size_t>(b) * kSumVals + j];
+      acc = kind == 3 ? fmin(acc, v) : (kind == 4 ? fmax(acc, v) : acc + v);
+    }
+    sh[row][j] = acc;
+  }
+  __syncthreads();
+  if (t < kSumVals) {
+    double r = sh[0][t];
+    for (int q = 1; q < kStatRows; ++q) {
+      const double v = sh[q][t];
+      r = kind == 3 ? fmin(r, v) : (kind == 4 ? fmax(r, v) : r + v);
+    }
+    mid[(static_cast<size_t>(blockIdx.y) * kStatMid + blockIdx.x) * kSumVals + t] = r;
+  }
+}
+
+// Second stage: workgroup q combines mid[q] and writes the three statistics in
+// the (n, mean, M2, min, max, nan) layout of the Welford path to out_q.
+__global__ void __launch_bounds__(256) k_sum_stats_final(const double* __restrict__ mid, double* out0,
+                                                         double* out1) {
   SumStat r[3];
   for (int q = 0; q < 3; ++q) r[q].init();
-  for (int b = threadIdx.x; b < nblocks; b += 256)
+  const double* part = mid + static_cast<size_t>(blockIdx.x) * kStatMid * kSumVals;
+  for (int b = threadIdx.x; b < kStatMid; b += 256)
     for (int q = 0; q < 3; ++q) {
-      const double* p = partials + static_cast<size_t>(b) * kSumVals + q * 6;
+      const double* p = part + static_cast<size_t>(b) * kSumVals + q * 6;
       r[q].n += p[0];
       r[q].s1 += p[1];
       r[q].s2 += p[2];
@@ -1333,8 +1576,8 @@ __global__ void __launch_bounds__(256) k_sum_stats_final(const double* __restric
     }
   __shared__ double fin[kSumVals];
   sum_stats_block(r, fin);
+  double* out = blockIdx.x == 0 ? out0 : out1;
   if (threadIdx.x < 3) {
-    // convert to the (n, mean, M2, min, max, nan) layout of the Welford path
     const int q = threadIdx.x;
     const double n = fin[q * 6 + 0];
     const double mean = n > 0.0 ? fin[q * 6 + 1] / n : 0.0;
@@ -1405,7 +1648,10 @@ BalanceWs carve_balance(Carver& c, int nx, int ny) {
     const size_t need = sides * 3 * static_cast<size_t>(stride_grid(nx, ny, L).blocks) * kSumVals;
     if (np < need) np = need;
   }
-  w.partials = c.take<double>(np + static_cast<size_t>(NT) * kMeanBlocks);
+  // after them, the field-sum partials: the paired term passes' workgroup sums
+  // or the fallback reduction's block sums
+  const size_t pass_blocks = static_cast<size_t>((nx / 2 + 63) / 64) * ((ny + 3) / 4);
+  w.partials = c.take<double>(np + static_cast<size_t>(NT) * std::max<size_t>(kMeanBlocks, pass_blocks));
   w.partials_cap = np;
   w.stats = c.take<double>(static_cast<size_t>(kMaxSizes) * kStatVals);
   w.sstats = c.take<double>(static_cast<size_t>(kMaxSizes) * kStatVals);
@@ -1440,6 +1686,7 @@ int balance_terms(const lbm_balance_input& in, const BalanceWs& ws) {
   bool paired = nx % 2 == 0 && al16(a.terms) && al16(a.aux) && al16(a.fx) && al16(a.fy) &&
                 al16(a.nu_field);
   for (int k = 0; k < 3; ++k) paired = paired && al16(a.rho[k]) && al16(a.ux[k]) && al16(a.uy[k]);
+  a.psum = ws.partials + ws.partials_cap;
   dim3 blk(64, 4);
   if (paired) {
     dim3 grd((nx / 2 + 63) / 64, (ny + 3) / 4);
@@ -1448,6 +1695,10 @@ int balance_terms(const lbm_balance_input& in, const BalanceWs& ws) {
     hipLaunchKernelGGL(k_bal_b2, grd, blk, 0, s, a);
     LBM_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_bal_c2, grd, blk, 0, s, a);
+    LBM_HIP(hipGetLastError());
+    // the field means from the passes' workgroup sums
+    hipLaunchKernelGGL(k_field_means, dim3(NT), dim3(kRedThreads), 0, s, a.psum,
+                       static_cast<int>(grd.x * grd.y), 1.0 / (double(nx) * ny), ws.means);
     LBM_HIP(hipGetLastError());
     return LBM_OK;
   }
@@ -1458,7 +1709,7 @@ int balance_terms(const lbm_balance_input& in, const BalanceWs& ws) {
   LBM_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_bal_c, grd, blk, 0, s, a);
   LBM_HIP(hipGetLastError());
-  return LBM_OK;
+  return field_means(ws.terms, NT, nx, ny, a.psum, ws.means, s);
 }
 
 int field_means(const double* g, int nf, int nx, int ny, double* partials, double* means,
@@ -1581,6 +1832,18 @@ int validate_balance_extra(int nsizes, const lbm_balance_stats* out, const lbm_b
 
 namespace {
 
+// Merge of nsets sets of nblocks window-walk partials (ws.partials, one set
+// after the other) into out0 (and out1), through the first-stage sums kept
+// after the window partials.
+int merge_sum_stats(const BalanceWs& ws, int nblocks, int nsets, double* out0, double* out1, hipStream_t s) {
+  double* mid = ws.partials + ws.partials_cap;
+  hipLaunchKernelGGL(k_sum_stats_mid, dim3(kStatMid, nsets), dim3(256), 0, s, ws.partials, nblocks, mid);
+  LBM_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_sum_stats_final, dim3(nsets), dim3(256), 0, s, mid, out0, out1);
+  LBM_HIP(hipGetLastError());
+  return LBM_OK;
+}
+
 // Statistics over every corner for each box side: window kernels, the merge of
 // their partials into ws.stats, then the pool (started anew unless acc).
 int corner_stats(const SatView& v, const BalanceWs& ws, const int32_t* sizes, int nsizes, double* dmaps,
@@ -1616,13 +1879,9 @@ int corner_stats(const SatView& v, const BalanceWs& ws, const int32_t* sizes, in
       hipLaunchKernelGGL(k_windows_pair, dim3(per_xcd * 8), dim3(256), 0, s, v, L, g.strips, g.S, nb,
                          per_xcd, ws.partials);
       LBM_HIP(hipGetLastError());
-      hipLaunchKernelGGL(k_sum_stats_final, dim3(1), dim3(256), 0, s, ws.partials, 3 * nb,
-                         ws.stats + static_cast<size_t>(k) * kStatVals);
-      LBM_HIP(hipGetLastError());
-      hipLaunchKernelGGL(k_sum_stats_final, dim3(1), dim3(256), 0, s,
-                         ws.partials + static_cast<size_t>(3) * nb * kSumVals, 3 * nb,
-                         ws.stats + static_cast<size_t>(twin[k]) * kStatVals);
-      LBM_HIP(hipGetLastError());
+      if (int rc = merge_sum_stats(ws, 3 * nb, 2, ws.stats + static_cast<size_t>(k) * kStatVals,
+                                   ws.stats + static_cast<size_t>(twin[k]) * kStatVals, s))
+        return rc;
       continue;
     }
     double* maps = dmaps ? dmaps + static_cast<size_t>(k) * 3 * plane : nullptr;
@@ -1647,9 +1906,8 @@ int corner_stats(const SatView& v, const BalanceWs& ws, const int32_t* sizes, in
       hipLaunchKernelGGL(k_windows_strided<false>, dim3(per_xcd * 8), dim3(256), 0, s, v, L, g.strips, g.S,
                          nb, per_xcd, maps, ws.partials, ws.edges, ne, hk);
     LBM_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_sum_stats_final, dim3(1), dim3(256), 0, s, ws.partials, 3 * nb,
-                       ws.stats + static_cast<size_t>(k) * kStatVals);
-    LBM_HIP(hipGetLastError());
+    if (int rc = merge_sum_stats(ws, 3 * nb, 1, ws.stats + static_cast<size_t>(k) * kStatVals, nullptr, s))
+      return rc;
   }
   if (nsizes > 0) {
     hipLaunchKernelGGL(k_stats_pool, dim3((3 * nsizes + 63) / 64), dim3(64), 0, s, ws.stats, ws.pool,
@@ -1706,7 +1964,6 @@ int run_balance_async(const lbm_balance_input& in, const BalanceWs& ws, const in
                       double* host_stats) {
   hipStream_t s = static_cast<hipStream_t>(in.stream);
   if (int rc = balance_terms(in, ws)) return rc;
-  if (int rc = field_means(ws.terms, NT, in.nx, in.ny, ws.partials + ws.partials_cap, ws.means, s)) return rc;
   if (int rc = sat_build(ws.terms, NT, ws.means, ws.sat, in.nx, in.ny, s)) return rc;
   SatView v{ws.sat, ws.means, in.nx, in.ny, NT};
   if (int rc = corner_stats(v, ws, sizes, nsizes, nullptr, false, 0, ws.hist, 0, 0, s)) return rc;
@@ -1731,8 +1988,6 @@ int run_balance(const lbm_balance_input& in, const BalanceWs& ws, const int32_t*
   if (term_fields)
     LBM_HIP(hipMemcpyAsync(term_fields, ws.terms, NT * plane * sizeof(double),
                            hipMemcpyDeviceToDevice, s));
-  if (int rc = field_means(ws.terms, NT, nx, ny, ws.partials + ws.partials_cap, ws.means, s))
-    return rc;
   if (int rc = sat_build(ws.terms, NT, ws.means, ws.sat, nx, ny, s)) return rc;
 
   const bool hist = extra && extra->edges;

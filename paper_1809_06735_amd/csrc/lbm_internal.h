@@ -205,7 +205,8 @@ BalanceWs carve_balance(Carver& c, int nx, int ny);
 int balance_grid_ok(int nx, int ny);
 // Pieces of the balance reused by the adjoint: the 13 term fields and the aux
 // fields (E, Omega, omega, sigma_xx, sigma_yy, sigma_xy, H_x, H_y) of passes
-// A-C; domain means of nf consecutive fields; their mean-centred prefix tables
+// A-C, with the 13 fields' domain means in ws.means; domain means of nf
+// consecutive fields; their mean-centred prefix tables
 // (row-interleaved: table row y of field f starts at (y nf + f)(nx + 1), so the
 // rows of all fields at one y are adjacent); and scaled box sums of field f of
 // such a table for every corner shifted by `off`.
