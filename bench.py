@@ -500,12 +500,23 @@ def _ensemble_extra(log, steps=500):
     return ens_mod.bench_ensemble(steps=steps, log=log)
 
 
+def _ensemble_fixed_extra(log, steps=204):
+    """The 64-run ensemble in every mode at fixed shapes (the autotuner's picks on MI355X:
+    1024 threads x 1 site x 2 groups for the one-step modes; K = 6, 128-lane strips with the
+    packed halo, 32-row bands for the multi-step modes), without the autotuner's trial
+    launches: the run that kernel profiles are taken from."""
+    from paper_1809_06735_amd import ensemble as ens_mod
+    return ens_mod.bench_ensemble(steps=steps, log=log, tile=(1024, 1, 2), multi=(6, 128, 32, 1, 1),
+                                  one_by_one=False)
+
+
 def _adjoint_extra(log):
     from paper_1809_06735_amd import adjoint as adj_mod
     return adj_mod.bench_adjoint(log=log)
 
 
 EXTRAS["ensemble"] = _ensemble_extra
+EXTRAS["ensemble_fixed"] = _ensemble_fixed_extra
 EXTRAS["adjoint"] = _adjoint_extra
 
 

@@ -445,8 +445,13 @@ LBM_API int lbm_balance_fields_noalloc(const lbm_balance_input* in, const int32_
  * advances every run by K steps per launch over the (run, strip, band) tiles
  * of the single-grid multi-step kernel (see lbm_tile.fuse), bit-identical to
  * single steps; step counts that are not a multiple of K end with single-step
+ * launches.  Mode LBM_BATCH_PERSISTENT_MULTI runs those K-step tiles inside
+ * one persistent launch per chunk: a round of K steps over every tile, then
+ * a grid-wide barrier (bounded waits as above), bit-identical to the
+ * multi-step mode; the steps of a chunk beyond a multiple of K are single-step
  * launches.  All modes are replayed from hipGraphs. */
-enum { LBM_BATCH_PERSISTENT = 0, LBM_BATCH_PER_STEP = 1, LBM_BATCH_MULTI_STEP = 2 };
+enum { LBM_BATCH_PERSISTENT = 0, LBM_BATCH_PER_STEP = 1, LBM_BATCH_MULTI_STEP = 2,
+       LBM_BATCH_PERSISTENT_MULTI = 3 };
 typedef struct lbm_batch_s* lbm_batch;
 
 /* cfgs[nruns]: per-run configuration; with_balance must be 0, force_scheme
@@ -460,8 +465,9 @@ LBM_API int lbm_batch_init(const lbm_config* cfgs, int32_t nruns, void* ws, size
                    const double* const* rho0, const double* const* ux0,
                    const double* const* uy0, const double* const* fx,
                    const double* const* fy, lbm_batch* out);
-/* mode: LBM_BATCH_PERSISTENT, LBM_BATCH_PER_STEP or LBM_BATCH_MULTI_STEP;
- * chunk: even number of steps per graph replay (2..100000). */
+/* mode: LBM_BATCH_PERSISTENT, LBM_BATCH_PER_STEP, LBM_BATCH_MULTI_STEP or
+ * LBM_BATCH_PERSISTENT_MULTI; chunk: even number of steps per graph replay
+ * (2..100000). */
 LBM_API int lbm_batch_set_mode(lbm_batch b, int32_t mode, int32_t chunk);
 /* Work-item shape: block_threads (256, 512 or 1024) threads per workgroup;
  * vx (1, 2 or 4, dividing every run's nx) sites per thread; band_rows (1..64)
@@ -474,9 +480,9 @@ LBM_API int lbm_batch_set_tile(lbm_batch b, int32_t block_threads, int32_t vx, i
  * by = vx = 1.  The next-row loads are always issued early (pf = 1). */
 LBM_API int lbm_batch_set_multi(lbm_batch b, const lbm_tile* t);
 LBM_API int lbm_batch_get_multi(lbm_batch b, lbm_tile* t);
-/* Time every (mode, block_threads, vx, band_rows) candidate and every
- * multi-step shape over about trial_steps (even) steps and keep the fastest
- * per step; the chosen mode is readable with lbm_batch_get_mode, the
+/* Time every (mode, block_threads, vx, band_rows) candidate, every
+ * multi-step shape and the fastest of those in the persistent multi-step mode
+ * over about trial_steps (even) steps and keep the fastest per step; the chosen mode is readable with lbm_batch_get_mode, the
  * multi-step shape with lbm_batch_get_multi.  The trials are real steps: the
  * ensemble advances by them and lbm_batch_time says so. */
 LBM_API int lbm_batch_autotune(lbm_batch b, int32_t trial_steps, int32_t* block_threads,

@@ -34,6 +34,7 @@ COLLISIONS = {"bgk": LBM_COLLISION_BGK, "entropic": LBM_COLLISION_ENTROPIC}
 LBM_BATCH_PERSISTENT = 0
 LBM_BATCH_PER_STEP = 1
 LBM_BATCH_MULTI_STEP = 2
+LBM_BATCH_PERSISTENT_MULTI = 3
 NTERMS = 13
 NWVALS = 16   # per explicit window: 13 box means, delta^E, delta^Omega, Ma
 TERM_NAMES = ("lhs_E", "e1", "e2", "e3", "e4", "e5",

@@ -9,7 +9,9 @@
 // of hanging).  Per-step mode: one ordinary launch per step over the same list.
 // Multi-step mode: one launch advances every run by K steps, its workgroups
 // taking the (run, strip, band) tiles of the single-grid multi-step kernel
-// (temporal blocking through LDS).  All modes are captured into hipGraphs and
+// (temporal blocking through LDS).  Persistent multi-step mode: one persistent
+// kernel whose workgroups take those tiles, K steps per round, with a grid
+// barrier between rounds.  All modes are captured into hipGraphs and
 // replayed.  The arithmetic per site is the single-grid step's (pull, BGK
 // collide, Guo force, drag).
 #include <hip/hip_runtime.h>
@@ -41,6 +43,14 @@ struct RunDesc {
   int pad;
 };
 
+// the grid barrier's counters, error flag, bounded wait and variant
+struct BarrierArgs {
+  unsigned* barrier;      // zeroed before each persistent launch
+  int* error;             // set to 1 by a barrier wait that ran out
+  unsigned spin_limit;
+  int flavor;             // grid-barrier variant (see grid_barrier)
+};
+
 struct BatchArgs {
   const RunDesc* runs;
   const int* item_run;
@@ -50,10 +60,7 @@ struct BatchArgs {
   int bt;                 // threads per workgroup (256, 512 or 1024)
   int parity0;            // buffer index holding the state at the first step
   int nsteps;
-  unsigned* barrier;      // zeroed before each persistent launch
-  int* error;             // set to 1 by a barrier wait that ran out
-  unsigned spin_limit;
-  int flavor;             // grid-barrier variant (see grid_barrier)
+  BarrierArgs bar;
 };
 
 template <typename T, int VX>
@@ -127,22 +134,29 @@ __device__ __forceinline__ void process_item(const BatchArgs& a, int item, int p
 //      arrived, releases its group through a per-group flag
 // A wait that runs out of spins sets the error flag; every later barrier then
 // fails at once, so every workgroup leaves the kernel.
+// Words 0 .. 17 (x kCounterStride) hold the barrier's counters and flags,
+// words 18 .. 25 the persistent multi-step kernel's tile tickets.
 constexpr int kCounterStride = 64;  // unsigned words between counters (256 bytes)
-constexpr int kBarrierWords = kCounterStride * 18;
+constexpr int kTicketSlot = 18;
+constexpr int kBarrierWords = kCounterStride * (kTicketSlot + 8);
 
-__device__ __forceinline__ bool spin_until(const BatchArgs& a, unsigned* p, unsigned target) {
+// Polls with relaxed loads (an acquire load would invalidate the caches on
+// every poll, under the feet of the workgroups still computing) and acquires
+// once, by a fence, when the target is reached.
+__device__ __forceinline__ bool spin_until(const BarrierArgs& a, unsigned* p, unsigned target) {
   unsigned spins = 0;
-  while (__hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+  while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
     if (++spins > a.spin_limit) {
       __hip_atomic_store(a.error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return false;
     }
     __builtin_amdgcn_s_sleep(2);
   }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   return true;
 }
 
-__device__ bool grid_barrier(const BatchArgs& a, unsigned gen) {
+__device__ bool grid_barrier(const BarrierArgs& a, unsigned gen) {
   __shared__ int ok;
   if (a.flavor == 0) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
@@ -160,9 +174,13 @@ __device__ bool grid_barrier(const BatchArgs& a, unsigned gen) {
       const unsigned ngroups = G < 8 ? G : 8;
       unsigned* cg = a.barrier + kCounterStride * (1 + g);
       unsigned* rel = a.barrier + kCounterStride * (9 + g);
-      const unsigned prev = __hip_atomic_fetch_add(cg, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      // arrivals only release (an acquire would invalidate the caches of the
+      // workgroups still computing); the last arrival of the group acquires the
+      // others' writes before it forwards them
+      const unsigned prev = __hip_atomic_fetch_add(cg, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       if (prev + 1 == gen * gsize) {
-        __hip_atomic_fetch_add(a.barrier, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        __hip_atomic_fetch_add(a.barrier, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         good = spin_until(a, a.barrier, gen * ngroups);
         if (good) __hip_atomic_store(rel, gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       } else {
@@ -176,13 +194,31 @@ __device__ bool grid_barrier(const BatchArgs& a, unsigned gen) {
   return ok != 0;
 }
 
+// Persistent one-step mode: the work list is split into eight contiguous parts
+// drawn from tickets, as the tiles of the persistent multi-step kernel below.
 template <typename T, int VX>
 __global__ void __launch_bounds__(kBTMax) k_batch_persistent(BatchArgs a) {
+  __shared__ unsigned tk;
+  const unsigned per_part = gridDim.x >> 3;
+  const int part = blockIdx.x & 7;
+  const int per = (a.nitems + 7) / 8;
+  const int first = part * per;
+  const unsigned count = static_cast<unsigned>(max(0, min(a.nitems, first + per) - first));
+  unsigned* ticket = a.bar.barrier + kCounterStride * (kTicketSlot + part);
   for (int s = 0; s < a.nsteps; ++s) {
     const int par = (a.parity0 + s) & 1;
-    for (int it = blockIdx.x; it < a.nitems; it += gridDim.x) process_item<T, VX>(a, it, par);
+    const unsigned base = static_cast<unsigned>(s) * (count + per_part);  // modulo 2^32
+    for (;;) {
+      if (threadIdx.x == 0)
+        tk = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - base;
+      __syncthreads();
+      const unsigned k = tk;
+      __syncthreads();  // every thread has read tk before thread 0 draws again
+      if (k >= count) break;  // uniform over the workgroup
+      process_item<T, VX>(a, first + static_cast<int>(k), par);
+    }
     if (s + 1 < a.nsteps)
-      if (!grid_barrier(a, static_cast<unsigned>(s + 1))) return;
+      if (!grid_barrier(a.bar, static_cast<unsigned>(s + 1))) return;
   }
 }
 
@@ -229,6 +265,81 @@ __global__ void __launch_bounds__(fused_detail::kFusedMaxThreads) k_batch_fused(
     fused_detail::fused_tile<T, K, true, NT, true>(p, lds, a.W, a.H, strips, a.item_tile[it], a.halo != 0);
   else
     fused_detail::fused_tile<T, K, false, NT, true>(p, lds, a.W, a.H, strips, a.item_tile[it], a.halo != 0);
+}
+
+// Persistent multi-step mode: `rounds` rounds of K steps, round r from buffer
+// parity + r.  The tile list is split into eight contiguous parts, part x
+// taken by the workgroups b with b % 8 == x (gridDim.x is a multiple of 8), so
+// that a run's neighbouring tiles, whose halos overlap, tend to share an L2.
+// Within a part the workgroups draw tiles from a ticket counter, so a
+// workgroup that finishes early takes more.  Each workgroup draws until a
+// ticket is past the part's end, so a round adds exactly (tiles + workgroups)
+// of the part to its counter and round r's tickets start at r times that.
+// Tiles are independent within a round, so which workgroup takes a tile does
+// not change any result.  Correctness does not depend on where a workgroup
+// runs: the grid barrier between rounds publishes every write to every
+// workgroup.
+template <typename T, int K, bool NT>
+__global__ void __launch_bounds__(fused_detail::kFusedMaxThreads) k_batch_fused_persistent(FusedArgs a,
+                                                                                          int rounds,
+                                                                                          BarrierArgs bar) {
+  extern __shared__ unsigned char smem_raw[];
+  T* const lds = reinterpret_cast<T*>(smem_raw);
+  __shared__ unsigned tk;
+  const unsigned per_part = gridDim.x >> 3;
+  const int part = blockIdx.x & 7;
+  const int first = part * a.per_xcd;
+  const unsigned count = static_cast<unsigned>(max(0, min(a.nitems, first + a.per_xcd) - first));
+  unsigned* ticket = bar.barrier + kCounterStride * (kTicketSlot + part);
+  for (int r = 0; r < rounds; ++r) {
+    const int par = (a.parity + r) & 1;
+    const unsigned base = static_cast<unsigned>(r) * (count + per_part);  // modulo 2^32
+    for (;;) {
+      if (threadIdx.x == 0)
+        tk = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - base;
+      __syncthreads();
+      const unsigned k = tk;  // rewritten only after the tile's barriers
+      if (k >= count) break;  // uniform over the workgroup
+      const int it = first + static_cast<int>(k);
+      const RunDesc rd = a.runs[a.item_run[it]];
+      StepParams p{};
+      p.src = rd.pop[par];
+      p.dst = rd.pop[par ^ 1];
+      p.fx = rd.fx;
+      p.fy = rd.fy;
+      p.nx = rd.nx;
+      p.ny = rd.ny;
+      p.ps = rd.ps;
+      p.rs = rd.rs;
+      p.omega = rd.omega;
+      p.alpha = rd.alpha;
+      const int strips = (rd.nx + a.W - 1) / a.W;
+      if (rd.forced)
+        fused_detail::fused_tile<T, K, true, NT, true>(p, lds, a.W, a.H, strips, a.item_tile[it], a.halo != 0);
+      else
+        fused_detail::fused_tile<T, K, false, NT, true>(p, lds, a.W, a.H, strips, a.item_tile[it], a.halo != 0);
+      __syncthreads();  // the next tile rewrites the LDS rows
+    }
+    if (r + 1 < rounds)
+      if (!grid_barrier(bar, static_cast<unsigned>(r + 1))) return;
+  }
+}
+
+template <typename T, int K>
+const void* fused_persistent_fn(bool nt) {
+  return nt ? reinterpret_cast<const void*>(&k_batch_fused_persistent<T, K, true>)
+            : reinterpret_cast<const void*>(&k_batch_fused_persistent<T, K, false>);
+}
+
+template <typename T>
+const void* fused_persistent_fn(int K, bool nt) {
+  switch (K) {
+    case 2: return fused_persistent_fn<T, 2>(nt);
+    case 3: return fused_persistent_fn<T, 3>(nt);
+    case 4: return fused_persistent_fn<T, 4>(nt);
+    case 5: return fused_persistent_fn<T, 5>(nt);
+    default: return fused_persistent_fn<T, 6>(nt);
+  }
 }
 
 template <typename T, int K>
@@ -313,6 +424,7 @@ struct lbm_batch_s {
   int* d_fitem_tile = nullptr;
   size_t fitem_cap = 0;
   int nfitems = 0;
+  int fgrid = 0;                 // persistent multi-step grid (a multiple of 8)
   lbm_tile ftile{256, 1, 1, 64, 1, 4, 1};  // multi-step shape: strip, band, K, nt
   unsigned* d_barrier = nullptr;
   int* d_error = nullptr;
@@ -421,6 +533,22 @@ int validate_batch(const lbm_config* cfgs, int32_t nruns) {
   return LBM_OK;
 }
 
+// work list and shape of the multi-step tiles, from buffer parity `par`
+FusedArgs fused_args(const lbm_batch_s* b, int par) {
+  FusedArgs f{};
+  f.runs = b->d_runs;
+  f.item_run = b->d_fitem_run;
+  f.item_tile = b->d_fitem_tile;
+  f.nitems = b->nfitems;
+  f.per_xcd = (b->nfitems + 7) / 8;
+  f.W = fused_strip_width(b->ftile);
+  f.H = b->ftile.ry;
+  f.halo = b->ftile.halo;
+  f.threads = f.halo ? b->ftile.bx : f.W + 64;
+  f.parity = par;
+  return f;
+}
+
 int build_items(lbm_batch_s* b) {
   std::vector<int> ir_run, ir_start;
   const size_t per = static_cast<size_t>(b->bt) * b->vx * b->ir;
@@ -459,7 +587,21 @@ int build_items(lbm_batch_s* b) {
   if (int rc = b->dtype == LBM_F32 ? occupancy_for<float>(b->vx, b->bt, &occ)
                                    : occupancy_for<double>(b->vx, b->bt, &occ))
     return rc;
-  b->grid = std::min(occ, b->nitems);
+  // every workgroup resident, eight equal groups
+  b->grid = std::min(occ / 8 * 8, 8 * ((b->nitems + 7) / 8));
+  // persistent multi-step: every workgroup resident, eight equal groups
+  {
+    const FusedArgs f = fused_args(b, 0);
+    const void* fn = b->dtype == LBM_F32 ? fused_persistent_fn<float>(b->ftile.fuse, b->ftile.nt != 0)
+                                         : fused_persistent_fn<double>(b->ftile.fuse, b->ftile.nt != 0);
+    const size_t lds = fused_lds_bytes(f.W, b->ftile.fuse, b->dtype);
+    int per_cu = 0, dev = 0, cus = 0;
+    LBM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, f.threads, lds));
+    LBM_HIP(hipGetDevice(&dev));
+    LBM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int resident = (per_cu * cus) / 8 * 8;
+    b->fgrid = std::min(resident, 8 * f.per_xcd);
+  }
   return LBM_OK;
 }
 
@@ -469,6 +611,15 @@ void drop_batch_graphs(lbm_batch_s* b) {
       (void)hipGraphExecDestroy(g);
       g = nullptr;
     }
+}
+
+BarrierArgs barrier_args(const lbm_batch_s* b) {
+  BarrierArgs g{};
+  g.barrier = b->d_barrier;
+  g.error = b->d_error;
+  g.spin_limit = b->spin_limit;
+  g.flavor = b->flavor;
+  return g;
 }
 
 BatchArgs make_args(lbm_batch_s* b, int parity0, int nsteps) {
@@ -481,17 +632,28 @@ BatchArgs make_args(lbm_batch_s* b, int parity0, int nsteps) {
   a.bt = b->bt;
   a.parity0 = parity0;
   a.nsteps = nsteps;
-  a.barrier = b->d_barrier;
-  a.error = b->d_error;
-  a.spin_limit = b->spin_limit;
-  a.flavor = b->flavor;
+  a.bar = barrier_args(b);
   return a;
 }
 
-// Launches (buffer swaps) that n steps take in the current mode.
+// Buffer swaps that n steps take in the current mode.
 int step_launches(const lbm_batch_s* b, int n) {
-  if (b->mode != LBM_BATCH_MULTI_STEP) return n;
+  if (b->mode != LBM_BATCH_MULTI_STEP && b->mode != LBM_BATCH_PERSISTENT_MULTI) return n;
   return n / b->ftile.fuse + n % b->ftile.fuse;
+}
+
+// n % K remaining steps, one per-step launch each, from parity p; returns the
+// parity after them
+int enqueue_single_steps(lbm_batch_s* b, int p, int n, hipStream_t s, int* p_out) {
+  for (int k = 0; k < n; ++k) {
+    BatchArgs a = make_args(b, p, 1);
+    if (b->dtype == LBM_F32) launch_batch_vx<float>(b->vx, false, a, 0, s);
+    else launch_batch_vx<double>(b->vx, false, a, 0, s);
+    LBM_HIP(hipGetLastError());
+    p ^= 1;
+  }
+  *p_out = p;
+  return LBM_OK;
 }
 
 // Enqueue `n` steps starting from buffer parity `par` on stream s.
@@ -499,16 +661,7 @@ int enqueue_steps(lbm_batch_s* b, int par, int n, hipStream_t s) {
   if (n <= 0) return LBM_OK;
   if (b->mode == LBM_BATCH_MULTI_STEP) {
     const int K = b->ftile.fuse;
-    FusedArgs f{};
-    f.runs = b->d_runs;
-    f.item_run = b->d_fitem_run;
-    f.item_tile = b->d_fitem_tile;
-    f.nitems = b->nfitems;
-    f.per_xcd = (b->nfitems + 7) / 8;
-    f.W = fused_strip_width(b->ftile);
-    f.H = b->ftile.ry;
-    f.halo = b->ftile.halo;
-    f.threads = f.halo ? b->ftile.bx : f.W + 64;
+    FusedArgs f = fused_args(b, par);
     int p = par;
     for (int k = 0; k + K <= n; k += K) {
       f.parity = p;
@@ -517,16 +670,31 @@ int enqueue_steps(lbm_batch_s* b, int par, int n, hipStream_t s) {
       LBM_HIP(hipGetLastError());
       p ^= 1;
     }
-    for (int k = 0; k < n % K; ++k) {  // the remainder, one step per launch
-      BatchArgs a = make_args(b, p, 1);
-      if (b->dtype == LBM_F32) launch_batch_vx<float>(b->vx, false, a, 0, s);
-      else launch_batch_vx<double>(b->vx, false, a, 0, s);
+    return enqueue_single_steps(b, p, n % K, s, &p);
+  }
+  if (b->mode == LBM_BATCH_PERSISTENT_MULTI) {
+    const int K = b->ftile.fuse;
+    const int rounds = n / K;
+    int p = par;
+    if (rounds > 0) {
+      if (b->fgrid < 8) return fail(LBM_E_UNSUPPORTED, "the multi-step tiles do not fit a persistent grid");
+      hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, b->d_barrier);
       LBM_HIP(hipGetLastError());
-      p ^= 1;
+      const FusedArgs f = fused_args(b, par);
+      const size_t lds = fused_lds_bytes(f.W, K, b->dtype);
+      const void* fn = b->dtype == LBM_F32 ? fused_persistent_fn<float>(K, b->ftile.nt != 0)
+                                           : fused_persistent_fn<double>(K, b->ftile.nt != 0);
+      FusedArgs fa = f;
+      int rr = rounds;
+      BarrierArgs bar = barrier_args(b);
+      void* args[] = {&fa, &rr, &bar};
+      LBM_HIP(hipLaunchKernel(fn, dim3(b->fgrid), dim3(f.threads), args, lds, s));
+      p ^= rounds & 1;
     }
-    return LBM_OK;
+    return enqueue_single_steps(b, p, n % K, s, &p);
   }
   if (b->mode == LBM_BATCH_PERSISTENT) {
+    if (b->grid < 8) return fail(LBM_E_UNSUPPORTED, "the work items do not fit a persistent grid");
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, b->d_barrier);
     LBM_HIP(hipGetLastError());
     BatchArgs a = make_args(b, par, n);
@@ -665,8 +833,9 @@ int lbm_batch_init(const lbm_config* cfgs, int32_t nruns, void* ws, size_t ws_by
 
 int lbm_batch_set_mode(lbm_batch b, int32_t mode, int32_t chunk) {
   if (!b) return fail(LBM_E_INVALID, "batch is NULL");
-  if (mode != LBM_BATCH_PERSISTENT && mode != LBM_BATCH_PER_STEP && mode != LBM_BATCH_MULTI_STEP)
-    return fail(LBM_E_INVALID, "mode must be LBM_BATCH_PERSISTENT, _PER_STEP or _MULTI_STEP");
+  if (mode != LBM_BATCH_PERSISTENT && mode != LBM_BATCH_PER_STEP && mode != LBM_BATCH_MULTI_STEP &&
+      mode != LBM_BATCH_PERSISTENT_MULTI)
+    return fail(LBM_E_INVALID, "mode must be LBM_BATCH_PERSISTENT, _PER_STEP, _MULTI_STEP or _PERSISTENT_MULTI");
   if (chunk < 2 || chunk % 2 || chunk > 100000) return fail(LBM_E_INVALID, "chunk: even, 2..100000");
   b->mode = mode;
   b->chunk = chunk;
@@ -814,6 +983,13 @@ int lbm_batch_autotune(lbm_batch b, int32_t trial_steps, int32_t* block_threads,
           bir = kbir;
           bbt = kbbt;
         }
+    // the fastest multi-step shape inside one persistent launch
+    if (rc == LBM_OK) {
+      b->mode = LBM_BATCH_PERSISTENT_MULTI;
+      b->ftile = bf;
+      const int K = bf.fuse;
+      rc = trial(K * ((trial_steps + K - 1) / K));
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

@@ -11,7 +11,7 @@ from . import _lib as L
 from .sim import _dev64, _ptr, _require_gpu, _stream_handle
 
 MODES = {"persistent": L.LBM_BATCH_PERSISTENT, "per_step": L.LBM_BATCH_PER_STEP,
-         "multi_step": L.LBM_BATCH_MULTI_STEP}
+         "multi_step": L.LBM_BATCH_MULTI_STEP, "persistent_multi": L.LBM_BATCH_PERSISTENT_MULTI}
 
 
 class Ensemble:
@@ -140,10 +140,12 @@ def _timed(fn):
     return time.perf_counter() - t0
 
 
-def bench_ensemble(nruns=64, steps=500, log=print):
+def bench_ensemble(nruns=64, steps=500, log=print, tile=None, multi=None, one_by_one=True):
     """MLUPS of the 64-run decaying ensemble (sizes 256^2..1024^2, FP32) in the persistent,
-    per-step and multi-step modes, against the plain single-grid step (autotuned, multi-step
-    shapes included) run member by member."""
+    per-step, multi-step and persistent multi-step modes, against the plain single-grid step
+    (autotuned, multi-step shapes included) run member by member.  With tile =
+    (block_threads, vx, groups) and multi = (K, strip, band, nt, halo) given, those shapes
+    are set instead of autotuned."""
     import lbm_inputs as inp
     from .sim import Simulation
 
@@ -151,24 +153,41 @@ def bench_ensemble(nruns=64, steps=500, log=print):
     members = inp.ensemble_members(nruns)
     ens = Ensemble(members, dtype="f32", mode="persistent", chunk=100)
     sites = ens.sites
-    tile = ens.autotune(trial_steps=12)
-    multi = ens.get_multi()
-    out = {"runs": nruns, "sites": sites,
-           "autotuned": {"mode": ens.mode, "block_threads": tile[0], "vx": tile[1], "groups": tile[2],
-                         "multi_step": {"steps_per_launch": multi[0], "strip": multi[1],
-                                        "band": multi[2], "nt": multi[3], "halo": multi[4]}}}
-    for mode in ("persistent", "per_step", "multi_step"):
-        ens.set_mode(mode, 100)
-        ens.step(100)                      # warm-up, builds the graph
-        dt = _timed(lambda: ens.step(steps))
-        out[f"{mode}_MLUPS"] = round(sites * steps / dt / 1e6, 1)
-        shape = multi if mode == "multi_step" else tile
-        log(f"[ensemble] {mode} (shape {shape}): {out[f'{mode}_MLUPS']} MLUPS")
+    if tile is None or multi is None:
+        tile = ens.autotune(trial_steps=12)
+        multi = ens.get_multi()
+        how = "autotuned"
+    else:
+        ens.set_tile(tile[1], tile[2], tile[0])
+        ens.set_multi(*multi)
+        how = "fixed"
+    shapes = {"block_threads": tile[0], "vx": tile[1], "groups": tile[2],
+              "multi_step": {"steps_per_launch": multi[0], "strip": multi[1], "band": multi[2],
+                             "nt": multi[3], "halo": multi[4]}}
+    if how == "autotuned":
+        shapes["mode"] = ens.mode
+    out = {"runs": nruns, "sites": sites, how: shapes}
+    for mode in ("persistent", "per_step", "multi_step", "persistent_multi"):
+        chunk = 100
+        if mode in ("multi_step", "persistent_multi"):
+            # a whole number of K-step rounds per graph replay (chunk is even)
+            k = multi[0]
+            chunk = k * -(-100 // k)
+            chunk += k if chunk % 2 else 0
+        n = chunk * max(1, round(steps / chunk))
+        ens.set_mode(mode, chunk)
+        ens.step(chunk)                    # warm-up, builds the graph
+        dt = _timed(lambda: ens.step(n))
+        out[f"{mode}_MLUPS"] = round(sites * n / dt / 1e6, 1)
+        shape = multi if mode in ("multi_step", "persistent_multi") else tile
+        log(f"[ensemble] {mode} (shape {shape}, {n} steps): {out[f'{mode}_MLUPS']} MLUPS")
     r, _, _, sc = ens.moments(0)
     out["finite"] = bool(sc["nonfinite"] == 0)
     ens.close()
     del ens
     torch.cuda.empty_cache()
+    if not one_by_one:
+        return out
     # plain single-grid step, one member of each size
     per_size = {}
     for m in members:

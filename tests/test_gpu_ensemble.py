@@ -35,7 +35,7 @@ def small_members(seed=0):
     return out
 
 
-@pytest.mark.parametrize("mode", ["persistent", "per_step", "multi_step"])
+@pytest.mark.parametrize("mode", ["persistent", "per_step", "multi_step", "persistent_multi"])
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_ensemble_matches_single_grid_and_oracle(gpu_lib, mode, dtype):
     from paper_1809_06735_amd import Simulation
@@ -43,7 +43,7 @@ def test_ensemble_matches_single_grid_and_oracle(gpu_lib, mode, dtype):
     say(f"ensemble small {mode} {dtype}")
     mem = small_members()
     ens = Ensemble(mem, dtype=dtype, mode=mode, chunk=8)
-    if mode == "multi_step":
+    if mode in ("multi_step", "persistent_multi"):
         ens.set_multi(3, 64, 8)     # several strips and bands per member
     steps = 21                      # two graph replays + an odd remainder
     ens.step(steps)
@@ -102,7 +102,7 @@ def test_ensemble_tiles_and_autotune_keep_results(gpu_lib):
     t = Ensemble(mem, mode="persistent", chunk=6)
     bt, vx, g = t.autotune(trial_steps=4)
     assert bt in (256, 1024) and vx in (1, 2, 4) and 1 <= g <= 64
-    assert t.get_mode()[0] in ("persistent", "per_step", "multi_step")
+    assert t.get_mode()[0] in ("persistent", "per_step", "multi_step", "persistent_multi")
     k, w, h, nt, halo = t.get_multi()
     assert 2 <= k <= 6 and w in (128, 256, 512) and h in (32, 64, 128) and halo in (0, 1)
     assert t.time > 0
@@ -125,18 +125,19 @@ def test_multi_step_mode_equals_per_step_bitwise(gpu_lib, dtype):
     for (k, w, h, nt, chunk, halo) in ((2, 64, 8, 1, 4, 0), (3, 64, 16, 0, 6, 0), (4, 128, 8, 1, 10, 0),
                                        (4, 64, 32, 1, 2, 0), (3, 512, 64, 1, 8, 0), (4, 64, 8, 1, 4, 1),
                                        (5, 128, 16, 0, 10, 1), (6, 256, 32, 1, 6, 1), (6, 64, 8, 1, 2, 1)):
-        e = Ensemble(mem, dtype=dtype, mode="multi_step", chunk=chunk)
-        e.set_multi(k, w, h, nt, halo)
-        assert e.get_multi() == (k, w, h, nt, halo)
-        e.step(7)
-        for r in range(len(mem)):
-            for x, y in zip(e.moments(r, scalars=False), r7[r]):
-                assert torch.equal(x, y), (k, w, h, chunk, r, 7)
-        e.step(30)
-        for r in range(len(mem)):
-            for x, y in zip(e.moments(r, scalars=False), r37[r]):
-                assert torch.equal(x, y), (k, w, h, chunk, r, 37)
-        e.close()
+        for mode in ("multi_step", "persistent_multi"):
+            e = Ensemble(mem, dtype=dtype, mode=mode, chunk=chunk)
+            e.set_multi(k, w, h, nt, halo)
+            assert e.get_multi() == (k, w, h, nt, halo)
+            e.step(7)
+            for r in range(len(mem)):
+                for x, y in zip(e.moments(r, scalars=False), r7[r]):
+                    assert torch.equal(x, y), (mode, k, w, h, chunk, r, 7)
+            e.step(30)
+            for r in range(len(mem)):
+                for x, y in zip(e.moments(r, scalars=False), r37[r]):
+                    assert torch.equal(x, y), (mode, k, w, h, chunk, r, 37)
+            e.close()
     e = Ensemble(mem, dtype=dtype, mode="multi_step", chunk=4)
     for bad in ((7, 64, 8), (1, 64, 8), (2, 96, 8), (2, 64, 4), (2, 1024, 8), (4, 64, 8, 1, 2)):
         with pytest.raises(LBMError):
@@ -144,12 +145,13 @@ def test_multi_step_mode_equals_per_step_bitwise(gpu_lib, dtype):
     e.close()
 
 
-@pytest.mark.parametrize("mode", ["persistent", "multi_step_autotuned"])
+@pytest.mark.parametrize("mode", ["persistent", "multi_step_autotuned", "persistent_multi_autotuned"])
 def test_ensemble64_workload_sampled(gpu_lib, mode):
     """Workload ensemble64 (64 runs, 256^2..1024^2, FP32, tau in [0.505, 0.6]): 20 steps in
     one graph replay chunk, in the persistent mode and in the multi-step shape that the
-    autotuner picks for this workload (the shape the benchmark times); three members (the
-    largest and two others) checked on oracle patches, one across the periodic corner."""
+    autotuner picks for this workload (the shape the benchmark times), as separate launches
+    and inside one persistent launch; three members (the largest and two others) checked on
+    oracle patches, one across the periodic corner."""
     from paper_1809_06735_amd.ensemble import Ensemble
     say(f"ensemble64 build ({mode})")
     mem = inp.ensemble_members(64)
@@ -163,7 +165,7 @@ def test_ensemble64_workload_sampled(gpu_lib, mode):
         del tuner
         torch.cuda.empty_cache()
         say(f"ensemble64 autotuned multi-step shape (K, strip, band, nt, halo) = {shape}")
-        ens = Ensemble(mem, dtype="f32", mode="multi_step", chunk=20)
+        ens = Ensemble(mem, dtype="f32", mode=mode[:-len("_autotuned")], chunk=20)
         ens.set_multi(shape[0], shape[1], shape[2], shape[3], shape[4])
     assert ens.sites == sum(m["n"] ** 2 for m in mem)
     ens.step(20)
