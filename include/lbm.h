@@ -454,9 +454,15 @@ enum { LBM_BATCH_PERSISTENT = 0, LBM_BATCH_PER_STEP = 1, LBM_BATCH_MULTI_STEP = 
        LBM_BATCH_PERSISTENT_MULTI = 3 };
 typedef struct lbm_batch_s* lbm_batch;
 
-/* cfgs[nruns]: per-run configuration; with_balance must be 0, force_scheme
- * LBM_FORCE_GUO and collision LBM_COLLISION_BGK (LBM_E_UNSUPPORTED otherwise),
- * stream is taken from cfgs[0]. */
+/* cfgs[nruns]: per-run configuration; with_balance must be 0 and collision
+ * LBM_COLLISION_BGK (LBM_E_UNSUPPORTED otherwise), stream is taken from
+ * cfgs[0].  Every run has the same force_scheme.  LBM_FORCE_EDM runs (Sec. 3,
+ * at most 64) share nx, ny, layout, has_force and the damped shell (tau,
+ * damp_f0 and the force fields may differ); they step in
+ * LBM_BATCH_PER_STEP mode only (set at init; the other modes, set_tile,
+ * set_multi and autotune give LBM_E_UNSUPPORTED), each step one launch of
+ * every run's Fourier sums, one of their coefficients and one of the step
+ * kernel, bit-identical to the runs stepped alone. */
 LBM_API int lbm_batch_workspace_bytes(const lbm_config* cfgs, int32_t nruns, size_t* bytes);
 /* rho0/ux0/uy0/fx/fy: host arrays of nruns device FP64 pointers (fx/fy NULL,
  * or entries NULL for runs without force).  Every run starts at f^eq of its

@@ -443,6 +443,12 @@ struct lbm_batch_s {
   unsigned spin_limit = 1u << 22;
   int flavor = 2;
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  // exact-difference runs (every run LBM_FORCE_EDM on one grid size)
+  bool edm = false;
+  EdmModes edm_md{};
+  EdmWs edm_ws{};
+  EdmRuns edm_runs{};
+  lbm_tile edm_tile{};
 };
 
 namespace {
@@ -459,9 +465,12 @@ struct BatchLayout {
   int* error;
   double* partials;
   double* scalars;
+  EdmWs edm;
   size_t item_cap;
   size_t bytes;
 };
+
+bool edm_batch(const lbm_config* cfgs) { return cfgs[0].force_scheme == LBM_FORCE_EDM; }
 
 size_t max_items(const lbm_config* cfgs, int nruns) {
   // smallest item: kBT sites (vx = 1, ir = 1)
@@ -514,8 +523,44 @@ BatchLayout carve_batch(const lbm_config* cfgs, int nruns, void* base, size_t ca
   l.error = cv.take<int>(64);
   l.partials = cv.take<double>(static_cast<size_t>(maxblocks) * 8 + 8);
   l.scalars = cv.take<double>(8);
+  if (edm_batch(cfgs)) {
+    EdmModes md{};
+    if (edm_modes(cfgs[0], &md) == LBM_OK) l.edm = carve_edm_runs(cv, cfgs[0], md, nruns);
+  }
   l.bytes = cv.used + 256;
   return l;
+}
+
+// Exact-difference runs: damped modes, per-run 1/tau and damping rate, the
+// equal strides between the runs' buffers, the shared tables.
+int setup_edm(lbm_batch_s* b, const BatchLayout& l) {
+  b->edm = true;
+  b->mode = LBM_BATCH_PER_STEP;
+  b->edm_ws = l.edm;
+  b->edm_tile = edm_default_tile(b->cfg[0].nx);
+  EdmRuns& R = b->edm_runs;
+  R.n = b->nruns;
+  const size_t es = b->dtype == LBM_F32 ? 4 : 8;
+  for (int r = 0; r < b->nruns; ++r) {
+    EdmModes md{};
+    if (int rc = edm_modes(b->cfg[r], &md)) return rc;
+    if (r == 0) b->edm_md = md;
+    R.omega[r] = b->runs[r].omega;
+    R.f0[r] = md.f0;
+    if (r > 0) {
+      const auto gap = [&](const void* a, const void* z) {
+        return static_cast<size_t>(static_cast<const char*>(z) - static_cast<const char*>(a)) / es;
+      };
+      const size_t st = gap(b->runs[0].pop[0], b->runs[1].pop[0]);
+      bool ok = gap(b->runs[r - 1].pop[0], b->runs[r].pop[0]) == st &&
+                gap(b->runs[r - 1].pop[1], b->runs[r].pop[1]) == st;
+      if (b->cfg[0].has_force)
+        ok = ok && gap(b->runs[r - 1].fx, b->runs[r].fx) == st && gap(b->runs[r - 1].fy, b->runs[r].fy) == st;
+      if (!ok) return fail(LBM_E_UNSUPPORTED, "exact-difference runs are not equally spaced in the workspace");
+      R.pop_stride = R.force_stride = st;
+    }
+  }
+  return edm_tables(b->cfg[0], b->edm_ws, b->edm_md, b->stream);
 }
 
 int validate_batch(const lbm_config* cfgs, int32_t nruns) {
@@ -525,8 +570,19 @@ int validate_batch(const lbm_config* cfgs, int32_t nruns) {
     if (int rc = validate_config(&c)) return rc;
     if (c.dtype != cfgs[0].dtype) return fail(LBM_E_INVALID, "run %d: all runs need one dtype", r);
     if (c.with_balance) return fail(LBM_E_INVALID, "run %d: with_balance must be 0 in a batch", r);
-    if (c.force_scheme != LBM_FORCE_GUO || c.collision != LBM_COLLISION_BGK)
-      return fail(LBM_E_UNSUPPORTED, "run %d: a batch runs the Guo-forced BGK step only", r);
+    if (c.collision != LBM_COLLISION_BGK)
+      return fail(LBM_E_UNSUPPORTED, "run %d: a batch runs the BGK collision only", r);
+    if (c.force_scheme != cfgs[0].force_scheme)
+      return fail(LBM_E_UNSUPPORTED, "run %d: all runs of a batch need one force scheme", r);
+    if (c.force_scheme == LBM_FORCE_EDM) {
+      // exact-difference runs share the grid, the layout, the force flag and the damped modes
+      const lbm_config& a = cfgs[0];
+      if (c.nx != a.nx || c.ny != a.ny || c.layout != a.layout || c.has_force != a.has_force ||
+          (c.damp_f0 > 0.0) != (a.damp_f0 > 0.0) || c.damp_kmin != a.damp_kmin || c.damp_kmax != a.damp_kmax)
+        return fail(LBM_E_UNSUPPORTED, "run %d: exact-difference runs of a batch need one grid, layout, "
+                                       "force flag and damped shell", r);
+      if (nruns > kEdmMaxRuns) return fail(LBM_E_UNSUPPORTED, "at most %d exact-difference runs", kEdmMaxRuns);
+    }
     if (static_cast<size_t>(c.nx) * c.ny > 0x7fffffffu)
       return fail(LBM_E_INVALID, "run %d: grid too large for a batch", r);
   }
@@ -659,6 +715,24 @@ int enqueue_single_steps(lbm_batch_s* b, int p, int n, hipStream_t s, int* p_out
 // Enqueue `n` steps starting from buffer parity `par` on stream s.
 int enqueue_steps(lbm_batch_s* b, int par, int n, hipStream_t s) {
   if (n <= 0) return LBM_OK;
+  if (b->edm) {
+    // one launch sequence per step for all runs: Fourier sums, coefficients, step
+    const RunDesc& r0 = b->runs[0];
+    StepParams p{};
+    p.fx = r0.fx;
+    p.fy = r0.fy;
+    p.nx = r0.nx;
+    p.ny = r0.ny;
+    p.ps = r0.ps;
+    p.rs = r0.rs;
+    p.omega = r0.omega;
+    for (int k = 0; k < n; ++k) {
+      p.src = r0.pop[(par + k) & 1];
+      p.dst = r0.pop[(par + k + 1) & 1];
+      if (int rc = edm_step_runs(b->cfg[0], b->edm_ws, b->edm_md, b->edm_runs, p, b->edm_tile, s)) return rc;
+    }
+    return LBM_OK;
+  }
   if (b->mode == LBM_BATCH_MULTI_STEP) {
     const int K = b->ftile.fuse;
     FusedArgs f = fused_args(b, par);
@@ -816,6 +890,7 @@ int lbm_batch_init(const lbm_config* cfgs, int32_t nruns, void* ws, size_t ws_by
       if (rc == LBM_OK) rc = launch_to_storage(b->dtype, l.fy[r], fy[r], plane, b->stream);
     }
   }
+  if (rc == LBM_OK && edm_batch(cfgs)) rc = setup_edm(b, l);
   if (rc == LBM_OK) {
     hipError_t e = hipMemcpyAsync(b->d_runs, b->runs.data(), sizeof(RunDesc) * nruns,
                                   hipMemcpyHostToDevice, b->stream);
@@ -837,6 +912,8 @@ int lbm_batch_set_mode(lbm_batch b, int32_t mode, int32_t chunk) {
       mode != LBM_BATCH_PERSISTENT_MULTI)
     return fail(LBM_E_INVALID, "mode must be LBM_BATCH_PERSISTENT, _PER_STEP, _MULTI_STEP or _PERSISTENT_MULTI");
   if (chunk < 2 || chunk % 2 || chunk > 100000) return fail(LBM_E_INVALID, "chunk: even, 2..100000");
+  if (b->edm && mode != LBM_BATCH_PER_STEP)
+    return fail(LBM_E_UNSUPPORTED, "exact-difference runs step in LBM_BATCH_PER_STEP mode only");
   b->mode = mode;
   b->chunk = chunk;
   drop_batch_graphs(b);
@@ -845,6 +922,7 @@ int lbm_batch_set_mode(lbm_batch b, int32_t mode, int32_t chunk) {
 
 int lbm_batch_set_tile(lbm_batch b, int32_t block_threads, int32_t vx, int32_t band_rows) {
   if (!b) return fail(LBM_E_INVALID, "batch is NULL");
+  if (b->edm) return fail(LBM_E_UNSUPPORTED, "exact-difference runs use their step kernel's own shape");
   if (block_threads != 256 && block_threads != 512 && block_threads != 1024)
     return fail(LBM_E_INVALID, "block_threads must be 256, 512 or 1024");
   if (vx != 1 && vx != 2 && vx != 4) return fail(LBM_E_INVALID, "vx must be 1, 2 or 4");
@@ -860,6 +938,7 @@ int lbm_batch_set_tile(lbm_batch b, int32_t block_threads, int32_t vx, int32_t b
 
 int lbm_batch_set_multi(lbm_batch b, const lbm_tile* t) {
   if (!b || !t) return fail(LBM_E_INVALID, "NULL argument");
+  if (b->edm) return fail(LBM_E_UNSUPPORTED, "exact-difference runs have no multi-step mode");
   if (!fused_tile_ok(*t, b->dtype) || t->ry < kMinFusedBand)
     return fail(LBM_E_INVALID, "multi-step shape: fuse 2..6, halo 0 or 1, width a multiple of 64 up "
                                "to 512, band >= %d rows", kMinFusedBand);
@@ -899,6 +978,7 @@ int lbm_batch_autotune(lbm_batch b, int32_t trial_steps, int32_t* block_threads,
   if (!b) return fail(LBM_E_INVALID, "batch is NULL");
   if (trial_steps < 2 || trial_steps > 1000 || trial_steps % 2)
     return fail(LBM_E_INVALID, "trial_steps: even, 2..1000");
+  if (b->edm) return fail(LBM_E_UNSUPPORTED, "exact-difference runs have one launch shape (no autotuning)");
   const int saved_vx = b->vx, saved_ir = b->ir, saved_bt = b->bt, saved_mode = b->mode;
   const lbm_tile saved_f = b->ftile;
   hipEvent_t e0, e1;
@@ -1037,7 +1117,14 @@ int lbm_batch_moments(lbm_batch b, int32_t run, void* rho, void* ux, void* uy, i
   m.ps = r.ps;
   m.rs = r.rs;
   m.alpha = r.alpha;
-  if (int rc = launch_moments(b->dtype, r.forced != 0, m, b->stream)) return rc;
+  if (b->edm) {
+    EdmModes md = b->edm_md;
+    md.f0 = b->edm_runs.f0[run];
+    const EdmWs w = edm_run_view(b->edm_ws, b->cfg[0], b->edm_md, run);
+    if (int rc = edm_moments(b->cfg[run], w, md, m, b->stream)) return rc;
+  } else if (int rc = launch_moments(b->dtype, r.forced != 0, m, b->stream)) {
+    return rc;
+  }
   if (!scalars8) return LBM_OK;
   if (int rc = launch_reduce_scalars(b->d_partials, moment_blocks(r.nx, r.ny), b->d_scalars, b->stream))
     return rc;

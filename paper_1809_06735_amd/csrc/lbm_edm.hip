@@ -3,15 +3,17 @@
 // damping of the large scales, F^R = -F0^R sum_k u^(k) e^{i k.x} over the
 // damped shell, recomputed every step from the bare velocity j/rho.
 //
-// One damped step is three launches:
+// One damped step is two launches (the coefficient stage below runs inside
+// the step kernel; the moment kernel has it as a launch of its own):
 //  1. k_edm_fourier: each workgroup pulls the pre-collision populations of a
 //     block of 256 columns and `rows` rows, forms u = j/rho and reduces the
 //     Fourier sums C_k = sum u cos(k.x), S_k = sum u sin(k.x) of both
 //     components over its sites (first along y per column against the y
 //     tables, then per mode against the column's x tables, summed over the
 //     workgroup) into 4 m partials.
-//  2. k_edm_coef: one workgroup adds the partials in block order and turns the
-//     sums into per-row coefficients: with theta = kx phi + ky beta,
+//  2. coefficients: the partials are added in a fixed order (edm_sums) and the
+//     sums turned into per-row coefficients (edm_row_coef): with
+//     theta = kx phi + ky beta,
 //       F^R(x, y) = sum_{m = 0..km} A_m(y) cos(m phi) + B_m(y) sin(m phi),
 //     A_m = -2 F0 sum_{|kx| = m} (C cos ky beta + S sin ky beta),
 //     B_m = -2 F0 sum_{|kx| = m} sgn(kx) (S cos ky beta - C sin ky beta)
@@ -39,11 +41,13 @@ using namespace reduce_detail;
 // one workgroup of kCoefThreads threads.
 constexpr int kFourierCols = 256;
 constexpr int kCoefThreads = 1024;
+constexpr int kEdmTileRows = 64;
 
 int dft_xblocks(int nx) { return (nx + kFourierCols - 1) / kFourierCols; }
+// at least 4 rows per workgroup (fewer partials to add), at most 1024 workgroups
 int dft_rows(int nx, int ny) {
   const long long r = (static_cast<long long>(ny) * dft_xblocks(nx) + 1023) / 1024;
-  return static_cast<int>(std::max<long long>(1, r));
+  return static_cast<int>(std::min<long long>(ny, std::max<long long>(4, r)));
 }
 int dft_blocks(int nx, int ny) {
   const int r = dft_rows(nx, ny);
@@ -140,9 +144,11 @@ __global__ void __launch_bounds__(kFourierCols) k_edm_fourier(const T* __restric
                                                               int nx, int ny, int rows, int xblocks,
                                                               const double* __restrict__ tabx,
                                                               const double* __restrict__ taby, EdmModes md,
-                                                              double* __restrict__ partials) {
+                                                              double* __restrict__ partials, size_t pop_stride) {
   constexpr int K1 = KM + 1;
   constexpr int kWaves = kFourierCols / 64;
+  pop += blockIdx.y * pop_stride;  // run blockIdx.y
+  partials += static_cast<size_t>(blockIdx.y) * gridDim.x * 4 * md.m;
   __shared__ double wsum[kWaves][4 * kEdmMaxModes];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int xb = blockIdx.x % xblocks, yc = blockIdx.x / xblocks;
@@ -160,23 +166,34 @@ __global__ void __launch_bounds__(kFourierCols) k_edm_fourier(const T* __restric
     sx[m] = x < nx ? tabx[(2 * m + 1) * nx + x] : 0.0;
   }
   if (x < nx) {
-    for (int y = y0; y < y1; ++y) {
-      const int yn = (y == 0) ? ny - 1 : y - 1;
-      const int yp = (y == ny - 1) ? 0 : y + 1;
-      T d[9][1];
-      pull_all<T, 1>(pop, ps, rs, nx, x, y, yn, yp, d);
-      T di[9];
+    // rows in groups of four, the group's loads issued together; the sums still
+    // run row by row
+    for (int yg = y0; yg < y1; yg += 4) {
+      T d[4][9][1];
 #pragma unroll
-      for (int l = 0; l < 9; ++l) di[l] = d[l][0];
-      const EdmSite<T> st(di);
-      const double ux = double(st.jx * st.inv), uy = double(st.jy * st.inv);
+      for (int q = 0; q < 4; ++q) {
+        const int y = min(yg + q, y1 - 1);
+        const int yn = (y == 0) ? ny - 1 : y - 1;
+        const int yp = (y == ny - 1) ? 0 : y + 1;
+        pull_all<T, 1>(pop, ps, rs, nx, x, y, yn, yp, d[q]);
+      }
 #pragma unroll
-      for (int n = 0; n < K1; ++n) {
-        const double c = taby[(2 * n) * ny + y], sn = taby[(2 * n + 1) * ny + y];
-        ucx[n] += ux * c;
-        usx[n] += ux * sn;
-        ucy[n] += uy * c;
-        usy[n] += uy * sn;
+      for (int q = 0; q < 4; ++q) {
+        const int y = yg + q;
+        if (y >= y1) break;
+        T di[9];
+#pragma unroll
+        for (int l = 0; l < 9; ++l) di[l] = d[q][l][0];
+        const EdmSite<T> st(di);
+        const double ux = double(st.jx * st.inv), uy = double(st.jy * st.inv);
+#pragma unroll
+        for (int n = 0; n < K1; ++n) {
+          const double c = taby[(2 * n) * ny + y], sn = taby[(2 * n + 1) * ny + y];
+          ucx[n] += ux * c;
+          usx[n] += ux * sn;
+          ucy[n] += uy * c;
+          usy[n] += uy * sn;
+        }
       }
     }
   }
@@ -227,89 +244,153 @@ __global__ void __launch_bounds__(kFourierCols) k_edm_fourier(const T* __restric
   }
 }
 
-// One workgroup: add the partials in block order, then the per-row coefficients.
+// ---- 2. coefficients ---------------------------------------------------------------------
+// cf[v] = sum over the nparts partials of value v, in an order that does not
+// depend on the workgroup's size: eight interleaved running sums
+// (b = j, j + 8, ...) added as ((0 + 1) + (2 + 3)) + ((4 + 5) + (6 + 7)).
+// part is LDS scratch of 8 x V doubles; every thread of the workgroup calls it.
+__device__ __forceinline__ void edm_sums(const double* __restrict__ partials, int nparts, int V,
+                                         double* part, double* cf) {
+  const int nt = blockDim.x * blockDim.y;
+  const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+  for (int q = tid; q < 8 * V; q += nt) {
+    const int v = q % V, j = q / V;
+    double a = 0.0;
+    int b = j;
+    for (; b + 56 < nparts; b += 64) {  // eight loads in flight, added in order
+      double t[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) t[i] = partials[static_cast<size_t>(b + 8 * i) * V + v];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) a += t[i];
+    }
+    for (; b < nparts; b += 8) a += partials[static_cast<size_t>(b) * V + v];
+    part[j * V + v] = a;
+  }
+  __syncthreads();
+  for (int v = tid; v < V; v += nt) {
+    const double* p = part + v;
+    cf[v] = ((p[0] + p[V]) + (p[2 * V] + p[3 * V])) + ((p[4 * V] + p[5 * V]) + (p[6 * V] + p[7 * V]));
+  }
+  __syncthreads();
+}
+
+// The coefficients (A_x, B_x, A_y, B_y) per m = 0..KM of row y, from the sums cf.
+template <typename T, int KM>
+__device__ __forceinline__ void edm_row_coef(const double* cf, const double* __restrict__ taby,
+                                             const EdmModes& md, int ny, int y, double scale, T* out) {
+  constexpr int K1 = KM + 1;
+  double cb[K1], sb[K1];
+#pragma unroll
+  for (int n = 0; n < K1; ++n) {
+    cb[n] = taby[(2 * n) * ny + y];
+    sb[n] = taby[(2 * n + 1) * ny + y];
+  }
+  double A[2][K1], B[2][K1];
+#pragma unroll
+  for (int m = 0; m < K1; ++m) A[0][m] = A[1][m] = B[0][m] = B[1][m] = 0.0;
+  for (int k = 0; k < md.m; ++k) {
+    const int kx = md.kx[k], ky = md.ky[k];
+    const int mk = kx < 0 ? -kx : kx;
+    const double sg = kx < 0 ? -1.0 : (kx > 0 ? 1.0 : 0.0);
+    double c = 0.0, sn = 0.0;
+#pragma unroll
+    for (int n = 0; n < K1; ++n) {
+      c = n == ky ? cb[n] : c;
+      sn = n == ky ? sb[n] : sn;
+    }
+#pragma unroll
+    for (int m = 0; m < K1; ++m) {
+      if (m != mk) continue;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const double C = cf[4 * k + 2 * q], S = cf[4 * k + 2 * q + 1];
+        A[q][m] += C * c + S * sn;
+        B[q][m] += sg * (S * c - C * sn);
+      }
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < K1; ++m) {
+    out[4 * m] = T(scale * A[0][m]);
+    out[4 * m + 1] = T(scale * B[0][m]);
+    out[4 * m + 2] = T(scale * A[1][m]);
+    out[4 * m + 3] = T(scale * B[1][m]);
+  }
+}
+
+// Per-run damping rates of a launch.
+struct EdmRates {
+  double f0[kEdmMaxRuns];
+};
+
+// One workgroup per run (blockIdx.x): every row's coefficients into coef (the
+// moment kernel's input).
 template <typename T, int KM>
 __global__ void __launch_bounds__(kCoefThreads) k_edm_coef(const double* __restrict__ partials, int nparts,
                                                               const double* __restrict__ taby, EdmModes md,
-                                                              int ny, T* __restrict__ coef) {
+                                                              int ny, T* __restrict__ coef, EdmRates rates) {
   constexpr int K1 = KM + 1;
-  __shared__ double scratch[kCoefThreads];
+  __shared__ double part[8 * 4 * kEdmMaxModes];
   __shared__ double cf[4 * kEdmMaxModes];
-  const int tid = threadIdx.x;
   const int V = 4 * md.m;
-  {
-    const int R = kCoefThreads / V;
-    const int v = tid % V, r = tid / V;
-    double sum = 0.0;
-    if (r < R) {
-#pragma unroll 4
-      for (int b = r; b < nparts; b += R) sum += partials[static_cast<size_t>(b) * V + v];
-    }
-    scratch[tid] = sum;
-    __syncthreads();
-    if (tid < V) {
-      double a = 0.0;
-      for (int q = 0; q < R; ++q) a += scratch[q * V + tid];
-      cf[tid] = a;
-    }
-  }
-  __syncthreads();
-  const double scale = -2.0 * md.f0;
-  for (int y = tid; y < ny; y += kCoefThreads) {
-    double cb[K1], sb[K1];
-#pragma unroll
-    for (int n = 0; n < K1; ++n) {
-      cb[n] = taby[(2 * n) * ny + y];
-      sb[n] = taby[(2 * n + 1) * ny + y];
-    }
-    double A[2][K1], B[2][K1];
-#pragma unroll
-    for (int m = 0; m < K1; ++m) A[0][m] = A[1][m] = B[0][m] = B[1][m] = 0.0;
-    for (int k = 0; k < md.m; ++k) {
-      const int kx = md.kx[k], ky = md.ky[k];
-      const int mk = kx < 0 ? -kx : kx;
-      const double sg = kx < 0 ? -1.0 : (kx > 0 ? 1.0 : 0.0);
-      double c = 0.0, sn = 0.0;
-#pragma unroll
-      for (int n = 0; n < K1; ++n) {
-        c = n == ky ? cb[n] : c;
-        sn = n == ky ? sb[n] : sn;
-      }
-#pragma unroll
-      for (int m = 0; m < K1; ++m) {
-        if (m != mk) continue;
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-          const double C = cf[4 * k + 2 * q], S = cf[4 * k + 2 * q + 1];
-          A[q][m] += C * c + S * sn;
-          B[q][m] += sg * (S * c - C * sn);
-        }
-      }
-    }
-    T* out = coef + static_cast<size_t>(y) * K1 * 4;
-#pragma unroll
-    for (int m = 0; m < K1; ++m) {
-      out[4 * m] = T(scale * A[0][m]);
-      out[4 * m + 1] = T(scale * B[0][m]);
-      out[4 * m + 2] = T(scale * A[1][m]);
-      out[4 * m + 3] = T(scale * B[1][m]);
-    }
-  }
+  partials += static_cast<size_t>(blockIdx.x) * nparts * V;
+  coef += static_cast<size_t>(blockIdx.x) * ny * K1 * 4;
+  edm_sums(partials, nparts, V, part, cf);
+  const double scale = -2.0 * rates.f0[blockIdx.x];
+  for (int y = threadIdx.x; y < ny; y += kCoefThreads)
+    edm_row_coef<T, KM>(cf, taby, md, ny, y, scale, coef + static_cast<size_t>(y) * K1 * 4);
 }
 
 // ---- 3. the step ---------------------------------------------------------------------
 // Same tiling as the Guo single step with one site per thread: a workgroup
 // of blockDim.x x blockDim.y threads covers blockDim.x columns and
 // blockDim.y * ry rows; consecutive tiles on one XCD.
+// Per-run values of a step launch (run = blockIdx.y).
+struct EdmStepRuns {
+  size_t pop_stride, force_stride;
+  double omega[kEdmMaxRuns];
+  double f0[kEdmMaxRuns];
+};
+// With damping on a small grid (partials given), each workgroup first adds
+// the run's Fourier partials itself (edm_sums, the coefficient kernel's
+// order) and forms the coefficients of its tile's rows in LDS (at most
+// kEdmTileRows rows); otherwise it reads them from coef, which the
+// coefficient kernel wrote.
 template <typename T, int KM, bool FT, bool DAMP, bool NT>
 __global__ void __launch_bounds__(1024) k_edm_step(StepParams p, const T* __restrict__ tabx_t,
-                                                   const T* __restrict__ coef, int tiles_x, int total,
-                                                   int per_xcd, int ry) {
+                                                   const double* __restrict__ partials, int nparts,
+                                                   const double* __restrict__ taby, const T* __restrict__ coef,
+                                                   EdmModes md, int tiles_x, int total, int per_xcd, int ry,
+                                                   EdmStepRuns runs) {
   const int b = blockIdx.x;
   const int tile = (b & 7) * per_xcd + (b >> 3);
-  if (tile >= total) return;
+  if (tile >= total) return;  // uniform over the workgroup
+  const int r = blockIdx.y;
+  p.src = static_cast<const T*>(p.src) + r * runs.pop_stride;
+  p.dst = static_cast<T*>(p.dst) + r * runs.pop_stride;
+  if constexpr (FT) {
+    p.fx = static_cast<const T*>(p.fx) + r * runs.force_stride;
+    p.fy = static_cast<const T*>(p.fy) + r * runs.force_stride;
+  }
+  p.omega = runs.omega[r];
   const int tx = tile % tiles_x;
   const int ty = tile / tiles_x;
+  __shared__ T crow[DAMP ? kEdmTileRows : 1][4 * (KM + 1)];
+  if constexpr (DAMP) {
+    coef += static_cast<size_t>(r) * p.ny * (KM + 1) * 4;
+    if (partials) {  // uniform over the launch
+      __shared__ double part[8 * 4 * kEdmMaxModes];
+      __shared__ double cf[4 * kEdmMaxModes];
+      const int V = 4 * md.m;
+      edm_sums(partials + static_cast<size_t>(r) * nparts * V, nparts, V, part, cf);
+      const int rows = blockDim.y * ry, y0 = ty * rows;
+      const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+      for (int q = tid; q < rows; q += blockDim.x * blockDim.y)
+        if (y0 + q < p.ny) edm_row_coef<T, KM>(cf, taby, md, p.ny, y0 + q, -2.0 * runs.f0[r], crow[q]);
+      __syncthreads();
+    }
+  }
   const int x = tx * blockDim.x + threadIdx.x;
   if (x >= p.nx) return;
   const int ybase = (ty * blockDim.y + threadIdx.y) * ry;
@@ -341,7 +422,9 @@ __global__ void __launch_bounds__(1024) k_edm_step(StepParams p, const T* __rest
       Fx = static_cast<const T*>(p.fx)[i];
       Fy = static_cast<const T*>(p.fy)[i];
     }
-    if constexpr (DAMP) damp_force<T, KM>(coef + static_cast<size_t>(y) * (KM + 1) * 4, cm, sm, Fx, Fy);
+    if constexpr (DAMP)
+      damp_force<T, KM>(partials ? crow[threadIdx.y * ry + k] : coef + static_cast<size_t>(y) * (KM + 1) * 4, cm,
+                        sm, Fx, Fy);
     const EdmSite<T> s(di);
     const T ux = s.jx * s.inv, uy = s.jy * s.inv;
     const T vx = (s.jx + Fx) * s.inv, vy = (s.jy + Fy) * s.inv;
@@ -428,38 +511,76 @@ __global__ void __launch_bounds__(kRedThreads) k_edm_moments(MomentParams p, con
 // ---- host side ---------------------------------------------------------------------------
 size_t esize(int dtype) { return dtype == LBM_F64 ? 8 : 4; }
 
+// The Fourier sums of runs.n runs (run 0's populations at pop) into w.partials.
 template <typename T, int KM>
-int launch_fourier(const lbm_config& c, const EdmWs& w, const EdmModes& md, const void* pop, size_t ps,
-                   size_t rs, hipStream_t s) {
+int launch_sums(const lbm_config& c, const EdmWs& w, const EdmModes& md, const EdmRuns& runs,
+                const void* pop, size_t ps, size_t rs, hipStream_t s) {
   const int nb = dft_blocks(c.nx, c.ny);
-  hipLaunchKernelGGL((k_edm_fourier<T, KM>), dim3(nb), dim3(kFourierCols), 0, s, static_cast<const T*>(pop),
-                     ps, rs, c.nx, c.ny, dft_rows(c.nx, c.ny), dft_xblocks(c.nx), w.tabx, w.taby, md,
-                     w.partials);
-  LBM_HIP(hipGetLastError());
-  hipLaunchKernelGGL((k_edm_coef<T, KM>), dim3(1), dim3(kCoefThreads), 0, s, w.partials, nb, w.taby, md,
-                     c.ny, static_cast<T*>(w.coef));
+  hipLaunchKernelGGL((k_edm_fourier<T, KM>), dim3(nb, runs.n), dim3(kFourierCols), 0, s,
+                     static_cast<const T*>(pop), ps, rs, c.nx, c.ny, dft_rows(c.nx, c.ny), dft_xblocks(c.nx),
+                     w.tabx, w.taby, md, w.partials, runs.pop_stride);
   LBM_HIP(hipGetLastError());
   return LBM_OK;
 }
 
+// The Fourier sums and every row's coefficients of runs.n runs.
+template <typename T, int KM>
+int launch_fourier(const lbm_config& c, const EdmWs& w, const EdmModes& md, const EdmRuns& runs,
+                   const void* pop, size_t ps, size_t rs, hipStream_t s) {
+  if (int rc = launch_sums<T, KM>(c, w, md, runs, pop, ps, rs, s)) return rc;
+  const int nb = dft_blocks(c.nx, c.ny);
+  EdmRates rates{};
+  for (int r = 0; r < runs.n; ++r) rates.f0[r] = runs.f0[r];
+  hipLaunchKernelGGL((k_edm_coef<T, KM>), dim3(runs.n), dim3(kCoefThreads), 0, s, w.partials, nb, w.taby, md,
+                     c.ny, static_cast<T*>(w.coef), rates);
+  LBM_HIP(hipGetLastError());
+  return LBM_OK;
+}
+
+// One run: its own 1/tau and damping rate, no strides.
+EdmRuns single_run(const EdmModes& md, double omega) {
+  EdmRuns r;
+  r.omega[0] = omega;
+  r.f0[0] = md.f0;
+  return r;
+}
+
 template <typename T, int KM, bool FT, bool DAMP>
-int launch_step_k(const lbm_config& c, const EdmWs& w, const EdmModes& md, const StepParams& p,
-                  const lbm_tile& t, hipStream_t s) {
-  if constexpr (DAMP)
-    if (int rc = launch_fourier<T, KM>(c, w, md, p.src, p.ps, p.rs, s)) return rc;
+int launch_step_k(const lbm_config& c, const EdmWs& w, const EdmModes& md, const EdmRuns& runs,
+                  const StepParams& p, const lbm_tile& t, hipStream_t s) {
   const int tiles_x = (p.nx + t.bx - 1) / t.bx;
   const int rows_per_tile = t.by * t.ry;
   const int tiles_y = (p.ny + rows_per_tile - 1) / rows_per_tile;
   const int total = tiles_x * tiles_y;
+  // the step's workgroups add the partials themselves while all of them read
+  // at most 8 MiB per run; else one coefficient launch first
+  const int nb = DAMP ? dft_blocks(c.nx, c.ny) : 0;
+  const bool in_step = DAMP && static_cast<double>(nb) * total * 4 * md.m * 8 <= 8.0 * (1 << 20);
+  if constexpr (DAMP) {
+    if (in_step) {
+      if (int rc = launch_sums<T, KM>(c, w, md, runs, p.src, p.ps, p.rs, s)) return rc;
+    } else if (int rc = launch_fourier<T, KM>(c, w, md, runs, p.src, p.ps, p.rs, s)) {
+      return rc;
+    }
+  }
   const int per_xcd = (total + 7) / 8;
   const T* tabx_t = static_cast<const T*>(w.tabx_t);
+  EdmStepRuns sr{};
+  sr.pop_stride = runs.pop_stride;
+  sr.force_stride = runs.force_stride;
+  for (int r = 0; r < runs.n; ++r) {
+    sr.omega[r] = runs.omega[r];
+    sr.f0[r] = runs.f0[r];
+  }
+  const dim3 grid(per_xcd * 8, runs.n);
+  const double* parts = in_step ? w.partials : nullptr;
   const T* coef = static_cast<const T*>(w.coef);
   if (t.nt)
-    hipLaunchKernelGGL((k_edm_step<T, KM, FT, DAMP, true>), dim3(per_xcd * 8), dim3(t.bx, t.by), 0, s, p,
-                       tabx_t, coef, tiles_x, total, per_xcd, t.ry);
+    hipLaunchKernelGGL((k_edm_step<T, KM, FT, DAMP, true>), grid, dim3(t.bx, t.by), 0, s, p, tabx_t, parts,
+                       nb, w.taby, coef, md, tiles_x, total, per_xcd, t.ry, sr);
   else
-    hipLaunchKernelGGL((k_edm_step<T, KM, FT, DAMP, false>), dim3(per_xcd * 8), dim3(t.bx, t.by), 0, s, p,
-                       tabx_t, coef, tiles_x, total, per_xcd, t.ry);
+    hipLaunchKernelGGL((k_edm_step<T, KM, FT, DAMP, false>), grid, dim3(t.bx, t.by), 0, s, p, tabx_t, parts,
+                       nb, w.taby, coef, md, tiles_x, total, per_xcd, t.ry, sr);
   LBM_HIP(hipGetLastError());
   return LBM_OK;
 }
@@ -468,7 +589,7 @@ template <typename T, int KM, bool FT, bool DAMP>
 int launch_moments_k(const lbm_config& c, const EdmWs& w, const EdmModes& md, const MomentParams& p,
                      hipStream_t s) {
   if constexpr (DAMP)
-    if (int rc = launch_fourier<T, KM>(c, w, md, p.pop, p.ps, p.rs, s)) return rc;
+    if (int rc = launch_fourier<T, KM>(c, w, md, single_run(md, 0.0), p.pop, p.ps, p.rs, s)) return rc;
   const int g = moment_blocks(p.nx, p.ny);
   const T* tabx_t = static_cast<const T*>(w.tabx_t);
   const T* coef = static_cast<const T*>(w.coef);
@@ -486,12 +607,13 @@ struct StepGo {
   const lbm_config& c;
   const EdmWs& w;
   const EdmModes& md;
+  const EdmRuns& runs;
   const StepParams& p;
   const lbm_tile& t;
   hipStream_t s;
   template <typename T, int KM, bool FT, bool DAMP>
   int run() const {
-    return launch_step_k<T, KM, FT, DAMP>(c, w, md, p, t, s);
+    return launch_step_k<T, KM, FT, DAMP>(c, w, md, runs, p, t, s);
   }
 };
 
@@ -551,16 +673,27 @@ int edm_modes(const lbm_config& c, EdmModes* out) {
   return LBM_OK;
 }
 
-EdmWs carve_edm(Carver& cv, const lbm_config& c, const EdmModes& md) {
+EdmWs carve_edm(Carver& cv, const lbm_config& c, const EdmModes& md) { return carve_edm_runs(cv, c, md, 1); }
+
+EdmWs carve_edm_runs(Carver& cv, const lbm_config& c, const EdmModes& md, int nruns) {
   EdmWs w;
   if (c.force_scheme != LBM_FORCE_EDM || md.m == 0) return w;
   const size_t k1 = static_cast<size_t>(md.km) + 1, es = esize(c.dtype);
   w.tabx = cv.take<double>(k1 * 2 * c.nx);
   w.taby = cv.take<double>(k1 * 2 * c.ny);
   w.tabx_t = cv.take<char>(k1 * 2 * c.nx * es);
-  w.partials = cv.take<double>(static_cast<size_t>(dft_blocks(c.nx, c.ny)) * 4 * md.m);
-  w.coef = cv.take<char>(static_cast<size_t>(c.ny) * k1 * 4 * es);
+  w.partials = cv.take<double>(static_cast<size_t>(nruns) * dft_blocks(c.nx, c.ny) * 4 * md.m);
+  w.coef = cv.take<char>(static_cast<size_t>(nruns) * c.ny * k1 * 4 * es);
   return w;
+}
+
+EdmWs edm_run_view(const EdmWs& w, const lbm_config& c, const EdmModes& md, int r) {
+  EdmWs v = w;
+  if (md.m == 0) return v;
+  const size_t k1 = static_cast<size_t>(md.km) + 1;
+  v.partials = w.partials + static_cast<size_t>(r) * dft_blocks(c.nx, c.ny) * 4 * md.m;
+  v.coef = static_cast<char*>(w.coef) + static_cast<size_t>(r) * c.ny * k1 * 4 * esize(c.dtype);
+  return v;
 }
 
 int edm_tables(const lbm_config& c, const EdmWs& w, const EdmModes& md, hipStream_t s) {
@@ -583,6 +716,7 @@ bool edm_tile_ok(const lbm_tile& t, int nx, int ny) {
   if (t.fuse < 0 || t.fuse > 1 || t.vx != 1 || t.pf != 0 || t.halo != 0) return false;
   const int threads = t.bx * t.by;
   if (t.bx < 1 || t.by < 1 || t.ry < 1 || threads > 1024 || threads % 64 != 0) return false;
+  if (t.by * t.ry > kEdmTileRows) return false;  // the step kernel's rows of coefficients in LDS
   return t.nt == 0 || t.nt == 1;
 }
 
@@ -604,7 +738,17 @@ int edm_step(const lbm_config& c, const EdmWs& w, const EdmModes& md, const Step
              const lbm_tile& t, hipStream_t s) {
   if (!edm_tile_ok(t, c.nx, c.ny))
     return fail(LBM_E_INVALID, "invalid launch shape for the exact-difference step");
-  return dispatch(c, md, StepGo{c, w, md, p, t, s});
+  const EdmRuns one = single_run(md, p.omega);
+  return dispatch(c, md, StepGo{c, w, md, one, p, t, s});
+}
+
+int edm_step_runs(const lbm_config& c, const EdmWs& w, const EdmModes& md, const EdmRuns& runs,
+                  const StepParams& p, const lbm_tile& t, hipStream_t s) {
+  if (!edm_tile_ok(t, c.nx, c.ny))
+    return fail(LBM_E_INVALID, "invalid launch shape for the exact-difference step");
+  if (runs.n < 1 || runs.n > kEdmMaxRuns) return fail(LBM_E_INVALID, "1..%d runs per launch", kEdmMaxRuns);
+  if (p.h_rho) return fail(LBM_E_INVALID, "no moment record in a batched step");
+  return dispatch(c, md, StepGo{c, w, md, runs, p, t, s});
 }
 
 int edm_moments(const lbm_config& c, const EdmWs& w, const EdmModes& md, const MomentParams& p,

@@ -159,6 +159,17 @@ struct EdmModes {
   int8_t ky[kEdmMaxModes] = {};
 };
 int edm_modes(const lbm_config& c, EdmModes* out);
+// Equal grids stepped by one set of launches (the run is the grid's y index):
+// run r's populations, force fields, Fourier partials and coefficients sit r
+// strides after run 0's; each run has its own 1/tau and damping rate.
+constexpr int kEdmMaxRuns = 64;
+struct EdmRuns {
+  int n = 1;
+  size_t pop_stride = 0;    // elements between runs' population arrays
+  size_t force_stride = 0;  // elements between runs' force fields
+  double omega[kEdmMaxRuns] = {};
+  double f0[kEdmMaxRuns] = {};  // damp_f0 / (nx ny) per run
+};
 struct EdmWs {
   double* tabx = nullptr;  // [km+1][2][nx] cos, sin of 2 pi m x / nx (FP64)
   double* taby = nullptr;  // [km+1][2][ny] same in y
@@ -174,6 +185,13 @@ lbm_tile edm_default_tile(int nx);
 // exact-difference step kernel src -> dst (optional moment record in p.h_*).
 int edm_step(const lbm_config& c, const EdmWs& w, const EdmModes& md, const StepParams& p,
              const lbm_tile& t, hipStream_t s);
+// One step of runs.n equal grids: p describes run 0 (no moment record); w
+// holds runs.n partial and coefficient blocks (carve_edm_runs).
+int edm_step_runs(const lbm_config& c, const EdmWs& w, const EdmModes& md, const EdmRuns& runs,
+                  const StepParams& p, const lbm_tile& t, hipStream_t s);
+EdmWs carve_edm_runs(Carver& cv, const lbm_config& c, const EdmModes& md, int nruns);
+// Partials and coefficients of run r of such a workspace.
+EdmWs edm_run_view(const EdmWs& w, const lbm_config& c, const EdmModes& md, int r);
 // Moments of the current populations as launch_moments, with the physical
 // velocity (j + F/2)/rho and the total force F_ext + F^R.
 int edm_moments(const lbm_config& c, const EdmWs& w, const EdmModes& md, const MomentParams& p,

@@ -19,9 +19,15 @@ class Ensemble:
 
     members: list of dicts with keys rho, ux, uy (arrays [ny, nx]), tau, and
     optionally fx, fy, alpha.  dtype: "f32" or "f64" for every run.
+
+    Exact-difference runs (member key scheme = "edm", optional damp_f0 and
+    damp_shell as for Simulation): every member on one grid size with the same
+    force flag and damped shell; tau, damp_f0 and the force fields may differ.
+    They step in the per-step mode, every run's Fourier sums, coefficients and
+    step in one launch each.
     """
 
-    def __init__(self, members, dtype="f32", device="cuda", stream=None, mode="persistent",
+    def __init__(self, members, dtype="f32", device="cuda", stream=None, mode=None,
                  chunk=100, layout="rows"):
         _require_gpu()
         self._lib = L.load()
@@ -41,10 +47,13 @@ class Ensemble:
             fy = _dev64(m["fy"], self.device) if has_f else None
             ny, nx = rho.shape
             self.shapes.append((ny, nx))
+            shell = m.get("damp_shell", (1.0, 2.0))
             cfgs[r] = L.Config(nx=nx, ny=ny, dtype=dt, has_force=int(has_f), with_balance=0,
                                layout=L.LAYOUTS[layout], tau=float(m["tau"]),
                                drag_alpha=float(m.get("alpha", 0.0)),
-                               stream=sh)
+                               force_scheme=L.SCHEMES[m.get("scheme", "guo")],
+                               damp_f0=float(m.get("damp_f0", 0.0)), damp_kmin=float(shell[0]),
+                               damp_kmax=float(shell[1]), stream=sh)
             dev_inputs.append((rho, ux, uy, fx, fy))
         nbytes = C.c_size_t()
         L.check(self._lib.lbm_batch_workspace_bytes(cfgs, self.n, C.byref(nbytes)),
@@ -58,6 +67,8 @@ class Ensemble:
         self._h = h
         (stream or torch.cuda.current_stream(self.device)).synchronize()
         del dev_inputs
+        if mode is None:
+            mode = "per_step" if members[0].get("scheme", "guo") == "edm" else "persistent"
         self.set_mode(mode, chunk)
 
     def close(self):

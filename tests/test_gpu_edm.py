@@ -279,3 +279,82 @@ def test_configuration_sampling_and_pooled_statistics(gpu_lib):
                     assert g[m] == pytest.approx(w[m], rel=1e-7), (kind, L, name, m)
                 hw = ref.histogram(vals, torch.as_tensor(edges)).numpy()
                 assert int(np.abs(gh[q] - hw).sum()) <= 2, (kind, L, name, gh[q], hw)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_edm_runs_batched_equal_single_runs(gpu_lib, dtype):
+    """Five exact-difference runs on one 64 x 48 grid (the five tau0 of the paper's set-up,
+    different damping rates, force fields and initial states) stepped together: each run's
+    moments equal, bit for bit, those of the same run stepped alone, after 9 steps (one
+    graph replay of 8 plus one enqueued step) and after 40; one run also against the
+    oracle.  Without force, the batch takes forceless runs as well."""
+    from paper_1809_06735_amd.ensemble import Ensemble
+    ny, nx = 64, 48
+    taus = (0.5005, 0.501, 0.505, 0.51, 0.55)
+    mem = []
+    for k, tau in enumerate(taus):
+        rho, ux, uy = _fields(ny, nx, 20 + k, mach=0.05)
+        fx, fy = inp.forcing_field(max(nx, ny), seed=40 + k, max_force=2e-5)
+        mem.append({"rho": rho, "ux": ux, "uy": uy, "tau": tau, "scheme": "edm",
+                    "fx": fx[:ny, :nx].copy(), "fy": fy[:ny, :nx].copy(),
+                    "damp_f0": 0.05 * (k + 1), "damp_shell": (1.0, 2.0)})
+    ens = Ensemble(mem, dtype=dtype, chunk=8)
+    assert ens.get_mode()[0] == "per_step"
+    for steps in (9, 40):
+        ens.step(steps - ens.time)
+        for r, m in enumerate(mem):
+            s = Sim(m["rho"], m["ux"], m["uy"], m["tau"], dtype=dtype, fx=m["fx"], fy=m["fy"], scheme="edm",
+                    damp_f0=m["damp_f0"], damp_shell=m["damp_shell"])
+            s.step(steps)
+            want = s.moments(scalars=False)
+            got = ens.moments(r, scalars=False)
+            for name, g, w in zip(("rho", "ux", "uy"), got, want):
+                assert torch.equal(g, w), (dtype, steps, r, name)
+            s.close()
+        say(f"edm batch {dtype}: 5 runs bitwise equal to single runs at {steps} steps")
+    m = mem[3]
+    want = _oracle(m["rho"], m["ux"], m["uy"], 40, m["tau"], m["fx"], m["fy"], m["damp_f0"], (1.0, 2.0))
+    r, vx, vy, _ = ens.moments(3)
+    for name, g, w in zip(("rho", "ux", "uy"), (r, vx, vy), want[:3]):
+        e = moment_err(name, g, w, dtype)
+        tol = moment_tol(name, want[:3], dtype, 40, TOL64 if dtype == "f64" else TOL32)
+        say(f"edm batch {dtype} run 3 {name} vs oracle {e:.1e} (tol {tol:.1e})")
+        assert e < tol, (name, e, tol)
+    ens.close()
+    plain = [{k: v for k, v in m.items() if k not in ("fx", "fy")} for m in mem[:2]]
+    e2 = Ensemble(plain, dtype=dtype)
+    e2.step(6)
+    s = Sim(plain[1]["rho"], plain[1]["ux"], plain[1]["uy"], plain[1]["tau"], dtype=dtype, scheme="edm",
+            damp_f0=plain[1]["damp_f0"])
+    s.step(6)
+    for g, w in zip(e2.moments(1, scalars=False), s.moments(scalars=False)):
+        assert torch.equal(g, w)
+    s.close()
+    e2.close()
+
+
+def test_edm_batch_rejects_what_it_does_not_run(gpu_lib):
+    from paper_1809_06735_amd import LBMError
+    from paper_1809_06735_amd.ensemble import Ensemble
+    rho, ux, uy = _fields(32, 32, 1)
+    a = {"rho": rho, "ux": ux, "uy": uy, "tau": 0.6, "scheme": "edm", "damp_f0": 0.1}
+    b = dict(a, rho=_fields(32, 40, 2)[0], ux=_fields(32, 40, 2)[1], uy=_fields(32, 40, 2)[2])
+    with pytest.raises(LBMError):
+        Ensemble([a, b])                                  # two grid sizes
+    with pytest.raises(LBMError):
+        Ensemble([a, dict(a, damp_shell=(1.0, 3.0))])     # two damped shells
+    with pytest.raises(LBMError):
+        Ensemble([a, dict(a, scheme="guo", damp_f0=0.0)])  # two force schemes
+    e = Ensemble([a, dict(a, tau=0.7)])
+    for bad in (lambda: e.set_mode("persistent"), lambda: e.set_multi(4, 128, 32),
+                lambda: e.set_tile(1, 1), lambda: e.autotune(4)):
+        with pytest.raises(LBMError):
+            bad()
+    e.close()
+
+
+def test_edm_damped_512_coefficient_launch(gpu_lib):
+    """512^2: the step's workgroups would read too many Fourier partials to add them
+    themselves, so the coefficients come from their own launch (the large-grid path); FP64
+    against the oracle."""
+    _run_case(512, 512, "f64", 8, 0.55, 0.3, seed=12, label="edm64 512^2")
