@@ -538,9 +538,9 @@ def _ensemble_fixed_extra(log, steps=204):
                                   one_by_one=False)
 
 
-def _adjoint_extra(log):
+def _adjoint_extra(log, steps=None):
     from paper_1809_06735_amd import adjoint as adj_mod
-    return adj_mod.bench_adjoint(log=log)
+    return adj_mod.bench_adjoint(log=log, steps=steps)
 
 
 EXTRAS["ensemble"] = _ensemble_extra

@@ -69,10 +69,11 @@ def enstrophy_residual_loss(ux0, uy0, tau, steps, box, ckpt_every=100, dtype="f3
     return LBMAdjointFn.apply(ux0, uy0, tau_t, int(steps), int(box), int(ckpt_every), dtype)
 
 
-def bench_adjoint(log=print):
+def bench_adjoint(log=print, steps=None):
     """Workload adjoint512: 512^2 FP32 decaying spectrum (seed 7), tau 0.51, 2000 steps,
     checkpoints every 100, loss at box 32.  MLUPS of the loss-only run, of the whole
-    gradient run and of its backward part, against the plain forward step."""
+    gradient run and of its backward part, against the plain forward step.  `steps` (a
+    multiple of 100) shortens every run, for profiling."""
     import lbm_inputs as inp
     from .sim import Simulation
     w = inp.WORKLOADS["adjoint512"]
@@ -81,7 +82,8 @@ def bench_adjoint(log=print):
     vx = torch.as_tensor(ux, device=dev)
     vy = torch.as_tensor(uy, device=dev)
     sites = w.n * w.n
-    out = {"grid": w.n, "steps": w.steps, "ckpt_every": 100, "box": 32, "dtype": "f32"}
+    nsteps = w.steps if steps is None else int(steps)
+    out = {"grid": w.n, "steps": nsteps, "ckpt_every": 100, "box": 32, "dtype": "f32"}
     # tune the step-kernel shape for this grid once; the adjoint run reuses it
     s = Simulation(torch.ones_like(vx), vx, vy, w.tau, dtype="f32")
     out["tile"] = list(s.autotune(trial_steps=10))
@@ -94,21 +96,21 @@ def bench_adjoint(log=print):
         torch.cuda.synchronize()
         return time.perf_counter() - t0, r
 
-    t_fwd, _ = timed(lambda: adjoint_run(vx, vy, w.tau, w.steps, 32, 100, need_grad=False))
-    t_all, res = timed(lambda: adjoint_run(vx, vy, w.tau, w.steps, 32, 100))
+    t_fwd, _ = timed(lambda: adjoint_run(vx, vy, w.tau, nsteps, 32, 100, need_grad=False))
+    t_all, res = timed(lambda: adjoint_run(vx, vy, w.tau, nsteps, 32, 100))
     out["loss"] = res[0]
     out["dJ_dtau"] = res[3]
-    out["forward_and_loss_MLUPS"] = round(sites * w.steps / t_fwd / 1e6, 1)
-    out["gradient_run_MLUPS"] = round(sites * w.steps / t_all / 1e6, 1)
-    out["backward_part_MLUPS"] = round(sites * w.steps / max(t_all - t_fwd, 1e-9) / 1e6, 1)
+    out["forward_and_loss_MLUPS"] = round(sites * nsteps / t_fwd / 1e6, 1)
+    out["gradient_run_MLUPS"] = round(sites * nsteps / t_all / 1e6, 1)
+    out["backward_part_MLUPS"] = round(sites * nsteps / max(t_all - t_fwd, 1e-9) / 1e6, 1)
     # the same gradient run in FP64 (the verified gradient of this workload: checked against
     # central differences at 1e-3; FP32 rounding exceeds this loss's residual, see the tests)
     adjoint_run(vx, vy, w.tau, 20, 32, 10, dtype="f64")
-    t64_all, res64 = timed(lambda: adjoint_run(vx, vy, w.tau, w.steps, 32, 100, dtype="f64"))
+    t64_all, res64 = timed(lambda: adjoint_run(vx, vy, w.tau, nsteps, 32, 100, dtype="f64"))
     g32 = torch.cat([res[1].flatten(), res[2].flatten()])
     g64 = torch.cat([res64[1].flatten(), res64[2].flatten()])
     out["fp64"] = {"loss": res64[0], "dJ_dtau": res64[3],
-                   "gradient_run_MLUPS": round(sites * w.steps / t64_all / 1e6, 1),
+                   "gradient_run_MLUPS": round(sites * nsteps / t64_all / 1e6, 1),
                    "verified": "central differences of the FP64 loss (1e-3) on this workload; "
                                "the oracle's autodiff at 32^2 (1e-8)"}
     out["fp32_vs_fp64"] = {"loss_ratio": res[0] / res64[0],
@@ -117,8 +119,8 @@ def bench_adjoint(log=print):
                                        "32^2 case; on this workload FP32 does not resolve the "
                                        "loss's residual, so its gradient direction is not meaningful"}
     s.step(100)
-    tp, _ = timed(lambda: s.step(w.steps))
-    out["plain_forward_MLUPS"] = round(sites * w.steps / tp / 1e6, 1)
+    tp, _ = timed(lambda: s.step(nsteps))
+    out["plain_forward_MLUPS"] = round(sites * nsteps / tp / 1e6, 1)
     s.close()
     log(f"[adjoint] gradient run {out['gradient_run_MLUPS']} MLUPS, backward part "
         f"{out['backward_part_MLUPS']} MLUPS, plain forward {out['plain_forward_MLUPS']} MLUPS")
