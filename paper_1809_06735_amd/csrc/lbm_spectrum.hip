@@ -10,9 +10,9 @@
 // Passes (FP64 complex throughout): pack z and transform every row in LDS
 // (radix-2, decimation in time, bit-reversed load, twiddles from a table of
 // exp(-2 pi i k / nmax)); transpose through LDS tiles; transform the rows of
-// the transpose (the columns); add 1/2 |Z|^2 into the shells in LDS and then
-// into the device spectrum.  The shell sums use FP64 atomics, so the last bits
-// of a shell's sum depend on the order in which workgroups finish.
+// the transpose (the columns); then one workgroup per shell adds 1/2 |Z|^2
+// over the shell's wavevectors in a fixed order (no atomics: the spectrum is
+// bitwise reproducible).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -82,42 +82,53 @@ __global__ void __launch_bounds__(256) k_transpose(const double2* __restrict__ a
   }
 }
 
-__global__ void k_zero_f64(double* p, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0.0;
-}
-
-// Signed frequency of FFT index i of length n (n/2 maps to -n/2).
-__device__ __forceinline__ int signed_freq(int i, int n) { return i < n / 2 ? i : i - n; }
-
-// Shell s with (2s - 1)^2 <= 4 k2 < (2s + 1)^2 (s = 0 for k2 = 0).
-__device__ __forceinline__ int shell_of(long long k2) {
-  int s = static_cast<int>(floor(sqrt(static_cast<double>(k2)) + 0.5));
-  const long long q = 4 * k2;
-  if (s > 0 && static_cast<long long>(2 * s - 1) * (2 * s - 1) > q) --s;
-  if (static_cast<long long>(2 * s + 1) * (2 * s + 1) <= q) ++s;
-  return s;
+// Largest f >= 0 with 4 f^2 <= q (q >= 0).
+__device__ __forceinline__ long long isqrt4(long long q) {
+  long long f = static_cast<long long>(sqrt(static_cast<double>(q) / 4.0));
+  while (f > 0 && 4 * f * f > q) --f;
+  while (4 * (f + 1) * (f + 1) <= q) ++f;
+  return f;
 }
 
 // z [nx][ny] after both passes: row index = x frequency, column = y frequency.
-__global__ void __launch_bounds__(256) k_shells(const double2* __restrict__ z, int nx, int ny, int nshells,
-                                                double scale, double* __restrict__ spec) {
-  extern __shared__ double bins[];
-  for (int s = threadIdx.x; s < nshells; s += blockDim.x) bins[s] = 0.0;
-  __syncthreads();
-  const size_t total = static_cast<size_t>(nx) * ny;
-  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < total; i += size_t(gridDim.x) * blockDim.x) {
-    const int kxi = static_cast<int>(i / ny), kyi = static_cast<int>(i % ny);
-    const long long fx = signed_freq(kxi, nx), fy = signed_freq(kyi, ny);
-    const int s = shell_of(fx * fx + fy * fy);
-    if (s < nshells) {
-      const double2 v = z[i];
-      atomicAdd(&bins[s], 0.5 * scale * (v.x * v.x + v.y * v.y));
+// One workgroup per shell s gathers the shell's wavevectors, those with
+// (2s - 1)^2 <= 4 |k|^2 < (2s + 1)^2: thread t takes the x frequencies
+// fx = -s + t, -s + t + 256, ... (within the grid's signed range), and for each
+// the y frequencies of the annulus, two contiguous runs +-[fy_lo, fy_hi], in
+// increasing order; the threads' sums are added by a fixed tree.  No atomics:
+// the result does not depend on scheduling.
+__global__ void __launch_bounds__(256) k_shells(const double2* __restrict__ z, int nx, int ny, double scale,
+                                                double* __restrict__ spec) {
+  __shared__ double wsum[4];
+  const long long sh = blockIdx.x;
+  const long long qlo = sh > 0 ? (2 * sh - 1) * (2 * sh - 1) : 0;  // 4|k|^2 >= qlo
+  const long long qhi = (2 * sh + 1) * (2 * sh + 1) - 1;           // 4|k|^2 <= qhi
+  const long long fxa = max(-sh, static_cast<long long>(-(nx / 2)));
+  const long long fxb = min(sh, static_cast<long long>(nx - nx / 2 - 1));
+  const long long fya = -(ny / 2), fyb = ny - ny / 2 - 1;
+  double acc = 0.0;
+  for (long long fx = fxa + threadIdx.x; fx <= fxb; fx += 256) {
+    const long long a4 = 4 * fx * fx;
+    if (a4 > qhi) continue;
+    const long long hi = isqrt4(qhi - a4);                       // |fy| <= hi
+    const long long lo = qlo > a4 ? isqrt4(qlo - a4 - 1) + 1 : 0;  // |fy| >= lo
+    if (lo > hi) continue;
+    const double2* row = z + static_cast<size_t>(fx < 0 ? fx + nx : fx) * ny;
+    // negative y frequencies -hi .. -lo (skipping 0), then lo .. hi
+    for (long long fy = max(-hi, fya); fy <= min(-max(lo, 1LL), fyb); ++fy) {
+      const double2 v = row[fy + ny];
+      acc += v.x * v.x + v.y * v.y;
+    }
+    for (long long fy = max(lo, fya); fy <= min(hi, fyb); ++fy) {
+      const double2 v = row[fy];
+      acc += v.x * v.x + v.y * v.y;
     }
   }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = acc;
   __syncthreads();
-  for (int s = threadIdx.x; s < nshells; s += blockDim.x)
-    if (bins[s] != 0.0) atomicAdd(&spec[s], bins[s]);
+  if (threadIdx.x == 0) spec[blockIdx.x] = 0.5 * scale * ((wsum[0] + wsum[1]) + (wsum[2] + wsum[3]));
 }
 
 int ilog2(int n) {
@@ -174,12 +185,8 @@ int run_spectrum(int nx, int ny, const double* ux, const double* uy, void* ws, s
   hipLaunchKernelGGL(k_fft_rows<false>, dim3(nx), dim3(kFftThreads), 0, s, nullptr, nullptr, b, ny, ilog2(ny),
                      tw, nmax);
   LBM_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_zero_f64, dim3((ns + 255) / 256), dim3(256), 0, s, spec, ns);
-  LBM_HIP(hipGetLastError());
   const double inv = 1.0 / (static_cast<double>(nx) * ny);
-  const size_t total = static_cast<size_t>(nx) * ny;
-  const int g = static_cast<int>(std::min<size_t>(1024, (total + 255) / 256));
-  hipLaunchKernelGGL(k_shells, dim3(g), dim3(256), ns * sizeof(double), s, b, nx, ny, ns, inv * inv, spec);
+  hipLaunchKernelGGL(k_shells, dim3(ns), dim3(256), 0, s, b, nx, ny, inv * inv, spec);
   LBM_HIP(hipGetLastError());
   LBM_HIP(hipMemcpyAsync(spectrum, spec, ns * sizeof(double), hipMemcpyDeviceToHost, s));
   LBM_HIP(hipStreamSynchronize(s));

@@ -372,13 +372,15 @@ def test_balance_pooled_over_configurations(gpu_lib):
 @pytest.mark.parametrize("ny,nx", [(64, 64), (32, 128), (256, 256)])
 def test_energy_spectrum_fields(gpu_lib, ny, nx):
     """Shell-summed spectrum of random-phase fields against the oracle's FFT spectrum:
-    every shell within 1e-12 of the largest shell; the sum is half the mean |u|^2."""
+    every shell within 1e-12 of the largest shell; the sum is half the mean |u|^2; a second
+    call gives the same bits (fixed-order shell sums)."""
     from paper_1809_06735_amd import energy_spectrum
     g = np.random.default_rng(nx + ny)
     ux = g.standard_normal((ny, nx)) * 0.01
     uy = g.standard_normal((ny, nx)) * 0.01
     ns = int(np.floor(np.hypot(nx // 2, ny // 2) + 0.5)) + 3
     got = energy_spectrum(ux, uy, ns)
+    assert np.array_equal(got, energy_spectrum(ux, uy, ns))
     want = ref.energy_spectrum(ux, uy, ns).numpy()
     err = np.abs(got - want).max() / want.max()
     say(f"spectrum {ny}x{nx}: rel err {err:.1e}")

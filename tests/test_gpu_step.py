@@ -293,6 +293,50 @@ def test_divergence_is_reported(gpu_lib):
     assert ei.value.code == -4
 
 
+def _oracle_divergence_step(rho, ux, uy, tau, limit):
+    """First step after which the oracle's moments hold a non-finite value or rho <= 0 (the
+    library's divergence criterion), or None within `limit` steps."""
+    f = ref.init_populations(rho, ux, uy)
+    for t in range(1, limit + 1):
+        f = ref.step(f, tau)
+        r, vx, vy = ref.moments(f)
+        if not (torch.isfinite(r).all() and torch.isfinite(vx).all() and torch.isfinite(vy).all()):
+            return t
+        if float(r.min()) <= 0.0:
+            return t
+    return None
+
+
+@pytest.mark.parametrize("seed,mach,tau", [(0, 0.5, 0.5001), (1, 0.6, 0.5001), (2, 0.5, 0.501)])
+def test_divergence_window_matches_the_oracle(gpu_lib, seed, mach, tau):
+    """An unstable run (32^2 at Mach 0.5-0.6 and tau near 1/2, FP64): the oracle's first
+    diverged step t* lies in the window the library flags.  The library is finite at t* - 5
+    and reports LBM_E_DIVERGED (-4) at t* + 5, with the step in its message; a state saved at
+    t* - 5 restores a finite run (rollback to the last checkpoint)."""
+    from paper_1809_06735_amd import LBMError
+    n = 32
+    _, ux, uy = inp.spectrum_velocity(n, seed=seed, max_mach=mach)
+    rho = np.ones((n, n))
+    ts = _oracle_divergence_step(rho, ux, uy, tau, 1000)
+    say(f"divergence seed {seed} Ma {mach} tau {tau}: oracle diverges at step {ts}")
+    assert ts is not None and ts > 10
+    sim = Sim(rho, ux, uy, tau, dtype="f64")
+    sim.step(ts - 5)
+    r0, vx0, vy0, sc = sim.moments()
+    assert sc["nonfinite"] == 0 and sc["min_rho"] > 0
+    saved = sim.save()
+    sim.step(10)
+    with pytest.raises(LBMError) as ei:
+        sim.moments()
+    assert ei.value.code == -4
+    assert str(ts + 5) in str(ei.value)
+    sim.load(saved)
+    r1, vx1, vy1, sc1 = sim.moments()
+    assert sc1["nonfinite"] == 0 and sc1["time"] == ts - 5
+    for a, b in zip((r0, vx0, vy0), (r1, vx1, vy1)):
+        assert torch.equal(a, b)
+
+
 def test_state_errors(gpu_lib):
     from paper_1809_06735_amd import LBMError
     rho, ux, uy = inp.taylor_green(32, 0.01)
