@@ -30,6 +30,11 @@ using namespace step_detail;
 
 // below this max_l |delta_l| / f_l the site counts as at equilibrium: alpha = 2
 constexpr double kNearEq = 1e-8;
+// below this max_l |delta_l| / f_l the gain is evaluated as its power series in
+// x = delta / f, truncated after x^kSeriesN: for a <= 3 the first omitted term
+// is below (3 * 0.015)^(kSeriesN + 1) / kSeriesN ~ 1e-17 of the leading one
+constexpr double kSeriesMax = 0.015;
+constexpr int kSeriesN = 12;
 // workgroups of at most this many threads, so the FP64 site state stays in registers
 constexpr int kEntropicMaxThreads = 256;
 
@@ -81,6 +86,50 @@ __device__ __forceinline__ double entropy_gain(const EntropicSite& s, double c1,
   return g - a * c1;
 }
 
+// The gain as a power series: with t = a x, (1 + t) log1p(t) - t =
+// sum_{n>=2} (-1)^n t^n / (n (n - 1)) and x log1p(x) = sum_{n>=2} (-1)^n x^n / (n - 1), so
+//   g(a) = P(a) - a Q,  P(a) = sum_n (-1)^n S_n a^n / (n (n - 1)),  Q = sum_n (-1)^n S_n / (n - 1),
+// S_n = sum_l f_l x_l^n; g'(a) = P'(a) - Q.  cp[n] = (-1)^n S_n / (n (n - 1)).
+struct GainSeries {
+  double cp[kSeriesN + 1];
+  double q;
+  __device__ __forceinline__ double eval(double a, double& dg) const {
+    double p = cp[kSeriesN], dp = kSeriesN * cp[kSeriesN];
+#pragma unroll
+    for (int n = kSeriesN - 1; n >= 2; --n) {
+      p = p * a + cp[n];
+      dp = dp * a + n * cp[n];
+    }
+    // p = sum cp[n] a^(n-2), dp = sum n cp[n] a^(n-2)
+    const double a2 = a * a;
+    dg = dp * a - q;
+    return p * a2 - a * q;
+  }
+};
+
+__device__ __forceinline__ void gain_series(const EntropicSite& s, GainSeries& gs) {
+  double sn[kSeriesN + 1];
+#pragma unroll
+  for (int n = 0; n <= kSeriesN; ++n) sn[n] = 0.0;
+#pragma unroll
+  for (int l = 0; l < 9; ++l) {
+    const double x = s.x[l];
+    double p = s.f[l] * x * x;
+#pragma unroll
+    for (int n = 2; n <= kSeriesN; ++n) {
+      sn[n] += p;
+      p *= x;
+    }
+  }
+  gs.q = 0.0;
+#pragma unroll
+  for (int n = 2; n <= kSeriesN; ++n) {
+    const double sg = (n & 1) ? -sn[n] : sn[n];
+    gs.cp[n] = sg / (n * (n - 1.0));
+    gs.q += sg / (n - 1.0);
+  }
+}
+
 __device__ double entropic_alpha(const EntropicSite& s) {
   double mr = 0.0, xmin = 0.0;
   double s2 = 0.0, s3 = 0.0, s4 = 0.0;  // sum f x^k: the expansion of the gain in x = delta / f
@@ -96,20 +145,29 @@ __device__ double entropic_alpha(const EntropicSite& s) {
   }
   if (mr < kNearEq) return 2.0;
   const double amax = xmin < 0.0 ? -1.0 / xmin : 1e300;  // every f + a delta > 0 below it
+  // close to equilibrium the series replaces the logarithms, for a <= 3
+  const bool series = mr < kSeriesMax;
+  GainSeries gs;
   double c1 = 0.0;
+  if (series) {
+    gain_series(s, gs);
+  } else {
 #pragma unroll
-  for (int l = 0; l < 9; ++l) c1 += s.f[l] * s.x[l] * log1p(s.x[l]);
+    for (int l = 0; l < 9; ++l) c1 += s.f[l] * s.x[l] * log1p(s.x[l]);
+  }
+  auto gain = [&](double a, double& dg) { return series ? gs.eval(a, dg) : entropy_gain(s, c1, a, dg); };
   double lo = 1.0, hi = amax < 1e300 ? amax * (1.0 - 1e-12) : 1e6;
+  if (series) hi = fmin(hi, 3.0);  // the root lies within 2 +- O(mr); the series holds up to 3
   // start from the root of the gain expanded to fourth order around a = 2:
   // g(2 + e) / (2 + e) = e S2 / 2 - S3 / 6 + S4 / 3 + ... = 0
   // (the expansion is only trusted close to 2: far from equilibrium start at 2)
   double a = 2.0 + (s3 - 2.0 * s4) / (3.0 * s2);
   if (!(fabs(a - 2.0) < 0.25 && a > lo && a < hi)) a = 2.0 < hi ? 2.0 : 0.5 * (lo + hi);
   double dg;
-  double ga = entropy_gain(s, c1, a, dg);
+  double ga = gain(a, dg);
   if (ga < 0.0) {
     double dgh;
-    if (entropy_gain(s, c1, hi, dgh) < 0.0) return hi;  // no root below the positivity limit
+    if (gain(hi, dgh) < 0.0) return hi;  // no root below the positivity limit
     lo = a;
   } else {
     hi = a;
@@ -122,7 +180,7 @@ __device__ double entropic_alpha(const EntropicSite& s) {
     // ~1e-20 of the root; bisection steps run until the bracket itself is that small
     if (newton ? fabs(an - a) <= 1e-10 * a : hi - lo <= 1e-15 * hi) return an;
     a = an;
-    ga = entropy_gain(s, c1, a, dg);
+    ga = gain(a, dg);
     if (ga < 0.0)
       lo = a;
     else
