@@ -68,6 +68,41 @@ def test_entropic_run_parity(gpu_lib, dtype, tol):
     assert float((nu.cpu() - ref.effective_viscosity(wa, tau0)).abs().max()) < atol
 
 
+@pytest.mark.parametrize("dtype,tol", [("f64", TOL64), ("f32", TOL32)])
+def test_entropic_near_equilibrium_series_path(gpu_lib, dtype, tol):
+    """A mild field (Mach 0.01, uniform density, 44 x 40, tau0 = 0.52, 30 steps) where every
+    site has max |f^eq - f| / f below 0.015, so the library evaluates the entropy gain by
+    its power series: moments, alpha and nu_eff against the oracle's bisection on the
+    logarithmic gain, with alpha visibly away from 2."""
+    ny, nx, tau0, steps = 44, 40, 0.52, 30
+    _, ux, uy = inp.spectrum_velocity(max(nx, ny), seed=13, max_mach=0.01)
+    ux, uy = ux[:ny, :nx].copy(), uy[:ny, :nx].copy()
+    rho = np.ones((ny, nx))
+    sim = Sim(rho, ux, uy, tau0, dtype=dtype, collision="entropic")
+    sim.step(steps)
+    f = ref.entropic_run(ref.init_populations(rho, ux, uy), steps, tau0)
+    r0 = ref.density(f)
+    jx, jy = ref.momentum(f)
+    feq = ref.entropic_equilibrium(r0, jx / r0, jy / r0)
+    mr = float(((feq - f).abs() / f).amax())
+    say(f"series path {dtype}: max |f^eq - f| / f = {mr:.2e}")
+    assert mr < 0.015
+    r, vx, vy, _ = sim.moments()
+    want = ref.moments(f)
+    for name, g, w in zip(("rho", "ux", "uy"), (r, vx, vy), want):
+        e = moment_err(name, g, w, dtype)
+        tol_f = moment_tol(name, want, dtype, steps, tol)
+        assert e < tol_f, (name, e, tol_f)
+    a, nu = sim.relaxation()
+    wa = _oracle_alpha(f, tau0)
+    say(f"series path {dtype}: alpha range {float(wa.min()):.9f} .. {float(wa.max()):.9f}, "
+        f"max |alpha - oracle| {float((a.cpu() - wa).abs().max()):.1e}")
+    assert float((wa - 2).abs().max()) > 1e-6
+    atol = 1e-9 if dtype == "f64" else 1e-4
+    assert float((a.cpu() - wa).abs().max()) < atol
+    assert float((nu.cpu() - ref.effective_viscosity(wa, tau0)).abs().max()) < atol
+
+
 def test_entropic_h_theorem_and_bgk_relaxation(gpu_lib):
     """The lattice total of H (Eq. 6) never increases over entropic steps (checked on the
     library's own checkpointed populations); a BGK handle reports alpha = 2 and nu."""
