@@ -673,6 +673,11 @@ __global__ void __launch_bounds__(kRedThreads) k_field_means(const double* __res
   }
 }
 
+// Table rows of one field are sat_ld(nx) = nx + 1 doubles apart.  Rows padded to
+// 128-byte multiples (nx + 1 rounded up to 16) made the balance 2 % slower at
+// 4096^2: the odd stride spreads a column's rows over more memory channels.
+__host__ __device__ __forceinline__ int sat_ld(int nx) { return nx + 1; }
+
 // ---- summed-area tables ------------------------------------------------------------------
 // Row pass: P[f][y+1][x+1] = sum_{x' <= x} (g[f][y][x'] - mean_f); P[f][0][*] = P[f][*][0] = 0.
 // One workgroup per (row, field); the row is consumed in coalesced segments of
@@ -686,7 +691,7 @@ __global__ void __launch_bounds__(256) k_sat_rows(const double* __restrict__ g,
   const int f = blockIdx.y;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const size_t plane = static_cast<size_t>(nx) * ny;
-  const size_t s = static_cast<size_t>(nx + 1);
+  const size_t s = static_cast<size_t>(sat_ld(nx));
   const double mean = means[f];
   const double* row = g + f * plane + static_cast<size_t>(y) * nx;
   double* out = sat + (static_cast<size_t>(y + 1) * nf + f) * s;
@@ -728,8 +733,8 @@ __global__ void __launch_bounds__(64 * kColG) k_sat_cols(double* sat, int nx, in
   const int c = blockIdx.x * 64 + threadIdx.x;
   const int g = threadIdx.y;
   const int f = blockIdx.y;
-  double* P = sat + f * static_cast<size_t>(nx + 1);
-  const size_t s = static_cast<size_t>(nx + 1) * nf;  // between rows of one field
+  double* P = sat + f * static_cast<size_t>(sat_ld(nx));
+  const size_t s = static_cast<size_t>(sat_ld(nx)) * nf;  // between rows of one field
   const bool active = c <= nx;
   double carry = 0.0;  // this column's sum over the rows above the chunk
   for (int y0 = 1; y0 <= ny; y0 += kColG * kColR) {
@@ -766,15 +771,16 @@ __global__ void __launch_bounds__(64 * kColG) k_sat_cols(double* sat, int nx, in
 
 // ---- windows -----------------------------------------------------------------------------------
 struct SatView {
-  const double* P;  // [ny+1][nf][nx+1]
+  const double* P;  // [ny+1][nf][ld], entries x = 0 .. nx of each row used
   const double* means;
   int nx, ny;
   int nf;           // fields per table row
+  int ld;           // sat_ld(nx): doubles between consecutive fields' rows
   // Q(y, x) for 0 <= y < 2 ny, 0 <= x < 2 nx: the periodic continuation of the
   // prefix table through its totals.
   __device__ __forceinline__ double Q(int f, int y, int x) const {
-    const size_t s = static_cast<size_t>(nx + 1) * nf;  // between rows of one field
-    const double* p = P + f * static_cast<size_t>(nx + 1);
+    const size_t s = static_cast<size_t>(ld) * nf;  // between rows of one field
+    const double* p = P + f * static_cast<size_t>(ld);
     const int qy = y > ny ? 1 : 0;
     const int qx = x > nx ? 1 : 0;
     const int ym = y - qy * ny;
@@ -1138,8 +1144,8 @@ template <int F0, int NF>
 __device__ __forceinline__ void stride_windows(const SatView& v, int L, int x0, int y0, int S,
                                                double* maps, SumStat& r, const LdsHist* h) {
   const int nx = v.nx, ny = v.ny;
-  const unsigned s = static_cast<unsigned>(nx + 1) * v.nf;  // between rows of one field
-  const unsigned fs = static_cast<unsigned>(nx + 1);        // between fields of one row
+  const unsigned s = static_cast<unsigned>(v.ld) * v.nf;  // between rows of one field
+  const unsigned fs = static_cast<unsigned>(v.ld);        // between fields of one row
   const double inv = 1.0 / (double(L) * double(L));
   const bool qx = x0 + L > nx;
   const unsigned xm = qx ? x0 + L - nx : x0 + L;
@@ -1225,7 +1231,10 @@ __device__ __forceinline__ void stride_windows(const SatView& v, int L, int x0, 
 // window is the top row of the next, so each table row is loaded once per side
 // (plus one row per segment) and reused from registers.  Workgroups are
 // numbered so that neighbouring strips share an XCD (and its L2, which serves
-// the columns x0 + L past the strip).
+// the columns x0 + L past the strip), and the three field groups alternate
+// (logical index = 3 x block + group): each XCD's contiguous range holds equal
+// shares of the six-field groups and of the one-field group, so no XCD runs
+// out of work while another still walks its six-field windows.
 template <bool HIST>
 __global__ void __launch_bounds__(256) k_windows_strided(SatView v, int L, int strips, int S, int nblocks,
                                                          int per_xcd, double* maps, double* partials,
@@ -1234,8 +1243,8 @@ __global__ void __launch_bounds__(256) k_windows_strided(SatView v, int L, int s
   const int b = blockIdx.x;
   const int logical = (b & 7) * per_xcd + (b >> 3);
   if (logical >= 3 * nblocks) return;  // uniform over the workgroup
-  const int grp = logical / nblocks;
-  const int wb = logical - grp * nblocks;
+  const int grp = logical % 3;
+  const int wb = logical / 3;
   const int strip = wb % strips;
   const int rest = wb / strips;
   const int j = rest % L, g = rest / L;
@@ -1277,8 +1286,8 @@ template <int F0, int NF>
 __device__ __forceinline__ void stride_windows2(const SatView& v, int L, int x0, int y0, int S,
                                                 SumStat& r1, SumStat& r2) {
   const int nx = v.nx, ny = v.ny;
-  const unsigned s = static_cast<unsigned>(nx + 1) * v.nf;
-  const unsigned fs = static_cast<unsigned>(nx + 1);
+  const unsigned s = static_cast<unsigned>(v.ld) * v.nf;
+  const unsigned fs = static_cast<unsigned>(v.ld);
   const int L2 = 2 * L;
   const double inv1 = 1.0 / (double(L) * double(L));
   const double inv2 = 1.0 / (double(L2) * double(L2));
@@ -1396,9 +1405,9 @@ __device__ __forceinline__ double buf_load_f64(__amdgpu_buffer_rsrc_t r, unsigne
 template <int F0, int NF>
 __device__ __forceinline__ void stride_windows2_inner(const SatView& v, int L, int x0, int y0, int nwin,
                                                       SumStat& r1, SumStat& r2) {
-  const unsigned fsb = static_cast<unsigned>(v.nx + 1) * 8u;  // bytes between fields of one row
-  const double* base = v.P + static_cast<size_t>(F0) * (v.nx + 1);
-  const size_t rs = static_cast<size_t>(v.nx + 1) * v.nf;     // doubles between table rows
+  const unsigned fsb = static_cast<unsigned>(v.ld) * 8u;  // bytes between fields of one row
+  const double* base = v.P + static_cast<size_t>(F0) * v.ld;
+  const size_t rs = static_cast<size_t>(v.ld) * v.nf;     // doubles between table rows
   const unsigned o0 = static_cast<unsigned>(x0) * 8u;
   const unsigned o1 = static_cast<unsigned>(x0 + L) * 8u;
   const unsigned o2 = static_cast<unsigned>(x0 + 2 * L) * 8u;
@@ -1474,8 +1483,8 @@ __device__ __forceinline__ PairWork pair_work(const SatView& v, int L, int strip
   PairWork w{};
   w.live = logical < 3 * nblocks;
   if (!w.live) return w;
-  w.grp = logical / nblocks;
-  const int wb = logical - w.grp * nblocks;
+  w.grp = logical % 3;  // groups alternate, as in k_windows_strided
+  const int wb = logical / 3;
   w.strip = wb % strips;
   const int rest = wb / strips;
   const int j = rest % L, g = rest / L;
@@ -1617,7 +1626,7 @@ int stat_blocks(size_t count) {
 }  // namespace
 
 int balance_grid_ok(int nx, int ny) {
-  const unsigned long long elems = static_cast<unsigned long long>(NT) * (static_cast<unsigned long long>(nx) + 1) *
+  const unsigned long long elems = static_cast<unsigned long long>(NT) * static_cast<unsigned long long>(sat_ld(nx)) *
                                    (static_cast<unsigned long long>(ny) + 1);
   if (elems >= (1ull << 32))
     return fail(LBM_E_UNSUPPORTED,
@@ -1635,7 +1644,7 @@ size_t balance_ws_bytes(int nx, int ny) {
 
 BalanceWs carve_balance(Carver& c, int nx, int ny) {
   const size_t plane = static_cast<size_t>(nx) * ny;
-  const size_t splane = static_cast<size_t>(nx + 1) * (ny + 1);
+  const size_t splane = static_cast<size_t>(sat_ld(nx)) * (ny + 1);
   BalanceWs w;
   w.terms = c.take<double>(NT * plane);
   w.aux = c.take<double>(NAUX * plane);
@@ -1753,7 +1762,7 @@ __global__ void __launch_bounds__(256) k_box_map(SatView v, int f, int L, int of
 
 int box_map(const double* sat, const double* means, int nf, int f, int L, int off, double scale,
             double* out, int nx, int ny, hipStream_t s) {
-  SatView v{sat, means, nx, ny, nf};
+  SatView v{sat, means, nx, ny, nf, sat_ld(nx)};
   const size_t plane = static_cast<size_t>(nx) * ny;
   int g = static_cast<int>((plane + 255) / 256);
   if (g > 4096) g = 4096;
@@ -1965,7 +1974,7 @@ int run_balance_async(const lbm_balance_input& in, const BalanceWs& ws, const in
   hipStream_t s = static_cast<hipStream_t>(in.stream);
   if (int rc = balance_terms(in, ws)) return rc;
   if (int rc = sat_build(ws.terms, NT, ws.means, ws.sat, in.nx, in.ny, s)) return rc;
-  SatView v{ws.sat, ws.means, in.nx, in.ny, NT};
+  SatView v{ws.sat, ws.means, in.nx, in.ny, NT, sat_ld(in.nx)};
   if (int rc = corner_stats(v, ws, sizes, nsizes, nullptr, false, 0, ws.hist, 0, 0, s)) return rc;
   LBM_HIP(hipMemcpyAsync(host_stats, ws.pool, static_cast<size_t>(nsizes) * kStatVals * sizeof(double),
                          hipMemcpyDeviceToHost, s));
@@ -2005,7 +2014,7 @@ int run_balance(const lbm_balance_input& in, const BalanceWs& ws, const int32_t*
     }
   }
 
-  SatView v{ws.sat, ws.means, nx, ny, NT};
+  SatView v{ws.sat, ws.means, nx, ny, NT, sat_ld(nx)};
   if (out)
     if (int rc = corner_stats(v, ws, sizes, nsizes, dmaps, hist, ne, hall, hslot, acc, s)) return rc;
   if (sampled) {
