@@ -1,5 +1,5 @@
-"""FP64 CPU oracle for the three-dimensional extension: D2Q9's counterpart D3Q19 with
-the LBGK update and Guo's forcing term, and the sub-volume kinetic-energy and enstrophy
+"""FP64 CPU oracle for the three-dimensional extension: D2Q9's counterparts D3Q19 and
+D3Q27 with the LBGK update and Guo's forcing term, and the sub-volume kinetic-energy and enstrophy
 balances in 3D, where the enstrophy equation gains the vortex-stretching term.
 
 TEST INFRASTRUCTURE ONLY: only the tests, the smoke check and the CPU-baseline leg of
@@ -10,10 +10,12 @@ form (Eqs. 8-11, written for any dimension; the paper's 2D runs drop the stretch
 term, and Sec. 2 notes that 3D keeps it), the time and space derivatives of Sec. 3
 (Eqs. 17-18) and the balancing errors of Eqs. 12-13 over cubic sub-volumes.
 
-Arrays are indexed [z, y, x]; populations are [19, nz, ny, nx].  Lattice units.
+Arrays are indexed [z, y, x]; populations are [Q, nz, ny, nx], Q = 19 or 27 (the
+lattice of a population array is read off its first extent).  Lattice units.
 
 Readings (also in the design notes): D3Q19 with weights 1/3, 1/18, 1/36 and
-c_s^2 = 1/3; Guo's force term with the half-force velocity (as the 2D hot path); the
+c_s^2 = 1/3; D3Q27, the product of three D1Q3 lattices, with weights 8/27, 2/27, 1/54,
+1/216 and the same c_s^2 and second-order equilibrium; Guo's force term with the half-force velocity (as the 2D hot path); the
 vorticity omega = curl u; Eq. 11's terms in 3D: -d_j(Omega u_j), -Omega d_j u_j,
 omega . curl(F / rho), H . curl(omega), div(H x omega) (H_i = d_j sigma_ij / rho) and the
 stretching term omega_i omega_j d_j u_i; cubes L^3 at every corner with periodic wrap;
@@ -43,14 +45,30 @@ W = (1.0 / 3.0,) + (1.0 / 18.0,) * 6 + (1.0 / 36.0,) * 12
 CS2 = 1.0 / 3.0
 Q = 19
 
+# ---------------------------------------------------------------------------
+# D3Q27 lattice: every c in {-1, 0, 1}^3, weight prod_a (2/3 for c_a = 0, 1/6 otherwise)
+# ---------------------------------------------------------------------------
+#: rest, the 6 axis and 12 edge velocities in the D3Q19 order, then the 8 corners in
+#: opposite pairs
+C27 = C + ((1, 1, 1), (-1, -1, -1), (1, 1, -1), (-1, -1, 1),
+           (1, -1, 1), (-1, 1, -1), (-1, 1, 1), (1, -1, -1))
+W27 = (8.0 / 27.0,) + (2.0 / 27.0,) * 6 + (1.0 / 54.0,) * 12 + (1.0 / 216.0,) * 8
+LATTICES = {19: (C, W), 27: (C27, W27)}
+
+
+def lattice(q):
+    """(velocities, weights) of the lattice with q populations (19 or 27)."""
+    return LATTICES[q]
+
 t64 = ref.t64
 
 
-def equilibrium(rho, ux, uy, uz):
-    """Eq. 2 on D3Q19: t_l rho (1 + 3 c.u + 9/2 (c.u)^2 - 3/2 |u|^2)."""
+def equilibrium(rho, ux, uy, uz, q=19):
+    """Eq. 2 on D3Q19 (q = 19) or D3Q27 (q = 27): t_l rho (1 + 3 c.u + 9/2 (c.u)^2 - 3/2 |u|^2)."""
+    cs, ws = lattice(q)
     usq = ux * ux + uy * uy + uz * uz
     out = []
-    for (cx, cy, cz), w in zip(C, W):
+    for (cx, cy, cz), w in zip(cs, ws):
         cu = cx * ux + cy * uy + cz * uz
         out.append(w * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq))
     return torch.stack(out)
@@ -61,9 +79,10 @@ def density(f):
 
 
 def momentum(f):
-    jx = sum(cx * f[l] for l, (cx, _, _) in enumerate(C))
-    jy = sum(cy * f[l] for l, (_, cy, _) in enumerate(C))
-    jz = sum(cz * f[l] for l, (_, _, cz) in enumerate(C))
+    cs, _ = lattice(f.shape[0])
+    jx = sum(cx * f[l] for l, (cx, _, _) in enumerate(cs))
+    jy = sum(cy * f[l] for l, (_, cy, _) in enumerate(cs))
+    jz = sum(cz * f[l] for l, (_, _, cz) in enumerate(cs))
     return jx, jy, jz
 
 
@@ -76,10 +95,11 @@ def macroscopic(f, fx=None, fy=None, fz=None):
     return rho, jx / rho, jy / rho, jz / rho
 
 
-def guo_source(ux, uy, uz, fx, fy, fz, tau):
+def guo_source(ux, uy, uz, fx, fy, fz, tau, q=19):
     """Guo's forcing term (1 - 1/(2 tau)) t_l [3 (c - u) + 9 (c.u) c] . F."""
+    cs, ws = lattice(q)
     out = []
-    for (cx, cy, cz), w in zip(C, W):
+    for (cx, cy, cz), w in zip(cs, ws):
         cu = cx * ux + cy * uy + cz * uz
         gx = 3.0 * (cx - ux) + 9.0 * cu * cx
         gy = 3.0 * (cy - uy) + 9.0 * cu * cy
@@ -90,25 +110,27 @@ def guo_source(ux, uy, uz, fx, fy, fz, tau):
 
 def collide(f, tau, fx=None, fy=None, fz=None):
     """Eq. 1's collision: f - (f - f^eq) / tau (+ Guo's term)."""
+    q = f.shape[0]
     rho, ux, uy, uz = macroscopic(f, fx, fy, fz)
-    post = f - (f - equilibrium(rho, ux, uy, uz)) / tau
+    post = f - (f - equilibrium(rho, ux, uy, uz, q)) / tau
     if fx is not None:
-        post = post + guo_source(ux, uy, uz, fx, fy, fz, tau)
+        post = post + guo_source(ux, uy, uz, fx, fy, fz, tau, q)
     return post
 
 
 def stream(fpost):
     """f_l(x + c_l, t + 1) = f*_l(x, t), periodic."""
+    cs, _ = lattice(fpost.shape[0])
     return torch.stack([torch.roll(fpost[l], shifts=(cz, cy, cx), dims=(0, 1, 2))
-                        for l, (cx, cy, cz) in enumerate(C)])
+                        for l, (cx, cy, cz) in enumerate(cs)])
 
 
 def step(f, tau, fx=None, fy=None, fz=None):
     return stream(collide(f, tau, fx, fy, fz))
 
 
-def init_populations(rho, ux, uy, uz):
-    return equilibrium(t64(rho), t64(ux), t64(uy), t64(uz))
+def init_populations(rho, ux, uy, uz, q=19):
+    return equilibrium(t64(rho), t64(ux), t64(uy), t64(uz), q)
 
 
 def run(f, nsteps, tau, fx=None, fy=None, fz=None):

@@ -1,7 +1,9 @@
 """Pins of the 3D oracle (oracle/ref3d.py) against what the lattice, the mathematics and the
-2D oracle fix: D3Q19 isotropy, equilibrium and forcing moments, the Taylor-Green decay rate
-(Eq. 5), the z-invariant limit equal to the 2D balance, the vortex-stretching term and the
-viscous identities by spectral derivatives, cube means by brute force."""
+2D oracle fix: D3Q19 and D3Q27 isotropy, equilibrium and forcing moments, the Taylor-Green
+decay rate (Eq. 5), the z-invariant limit equal to the 2D balance and (D3Q27, a product
+lattice) to the 2D run, the one-dimensional limit equal to a D1Q3 run, the vortex-stretching
+term and the viscous identities by spectral derivatives, cube means by brute force."""
+import itertools
 import math
 
 import numpy as np
@@ -55,24 +57,45 @@ def test_d3q19_isotropy():
     assert ref3d.C[0] == (0, 0, 0) and all(tuple(-v for v in ref3d.C[l]) in ref3d.C for l in range(19))
 
 
-def test_equilibrium_and_guo_moments():
+def test_d3q27_isotropy_and_product_weights():
+    """D3Q27 is every c in {-1, 0, 1}^3 once, its weights the products of the D1Q3 weights
+    (2/3 at rest, 1/6 moving), and it is isotropic to fourth order with c_s^2 = 1/3."""
+    c = np.array(ref3d.C27, dtype=float)
+    w = np.array(ref3d.W27)
+    assert sorted(map(tuple, c.astype(int))) == sorted(itertools.product((-1, 0, 1), repeat=3))
+    w1 = {0: 2.0 / 3.0, 1: 1.0 / 6.0, -1: 1.0 / 6.0}
+    for cl, wl in zip(ref3d.C27, ref3d.W27):
+        assert wl == pytest.approx(w1[cl[0]] * w1[cl[1]] * w1[cl[2]], rel=1e-15)
+    assert ref3d.C27[:19] == ref3d.C
+    assert all(ref3d.C27[l + 1] == tuple(-v for v in ref3d.C27[l]) for l in range(1, 27, 2))
+    assert w.sum() == pytest.approx(1.0, rel=1e-15)
+    assert np.abs(np.einsum("l,la,lb->ab", w, c, c) - np.eye(3) / 3).max() < 1e-15
+    m4 = np.einsum("l,la,lb,lc,ld->abcd", w, c, c, c, c)
+    d = np.eye(3)
+    want = (np.einsum("ab,cd->abcd", d, d) + np.einsum("ac,bd->abcd", d, d) + np.einsum("ad,bc->abcd", d, d)) / 9
+    assert np.abs(m4 - want).max() < 1e-15
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_equilibrium_and_guo_moments(q):
     g = torch.Generator().manual_seed(1)
     shp = (4, 5, 6)
     rho = 1 + 0.05 * torch.randn(*shp, generator=g, dtype=D)
     u = [0.05 * torch.randn(*shp, generator=g, dtype=D) for _ in range(3)]
-    f = ref3d.equilibrium(rho, *u)
+    f = ref3d.equilibrium(rho, *u, q=q)
+    assert f.shape[0] == q
     assert float((f.sum(0) - rho).abs().max()) < 1e-15
     for j, ui in zip(ref3d.momentum(f), u):
         assert float((j - rho * ui).abs().max()) < 1e-15
-    c = ref3d.C
+    c = ref3d.lattice(q)[0]
     for a in range(3):
         for b in range(3):
-            p = sum(c[l][a] * c[l][b] * f[l] for l in range(19))
+            p = sum(c[l][a] * c[l][b] * f[l] for l in range(q))
             want = rho * u[a] * u[b] + (rho / 3 if a == b else 0)
             assert float((p - want).abs().max()) < 1e-15
     # Guo's term: no mass, momentum change F per collision
     F = [1e-4 * torch.randn(*shp, generator=g, dtype=D) for _ in range(3)]
-    fneq = f + 1e-3 * torch.randn(19, *shp, generator=g, dtype=D)
+    fneq = f + 1e-3 * torch.randn(q, *shp, generator=g, dtype=D)
     post = ref3d.collide(fneq, 0.7, *F)
     dlt = post - fneq
     assert float(dlt.sum(0).abs().max()) < 1e-15
@@ -80,16 +103,17 @@ def test_equilibrium_and_guo_moments():
         assert float((j - Fi).abs().max()) < 1e-15
 
 
-def test_taylor_green_3d_decay_rate():
+@pytest.mark.parametrize("q", [19, 27])
+def test_taylor_green_3d_decay_rate(q):
     """u = u0 (sin kx cos ky cos kz, -cos kx sin ky cos kz, 0) decays like exp(-3 nu k^2 t) in
-    the linear regime (Eq. 5: nu = (tau - 1/2) / 3)."""
+    the linear regime (Eq. 5: nu = (tau - 1/2) / 3), on both lattices."""
     n, tau, u0 = 32, 0.8, 1e-5
     k = 2 * np.pi / n
     z, y, x = np.meshgrid(*[np.arange(n)] * 3, indexing="ij")
     ux = u0 * np.sin(k * x) * np.cos(k * y) * np.cos(k * z)
     uy = -u0 * np.cos(k * x) * np.sin(k * y) * np.cos(k * z)
     uz = np.zeros_like(ux)
-    f = ref3d.init_populations(np.ones_like(ux), ux, uy, uz)
+    f = ref3d.init_populations(np.ones_like(ux), ux, uy, uz, q)
     f = ref3d.run(f, 20, tau)  # let the initial non-equilibrium adjust
     a0 = float(ref3d.macroscopic(f)[1].abs().max())
     steps = 100
@@ -98,6 +122,65 @@ def test_taylor_green_3d_decay_rate():
     nu = (tau - 0.5) / 3
     rate = -math.log(a1 / a0) / steps
     assert rate == pytest.approx(3 * nu * k * k, rel=0.01)
+
+
+def test_d3q27_z_invariant_run_equals_the_2d_run():
+    """D3Q27 is D2Q9 times D1Q3: for a field uniform in z with u_z = F_z = 0, the z-sums of
+    the populations with equal (c_x, c_y) evolve exactly as D2Q9 (the equilibrium and Guo's
+    term sum over c_z to the D2Q9 ones), so the forced 3D run's moments equal the 2D
+    oracle's on every slice."""
+    n, nz, steps, tau = 12, 4, 25, 0.6
+    rng = np.random.default_rng(8)
+    y, x = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    rho = 1 + 0.01 * np.cos(2 * np.pi * (x + y) / n + 0.3)
+    ux = 0.04 * np.sin(2 * np.pi * (2 * x - y) / n + rng.uniform(0, 6))
+    uy = 0.03 * np.cos(2 * np.pi * (x + 3 * y) / n + rng.uniform(0, 6))
+    fx = 1e-4 * np.sin(2 * np.pi * y / n)
+    fy = -1e-4 * np.cos(2 * np.pi * 2 * x / n)
+    f2 = ref.run(ref.init_populations(rho, ux, uy), steps, tau, ref.t64(fx), ref.t64(fy))
+    want = ref.moments(f2, ref.t64(fx), ref.t64(fy))
+    ext = lambda a: torch.as_tensor(np.broadcast_to(a, (nz, n, n)).copy(), dtype=D)  # noqa: E731
+    f3 = ref3d.init_populations(ext(rho), ext(ux), ext(uy), ext(0 * rho), q=27)
+    F3 = (ext(fx), ext(fy), ext(0 * rho))
+    f3 = ref3d.run(f3, steps, tau, *F3)
+    got = ref3d.macroscopic(f3, *F3)
+    for a, b in zip((got[0], got[1], got[2]), want):
+        for zi in range(nz):
+            assert float((a[zi] - b).abs().max()) < 1e-14
+    assert float(got[3].abs().max()) < 1e-17
+
+
+def test_d3q27_one_dimensional_run_equals_d1q3():
+    """A field that varies along z only: the sums of the D3Q27 populations with equal c_z
+    evolve as the D1Q3 lattice (weights 2/3, 1/6, 1/6, c_s^2 = 1/3), written here directly:
+    BGK towards rho w (1 + 3 c u + 9/2 (c u)^2 - 3/2 u^2), Guo's term, streaming along z."""
+    nz, steps, tau = 16, 30, 0.7
+    z = np.arange(nz)
+    rho = 1 + 0.02 * np.cos(2 * np.pi * z / nz)
+    uz = 0.05 * np.sin(2 * np.pi * 2 * z / nz + 0.4)
+    fz = 2e-4 * np.cos(2 * np.pi * z / nz)
+    cs, ws = (0, 1, -1), (2.0 / 3.0, 1.0 / 6.0, 1.0 / 6.0)
+
+    def feq(r, u):
+        return np.stack([w * r * (1 + 3 * c * u + 4.5 * (c * u) ** 2 - 1.5 * u * u) for c, w in zip(cs, ws)])
+
+    g = feq(rho, uz)
+    for _ in range(steps):
+        r = g.sum(0)
+        u = (sum(c * g[i] for i, c in enumerate(cs)) + 0.5 * fz) / r
+        src = np.stack([(1 - 0.5 / tau) * w * (3 * (c - u) + 9 * c * u * c) * fz for c, w in zip(cs, ws)])
+        post = g - (g - feq(r, u)) / tau + src
+        g = np.stack([np.roll(post[i], c) for i, c in enumerate(cs)])
+    r1 = g.sum(0)
+    u1 = (sum(c * g[i] for i, c in enumerate(cs)) + 0.5 * fz) / r1
+    ext = lambda a: torch.as_tensor(np.broadcast_to(a[:, None, None], (nz, 3, 2)).copy(), dtype=D)  # noqa: E731
+    f3 = ref3d.init_populations(ext(rho), ext(0 * rho), ext(0 * rho), ext(uz), q=27)
+    F3 = (ext(0 * rho), ext(0 * rho), ext(fz))
+    f3 = ref3d.run(f3, steps, tau, *F3)
+    got = ref3d.macroscopic(f3, *F3)
+    assert float((got[0][:, 0, 0] - torch.as_tensor(r1)).abs().max()) < 1e-14
+    assert float((got[3][:, 0, 0] - torch.as_tensor(u1)).abs().max()) < 1e-15
+    assert float(got[1].abs().max()) < 1e-17 and float(got[2].abs().max()) < 1e-17
 
 
 def test_z_invariant_limit_equals_the_2d_balance():
