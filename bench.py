@@ -343,19 +343,22 @@ def decay1024(log, passes=20):
     return out
 
 
-def d3q19_256(log, n=256, tau=0.52, steps=200):
-    """The three-dimensional extension: a forced 256^3 D3Q19 FP32 run (one launch per step,
-    164 algorithmic bytes per site: 19 populations read and written, 3 force values read),
-    timed with HIP events on the handle's stream, then the 3D balance with the stretching
-    term at L = 16, 64, 256 over every cube corner.  `traffic`: HBM bytes per launch from
-    the committed counter summary, if it was taken on the current kernel source."""
+def d3q19_256(log, n=256, tau=0.52, steps=200, lattice="d3q19"):
+    """The three-dimensional extension: a forced 256^3 FP32 run on D3Q19 (or D3Q27) (one
+    launch per step, 164 (228) algorithmic bytes per site: 19 (27) populations read and
+    written, 3 force values read), timed with HIP events on the handle's stream, then the 3D
+    balance with the stretching term at L = 16, 64, 256 over every cube corner.  `traffic`:
+    HBM bytes per launch from the committed counter summary, if it was taken on the current
+    kernel source (D3Q19 only)."""
     import torch
     import lbm_inputs as inp
     from paper_1809_06735_amd import Simulation3D
     shape = (n, n, n)
     rho, ux, uy, uz = inp.fields3(shape, seed=0, max_mach=0.1)
     fx, fy, fz = inp.force3(shape, seed=0, amp=1e-6)
-    sim = Simulation3D(rho, ux, uy, uz, tau, dtype="f32", fx=fx, fy=fy, fz=fz, with_balance=True)
+    sim = Simulation3D(rho, ux, uy, uz, tau, dtype="f32", fx=fx, fy=fy, fz=fz, with_balance=True,
+                       lattice=lattice)
+    q = 27 if lattice == "d3q27" else 19
     del rho, ux, uy, uz, fx, fy, fz
     tile = sim.autotune(3)  # one step per launch, or 2..4 steps per launch (temporal blocking)
     sim.step(10)
@@ -367,11 +370,13 @@ def d3q19_256(log, n=256, tau=0.52, steps=200):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
     sites = n ** 3
-    gbs = 164 * sites / (ms * 1e-3) / 1e9
-    out = {"grid": [n, n, n], "dtype": "f32", "steps": steps, "shape": list(tile), "ms_per_step": round(ms, 4),
+    gbs = (8 * q + 12) * sites / (ms * 1e-3) / 1e9
+    out = {"grid": [n, n, n], "lattice": lattice, "dtype": "f32", "steps": steps, "shape": list(tile),
+           "ms_per_step": round(ms, 4), "algorithmic_bytes_per_site": 8 * q + 12,
            "MLUPS": round(sites / (ms * 1e-3) / 1e6, 1), "kernel_GBps": round(gbs, 1),
            "frac_of_8TBps": round(gbs / HBM_PEAK_GBS, 4),
-           "traffic": traffic_from_profile("k3_step", "d3q19_256", ["rows", "nt"]) if tile[0] == 1 else None}
+           "traffic": (traffic_from_profile("k3_step", "d3q19_256", ["rows", "nt"])
+                       if tile[0] == 1 and q == 19 else None)}
     sizes = (16, 64, 256)
     t0 = time.perf_counter()
     res = sim.balance(sizes)
@@ -381,7 +386,7 @@ def d3q19_256(log, n=256, tau=0.52, steps=200):
     _, _, _, _, sc = sim.moments()
     out["finite"] = sc["nonfinite"] == 0
     sim.close()
-    log(f"[bench] d3q19 {n}^3: {out['MLUPS']} MLUPS ({out['kernel_GBps']} GB/s), balance {out['balance_s']} s")
+    log(f"[bench] {lattice} {n}^3: {out['MLUPS']} MLUPS ({out['kernel_GBps']} GB/s), balance {out['balance_s']} s")
     return out
 
 
@@ -520,6 +525,7 @@ def cpu_baseline(n, tau, alpha, fx, fy, steps):
 EXTRAS = {"paper_set_up_256": paper_set_up_256, "paper_statistics_256": paper_statistics_256,
           "entropic_1024": entropic_1024, "d3q19_256": d3q19_256, "decay1024": decay1024,
           "tau_sweep_4096": tau_sweep_4096,
+          "d3q27_256": lambda log, steps=200: d3q19_256(log, steps=steps, lattice="d3q27"),
           "balance4096": balance4096}
 
 
@@ -818,6 +824,10 @@ def main():
             extras["d3q19_256"] = d3q19_256(log)
         except Exception as e:  # noqa: BLE001
             extras["d3q19_256"] = f"error: {e}"
+        try:
+            extras["d3q27_256"] = d3q19_256(log, lattice="d3q27")
+        except Exception as e:  # noqa: BLE001
+            extras["d3q27_256"] = f"error: {e}"
         try:
             from paper_1809_06735_amd import ensemble as ens_mod
             extras["ensemble"] = ens_mod.bench_ensemble(log=log)

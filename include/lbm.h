@@ -534,11 +534,13 @@ LBM_API int lbm_adjoint_run(const lbm_adjoint_config* cfg, void* ws, size_t ws_b
                     const double* ux0, const double* uy0, double* loss,
                     double* grad_ux0, double* grad_uy0, double* grad_tau);
 
-/* ---- three dimensions: D3Q19 ------------------------------------------------------- */
+/* ---- three dimensions: D3Q19 and D3Q27 --------------------------------------------- */
 /* The same method in three dimensions: the LBGK update of Eq. 1 with the
  * equilibrium of Eq. 2 on the D3Q19 lattice (rest weight 1/3, six axis
  * velocities of weight 1/18, twelve edge diagonals of weight 1/36,
- * c_s^2 = 1/3), Guo's forcing term with the half-force velocity, and the
+ * c_s^2 = 1/3) or the D3Q27 lattice (every velocity in {-1, 0, 1}^3; weights
+ * 8/27, 2/27 for the axes, 1/54 for the edges, 1/216 for the corners, the same
+ * c_s^2), Guo's forcing term with the half-force velocity, and the
  * balances of Sec. 2 in index form over cubic sub-volumes L^3.  In 3D the
  * enstrophy equation keeps the vortex-stretching term omega_i omega_j d_j u_i
  * (Sec. 2 drops it only because it vanishes in 2D).
@@ -550,7 +552,11 @@ typedef struct {
   int32_t with_balance;/* 1: reserve the balance scratch (lbm3_subvolume_balance) */
   double tau;          /* relaxation time > 1/2; nu = (tau - 1/2)/3              */
   void* stream;        /* hipStream_t to enqueue on, or NULL                     */
+  int32_t lattice;     /* LBM3_D3Q19 (0) or LBM3_D3Q27 (1); populations are
+                          row-interleaved [nz][ny][Q][nx], Q = 19 or 27          */
+  int32_t reserved;    /* 0                                                      */
 } lbm3_config;
+enum { LBM3_D3Q19 = 0, LBM3_D3Q27 = 1 };
 
 typedef struct lbm3_ctx_s* lbm3_ctx;
 
@@ -574,7 +580,8 @@ enum {
 };
 
 /* Launch shape of the bulk of lbm3_step.  fuse = 1: one step per launch (the
- * other fields are ignored).  fuse = 2..4: that many steps per launch
+ * other fields are ignored; the only shape of a D3Q27 handle).  fuse = 2..4
+ * (D3Q19): that many steps per launch
  * (temporal blocking; bit-identical to one-step launches): workgroups of
  * bx * by lanes (a multiple of 64, at most 512, with 2 * 16 * bx * by values of
  * LDS at most 64 KiB) each update a tile of (bx - 2 (fuse - 1)) x

@@ -115,7 +115,10 @@ class Tile3(C.Structure):
 class Config3(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("dtype", C.c_int32),
                 ("has_force", C.c_int32), ("with_balance", C.c_int32), ("tau", C.c_double),
-                ("stream", C.c_void_p)]
+                ("stream", C.c_void_p), ("lattice", C.c_int32), ("reserved", C.c_int32)]
+
+
+LATTICES3 = {"d3q19": 0, "d3q27": 1}
 
 
 _I64 = C.c_int64

@@ -1,11 +1,11 @@
-// Three-dimensional extension for gfx950: D3Q19 LBGK step (Eq. 1 with the
-// D3Q19 equilibrium of Eq. 2 and Guo's forcing term), moments, and the
+// Three-dimensional extension for gfx950: D3Q19 and D3Q27 LBGK steps (Eq. 1
+// with the equilibrium of Eq. 2 on either lattice and Guo's forcing term), moments, and the
 // sub-volume kinetic-energy and enstrophy balances in 3D, where the enstrophy
 // equation gains the vortex-stretching term omega_i omega_j d_j u_i (Sec. 2
 // notes that 3D keeps it), averaged over cubes L^3 at every corner.
 //
-// Populations: row-interleaved [nz][ny][19][nx] (the 19 population rows of one
-// (y, z) row of sites are contiguous), deviations from the weights, kept
+// Populations: row-interleaved [nz][ny][Q][nx], Q = 19 or 27 (the Q population
+// rows of one (y, z) row of sites are contiguous), deviations from the weights, kept
 // un-streamed (population l stored at x is f_l(x + c_l)): one step pulls from
 // x - c_l, collides and writes at x, 19 + 19 values per update (152 B FP32),
 // both streams non-temporal (each value is touched once per step).
@@ -42,11 +42,33 @@ __host__ __device__ constexpr int c3(int l, int a) {
 }
 __host__ __device__ constexpr double w3(int l) { return l == 0 ? 1.0 / 3.0 : (l <= 6 ? 1.0 / 18.0 : 1.0 / 36.0); }
 
+// D3Q27: every c in {-1, 0, 1}^3, weight the product of the D1Q3 weights (2/3 at
+// rest, 1/6 moving): the D3Q19 velocities in their order, then the eight
+// corners in opposite pairs.
+__host__ __device__ constexpr int c27(int l, int a) {
+  constexpr int t[8][3] = {{1, 1, 1},  {-1, -1, -1}, {1, 1, -1},  {-1, -1, 1},
+                           {1, -1, 1}, {-1, 1, -1},  {-1, 1, 1},  {1, -1, -1}};
+  return l < 19 ? c3(l, a) : t[l - 19][a];
+}
+__host__ __device__ constexpr double w27(int l) {
+  return l == 0 ? 8.0 / 27.0 : (l <= 6 ? 2.0 / 27.0 : (l <= 18 ? 1.0 / 54.0 : 1.0 / 216.0));
+}
+// velocity component a and weight of population l of the lattice with Q populations
+template <int Q>
+__host__ __device__ constexpr int cq3(int l, int a) {
+  return Q == 19 ? c3(l, a) : c27(l, a);
+}
+template <int Q>
+__host__ __device__ constexpr double wq3(int l) {
+  return Q == 19 ? w3(l) : w27(l);
+}
+
 __device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
-// Element (l, z, y, x) of the row-interleaved population array.
+// Element (l, z, y, x) of the row-interleaved population array of Q populations.
+template <int Q = Q3>
 __device__ __forceinline__ size_t pop_at(int l, int z, int y, int x, int ny, int nx) {
-  return ((static_cast<size_t>(z) * ny + y) * Q3 + l) * nx + x;
+  return ((static_cast<size_t>(z) * ny + y) * Q + l) * nx + x;
 }
 
 // ---- step ---------------------------------------------------------------------------------
@@ -141,7 +163,73 @@ __device__ __forceinline__ void collide3(const T (&d)[Q3], T Fx, T Fy, T Fz, T o
   pair(17, 18, uy - uz, Fy - Fz, we, wBe, wRe);
 }
 
+// The same collision on D3Q27 (the pairs of the D3Q19 collision plus the four
+// corner pairs of weight 1/216; axis weight 2/27, edge weight 1/54).
 template <typename T, bool FORCE>
+__device__ __forceinline__ void collide27(const T (&d)[27], T Fx, T Fy, T Fz, T om, T (&o)[27], T& drho_out,
+                                          T& ux, T& uy, T& uz) {
+  // c.v for a velocity with components in {-1, 0, 1}: signed sums, no products (the
+  // loops below are unrolled, so the branches fold away)
+  auto dot = [](int cx, int cy, int cz, T a, T b, T c) {
+    T r = cx > 0 ? a : -a;
+    if (cx == 0) r = cy > 0 ? b : -b;
+    else if (cy != 0) r += cy > 0 ? b : -b;
+    if (cx == 0 && cy == 0) r = cz > 0 ? c : -c;
+    else if (cz != 0) r += cz > 0 ? c : -c;
+    return r;
+  };
+  T drho = d[0], jx = T(0), jy = T(0), jz = T(0);
+#pragma unroll
+  for (int l = 1; l < 27; l += 2) {
+    drho += d[l] + d[l + 1];
+    const T df = d[l] - d[l + 1];
+    if (c27(l, 0) != 0) jx += c27(l, 0) > 0 ? df : -df;
+    if (c27(l, 1) != 0) jy += c27(l, 1) > 0 ? df : -df;
+    if (c27(l, 2) != 0) jz += c27(l, 2) > 0 ? df : -df;
+  }
+  drho_out = drho;
+  const T rho = T(1) + drho;
+  const T inv = recip3<T>(rho);
+  if constexpr (FORCE) {
+    ux = (jx + T(0.5) * Fx) * inv;
+    uy = (jy + T(0.5) * Fy) * inv;
+    uz = (jz + T(0.5) * Fz) * inv;
+  } else {
+    ux = jx * inv;
+    uy = jy * inv;
+    uz = jz * inv;
+  }
+  const T om1 = T(1) - om;
+  const T b = drho - rho * (T(1.5) * ((ux * ux + uy * uy) + uz * uz));
+  const T p3 = (T(1.5) * om) * rho;
+  T B0 = om * b;
+  T g3 = T(0);
+  if constexpr (FORCE) {
+    g3 = T(3) * (T(1) - T(0.5) * om);
+    B0 = B0 - g3 * ((ux * Fx + uy * Fy) + uz * Fz);
+  }
+  o[0] = om1 * d[0] + T(w27(0)) * B0;
+#pragma unroll
+  for (int l = 1; l < 27; l += 2) {
+    const T w = T(w27(l));
+    const T cu = dot(c27(l, 0), c27(l, 1), c27(l, 2), ux, uy, uz);
+    const T wR = (T(3) * om * w) * rho;
+    T S, A;
+    if constexpr (FORCE) {
+      const T cF = dot(c27(l, 0), c27(l, 1), c27(l, 2), Fx, Fy, Fz);
+      const T gc = g3 * cF;
+      S = (T(3) * w) * (cu * (p3 * cu + gc)) + w * B0;
+      A = wR * cu + w * gc;
+    } else {
+      S = (T(3) * w) * (cu * (p3 * cu)) + w * B0;
+      A = wR * cu;
+    }
+    o[l] = om1 * d[l] + (S + A);
+    o[l + 1] = om1 * d[l + 1] + (S - A);
+  }
+}
+
+template <typename T, bool FORCE, int Q = Q3>
 __global__ void __launch_bounds__(256) k3_step(Step3 p) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= p.nx) return;
@@ -149,11 +237,11 @@ __global__ void __launch_bounds__(256) k3_step(Step3 p) {
   const int nx = p.nx, ny = p.ny, nz = p.nz;
   const T* __restrict__ src = static_cast<const T*>(p.src);
   T* __restrict__ dst = static_cast<T*>(p.dst);
-  T d[Q3];
+  T d[Q];
 #pragma unroll
-  for (int l = 0; l < Q3; ++l) {
-    const int xs = wrap(x - c3(l, 0), nx), ys = wrap(y - c3(l, 1), ny), zs = wrap(z - c3(l, 2), nz);
-    d[l] = __builtin_nontemporal_load(src + pop_at(l, zs, ys, xs, ny, nx));
+  for (int l = 0; l < Q; ++l) {
+    const int xs = wrap(x - cq3<Q>(l, 0), nx), ys = wrap(y - cq3<Q>(l, 1), ny), zs = wrap(z - cq3<Q>(l, 2), nz);
+    d[l] = __builtin_nontemporal_load(src + pop_at<Q>(l, zs, ys, xs, ny, nx));
   }
   const size_t i = (static_cast<size_t>(z) * ny + y) * nx + x;
   T Fx = T(0), Fy = T(0), Fz = T(0);
@@ -162,10 +250,13 @@ __global__ void __launch_bounds__(256) k3_step(Step3 p) {
     Fy = static_cast<const T*>(p.fy)[i];
     Fz = static_cast<const T*>(p.fz)[i];
   }
-  T o[Q3], drho, ux, uy, uz;
-  collide3<T, FORCE>(d, Fx, Fy, Fz, T(p.omega), o, drho, ux, uy, uz);
+  T o[Q], drho, ux, uy, uz;
+  if constexpr (Q == 19)
+    collide3<T, FORCE>(d, Fx, Fy, Fz, T(p.omega), o, drho, ux, uy, uz);
+  else
+    collide27<T, FORCE>(d, Fx, Fy, Fz, T(p.omega), o, drho, ux, uy, uz);
 #pragma unroll
-  for (int l = 0; l < Q3; ++l) __builtin_nontemporal_store(o[l], dst + pop_at(l, z, y, x, ny, nx));
+  for (int l = 0; l < Q; ++l) __builtin_nontemporal_store(o[l], dst + pop_at<Q>(l, z, y, x, ny, nx));
   if (p.h[0]) {
     p.h[0][i] = 1.0 + double(drho);  // rho - 1 kept to the storage type's precision
     p.h[1][i] = double(ux);
@@ -350,7 +441,7 @@ __global__ void __launch_bounds__(512) k3_step_fused(Fused3 p) {
   }
 }
 
-template <typename T>
+template <typename T, int Q = Q3>
 __global__ void __launch_bounds__(256) k3_init(T* __restrict__ pop, const double* __restrict__ r0,
                                                const double* __restrict__ u0, const double* __restrict__ v0,
                                                const double* __restrict__ w0, int nx, int ny, int nz) {
@@ -362,11 +453,11 @@ __global__ void __launch_bounds__(256) k3_init(T* __restrict__ pop, const double
     const double rho = r0[i], ux = u0[i], uy = v0[i], uz = w0[i];
     const double usq15 = 1.5 * (ux * ux + uy * uy + uz * uz);
 #pragma unroll
-    for (int l = 0; l < Q3; ++l) {
-      const double cu = c3(l, 0) * ux + c3(l, 1) * uy + c3(l, 2) * uz;
-      const double dev = w3(l) * ((rho - 1.0) + rho * (3.0 * cu + 4.5 * cu * cu - usq15));
-      const int xs = wrap(x - c3(l, 0), nx), ys = wrap(y - c3(l, 1), ny), zs = wrap(z - c3(l, 2), nz);
-      pop[pop_at(l, zs, ys, xs, ny, nx)] = T(dev);
+    for (int l = 0; l < Q; ++l) {
+      const double cu = cq3<Q>(l, 0) * ux + cq3<Q>(l, 1) * uy + cq3<Q>(l, 2) * uz;
+      const double dev = wq3<Q>(l) * ((rho - 1.0) + rho * (3.0 * cu + 4.5 * cu * cu - usq15));
+      const int xs = wrap(x - cq3<Q>(l, 0), nx), ys = wrap(y - cq3<Q>(l, 1), ny), zs = wrap(z - cq3<Q>(l, 2), nz);
+      pop[pop_at<Q>(l, zs, ys, xs, ny, nx)] = T(dev);
     }
   }
 }
@@ -379,7 +470,7 @@ __global__ void k3_to_storage(T* __restrict__ dst, const double* __restrict__ sr
 
 // ---- moments ---------------------------------------------------------------------------------
 constexpr int kS3 = 8;  // mass, momx, momy, momz, energy, max |u|, min rho, non-finite
-template <typename T, bool FORCE>
+template <typename T, bool FORCE, int Q = Q3>
 __global__ void __launch_bounds__(kRedThreads) k3_moments(const T* __restrict__ pop, const T* __restrict__ fx,
                                                           const T* __restrict__ fy, const T* __restrict__ fz,
                                                           int nx, int ny, int nz, double* r, double* u,
@@ -394,13 +485,13 @@ __global__ void __launch_bounds__(kRedThreads) k3_moments(const T* __restrict__ 
     // the same rounding as the step: moments in the storage type
     T tr = T(0), tx = T(0), ty = T(0), tz = T(0);
 #pragma unroll
-    for (int l = 0; l < Q3; ++l) {
-      const int xs = wrap(x - c3(l, 0), nx), ys = wrap(y - c3(l, 1), ny), zs = wrap(z - c3(l, 2), nz);
-      const T dl = pop[pop_at(l, zs, ys, xs, ny, nx)];
+    for (int l = 0; l < Q; ++l) {
+      const int xs = wrap(x - cq3<Q>(l, 0), nx), ys = wrap(y - cq3<Q>(l, 1), ny), zs = wrap(z - cq3<Q>(l, 2), nz);
+      const T dl = pop[pop_at<Q>(l, zs, ys, xs, ny, nx)];
       tr += dl;
-      if (c3(l, 0)) tx += c3(l, 0) * dl;
-      if (c3(l, 1)) ty += c3(l, 1) * dl;
-      if (c3(l, 2)) tz += c3(l, 2) * dl;
+      if (cq3<Q>(l, 0)) tx += cq3<Q>(l, 0) * dl;
+      if (cq3<Q>(l, 1)) ty += cq3<Q>(l, 1) * dl;
+      if (cq3<Q>(l, 2)) tz += cq3<Q>(l, 2) * dl;
     }
     const T rho = T(1) + tr;
     T Fx = T(0), Fy = T(0), Fz = T(0);
@@ -936,6 +1027,7 @@ using namespace lbm;
 
 struct lbm3_ctx_s {
   lbm3_config cfg{};
+  int q = 19;  // populations per site: 19 (D3Q19) or 27 (D3Q27)
   hipStream_t stream = nullptr;
   void* pop[2] = {nullptr, nullptr};
   int cur = 0;
@@ -976,7 +1068,8 @@ Layout3 carve3(const lbm3_config& c, void* base, size_t cap) {
   const size_t plane = static_cast<size_t>(c.nx) * c.ny * c.nz;
   const size_t es = c.dtype == LBM_F64 ? 8 : 4;
   Layout3 l{};
-  for (int b = 0; b < 2; ++b) l.pop[b] = cv.take<char>(Q3 * plane * es);
+  const size_t q = c.lattice == LBM3_D3Q27 ? 27 : 19;
+  for (int b = 0; b < 2; ++b) l.pop[b] = cv.take<char>(q * plane * es);
   if (c.has_force)
     for (int k = 0; k < 3; ++k) {
       l.f[k] = cv.take<char>(plane * es);
@@ -1009,6 +1102,8 @@ int validate3(const lbm3_config* c) {
   if (!(c->tau > 0.5) || !std::isfinite(c->tau)) return fail(LBM_E_INVALID, "tau must be a finite number > 0.5");
   if (c->has_force != 0 && c->has_force != 1) return fail(LBM_E_INVALID, "has_force must be 0 or 1");
   if (c->with_balance != 0 && c->with_balance != 1) return fail(LBM_E_INVALID, "with_balance must be 0 or 1");
+  if (c->lattice != LBM3_D3Q19 && c->lattice != LBM3_D3Q27)
+    return fail(LBM_E_INVALID, "lattice must be LBM3_D3Q19 or LBM3_D3Q27");
   return LBM_OK;
 }
 
@@ -1028,16 +1123,22 @@ int launch3_step(lbm3_ctx_s* c, bool record) {
   p.omega = 1.0 / c->cfg.tau;
   const dim3 grid((p.nx + 255) / 256, p.ny, p.nz), block(256);
   const bool force = c->cfg.has_force != 0;
+  auto go = [&](auto tag, auto q) {
+    using T = decltype(tag);
+    constexpr int Q = decltype(q)::value;
+    if (force)
+      hipLaunchKernelGGL((k3_step<T, true, Q>), grid, block, 0, c->stream, p);
+    else
+      hipLaunchKernelGGL((k3_step<T, false, Q>), grid, block, 0, c->stream, p);
+  };
+  using Q19 = std::integral_constant<int, 19>;
+  using Q27 = std::integral_constant<int, 27>;
   if (c->cfg.dtype == LBM_F64) {
-    if (force)
-      hipLaunchKernelGGL((k3_step<double, true>), grid, block, 0, c->stream, p);
-    else
-      hipLaunchKernelGGL((k3_step<double, false>), grid, block, 0, c->stream, p);
+    if (c->q == 27) go(double{}, Q27{});
+    else go(double{}, Q19{});
   } else {
-    if (force)
-      hipLaunchKernelGGL((k3_step<float, true>), grid, block, 0, c->stream, p);
-    else
-      hipLaunchKernelGGL((k3_step<float, false>), grid, block, 0, c->stream, p);
+    if (c->q == 27) go(float{}, Q27{});
+    else go(float{}, Q19{});
   }
   LBM_HIP(hipGetLastError());
   if (record) c->hist_t[slot] = c->t;
@@ -1050,8 +1151,9 @@ size_t fused3_lds_bytes(const lbm3_tile& t, int dtype) {
   return static_cast<size_t>(2) * 16 * t.bx * t.by * (dtype == LBM_F64 ? 8 : 4);
 }
 
-bool tile3_ok(const lbm3_tile& t, int dtype) {
+bool tile3_ok(const lbm3_tile& t, int dtype, int q) {
   if (t.fuse == 1) return true;
+  if (q != 19) return false;  // the multi-step kernel is written for D3Q19
   if (t.fuse < 2 || t.fuse > 4) return false;
   const int lanes = t.bx * t.by;
   if (t.bx <= 2 * (t.fuse - 1) || t.by <= 2 * (t.fuse - 1) || t.bz < 1 || t.bz > 65536) return false;
@@ -1115,24 +1217,26 @@ int moments3(lbm3_ctx_s* c, double* r, double* u, double* v, double* w, double* 
   const int nb = moment_blocks3(plane);
   const int nx = c->cfg.nx, ny = c->cfg.ny, nz = c->cfg.nz;
   const bool force = c->cfg.has_force != 0;
+  auto go = [&](auto tag, auto q) {
+    using T = decltype(tag);
+    constexpr int Q = decltype(q)::value;
+    const T* pop = static_cast<const T*>(c->pop[c->cur]);
+    if (force)
+      hipLaunchKernelGGL((k3_moments<T, true, Q>), dim3(nb), dim3(kRedThreads), 0, c->stream, pop,
+                         static_cast<const T*>(c->f[0]), static_cast<const T*>(c->f[1]),
+                         static_cast<const T*>(c->f[2]), nx, ny, nz, r, u, v, w, c->partials);
+    else
+      hipLaunchKernelGGL((k3_moments<T, false, Q>), dim3(nb), dim3(kRedThreads), 0, c->stream, pop, nullptr,
+                         nullptr, nullptr, nx, ny, nz, r, u, v, w, c->partials);
+  };
+  using Q19 = std::integral_constant<int, 19>;
+  using Q27 = std::integral_constant<int, 27>;
   if (c->cfg.dtype == LBM_F64) {
-    const double* pop = static_cast<const double*>(c->pop[c->cur]);
-    if (force)
-      hipLaunchKernelGGL((k3_moments<double, true>), dim3(nb), dim3(kRedThreads), 0, c->stream, pop,
-                         static_cast<const double*>(c->f[0]), static_cast<const double*>(c->f[1]),
-                         static_cast<const double*>(c->f[2]), nx, ny, nz, r, u, v, w, c->partials);
-    else
-      hipLaunchKernelGGL((k3_moments<double, false>), dim3(nb), dim3(kRedThreads), 0, c->stream, pop, nullptr,
-                         nullptr, nullptr, nx, ny, nz, r, u, v, w, c->partials);
+    if (c->q == 27) go(double{}, Q27{});
+    else go(double{}, Q19{});
   } else {
-    const float* pop = static_cast<const float*>(c->pop[c->cur]);
-    if (force)
-      hipLaunchKernelGGL((k3_moments<float, true>), dim3(nb), dim3(kRedThreads), 0, c->stream, pop,
-                         static_cast<const float*>(c->f[0]), static_cast<const float*>(c->f[1]),
-                         static_cast<const float*>(c->f[2]), nx, ny, nz, r, u, v, w, c->partials);
-    else
-      hipLaunchKernelGGL((k3_moments<float, false>), dim3(nb), dim3(kRedThreads), 0, c->stream, pop, nullptr,
-                         nullptr, nullptr, nx, ny, nz, r, u, v, w, c->partials);
+    if (c->q == 27) go(float{}, Q27{});
+    else go(float{}, Q19{});
   }
   LBM_HIP(hipGetLastError());
   if (!scalars) return LBM_OK;
@@ -1174,6 +1278,7 @@ int lbm3_init(const lbm3_config* cfg, void* ws, size_t ws_bytes, const double* r
   l = carve3(*cfg, ws, ws_bytes);
   lbm3_ctx_s* c = new lbm3_ctx_s();
   c->cfg = *cfg;
+  c->q = cfg->lattice == LBM3_D3Q27 ? 27 : 19;
   c->stream = static_cast<hipStream_t>(cfg->stream);
   c->plane = static_cast<size_t>(cfg->nx) * cfg->ny * cfg->nz;
   for (int b = 0; b < 2; ++b) c->pop[b] = l.pop[b];
@@ -1193,12 +1298,21 @@ int lbm3_init(const lbm3_config* cfg, void* ws, size_t ws_bytes, const double* r
   c->wpart = l.wpart;
   c->wstat = l.wstat;
   const int g = grid1(c->plane, 4096);
-  if (cfg->dtype == LBM_F64)
-    hipLaunchKernelGGL(k3_init<double>, dim3(g), dim3(256), 0, c->stream, static_cast<double*>(c->pop[0]), rho0,
-                       ux0, uy0, uz0, cfg->nx, cfg->ny, cfg->nz);
-  else
-    hipLaunchKernelGGL(k3_init<float>, dim3(g), dim3(256), 0, c->stream, static_cast<float*>(c->pop[0]), rho0,
-                       ux0, uy0, uz0, cfg->nx, cfg->ny, cfg->nz);
+  if (cfg->dtype == LBM_F64) {
+    if (c->q == 27)
+      hipLaunchKernelGGL((k3_init<double, 27>), dim3(g), dim3(256), 0, c->stream, static_cast<double*>(c->pop[0]),
+                         rho0, ux0, uy0, uz0, cfg->nx, cfg->ny, cfg->nz);
+    else
+      hipLaunchKernelGGL((k3_init<double, 19>), dim3(g), dim3(256), 0, c->stream, static_cast<double*>(c->pop[0]),
+                         rho0, ux0, uy0, uz0, cfg->nx, cfg->ny, cfg->nz);
+  } else {
+    if (c->q == 27)
+      hipLaunchKernelGGL((k3_init<float, 27>), dim3(g), dim3(256), 0, c->stream, static_cast<float*>(c->pop[0]),
+                         rho0, ux0, uy0, uz0, cfg->nx, cfg->ny, cfg->nz);
+    else
+      hipLaunchKernelGGL((k3_init<float, 19>), dim3(g), dim3(256), 0, c->stream, static_cast<float*>(c->pop[0]),
+                         rho0, ux0, uy0, uz0, cfg->nx, cfg->ny, cfg->nz);
+  }
   hipError_t e = hipGetLastError();
   if (e == hipSuccess && cfg->has_force) {
     const double* src[3] = {fx, fy, fz};
@@ -1238,7 +1352,7 @@ int lbm3_step(lbm3_ctx c, int64_t n) {
 
 int lbm3_set_tile(lbm3_ctx c, const lbm3_tile* tile) {
   if (!c || !tile) return fail(LBM_E_INVALID, "NULL argument");
-  if (!tile3_ok(*tile, c->cfg.dtype))
+  if (!tile3_ok(*tile, c->cfg.dtype, c->q))
     return fail(LBM_E_INVALID, "3D shape (fuse %d, %d x %d lanes, band %d) not valid", tile->fuse, tile->bx,
                 tile->by, tile->bz);
   c->tile = *tile;
@@ -1262,7 +1376,7 @@ int lbm3_autotune(lbm3_ctx c, int32_t trial_launches, lbm3_tile* chosen) {
     for (auto& sh : shapes)
       for (int bz : bands) {
         lbm3_tile t{K, sh[0], sh[1], bz};
-        if (tile3_ok(t, c->cfg.dtype) && (bz <= c->cfg.nz || bz == 16)) cand.push_back(t);
+        if (tile3_ok(t, c->cfg.dtype, c->q) && (bz <= c->cfg.nz || bz == 16)) cand.push_back(t);
       }
   hipEvent_t e0, e1;
   LBM_HIP(hipEventCreate(&e0));

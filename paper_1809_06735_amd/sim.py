@@ -548,15 +548,15 @@ def set_tuned_tile(nx, ny, dtype="f32", forced=False, layout="rows", tile=(512, 
 
 
 class Simulation3D:
-    """One periodic D3Q19 BGK grid on the current GPU (the method of Sec. 1 in three
-    dimensions, with the 3D balance of Sec. 2 and its vortex-stretching term).
+    """One periodic D3Q19 or D3Q27 BGK grid on the current GPU (the method of Sec. 1 in
+    three dimensions, with the 3D balance of Sec. 2 and its vortex-stretching term).
 
     rho0, ux0, uy0, uz0: [nz, ny, nx] initial fields; fx, fy, fz: optional static force;
-    dtype: "f32" or "f64" population storage.
+    dtype: "f32" or "f64" population storage; lattice: "d3q19" or "d3q27".
     """
 
     def __init__(self, rho0, ux0, uy0, uz0, tau, dtype="f32", fx=None, fy=None, fz=None,
-                 with_balance=False, device="cuda", stream=None):
+                 with_balance=False, device="cuda", stream=None, lattice="d3q19"):
         _require_gpu()
         self._lib = L.load()
         self.device = torch.device(device)
@@ -566,8 +566,10 @@ class Simulation3D:
         self.dtype_name = dtype
         self.tau = float(tau)
         has_force = fx is not None
+        self.lattice = lattice
         cfg = L.Config3(nx=self.nx, ny=self.ny, nz=self.nz, dtype=self.dtype, has_force=int(has_force),
-                        with_balance=int(with_balance), tau=self.tau, stream=_stream_handle(stream))
+                        with_balance=int(with_balance), tau=self.tau, stream=_stream_handle(stream),
+                        lattice=L.LATTICES3[lattice])
         self._cfg = cfg
         nbytes = C.c_size_t()
         L.check(self._lib.lbm3_workspace_bytes(C.byref(cfg), C.byref(nbytes)), "lbm3_workspace_bytes")

@@ -43,14 +43,15 @@ def rho_floor32(rho, us, steps, q=9):
     return steps * q * 2.0 ** -24 * dmax
 
 
-def moment_tol(name, want, dtype, steps, base):
+def moment_tol(name, want, dtype, steps, base, q=None):
     """Tolerance of :func:`moment_err` for one field: `base` (1e-12 FP64, 1e-5 FP32), except
     FP32 density, whose rho - 1 cannot be more exact than :func:`rho_floor32` allows: there
-    max(base, floor / max|rho - 1|).  want = (rho, ux, uy[, uz]) of the oracle."""
+    max(base, floor / max|rho - 1|).  want = (rho, ux, uy[, uz]) of the oracle; q the
+    populations per site (9 in 2D, 19 in 3D unless given)."""
     if name != "rho" or dtype != "f32":
         return base
     dr = float((torch.as_tensor(want[0], dtype=torch.float64) - 1).abs().max())
-    floor = rho_floor32(want[0], want[1:], steps, 9 if len(want) == 3 else 19)
+    floor = rho_floor32(want[0], want[1:], steps, q or (9 if len(want) == 3 else 19))
     return max(base, floor / dr) if dr > 0 else float("inf")
 
 

@@ -161,7 +161,8 @@ def test_exact_difference_config_validation():
 
 
 def test_3d_config_validation():
-    """lbm3_workspace_bytes and lbm3_init validate the D3Q19 configuration on the host."""
+    """lbm3_workspace_bytes and lbm3_init validate the 3D configuration on the host; a D3Q27
+    handle holds 27 populations per site."""
     lib = L.load()
 
     def c3(**kw):
@@ -178,8 +179,11 @@ def test_3d_config_validation():
     lib.lbm3_workspace_bytes(C.byref(c3(with_balance=1)), C.byref(nb))
     lib.lbm3_workspace_bytes(C.byref(c3(has_force=1)), C.byref(nf))
     assert n64.value > n.value and nb.value > n.value + 14 * plane * 8 and nf.value > n.value
+    n27 = C.c_size_t()
+    assert lib.lbm3_workspace_bytes(C.byref(c3(lattice=1)), C.byref(n27)) == L.LBM_OK
+    assert n27.value - n.value >= 2 * 8 * plane * 4
     for bad in (dict(nx=8), dict(nz=5000), dict(dtype=7), dict(tau=0.5), dict(tau=float("nan")),
-                dict(has_force=2), dict(with_balance=-1)):
+                dict(has_force=2), dict(with_balance=-1), dict(lattice=2), dict(lattice=-1)):
         assert lib.lbm3_workspace_bytes(C.byref(c3(**bad)), C.byref(n)) == L.LBM_E_INVALID, bad
     assert lib.lbm3_workspace_bytes(None, C.byref(n)) == L.LBM_E_INVALID
     h = C.c_void_p()

@@ -1,4 +1,4 @@
-"""GPU parity of the three-dimensional extension (D3Q19 LBGK with Guo's forcing term, the
+"""GPU parity of the three-dimensional extension (D3Q19 and D3Q27 LBGK with Guo's forcing term, the
 3D energy and enstrophy balances with the vortex-stretching term over cubic sub-volumes)
 against the FP64 oracle (oracle/ref3d.py) on identical seeded inputs.
 
@@ -31,31 +31,33 @@ def Sim3(*a, **k):
     return Simulation3D(*a, **k)
 
 
-def _oracle_run(fields, tau, steps, force):
-    f = ref3d.init_populations(*fields)
+def _oracle_run(fields, tau, steps, force, q=19):
+    f = ref3d.init_populations(*fields, q=q)
     F = [ref3d.t64(a) for a in force] if force is not None else [None] * 3
     return ref3d.run_with_history(f, steps, tau, *F)
 
 
+@pytest.mark.parametrize("lattice", ["d3q19", "d3q27"])
 @pytest.mark.parametrize("shape", [(16, 20, 24), (17, 16, 272)])
 @pytest.mark.parametrize("dtype,tol", [("f64", TOL64), ("f32", TOL32)])
 @pytest.mark.parametrize("forced", [False, True])
-def test_3d_step_parity(gpu_lib, shape, dtype, tol, forced):
+def test_3d_step_parity(gpu_lib, shape, dtype, tol, forced, lattice):
     """rho, u after 25 steps on a non-cubic grid (a ragged x extent, one and two workgroups
-    per row) against the oracle; the scalars against the oracle's sums."""
+    per row) against the oracle on the same lattice; the scalars against the oracle's sums."""
     tau, steps = 0.56, 25
+    q = 27 if lattice == "d3q27" else 19
     fields = inp.fields3(shape, seed=sum(shape), max_mach=0.15)
     force = inp.force3(shape, seed=3, amp=2e-5) if forced else None
-    say(f"3d step {shape} {dtype} forced={forced}")
+    say(f"3d step {lattice} {shape} {dtype} forced={forced}")
     kw = dict(fx=force[0], fy=force[1], fz=force[2]) if forced else {}
-    sim = Sim3(*fields, tau, dtype=dtype, **kw)
+    sim = Sim3(*fields, tau, dtype=dtype, lattice=lattice, **kw)
     sim.step(steps)
     r, vx, vy, vz, sc = sim.moments()
-    _, hist = _oracle_run(fields, tau, steps, force)
+    _, hist = _oracle_run(fields, tau, steps, force, q)
     want = hist[-1]
     for name, g, w in zip(("rho", "ux", "uy", "uz"), (r, vx, vy, vz), want):
         e = moment_err(name, g, w, dtype)
-        tol_f = moment_tol(name, want, dtype, steps, tol)
+        tol_f = moment_tol(name, want, dtype, steps, tol, q)
         say(f"  {name}: {e:.1e} (tol {tol_f:.1e})")
         assert e < tol_f, (name, e, tol_f)
     assert sc["time"] == steps
@@ -131,21 +133,23 @@ def _compare_stats(got, want, kappa, label):
             assert abs(g[k] - w[k]) <= r * max(abs(w[k]), 1e-300), (label, q, k, g[k], w[k], r)
 
 
-@pytest.mark.parametrize("shape,sizes,forced", [((20, 20, 20), (1, 3, 8, 19, 20), True),
-                                                 ((16, 20, 24), (1, 5, 16), False),
-                                                 ((16, 16, 272), (2, 9, 16), True)])
-def test_3d_balance_parity(gpu_lib, shape, sizes, forced):
+@pytest.mark.parametrize("shape,sizes,forced,lattice", [((20, 20, 20), (1, 3, 8, 19, 20), True, "d3q19"),
+                                                         ((16, 20, 24), (1, 5, 16), False, "d3q19"),
+                                                         ((16, 16, 272), (2, 9, 16), True, "d3q19"),
+                                                         ((20, 20, 20), (1, 4, 20), True, "d3q27")])
+def test_3d_balance_parity(gpu_lib, shape, sizes, forced, lattice):
     """Balance of an FP64 run: the 14 integrand fields (with the stretching term z6) and the
-    per-size statistics over every cube corner, against the oracle's run."""
+    per-size statistics over every cube corner, against the oracle's run on the same lattice."""
     tau, steps = 0.53, 20
+    q = 27 if lattice == "d3q27" else 19
     fields = inp.fields3(shape, seed=5 + shape[2], max_mach=0.2)
     force = inp.force3(shape, seed=9, amp=3e-5) if forced else None
     kw = dict(fx=force[0], fy=force[1], fz=force[2]) if forced else {}
-    say(f"3d balance {shape} sizes={sizes} forced={forced}")
-    sim = Sim3(*fields, tau, dtype="f64", with_balance=True, **kw)
+    say(f"3d balance {lattice} {shape} sizes={sizes} forced={forced}")
+    sim = Sim3(*fields, tau, dtype="f64", with_balance=True, lattice=lattice, **kw)
     sim.step(steps)
     res = sim.balance(sizes, term_fields=True)
-    _, hist = _oracle_run(fields, tau, steps, force)
+    _, hist = _oracle_run(fields, tau, steps, force, q)
     r, vx, vy, vz, _ = sim.moments()
     dmom = max(rel_err(g, w) for g, w in zip((r, vx, vy, vz), hist[-1]))
     assert dmom < TOL64
@@ -191,6 +195,24 @@ def test_3d_cube_windows_properties(gpu_lib):
     den = max(abs(m[k]) for k in ("e1", "e2", "e3", "e4", "e5"))
     d_e = abs(rhs - m["lhs_E"]) / den
     assert abs(whole["dE"]["mean"] - d_e) <= 1e-6 * d_e + 1e-12, (whole["dE"]["mean"], d_e)
+
+
+def test_d3q27_runs_one_step_per_launch(gpu_lib):
+    """A D3Q27 handle refuses the multi-step shapes (written for D3Q19), its autotuner keeps
+    one step per launch, and D3Q27 differs from D3Q19 on a fully three-dimensional field
+    (the corner populations matter)."""
+    from paper_1809_06735_amd import _lib as L
+    shape = (16, 16, 32)
+    fields = inp.fields3(shape, seed=2, max_mach=0.15)
+    s27 = Sim3(*fields, 0.6, dtype="f64", lattice="d3q27")
+    with pytest.raises(L.LBMError):
+        s27.set_tile(2, 64, 4, 8)
+    assert s27.autotune(2)[0] == 1
+    s27.step(10)
+    s19 = Sim3(*fields, 0.6, dtype="f64")
+    s19.step(10)
+    a, b = s27.moments(scalars=False), s19.moments(scalars=False)
+    assert max(rel_err(x, y) for x, y in zip(a, b)) > 1e-6
 
 
 def test_3d_errors(gpu_lib):
