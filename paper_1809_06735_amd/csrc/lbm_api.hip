@@ -782,7 +782,7 @@ int lbm_balance_fields_noalloc(const lbm_balance_input* in, const int32_t* sizes
   if (need > kNoAllocScratchBytes)
     return fail(LBM_E_NOMEM,
                 "a %d x %d balance needs %zu bytes of scratch; the static scratch holds %zu "
-                "(square grids up to 590 x 590): use lbm_balance_fields with a workspace",
+                "(square grids up to 591 x 591): use lbm_balance_fields with a workspace",
                 in->nx, in->ny, need, kNoAllocScratchBytes);
   if (int rc = validate_fields_input(in)) return rc;
   if (int rc = validate_balance_request(in->nx, in->ny, sizes, nsizes, out, windows, nwin, wterms))

@@ -8,10 +8,15 @@
 //             difference, total stencil radius 12)
 //             (passes A-C on two sites per thread with 16-byte loads where the
 //             width is even and the fields aligned, bitwise the same results)
-//   means   : domain mean of each of the 13 fields (deterministic two-level sum)
+//   means   : domain mean of each of the 13 fields (deterministic two-level sum
+//             of the passes' workgroup sums)
 //   SAT     : mean-centred inclusive 2D prefix sums, one (ny+1) x (nx+1) table
-//             per field, rows of all fields at one y adjacent (row scan, then
-//             column scan; each reads the table once)
+//             per field, rows of all fields at one y adjacent and 128-byte
+//             aligned.  The two-site passes write their rows as 128-site scans
+//             straight into the table; a column pass adds each row's carry from
+//             the tiles to its left, centres on the mean and scans the columns
+//             (the table is read and written once after the passes).  The
+//             one-site passes write term planes, scanned by a row pass first.
 //   windows : for each box side L and every window corner, the 13 box means
 //             (differences of the table across the window's top and bottom
 //             rows, periodic wrap through the table totals), the balancing
@@ -50,9 +55,15 @@ struct PassArgs {
   double nu;
   const double* nu_field;  // per-site viscosity at level n, or null
   int nx, ny;
-  double* terms;
+  double* terms;  // [13][ny][nx] term fields, or null (paired passes writing the table only)
   double* aux;
   double* psum;  // paired passes: [13][blocks] workgroup sums of each term field
+  // paired passes, when non-null: each wave's 128 sites of a row, scanned, as
+  // entries x + 1 of the prefix table's rows y + 1 (rows ld doubles apart), and
+  // the 128-site totals in rtot[(y * 13 + field) * gridDim.x + blockIdx.x]
+  double* sat;
+  double* rtot;
+  int ld;
 };
 
 // Weights of Eq. 18 per offset m = 1..4 (the difference g(i+m) - g(i-m) is
@@ -244,6 +255,44 @@ __device__ __forceinline__ void dx_pair(const double (&v)[10], double (&d)[2]) {
 // of the tables: the 256 threads' values go through LDS, 32 threads per field add
 // eight each and a 32-lane butterfly adds those, so the order is fixed.
 // psum[field * blocks + block], block = blockIdx.y * gridDim.x + blockIdx.x.
+// Table output of a paired pass, per term field F: the exclusive prefix sums of
+// the raw values along the wave's 128 sites of row y (a wave is one row of the
+// workgroup: lanes x / 2 - tile start), entries x and x + 1 of the field's table
+// row y + 1 (entry c: the sum over the tile's sites before c), the last pair's
+// inclusive sum also at entry nx, and the 128-site total for the row carries.
+// Sites past the grid's width count as zero.  The column pass later adds the
+// carries from the tiles to the left and centres the values on the field's mean.
+template <int... F>
+__device__ __forceinline__ void row_scan_store(const PassArgs& a, const double (*o)[2], bool live, int x,
+                                               int y) {
+  constexpr int NF = sizeof...(F);
+  constexpr int fld[NF] = {F...};
+  const int lane = threadIdx.x;
+  const size_t ld = static_cast<size_t>(a.ld);
+  double* row = a.sat + static_cast<size_t>(y + 1) * NT * ld + x;
+  const bool last = x + 2 == a.nx;
+#pragma unroll
+  for (int k = 0; k < NF; ++k) {
+    const double o0 = live ? o[k][0] : 0.0;
+    const double o1 = live ? o[k][1] : 0.0;
+    double incl = o0 + o1;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const double t = __shfl_up(incl, off, 64);
+      incl += lane >= off ? t : 0.0;
+    }
+    double excl = __shfl_up(incl, 1, 64);
+    excl = lane == 0 ? 0.0 : excl;
+    if (live) {
+      double* p = row + fld[k] * ld;
+      *reinterpret_cast<double2*>(p) = make_double2(excl, excl + o0);
+      if (last) p[2] = incl;
+    }
+    if (lane == 63 && y < a.ny)
+      a.rtot[(static_cast<size_t>(y) * NT + fld[k]) * gridDim.x + blockIdx.x] = incl;
+  }
+}
+
 template <int... F>
 __device__ __forceinline__ void block_field_sums(const double (&v)[sizeof...(F)], double* psum) {
   constexpr int NF = sizeof...(F);
@@ -381,7 +430,7 @@ __global__ void __launch_bounds__(256) k_bal_a2(PassArgs a) {
     o[11][s] = syy;
     o[12][s] = sxy;
   }
-  if (live) {
+  if (live && a.terms) {
     double* t = a.terms;
     st2(t, LBM_T_LHS_E * plane + i, o[0][0], o[0][1]);
     st2(t, LBM_T_E2 * plane + i, o[1][0], o[1][1]);
@@ -390,6 +439,8 @@ __global__ void __launch_bounds__(256) k_bal_a2(PassArgs a) {
     st2(t, LBM_T_LHS_Z * plane + i, o[4][0], o[4][1]);
     st2(t, LBM_T_Z2 * plane + i, o[5][0], o[5][1]);
     st2(t, LBM_T_USQ * plane + i, o[6][0], o[6][1]);
+  }
+  if (live) {
     double* ax = a.aux;
     st2(ax, A_E * plane + i, o[7][0], o[7][1]);
     st2(ax, A_OM2 * plane + i, o[8][0], o[8][1]);
@@ -397,6 +448,9 @@ __global__ void __launch_bounds__(256) k_bal_a2(PassArgs a) {
     st2(ax, A_SXX * plane + i, o[10][0], o[10][1]);
     st2(ax, A_SYY * plane + i, o[11][0], o[11][1]);
     st2(ax, A_SXY * plane + i, o[12][0], o[12][1]);
+  }
+  if (a.sat) {
+    row_scan_store<LBM_T_LHS_E, LBM_T_E2, LBM_T_E3, LBM_T_E4, LBM_T_LHS_Z, LBM_T_Z2, LBM_T_USQ>(a, o, live, x, yt);
   }
   double v[7];
 #pragma unroll
@@ -550,15 +604,20 @@ __global__ void __launch_bounds__(256) k_bal_b2(PassArgs a) {
     o[5][s] = hx;
     o[6][s] = hy;
   }
-  if (live) {
+  if (live && a.terms) {
     double* t = a.terms;
     st2(t, LBM_T_E1 * plane + i, o[0][0], o[0][1]);
     st2(t, LBM_T_E5 * plane + i, o[1][0], o[1][1]);
     st2(t, LBM_T_Z1 * plane + i, o[2][0], o[2][1]);
     st2(t, LBM_T_Z3 * plane + i, o[3][0], o[3][1]);
     st2(t, LBM_T_Z4 * plane + i, o[4][0], o[4][1]);
+  }
+  if (live) {
     st2(a.aux, A_HX * plane + i, o[5][0], o[5][1]);
     st2(a.aux, A_HY * plane + i, o[6][0], o[6][1]);
+  }
+  if (a.sat) {
+    row_scan_store<LBM_T_E1, LBM_T_E5, LBM_T_Z1, LBM_T_Z3, LBM_T_Z4>(a, o, live, x, yt);
   }
   double v[5];
 #pragma unroll
@@ -613,7 +672,11 @@ __global__ void __launch_bounds__(256) k_bal_c2(PassArgs a) {
     const double fy = (4.0 * e1 - e2 + (4.0 / 21.0) * e3 - (1.0 / 56.0) * e4) / 5.0;
     out[s] = fx - fy;
   }
-  if (live) st2(a.terms, LBM_T_Z5 * plane + row + x, out[0], out[1]);
+  if (live && a.terms) st2(a.terms, LBM_T_Z5 * plane + row + x, out[0], out[1]);
+  if (a.sat) {
+    const double ot[1][2] = {{out[0], out[1]}};
+    row_scan_store<LBM_T_Z5>(a, ot, live, x, yt);
+  }
   const double v[1] = {live ? out[0] + out[1] : 0.0};
   block_field_sums<LBM_T_Z5>(v, a.psum);
 }
@@ -673,10 +736,11 @@ __global__ void __launch_bounds__(kRedThreads) k_field_means(const double* __res
   }
 }
 
-// Table rows of one field are sat_ld(nx) = nx + 1 doubles apart.  Rows padded to
-// 128-byte multiples (nx + 1 rounded up to 16) made the balance 2 % slower at
-// 4096^2: the odd stride spreads a column's rows over more memory channels.
-__host__ __device__ __forceinline__ int sat_ld(int nx) { return nx + 1; }
+// Table rows of one field are sat_ld(nx) doubles apart: nx + 1 rounded up to a
+// multiple of 16, so every row starts on a 128-byte line (the workspace is
+// 256-byte aligned) and the passes' 64-column segments (column passes, window
+// walks) and 128-column segments (term passes) cover whole lines.
+__host__ __device__ __forceinline__ int sat_ld(int nx) { return (nx + 16) & ~15; }
 
 // ---- summed-area tables ------------------------------------------------------------------
 // Row pass: P[f][y+1][x+1] = sum_{x' <= x} (g[f][y][x'] - mean_f); P[f][0][*] = P[f][*][0] = 0.
@@ -721,30 +785,69 @@ __global__ void __launch_bounds__(256) k_sat_rows(const double* __restrict__ g,
 }
 
 // Column pass: a workgroup of 64 columns x kColG row groups walks the table
-// down in chunks of kColG x kColR rows.  Each thread holds its kColR rows of
-// one column in registers; the group totals go through LDS, and each thread
-// writes its rows back as running sums offset by the column's carry from the
-// chunks above and by the totals of the groups above it in the chunk.  The
-// table is read once and written once.
-constexpr int kColG = 8;
+// down in chunks of kColG x kColR rows.  Each thread holds its kColR rows of one
+// column in registers; the group totals go through LDS, and each thread writes
+// its rows back as running sums offset by the column's carry from the chunks
+// above and by the totals of the groups above it in the chunk.  The table is
+// read once and written once.  Every load is issued (at a clamped row and
+// column) and its value selected away where it lies outside the table; an empty
+// asm statement takes each loaded value, so the compiler cannot sink the loads
+// into conditional blocks (one load in flight at a time) and a chunk's loads are
+// all in flight together.  All workgroups of a 4096^2 table are resident at once.
+//
+// With CARRY, the rows hold the paired term passes' 128-site scans of the raw
+// values instead (entry c the sum over its tile's sites before c; entry nx the
+// last tile's total) and rcarry[(y * nf + f) * ntx + t] the centred sum of row y
+// over the tiles left of tile t; each value is completed to the centred row
+// prefix as it is loaded, entry + carry - mean x (sites summed in the tile).  A
+// wave's 64 columns lie in one tile, so its carries are wave-uniform (scalar
+// loads).  The pass also writes the zero top row.
+constexpr int kColG = 4;
 constexpr int kColR = 16;
-__global__ void __launch_bounds__(64 * kColG) k_sat_cols(double* sat, int nx, int ny, int nf) {
+constexpr int kScanTile = 128;  // sites of a row in one paired-pass wave
+template <bool CARRY>
+__global__ void __launch_bounds__(64 * kColG) k_sat_cols(double* sat, int nx, int ny, int nf,
+                                                         const double* __restrict__ rcarry,
+                                                         const double* __restrict__ means, int ntx) {
   __shared__ double sh[kColG][64];
   const int c = blockIdx.x * 64 + threadIdx.x;
-  const int g = threadIdx.y;
+  const int g = __builtin_amdgcn_readfirstlane(threadIdx.y);
   const int f = blockIdx.y;
   double* P = sat + f * static_cast<size_t>(sat_ld(nx));
   const size_t s = static_cast<size_t>(sat_ld(nx)) * nf;  // between rows of one field
   const bool active = c <= nx;
+  const int cl = active ? c : nx;
+  // completion of the scanned rows: the wave's tile and the sites summed at this column
+  const int tile = min(static_cast<int>(blockIdx.x) / (kScanTile / 64), ntx - 1);
+  const double msum = CARRY ? means[f] * double(c - tile * kScanTile) : 0.0;
+  const double* rc = CARRY ? rcarry + static_cast<size_t>(f) * ntx + tile : nullptr;
+  const size_t rcs = static_cast<size_t>(nf) * ntx;  // between rows of the carries
+  if (CARRY && g == 0 && active) P[c] = 0.0;  // top row
   double carry = 0.0;  // this column's sum over the rows above the chunk
   for (int y0 = 1; y0 <= ny; y0 += kColG * kColR) {
     const int ya = y0 + g * kColR;
-    double v[kColR];
+    double v[kColR], k[kColR];
     double acc = 0.0;
+    if constexpr (CARRY) {
+#pragma unroll
+      for (int q = 0; q < kColR; ++q) k[q] = rc[static_cast<size_t>((ya + q <= ny ? ya + q : ny) - 1) * rcs];
+    }
+#pragma unroll
+    for (int q = 0; q < kColR; ++q) {
+      const int yl = ya + q <= ny ? ya + q : ny;
+      v[q] = P[yl * s + cl];
+    }
+#pragma unroll
+    for (int q = 0; q < kColR; ++q) {
+      if constexpr (CARRY) asm volatile("" ::"s"(k[q]));
+      asm volatile("" ::"v"(v[q]));
+    }
 #pragma unroll
     for (int q = 0; q < kColR; ++q) {
       const int y = ya + q;
-      v[q] = (active && y <= ny) ? P[y * s + c] : 0.0;
+      double t = v[q];
+      if constexpr (CARRY) t = (t + k[q]) - msum;
+      v[q] = (active && y <= ny) ? t : 0.0;
       acc += v[q];
     }
     sh[g][threadIdx.x] = acc;
@@ -1104,6 +1207,40 @@ __device__ void sum_stats_block(SumStat (&r)[3], double* out) {
   __syncthreads();
 }
 
+// The same partial slot from a workgroup whose windows all belong to field group
+// grp: only that group's six values are reduced (the same butterfly and fixed
+// order), the other groups' slots get the empty statistics.  A walk then keeps
+// one SumStat per side in registers instead of three.
+__device__ void sum_stats_group(const SumStat& r, int grp, double* out) {
+  __shared__ double sh[4][6];
+  double v[6] = {r.n, r.s1, r.s2, r.mn, r.mx, r.nan};
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const double o = __shfl_xor(v[k], off, 64);
+      v[k] = k == 3 ? fmin(v[k], o) : (k == 4 ? fmax(v[k], o) : v[k] + o);
+    }
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0)
+    for (int k = 0; k < 6; ++k) sh[wv][k] = v[k];
+  __syncthreads();
+  if (threadIdx.x < kSumVals) {
+    const int k = threadIdx.x % 6, q = threadIdx.x / 6;
+    double a = k == 3 ? 1e300 : (k == 4 ? -1e300 : 0.0);
+    if (q == grp) {
+      a = sh[0][k];
+      for (int w = 1; w < 4; ++w) {
+        const double o = sh[w][k];
+        a = k == 3 ? fmin(a, o) : (k == 4 ? fmax(a, o) : a + o);
+      }
+    }
+    out[threadIdx.x] = a;
+  }
+  __syncthreads();
+}
+
 // Work split of the windows of one box side L (see k_windows_strided): strips
 // of 256 columns, residues j < L, and segments of at most kStrideSteps corner
 // rows of each residue's sequence.
@@ -1251,8 +1388,8 @@ __global__ void __launch_bounds__(256) k_windows_strided(SatView v, int L, int s
   const int x0 = strip * 256 + threadIdx.x;
   const int y0 = j + L * (g * S);
   const size_t plane = static_cast<size_t>(v.nx) * v.ny;
-  SumStat r[3];
-  for (int q = 0; q < 3; ++q) r[q].init();
+  SumStat r;
+  r.init();
   LdsHist hh{nullptr, nullptr, 0};
   if constexpr (HIST) {
     __shared__ unsigned bins[LBM_MAX_EDGES + 1];
@@ -1264,17 +1401,17 @@ __global__ void __launch_bounds__(256) k_windows_strided(SatView v, int L, int s
   const LdsHist* h = HIST ? &hh : nullptr;
   if (x0 < v.nx && y0 < v.ny) {
     if (grp == 0)
-      stride_windows<LBM_T_LHS_E, 6>(v, L, x0, y0, S, maps, r[0], h);
+      stride_windows<LBM_T_LHS_E, 6>(v, L, x0, y0, S, maps, r, h);
     else if (grp == 1)
-      stride_windows<LBM_T_LHS_Z, 6>(v, L, x0, y0, S, maps ? maps + plane : nullptr, r[1], h);
+      stride_windows<LBM_T_LHS_Z, 6>(v, L, x0, y0, S, maps ? maps + plane : nullptr, r, h);
     else
-      stride_windows<LBM_T_USQ, 1>(v, L, x0, y0, S, maps ? maps + 2 * plane : nullptr, r[2], h);
+      stride_windows<LBM_T_USQ, 1>(v, L, x0, y0, S, maps ? maps + 2 * plane : nullptr, r, h);
   }
   if constexpr (HIST) {
     __syncthreads();
     lds_hist_flush(hh.bins, nedges, hist + grp * (nedges + 1));
   }
-  sum_stats_block(r, partials + static_cast<size_t>(logical) * kSumVals);
+  sum_stats_group(r, grp, partials + static_cast<size_t>(logical) * kSumVals);
 }
 
 // Sides L and 2 L at the same corners in one walk (no histograms, no maps):
@@ -1505,28 +1642,26 @@ __global__ void __launch_bounds__(256) k_windows_pair(SatView v, int L, int stri
   const PairWork w = pair_work(v, L, strips, S, nblocks, per_xcd);
   if (!w.live) return;  // uniform over the workgroup
   const int logical = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-  SumStat r1[3], r2[3];
-  for (int q = 0; q < 3; ++q) {
-    r1[q].init();
-    r2[q].init();
-  }
+  SumStat r1, r2;
+  r1.init();
+  r2.init();
   if (pair_inner(v, L, w)) {
     if (w.grp == 0)
-      stride_windows2_inner<LBM_T_LHS_E, 6>(v, L, w.x0, w.y0, w.nwin, r1[0], r2[0]);
+      stride_windows2_inner<LBM_T_LHS_E, 6>(v, L, w.x0, w.y0, w.nwin, r1, r2);
     else if (w.grp == 1)
-      stride_windows2_inner<LBM_T_LHS_Z, 6>(v, L, w.x0, w.y0, w.nwin, r1[1], r2[1]);
+      stride_windows2_inner<LBM_T_LHS_Z, 6>(v, L, w.x0, w.y0, w.nwin, r1, r2);
     else
-      stride_windows2_inner<LBM_T_USQ, 1>(v, L, w.x0, w.y0, w.nwin, r1[2], r2[2]);
+      stride_windows2_inner<LBM_T_USQ, 1>(v, L, w.x0, w.y0, w.nwin, r1, r2);
   } else if (w.x0 < v.nx && w.y0 < v.ny) {
     if (w.grp == 0)
-      stride_windows2<LBM_T_LHS_E, 6>(v, L, w.x0, w.y0, S, r1[0], r2[0]);
+      stride_windows2<LBM_T_LHS_E, 6>(v, L, w.x0, w.y0, S, r1, r2);
     else if (w.grp == 1)
-      stride_windows2<LBM_T_LHS_Z, 6>(v, L, w.x0, w.y0, S, r1[1], r2[1]);
+      stride_windows2<LBM_T_LHS_Z, 6>(v, L, w.x0, w.y0, S, r1, r2);
     else
-      stride_windows2<LBM_T_USQ, 1>(v, L, w.x0, w.y0, S, r1[2], r2[2]);
+      stride_windows2<LBM_T_USQ, 1>(v, L, w.x0, w.y0, S, r1, r2);
   }
-  sum_stats_block(r1, partials + static_cast<size_t>(logical) * kSumVals);
-  sum_stats_block(r2, partials + (static_cast<size_t>(3) * nblocks + logical) * kSumVals);
+  sum_stats_group(r1, w.grp, partials + static_cast<size_t>(logical) * kSumVals);
+  sum_stats_group(r2, w.grp, partials + (static_cast<size_t>(3) * nblocks + logical) * kSumVals);
 }
 
 // The window walks' partials are merged in two stages.  First stage: set
@@ -1649,6 +1784,7 @@ BalanceWs carve_balance(Carver& c, int nx, int ny) {
   w.terms = c.take<double>(NT * plane);
   w.aux = c.take<double>(NAUX * plane);
   w.sat = c.take<double>(NT * splane);
+  w.rtot = c.take<double>(static_cast<size_t>(NT) * ny * ((nx / 2 + 63) / 64));
   w.means = c.take<double>(16);
   size_t np = static_cast<size_t>(kWinMaxBlocks) * kStatVals;
   for (int L = 1; L <= (nx < ny ? nx : ny); ++L) {
@@ -1673,6 +1809,10 @@ BalanceWs carve_balance(Carver& c, int nx, int ny) {
 }
 
 int balance_terms(const lbm_balance_input& in, const BalanceWs& ws) {
+  return balance_terms(in, ws, true, nullptr);
+}
+
+int balance_terms(const lbm_balance_input& in, const BalanceWs& ws, bool planes, bool* table) {
   hipStream_t s = static_cast<hipStream_t>(in.stream);
   const int nx = in.nx, ny = in.ny;
   PassArgs a;
@@ -1689,6 +1829,9 @@ int balance_terms(const lbm_balance_input& in, const BalanceWs& ws) {
   a.ny = ny;
   a.terms = ws.terms;
   a.aux = ws.aux;
+  a.sat = nullptr;
+  a.rtot = nullptr;
+  a.ld = sat_ld(nx);
   // two sites per thread where the grid width is even and every field is
   // 16-byte aligned (bitwise the same results), else one site per thread
   auto al16 = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
@@ -1697,7 +1840,14 @@ int balance_terms(const lbm_balance_input& in, const BalanceWs& ws) {
   for (int k = 0; k < 3; ++k) paired = paired && al16(a.rho[k]) && al16(a.ux[k]) && al16(a.uy[k]);
   a.psum = ws.partials + ws.partials_cap;
   dim3 blk(64, 4);
+  if (table) *table = paired;
   if (paired) {
+    if (table) {
+      // the passes scan their rows into the prefix table; the planes only on request
+      a.sat = ws.sat;
+      a.rtot = ws.rtot;
+      if (!planes) a.terms = nullptr;
+    }
     dim3 grd((nx / 2 + 63) / 64, (ny + 3) / 4);
     hipLaunchKernelGGL(k_bal_a2, grd, blk, 0, s, a);
     LBM_HIP(hipGetLastError());
@@ -1738,7 +1888,44 @@ int sat_build(const double* g, int nf, const double* means, double* sat, int nx,
               hipStream_t s) {
   hipLaunchKernelGGL(k_sat_rows, dim3(ny, nf), dim3(256), 0, s, g, means, sat, nx, ny, nf);
   LBM_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_sat_cols, dim3((nx + 1 + 63) / 64, nf), dim3(64, kColG), 0, s, sat, nx, ny, nf);
+  hipLaunchKernelGGL(k_sat_cols<false>, dim3((nx + 1 + 63) / 64, nf), dim3(64, kColG), 0, s, sat, nx, ny, nf,
+                     static_cast<const double*>(nullptr), static_cast<const double*>(nullptr), 0);
+  LBM_HIP(hipGetLastError());
+  return LBM_OK;
+}
+
+namespace {
+// Row carries of the scanned table rows, in place: thread (y, f) turns the
+// 128-site totals of row y into their centred exclusive prefix sums,
+// carry(t) = sum over t' < t of (total(t') - mean_f x sites of tile t').
+__global__ void __launch_bounds__(256) k_row_carries(double* rtot, const double* __restrict__ means, int nx,
+                                                     int ny, int ntx) {
+  const int i = blockIdx.x * 256 + threadIdx.x;  // y * 13 + f
+  if (i >= ny * NT) return;
+  const double m = means[i % NT];
+  double* r = rtot + static_cast<size_t>(i) * ntx;
+  double run = 0.0;
+  for (int t = 0; t < ntx; ++t) {
+    const double tot = r[t];
+    r[t] = run;
+    const int w = nx - t * kScanTile < kScanTile ? nx - t * kScanTile : kScanTile;
+    run += tot - m * double(w);
+  }
+}
+}  // namespace
+
+int balance_table(const lbm_balance_input& in, const BalanceWs& ws, bool planes) {
+  hipStream_t s = static_cast<hipStream_t>(in.stream);
+  const int nx = in.nx, ny = in.ny;
+  bool paired = false;
+  if (int rc = balance_terms(in, ws, planes, &paired)) return rc;
+  if (!paired) return sat_build(ws.terms, NT, ws.means, ws.sat, nx, ny, s);
+  const int ntx = (nx / 2 + 63) / 64;
+  hipLaunchKernelGGL(k_row_carries, dim3((ny * NT + 255) / 256), dim3(256), 0, s, ws.rtot,
+                     static_cast<const double*>(ws.means), nx, ny, ntx);
+  LBM_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_sat_cols<true>, dim3((nx + 1 + 63) / 64, NT), dim3(64, kColG), 0, s, ws.sat, nx, ny, NT,
+                     static_cast<const double*>(ws.rtot), static_cast<const double*>(ws.means), ntx);
   LBM_HIP(hipGetLastError());
   return LBM_OK;
 }
@@ -1972,8 +2159,7 @@ int global_enstrophy(const double* ux, const double* uy, int nx, int ny, double*
 int run_balance_async(const lbm_balance_input& in, const BalanceWs& ws, const int32_t* sizes, int nsizes,
                       double* host_stats) {
   hipStream_t s = static_cast<hipStream_t>(in.stream);
-  if (int rc = balance_terms(in, ws)) return rc;
-  if (int rc = sat_build(ws.terms, NT, ws.means, ws.sat, in.nx, in.ny, s)) return rc;
+  if (int rc = balance_table(in, ws, false)) return rc;
   SatView v{ws.sat, ws.means, in.nx, in.ny, NT, sat_ld(in.nx)};
   if (int rc = corner_stats(v, ws, sizes, nsizes, nullptr, false, 0, ws.hist, 0, 0, s)) return rc;
   LBM_HIP(hipMemcpyAsync(host_stats, ws.pool, static_cast<size_t>(nsizes) * kStatVals * sizeof(double),
@@ -1993,11 +2179,10 @@ int run_balance(const lbm_balance_input& in, const BalanceWs& ws, const int32_t*
   hipStream_t s = static_cast<hipStream_t>(in.stream);
   const int nx = in.nx, ny = in.ny;
   const size_t plane = static_cast<size_t>(nx) * ny;
-  if (int rc = balance_terms(in, ws)) return rc;
+  if (int rc = balance_table(in, ws, term_fields != nullptr)) return rc;
   if (term_fields)
     LBM_HIP(hipMemcpyAsync(term_fields, ws.terms, NT * plane * sizeof(double),
                            hipMemcpyDeviceToDevice, s));
-  if (int rc = sat_build(ws.terms, NT, ws.means, ws.sat, nx, ny, s)) return rc;
 
   const bool hist = extra && extra->edges;
   const int ne = hist ? extra->nedges : 0;

@@ -201,7 +201,8 @@ int edm_moments(const lbm_config& c, const EdmWs& w, const EdmModes& md, const M
 struct BalanceWs {
   double* terms;     // [13][ny][nx]
   double* aux;       // [8][ny][nx]: E, Omega, omega, sxx, syy, sxy, Hx, Hy
-  double* sat;       // [13][ny+1][nx+1]
+  double* sat;       // [ny+1][13][sat_ld(nx)]: rows of the 13 fields' prefix tables, 128-byte aligned
+  double* rtot;      // [ny][13][nx / 128 rounded up]: row totals and carries of the scanned rows
   double* means;     // [16]
   double* partials;  // block partials
   size_t partials_cap;  // doubles of window partials before the field-sum partials
@@ -218,17 +219,25 @@ constexpr int kMaxSizes = 64;
 size_t balance_ws_bytes(int nx, int ny);
 BalanceWs carve_balance(Carver& c, int nx, int ny);
 // The window walks address the 13 prefix tables with 32-bit element offsets:
-// a grid is accepted for the balance only while 13 (nx + 1)(ny + 1) < 2^32
-// (square grids up to 18 175^2).  LBM_OK, or LBM_E_UNSUPPORTED with a message.
+// a grid is accepted for the balance only while 13 ld (ny + 1) < 2^32, ld =
+// nx + 1 rounded up to 16 (square grids up to 18 175^2).  LBM_OK, or LBM_E_UNSUPPORTED with a message.
 int balance_grid_ok(int nx, int ny);
 // Pieces of the balance reused by the adjoint: the 13 term fields and the aux
 // fields (E, Omega, omega, sigma_xx, sigma_yy, sigma_xy, H_x, H_y) of passes
 // A-C, with the 13 fields' domain means in ws.means; domain means of nf
 // consecutive fields; their mean-centred prefix tables
-// (row-interleaved: table row y of field f starts at (y nf + f)(nx + 1), so the
-// rows of all fields at one y are adjacent); and scaled box sums of field f of
-// such a table for every corner shifted by `off`.
+// (row-interleaved: table row y of field f starts at (y nf + f) ld, ld = nx + 1
+// rounded up to 16, so the rows of all fields at one y are adjacent); and scaled
+// box sums of field f of such a table for every corner shifted by `off`.
 int balance_terms(const lbm_balance_input& in, const BalanceWs& ws);
+// The same passes; where the two-site passes run (even width, 16-byte aligned
+// fields: *table set) and table is non-null, they also scan their rows into
+// ws.sat and ws.rtot for balance_table, and write the term planes only when
+// planes is set.
+int balance_terms(const lbm_balance_input& in, const BalanceWs& ws, bool planes, bool* table);
+// The 13 fields' means and complete prefix table ws.sat (the term planes
+// ws.terms too when planes is set, and always where the one-site passes run).
+int balance_table(const lbm_balance_input& in, const BalanceWs& ws, bool planes);
 int field_means(const double* g, int nf, int nx, int ny, double* partials, double* means,
                 hipStream_t s);
 int sat_build(const double* g, int nf, const double* means, double* sat, int nx, int ny,

@@ -88,12 +88,13 @@ def test_balance_fields_parity(gpu_lib, n, sizes, force):
             assert torch.allclose(g[fin], o[fin], rtol=r, atol=1e-12 * float(o[fin].abs().max()))
 
 
-@pytest.mark.parametrize("ny,nx", [(48, 80), (47, 81)])
+@pytest.mark.parametrize("ny,nx", [(48, 80), (47, 81), (20, 392)])
 def test_balance_fields_nonsquare(gpu_lib, ny, nx):
-    """Even widths take the two-sites-per-thread term passes, odd widths the one-site ones."""
+    """Even widths take the two-sites-per-thread term passes, odd widths the one-site ones.
+    392 = 3 x 128 + 8: the even-width passes' 128-site row scans end in a ragged tile."""
     from paper_1809_06735_amd import balance_fields
     say(f"balance_fields {ny}x{nx}")
-    lv = inp.balance_levels(96, seed=9)
+    lv = inp.balance_levels(max(96, nx), seed=9)
     cut = {k: ([a[:ny, :nx] for a in v] if isinstance(v, list) else v[:ny, :nx]) for k, v in lv.items()}
     sizes = (4, 16, min(ny, nx))
     res = balance_fields(cut["rho"], cut["ux"], cut["uy"], 0.002, sizes, fx=cut["fx"],
