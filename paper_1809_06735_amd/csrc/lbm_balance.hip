@@ -1159,6 +1159,12 @@ struct SumStat {
     mn = ok ? fmin(mn, v) : mn;
     mx = ok ? fmax(mx, v) : mx;
   }
+  // Keeps the running values in registers at this point of the program: in a
+  // fully unrolled walk the compiler would otherwise defer every window's update
+  // to the end and hold all the window values live meanwhile.
+  __device__ __forceinline__ void pin() {
+    asm volatile("" : "+v"(n), "+v"(s1), "+v"(s2), "+v"(mn), "+v"(mx), "+v"(nan));
+  }
   __device__ __forceinline__ void add(double v) {
     const bool ok = isfinite(v);
     const double w = ok ? v : 0.0;
@@ -1594,6 +1600,8 @@ __device__ __forceinline__ void stride_windows2_inner(const SatView& v, int L, i
     }
     r1.add_if(window_value<NF>(m1), j - 1 < nwin);
     r2.add_if(window_value<NF>(m2), j >= 2 && j <= last);
+    r1.pin();
+    r2.pin();
 #pragma unroll
     for (int k = 0; k < NF; ++k) {
       h1[P][k] = d1[k];
@@ -1611,17 +1619,20 @@ __device__ __forceinline__ void stride_windows2_inner(const SatView& v, int L, i
 // the partials of side 2 L follow those of side L.
 struct PairWork {
   int grp, strip, y0, x0, nwin;
+  int slot;  // partial slot, 3 x work item + group
   bool live;
 };
+template <int G0, int NG>
 __device__ __forceinline__ PairWork pair_work(const SatView& v, int L, int strips, int S, int nblocks,
                                               int per_xcd) {
   const int b = blockIdx.x;
   const int logical = (b & 7) * per_xcd + (b >> 3);
   PairWork w{};
-  w.live = logical < 3 * nblocks;
+  w.live = logical < NG * nblocks;
   if (!w.live) return w;
-  w.grp = logical % 3;  // groups alternate, as in k_windows_strided
-  const int wb = logical / 3;
+  w.grp = G0 + logical % NG;  // groups alternate, as in k_windows_strided
+  const int wb = logical / NG;
+  w.slot = 3 * wb + w.grp;
   w.strip = wb % strips;
   const int rest = wb / strips;
   const int j = rest % L, g = rest / L;
@@ -1637,31 +1648,34 @@ __device__ __forceinline__ bool pair_inner(const SatView& v, int L, const PairWo
   return w.strip * 256 + 255 + 2 * L <= v.nx && w.y0 + (w.nwin + 1) * L <= v.ny && w.y0 < v.ny;
 }
 
+// Groups G0 .. G0 + NG - 1 of the pair walk: the six-field groups (0, 1) in one
+// launch and the one-field group (2) in another, so that each is compiled for its
+// own register count (the one-field walk runs at higher occupancy).
+template <int G0, int NG>
 __global__ void __launch_bounds__(256) k_windows_pair(SatView v, int L, int strips, int S, int nblocks,
                                                       int per_xcd, double* partials) {
-  const PairWork w = pair_work(v, L, strips, S, nblocks, per_xcd);
+  const PairWork w = pair_work<G0, NG>(v, L, strips, S, nblocks, per_xcd);
   if (!w.live) return;  // uniform over the workgroup
-  const int logical = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
   SumStat r1, r2;
   r1.init();
   r2.init();
   if (pair_inner(v, L, w)) {
-    if (w.grp == 0)
-      stride_windows2_inner<LBM_T_LHS_E, 6>(v, L, w.x0, w.y0, w.nwin, r1, r2);
-    else if (w.grp == 1)
-      stride_windows2_inner<LBM_T_LHS_Z, 6>(v, L, w.x0, w.y0, w.nwin, r1, r2);
-    else
+    if (G0 == 2)
       stride_windows2_inner<LBM_T_USQ, 1>(v, L, w.x0, w.y0, w.nwin, r1, r2);
-  } else if (w.x0 < v.nx && w.y0 < v.ny) {
-    if (w.grp == 0)
-      stride_windows2<LBM_T_LHS_E, 6>(v, L, w.x0, w.y0, S, r1, r2);
-    else if (w.grp == 1)
-      stride_windows2<LBM_T_LHS_Z, 6>(v, L, w.x0, w.y0, S, r1, r2);
+    else if (w.grp == 0)
+      stride_windows2_inner<LBM_T_LHS_E, 6>(v, L, w.x0, w.y0, w.nwin, r1, r2);
     else
+      stride_windows2_inner<LBM_T_LHS_Z, 6>(v, L, w.x0, w.y0, w.nwin, r1, r2);
+  } else if (w.x0 < v.nx && w.y0 < v.ny) {
+    if (G0 == 2)
       stride_windows2<LBM_T_USQ, 1>(v, L, w.x0, w.y0, S, r1, r2);
+    else if (w.grp == 0)
+      stride_windows2<LBM_T_LHS_E, 6>(v, L, w.x0, w.y0, S, r1, r2);
+    else
+      stride_windows2<LBM_T_LHS_Z, 6>(v, L, w.x0, w.y0, S, r1, r2);
   }
-  sum_stats_group(r1, w.grp, partials + static_cast<size_t>(logical) * kSumVals);
-  sum_stats_group(r2, w.grp, partials + (static_cast<size_t>(3) * nblocks + logical) * kSumVals);
+  sum_stats_group(r1, w.grp, partials + static_cast<size_t>(w.slot) * kSumVals);
+  sum_stats_group(r2, w.grp, partials + (static_cast<size_t>(3) * nblocks + w.slot) * kSumVals);
 }
 
 // The window walks' partials are merged in two stages.  First stage: set
@@ -2071,9 +2085,12 @@ int corner_stats(const SatView& v, const BalanceWs& ws, const int32_t* sizes, in
       if (2 * 3 * g.blocks * kSumVals > static_cast<long long>(ws.partials_cap))
         return fail(LBM_E_INVALID, "box sides %d, %d: window partials exceed the workspace", L, 2 * L);
       const int nb = static_cast<int>(g.blocks);
-      const int per_xcd = (3 * nb + 7) / 8;
-      hipLaunchKernelGGL(k_windows_pair, dim3(per_xcd * 8), dim3(256), 0, s, v, L, g.strips, g.S, nb,
-                         per_xcd, ws.partials);
+      const int per_xcd6 = (2 * nb + 7) / 8, per_xcd1 = (nb + 7) / 8;
+      hipLaunchKernelGGL((k_windows_pair<0, 2>), dim3(per_xcd6 * 8), dim3(256), 0, s, v, L, g.strips, g.S, nb,
+                         per_xcd6, ws.partials);
+      LBM_HIP(hipGetLastError());
+      hipLaunchKernelGGL((k_windows_pair<2, 1>), dim3(per_xcd1 * 8), dim3(256), 0, s, v, L, g.strips, g.S, nb,
+                         per_xcd1, ws.partials);
       LBM_HIP(hipGetLastError());
       if (int rc = merge_sum_stats(ws, 3 * nb, 2, ws.stats + static_cast<size_t>(k) * kStatVals,
                                    ws.stats + static_cast<size_t>(twin[k]) * kStatVals, s))
