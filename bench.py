@@ -390,13 +390,17 @@ def d3q19_256(log, n=256, tau=0.52, steps=200, lattice="d3q19"):
     return out
 
 
-# Algorithmic HBM bytes per site of one balance call (FP64 fields, 13 term fields): the term
+# Algorithmic HBM bytes per site of one balance call (FP64 fields, 13 term fields): the
+# level-n moments (nine FP32 populations and the FP32 force in; FP64 rho, u and total
+# force out), the term
 # passes (levels n-2..n of rho, u and the force in, 13 terms + 8 auxiliary fields out, the
-# auxiliary fields read back), the field means (13 reads), the two table passes (13 reads +
-# 13 writes each) and one read of the table per walk over the window corners (a side L
-# whose double 2 L is also asked for shares one walk with it).
+# auxiliary fields read back; the field means come from their workgroup sums), the prefix
+# table's one read and one write after the passes, and one read of the table per walk
+# over the window corners (a side L whose double 2 L is also asked for shares one walk
+# with it).
+BAL_BYTES_MOMENTS = (9 * 4 + 2 * 4) + (3 * 8 + 2 * 8)
 BAL_BYTES_TERMS = (11 * 8 + 13 * 8) + (11 * 8 + 7 * 8) + (3 * 8 + 8)
-BAL_BYTES_TABLES = 13 * 8 + 2 * (13 * 8 + 13 * 8)
+BAL_BYTES_TABLES = 13 * 8 + 13 * 8
 BAL_BYTES_PER_WALK = 13 * 8
 
 
@@ -440,7 +444,7 @@ def balance4096(log, calls=5):
     sim.close()
     ms = float(np.median(ts)) * 1e3
     walks = table_walks(SIZES, n, n)
-    per_site = BAL_BYTES_TERMS + BAL_BYTES_TABLES + walks * BAL_BYTES_PER_WALK
+    per_site = BAL_BYTES_MOMENTS + BAL_BYTES_TERMS + BAL_BYTES_TABLES + walks * BAL_BYTES_PER_WALK
     gbs = per_site * n * n / (ms * 1e-3) / 1e9
     out = {"grid": n, "sizes": list(SIZES), "table_walks": walks, "calls": calls, "ms_per_call": round(ms, 3),
            "algorithmic_bytes_per_site": per_site, "GBps": round(gbs, 1),
