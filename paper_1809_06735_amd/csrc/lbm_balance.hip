@@ -228,6 +228,12 @@ __device__ __forceinline__ double2 ld2(const double* f, size_t row, int x) {
 __device__ __forceinline__ void st2(double* f, size_t i, double a, double b) {
   *reinterpret_cast<double2*>(f + i) = make_double2(a, b);
 }
+// the auxiliary fields are stored non-temporal: passes B and C read them back
+// from HBM (eight fields of N^2 doubles do not stay in the caches)
+__device__ __forceinline__ void st2nt(double* f, size_t i, double a, double b) {
+  __builtin_nontemporal_store(a, f + i);
+  __builtin_nontemporal_store(b, f + i + 1);
+}
 // values at columns x - 4 .. x + 5 of one row (x and nx even)
 __device__ __forceinline__ void seg10(const double* f, size_t row, int x, int nx, double (&v)[10]) {
 #pragma unroll
@@ -259,7 +265,8 @@ __device__ __forceinline__ void dx_pair(const double (&v)[10], double (&d)[2]) {
 // the raw values along the wave's 128 sites of row y (a wave is one row of the
 // workgroup: lanes x / 2 - tile start), entries x and x + 1 of the field's table
 // row y + 1 (entry c: the sum over the tile's sites before c), the last pair's
-// inclusive sum also at entry nx, and the 128-site total for the row carries.
+// inclusive sum also at entry nx (non-temporal stores: the column pass reads them
+// back from HBM), and the 128-site total for the row carries.
 // Sites past the grid's width count as zero.  The column pass later adds the
 // carries from the tiles to the left and centres the values on the field's mean.
 template <int... F>
@@ -285,8 +292,9 @@ __device__ __forceinline__ void row_scan_store(const PassArgs& a, const double (
     excl = lane == 0 ? 0.0 : excl;
     if (live) {
       double* p = row + fld[k] * ld;
-      *reinterpret_cast<double2*>(p) = make_double2(excl, excl + o0);
-      if (last) p[2] = incl;
+      __builtin_nontemporal_store(excl, p);
+      __builtin_nontemporal_store(excl + o0, p + 1);
+      if (last) __builtin_nontemporal_store(incl, p + 2);
     }
     if (lane == 63 && y < a.ny)
       a.rtot[(static_cast<size_t>(y) * NT + fld[k]) * gridDim.x + blockIdx.x] = incl;
@@ -442,12 +450,12 @@ __global__ void __launch_bounds__(256) k_bal_a2(PassArgs a) {
   }
   if (live) {
     double* ax = a.aux;
-    st2(ax, A_E * plane + i, o[7][0], o[7][1]);
-    st2(ax, A_OM2 * plane + i, o[8][0], o[8][1]);
-    st2(ax, A_W * plane + i, o[9][0], o[9][1]);
-    st2(ax, A_SXX * plane + i, o[10][0], o[10][1]);
-    st2(ax, A_SYY * plane + i, o[11][0], o[11][1]);
-    st2(ax, A_SXY * plane + i, o[12][0], o[12][1]);
+    st2nt(ax, A_E * plane + i, o[7][0], o[7][1]);
+    st2nt(ax, A_OM2 * plane + i, o[8][0], o[8][1]);
+    st2nt(ax, A_W * plane + i, o[9][0], o[9][1]);
+    st2nt(ax, A_SXX * plane + i, o[10][0], o[10][1]);
+    st2nt(ax, A_SYY * plane + i, o[11][0], o[11][1]);
+    st2nt(ax, A_SXY * plane + i, o[12][0], o[12][1]);
   }
   if (a.sat) {
     row_scan_store<LBM_T_LHS_E, LBM_T_E2, LBM_T_E3, LBM_T_E4, LBM_T_LHS_Z, LBM_T_Z2, LBM_T_USQ>(a, o, live, x, yt);
@@ -613,8 +621,8 @@ __global__ void __launch_bounds__(256) k_bal_b2(PassArgs a) {
     st2(t, LBM_T_Z4 * plane + i, o[4][0], o[4][1]);
   }
   if (live) {
-    st2(a.aux, A_HX * plane + i, o[5][0], o[5][1]);
-    st2(a.aux, A_HY * plane + i, o[6][0], o[6][1]);
+    st2nt(a.aux, A_HX * plane + i, o[5][0], o[5][1]);
+    st2nt(a.aux, A_HY * plane + i, o[6][0], o[6][1]);
   }
   if (a.sat) {
     row_scan_store<LBM_T_E1, LBM_T_E5, LBM_T_Z1, LBM_T_Z3, LBM_T_Z4>(a, o, live, x, yt);
@@ -789,11 +797,12 @@ __global__ void __launch_bounds__(256) k_sat_rows(const double* __restrict__ g,
 // column in registers; the group totals go through LDS, and each thread writes
 // its rows back as running sums offset by the column's carry from the chunks
 // above and by the totals of the groups above it in the chunk.  The table is
-// read once and written once.  Every load is issued (at a clamped row and
-// column) and its value selected away where it lies outside the table; an empty
-// asm statement takes each loaded value, so the compiler cannot sink the loads
-// into conditional blocks (one load in flight at a time) and a chunk's loads are
-// all in flight together.  All workgroups of a 4096^2 table are resident at once.
+// read once and written once, both non-temporal (the table is far larger than the
+// caches).  Every load is issued (at a clamped row and column) and its value
+// selected away where it lies outside the table; an empty asm statement takes
+// each loaded value, so the compiler cannot sink the loads into conditional
+// blocks (one load in flight at a time) and a chunk's loads are all in flight
+// together.  All workgroups of a 4096^2 table are resident at once.
 //
 // With CARRY, the rows hold the paired term passes' 128-site scans of the raw
 // values instead (entry c the sum over its tile's sites before c; entry nx the
@@ -835,7 +844,7 @@ __global__ void __launch_bounds__(64 * kColG) k_sat_cols(double* sat, int nx, in
 #pragma unroll
     for (int q = 0; q < kColR; ++q) {
       const int yl = ya + q <= ny ? ya + q : ny;
-      v[q] = P[yl * s + cl];
+      v[q] = __builtin_nontemporal_load(P + yl * s + cl);
     }
 #pragma unroll
     for (int q = 0; q < kColR; ++q) {
@@ -865,7 +874,7 @@ __global__ void __launch_bounds__(64 * kColG) k_sat_cols(double* sat, int nx, in
       for (int q = 0; q < kColR; ++q) {
         const int y = ya + q;
         run += v[q];
-        if (y <= ny) P[y * s + c] = run;
+        if (y <= ny) __builtin_nontemporal_store(run, P + y * s + c);
       }
     }
     carry = tot;
