@@ -392,14 +392,14 @@ def d3q19_256(log, n=256, tau=0.52, steps=200, lattice="d3q19"):
 
 # Algorithmic HBM bytes per site of one balance call (FP64 fields, 13 term fields): the
 # level-n moments (nine FP32 populations and the FP32 force in; FP64 rho, u and total
-# force out), the term
-# passes (levels n-2..n of rho, u and the force in, 13 terms + 8 auxiliary fields out, the
-# auxiliary fields read back; the field means come from their workgroup sums), the prefix
-# table's one read and one write after the passes, and one read of the table per walk
-# over the window corners (a side L whose double 2 L is also asked for shares one walk
-# with it).
+# force out), the term passes (pass A: levels n-2..n of rho, u and the force in, 7 terms
+# and the auxiliary omega, sigma_xx, sigma_yy, sigma_xy out; pass B: level-n rho, u, the
+# force and those four in, 5 terms and H out; pass C: omega and H in, 1 term out; the
+# field means come from their workgroup sums), the prefix table's one read and one write
+# after the passes, and one read of the table per walk over the window corners (a side L
+# whose double 2 L is also asked for shares one walk with it).
 BAL_BYTES_MOMENTS = (9 * 4 + 2 * 4) + (3 * 8 + 2 * 8)
-BAL_BYTES_TERMS = (11 * 8 + 13 * 8) + (11 * 8 + 7 * 8) + (3 * 8 + 8)
+BAL_BYTES_TERMS = (11 * 8 + 11 * 8) + (9 * 8 + 7 * 8) + (3 * 8 + 8)
 BAL_BYTES_TABLES = 13 * 8 + 13 * 8
 BAL_BYTES_PER_WALK = 13 * 8
 

@@ -450,8 +450,10 @@ __global__ void __launch_bounds__(256) k_bal_a2(PassArgs a) {
   }
   if (live) {
     double* ax = a.aux;
-    st2nt(ax, A_E * plane + i, o[7][0], o[7][1]);
-    st2nt(ax, A_OM2 * plane + i, o[8][0], o[8][1]);
+    if (!a.sat) {
+      st2nt(ax, A_E * plane + i, o[7][0], o[7][1]);
+      st2nt(ax, A_OM2 * plane + i, o[8][0], o[8][1]);
+    }
     st2nt(ax, A_W * plane + i, o[9][0], o[9][1]);
     st2nt(ax, A_SXX * plane + i, o[10][0], o[10][1]);
     st2nt(ax, A_SYY * plane + i, o[11][0], o[11][1]);
@@ -482,13 +484,16 @@ __global__ void __launch_bounds__(256) k_bal_b2(PassArgs a) {
   const double* uy = a.uy[2];
   const double* rho = a.rho[2];
   const double* ax = a.aux;
-  const double* E = ax + A_E * plane;
-  const double* Om = ax + A_OM2 * plane;
   const double* W = ax + A_W * plane;
   const double* sxx = ax + A_SXX * plane;
   const double* syy = ax + A_SYY * plane;
   const double* sxy = ax + A_SXY * plane;
   const bool forced = a.fx != nullptr;
+  // E = rho |u|^2 / 2 and Omega = omega^2 / 2 at the stencil points are formed
+  // here from rho, u and omega (which the stencils load anyway), with pass A's
+  // expressions, instead of being stored by pass A and read back
+  auto energy = [](double r, double vx, double vy) { return 0.5 * r * (vx * vx + vy * vy); };
+  auto enstrophy = [](double w) { return 0.5 * w * w; };
   double dEx[2] = {}, dEy[2] = {}, dSx[2] = {}, dSy[2] = {}, dOx[2] = {}, dOy[2] = {};
   double dxsxx[2] = {}, dysxy[2] = {}, dxsxy[2] = {}, dysyy[2] = {}, dxw[2] = {}, dyw[2] = {};
   double dxf[2] = {}, dyf[2] = {};
@@ -502,36 +507,38 @@ __global__ void __launch_bounds__(256) k_bal_b2(PassArgs a) {
     const size_t rm = static_cast<size_t>(wrap_add(y, -m, ny)) * nx;
     const double2 uxp = ld2(ux, rp, x), uxm = ld2(ux, rm, x), uyp = ld2(uy, rp, x), uym = ld2(uy, rm, x);
     const double2 sxyp = ld2(sxy, rp, x), sxym = ld2(sxy, rm, x), syyp = ld2(syy, rp, x), syym = ld2(syy, rm, x);
-    const double2 Ep = ld2(E, rp, x), Em = ld2(E, rm, x), Op = ld2(Om, rp, x), Omm = ld2(Om, rm, x);
-    const double2 Wp = ld2(W, rp, x), Wm = ld2(W, rm, x);
+    const double2 rpp = ld2(rho, rp, x), rmm = ld2(rho, rm, x), Wp = ld2(W, rp, x), Wm = ld2(W, rm, x);
     const double pux[2] = {uxp.x, uxp.y}, mux[2] = {uxm.x, uxm.y}, puy[2] = {uyp.x, uyp.y}, muy[2] = {uym.x, uym.y};
     const double psxy[2] = {sxyp.x, sxyp.y}, msxy[2] = {sxym.x, sxym.y};
     const double psyy[2] = {syyp.x, syyp.y}, msyy[2] = {syym.x, syym.y};
-    const double pE[2] = {Ep.x, Ep.y}, mE[2] = {Em.x, Em.y}, pO[2] = {Op.x, Op.y}, mO[2] = {Omm.x, Omm.y};
+    const double pr[2] = {rpp.x, rpp.y}, mr[2] = {rmm.x, rmm.y};
     const double pW[2] = {Wp.x, Wp.y}, mW[2] = {Wm.x, Wm.y};
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-      dEy[s] += c * (pE[s] * puy[s] - mE[s] * muy[s]);
+      const double pE = energy(pr[s], pux[s], puy[s]), mE = energy(mr[s], mux[s], muy[s]);
+      const double pO = enstrophy(pW[s]), mO = enstrophy(mW[s]);
+      dEy[s] += c * (pE * puy[s] - mE * muy[s]);
       dSy[s] += c * ((pux[s] * psxy[s] + puy[s] * psyy[s]) - (mux[s] * msxy[s] + muy[s] * msyy[s]));
-      dOy[s] += c * (pO[s] * puy[s] - mO[s] * muy[s]);
+      dOy[s] += c * (pO * puy[s] - mO * muy[s]);
       dysxy[s] += c * (psxy[s] - msxy[s]);
       dysyy[s] += c * (psyy[s] - msyy[s]);
       dyw[s] += c * (pW[s] - mW[s]);
     }
     if (forced) {
-      const double2 fp = ld2(a.fx, rp, x), fm = ld2(a.fx, rm, x), rpp = ld2(rho, rp, x), rmm = ld2(rho, rm, x);
-      const double pf[2] = {fp.x, fp.y}, mf[2] = {fm.x, fm.y}, pr[2] = {rpp.x, rpp.y}, mr[2] = {rmm.x, rmm.y};
+      const double2 fp = ld2(a.fx, rp, x), fm = ld2(a.fx, rm, x);
+      const double pf[2] = {fp.x, fp.y}, mf[2] = {fm.x, fm.y};
 #pragma unroll
       for (int s = 0; s < 2; ++s) dyf[s] += c * (pf[s] / pr[s] - mf[s] / mr[s]);
     }
   }
   // x-derivatives from 10-value row segments, a few fields at a time
   {
-    double vux[10];
+    double vux[10], vuy[10], vr[10];
     seg10(ux, row, x, nx, vux);
+    seg10(uy, row, x, nx, vuy);
+    seg10(rho, row, x, nx, vr);
     {
-      double vuy[10], vsxx[10], vsxy[10];
-      seg10(uy, row, x, nx, vuy);
+      double vsxx[10], vsxy[10];
       seg10(sxx, row, x, nx, vsxx);
       seg10(sxy, row, x, nx, vsxy);
 #pragma unroll
@@ -546,56 +553,46 @@ __global__ void __launch_bounds__(256) k_bal_b2(PassArgs a) {
         }
       }
     }
-    {
-      double v[10];
-      seg10(E, row, x, nx, v);
-#pragma unroll
-      for (int m = 1; m <= 4; ++m) {
-        const double c = kFd8[m - 1];
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-          const int p = 4 + s + m, q = 4 + s - m;
-          dEx[s] += c * (v[p] * vux[p] - v[q] * vux[q]);
-        }
-      }
-      seg10(Om, row, x, nx, v);
-#pragma unroll
-      for (int m = 1; m <= 4; ++m) {
-        const double c = kFd8[m - 1];
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-          const int p = 4 + s + m, q = 4 + s - m;
-          dOx[s] += c * (v[p] * vux[p] - v[q] * vux[q]);
-        }
-      }
-    }
-  }
-  {
-    double v[10];
-    seg10(W, row, x, nx, v);
-    dx_pair(v, dxw);
-    cw[0] = v[4];
-    cw[1] = v[5];
-  }
-  if (forced) {
-    double vf[10], vr[10];
-    seg10(a.fy, row, x, nx, vf);
-    seg10(rho, row, x, nx, vr);
 #pragma unroll
     for (int m = 1; m <= 4; ++m) {
       const double c = kFd8[m - 1];
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
         const int p = 4 + s + m, q = 4 + s - m;
-        dxf[s] += c * (vf[p] / vr[p] - vf[q] / vr[q]);
+        dEx[s] += c * (energy(vr[p], vux[p], vuy[p]) * vux[p] - energy(vr[q], vux[q], vuy[q]) * vux[q]);
+      }
+    }
+    {
+      double v[10];
+      seg10(W, row, x, nx, v);
+      dx_pair(v, dxw);
+      cw[0] = v[4];
+      cw[1] = v[5];
+#pragma unroll
+      for (int m = 1; m <= 4; ++m) {
+        const double c = kFd8[m - 1];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+          const int p = 4 + s + m, q = 4 + s - m;
+          dOx[s] += c * (enstrophy(v[p]) * vux[p] - enstrophy(v[q]) * vux[q]);
+        }
+      }
+    }
+    if (forced) {
+      double vf[10];
+      seg10(a.fy, row, x, nx, vf);
+#pragma unroll
+      for (int m = 1; m <= 4; ++m) {
+        const double c = kFd8[m - 1];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+          const int p = 4 + s + m, q = 4 + s - m;
+          dxf[s] += c * (vf[p] / vr[p] - vf[q] / vr[q]);
+        }
       }
     }
     cr[0] = vr[4];
     cr[1] = vr[5];
-  } else {
-    const double2 r = ld2(rho, row, x);
-    cr[0] = r.x;
-    cr[1] = r.y;
   }
   double o[7][2];
 #pragma unroll
