@@ -145,6 +145,50 @@ __device__ __forceinline__ void gain_series(const EntropicSite& s, GainSeries& g
   }
 }
 
+// Newton's method on g(a) = 0 in the bracket [lo, hi], from a; with SERIES the
+// gain is the power series gs, else the logarithm form with c1.  A Newton step
+// below 1e-10 a ends it (quadratic convergence: the iterate is then within
+// ~1e-20 of the root), whether or not it stays inside the bracket: a step that
+// lands on the bracket's end (the gain's sign at the root decided by rounding)
+// used to fall back to bisection down to a 1e-15 bracket, up to 50 iterations,
+// and a wavefront runs as long as its slowest site.  Steps leaving the bracket
+// otherwise are replaced by bisection, which ends at a 1e-15 bracket.
+template <bool SERIES>
+__device__ __forceinline__ double newton_alpha(const EntropicSite& s, const GainSeries& gs, double c1,
+                                               double a, double lo, double hi) {
+  auto gain = [&](double x, double& dg) {
+    if constexpr (SERIES)
+      return gs.eval(x, dg);
+    else
+      return entropy_gain(s, c1, x, dg);
+  };
+  double dg;
+  double ga = gain(a, dg);
+  if (ga < 0.0) {
+    double dgh;
+    if (gain(hi, dgh) < 0.0) return hi;  // no root below the positivity limit
+    lo = a;
+  } else {
+    hi = a;
+  }
+  for (int it = 0; it < 64; ++it) {
+    const double step = ga / dg;
+    if (fabs(step) <= 1e-10 * a) return a - step;
+    double an = a - step;
+    if (!(an > lo && an < hi)) {
+      an = 0.5 * (lo + hi);
+      if (hi - lo <= 1e-15 * hi) return an;
+    }
+    a = an;
+    ga = gain(a, dg);
+    if (ga < 0.0)
+      lo = a;
+    else
+      hi = a;
+  }
+  return a;
+}
+
 __device__ double entropic_alpha(const EntropicSite& s) {
   double mr = 0.0, xmin = 0.0;
   double s2 = 0.0, s3 = 0.0, s4 = 0.0;  // sum f x^k: the expansion of the gain in x = delta / f
@@ -162,15 +206,6 @@ __device__ double entropic_alpha(const EntropicSite& s) {
   const double amax = xmin < 0.0 ? -1.0 / xmin : 1e300;  // every f + a delta > 0 below it
   // close to equilibrium the series replaces the logarithms, for a <= 3
   const bool series = mr < kSeriesMax;
-  GainSeries gs;
-  double c1 = 0.0;
-  if (series) {
-    gain_series(s, gs);
-  } else {
-#pragma unroll
-    for (int l = 0; l < 9; ++l) c1 += s.f[l] * s.x[l] * log1p(s.x[l]);
-  }
-  auto gain = [&](double a, double& dg) { return series ? gs.eval(a, dg) : entropy_gain(s, c1, a, dg); };
   double lo = 1.0, hi = amax < 1e300 ? amax * (1.0 - 1e-12) : 1e6;
   if (series) hi = fmin(hi, 3.0);  // the root lies within 2 +- O(mr); the series holds up to 3
   // start from the root of the gain expanded to fourth order around a = 2:
@@ -178,30 +213,15 @@ __device__ double entropic_alpha(const EntropicSite& s) {
   // (the expansion is only trusted close to 2: far from equilibrium start at 2)
   double a = 2.0 + (s3 - 2.0 * s4) / (3.0 * s2);
   if (!(fabs(a - 2.0) < 0.25 && a > lo && a < hi)) a = 2.0 < hi ? 2.0 : 0.5 * (lo + hi);
-  double dg;
-  double ga = gain(a, dg);
-  if (ga < 0.0) {
-    double dgh;
-    if (gain(hi, dgh) < 0.0) return hi;  // no root below the positivity limit
-    lo = a;
-  } else {
-    hi = a;
+  GainSeries gs;
+  if (series) {
+    gain_series(s, gs);
+    return newton_alpha<true>(s, gs, 0.0, a, lo, hi);
   }
-  for (int it = 0; it < 64; ++it) {
-    double an = a - ga / dg;
-    const bool newton = an > lo && an < hi;
-    if (!newton) an = 0.5 * (lo + hi);
-    // quadratic convergence: after a Newton step below 1e-10 the iterate is within
-    // ~1e-20 of the root; bisection steps run until the bracket itself is that small
-    if (newton ? fabs(an - a) <= 1e-10 * a : hi - lo <= 1e-15 * hi) return an;
-    a = an;
-    ga = gain(a, dg);
-    if (ga < 0.0)
-      lo = a;
-    else
-      hi = a;
-  }
-  return a;
+  double c1 = 0.0;
+#pragma unroll
+  for (int l = 0; l < 9; ++l) c1 += s.f[l] * s.x[l] * log1p(s.x[l]);
+  return newton_alpha<false>(s, gs, c1, a, lo, hi);
 }
 
 template <typename T, bool NT>
