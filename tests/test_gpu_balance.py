@@ -46,7 +46,8 @@ def term_tol(kappa, name, floor=1e-12):
 
 @pytest.mark.parametrize("n,sizes,force", [(64, (1, 4, 8, 16, 32, 63, 64), True),
                                             (256, (8, 32, 128, 256), True),
-                                            (96, (5, 16, 96), False)])
+                                            (96, (5, 16, 96), False),
+                                            (16, (1, 2, 3, 16), True)])
 def test_balance_fields_parity(gpu_lib, n, sizes, force):
     from paper_1809_06735_amd import balance_fields
     say(f"balance_fields n={n} sizes={sizes} force={force}")
@@ -124,6 +125,22 @@ def test_balance_1024_parity(gpu_lib):
         compare_stats(got, w, kk, label="1024 paired")
     res1 = balance_fields(lv["rho"], lv["ux"], lv["uy"], nu, (32,), fx=lv["fx"], fy=lv["fy"])
     compare_stats(res1["stats"][0], want[2], ks[2], label="1024 single")
+
+
+def test_balance_smallest_grids_paired_walks(gpu_lib):
+    """The smallest grids the library takes (16^2, and 16 x 18 with the even-width passes'
+    one 128-site tile mostly empty), sides 1, 2, 4, 8 without maps: the walks pair 1 with 2
+    and 4 with 8, and most windows wrap through the table totals."""
+    from paper_1809_06735_amd import balance_fields
+    for ny, nx in ((16, 16), (16, 18)):
+        say(f"balance_fields {ny}x{nx}, paired walks")
+        lv = inp.balance_levels(32, seed=5)
+        cut = {k: ([a[:ny, :nx] for a in v] if isinstance(v, list) else v[:ny, :nx]) for k, v in lv.items()}
+        sizes = (1, 2, 4, 8)
+        res = balance_fields(cut["rho"], cut["ux"], cut["uy"], 0.004, sizes, fx=cut["fx"], fy=cut["fy"])
+        _, want, _, ks = balance_sensitivity(cut, 0.004, sizes, cut["fx"], cut["fy"])
+        for got, w, kk in zip(res["stats"], want, ks):
+            compare_stats(got, w, kk, label=f"{ny}x{nx} paired")
 
 
 def test_decay1024_run_balance_paired_walks_against_oracle(gpu_lib):
