@@ -253,82 +253,150 @@ __global__ void __launch_bounds__(kAT) k_adj_init(const T* __restrict__ g, T* __
 }
 
 // C'(f)^T v + M'(f)^T (rho_hat, u_hat) for one site; returns v . (f - f^eq)/tau^2.
-template <typename T>
-__device__ __forceinline__ double adjoint_site(const T (&d)[9], const T (&v)[9], T om, bool seed,
-                                               double rh, double sx, double sy, T (&o)[9]) {
+//
+// With P_l = 1 + 3 c_l.u + 4.5 (c_l.u)^2 - 1.5 |u|^2 (Eq. 2: f^eq_l = w_l rho P_l),
+// the transpose of the collision's Jacobian maps v to
+//   r_k = (1 - omega) v_k + omega [A + B . (c_k - u)],
+//   A = sum_l w_l v_l P_l,  B = sum_l w_l v_l dP_l/du = sum_l w_l v_l (3 c_l + 9 (c_l.u) c_l - 3 u)
+// (the rho of df^eq/du cancels the 1/rho of du/df).  A and B are linear in v, so
+// they follow from the weighted moments of v, V = sum w v, V_a = sum w c_a v and
+// V_ab = sum w c_a c_b v:  A = (1 - 1.5 |u|^2) V + 3 u.V_a + 4.5 u.V_ab.u and
+// B = 3 (V_a - u V) + 9 V_ab.u.  The non-equilibrium part d_l - f^eq_l is formed
+// per velocity (it is small against either term), opposite velocities sharing the
+// even and odd parts of f^eq.
+template <typename T, bool SEED>
+__device__ __forceinline__ double adjoint_site(const T (&d)[9], const T (&v)[9], T om, double rh,
+                                               double sx, double sy, T (&o)[9]) {
   SiteMoments<T, false> m(d, T(0), T(0), T(0));
-  const T usq15 = T(1.5) * (m.ux * m.ux + m.uy * m.uy);
-  T A = T(0), Bx = T(0), By = T(0), neq = T(0);
-#pragma unroll
-  for (int l = 0; l < 9; ++l) {
-    const T w = T(wq(l));
-    const T cx = T(cxq(l)), cy = T(cyq(l));
-    const T cu = cx * m.ux + cy * m.uy;
-    const T P = T(1) + T(3) * cu + T(4.5) * cu * cu - usq15;
-    const T deq = w * (m.drho + m.rho * (P - T(1)));
-    A += v[l] * w * P;
-    Bx += v[l] * w * (T(3) * cx + T(9) * cu * cx - T(3) * m.ux);
-    By += v[l] * w * (T(3) * cy + T(9) * cu * cy - T(3) * m.uy);
-    neq += v[l] * (d[l] - deq);
-  }
-  Bx *= m.rho;
-  By *= m.rho;
-  const T inv = T(1) / m.rho;
+  const T ux = m.ux, uy = m.uy;
+  const T usq15 = T(1.5) * (ux * ux + uy * uy);
+  const T wa = T(wq(1)), wd = T(wq(5));
+  // weighted moments of v (axis velocities 1..4, diagonals 5..8)
+  const T ax = v[1] + v[3], ay = v[2] + v[4];
+  const T dp = v[5] + v[7], dm = v[6] + v[8];
+  const T V0 = T(wq(0)) * v[0] + wa * (ax + ay) + wd * (dp + dm);
+  const T Vx = wa * (v[1] - v[3]) + wd * ((v[5] - v[7]) + (v[8] - v[6]));
+  const T Vy = wa * (v[2] - v[4]) + wd * ((v[5] - v[7]) + (v[6] - v[8]));
+  const T Vxx = wa * ax + wd * (dp + dm);
+  const T Vyy = wa * ay + wd * (dp + dm);
+  const T Vxy = wd * (dp - dm);
+  const T uVx = ux * Vxx + uy * Vxy, uVy = ux * Vxy + uy * Vyy;   // sum_l w_l v_l (c_l.u) c_l
+  const T A = (T(1) - usq15) * V0 + T(3) * (ux * Vx + uy * Vy) + T(4.5) * (ux * uVx + uy * uVy);
+  const T Bx = T(3) * (Vx - ux * V0) + T(9) * uVx;
+  const T By = T(3) * (Vy - uy * V0) + T(9) * uVy;
+  // v . (d - f^eq) in deviation form: f^eq_l - w_l = w_l (drho + rho (P_l - 1))
+  const T base = m.drho - m.rho * usq15;
+  const T r45 = T(4.5) * m.rho, r3 = T(3) * m.rho;
+  T neq = v[0] * (d[0] - T(wq(0)) * base);
+  auto pair = [&](int l, int lb, T w, T cu) {
+    const T e = w * (base + r45 * cu * cu), od = w * (r3 * cu);
+    neq += v[l] * ((d[l] - e) - od) + v[lb] * ((d[lb] - e) + od);
+  };
+  pair(1, 3, wa, ux);
+  pair(2, 4, wa, uy);
+  pair(5, 7, wd, ux + uy);
+  pair(6, 8, wd, uy - ux);
+  const T keep = T(1) - om;
+  const T G = om * (A - (Bx * ux + By * uy)), Hx = om * Bx, Hy = om * By;
+  const double inv_rho = SEED ? 1.0 / double(m.rho) : 0.0;
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
-    const T ex = T(cxq(k)) - m.ux, ey = T(cyq(k)) - m.uy;
-    T r = (T(1) - om) * v[k] + om * (A + (Bx * ex + By * ey) * inv);
-    if (seed) r += T(rh + (sx * double(ex) + sy * double(ey)) / double(m.rho));
+    T r = keep * v[k] + G;
+    if (cxq(k) != 0) r = cxq(k) > 0 ? r + Hx : r - Hx;
+    if (cyq(k) != 0) r = cyq(k) > 0 ? r + Hy : r - Hy;
+    if constexpr (SEED) {
+      const T ex = T(cxq(k)) - ux, ey = T(cyq(k)) - uy;
+      r += T(rh + (sx * double(ex) + sy * double(ey)) * inv_rho);
+    }
     o[k] = r;
   }
   return double(neq) * double(om) * double(om);
 }
 
-// One backward step over a tile of (blockDim.x * VX) x (blockDim.y * ry) sites (the
-// step kernel's tiling and XCD-aware numbering); adds the tile's sum of
-// v . dC/dtau to its own slot of tau_acc.
-template <typename T, int VX>
+// Element (l, y, x) of a state in the row layout sits at (9 y + l) nx + x.  When
+// a state spans less than 4 GiB, a site's byte offset fits 32 bits: each load is
+// then a per-plane base (uniform, in scalar registers) plus a 32-bit lane offset
+// that all nine planes share, with no 64-bit address arithmetic per access.
+template <typename T>
+__device__ __forceinline__ T ld_at(const T* __restrict__ plane, uint32_t byte_off) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(plane) + byte_off);
+}
+template <typename T>
+__device__ __forceinline__ void st_at(T* __restrict__ plane, uint32_t byte_off, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(plane) + byte_off) = v;
+}
+
+// One backward step over a tile of blockDim.x x (blockDim.y * ry) sites, one site
+// per thread (the step kernel's XCD-aware tile numbering): a^t(x) from f^t pulled
+// at x and a^{t+1}(x + c_l); adds the tile's sum of v . dC/dtau to its own slot of
+// tau_acc.  SEED adds the loss seeds of the last two steps; OFF32 takes the
+// 32-bit offset path above.
+template <typename T, bool SEED, bool OFF32>
 __global__ void __launch_bounds__(512) k_adj_step(const T* __restrict__ g, const T* __restrict__ ain,
-                                                   T* __restrict__ aout, Seeds s, int has_seed,
-                                                   PopLayout lay, int nx, int ny, double omega,
-                                                   double* tau_acc, int tiles_x, int total,
+                                                   T* __restrict__ aout, Seeds s, int nx, int ny,
+                                                   double omega, double* tau_acc, int tiles_x, int total,
                                                    int per_xcd, int ry) {
   __shared__ double sh[16];
   const int b = blockIdx.x;
   const int tile = (b & 7) * per_xcd + (b >> 3);
   if (tile >= total) return;
   const int tx = tile % tiles_x, ty = tile / tiles_x;
-  const int x0 = (tx * blockDim.x + threadIdx.x) * VX;
+  const int x = tx * blockDim.x + threadIdx.x;
   const int ybase = (ty * blockDim.y + threadIdx.y) * ry;
+  const size_t ps = static_cast<size_t>(nx), rs = 9 * ps;   // the row layout's strides
   const T om = T(omega);
   double dtau = 0.0;
-  if (x0 < nx) {
+  if (x < nx) {
+    const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
     for (int k = 0; k < ry; ++k) {
       const int y = ybase + k;
       if (y >= ny) break;
       const int yn = (y == 0) ? ny - 1 : y - 1;
       const int yp = (y == ny - 1) ? 0 : y + 1;
-      T d[9][VX], v[9][VX], o[9][VX];
-      pull_all<T, VX>(g, lay.ps, lay.rs, nx, x0, y, yn, yp, d);        // f^t(x) - w
-      pull_all_rev<T, VX>(ain, lay.ps, lay.rs, nx, x0, y, yn, yp, v);  // a^{t+1}(x + c_l)
-      const size_t row = static_cast<size_t>(y) * nx + x0;
-#pragma unroll
-      for (int i = 0; i < VX; ++i) {
-        T di[9], vi[9], oi[9];
+      T d[9], v[9], o[9];
+      if constexpr (OFF32) {
+        // byte offsets of the row starts (plane 0) and of the three columns
+        const uint32_t rs = 9u * static_cast<uint32_t>(nx) * sizeof(T);
+        const uint32_t rn = static_cast<uint32_t>(yn) * rs, r0 = static_cast<uint32_t>(y) * rs,
+                       rp = static_cast<uint32_t>(yp) * rs;
+        const uint32_t cm = static_cast<uint32_t>(xm) * sizeof(T), c0 = static_cast<uint32_t>(x) * sizeof(T),
+                       cp = static_cast<uint32_t>(xp) * sizeof(T);
+        auto row = [&](int dy) { return dy > 0 ? rp : (dy < 0 ? rn : r0); };
+        auto col = [&](int dx) { return dx > 0 ? cp : (dx < 0 ? cm : c0); };
 #pragma unroll
         for (int l = 0; l < 9; ++l) {
-          di[l] = d[l][i];
-          vi[l] = v[l][i];
+          // f^t_l(x - c_l) and a^{t+1}_l(x + c_l)
+          d[l] = ld_at(g + l * nx, row(-cyq(l)) + col(-cxq(l)));
+          v[l] = ld_at(ain + l * nx, row(cyq(l)) + col(cxq(l)));
         }
-        const double rh = (has_seed && s.rho) ? s.rho[row + i] : 0.0;
-        const double sx = has_seed ? s.ux[row + i] : 0.0, sy = has_seed ? s.uy[row + i] : 0.0;
-        dtau += adjoint_site<T>(di, vi, om, has_seed != 0, rh, sx, sy, oi);
+      } else {
+        T dd[9][1], vv[9][1];
+        pull_all<T, 1>(g, ps, rs, nx, x, y, yn, yp, dd);
+        pull_all_rev<T, 1>(ain, ps, rs, nx, x, y, yn, yp, vv);
 #pragma unroll
-        for (int l = 0; l < 9; ++l) o[l][i] = oi[l];
+        for (int l = 0; l < 9; ++l) {
+          d[l] = dd[l][0];
+          v[l] = vv[l][0];
+        }
       }
+      double rh = 0.0, sx = 0.0, sy = 0.0;
+      if constexpr (SEED) {
+        const size_t i = static_cast<size_t>(y) * nx + x;
+        rh = s.rho ? s.rho[i] : 0.0;
+        sx = s.ux[i];
+        sy = s.uy[i];
+      }
+      dtau += adjoint_site<T, SEED>(d, v, om, rh, sx, sy, o);
+      if constexpr (OFF32) {
+        const uint32_t at = static_cast<uint32_t>(y) * (9u * static_cast<uint32_t>(nx) * sizeof(T)) +
+                            static_cast<uint32_t>(x) * sizeof(T);
 #pragma unroll
-      for (int l = 0; l < 9; ++l)
-        store_aligned<T, VX, false>(aout + l * lay.ps + static_cast<size_t>(y) * lay.rs + x0, o[l]);
+        for (int l = 0; l < 9; ++l) st_at(aout + l * nx, at, o[l]);
+      } else {
+        T* const out = aout + static_cast<size_t>(y) * rs + x;
+#pragma unroll
+        for (int l = 0; l < 9; ++l) out[l * ps] = o[l];
+      }
     }
   }
 #pragma unroll
@@ -374,7 +442,7 @@ __global__ void k_zero(double* p, size_t n) {
 // ---- workspace ------------------------------------------------------------------------
 struct AdjWs {
   void* ckpt;          // [nck][9][plane] storage type
-  void* seg;           // [K+1][9][plane]
+  void* seg[2];        // [K+1][9][plane] each; the second only with two or more segments
   void* adj[2];        // [9][plane]
   double* mom[3][3];   // levels T-2, T-1, T: rho, ux, uy
   double* r;           // residual field
@@ -397,7 +465,9 @@ AdjWs carve_adj(const lbm_adjoint_config& c, void* base, size_t cap) {
   const int64_t nck = (c.steps + c.ckpt_every - 1) / c.ckpt_every;
   AdjWs w{};
   w.ckpt = cv.take<char>(static_cast<size_t>(nck) * 9 * plane * es);
-  w.seg = cv.take<char>(static_cast<size_t>(c.ckpt_every + 1) * 9 * plane * es);
+  const size_t seg_bytes = static_cast<size_t>(c.ckpt_every + 1) * 9 * plane * es;
+  w.seg[0] = cv.take<char>(seg_bytes);
+  w.seg[1] = cv.take<char>(nck > 1 ? seg_bytes : 0);
   w.adj[0] = cv.take<char>(9 * plane * es);
   w.adj[1] = cv.take<char>(9 * plane * es);
   for (int l = 0; l < 3; ++l)
@@ -441,34 +511,27 @@ int launch_adj_init(const void* g, void* adj, Seeds s, int nx, int ny, hipStream
   return LBM_OK;
 }
 
-template <typename T, int VX>
-int launch_adj_step_t(const void* g, const void* ain, void* aout, Seeds s, int has_seed, int nx, int ny,
-                      double omega, double* tau_acc, const lbm_tile& t, hipStream_t st) {
-  const int tiles_x = (nx / VX + t.bx - 1) / t.bx;
+// One backward step in the launch shape t (its bx, by and ry; one site per thread).
+template <typename T>
+int launch_adj_step(const void* g, const void* ain, void* aout, Seeds s, int has_seed, int nx, int ny,
+                    double omega, double* tau_acc, const lbm_tile& t, hipStream_t st) {
+  const int tiles_x = (nx + t.bx - 1) / t.bx;
   const int tiles_y = (ny + t.by * t.ry - 1) / (t.by * t.ry);
   const int total = tiles_x * tiles_y;
   const int per_xcd = (total + 7) / 8;
-  hipLaunchKernelGGL((k_adj_step<T, VX>), dim3(per_xcd * 8), dim3(t.bx, t.by), 0, st,
-                     static_cast<const T*>(g), static_cast<const T*>(ain), static_cast<T*>(aout), s,
-                     has_seed, pop_layout(kAdjLayout, nx, ny), nx, ny, omega, tau_acc, tiles_x, total,
-                     per_xcd, t.ry);
+  const bool off32 = 9ull * static_cast<uint64_t>(nx) * ny * sizeof(T) <= 0xffffffffull;
+  auto kern = has_seed ? (off32 ? k_adj_step<T, true, true> : k_adj_step<T, true, false>)
+                       : (off32 ? k_adj_step<T, false, true> : k_adj_step<T, false, false>);
+  hipLaunchKernelGGL(kern, dim3(per_xcd * 8), dim3(t.bx, t.by), 0, st, static_cast<const T*>(g),
+                     static_cast<const T*>(ain), static_cast<T*>(aout), s, nx, ny, omega, tau_acc, tiles_x,
+                     total, per_xcd, t.ry);
   LBM_HIP(hipGetLastError());
   return LBM_OK;
 }
 
-template <typename T>
-int launch_adj_step(const void* g, const void* ain, void* aout, Seeds s, int has_seed, int nx, int ny,
-                    double omega, double* tau_acc, const lbm_tile& t, hipStream_t st) {
-  switch (t.vx) {
-    case 1: return launch_adj_step_t<T, 1>(g, ain, aout, s, has_seed, nx, ny, omega, tau_acc, t, st);
-    case 2: return launch_adj_step_t<T, 2>(g, ain, aout, s, has_seed, nx, ny, omega, tau_acc, t, st);
-    default: return launch_adj_step_t<T, 4>(g, ain, aout, s, has_seed, nx, ny, omega, tau_acc, t, st);
-  }
-}
-
 // number of tiles of a launch shape (slots of the tau accumulator)
 int tile_count(int nx, int ny, const lbm_tile& t) {
-  return ((nx / t.vx + t.bx - 1) / t.bx) * ((ny + t.by * t.ry - 1) / (t.by * t.ry));
+  return ((nx + t.bx - 1) / t.bx) * ((ny + t.by * t.ry - 1) / (t.by * t.ry));
 }
 
 template <typename T>
@@ -489,7 +552,7 @@ struct Runner {
   size_t plane, state_bytes;
   lbm_tile tile;   // single-step shape (the segments keep every intermediate state)
   lbm_tile ftile;  // shape of the first forward pass, which keeps only checkpoints
-  void* seg_state(int k) const { return static_cast<char*>(w.seg) + k * state_bytes; }
+  void* seg_state(int b, int k) const { return static_cast<char*>(w.seg[b]) + k * state_bytes; }
   void* ckpt_state(int64_t k) const { return static_cast<char*>(w.ckpt) + k * state_bytes; }
 
   int step(const void* src, void* dst, double* hr, double* hx, double* hy) {
@@ -514,15 +577,24 @@ struct Runner {
   }
 };
 
-// Graphs captured on a private stream, destroyed with the cache.
+// Graphs captured on a private stream, destroyed with the cache, and the
+// second stream on which the backward pass recomputes the next segment.
 struct GraphCache {
   hipStream_t cs = nullptr;
   hipStream_t main = nullptr;   // replays go here; synchronised before the graphs are freed
-  hipGraphExec_t fwd = nullptr;
+  hipStream_t rs = nullptr;     // recomputation stream (default priority, like every stream here)
+  hipEvent_t go = nullptr, fwd_done[2] = {nullptr, nullptr}, bwd_done[2] = {nullptr, nullptr};
+  hipGraphExec_t fwd[2] = {nullptr, nullptr};   // K steps through segment buffer b
   hipGraphExec_t ffwd = nullptr;  // first pass: K steps, intermediate states not kept
-  hipGraphExec_t bwd[2] = {nullptr, nullptr};
+  hipGraphExec_t bwd[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // [adjoint parity][buffer]
   int init() {
     LBM_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    LBM_HIP(hipStreamCreateWithFlags(&rs, hipStreamNonBlocking));
+    LBM_HIP(hipEventCreateWithFlags(&go, hipEventDisableTiming));
+    for (int b = 0; b < 2; ++b) {
+      LBM_HIP(hipEventCreateWithFlags(&fwd_done[b], hipEventDisableTiming));
+      LBM_HIP(hipEventCreateWithFlags(&bwd_done[b], hipEventDisableTiming));
+    }
     return LBM_OK;
   }
   template <class F>
@@ -543,10 +615,16 @@ struct GraphCache {
   }
   ~GraphCache() {
     if (main) (void)hipStreamSynchronize(main);
-    if (fwd) (void)hipGraphExecDestroy(fwd);
+    if (rs) (void)hipStreamSynchronize(rs);
+    for (auto& f : fwd)
+      if (f) (void)hipGraphExecDestroy(f);
     if (ffwd) (void)hipGraphExecDestroy(ffwd);
-    for (auto& b : bwd)
-      if (b) (void)hipGraphExecDestroy(b);
+    for (auto& bp : bwd)
+      for (auto& b : bp)
+        if (b) (void)hipGraphExecDestroy(b);
+    for (hipEvent_t e : {go, fwd_done[0], fwd_done[1], bwd_done[0], bwd_done[1]})
+      if (e) (void)hipEventDestroy(e);
+    if (rs) (void)hipStreamDestroy(rs);
     if (cs) (void)hipStreamDestroy(cs);
   }
 };
@@ -615,20 +693,21 @@ int lbm_adjoint_run(const lbm_adjoint_config* cfg, void* ws, size_t ws_bytes, co
   if (int rc = gc.init()) return rc;
   auto seg_len = [&](int64_t sg) { return std::min<int64_t>(sg * K + K, T) - sg * K; };
   auto seg_plain = [&](int64_t sg) { return seg_len(sg) == K && sg * K + K <= T - 2; };
-  auto forward_segment = [&](int64_t sg, bool record) -> int {
+  // segment sg from its checkpoint through segment buffer b on stream st
+  auto forward_segment = [&](int64_t sg, bool record, int b, hipStream_t st) -> int {
     const int64_t t0 = sg * K, len = seg_len(sg);
-    LBM_HIP(hipMemcpyAsync(R.seg_state(0), R.ckpt_state(sg), R.state_bytes, hipMemcpyDeviceToDevice, s));
+    LBM_HIP(hipMemcpyAsync(R.seg_state(b, 0), R.ckpt_state(sg), R.state_bytes, hipMemcpyDeviceToDevice, st));
     if (seg_plain(sg)) {
-      if (!gc.fwd) {
-        if (int rc = gc.capture(&gc.fwd, [&](hipStream_t cs) -> int {
+      if (!gc.fwd[b]) {
+        if (int rc = gc.capture(&gc.fwd[b], [&](hipStream_t cs) -> int {
               for (int k = 0; k < K; ++k)
-                if (int r2 = R.step_on(cs, R.seg_state(k), R.seg_state(k + 1), nullptr, nullptr, nullptr))
+                if (int r2 = R.step_on(cs, R.seg_state(b, k), R.seg_state(b, k + 1), nullptr, nullptr, nullptr))
                   return r2;
               return LBM_OK;
             }))
           return rc;
       }
-      LBM_HIP(hipGraphLaunch(gc.fwd, s));
+      LBM_HIP(hipGraphLaunch(gc.fwd[b], st));
       return LBM_OK;
     }
     for (int64_t k = 0; k < len; ++k) {
@@ -638,8 +717,8 @@ int lbm_adjoint_run(const lbm_adjoint_config* cfg, void* ws, size_t ws_bytes, co
         const int lv = static_cast<int>(t - (T - 2));
         for (int q = 0; q < 3; ++q) h[q] = R.w.mom[lv][q];
       }
-      if (int rc = R.step(R.seg_state(static_cast<int>(k)), R.seg_state(static_cast<int>(k + 1)), h[0],
-                          h[1], h[2]))
+      if (int rc = R.step_on(st, R.seg_state(b, static_cast<int>(k)), R.seg_state(b, static_cast<int>(k + 1)),
+                             h[0], h[1], h[2]))
         return rc;
     }
     return LBM_OK;
@@ -650,15 +729,15 @@ int lbm_adjoint_run(const lbm_adjoint_config* cfg, void* ws, size_t ws_bytes, co
   const int spl = steps_per_launch(R.ftile);
   const int ff_par = (K / spl + K % spl) & 1;
   auto fast_segment = [&](int64_t sg) -> int {
-    LBM_HIP(hipMemcpyAsync(R.seg_state(0), R.ckpt_state(sg), R.state_bytes, hipMemcpyDeviceToDevice, s));
+    LBM_HIP(hipMemcpyAsync(R.seg_state(0, 0), R.ckpt_state(sg), R.state_bytes, hipMemcpyDeviceToDevice, s));
     if (!gc.ffwd) {
       if (int rc = gc.capture(&gc.ffwd, [&](hipStream_t cs) -> int {
             int p = 0;
             for (int k = 0; k + spl <= K; k += spl, p ^= 1)
-              if (int r2 = R.step_on(cs, R.seg_state(p), R.seg_state(p ^ 1), nullptr, nullptr, nullptr, true))
+              if (int r2 = R.step_on(cs, R.seg_state(0, p), R.seg_state(0, p ^ 1), nullptr, nullptr, nullptr, true))
                 return r2;
             for (int k = 0; k < K % spl; ++k, p ^= 1)
-              if (int r2 = R.step_on(cs, R.seg_state(p), R.seg_state(p ^ 1), nullptr, nullptr, nullptr))
+              if (int r2 = R.step_on(cs, R.seg_state(0, p), R.seg_state(0, p ^ 1), nullptr, nullptr, nullptr))
                 return r2;
             return LBM_OK;
           }))
@@ -670,16 +749,16 @@ int lbm_adjoint_run(const lbm_adjoint_config* cfg, void* ws, size_t ws_bytes, co
   for (int64_t sg = 0; sg < nseg; ++sg) {
     if (seg_plain(sg) && sg + 1 < nseg) {
       if (int rc = fast_segment(sg)) return rc;
-      LBM_HIP(hipMemcpyAsync(R.ckpt_state(sg + 1), R.seg_state(ff_par), R.state_bytes,
+      LBM_HIP(hipMemcpyAsync(R.ckpt_state(sg + 1), R.seg_state(0, ff_par), R.state_bytes,
                              hipMemcpyDeviceToDevice, s));
       continue;
     }
-    if (int rc = forward_segment(sg, true)) return rc;
+    if (int rc = forward_segment(sg, true, 0, s)) return rc;
     if (sg + 1 < nseg)
-      LBM_HIP(hipMemcpyAsync(R.ckpt_state(sg + 1), R.seg_state(static_cast<int>(seg_len(sg))),
+      LBM_HIP(hipMemcpyAsync(R.ckpt_state(sg + 1), R.seg_state(0, static_cast<int>(seg_len(sg))),
                              R.state_bytes, hipMemcpyDeviceToDevice, s));
   }
-  void* cur = R.seg_state(static_cast<int>(seg_len(nseg - 1)));   // g^T
+  void* cur = R.seg_state(0, static_cast<int>(seg_len(nseg - 1)));   // g^T
   {
     MomentParams m{};
     m.pop = cur;
@@ -747,6 +826,26 @@ int lbm_adjoint_run(const lbm_adjoint_config* cfg, void* ws, size_t ws_bytes, co
     return LBM_OK;
   }
 
+  // The backward pass sweeps segment sg from buffer (nseg - 1 - sg) & 1 (the last
+  // segment's states are still in buffer 0 from the forward pass) while the second
+  // stream recomputes segment sg - 1 into the other buffer from its checkpoint.
+  // A recomputation waits for the sweep that last read its buffer; a sweep waits
+  // for its recomputation.  Kernels and operands are those of a one-stream run.
+  auto buf_of = [&](int64_t sg) { return static_cast<int>((nseg - 1 - sg) & 1); };
+  auto recompute = [&](int64_t sg) -> int {
+    const int b = buf_of(sg);
+    if (sg + 2 <= nseg - 1) LBM_HIP(hipStreamWaitEvent(gc.rs, gc.bwd_done[b], 0));
+    if (int rc = forward_segment(sg, false, b, gc.rs)) return rc;
+    LBM_HIP(hipEventRecord(gc.fwd_done[b], gc.rs));
+    return LBM_OK;
+  };
+  if (nseg >= 2) {
+    // checkpoints are complete once the forward pass's work on s is
+    LBM_HIP(hipEventRecord(gc.go, s));
+    LBM_HIP(hipStreamWaitEvent(gc.rs, gc.go, 0));
+    if (int rc = recompute(nseg - 2)) return rc;
+  }
+
   // ---- loss adjoint: seeds at T, T-1, T-2 and the explicit nu derivative ----
   AdjLoss al{};
   al.rho = R.w.mom[2][0];
@@ -788,27 +887,26 @@ int lbm_adjoint_run(const lbm_adjoint_config* cfg, void* ws, size_t ws_bytes, co
   for (int64_t sg = nseg - 1; sg >= 0; --sg) {
     const int64_t t0 = sg * K;
     const int64_t t1 = t0 + seg_len(sg);
-    // the last segment's states are still in the buffer from the forward pass
-    if (sg != nseg - 1)
-      if (int rc = forward_segment(sg, false)) return rc;
+    const int b = buf_of(sg);
+    if (sg != nseg - 1) LBM_HIP(hipStreamWaitEvent(s, gc.fwd_done[b], 0));
     if (sg == nseg - 1) {
-      const void* gT = R.seg_state(static_cast<int>(t1 - t0));
+      const void* gT = R.seg_state(b, static_cast<int>(t1 - t0));
       const int rc = f32 ? launch_adj_init<float>(gT, R.w.adj[par], sT, nx, ny, s)
                          : launch_adj_init<double>(gT, R.w.adj[par], sT, nx, ny, s);
       if (rc) return rc;
     }
     const bool seeded = t1 >= T - 1;   // holds t = T-1 or T-2
     if (seg_len(sg) == K && !seeded) {
-      hipGraphExec_t& gb = gc.bwd[par];
+      hipGraphExec_t& gb = gc.bwd[par][b];
       if (!gb) {
         const int p0 = par;
         if (int rc = gc.capture(&gb, [&](hipStream_t cs) -> int {
               int pp = p0;
               for (int k = K - 1; k >= 0; --k) {
-                const int r2 = f32 ? launch_adj_step<float>(R.seg_state(k), R.w.adj[pp], R.w.adj[pp ^ 1], s2, 0,
-                                                            nx, ny, omega, R.w.tau_acc, R.tile, cs)
-                                   : launch_adj_step<double>(R.seg_state(k), R.w.adj[pp], R.w.adj[pp ^ 1], s2,
-                                                             0, nx, ny, omega, R.w.tau_acc, R.tile, cs);
+                const int r2 = f32 ? launch_adj_step<float>(R.seg_state(b, k), R.w.adj[pp], R.w.adj[pp ^ 1], s2,
+                                                            0, nx, ny, omega, R.w.tau_acc, R.tile, cs)
+                                   : launch_adj_step<double>(R.seg_state(b, k), R.w.adj[pp], R.w.adj[pp ^ 1],
+                                                             s2, 0, nx, ny, omega, R.w.tau_acc, R.tile, cs);
                 if (r2) return r2;
                 pp ^= 1;
               }
@@ -818,18 +916,22 @@ int lbm_adjoint_run(const lbm_adjoint_config* cfg, void* ws, size_t ws_bytes, co
       }
       LBM_HIP(hipGraphLaunch(gb, s));
       par ^= (K & 1);
-      continue;
+    } else {
+      for (int64_t t = t1 - 1; t >= t0; --t) {
+        const bool seed = (t == T - 1) || (t == T - 2);
+        const Seeds sd = (t == T - 1) ? s1 : s2;
+        const void* gt = R.seg_state(b, static_cast<int>(t - t0));
+        const int rc = f32 ? launch_adj_step<float>(gt, R.w.adj[par], R.w.adj[par ^ 1], sd, seed ? 1 : 0, nx,
+                                                    ny, omega, R.w.tau_acc, R.tile, s)
+                           : launch_adj_step<double>(gt, R.w.adj[par], R.w.adj[par ^ 1], sd, seed ? 1 : 0, nx,
+                                                     ny, omega, R.w.tau_acc, R.tile, s);
+        if (rc) return rc;
+        par ^= 1;
+      }
     }
-    for (int64_t t = t1 - 1; t >= t0; --t) {
-      const bool seed = (t == T - 1) || (t == T - 2);
-      const Seeds sd = (t == T - 1) ? s1 : s2;
-      const void* gt = R.seg_state(static_cast<int>(t - t0));
-      const int rc = f32 ? launch_adj_step<float>(gt, R.w.adj[par], R.w.adj[par ^ 1], sd, seed ? 1 : 0, nx, ny,
-                                                  omega, R.w.tau_acc, R.tile, s)
-                         : launch_adj_step<double>(gt, R.w.adj[par], R.w.adj[par ^ 1], sd, seed ? 1 : 0, nx,
-                                                   ny, omega, R.w.tau_acc, R.tile, s);
-      if (rc) return rc;
-      par ^= 1;
+    if (sg >= 2) {
+      LBM_HIP(hipEventRecord(gc.bwd_done[b], s));
+      if (int rc = recompute(sg - 2)) return rc;
     }
   }
   void* ain = R.w.adj[par];
