@@ -511,7 +511,9 @@ LBM_API int lbm_batch_destroy(lbm_batch b);
  * (RHS^Omega_V - LHS^Omega_V)^2 (Eq. 11 residual at the last step; a box of
  * side nx == ny is one window).  The gradient is obtained by a discrete
  * adjoint sweep: checkpoints of the populations every ckpt_every steps, each
- * segment recomputed forward and swept backward. */
+ * segment recomputed forward and swept backward.  With two or more segments the
+ * workspace holds two segment buffers: a stream of the library's own recomputes
+ * the next segment while the current one is swept (results do not depend on it). */
 typedef struct {
   int32_t nx, ny;
   int32_t dtype;        /* LBM_F32 or LBM_F64 populations and adjoint states   */
