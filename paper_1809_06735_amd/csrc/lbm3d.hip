@@ -937,6 +937,43 @@ struct Run3 {
   __device__ void store(double* p) const { p[0] = n, p[1] = mean, p[2] = m2, p[3] = mn, p[4] = mx, p[5] = nan; }
 };
 
+// Merge of a thread's three accumulators across its workgroup (a lane-independent
+// butterfly in each wavefront, then the wavefronts in order) into the workgroup's partial.
+// lane = index in the wavefront, wv = wavefront index, nwv wavefronts (at most 4).
+__device__ void w3_block_partial(Run3 (&r)[3], int lane, int wv, int nwv, double* out) {
+#pragma unroll
+  for (int q = 0; q < 3; ++q)
+    for (int off = 1; off < 64; off <<= 1) {
+      Run3 o;
+      o.n = __shfl_xor(r[q].n, off, 64);
+      o.mean = __shfl_xor(r[q].mean, off, 64);
+      o.m2 = __shfl_xor(r[q].m2, off, 64);
+      o.mn = __shfl_xor(r[q].mn, off, 64);
+      o.mx = __shfl_xor(r[q].mx, off, 64);
+      o.nan = __shfl_xor(r[q].nan, off, 64);
+      if ((lane & off) == 0) {
+        r[q].merge(o);
+      } else {
+        o.merge(r[q]);
+        r[q] = o;
+      }
+    }
+  __shared__ double sh[4][kW3Vals];
+  if (lane == 0)
+    for (int q = 0; q < 3; ++q) r[q].store(&sh[wv][q * 6]);
+  __syncthreads();
+  if (wv == 0 && lane < 3) {
+    const int q = lane;
+    Run3 acc, b;
+    acc.load(&sh[0][q * 6]);
+    for (int w = 1; w < nwv; ++w) {
+      b.load(&sh[w][q * 6]);
+      acc.merge(b);
+    }
+    acc.store(out + q * 6);
+  }
+}
+
 __global__ void __launch_bounds__(kW3Threads) k3_windows(Vol v, int L, size_t count, double* partials) {
   Run3 r[3];
 #pragma unroll
@@ -952,39 +989,100 @@ __global__ void __launch_bounds__(kW3Threads) k3_windows(Vol v, int L, size_t co
 #pragma unroll
     for (int q = 0; q < 3; ++q) r[q].add(val[q]);
   }
-  // wavefront: butterfly merges in a lane-independent order (both lanes of a pair end equal)
-#pragma unroll
-  for (int q = 0; q < 3; ++q)
-    for (int off = 1; off < 64; off <<= 1) {
-      Run3 o;
-      o.n = __shfl_xor(r[q].n, off, 64);
-      o.mean = __shfl_xor(r[q].mean, off, 64);
-      o.m2 = __shfl_xor(r[q].m2, off, 64);
-      o.mn = __shfl_xor(r[q].mn, off, 64);
-      o.mx = __shfl_xor(r[q].mx, off, 64);
-      o.nan = __shfl_xor(r[q].nan, off, 64);
-      if ((threadIdx.x & off) == 0) {
-        r[q].merge(o);
-      } else {
-        o.merge(r[q]);
-        r[q] = o;
-      }
-    }
-  __shared__ double sh[kW3Threads / 64][kW3Vals];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (lane == 0)
-    for (int q = 0; q < 3; ++q) r[q].store(&sh[wv][q * 6]);
-  __syncthreads();
-  if (threadIdx.x < 3) {
-    const int q = threadIdx.x;
-    Run3 acc, b;
-    acc.load(&sh[0][q * 6]);
-    for (int w = 1; w < kW3Threads / 64; ++w) {
-      b.load(&sh[w][q * 6]);
-      acc.merge(b);
-    }
-    acc.store(partials + static_cast<size_t>(blockIdx.x) * kW3Vals + q * 6);
+  w3_block_partial(r, threadIdx.x & 63, threadIdx.x >> 6, kW3Threads / 64,
+                   partials + static_cast<size_t>(blockIdx.x) * kW3Vals);
+}
+
+// The corner's offsets in a table plane for the xy box [x0, x0 + L) x [y0, y0 + L),
+// through the periodic continuation of x and y: a corner index past the grid is its
+// remainder plus one full period (column nx, row ny of the table).
+struct XYBox {
+  size_t r0, r1, rt;   // rows y0, y1 (remainder) and ny, in plane 0
+  int x0, x1s, nx;
+  bool xw, yw;
+  __device__ XYBox(const Vol& v, int x, int y, int L) {
+    const int x1 = x + L, y1 = y + L;
+    xw = x1 > v.nx;
+    yw = y1 > v.ny;
+    x0 = x;
+    x1s = xw ? x1 - v.nx : x1;
+    nx = v.nx;
+    r0 = static_cast<size_t>(y) * v.sx();
+    r1 = static_cast<size_t>(yw ? y1 - v.ny : y1) * v.sx();
+    rt = static_cast<size_t>(v.ny) * v.sx();
   }
+  // box sum of table plane p (one field, one z); the row totals are loaded by every
+  // lane and selected, not multiplied, so a non-finite total reaches only wrapping boxes
+  __device__ __forceinline__ double sum(const double* __restrict__ p) const {
+    const double a00 = p[r0 + x0], a01 = p[r0 + x1s], a0t = p[r0 + nx];
+    const double a10 = p[r1 + x0], a11 = p[r1 + x1s], a1t = p[r1 + nx];
+    const double q11 = xw ? a11 + a1t : a11, q01 = xw ? a01 + a0t : a01;
+    double s = (q11 - a10) - (q01 - a00);
+    if (yw) {
+      const double t0 = p[rt + x0], t1 = p[rt + x1s], tt = p[rt + nx];
+      s += (xw ? t1 + tt : t1) - t0;
+    }
+    return s;
+  }
+};
+
+// Window statistics of side L < the grid by walks along z.  Thread (x0, y0) of the
+// 64 x 4 workgroup takes the cubes with corner (x0, y0, j + m L), m = 0, 1, ..., for
+// j = blockIdx.z, blockIdx.z + jg, ... < L: the xy box sums of table plane z serve as the
+// top of one cube and the bottom of the next, so a cube costs one plane of box sums
+// (six table values per field, nine where the box wraps in y) instead of eight corners.
+// The cube past nz takes planes z1 - nz and nz (one period of z).  A thread keeps its
+// bottom-plane sums in its own LDS slots (no barrier), so the field loop need not be
+// unrolled; the box means go straight into the sums and maxima of the error ratios, in
+// the field order of the corner-by-corner kernel.
+__global__ void __launch_bounds__(256) k3_windows_walk(Vol v, int L, int jg, double* partials) {
+  __shared__ double bp[NT3][256];
+  const int x0 = blockIdx.x * 64 + threadIdx.x;
+  const int y0 = blockIdx.y * 4 + threadIdx.y;
+  const int tid = threadIdx.y * 64 + threadIdx.x;
+  Run3 r[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) r[q].init();
+  if (x0 < v.nx && y0 < v.ny) {
+    const XYBox bx(v, x0, y0, L);
+    const double inv_vol = 1.0 / (double(L) * double(L) * double(L));
+    const size_t sy = v.sy(), sf = v.sf();
+    // one cube: bottom plane sums in bp, top plane sums from plane pa (plus pt past nz)
+    auto cube = [&](const double* pa, const double* pt) {
+      double rE = 0.0, denE = 0.0, rZ = 0.0, denZ = 0.0, lhsE = 0.0, lhsZ = 0.0, usq = 0.0;
+#pragma unroll 1
+      for (int f = 0; f < NT3; ++f) {
+        double bn = bx.sum(pa + f * sf);
+        if (pt) bn += bx.sum(pt + f * sf);
+        const double m = v.means[f] + (bn - bp[f][tid]) * inv_vol;
+        bp[f][tid] = bn;
+        if (f == T3_LHS_E) lhsE = m;
+        if (f == T3_LHS_Z) lhsZ = m;
+        if (f == T3_USQ) usq = m;
+        if (f >= T3_E1 && f <= T3_E5) {
+          rE = f == T3_E1 ? m : rE + m;
+          denE = f == T3_E1 ? fabs(m) : fmax(denE, fabs(m));
+        }
+        if (f >= T3_Z1 && f <= T3_Z6) {
+          rZ = f == T3_Z1 ? m : rZ + m;
+          denZ = f == T3_Z1 ? fabs(m) : fmax(denZ, fabs(m));
+        }
+      }
+      r[0].add(denE > 0.0 ? fabs(rE - lhsE) / denE : __builtin_nan(""));
+      r[1].add(denZ > 0.0 ? fabs(rZ - lhsZ) / denZ : __builtin_nan(""));
+      r[2].add(sqrt(usq) * 1.7320508075688772);
+    };
+    for (int j = blockIdx.z; j < L; j += jg) {
+#pragma unroll 2
+      for (int f = 0; f < NT3; ++f) bp[f][tid] = bx.sum(v.P + f * sf + static_cast<size_t>(j) * sy);
+      int z0 = j;
+      for (; z0 + L <= v.nz; z0 += L) cube(v.P + static_cast<size_t>(z0 + L) * sy, nullptr);
+      if (z0 < v.nz)
+        cube(v.P + static_cast<size_t>(z0 + L - v.nz) * sy, v.P + static_cast<size_t>(v.nz) * sy);
+    }
+  }
+  const size_t blk = (static_cast<size_t>(blockIdx.z) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+  w3_block_partial(r, threadIdx.x, threadIdx.y, 4, partials + blk * kW3Vals);
 }
 
 // Fixed-order merge of the workgroup partials: thread t takes partials t, t + 256, ...;
@@ -1487,8 +1585,19 @@ int lbm3_subvolume_balance(lbm3_ctx c, const int32_t* sizes, int32_t nsizes, lbm
   for (int k = 0; k < nsizes; ++k) {
     const int L = sizes[k];
     const size_t count = (L == nx && L == ny && L == nz) ? 1 : plane;
-    const int nb = grid1(count, kW3MaxBlocks);
-    hipLaunchKernelGGL(k3_windows, dim3(nb), dim3(kW3Threads), 0, s, v, L, count, c->wpart);
+    // walks along z over 64 x 4 corner tiles, the residues of z mod L split over jg
+    // workgroups per tile so the partials fit; the one whole-grid cube, and grids with more
+    // tiles than partial slots, take the corner-by-corner kernel
+    const int tx = (nx + 63) / 64, ty = (ny + 3) / 4;
+    int nb;
+    if (count > 1 && tx * ty <= kW3MaxBlocks) {
+      const int jg = std::max(1, std::min(L, kW3MaxBlocks / (tx * ty)));
+      nb = tx * ty * jg;
+      hipLaunchKernelGGL(k3_windows_walk, dim3(tx, ty, jg), dim3(64, 4), 0, s, v, L, jg, c->wpart);
+    } else {
+      nb = grid1(count, kW3MaxBlocks);
+      hipLaunchKernelGGL(k3_windows, dim3(nb), dim3(kW3Threads), 0, s, v, L, count, c->wpart);
+    }
     LBM_HIP(hipGetLastError());
     hipLaunchKernelGGL(k3_windows_final, dim3(1), dim3(256), 0, s, c->wpart, nb, c->wstat + k * kW3Vals);
     LBM_HIP(hipGetLastError());
