@@ -326,6 +326,66 @@ __device__ __forceinline__ void st_at(T* __restrict__ plane, uint32_t byte_off, 
   *reinterpret_cast<T*>(reinterpret_cast<char*>(plane) + byte_off) = v;
 }
 
+// out_l = p_l(x - c_l) (the pull, REV = false) or p_l(x + c_l) (its transpose,
+// REV = true) at site (x, y) of a row-layout state, periodic.
+template <typename T, bool OFF32, bool REV>
+__device__ __forceinline__ void pull9(const T* __restrict__ p, int nx, int ny, int x, int y, T (&out)[9]) {
+  const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+  const int yn = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+  constexpr int sg = REV ? 1 : -1;
+  if constexpr (OFF32) {
+    const uint32_t rs = 9u * static_cast<uint32_t>(nx) * sizeof(T);
+    const uint32_t rn = static_cast<uint32_t>(yn) * rs, r0 = static_cast<uint32_t>(y) * rs,
+                   rp = static_cast<uint32_t>(yp) * rs;
+    const uint32_t cm = static_cast<uint32_t>(xm) * sizeof(T), c0 = static_cast<uint32_t>(x) * sizeof(T),
+                   cp = static_cast<uint32_t>(xp) * sizeof(T);
+#pragma unroll
+    for (int l = 0; l < 9; ++l) {
+      const int dx = sg * cxq(l), dy = sg * cyq(l);
+      out[l] = ld_at(p + l * nx, (dy > 0 ? rp : (dy < 0 ? rn : r0)) + (dx > 0 ? cp : (dx < 0 ? cm : c0)));
+    }
+  } else {
+    const size_t ps = static_cast<size_t>(nx), rs = 9 * ps;
+#pragma unroll
+    for (int l = 0; l < 9; ++l) {
+      const int dx = sg * cxq(l), dy = sg * cyq(l);
+      const int xs = dx > 0 ? xp : (dx < 0 ? xm : x), ys = dy > 0 ? yp : (dy < 0 ? yn : y);
+      out[l] = p[l * ps + static_cast<size_t>(ys) * rs + xs];
+    }
+  }
+}
+
+// store the nine values of site (x, y) of a row-layout state
+template <typename T, bool OFF32>
+__device__ __forceinline__ void store9(T* __restrict__ p, int nx, int x, int y, const T (&v)[9]) {
+  if constexpr (OFF32) {
+    const uint32_t at = static_cast<uint32_t>(y) * (9u * static_cast<uint32_t>(nx) * sizeof(T)) +
+                        static_cast<uint32_t>(x) * sizeof(T);
+#pragma unroll
+    for (int l = 0; l < 9; ++l) st_at(p + l * nx, at, v[l]);
+  } else {
+    T* const out = p + static_cast<size_t>(y) * 9 * nx + x;
+#pragma unroll
+    for (int l = 0; l < 9; ++l) out[static_cast<size_t>(l) * nx] = v[l];
+  }
+}
+
+// Sum of a workgroup's per-thread values, added to its slot (fixed order).
+__device__ __forceinline__ void add_tile_sum(double v, double* slot) {
+  __shared__ double sh[16];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+  if ((tid & 63) == 0) sh[tid >> 6] = v;
+  __syncthreads();
+  if (tid == 0) {
+    double acc = 0.0;
+    const int nw = (blockDim.x * blockDim.y + 63) / 64;
+    for (int w = 0; w < nw; ++w) acc += sh[w];
+    *slot += acc;
+  }
+}
+
 // One backward step over a tile of blockDim.x x (blockDim.y * ry) sites, one site
 // per thread (the step kernel's XCD-aware tile numbering): a^t(x) from f^t pulled
 // at x and a^{t+1}(x + c_l); adds the tile's sum of v . dC/dtau to its own slot of
@@ -336,49 +396,21 @@ __global__ void __launch_bounds__(512) k_adj_step(const T* __restrict__ g, const
                                                    T* __restrict__ aout, Seeds s, int nx, int ny,
                                                    double omega, double* tau_acc, int tiles_x, int total,
                                                    int per_xcd, int ry) {
-  __shared__ double sh[16];
   const int b = blockIdx.x;
   const int tile = (b & 7) * per_xcd + (b >> 3);
   if (tile >= total) return;
   const int tx = tile % tiles_x, ty = tile / tiles_x;
   const int x = tx * blockDim.x + threadIdx.x;
   const int ybase = (ty * blockDim.y + threadIdx.y) * ry;
-  const size_t ps = static_cast<size_t>(nx), rs = 9 * ps;   // the row layout's strides
   const T om = T(omega);
   double dtau = 0.0;
   if (x < nx) {
-    const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
     for (int k = 0; k < ry; ++k) {
       const int y = ybase + k;
       if (y >= ny) break;
-      const int yn = (y == 0) ? ny - 1 : y - 1;
-      const int yp = (y == ny - 1) ? 0 : y + 1;
       T d[9], v[9], o[9];
-      if constexpr (OFF32) {
-        // byte offsets of the row starts (plane 0) and of the three columns
-        const uint32_t rs = 9u * static_cast<uint32_t>(nx) * sizeof(T);
-        const uint32_t rn = static_cast<uint32_t>(yn) * rs, r0 = static_cast<uint32_t>(y) * rs,
-                       rp = static_cast<uint32_t>(yp) * rs;
-        const uint32_t cm = static_cast<uint32_t>(xm) * sizeof(T), c0 = static_cast<uint32_t>(x) * sizeof(T),
-                       cp = static_cast<uint32_t>(xp) * sizeof(T);
-        auto row = [&](int dy) { return dy > 0 ? rp : (dy < 0 ? rn : r0); };
-        auto col = [&](int dx) { return dx > 0 ? cp : (dx < 0 ? cm : c0); };
-#pragma unroll
-        for (int l = 0; l < 9; ++l) {
-          // f^t_l(x - c_l) and a^{t+1}_l(x + c_l)
-          d[l] = ld_at(g + l * nx, row(-cyq(l)) + col(-cxq(l)));
-          v[l] = ld_at(ain + l * nx, row(cyq(l)) + col(cxq(l)));
-        }
-      } else {
-        T dd[9][1], vv[9][1];
-        pull_all<T, 1>(g, ps, rs, nx, x, y, yn, yp, dd);
-        pull_all_rev<T, 1>(ain, ps, rs, nx, x, y, yn, yp, vv);
-#pragma unroll
-        for (int l = 0; l < 9; ++l) {
-          d[l] = dd[l][0];
-          v[l] = vv[l][0];
-        }
-      }
+      pull9<T, OFF32, false>(g, nx, ny, x, y, d);     // f^t(x - c_l)
+      pull9<T, OFF32, true>(ain, nx, ny, x, y, v);    // a^{t+1}(x + c_l)
       double rh = 0.0, sx = 0.0, sy = 0.0;
       if constexpr (SEED) {
         const size_t i = static_cast<size_t>(y) * nx + x;
@@ -387,29 +419,81 @@ __global__ void __launch_bounds__(512) k_adj_step(const T* __restrict__ g, const
         sy = s.uy[i];
       }
       dtau += adjoint_site<T, SEED>(d, v, om, rh, sx, sy, o);
-      if constexpr (OFF32) {
-        const uint32_t at = static_cast<uint32_t>(y) * (9u * static_cast<uint32_t>(nx) * sizeof(T)) +
-                            static_cast<uint32_t>(x) * sizeof(T);
-#pragma unroll
-        for (int l = 0; l < 9; ++l) st_at(aout + l * nx, at, o[l]);
-      } else {
-        T* const out = aout + static_cast<size_t>(y) * rs + x;
-#pragma unroll
-        for (int l = 0; l < 9; ++l) out[l * ps] = o[l];
-      }
+      store9<T, OFF32>(aout, nx, x, y, o);
     }
   }
+  add_tile_sum(dtau, tau_acc + tile);
+}
+
+// Two backward steps in one launch over a tile of kA2W x TH sites: a^t from a^{t+1}
+// and f^t on the tile and a one-site ring around it (kept in LDS; the neighbouring
+// tiles compute the same ring values as their own), then a^{t-1} from a^t and f^{t-1}
+// on the tile.  The intermediate adjoint state never leaves the CU: two steps read
+// f^t, f^{t-1}, a^{t+1} and write a^{t-1}, 4 x 9 values per site instead of 6 x 9.
+// Per-site arithmetic is that of k_adj_step, so a^{t-1} is the same bits as after two
+// single steps; the tile's v . dC/dtau of both steps goes to its slot.  Loop counts
+// are compile-time; indices past the tile's work are clamped so every load is issued
+// unconditionally, and only stores and sums are guarded.
+constexpr int kA2W = 64, kA2T = 256;
+template <typename T, int TH, bool OFF32>
+__global__ void __launch_bounds__(kA2T) k_adj_step2(const T* __restrict__ g1, const T* __restrict__ g2,
+                                                    const T* __restrict__ ain, T* __restrict__ aout, int nx,
+                                                    int ny, double omega, double* tau_acc, int tiles_x, int total,
+                                                    int per_xcd) {
+  constexpr int RW = kA2W + 2, RN = RW * (TH + 2);
+  __shared__ T a1[9][RN];
+  const int b = blockIdx.x;
+  const int tile = (b & 7) * per_xcd + (b >> 3);
+  if (tile >= total) return;
+  const int tx = tile % tiles_x, ty = tile / tiles_x;
+  const int x0 = tx * kA2W, y0 = ty * TH;
+  const int tw = min(kA2W, nx - x0), th = min(TH, ny - y0);
+  const int rw = tw + 2, rn = rw * (th + 2);
+  const T om = T(omega);
+  double dtau = 0.0;
+  // step 1 on the tile and its ring
+  constexpr int R1 = (RN + kA2T - 1) / kA2T;
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) dtau += __shfl_xor(dtau, o, 64);
-  const int tid = threadIdx.y * blockDim.x + threadIdx.x;
-  if ((tid & 63) == 0) sh[tid >> 6] = dtau;
-  __syncthreads();
-  if (tid == 0) {
-    double acc = 0.0;
-    const int nw = (blockDim.x * blockDim.y + 63) / 64;
-    for (int w = 0; w < nw; ++w) acc += sh[w];
-    tau_acc[tile] += acc;
+  for (int k = 0; k < R1; ++k) {
+    const int i0 = static_cast<int>(threadIdx.x) + k * kA2T;
+    const int i = min(i0, rn - 1);
+    const int rx = i % rw, ry = i / rw;
+    int x = x0 - 1 + rx, y = y0 - 1 + ry;
+    x += x < 0 ? nx : 0;
+    x -= x >= nx ? nx : 0;
+    y += y < 0 ? ny : 0;
+    y -= y >= ny ? ny : 0;
+    T d[9], v[9], o[9];
+    pull9<T, OFF32, false>(g1, nx, ny, x, y, d);
+    pull9<T, OFF32, true>(ain, nx, ny, x, y, v);
+    const double nq = adjoint_site<T, false>(d, v, om, 0.0, 0.0, 0.0, o);
+    if (i0 < rn) {
+#pragma unroll
+      for (int l = 0; l < 9; ++l) a1[l][ry * RW + rx] = o[l];
+      if (rx >= 1 && rx <= tw && ry >= 1 && ry <= th) dtau += nq;
+    }
   }
+  __syncthreads();
+  // step 2 on the tile: v_l = a^t_l(x + c_l) from the LDS copy
+  constexpr int R2 = (kA2W * TH + kA2T - 1) / kA2T;
+#pragma unroll
+  for (int k = 0; k < R2; ++k) {
+    const int i = static_cast<int>(threadIdx.x) + k * kA2T;
+    const int lx = i % kA2W, ly = i / kA2W;
+    const bool live = lx < tw && ly < th;
+    const int cx = min(lx, tw - 1), cyy = min(ly, th - 1);
+    const int x = x0 + cx, y = y0 + cyy;
+    T d[9], v[9], o[9];
+    pull9<T, OFF32, false>(g2, nx, ny, x, y, d);
+#pragma unroll
+    for (int l = 0; l < 9; ++l) v[l] = a1[l][(cyy + 1 + cyq(l)) * RW + (cx + 1 + cxq(l))];
+    const double nq = adjoint_site<T, false>(d, v, om, 0.0, 0.0, 0.0, o);
+    if (live) {
+      store9<T, OFF32>(aout, nx, x, y, o);
+      dtau += nq;
+    }
+  }
+  add_tile_sum(dtau, tau_acc + tile);
 }
 
 // du0 = sum_l a^0_l df^eq_l/du at (rho0 = 1, u0)
@@ -529,6 +613,37 @@ int launch_adj_step(const void* g, const void* ain, void* aout, Seeds s, int has
   return LBM_OK;
 }
 
+// Band height of the two-step kernel: 16 rows in FP32 when that still gives 1024
+// tiles (42.8 KiB of LDS), else 8 (23.8 KiB in FP32, 47.5 KiB in FP64).
+template <typename T>
+int pair_rows(int nx, int ny) {
+  const int tx = (nx + kA2W - 1) / kA2W;
+  return (sizeof(T) == 4 && tx * ((ny + 15) / 16) >= 1024) ? 16 : 8;
+}
+template <typename T>
+int pair_tiles(int nx, int ny) {
+  const int th = pair_rows<T>(nx, ny);
+  return ((nx + kA2W - 1) / kA2W) * ((ny + th - 1) / th);
+}
+
+// Two backward steps: a^{t-1} (aout) from a^{t+1} (ain), g1 = f^t and g2 = f^{t-1}.
+template <typename T>
+int launch_adj_pair(const void* g1, const void* g2, const void* ain, void* aout, int nx, int ny,
+                    double omega, double* tau_acc, hipStream_t st) {
+  const int th = pair_rows<T>(nx, ny);
+  const int tiles_x = (nx + kA2W - 1) / kA2W;
+  const int total = tiles_x * ((ny + th - 1) / th);
+  const int per_xcd = (total + 7) / 8;
+  const bool off32 = 9ull * static_cast<uint64_t>(nx) * ny * sizeof(T) <= 0xffffffffull;
+  auto kern = th == 16 ? (off32 ? k_adj_step2<T, 16, true> : k_adj_step2<T, 16, false>)
+                       : (off32 ? k_adj_step2<T, 8, true> : k_adj_step2<T, 8, false>);
+  hipLaunchKernelGGL(kern, dim3(per_xcd * 8), dim3(kA2T), 0, st, static_cast<const T*>(g1),
+                     static_cast<const T*>(g2), static_cast<const T*>(ain), static_cast<T*>(aout), nx, ny,
+                     omega, tau_acc, tiles_x, total, per_xcd);
+  LBM_HIP(hipGetLastError());
+  return LBM_OK;
+}
+
 // number of tiles of a launch shape (slots of the tau accumulator)
 int tile_count(int nx, int ny, const lbm_tile& t) {
   return ((nx + t.bx - 1) / t.bx) * ((ny + t.by * t.ry - 1) / (t.by * t.ry));
@@ -586,7 +701,9 @@ struct GraphCache {
   hipEvent_t go = nullptr, fwd_done[2] = {nullptr, nullptr}, bwd_done[2] = {nullptr, nullptr};
   hipGraphExec_t fwd[2] = {nullptr, nullptr};   // K steps through segment buffer b
   hipGraphExec_t ffwd = nullptr;  // first pass: K steps, intermediate states not kept
-  hipGraphExec_t bwd[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // [adjoint parity][buffer]
+  // [adjoint parity][buffer][parity of the segment's first step], with its launch count
+  hipGraphExec_t bwd[2][2][2] = {};
+  int bwd_launches[2][2][2] = {};
   int init() {
     LBM_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     LBM_HIP(hipStreamCreateWithFlags(&rs, hipStreamNonBlocking));
@@ -620,8 +737,9 @@ struct GraphCache {
       if (f) (void)hipGraphExecDestroy(f);
     if (ffwd) (void)hipGraphExecDestroy(ffwd);
     for (auto& bp : bwd)
-      for (auto& b : bp)
-        if (b) (void)hipGraphExecDestroy(b);
+      for (auto& bb : bp)
+        for (auto& b : bb)
+          if (b) (void)hipGraphExecDestroy(b);
     for (hipEvent_t e : {go, fwd_done[0], fwd_done[1], bwd_done[0], bwd_done[1]})
       if (e) (void)hipEventDestroy(e);
     if (rs) (void)hipStreamDestroy(rs);
@@ -875,7 +993,12 @@ int lbm_adjoint_run(const lbm_adjoint_config* cfg, void* ws, size_t ws_bytes, co
   LBM_HIP(hipGetLastError());
 
   // ---- population adjoint, segment by segment from the last ----
-  const int nb = tile_count(nx, ny, R.tile);
+  // slots of the single-step and the two-step tilings (both add into tau_acc)
+  // The adjoint steps take a fixed shape (not the tuned one), so the slots' partial sums
+  // of dJ/dtau, and thus its bits, do not depend on the step kernel's tuning.
+  const lbm_tile atile = default_tile(cfg->dtype, nx, ny, kAdjLayout);
+  const int nb = std::max(tile_count(nx, ny, atile), cfg->dtype == LBM_F32 ? pair_tiles<float>(nx, ny)
+                                                                           : pair_tiles<double>(nx, ny));
   hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, s, R.w.tau_acc, static_cast<size_t>(nb));
   LBM_HIP(hipGetLastError());
   const double omega = 1.0 / cfg->tau;
@@ -896,38 +1019,47 @@ int lbm_adjoint_run(const lbm_adjoint_config* cfg, void* ws, size_t ws_bytes, co
       if (rc) return rc;
     }
     const bool seeded = t1 >= T - 1;   // holds t = T-1 or T-2
+    // Steps t and t - 1 go in one two-step launch when t is odd and neither is seeded
+    // (pairs fall on the same steps whatever the checkpoint interval); the rest run
+    // one step per launch.  *n receives the number of launches (each flips the buffers).
+    auto sweep = [&](hipStream_t st, int pp, int* n) -> int {
+      *n = 0;
+      for (int64_t t = t1 - 1; t >= t0; ++*n, pp ^= 1) {
+        const bool seed = (t == T - 1) || (t == T - 2);
+        const void* gt = R.seg_state(b, static_cast<int>(t - t0));
+        int rc;
+        if (!seed && (t & 1) && t - 1 >= t0) {
+          const void* gp = R.seg_state(b, static_cast<int>(t - 1 - t0));
+          rc = f32 ? launch_adj_pair<float>(gt, gp, R.w.adj[pp], R.w.adj[pp ^ 1], nx, ny, omega, R.w.tau_acc, st)
+                   : launch_adj_pair<double>(gt, gp, R.w.adj[pp], R.w.adj[pp ^ 1], nx, ny, omega, R.w.tau_acc, st);
+          t -= 2;
+        } else {
+          const Seeds sd = (t == T - 1) ? s1 : s2;
+          rc = f32 ? launch_adj_step<float>(gt, R.w.adj[pp], R.w.adj[pp ^ 1], sd, seed ? 1 : 0, nx, ny, omega,
+                                            R.w.tau_acc, atile, st)
+                   : launch_adj_step<double>(gt, R.w.adj[pp], R.w.adj[pp ^ 1], sd, seed ? 1 : 0, nx, ny, omega,
+                                             R.w.tau_acc, atile, st);
+          t -= 1;
+        }
+        if (rc) return rc;
+      }
+      return LBM_OK;
+    };
     if (seg_len(sg) == K && !seeded) {
-      hipGraphExec_t& gb = gc.bwd[par][b];
+      const int tp = static_cast<int>(t0 & 1);
+      hipGraphExec_t& gb = gc.bwd[par][b][tp];
       if (!gb) {
         const int p0 = par;
-        if (int rc = gc.capture(&gb, [&](hipStream_t cs) -> int {
-              int pp = p0;
-              for (int k = K - 1; k >= 0; --k) {
-                const int r2 = f32 ? launch_adj_step<float>(R.seg_state(b, k), R.w.adj[pp], R.w.adj[pp ^ 1], s2,
-                                                            0, nx, ny, omega, R.w.tau_acc, R.tile, cs)
-                                   : launch_adj_step<double>(R.seg_state(b, k), R.w.adj[pp], R.w.adj[pp ^ 1],
-                                                             s2, 0, nx, ny, omega, R.w.tau_acc, R.tile, cs);
-                if (r2) return r2;
-                pp ^= 1;
-              }
-              return LBM_OK;
-            }))
+        int& nl = gc.bwd_launches[par][b][tp];
+        if (int rc = gc.capture(&gb, [&](hipStream_t cs) -> int { return sweep(cs, p0, &nl); }))
           return rc;
       }
       LBM_HIP(hipGraphLaunch(gb, s));
-      par ^= (K & 1);
+      par ^= gc.bwd_launches[par][b][tp] & 1;
     } else {
-      for (int64_t t = t1 - 1; t >= t0; --t) {
-        const bool seed = (t == T - 1) || (t == T - 2);
-        const Seeds sd = (t == T - 1) ? s1 : s2;
-        const void* gt = R.seg_state(b, static_cast<int>(t - t0));
-        const int rc = f32 ? launch_adj_step<float>(gt, R.w.adj[par], R.w.adj[par ^ 1], sd, seed ? 1 : 0, nx,
-                                                    ny, omega, R.w.tau_acc, R.tile, s)
-                           : launch_adj_step<double>(gt, R.w.adj[par], R.w.adj[par ^ 1], sd, seed ? 1 : 0, nx,
-                                                     ny, omega, R.w.tau_acc, R.tile, s);
-        if (rc) return rc;
-        par ^= 1;
-      }
+      int n = 0;
+      if (int rc = sweep(s, par, &n)) return rc;
+      par ^= n & 1;
     }
     if (sg >= 2) {
       LBM_HIP(hipEventRecord(gc.bwd_done[b], s));

@@ -115,6 +115,25 @@ def test_adjoint_first_pass_in_multi_step_shapes_is_bitwise(gpu_lib):
     set_tuned_tile(32, 32, "f64", tile=(64, 1, 1, 1, 0, 1, 0))
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_two_step_launches_equal_single_steps(gpu_lib, dtype):
+    """The backward sweep runs steps t, t - 1 (t odd, neither seeded) in one two-step
+    launch when both lie in one checkpoint segment, else one step per launch.  Checkpoint
+    intervals 3, 7 and 50 split the pairs differently (7: steps 7, 14, ... start segments,
+    so pair (7, 6) straddles a boundary and both run alone), and 1 runs every step alone;
+    the loss and the u0 gradient must be the same bits in all four, and dJ/dtau equal up
+    to the order of its partial sums."""
+    from paper_1809_06735_amd.adjoint import adjoint_run
+    ux, uy = tiny(seed=11)
+    J0, gx0, gy0, gt0 = adjoint_run(ux, uy, 0.55, 50, 8, 1, dtype=dtype)
+    for ck in (3, 7, 50):
+        say(f"two-step launches {dtype} ckpt_every={ck}")
+        J, gx, gy, gt = adjoint_run(ux, uy, 0.55, 50, 8, ck, dtype=dtype)
+        assert J == J0, ck
+        assert torch.equal(gx, gx0) and torch.equal(gy, gy0), ck
+        assert gt == pytest.approx(gt0, rel=1e-12 if dtype == "f64" else 1e-5), ck
+
+
 def test_adjoint_matches_central_differences(gpu_lib):
     """dJ along a random direction and dJ/dtau against central differences of the GPU loss
     (FP64, 32^2, 50 steps): 1e-4 relative."""
