@@ -451,6 +451,15 @@ __global__ void __launch_bounds__(kA2T) k_adj_step2(const T* __restrict__ g1, co
   const int rw = tw + 2, rn = rw * (th + 2);
   const T om = T(omega);
   double dtau = 0.0;
+  // the second step's f^{t-1} loads go out first: they do not depend on the first step
+  constexpr int R2 = (kA2W * TH + kA2T - 1) / kA2T;
+  T d2[R2][9];
+#pragma unroll
+  for (int k = 0; k < R2; ++k) {
+    const int i = static_cast<int>(threadIdx.x) + k * kA2T;
+    const int cx = min(i % kA2W, tw - 1), cyy = min(i / kA2W, th - 1);
+    pull9<T, OFF32, false>(g2, nx, ny, x0 + cx, y0 + cyy, d2[k]);
+  }
   // step 1 on the tile and its ring
   constexpr int R1 = (RN + kA2T - 1) / kA2T;
 #pragma unroll
@@ -475,7 +484,6 @@ __global__ void __launch_bounds__(kA2T) k_adj_step2(const T* __restrict__ g1, co
   }
   __syncthreads();
   // step 2 on the tile: v_l = a^t_l(x + c_l) from the LDS copy
-  constexpr int R2 = (kA2W * TH + kA2T - 1) / kA2T;
 #pragma unroll
   for (int k = 0; k < R2; ++k) {
     const int i = static_cast<int>(threadIdx.x) + k * kA2T;
@@ -483,11 +491,10 @@ __global__ void __launch_bounds__(kA2T) k_adj_step2(const T* __restrict__ g1, co
     const bool live = lx < tw && ly < th;
     const int cx = min(lx, tw - 1), cyy = min(ly, th - 1);
     const int x = x0 + cx, y = y0 + cyy;
-    T d[9], v[9], o[9];
-    pull9<T, OFF32, false>(g2, nx, ny, x, y, d);
+    T v[9], o[9];
 #pragma unroll
     for (int l = 0; l < 9; ++l) v[l] = a1[l][(cyy + 1 + cyq(l)) * RW + (cx + 1 + cxq(l))];
-    const double nq = adjoint_site<T, false>(d, v, om, 0.0, 0.0, 0.0, o);
+    const double nq = adjoint_site<T, false>(d2[k], v, om, 0.0, 0.0, 0.0, o);
     if (live) {
       store9<T, OFF32>(aout, nx, x, y, o);
       dtau += nq;
