@@ -599,10 +599,20 @@ __device__ __forceinline__ double fd8(const Site3& s, int a, Fn val) {
   return (4.0 * d1 - d2 + (4.0 / 21.0) * d3 - (1.0 / 56.0) * d4) / 5.0;
 }
 
+// One workgroup per 256-site run of an x row.  Each plane's runs are dealt to the
+// eight XCDs in contiguous bands (workgroup b runs on XCD b mod 8, and workgroups
+// are started in order), plane after plane: all XCDs work on the same planes at a
+// time, and an XCD's y neighbours, and most of its stencil planes, are rows its own
+// L2 has just read.  The grid holds 8 * ceil(runs per plane / 8) * nz workgroups.
 __device__ __forceinline__ bool site3(int nx, int ny, int nz, Site3& s) {
-  s.x = blockIdx.x * blockDim.x + threadIdx.x;
-  s.y = blockIdx.y;
-  s.z = blockIdx.z;
+  const int gx = (nx + 255) / 256;
+  const int per_plane = gx * ny, chunk = (per_plane + 7) / 8;
+  const int k = static_cast<int>(blockIdx.x >> 3);
+  const int q = static_cast<int>(blockIdx.x & 7) * chunk + k % chunk;   // run within the plane
+  if (q >= per_plane) return false;
+  s.x = (q % gx) * 256 + threadIdx.x;
+  s.y = q / gx;
+  s.z = k / chunk;
   s.nx = nx;
   s.ny = ny;
   s.nz = nz;
@@ -1563,7 +1573,9 @@ int lbm3_subvolume_balance(lbm3_ctx c, const int32_t* sizes, int32_t nsizes, lbm
   a.nz = nz;
   a.terms = c->terms;
   a.aux = c->aux;
-  const dim3 grid((nx + 255) / 256, ny, nz), block(256);
+  // the pass kernels' row runs, in per-plane XCD bands (see site3)
+  const int chunk = (((nx + 255) / 256) * ny + 7) / 8;
+  const dim3 grid(8 * chunk * nz), block(256);
   hipLaunchKernelGGL(k3_bal_a, grid, block, 0, s, a);
   LBM_HIP(hipGetLastError());
   hipLaunchKernelGGL(k3_bal_b, grid, block, 0, s, a);
