@@ -852,6 +852,67 @@ __global__ void __launch_bounds__(256) k3_sat_x(const double* __restrict__ g, Vo
   if (threadIdx.x == 0) out[0] = 0.0;
 }
 
+// The x scans and the y running sums of one (z, field) plane in one pass, for
+// nx <= 256 * kXYChunks: the workgroup walks the plane's rows in order, scans each
+// row as k3_sat_x does and adds the row's prefix sums to per-column running sums kept
+// in registers, as k3_sat_y does (same operations in the same order: the same bits).
+// The next row's values are loaded before the current row is scanned, and the wave
+// totals alternate between two LDS slots so one barrier per row segment suffices.
+constexpr int kXYChunks = 4;
+__global__ void __launch_bounds__(256) k3_sat_xy(const double* __restrict__ g, Vol v) {
+  __shared__ double wsum[2][4];
+  const int z = blockIdx.x, f = blockIdx.y;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const size_t plane = static_cast<size_t>(v.nx) * v.ny * v.nz;
+  const double mean = v.means[f];
+  const double* src = g + f * plane + static_cast<size_t>(z) * v.ny * v.nx;
+  double* dst = v.P + f * v.sf() + (z + 1) * v.sy();
+  double run[kXYChunks], cur[kXYChunks];
+#pragma unroll
+  for (int c = 0; c < kXYChunks; ++c) {
+    run[c] = 0.0;
+    const int x = c * 256 + threadIdx.x;
+    cur[c] = x < v.nx ? src[x] : 0.0;
+  }
+  int par = 0;
+  for (int y = 0; y < v.ny; ++y) {
+    double nxt[kXYChunks];
+    const double* nrow = src + static_cast<size_t>(y + 1 < v.ny ? y + 1 : y) * v.nx;
+#pragma unroll
+    for (int c = 0; c < kXYChunks; ++c) {
+      const int x = c * 256 + threadIdx.x;
+      nxt[c] = x < v.nx ? nrow[x] : 0.0;
+    }
+    double* out = dst + (y + 1) * v.sx();
+    double carry = 0.0;
+#pragma unroll
+    for (int c = 0; c < kXYChunks; ++c) {
+      if (c * 256 >= v.nx) break;
+      const int x = c * 256 + threadIdx.x;
+      double val = x < v.nx ? cur[c] - mean : 0.0;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const double t = __shfl_up(val, off, 64);
+        if (lane >= off) val += t;
+      }
+      if (lane == 63) wsum[par][wv] = val;
+      __syncthreads();
+      double before = 0.0;
+      for (int w = 0; w < wv; ++w) before += wsum[par][w];
+      const double total = (wsum[par][0] + wsum[par][1]) + (wsum[par][2] + wsum[par][3]);
+      if (x < v.nx) {
+        run[c] += carry + (before + val);
+        out[x + 1] = run[c];
+      }
+      carry += total;
+      par ^= 1;
+    }
+    if (threadIdx.x == 0) out[0] = 0.0;
+#pragma unroll
+    for (int c = 0; c < kXYChunks; ++c) cur[c] = nxt[c];
+  }
+}
+
 // zero faces: z = 0 planes and y = 0 rows of every field
 __global__ void k3_sat_faces(Vol v, int nf) {
   const size_t face = v.sy();                                 // one z = 0 plane
@@ -1586,12 +1647,20 @@ int lbm3_subvolume_balance(lbm3_ctx c, const int32_t* sizes, int32_t nsizes, lbm
     LBM_HIP(hipMemcpyAsync(term_fields, c->terms, NT3 * plane * sizeof(double), hipMemcpyDeviceToDevice, s));
   if (int rc = field_means(c->terms, NT3, nx, ny * nz, c->wpart, c->means, s)) return rc;
   Vol v{c->sat, c->means, nx, ny, nz};
-  hipLaunchKernelGGL(k3_sat_x, dim3(ny, nz, NT3), dim3(256), 0, s, c->terms, v);
-  LBM_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k3_sat_faces, dim3(grid1(v.sy() * NT3, 4096)), dim3(256), 0, s, v, NT3);
-  LBM_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k3_sat_y, dim3((nx + 1 + 255) / 256, nz, NT3), dim3(256), 0, s, v);
-  LBM_HIP(hipGetLastError());
+  if (nx <= 256 * kXYChunks) {
+    // x scans and y sums in one pass per plane (the faces are zeroed on their own)
+    hipLaunchKernelGGL(k3_sat_xy, dim3(nz, NT3), dim3(256), 0, s, c->terms, v);
+    LBM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k3_sat_faces, dim3(grid1(v.sy() * NT3, 4096)), dim3(256), 0, s, v, NT3);
+    LBM_HIP(hipGetLastError());
+  } else {
+    hipLaunchKernelGGL(k3_sat_x, dim3(ny, nz, NT3), dim3(256), 0, s, c->terms, v);
+    LBM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k3_sat_faces, dim3(grid1(v.sy() * NT3, 4096)), dim3(256), 0, s, v, NT3);
+    LBM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k3_sat_y, dim3((nx + 1 + 255) / 256, nz, NT3), dim3(256), 0, s, v);
+    LBM_HIP(hipGetLastError());
+  }
   hipLaunchKernelGGL(k3_sat_z, dim3((nx + 1 + 255) / 256, ny + 1, NT3), dim3(256), 0, s, v);
   LBM_HIP(hipGetLastError());
   for (int k = 0; k < nsizes; ++k) {
