@@ -1106,14 +1106,22 @@ struct XYBox {
 // bottom-plane sums in its own LDS slots (no barrier), so the field loop need not be
 // unrolled; the box means go straight into the sums and maxima of the error ratios, in
 // the field order of the corner-by-corner kernel.
-__global__ void __launch_bounds__(256) k3_windows_walk(Vol v, int L, int jg, double* partials) {
+//
+// Work items r = (j group, y tile, x tile) are dealt to the XCDs in contiguous chunks
+// (workgroup b runs on XCD b mod 8): the tiles that read the same table rows (x0 + L,
+// y0 + L) share an L2, and at most sizes one XCD walks one residue class of z.
+__global__ void __launch_bounds__(256) k3_windows_walk(Vol v, int L, int tx, int ty, int jg, double* partials) {
   __shared__ double bp[NT3][256];
-  const int x0 = blockIdx.x * 64 + threadIdx.x;
-  const int y0 = blockIdx.y * 4 + threadIdx.y;
+  const int n = tx * ty * jg, per = (n + 7) / 8;
+  const int r = static_cast<int>(blockIdx.x & 7) * per + static_cast<int>(blockIdx.x >> 3);
+  if (r >= n) return;   // no partial slot: the merge reads slots 0 .. n - 1
+  const int bxi = r % tx, byi = (r / tx) % ty, bzi = r / (tx * ty);
+  const int x0 = bxi * 64 + threadIdx.x;
+  const int y0 = byi * 4 + threadIdx.y;
   const int tid = threadIdx.y * 64 + threadIdx.x;
-  Run3 r[3];
+  Run3 acc[3];
 #pragma unroll
-  for (int q = 0; q < 3; ++q) r[q].init();
+  for (int q = 0; q < 3; ++q) acc[q].init();
   if (x0 < v.nx && y0 < v.ny) {
     const XYBox bx(v, x0, y0, L);
     const double inv_vol = 1.0 / (double(L) * double(L) * double(L));
@@ -1139,11 +1147,11 @@ __global__ void __launch_bounds__(256) k3_windows_walk(Vol v, int L, int jg, dou
           denZ = f == T3_Z1 ? fabs(m) : fmax(denZ, fabs(m));
         }
       }
-      r[0].add(denE > 0.0 ? fabs(rE - lhsE) / denE : __builtin_nan(""));
-      r[1].add(denZ > 0.0 ? fabs(rZ - lhsZ) / denZ : __builtin_nan(""));
-      r[2].add(sqrt(usq) * 1.7320508075688772);
+      acc[0].add(denE > 0.0 ? fabs(rE - lhsE) / denE : __builtin_nan(""));
+      acc[1].add(denZ > 0.0 ? fabs(rZ - lhsZ) / denZ : __builtin_nan(""));
+      acc[2].add(sqrt(usq) * 1.7320508075688772);
     };
-    for (int j = blockIdx.z; j < L; j += jg) {
+    for (int j = bzi; j < L; j += jg) {
 #pragma unroll 2
       for (int f = 0; f < NT3; ++f) bp[f][tid] = bx.sum(v.P + f * sf + static_cast<size_t>(j) * sy);
       int z0 = j;
@@ -1152,8 +1160,7 @@ __global__ void __launch_bounds__(256) k3_windows_walk(Vol v, int L, int jg, dou
         cube(v.P + static_cast<size_t>(z0 + L - v.nz) * sy, v.P + static_cast<size_t>(v.nz) * sy);
     }
   }
-  const size_t blk = (static_cast<size_t>(blockIdx.z) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-  w3_block_partial(r, threadIdx.x, threadIdx.y, 4, partials + blk * kW3Vals);
+  w3_block_partial(acc, threadIdx.x, threadIdx.y, 4, partials + static_cast<size_t>(r) * kW3Vals);
 }
 
 // Fixed-order merge of the workgroup partials: thread t takes partials t, t + 256, ...;
@@ -1674,7 +1681,8 @@ int lbm3_subvolume_balance(lbm3_ctx c, const int32_t* sizes, int32_t nsizes, lbm
     if (count > 1 && tx * ty <= kW3MaxBlocks) {
       const int jg = std::max(1, std::min(L, kW3MaxBlocks / (tx * ty)));
       nb = tx * ty * jg;
-      hipLaunchKernelGGL(k3_windows_walk, dim3(tx, ty, jg), dim3(64, 4), 0, s, v, L, jg, c->wpart);
+      hipLaunchKernelGGL(k3_windows_walk, dim3(((nb + 7) / 8) * 8), dim3(64, 4), 0, s, v, L, tx, ty, jg,
+                         c->wpart);
     } else {
       nb = grid1(count, kW3MaxBlocks);
       hipLaunchKernelGGL(k3_windows, dim3(nb), dim3(kW3Threads), 0, s, v, L, count, c->wpart);
