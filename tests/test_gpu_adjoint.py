@@ -134,6 +134,20 @@ def test_two_step_launches_equal_single_steps(gpu_lib, dtype):
         assert gt == pytest.approx(gt0, rel=1e-12 if dtype == "f64" else 1e-5), ck
 
 
+def test_two_step_launches_equal_single_steps_16_row_tiles(gpu_lib):
+    """At 1024^2 in FP32 the two-step launches use 64 x 16 tiles (1024 of them) instead
+    of 64 x 8: the same bits as one step per launch (checkpoint interval 1)."""
+    from paper_1809_06735_amd.adjoint import adjoint_run
+    _, ux, uy = inp.spectrum_velocity(1024, seed=3, max_mach=0.1)
+    say("two-step launches f32 1024^2, 64 x 16 tiles")
+    J0, gx0, gy0, gt0 = adjoint_run(ux, uy, 0.55, 10, 16, 1, dtype="f32")
+    J, gx, gy, gt = adjoint_run(ux, uy, 0.55, 10, 16, 10, dtype="f32")
+    assert J == J0
+    assert torch.equal(gx, gx0) and torch.equal(gy, gy0)
+    assert gt == pytest.approx(gt0, rel=1e-5)
+    assert bool(torch.isfinite(gx).all()) and float(gx.abs().max()) > 0.0
+
+
 def test_adjoint_matches_central_differences(gpu_lib):
     """dJ along a random direction and dJ/dtau against central differences of the GPU loss
     (FP64, 32^2, 50 steps): 1e-4 relative."""
