@@ -621,6 +621,8 @@ __device__ __forceinline__ bool site3(int nx, int ny, int nz, Site3& s) {
   return true;
 }
 
+// The passes write their fields with non-temporal stores: only later kernels read
+// them, and kept out of L2 they do not evict the planes that the z differences reuse.
 __global__ void __launch_bounds__(256) k3_bal_a(Bal3 a) {
   Site3 s;
   if (!site3(a.nx, a.ny, a.nz, s)) return;
@@ -687,29 +689,29 @@ __global__ void __launch_bounds__(256) k3_bal_a(Bal3 a) {
       z6 += wn[c] * wn[j] * du[c][j];
     }
   double* t = a.terms;
-  t[T3_LHS_E * plane + i] = (3.0 * en[2] - 4.0 * en[1] + en[0]) / 2.0;
-  t[T3_E2 * plane + i] = -(v[0] * dr[0] + v[1] * dr[1] + v[2] * dr[2]) / 3.0;
-  t[T3_E3 * plane + i] = v[0] * F[0] + v[1] * F[1] + v[2] * F[2];
-  t[T3_E4 * plane + i] = e4;
-  t[T3_LHS_Z * plane + i] = (3.0 * ens[2] - 4.0 * ens[1] + ens[0]) / 2.0;
-  t[T3_Z2 * plane + i] = -ens[2] * (du[0][0] + du[1][1] + du[2][2]);
-  t[T3_Z6 * plane + i] = z6;
-  t[T3_USQ * plane + i] = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+  __builtin_nontemporal_store((3.0 * en[2] - 4.0 * en[1] + en[0]) / 2.0, &t[T3_LHS_E * plane + i]);
+  __builtin_nontemporal_store(-(v[0] * dr[0] + v[1] * dr[1] + v[2] * dr[2]) / 3.0, &t[T3_E2 * plane + i]);
+  __builtin_nontemporal_store(v[0] * F[0] + v[1] * F[1] + v[2] * F[2], &t[T3_E3 * plane + i]);
+  __builtin_nontemporal_store(e4, &t[T3_E4 * plane + i]);
+  __builtin_nontemporal_store((3.0 * ens[2] - 4.0 * ens[1] + ens[0]) / 2.0, &t[T3_LHS_Z * plane + i]);
+  __builtin_nontemporal_store(-ens[2] * (du[0][0] + du[1][1] + du[2][2]), &t[T3_Z2 * plane + i]);
+  __builtin_nontemporal_store(z6, &t[T3_Z6 * plane + i]);
+  __builtin_nontemporal_store(v[0] * v[0] + v[1] * v[1] + v[2] * v[2], &t[T3_USQ * plane + i]);
   double* x = a.aux;
-  x[A3_E * plane + i] = en[2];
-  x[A3_OM2 * plane + i] = ens[2];
-  x[A3_WX * plane + i] = wn[0];
-  x[A3_WY * plane + i] = wn[1];
-  x[A3_WZ * plane + i] = wn[2];
-  x[A3_SXX * plane + i] = sg[0][0];
-  x[A3_SYY * plane + i] = sg[1][1];
-  x[A3_SZZ * plane + i] = sg[2][2];
-  x[A3_SXY * plane + i] = sg[0][1];
-  x[A3_SXZ * plane + i] = sg[0][2];
-  x[A3_SYZ * plane + i] = sg[1][2];
-  x[A3_GX * plane + i] = F[0] / r;
-  x[A3_GY * plane + i] = F[1] / r;
-  x[A3_GZ * plane + i] = F[2] / r;
+  __builtin_nontemporal_store(en[2], &x[A3_E * plane + i]);
+  __builtin_nontemporal_store(ens[2], &x[A3_OM2 * plane + i]);
+  __builtin_nontemporal_store(wn[0], &x[A3_WX * plane + i]);
+  __builtin_nontemporal_store(wn[1], &x[A3_WY * plane + i]);
+  __builtin_nontemporal_store(wn[2], &x[A3_WZ * plane + i]);
+  __builtin_nontemporal_store(sg[0][0], &x[A3_SXX * plane + i]);
+  __builtin_nontemporal_store(sg[1][1], &x[A3_SYY * plane + i]);
+  __builtin_nontemporal_store(sg[2][2], &x[A3_SZZ * plane + i]);
+  __builtin_nontemporal_store(sg[0][1], &x[A3_SXY * plane + i]);
+  __builtin_nontemporal_store(sg[0][2], &x[A3_SXZ * plane + i]);
+  __builtin_nontemporal_store(sg[1][2], &x[A3_SYZ * plane + i]);
+  __builtin_nontemporal_store(F[0] / r, &x[A3_GX * plane + i]);
+  __builtin_nontemporal_store(F[1] / r, &x[A3_GY * plane + i]);
+  __builtin_nontemporal_store(F[2] / r, &x[A3_GZ * plane + i]);
 }
 
 __device__ __forceinline__ int sig_index(int c, int j) {
@@ -758,14 +760,14 @@ __global__ void __launch_bounds__(256) k3_bal_b(Bal3 a) {
     h[c] = dv / r;
   }
   double* t = a.terms;
-  t[T3_E1 * plane + i] = e1;
-  t[T3_E5 * plane + i] = e5;
-  t[T3_Z1 * plane + i] = z1;
-  t[T3_Z3 * plane + i] = w[0] * cg[0] + w[1] * cg[1] + w[2] * cg[2];
+  __builtin_nontemporal_store(e1, &t[T3_E1 * plane + i]);
+  __builtin_nontemporal_store(e5, &t[T3_E5 * plane + i]);
+  __builtin_nontemporal_store(z1, &t[T3_Z1 * plane + i]);
+  __builtin_nontemporal_store(w[0] * cg[0] + w[1] * cg[1] + w[2] * cg[2], &t[T3_Z3 * plane + i]);
   double* x = a.aux;
-  x[A3_HX * plane + i] = h[0];
-  x[A3_HY * plane + i] = h[1];
-  x[A3_HZ * plane + i] = h[2];
+  __builtin_nontemporal_store(h[0], &x[A3_HX * plane + i]);
+  __builtin_nontemporal_store(h[1], &x[A3_HY * plane + i]);
+  __builtin_nontemporal_store(h[2], &x[A3_HZ * plane + i]);
 }
 
 __global__ void __launch_bounds__(256) k3_bal_c(Bal3 a) {
@@ -788,8 +790,8 @@ __global__ void __launch_bounds__(256) k3_bal_c(Bal3 a) {
                     fd8(s, 1, [&](size_t k) { return hz[k] * wx[k] - hx[k] * wz[k]; }) +
                     fd8(s, 2, [&](size_t k) { return hx[k] * wy[k] - hy[k] * wx[k]; });
   double* t = a.terms;
-  t[T3_Z4 * plane + i] = hx[i] * cw[0] + hy[i] * cw[1] + hz[i] * cw[2];
-  t[T3_Z5 * plane + i] = z5;
+  __builtin_nontemporal_store(hx[i] * cw[0] + hy[i] * cw[1] + hz[i] * cw[2], &t[T3_Z4 * plane + i]);
+  __builtin_nontemporal_store(z5, &t[T3_Z5 * plane + i]);
 }
 
 // ---- summed-volume tables ---------------------------------------------------------------------
