@@ -512,8 +512,10 @@ LBM_API int lbm_batch_destroy(lbm_batch b);
  * side nx == ny is one window).  The gradient is obtained by a discrete
  * adjoint sweep: checkpoints of the populations every ckpt_every steps, each
  * segment recomputed forward and swept backward.  With two or more segments the
- * workspace holds two segment buffers: a stream of the library's own recomputes
- * the next segment while the current one is swept (results do not depend on it). */
+ * workspace size returned holds two segment buffers: a stream of the library's own
+ * recomputes the next segment while the current one is swept.  A workspace smaller by
+ * one segment buffer, (ckpt_every + 1) * 9 * nx * ny elements of the dtype rounded up
+ * to 256 bytes, also works, without that overlap; results are the same bits. */
 typedef struct {
   int32_t nx, ny;
   int32_t dtype;        /* LBM_F32 or LBM_F64 populations and adjoint states   */

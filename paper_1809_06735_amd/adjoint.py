@@ -30,13 +30,16 @@ def adjoint_run(ux0, uy0, tau, steps, box, ckpt_every=100, dtype="f32", need_gra
                           tau=float(tau), stream=_stream_handle(stream))
     nbytes = C.c_size_t()
     L.check(lib.lbm_adjoint_workspace_bytes(C.byref(cfg), C.byref(nbytes)), "lbm_adjoint_workspace_bytes")
-    if workspace is None or workspace.numel() < nbytes.value:
+    # the size asked for holds two segment buffers; a caller's workspace one buffer smaller
+    # also runs (without the overlapped recomputation), a smaller one is refused
+    if workspace is None:
         workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=dev)
     J = C.c_double()
     gt = C.c_double()
     gx = torch.empty_like(vx) if need_grad else None
     gy = torch.empty_like(vy) if need_grad else None
-    L.check(lib.lbm_adjoint_run(C.byref(cfg), _ptr(workspace), nbytes.value, _ptr(vx), _ptr(vy),
+    L.check(lib.lbm_adjoint_run(C.byref(cfg), _ptr(workspace), workspace.numel() * workspace.element_size(),
+                                _ptr(vx), _ptr(vy),
                                 C.byref(J), _ptr(gx), _ptr(gy), C.byref(gt) if need_grad else None),
             "lbm_adjoint_run")
     return J.value, gx, gy, (gt.value if need_grad else None)

@@ -549,7 +549,8 @@ struct AdjWs {
 
 int nblocks_sites(size_t plane) { return static_cast<int>((plane + kAT - 1) / kAT); }
 
-AdjWs carve_adj(const lbm_adjoint_config& c, void* base, size_t cap) {
+// second: a second segment buffer (the backward's recomputation then runs ahead on its own stream)
+AdjWs carve_adj(const lbm_adjoint_config& c, void* base, size_t cap, bool second = true) {
   Carver cv(base, cap);
   const size_t plane = static_cast<size_t>(c.nx) * c.ny;
   const size_t es = c.dtype == LBM_F32 ? 4 : 8;
@@ -558,7 +559,7 @@ AdjWs carve_adj(const lbm_adjoint_config& c, void* base, size_t cap) {
   w.ckpt = cv.take<char>(static_cast<size_t>(nck) * 9 * plane * es);
   const size_t seg_bytes = static_cast<size_t>(c.ckpt_every + 1) * 9 * plane * es;
   w.seg[0] = cv.take<char>(seg_bytes);
-  w.seg[1] = cv.take<char>(nck > 1 ? seg_bytes : 0);
+  w.seg[1] = (second && nck > 1) ? cv.take<char>(seg_bytes) : w.seg[0];
   w.adj[0] = cv.take<char>(9 * plane * es);
   w.adj[1] = cv.take<char>(9 * plane * es);
   for (int l = 0; l < 3; ++l)
@@ -777,12 +778,14 @@ int lbm_adjoint_run(const lbm_adjoint_config* cfg, void* ws, size_t ws_bytes, co
   if (!ux0 || !uy0 || !loss) return fail(LBM_E_INVALID, "ux0, uy0 and loss must not be NULL");
   if ((grad_ux0 == nullptr) != (grad_uy0 == nullptr))
     return fail(LBM_E_INVALID, "grad_ux0 and grad_uy0 must both be given or both be NULL");
-  const size_t need = carve_adj(*cfg, nullptr, 0).bytes;
+  // the preferred size holds two segment buffers; one is enough, without the overlap
+  const size_t need = carve_adj(*cfg, nullptr, 0, false).bytes;
+  const bool two = ws_bytes >= carve_adj(*cfg, nullptr, 0, true).bytes;
   if (ws_bytes < need) return fail(LBM_E_NOMEM, "workspace %zu < %zu", ws_bytes, need);
 
   Runner R;
   R.c = *cfg;
-  R.w = carve_adj(*cfg, ws, ws_bytes);
+  R.w = carve_adj(*cfg, ws, ws_bytes, two);
   R.s = static_cast<hipStream_t>(cfg->stream);
   R.plane = static_cast<size_t>(cfg->nx) * cfg->ny;
   R.state_bytes = 9 * R.plane * (cfg->dtype == LBM_F32 ? 4 : 8);
@@ -951,20 +954,22 @@ int lbm_adjoint_run(const lbm_adjoint_config* cfg, void* ws, size_t ws_bytes, co
     return LBM_OK;
   }
 
-  // The backward pass sweeps segment sg from buffer (nseg - 1 - sg) & 1 (the last
-  // segment's states are still in buffer 0 from the forward pass) while the second
-  // stream recomputes segment sg - 1 into the other buffer from its checkpoint.
-  // A recomputation waits for the sweep that last read its buffer; a sweep waits
-  // for its recomputation.  Kernels and operands are those of a one-stream run.
-  auto buf_of = [&](int64_t sg) { return static_cast<int>((nseg - 1 - sg) & 1); };
+  // The backward pass sweeps segment sg from buffer (nseg - 1 - sg) % nbuf (the last
+  // segment's states are still in buffer 0 from the forward pass) while, with two
+  // buffers, the second stream recomputes segment sg - 1 into the other buffer from its
+  // checkpoint.  A recomputation waits for the sweep that last read its buffer (with one
+  // buffer: the sweep just before it); a sweep waits for its recomputation.  Kernels and
+  // operands are those of a one-stream run.
+  const int nbuf = (two && nseg > 1) ? 2 : 1;
+  auto buf_of = [&](int64_t sg) { return static_cast<int>((nseg - 1 - sg) % nbuf); };
   auto recompute = [&](int64_t sg) -> int {
     const int b = buf_of(sg);
-    if (sg + 2 <= nseg - 1) LBM_HIP(hipStreamWaitEvent(gc.rs, gc.bwd_done[b], 0));
+    if (sg + nbuf <= nseg - 1) LBM_HIP(hipStreamWaitEvent(gc.rs, gc.bwd_done[b], 0));
     if (int rc = forward_segment(sg, false, b, gc.rs)) return rc;
     LBM_HIP(hipEventRecord(gc.fwd_done[b], gc.rs));
     return LBM_OK;
   };
-  if (nseg >= 2) {
+  if (nbuf == 2) {
     // checkpoints are complete once the forward pass's work on s is
     LBM_HIP(hipEventRecord(gc.go, s));
     LBM_HIP(hipStreamWaitEvent(gc.rs, gc.go, 0));
@@ -1068,9 +1073,9 @@ int lbm_adjoint_run(const lbm_adjoint_config* cfg, void* ws, size_t ws_bytes, co
       if (int rc = sweep(s, par, &n)) return rc;
       par ^= n & 1;
     }
-    if (sg >= 2) {
+    if (sg >= nbuf) {
       LBM_HIP(hipEventRecord(gc.bwd_done[b], s));
-      if (int rc = recompute(sg - 2)) return rc;
+      if (int rc = recompute(sg - nbuf)) return rc;
     }
   }
   void* ain = R.w.adj[par];

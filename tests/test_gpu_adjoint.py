@@ -148,6 +148,32 @@ def test_two_step_launches_equal_single_steps_16_row_tiles(gpu_lib):
     assert bool(torch.isfinite(gx).all()) and float(gx.abs().max()) > 0.0
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_workspace_with_one_segment_buffer(gpu_lib, dtype):
+    """A workspace one segment buffer smaller than the size the library asks for runs
+    the recomputation in line instead of beside the sweep: the same bits."""
+    import ctypes as C
+    from paper_1809_06735_amd import _lib as L
+    from paper_1809_06735_amd.adjoint import adjoint_run
+    ux, uy = tiny(seed=5)
+    n, steps, ck = 32, 50, 7
+    cfg = L.AdjointConfig(nx=n, ny=n, dtype={"f32": L.LBM_F32, "f64": L.LBM_F64}[dtype], box=8,
+                          ckpt_every=ck, reserved=0, steps=steps, tau=0.55, stream=None)
+    full = C.c_size_t()
+    L.check(L.load().lbm_adjoint_workspace_bytes(C.byref(cfg), C.byref(full)), "workspace")
+    es = 8 if dtype == "f64" else 4
+    seg = ((ck + 1) * 9 * n * n * es + 255) // 256 * 256
+    small = torch.empty(full.value - seg, dtype=torch.uint8, device="cuda")
+    say(f"one segment buffer {dtype}: {full.value - seg} of {full.value} bytes")
+    J0, gx0, gy0, gt0 = adjoint_run(ux, uy, 0.55, steps, 8, ck, dtype=dtype)
+    J, gx, gy, gt = adjoint_run(ux, uy, 0.55, steps, 8, ck, dtype=dtype, workspace=small)
+    assert J == J0 and gt == gt0
+    assert torch.equal(gx, gx0) and torch.equal(gy, gy0)
+    too_small = torch.empty(full.value - seg - 256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(RuntimeError):
+        adjoint_run(ux, uy, 0.55, steps, 8, ck, dtype=dtype, workspace=too_small)
+
+
 def test_adjoint_matches_central_differences(gpu_lib):
     """dJ along a random direction and dJ/dtau against central differences of the GPU loss
     (FP64, 32^2, 50 steps): 1e-4 relative."""
